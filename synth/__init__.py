@@ -1,0 +1,7 @@
+"""Seeded synthetic inputs for MCPT(2) solves (shared by the tests, the oracle
+callers and the benchmark; holds none of the method's arithmetic)."""
+from .hf_lattice import (  # noqa: F401
+    Problem, WORKLOADS, cubic_sites, cluster_sites, pair_list, make_lattice_problem,
+    make_workload, make_cluster_batch, make_served_request, concat_problems, SEED_ROOT,
+    SPACING_A, DEFAULT_COUPLING_SCALE,
+)

@@ -1,0 +1,327 @@
+"""Seeded synthetic inputs shaped like the HF molecular crystal of the paper.
+
+The paper's calculations (Sec. IV, HF crystal cubes up to 10x10x10 molecules,
+32 orbitals per molecule with 5 doubly occupied) use real integrals that are
+not available here.  This module draws inputs of the same shapes:
+
+* monomers on a simple cubic lattice, 3.4 Angstrom spacing, open boundaries
+  (the paper uses no periodic boundary conditions);
+* per monomer: o occupied and v virtual orbital energies (Eh), occupied drawn
+  from U[-1.5, -0.5], virtual from U[0.2, 3.0], and an intra-monomer block
+  K[i, j, a, b] = <ab|ij> drawn N(0, 0.05^2) and antisymmetrised in (i, j) and
+  in (a, b);
+* per unordered pair inside the cutoff: a dimer block V[i, a, j, b] = (ai|bj)
+  with i, a on the first monomer and j, b on the second, drawn
+  N(0, 1) * 0.05 * (3.4 / R)^3 * coupling_scale.
+
+Every value is keyed by a numpy SeedSequence built from the workload id, the
+cluster id, the kind of draw and the integer lattice coordinates of the site(s)
+involved, so inputs do not depend on monomer numbering or generation order.
+
+This module holds none of the method's arithmetic: it only draws numbers and
+builds the lattice and the cutoff pair list.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+SEED_ROOT = 14092700
+SPACING_A = 3.4
+SIGMA_K = 0.05
+SIGMA_V = 0.05
+EPS_OCC = (-1.5, -0.5)
+EPS_VIR = (0.2, 3.0)
+# default coupling scale: at scale 1 the sweep map of these random blocks has a
+# dominant eigenvalue > 1 and Jacobi diverges (stated deviation, see DESIGN)
+DEFAULT_COUPLING_SCALE = 0.25
+
+KIND_MONOMER = 0
+KIND_PAIR = 1
+KIND_CLUSTER = 2
+KIND_STREAM = 3
+
+
+@dataclasses.dataclass
+class Problem:
+    """Flat, concatenated MCPT(2) inputs (the layout the C-ABI takes).
+
+    eps:   concatenated per monomer, o_X occupied then v_X virtual energies
+    k:     concatenated K_X[i][j][a][b] = <ab|ij>, row-major (o, o, v, v)
+    pairs: [P, 2] monomer indices (X, Y), X != Y, each unordered pair once
+    v:     concatenated V_XY[i][a][j][b] = (ai|bj), row-major (oX, vX, oY, vY)
+    """
+    n_occ: np.ndarray
+    n_vir: np.ndarray
+    eps: np.ndarray
+    k: np.ndarray
+    pairs: np.ndarray
+    v: np.ndarray
+    sites: np.ndarray | None = None
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    def __post_init__(self):
+        self.n_occ = np.ascontiguousarray(self.n_occ, dtype=np.int32)
+        self.n_vir = np.ascontiguousarray(self.n_vir, dtype=np.int32)
+        self.pairs = np.ascontiguousarray(np.asarray(self.pairs, dtype=np.int32).reshape(-1, 2))
+        o = self.n_occ.astype(np.int64)
+        v = self.n_vir.astype(np.int64)
+        self.eps_off = np.concatenate([[0], np.cumsum(o + v)])
+        self.k_off = np.concatenate([[0], np.cumsum(o * o * v * v)])
+        nx = o * v
+        if len(self.pairs):
+            sizes = nx[self.pairs[:, 0]] * nx[self.pairs[:, 1]]
+        else:
+            sizes = np.zeros(0, dtype=np.int64)
+        self.v_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+
+    # -- sizes ------------------------------------------------------------
+    @property
+    def n_mono(self) -> int:
+        return int(len(self.n_occ))
+
+    @property
+    def n_pair(self) -> int:
+        return int(len(self.pairs))
+
+    def n_ov(self, x: int) -> int:
+        return int(self.n_occ[x]) * int(self.n_vir[x])
+
+    # -- views ------------------------------------------------------------
+    def eps_of(self, x: int):
+        o = int(self.n_occ[x])
+        e = self.eps[self.eps_off[x]:self.eps_off[x + 1]]
+        return e[:o], e[o:]
+
+    def k_of(self, x: int) -> np.ndarray:
+        o, v = int(self.n_occ[x]), int(self.n_vir[x])
+        return self.k[self.k_off[x]:self.k_off[x + 1]].reshape(o, o, v, v)
+
+    def v_of(self, p: int) -> np.ndarray:
+        x, y = (int(t) for t in self.pairs[p])
+        return self.v[self.v_off[p]:self.v_off[p + 1]].reshape(
+            int(self.n_occ[x]), int(self.n_vir[x]), int(self.n_occ[y]), int(self.n_vir[y]))
+
+    def nbytes(self) -> int:
+        return int(self.eps.nbytes + self.k.nbytes + self.v.nbytes + self.pairs.nbytes)
+
+    # -- transformations used by invariance tests ---------------------------
+    def relabel(self, perm, flip=None) -> "Problem":
+        """New problem with monomer old index perm[new] at position new; pairs
+        whose flip flag is set are stored in the reverse orientation (V -> V^T
+        over the (i,a) <-> (j,b) index pairs)."""
+        perm = np.asarray(perm, dtype=np.int64)
+        inv = np.empty_like(perm)
+        inv[perm] = np.arange(len(perm))
+        n_occ = self.n_occ[perm]
+        n_vir = self.n_vir[perm]
+        eps = np.concatenate([self.eps[self.eps_off[x]:self.eps_off[x + 1]] for x in perm]) \
+            if len(perm) else np.zeros(0)
+        k = np.concatenate([self.k[self.k_off[x]:self.k_off[x + 1]] for x in perm]) \
+            if len(perm) else np.zeros(0)
+        flip = np.zeros(self.n_pair, dtype=bool) if flip is None else np.asarray(flip, dtype=bool)
+        pairs = []
+        blocks = []
+        for p in range(self.n_pair):
+            x, y = (int(t) for t in self.pairs[p])
+            vb = self.v_of(p)
+            if flip[p]:
+                pairs.append((inv[y], inv[x]))
+                blocks.append(np.ascontiguousarray(vb.transpose(2, 3, 0, 1)).ravel())
+            else:
+                pairs.append((inv[x], inv[y]))
+                blocks.append(vb.ravel())
+        v = np.concatenate(blocks) if blocks else np.zeros(0)
+        sites = self.sites[perm] if self.sites is not None else None
+        return Problem(n_occ, n_vir, eps, k, np.array(pairs, dtype=np.int32).reshape(-1, 2), v,
+                       sites, dict(self.meta, relabelled=True))
+
+    def subset_pairs(self, keep) -> "Problem":
+        keep = np.asarray(keep, dtype=bool)
+        blocks = [self.v[self.v_off[p]:self.v_off[p + 1]] for p in range(self.n_pair) if keep[p]]
+        v = np.concatenate(blocks) if blocks else np.zeros(0)
+        return Problem(self.n_occ, self.n_vir, self.eps, self.k, self.pairs[keep], v,
+                       self.sites, dict(self.meta))
+
+
+def concat_problems(probs) -> Problem:
+    """Disjoint union of clusters (no pairs between clusters)."""
+    n_occ = np.concatenate([p.n_occ for p in probs])
+    n_vir = np.concatenate([p.n_vir for p in probs])
+    eps = np.concatenate([p.eps for p in probs])
+    k = np.concatenate([p.k for p in probs])
+    shift = np.concatenate([[0], np.cumsum([p.n_mono for p in probs])])
+    pairs = np.concatenate([p.pairs.astype(np.int64) + shift[i] for i, p in enumerate(probs)]) \
+        if probs else np.zeros((0, 2))
+    v = np.concatenate([p.v for p in probs])
+    return Problem(n_occ, n_vir, eps, k, pairs, v, None, {"union_of": len(probs)})
+
+
+# ---------------------------------------------------------------------------
+# lattice geometry
+# ---------------------------------------------------------------------------
+def cubic_sites(nx: int, ny: int, nz: int) -> np.ndarray:
+    """Integer lattice coordinates of an nx x ny x nz block, lexicographic order."""
+    g = np.stack(np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij"), -1)
+    return g.reshape(-1, 3).astype(np.int64)
+
+
+def cluster_sites(n: int) -> np.ndarray:
+    """First n sites (lexicographic) of the smallest cube holding n sites."""
+    side = 1
+    while side ** 3 < n:
+        side += 1
+    return cubic_sites(side, side, side)[:n]
+
+
+def pair_list(sites: np.ndarray, cutoff_spacings: float | None) -> np.ndarray:
+    """All unordered pairs X < Y whose lattice distance is within the cutoff.
+
+    The cutoff is inclusive and measured between lattice sites in units of the
+    spacing; it is applied on squared integer distances, so it is exact.
+    Open boundaries: no periodic images."""
+    n = len(sites)
+    if n < 2:
+        return np.zeros((0, 2), dtype=np.int32)
+    iu, ju = np.triu_indices(n, 1)
+    d = sites[iu] - sites[ju]
+    d2 = np.einsum("ij,ij->i", d, d)
+    if cutoff_spacings is None:
+        keep = np.ones(len(d2), dtype=bool)
+    else:
+        keep = d2 <= int(math.floor(cutoff_spacings ** 2 + 1e-9))
+    return np.stack([iu[keep], ju[keep]], 1).astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
+# seeded draws
+# ---------------------------------------------------------------------------
+def _rng(*key) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([SEED_ROOT, *[int(k) for k in key]]))
+
+
+def _monomer_draw(workload: int, cluster: int, site, o: int | None, v: int | None,
+                  mixed_sizes: bool = False):
+    rng = _rng(workload, cluster, KIND_MONOMER, *site)
+    # the size-class draw is always taken so the other draws do not depend on it
+    u = rng.random()
+    if mixed_sizes:
+        o, v = (5, 27) if u < 0.5 else (8, 56)
+    e_occ = np.sort(rng.uniform(*EPS_OCC, size=o))
+    e_vir = np.sort(rng.uniform(*EPS_VIR, size=v))
+    g = rng.normal(0.0, SIGMA_K, size=(o, o, v, v))
+    # antisymmetrise in (i, j) and (a, b); keeps sigma = 0.05 off the zero diagonals
+    k = 0.5 * (g - g.transpose(1, 0, 2, 3) - g.transpose(0, 1, 3, 2) + g.transpose(1, 0, 3, 2))
+    return o, v, np.concatenate([e_occ, e_vir]), k
+
+
+def _pair_block(workload: int, cluster: int, site_x, site_y, shape, r_angstrom: float,
+                coupling_scale: float) -> np.ndarray:
+    rng = _rng(workload, cluster, KIND_PAIR, *site_x, *site_y)
+    z = rng.standard_normal(size=shape)
+    return (coupling_scale * SIGMA_V * (SPACING_A / r_angstrom) ** 3) * z
+
+
+def make_lattice_problem(sites: np.ndarray, cutoff_spacings: float | None, *, o: int = 5,
+                         v: int = 27, workload: int = 0, cluster: int = 0,
+                         coupling_scale: float = DEFAULT_COUPLING_SCALE,
+                         mixed_sizes: bool = False, displacement=None,
+                         dtype_v=np.float64, sizes=None) -> Problem:
+    """Build a problem on the given integer lattice sites.
+
+    displacement: None or (monomer index, axis 0..2, signed shift in Angstrom);
+    the displaced monomer keeps its energies and intra block, its pair blocks
+    are rescaled by (R0 / R)^3 and the pair list stays that of the undisplaced
+    lattice (fixed topology).  sizes: optional per-monomer (o, v) list."""
+    sites = np.asarray(sites, dtype=np.int64)
+    n = len(sites)
+    n_occ = np.empty(n, dtype=np.int32)
+    n_vir = np.empty(n, dtype=np.int32)
+    eps_parts, k_parts = [], []
+    for x in range(n):
+        so, sv = (sizes[x] if sizes is not None else (o, v))
+        ox, vx, e, k = _monomer_draw(workload, cluster, sites[x], so, sv, mixed_sizes)
+        n_occ[x], n_vir[x] = ox, vx
+        eps_parts.append(e)
+        k_parts.append(k.ravel())
+    pairs = pair_list(sites, cutoff_spacings)
+    pos = sites.astype(np.float64) * SPACING_A
+    if displacement is not None:
+        dx, axis, shift = displacement
+        pos_new = pos.copy()
+        pos_new[int(dx), int(axis)] += float(shift)
+    else:
+        pos_new = pos
+    nxv = n_occ.astype(np.int64) * n_vir
+    sizes = nxv[pairs[:, 0]] * nxv[pairs[:, 1]] if len(pairs) else np.zeros(0, dtype=np.int64)
+    vflat = np.empty(int(sizes.sum()), dtype=dtype_v)
+    off = 0
+    for p, (x, y) in enumerate(pairs):
+        shape = (int(n_occ[x]), int(n_vir[x]), int(n_occ[y]), int(n_vir[y]))
+        r0 = float(np.linalg.norm(pos[x] - pos[y]))
+        blk = _pair_block(workload, cluster, sites[x], sites[y], shape, r0, coupling_scale)
+        if displacement is not None and (x == displacement[0] or y == displacement[0]):
+            r1 = float(np.linalg.norm(pos_new[x] - pos_new[y]))
+            blk *= (r0 / r1) ** 3
+        sz = int(sizes[p])
+        vflat[off:off + sz] = blk.ravel()
+        off += sz
+    eps = np.concatenate(eps_parts) if eps_parts else np.zeros(0)
+    k = np.concatenate(k_parts) if k_parts else np.zeros(0)
+    return Problem(n_occ, n_vir, eps, k, pairs, vflat, sites,
+                   dict(workload=workload, cluster=cluster, cutoff=cutoff_spacings,
+                        coupling_scale=coupling_scale, displacement=displacement))
+
+
+# named workloads: the HF-crystal-shaped cubes (o=5, v=27, 32 orbitals/monomer)
+WORKLOADS = {
+    "hf-2x2x2": dict(workload=1, dims=(2, 2, 2), cutoff=None),
+    "hf-5x5x5-c2": dict(workload=2, dims=(5, 5, 5), cutoff=2.0),
+    "hf-10x10x10-c3": dict(workload=3, dims=(10, 10, 10), cutoff=3.0),
+}
+
+
+def make_workload(name: str, coupling_scale: float = DEFAULT_COUPLING_SCALE, **kw) -> Problem:
+    spec = WORKLOADS[name]
+    p = make_lattice_problem(cubic_sites(*spec["dims"]), spec["cutoff"], workload=spec["workload"],
+                             coupling_scale=coupling_scale, **kw)
+    p.meta["name"] = name
+    return p
+
+
+def make_cluster_batch(n_clusters: int = 64, *, workload: int = 4, min_mono: int = 27,
+                       max_mono: int = 512, cutoff: float = 2.0,
+                       coupling_scale: float = DEFAULT_COUPLING_SCALE, mixed_sizes: bool = True,
+                       dtype_v=np.float64, first: int = 0):
+    """Uneven cubic-lattice clusters: n_mono log-uniform in [min, max], each
+    monomer o5v27 or o8v56 with probability 1/2."""
+    out = []
+    for c in range(first, first + n_clusters):
+        rng = _rng(workload, c, KIND_CLUSTER)
+        n = int(round(math.exp(rng.uniform(math.log(min_mono), math.log(max_mono)))))
+        p = make_lattice_problem(cluster_sites(n), cutoff, workload=workload, cluster=c,
+                                 coupling_scale=coupling_scale, mixed_sizes=mixed_sizes,
+                                 dtype_v=dtype_v)
+        p.meta["name"] = f"cluster-{c}"
+        out.append(p)
+    return out
+
+
+def make_served_request(r: int, *, workload: int = 5, min_mono: int = 8, max_mono: int = 1000,
+                        cutoff: float = 3.0, step_angstrom: float = 0.01,
+                        coupling_scale: float = DEFAULT_COUPLING_SCALE):
+    """One served request: a cluster of log-uniform size with one monomer
+    displaced by +-0.01 Angstrom along a seeded axis (finite-difference geometry,
+    Sec. IV.A)."""
+    rng = _rng(workload, r, KIND_STREAM)
+    n = int(round(math.exp(rng.uniform(math.log(min_mono), math.log(max_mono)))))
+    mono = int(rng.integers(0, n))
+    axis = int(rng.integers(0, 3))
+    sign = 1.0 if rng.random() < 0.5 else -1.0
+    p = make_lattice_problem(cluster_sites(n), cutoff, workload=workload, cluster=r,
+                             coupling_scale=coupling_scale,
+                             displacement=(mono, axis, sign * step_angstrom))
+    p.meta["name"] = f"request-{r}"
+    return p
