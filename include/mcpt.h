@@ -1,0 +1,177 @@
+/*
+ * mcpt.h - C ABI of the MCPT(2) doubles hot path on one AMD Instinct MI355X.
+ *
+ * Method: Byrd et al., "Molecular Cluster Perturbation Theory. I. Formalism",
+ * Sec. II.C.  The library solves, for every monomer X of a cluster, the monomer
+ * doubles amplitudes T_X (Eq. 58, tm2) and, for every pair (X, Y) inside the
+ * cutoff, the dimer doubles amplitudes Tau_XY (Eq. 59, td2), iterated to
+ * self-consistency as in step 6 of the program flow, and evaluates the monomer
+ * energies E_M2(X) (Eq. 54), their shift dE_M2(X) (Eq. 56) and the dimer
+ * energies E_D2(XY) (Eq. 55).
+ *
+ * Terms kept: the source integrals, the pair coupling of Eq. 58 and the
+ * monomer-amplitude coupling of Eq. 59 - the terms that the two integral
+ * classes taken as input can form.  Each amplitude equation is solved as
+ * eps * amplitude = integral + coupling terms, with eps^{ij}_{ab} =
+ * e_i + e_j - e_a - e_b < 0 (Eqs. 60-61).  Every dimer integral of Eqs. 55,
+ * 58, 59 is the one Coulomb block (ai|bj) of real orbitals (Eq. 29); the
+ * reversed pair uses its transpose.  The isolated-monomer reference of Eq. 56
+ * is the energy at zero coupling, E_M2 at T = D * K.
+ *
+ * Conventions for every call:
+ *  - Every function returns an mcpt_status; no C++ exception crosses the ABI.
+ *  - On error no output is written and mcpt_last_error() describes the cause
+ *    (message stored per calling thread, valid until its next call).
+ *  - Input arrays are owned by the caller and are copied before the call
+ *    returns; output arrays are allocated by the caller.
+ *  - Device memory and resident problems belong to the context until
+ *    mcpt_release() or mcpt_destroy().
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef MCPT_H
+#define MCPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MCPT_OK = 0,
+    MCPT_PENDING = 1,            /* mcpt_poll: the request has not finished yet */
+    MCPT_ERR_INVALID = -1,       /* bad sizes, pair list, options or denominator >= 0 */
+    MCPT_ERR_NOMEM = -2,         /* device allocation failed */
+    MCPT_ERR_DEVICE = -3,        /* HIP runtime error (message in mcpt_last_error) */
+    MCPT_ERR_NOT_CONVERGED = -4, /* max_sweeps reached with residual >= tol */
+    MCPT_ERR_DIVERGED = -5,      /* residual non-finite, > 1e6 x first, or 3 rises above first */
+    MCPT_ERR_NONFINITE = -6,     /* NaN or Inf in the inputs */
+    MCPT_ERR_ADMISSION = -7,     /* problem larger than the context's HBM budget */
+    MCPT_ERR_UNKNOWN_ID = -8     /* no resident problem / ticket with that id */
+} mcpt_status;
+
+/* Arithmetic of the pair contractions (Eqs. 58-59).  Denominators, residual,
+ * energies and the monomer update are FP64 in every mode. */
+typedef enum {
+    MCPT_FP64 = 0,               /* FP64 MFMA */
+    MCPT_FP32 = 1,               /* FP32 MFMA, FP32 accumulation */
+    MCPT_BF16 = 2                /* BF16 MFMA inputs, FP32 accumulation */
+} mcpt_precision;
+
+typedef enum {
+    MCPT_HOST = 0,               /* eps, k_intra, v_dimer are host pointers */
+    MCPT_DEVICE = 1              /* eps, k_intra, v_dimer are device pointers on the context's GPU */
+} mcpt_memory;
+
+typedef struct mcpt_ctx mcpt_ctx;   /* opaque: device, stream, resident problems */
+
+/* One cluster: monomer orbital energies and intra-monomer integrals from
+ * step 1-2 of the program flow, the cutoff pair list and the dimer blocks of
+ * step 2 (Eq. 29).  All offsets are implied by n_occ, n_vir and pair. */
+typedef struct {
+    int32_t        n_mono;   /* N >= 1 */
+    const int32_t *n_occ;    /* [N] o_X >= 1 (host) */
+    const int32_t *n_vir;    /* [N] v_X >= 1 (host) */
+    const double  *eps;      /* sum_X (o_X + v_X): per monomer o_X occupied then v_X virtual energies, Eh */
+    const double  *k_intra;  /* sum_X o_X^2 v_X^2: K_X[i][j][a][b] = <ab|ij>, row-major, monomers concatenated */
+    int64_t        n_pair;   /* P >= 0 */
+    const int32_t *pair;     /* [P][2] (X, Y), X != Y, each unordered pair at most once (host) */
+    const double  *v_dimer;  /* sum_p o_X v_X o_Y v_Y: V_XY[i][a][j][b] = (ai|bj), i,a on X, j,b on Y, row-major, pairs concatenated */
+    int32_t        memory;   /* mcpt_memory of eps, k_intra, v_dimer */
+} mcpt_problem;
+
+typedef struct {
+    double         tol;          /* > 0: stop at the first sweep with max|T_new - T| < tol;
+                                    == 0: run exactly max_sweeps sweeps (no convergence test) */
+    int32_t        max_sweeps;   /* >= 0 */
+    int32_t        precision;    /* mcpt_precision of the pair contractions */
+    int32_t        polish;       /* reduced precision: 1 = FP64 defect-correction sweeps until the
+                                    FP64 residual < tol; 0 = stop at the reduced-precision residual */
+    int32_t        deterministic;/* 1 = no floating-point atomics: bitwise repeatable results */
+    int32_t        check_every;  /* sweeps issued between host checks of the device residual (>= 1) */
+    int32_t        reserved;
+    const double  *warm_t;       /* NULL, or host T (layout of t_amp in mcpt_energy) to start from */
+} mcpt_options;
+
+typedef struct {
+    double  e_total;        /* e_mono + e_dimer, Eh */
+    double  e_mono;         /* sum_X E_M2(X) (Eq. 54) */
+    double  e_dimer;        /* sum over unordered pairs of E_D2(XY) (Eq. 55) */
+    double  e_mono0;        /* sum_X E_M2 at zero coupling (reference of Eq. 56) */
+    double  residual;       /* max|T_new - T| of the last sweep */
+    double  seconds;        /* wall time of the solve on the host */
+    int32_t sweeps;         /* sweeps run (reduced-precision + FP64 polish) */
+    int32_t polish_sweeps;  /* of which FP64 residual sweeps in polish mode */
+    int32_t status;         /* mcpt_status of this solve */
+    int32_t reserved;
+} mcpt_summary;
+
+/* Per-launch kernel timing, recorded with HIP events on the context's stream
+ * while enabled (mcpt_set_timing). */
+typedef struct {
+    double  pair_ms;        /* summed duration of pair-phase launches (Eqs. 58-59 contractions) */
+    double  mono_ms;        /* summed duration of monomer-phase launches */
+    int64_t pair_launches;
+    int64_t mono_launches;
+    double  pair_flops;     /* algorithmic flops of the timed pair launches: 4 nX nY (nX + nY) per pair
+                               with coupling, 2 nX nY (nX + nY) for energy-only passes */
+    double  pair_v_bytes;   /* dimer-block bytes those launches streamed (sizeof element x nX nY per pair) */
+} mcpt_timing;
+
+/* Create a context on HIP device `device`; at most hbm_budget_bytes of device
+ * memory are used for resident problems (0 = 90% of free memory).
+ * Errors: MCPT_ERR_INVALID (no such device), MCPT_ERR_DEVICE. */
+mcpt_status mcpt_create(int device, size_t hbm_budget_bytes, mcpt_ctx **out);
+
+/* Free every resident problem, the stream and the context.  NULL is a no-op. */
+void mcpt_destroy(mcpt_ctx *ctx);
+
+/* Message of the last error on this thread ("" if none). */
+const char *mcpt_last_error(void);
+
+/* Use an existing HIP stream (hipStream_t, e.g. a PyTorch stream) for all
+ * later work of this context; NULL restores the context's own stream. */
+mcpt_status mcpt_set_stream(mcpt_ctx *ctx, void *hip_stream);
+
+/* Validate a problem and copy it to the device (program-flow step 2 output:
+ * energies, integrals, pair list).  Builds the packed monomer layout and the
+ * pair table; the result stays resident under *id.
+ * Errors: MCPT_ERR_INVALID (sizes, pairs out of range, X == Y, duplicate
+ * pair, max occupied energy >= min virtual energy of a monomer),
+ * MCPT_ERR_NONFINITE, MCPT_ERR_ADMISSION, MCPT_ERR_NOMEM, MCPT_ERR_DEVICE. */
+mcpt_status mcpt_upload(mcpt_ctx *ctx, const mcpt_problem *prob, uint64_t *id);
+
+/* Solve a resident problem (step 6: macro iterations of Eqs. 58-59 until
+ * converged, then Eqs. 54-56).  Writes *out (may be NULL).  Returns the
+ * solve's status: MCPT_OK, MCPT_ERR_NOT_CONVERGED (results are those of the
+ * last sweep), MCPT_ERR_DIVERGED (no results), MCPT_ERR_INVALID (options),
+ * MCPT_ERR_UNKNOWN_ID, MCPT_ERR_DEVICE. */
+mcpt_status mcpt_run(mcpt_ctx *ctx, uint64_t id, const mcpt_options *opts, mcpt_summary *out);
+
+/* mcpt_upload followed by mcpt_run; the problem stays resident under *id. */
+mcpt_status mcpt_solve(mcpt_ctx *ctx, const mcpt_problem *prob, const mcpt_options *opts,
+                       uint64_t *id, mcpt_summary *out);
+
+/* Per-monomer and per-pair results of the last run of a resident problem.
+ * e_m2[N]: E_M2(X) (Eq. 54); de_m2[N]: E_M2(X) minus its zero-coupling value
+ * (Eq. 56); e_d2[P]: E_D2 of each stored pair (Eq. 55); t_amp[sum_X o^2 v^2]:
+ * T_X[i][j][a][b] = T^{ab}_{ij}, monomers concatenated.  Any may be NULL.
+ * Errors: MCPT_ERR_UNKNOWN_ID, MCPT_ERR_INVALID (never run), MCPT_ERR_DEVICE. */
+mcpt_status mcpt_energy(mcpt_ctx *ctx, uint64_t id, double *e_m2, double *de_m2, double *e_d2,
+                        double *t_amp);
+
+/* Free a resident problem. Errors: MCPT_ERR_UNKNOWN_ID. */
+mcpt_status mcpt_release(mcpt_ctx *ctx, uint64_t id);
+
+/* Enable (1) or disable (0) per-launch kernel timing; enabling resets the totals. */
+mcpt_status mcpt_set_timing(mcpt_ctx *ctx, int enable);
+
+/* Read the timing totals since timing was enabled. */
+mcpt_status mcpt_timing_read(mcpt_ctx *ctx, mcpt_timing *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCPT_H */

@@ -1,0 +1,637 @@
+// C ABI and host runtime of the MCPT(2) hot path: validation and upload of a
+// problem (program flow step 2 output), the sweep driver of step 6, and the
+// energy read-back (Eqs. 54-56).  See include/mcpt.h for the contract.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/mcpt.h"
+#include "mcpt_internal.hpp"
+
+using namespace mcpt;
+
+namespace {
+
+thread_local std::string g_err;
+
+mcpt_status fail(mcpt_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(MCPT_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Resident {
+    uint64_t id = 0;
+    int n_mono = 0;
+    int64_t n_pair = 0;
+    int max_n = 0, max_np = 0;
+    int64_t eps_elems = 0, raw_elems = 0, mat_elems = 0, v_elems = 0, max_slot = 0;
+    std::vector<MonoDesc> monos;
+    std::vector<PairDesc> pairs;      // sorted for locality; .orig is the caller's index
+    // device
+    MonoDesc* d_monos = nullptr;
+    PairDesc* d_pairs = nullptr;
+    double *d_eps = nullptr, *d_raw = nullptr, *d_K = nullptr, *d_T = nullptr, *d_M = nullptr;
+    double *d_G[2] = {nullptr, nullptr};
+    double* d_V = nullptr;
+    double *d_em2 = nullptr, *d_em2_0 = nullptr, *d_ed2 = nullptr, *d_res = nullptr;
+    std::vector<void*> allocations;
+    size_t bytes = 0;
+    bool has_result = false;
+    mcpt_summary last{};
+};
+
+struct Timing {
+    bool on = false;
+    struct Rec {
+        hipEvent_t a, b;
+        int kind;   // 0 pair, 1 monomer
+        double flops, vbytes;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    mcpt_timing tot{};
+};
+
+}  // namespace
+
+struct mcpt_ctx {
+    int device = 0;
+    int n_cu = 0;
+    hipStream_t own = nullptr;
+    hipStream_t stream = nullptr;
+    size_t budget = 0, in_use = 0;
+    uint64_t next_id = 1;
+    std::map<uint64_t, std::unique_ptr<Resident>> res;
+    Ctrl* d_ctrl = nullptr;
+    Ctrl* h_ctrl = nullptr;             // pinned
+    int32_t* d_flag = nullptr;
+    int32_t* h_flag = nullptr;          // pinned
+    double* d_scratch = nullptr;
+    int64_t scratch_slot = 0;
+    int scratch_slots = 0;
+    int pair_grid = 0;
+    Timing timing;
+};
+
+namespace {
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+mcpt_status ensure_device(mcpt_ctx* c) {
+    HIP_TRY(hipSetDevice(c->device));
+    return MCPT_OK;
+}
+
+void free_resident(mcpt_ctx* c, Resident* r) {
+    for (void* p : r->allocations) (void)hipFree(p);
+    r->allocations.clear();
+    c->in_use -= std::min(c->in_use, r->bytes);
+    r->bytes = 0;
+}
+
+template <class T>
+mcpt_status dev_alloc(mcpt_ctx* c, Resident* r, T** out, int64_t count) {
+    size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    bytes = (bytes + 255) / 256 * 256;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MCPT_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                        hipGetErrorString(e));
+    }
+    r->allocations.push_back(p);
+    r->bytes += bytes;
+    c->in_use += bytes;
+    *out = static_cast<T*>(p);
+    return MCPT_OK;
+}
+
+hipEvent_t take_event(Timing& t) {
+    if (!t.pool.empty()) {
+        hipEvent_t e = t.pool.back();
+        t.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+void drain_timing(Timing& t) {
+    for (auto& r : t.pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            if (r.kind == 0) {
+                t.tot.pair_ms += ms;
+                t.tot.pair_launches += 1;
+                t.tot.pair_flops += r.flops;
+                t.tot.pair_v_bytes += r.vbytes;
+            } else {
+                t.tot.mono_ms += ms;
+                t.tot.mono_launches += 1;
+            }
+        }
+        t.pool.push_back(r.a);
+        t.pool.push_back(r.b);
+    }
+    t.pending.clear();
+}
+
+mcpt_status ensure_scratch(mcpt_ctx* c, int64_t slot_elems) {
+    const int per_cu = pair_fp64_blocks_per_cu();
+    int grid = c->n_cu * per_cu;
+    grid = std::max(8, grid / 8 * 8);
+    if (c->d_scratch && c->scratch_slot >= slot_elems && c->scratch_slots >= grid) {
+        c->pair_grid = grid;
+        return MCPT_OK;
+    }
+    if (c->d_scratch) {
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        (void)hipFree(c->d_scratch);
+        c->d_scratch = nullptr;
+    }
+    const int64_t slot = std::max<int64_t>(slot_elems, c->scratch_slot);
+    hipError_t e = hipMalloc(&c->d_scratch, (size_t)slot * grid * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c->d_scratch = nullptr;
+        return fail(MCPT_ERR_NOMEM, "scratch allocation failed");
+    }
+    c->scratch_slot = slot;
+    c->scratch_slots = grid;
+    c->pair_grid = grid;
+    return MCPT_OK;
+}
+
+double pair_flops(const Resident& r, bool couple) {
+    double f = 0.0;
+    for (const auto& p : r.pairs) {
+        const double nx = r.monos[p.x].n, ny = r.monos[p.y].n;
+        f += (couple ? 4.0 : 2.0) * nx * ny * (nx + ny);
+    }
+    return f;
+}
+
+mcpt_status validate_problem(const mcpt_problem* pb) {
+    if (!pb) return fail(MCPT_ERR_INVALID, "problem is NULL");
+    if (pb->n_mono < 1) return fail(MCPT_ERR_INVALID, "n_mono must be >= 1");
+    if (!pb->n_occ || !pb->n_vir || !pb->eps || !pb->k_intra)
+        return fail(MCPT_ERR_INVALID, "n_occ, n_vir, eps and k_intra must be non-NULL");
+    if (pb->n_pair < 0) return fail(MCPT_ERR_INVALID, "n_pair must be >= 0");
+    if (pb->n_pair > 0 && (!pb->pair || !pb->v_dimer))
+        return fail(MCPT_ERR_INVALID, "pair and v_dimer must be non-NULL when n_pair > 0");
+    if (pb->memory != MCPT_HOST && pb->memory != MCPT_DEVICE)
+        return fail(MCPT_ERR_INVALID, "memory must be MCPT_HOST or MCPT_DEVICE");
+    for (int x = 0; x < pb->n_mono; ++x) {
+        const int o = pb->n_occ[x], v = pb->n_vir[x];
+        if (o < 1 || v < 1) return fail(MCPT_ERR_INVALID, "monomer " + std::to_string(x) + ": o, v must be >= 1");
+        if ((int64_t)o * v > 4096)
+            return fail(MCPT_ERR_INVALID, "monomer " + std::to_string(x) + ": o*v > 4096 not supported");
+    }
+    std::unordered_set<uint64_t> seen;
+    seen.reserve((size_t)pb->n_pair * 2);
+    for (int64_t p = 0; p < pb->n_pair; ++p) {
+        const int x = pb->pair[2 * p], y = pb->pair[2 * p + 1];
+        if (x < 0 || y < 0 || x >= pb->n_mono || y >= pb->n_mono)
+            return fail(MCPT_ERR_INVALID, "pair " + std::to_string(p) + " out of range");
+        if (x == y) return fail(MCPT_ERR_INVALID, "pair " + std::to_string(p) + " has X == Y");
+        const uint64_t key = ((uint64_t)std::min(x, y) << 32) | (uint32_t)std::max(x, y);
+        if (!seen.insert(key).second)
+            return fail(MCPT_ERR_INVALID, "pair " + std::to_string(p) + " duplicates an earlier pair");
+    }
+    return MCPT_OK;
+}
+
+mcpt_status check_energies(const std::vector<double>& eps, const mcpt_problem* pb) {
+    int64_t off = 0;
+    for (int x = 0; x < pb->n_mono; ++x) {
+        const int o = pb->n_occ[x], v = pb->n_vir[x];
+        double omax = -INFINITY, vmin = INFINITY;
+        for (int k = 0; k < o + v; ++k) {
+            const double e = eps[off + k];
+            if (!std::isfinite(e)) return fail(MCPT_ERR_NONFINITE, "non-finite orbital energy of monomer " + std::to_string(x));
+            if (k < o) omax = std::max(omax, e);
+            else vmin = std::min(vmin, e);
+        }
+        if (!(omax < vmin))
+            return fail(MCPT_ERR_INVALID, "monomer " + std::to_string(x) +
+                                              ": max occupied energy >= min virtual energy (denominator >= 0)");
+        off += o + v;
+    }
+    return MCPT_OK;
+}
+
+mcpt_status upload(mcpt_ctx* c, const mcpt_problem* pb, uint64_t* id_out) {
+    mcpt_status st = validate_problem(pb);
+    if (st != MCPT_OK) return st;
+    if (!id_out) return fail(MCPT_ERR_INVALID, "id is NULL");
+    if ((st = ensure_device(c)) != MCPT_OK) return st;
+    auto r = std::make_unique<Resident>();
+    r->n_mono = pb->n_mono;
+    r->n_pair = pb->n_pair;
+    r->monos.resize(pb->n_mono);
+    int64_t eoff = 0, roff = 0, moff = 0;
+    for (int x = 0; x < pb->n_mono; ++x) {
+        MonoDesc& d = r->monos[x];
+        d.o = pb->n_occ[x];
+        d.v = pb->n_vir[x];
+        d.n = d.o * d.v;
+        d.np = round_up(d.n, kTile);
+        d.eps_off = eoff;
+        d.raw_off = roff;
+        d.mat_off = moff;
+        eoff += d.o + d.v;
+        roff += (int64_t)d.n * d.n;
+        moff += (int64_t)d.np * d.np;
+        r->max_n = std::max(r->max_n, d.n);
+        r->max_np = std::max(r->max_np, d.np);
+    }
+    r->eps_elems = eoff;
+    r->raw_elems = roff;
+    r->mat_elems = moff;
+    // pairs: caller order gives V offsets; processing order is sorted by (min, max) monomer
+    std::vector<int64_t> voff(pb->n_pair);
+    int64_t vo = 0;
+    for (int64_t p = 0; p < pb->n_pair; ++p) {
+        voff[p] = vo;
+        vo += (int64_t)r->monos[pb->pair[2 * p]].n * r->monos[pb->pair[2 * p + 1]].n;
+    }
+    r->v_elems = vo;
+    r->pairs.resize(pb->n_pair);
+    for (int64_t p = 0; p < pb->n_pair; ++p) {
+        PairDesc& d = r->pairs[p];
+        d.x = pb->pair[2 * p];
+        d.y = pb->pair[2 * p + 1];
+        d.v_off = voff[p];
+        d.orig = p;
+        r->max_slot = std::max<int64_t>(r->max_slot, (int64_t)r->monos[d.x].np * r->monos[d.y].np);
+    }
+    std::stable_sort(r->pairs.begin(), r->pairs.end(), [](const PairDesc& a, const PairDesc& b) {
+        const int a0 = std::min(a.x, a.y), b0 = std::min(b.x, b.y);
+        if (a0 != b0) return a0 < b0;
+        return std::max(a.x, a.y) < std::max(b.x, b.y);
+    });
+    // energies: validated on the host (small)
+    std::vector<double> eps(eoff);
+    if (pb->memory == MCPT_HOST) {
+        std::memcpy(eps.data(), pb->eps, eoff * sizeof(double));
+    } else {
+        HIP_TRY(hipMemcpy(eps.data(), pb->eps, eoff * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    if ((st = check_energies(eps, pb)) != MCPT_OK) return st;
+    // footprint and admission
+    const size_t need = sizeof(double) * ((size_t)eoff + r->raw_elems + 5 * (size_t)r->mat_elems +
+                                          r->v_elems + 3 * (size_t)pb->n_mono + pb->n_pair) +
+                        r->monos.size() * sizeof(MonoDesc) + r->pairs.size() * sizeof(PairDesc);
+    if (c->in_use + need > c->budget)
+        return fail(MCPT_ERR_ADMISSION, "problem needs " + std::to_string(need) + " bytes; budget " +
+                                            std::to_string(c->budget) + ", in use " + std::to_string(c->in_use));
+    Resident* R = r.get();
+#define ALLOC(ptr, n)                                          \
+    do {                                                       \
+        if ((st = dev_alloc(c, R, &(ptr), (n))) != MCPT_OK) { \
+            free_resident(c, R);                               \
+            return st;                                         \
+        }                                                      \
+    } while (0)
+    ALLOC(R->d_monos, R->n_mono);
+    ALLOC(R->d_pairs, std::max<int64_t>(R->n_pair, 1));
+    ALLOC(R->d_eps, eoff);
+    ALLOC(R->d_raw, R->raw_elems);
+    ALLOC(R->d_K, R->mat_elems);
+    ALLOC(R->d_T, R->mat_elems);
+    ALLOC(R->d_M, R->mat_elems);
+    ALLOC(R->d_G[0], R->mat_elems);
+    ALLOC(R->d_G[1], R->mat_elems);
+    ALLOC(R->d_V, std::max<int64_t>(R->v_elems, 1));
+    ALLOC(R->d_em2, R->n_mono);
+    ALLOC(R->d_em2_0, R->n_mono);
+    ALLOC(R->d_res, R->n_mono);
+    ALLOC(R->d_ed2, std::max<int64_t>(R->n_pair, 1));
+#undef ALLOC
+    hipStream_t s = c->stream;
+    const hipMemcpyKind kind = pb->memory == MCPT_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+#define DTRY(expr)                   \
+    do {                             \
+        hipError_t e_ = (expr);      \
+        if (e_ != hipSuccess) {      \
+            free_resident(c, R);     \
+            return fail(MCPT_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+        }                            \
+    } while (0)
+    DTRY(hipMemcpyAsync(R->d_monos, R->monos.data(), R->monos.size() * sizeof(MonoDesc), hipMemcpyHostToDevice, s));
+    if (R->n_pair)
+        DTRY(hipMemcpyAsync(R->d_pairs, R->pairs.data(), R->pairs.size() * sizeof(PairDesc), hipMemcpyHostToDevice, s));
+    DTRY(hipMemcpyAsync(R->d_eps, eps.data(), eoff * sizeof(double), hipMemcpyHostToDevice, s));
+    DTRY(hipMemcpyAsync(R->d_raw, pb->k_intra, R->raw_elems * sizeof(double), kind, s));
+    if (R->v_elems) DTRY(hipMemcpyAsync(R->d_V, pb->v_dimer, R->v_elems * sizeof(double), kind, s));
+    *c->h_flag = 0;
+    DTRY(hipMemcpyAsync(c->d_flag, c->h_flag, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    launch_nonfinite(R->d_raw, R->raw_elems, c->d_flag, s);
+    launch_nonfinite(R->d_V, R->v_elems, c->d_flag, s);
+    launch_fill(R->d_K, R->mat_elems, 0.0, s);
+    launch_fill(R->d_T, R->mat_elems, 0.0, s);
+    launch_fill(R->d_M, R->mat_elems, 0.0, s);
+    launch_fill(R->d_G[0], R->mat_elems, 0.0, s);
+    launch_fill(R->d_G[1], R->mat_elems, 0.0, s);
+    launch_pack(R->d_monos, R->n_mono, R->d_raw, R->d_K, R->max_n, s);
+    DTRY(hipGetLastError());
+    DTRY(hipMemcpyAsync(c->h_flag, c->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DTRY(hipStreamSynchronize(s));
+#undef DTRY
+    if (*c->h_flag) {
+        free_resident(c, R);
+        return fail(MCPT_ERR_NONFINITE, "non-finite value in k_intra or v_dimer");
+    }
+    r->id = c->next_id++;
+    *id_out = r->id;
+    c->res[r->id] = std::move(r);
+    return MCPT_OK;
+}
+
+mcpt_status validate_options(const mcpt_options* o) {
+    if (!o) return fail(MCPT_ERR_INVALID, "options are NULL");
+    if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(MCPT_ERR_INVALID, "tol must be finite and >= 0");
+    if (o->max_sweeps < 0 || o->max_sweeps >= kMaxSweeps)
+        return fail(MCPT_ERR_INVALID, "max_sweeps must be in [0, " + std::to_string(kMaxSweeps - 1) + "]");
+    if (o->precision != MCPT_FP64)
+        return fail(MCPT_ERR_INVALID, "precision not supported by this build");
+    if (o->check_every < 0) return fail(MCPT_ERR_INVALID, "check_every must be >= 0");
+    return MCPT_OK;
+}
+
+void record_begin(mcpt_ctx* c, hipEvent_t* a) {
+    if (!c->timing.on) return;
+    *a = take_event(c->timing);
+    (void)hipEventRecord(*a, c->stream);
+}
+
+void record_end(mcpt_ctx* c, hipEvent_t a, int kind, double flops, double vbytes) {
+    if (!c->timing.on) return;
+    hipEvent_t b = take_event(c->timing);
+    (void)hipEventRecord(b, c->stream);
+    c->timing.pending.push_back({a, b, kind, flops, vbytes});
+}
+
+mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* out) {
+    mcpt_status st = validate_options(o);
+    if (st != MCPT_OK) return st;
+    if ((st = ensure_device(c)) != MCPT_OK) return st;
+    if ((st = ensure_scratch(c, R->max_slot)) != MCPT_OK) return st;
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = c->stream;
+    R->has_result = false;
+    Ctrl& h = *c->h_ctrl;
+    std::memset(&h, 0, offsetof(Ctrl, hist));
+    h.fixed = o->tol == 0.0;
+    h.max_sweeps = o->max_sweeps;
+    h.tol = o->tol;
+    HIP_TRY(hipMemcpyAsync(c->d_ctrl, &h, offsetof(Ctrl, hist), hipMemcpyHostToDevice, s));
+    launch_fill(R->d_G[0], R->mat_elems, 0.0, s);
+    launch_fill(R->d_G[1], R->mat_elems, 0.0, s);
+    if (o->warm_t) {
+        HIP_TRY(hipMemcpyAsync(R->d_raw, o->warm_t, R->raw_elems * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_fill(R->d_T, R->mat_elems, 0.0, s);
+        launch_pack(R->d_monos, R->n_mono, R->d_raw, R->d_T, R->max_n, s);
+        launch_monomer(kMonoE0, R->d_monos, R->n_mono, R->d_eps, R->d_K, nullptr, nullptr, R->d_T, R->d_M,
+                       R->d_em2, R->d_em2_0, R->d_res, nullptr, R->max_np, s);
+        launch_monomer(kMonoFromT, R->d_monos, R->n_mono, R->d_eps, R->d_K, nullptr, nullptr, R->d_T,
+                       R->d_M, R->d_em2, R->d_em2_0, R->d_res, nullptr, R->max_np, s);
+    } else {
+        launch_monomer(kMonoInit, R->d_monos, R->n_mono, R->d_eps, R->d_K, nullptr, nullptr, R->d_T, R->d_M,
+                       R->d_em2, R->d_em2_0, R->d_res, nullptr, R->max_np, s);
+    }
+    HIP_TRY(hipGetLastError());
+    const double fl_sweep = pair_flops(*R, true), fl_final = pair_flops(*R, false);
+    const double vb = (double)R->v_elems * sizeof(double);
+    const int every = o->check_every > 0 ? o->check_every : 1;
+    int issued = 0, cur = 0;
+    while (issued < o->max_sweeps) {
+        const int batch = std::min(every, o->max_sweeps - issued);
+        for (int k = 0; k < batch; ++k) {
+            hipEvent_t a = nullptr;
+            record_begin(c, &a);
+            launch_pair_fp64(R->d_pairs, R->n_pair, R->d_monos, R->d_eps, R->d_V, R->d_M, R->d_G[cur],
+                             c->d_scratch, c->scratch_slot, c->pair_grid, R->d_ed2, 1, c->d_ctrl, s);
+            record_end(c, a, 0, fl_sweep, vb);
+            record_begin(c, &a);
+            launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->d_eps, R->d_K, R->d_G[cur], R->d_G[cur ^ 1],
+                           R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, c->d_ctrl, R->max_np, s);
+            record_end(c, a, 1, 0.0, 0.0);
+            launch_reduce_sweep(R->n_mono, R->d_res, c->d_ctrl, s);
+            cur ^= 1;
+            ++issued;
+        }
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(&h, c->d_ctrl, offsetof(Ctrl, hist), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (h.done) break;
+    }
+    if (h.status == MCPT_ERR_DIVERGED) {
+        if (c->timing.on) drain_timing(c->timing);
+        mcpt_summary sm{};
+        sm.residual = h.residual;
+        sm.sweeps = h.sweeps;
+        sm.status = MCPT_ERR_DIVERGED;
+        sm.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        R->last = sm;
+        if (out) *out = sm;
+        return fail(MCPT_ERR_DIVERGED, "iteration diverged after " + std::to_string(h.sweeps) + " sweeps");
+    }
+    // energies of the returned amplitudes: Tau recomputed from the final T
+    {
+        hipEvent_t a = nullptr;
+        record_begin(c, &a);
+        launch_pair_fp64(R->d_pairs, R->n_pair, R->d_monos, R->d_eps, R->d_V, R->d_M, R->d_G[cur],
+                         c->d_scratch, c->scratch_slot, c->pair_grid, R->d_ed2, 0, nullptr, s);
+        record_end(c, a, 0, fl_final, vb);
+    }
+    launch_reduce_final(R->n_mono, R->n_pair, R->d_em2, R->d_em2_0, R->d_ed2, c->d_ctrl, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(&h, c->d_ctrl, offsetof(Ctrl, hist), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c->timing.on) drain_timing(c->timing);
+    mcpt_summary sm{};
+    sm.e_mono = h.e_mono;
+    sm.e_dimer = h.e_dimer;
+    sm.e_total = h.e_mono + h.e_dimer;
+    sm.e_mono0 = h.e_mono0;
+    sm.residual = h.residual;
+    sm.sweeps = h.sweeps;
+    sm.polish_sweeps = 0;
+    if (h.fixed) sm.status = MCPT_OK;
+    else if (h.sweeps > 0 && h.residual < o->tol) sm.status = MCPT_OK;
+    else sm.status = MCPT_ERR_NOT_CONVERGED;
+    sm.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    R->has_result = true;
+    R->last = sm;
+    if (out) *out = sm;
+    if (sm.status != MCPT_OK)
+        return fail((mcpt_status)sm.status, "not converged after " + std::to_string(h.sweeps) + " sweeps");
+    g_err.clear();
+    return MCPT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mcpt_status mcpt_create(int device, size_t hbm_budget_bytes, mcpt_ctx** out) {
+    if (!out) return fail(MCPT_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+        return fail(MCPT_ERR_INVALID, "no HIP device " + std::to_string(device));
+    auto c = std::make_unique<mcpt_ctx>();
+    c->device = device;
+    HIP_TRY(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    c->n_cu = prop.multiProcessorCount;
+    HIP_TRY(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+    c->stream = c->own;
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
+    HIP_TRY(hipMalloc(&c->d_ctrl, sizeof(Ctrl)));
+    HIP_TRY(hipHostMalloc(&c->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
+    HIP_TRY(hipMalloc(&c->d_flag, sizeof(int32_t)));
+    HIP_TRY(hipHostMalloc(&c->h_flag, sizeof(int32_t), hipHostMallocDefault));
+    g_err.clear();
+    *out = c.release();
+    return MCPT_OK;
+}
+
+void mcpt_destroy(mcpt_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->res) free_resident(c, kv.second.get());
+    c->res.clear();
+    if (c->timing.on) drain_timing(c->timing);
+    for (hipEvent_t e : c->timing.pool) (void)hipEventDestroy(e);
+    if (c->d_scratch) (void)hipFree(c->d_scratch);
+    if (c->d_ctrl) (void)hipFree(c->d_ctrl);
+    if (c->d_flag) (void)hipFree(c->d_flag);
+    if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
+    if (c->h_flag) (void)hipHostFree(c->h_flag);
+    if (c->own) (void)hipStreamDestroy(c->own);
+    delete c;
+}
+
+const char* mcpt_last_error(void) { return g_err.c_str(); }
+
+mcpt_status mcpt_set_stream(mcpt_ctx* c, void* hip_stream) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->own;
+    return MCPT_OK;
+}
+
+mcpt_status mcpt_upload(mcpt_ctx* c, const mcpt_problem* prob, uint64_t* id) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    try {
+        return upload(c, prob, id);
+    } catch (const std::exception& e) {
+        return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
+    }
+}
+
+mcpt_status mcpt_run(mcpt_ctx* c, uint64_t id, const mcpt_options* opts, mcpt_summary* out) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    auto it = c->res.find(id);
+    if (it == c->res.end()) return fail(MCPT_ERR_UNKNOWN_ID, "unknown problem id " + std::to_string(id));
+    try {
+        return run(c, it->second.get(), opts, out);
+    } catch (const std::exception& e) {
+        return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
+    }
+}
+
+mcpt_status mcpt_solve(mcpt_ctx* c, const mcpt_problem* prob, const mcpt_options* opts, uint64_t* id,
+                       mcpt_summary* out) {
+    mcpt_status st = validate_options(opts);
+    if (st != MCPT_OK) return st;
+    uint64_t local = 0;
+    st = mcpt_upload(c, prob, &local);
+    if (st != MCPT_OK) return st;
+    if (id) *id = local;
+    return mcpt_run(c, local, opts, out);
+}
+
+mcpt_status mcpt_energy(mcpt_ctx* c, uint64_t id, double* e_m2, double* de_m2, double* e_d2, double* t_amp) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    auto it = c->res.find(id);
+    if (it == c->res.end()) return fail(MCPT_ERR_UNKNOWN_ID, "unknown problem id " + std::to_string(id));
+    Resident* R = it->second.get();
+    if (!R->has_result) return fail(MCPT_ERR_INVALID, "problem has no result (not run, or diverged)");
+    mcpt_status st = ensure_device(c);
+    if (st != MCPT_OK) return st;
+    hipStream_t s = c->stream;
+    std::vector<double> a(R->n_mono), b(R->n_mono);
+    HIP_TRY(hipMemcpyAsync(a.data(), R->d_em2, R->n_mono * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(b.data(), R->d_em2_0, R->n_mono * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (e_d2 && R->n_pair)
+        HIP_TRY(hipMemcpyAsync(e_d2, R->d_ed2, R->n_pair * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (t_amp) {
+        launch_unpack(R->d_monos, R->n_mono, R->d_T, R->d_raw, R->max_n, s);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(t_amp, R->d_raw, R->raw_elems * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int x = 0; x < R->n_mono; ++x) {
+        if (e_m2) e_m2[x] = a[x];
+        if (de_m2) de_m2[x] = a[x] - b[x];
+    }
+    return MCPT_OK;
+}
+
+mcpt_status mcpt_release(mcpt_ctx* c, uint64_t id) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    auto it = c->res.find(id);
+    if (it == c->res.end()) return fail(MCPT_ERR_UNKNOWN_ID, "unknown problem id " + std::to_string(id));
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    free_resident(c, it->second.get());
+    c->res.erase(it);
+    return MCPT_OK;
+}
+
+mcpt_status mcpt_set_timing(mcpt_ctx* c, int enable) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    drain_timing(c->timing);
+    c->timing.on = enable != 0;
+    c->timing.tot = mcpt_timing{};
+    return MCPT_OK;
+}
+
+mcpt_status mcpt_timing_read(mcpt_ctx* c, mcpt_timing* out) {
+    if (!c || !out) return fail(MCPT_ERR_INVALID, "ctx or out is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    drain_timing(c->timing);
+    *out = c->timing.tot;
+    return MCPT_OK;
+}
+
+}  // extern "C"

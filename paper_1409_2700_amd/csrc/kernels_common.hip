@@ -1,0 +1,254 @@
+// Elementwise and reduction kernels of the MCPT(2) path: layout packing, the
+// monomer phase (Eq. 58 divided by its denominators, Eq. 54 energy) and the
+// per-sweep residual / stopping rule.
+#include <cfloat>
+#include <cmath>
+
+#include "mcpt_internal.hpp"
+
+namespace mcpt {
+
+namespace {
+
+constexpr int kMonoThreads = 256;
+constexpr int kReduceThreads = 1024;
+
+__global__ void fill_kernel(double* __restrict__ p, int64_t n, double value) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+// caller layout K[i][j][a][b] (o,o,v,v)  <->  packed np x np, row (i,a), column (j,b)
+__global__ void pack_kernel(const MonoDesc* __restrict__ monos, const double* __restrict__ raw,
+                            double* __restrict__ packed, int to_packed) {
+    const MonoDesc d = monos[blockIdx.x];
+    const int o = d.o, v = d.v, n = d.n, np = d.np;
+    const int nn = n * n;
+    for (int idx = blockIdx.y * blockDim.x + threadIdx.x; idx < nn; idx += gridDim.y * blockDim.x) {
+        const int r = idx / n, c = idx - r * n;
+        const int i = r / v, a = r - i * v;
+        const int j = c / v, b = c - j * v;
+        const int64_t ri = d.raw_off + ((int64_t)(i * o + j) * v + a) * v + b;
+        const int64_t pi = d.mat_off + (int64_t)r * np + c;
+        if (to_packed)
+            packed[pi] = raw[ri];
+        else
+            packed[ri] = raw[pi];   // here `raw` is the packed source and `packed` the caller layout
+    }
+}
+
+__global__ void nonfinite_kernel(const double* __restrict__ p, int64_t n, int32_t* flag) {
+    int bad = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(p[i]);
+    if (bad) *flag = 1;
+}
+
+template <int NT>
+__device__ double block_sum(double x, double* sh) {
+    sh[threadIdx.x] = x;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// max that propagates NaN (so a non-finite residual is seen by the stopping rule)
+__device__ inline double max_nan(double a, double b) { return (a != a || b != b) ? NAN : (a > b ? a : b); }
+
+template <int NT>
+__device__ double block_max(double x, double* sh) {
+    sh[threadIdx.x] = x;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = max_nan(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Monomer phase, one workgroup per monomer.  For element (r, c) = ((i,a),(j,b))
+// the occupied-swapped partner S(r, c) = ((j,a),(i,b)) has the same denominator
+// e_i + e_j - e_a - e_b (Eqs. 60-61); both T values are formed by the same
+// thread so M = 2T - S(T) (the spin-adapted combination of Eq. 59) needs no
+// second pass.  E_M2 = <2K - S(K), T> = <K, M> (Eq. 54).
+__global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
+    int mode, const MonoDesc* __restrict__ monos, const double* __restrict__ eps,
+    const double* __restrict__ K, const double* __restrict__ G, double* __restrict__ Gz,
+    double* __restrict__ T, double* __restrict__ M, double* __restrict__ em2,
+    double* __restrict__ em2_0, double* __restrict__ res, const Ctrl* __restrict__ ctrl) {
+    if (ctrl && ctrl->done) return;
+    __shared__ double sh[kMonoThreads];
+    const int x = blockIdx.x;
+    const MonoDesc d = monos[x];
+    const int o = d.o, v = d.v, n = d.n, np = d.np;
+    const double* e = eps + d.eps_off;
+    const double* Kx = K + d.mat_off;
+    const double* Gx = G ? G + d.mat_off : nullptr;
+    double* Tx = T + d.mat_off;
+    double* Mx = M + d.mat_off;
+    double rmax = 0.0, esum = 0.0;
+    const int nn = n * n;
+    for (int idx = threadIdx.x; idx < nn; idx += kMonoThreads) {
+        const int r = idx / n, c = idx - r * n;
+        const int i = r / v, a = r - i * v;
+        const int j = c / v, b = c - j * v;
+        const int rs = j * v + a, cs = i * v + b;
+        const int64_t e_rc = (int64_t)r * np + c, e_s = (int64_t)rs * np + cs;
+        const double dinv = 1.0 / (((e[i] + e[j]) - e[o + a]) - e[o + b]);
+        double tn, ts;
+        if (mode == kMonoUpdate) {
+            tn = dinv * ((Kx[e_rc] + Gx[e_rc]) + Gx[(int64_t)c * np + r]);
+            ts = dinv * ((Kx[e_s] + Gx[e_s]) + Gx[(int64_t)cs * np + rs]);
+            const double dt = fabs(tn - Tx[e_rc]);
+            rmax = max_nan(rmax, dt);
+        } else if (mode == kMonoFromT) {
+            tn = Tx[e_rc];
+            ts = Tx[e_s];
+        } else {
+            tn = dinv * Kx[e_rc];
+            ts = dinv * Kx[e_s];
+        }
+        const double m = 2.0 * tn - ts;
+        esum += Kx[e_rc] * m;
+        if (mode == kMonoInit || mode == kMonoUpdate) {
+            Tx[e_rc] = tn;
+            Mx[e_rc] = m;
+        } else if (mode == kMonoFromT) {
+            Mx[e_rc] = m;
+        }
+    }
+    if (Gz) {
+        double* gz = Gz + d.mat_off;
+        const int npp = np * np;
+        for (int idx = threadIdx.x; idx < npp; idx += kMonoThreads) gz[idx] = 0.0;
+    }
+    const double etot = block_sum<kMonoThreads>(esum, sh);
+    const double rtot = block_max<kMonoThreads>(rmax, sh);
+    if (threadIdx.x == 0) {
+        if (mode == kMonoE0) {
+            em2_0[x] = etot;
+        } else {
+            em2[x] = etot;
+            if (mode == kMonoInit) em2_0[x] = etot;
+            if (mode == kMonoUpdate) res[x] = rtot;
+        }
+    }
+}
+
+// Stopping rule, same as the oracle's: converged when r < tol; diverged when
+// r is not finite, r > 1e6 r_1, or r rose in each of the last three sweeps and
+// exceeds r_1; not converged when max_sweeps sweeps ran.
+__global__ __launch_bounds__(kReduceThreads) void reduce_sweep_kernel(
+    int n_mono, const double* __restrict__ res, Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ double sh[kReduceThreads];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < n_mono; i += kReduceThreads) m = max_nan(m, res[i]);
+    const double r = block_max<kReduceThreads>(m, sh);
+    if (threadIdx.x != 0) return;
+    const int s = ctrl->sweeps;
+    ctrl->hist[s] = r;
+    ctrl->sweeps = s + 1;
+    ctrl->residual = r;
+    const double* h = ctrl->hist;
+    int status = 0, done = 0;
+    if (!(r <= DBL_MAX)) {
+        status = -5;
+        done = 1;
+    } else if (!ctrl->fixed) {
+        if (r < ctrl->tol) {
+            done = 1;
+        } else if (r > 1e6 * h[0] ||
+                   (s >= 3 && h[s] > h[s - 1] && h[s - 1] > h[s - 2] && h[s - 2] > h[s - 3] && r > h[0])) {
+            status = -5;
+            done = 1;
+        } else if (s + 1 >= ctrl->max_sweeps) {
+            status = -4;
+            done = 1;
+        }
+    } else if (s + 1 >= ctrl->max_sweeps) {
+        done = 1;
+    }
+    ctrl->status = status;
+    ctrl->done = done;
+}
+
+__global__ __launch_bounds__(kReduceThreads) void reduce_final_kernel(
+    int n_mono, int64_t n_pair, const double* __restrict__ em2, const double* __restrict__ em2_0,
+    const double* __restrict__ ed2, Ctrl* __restrict__ ctrl) {
+    __shared__ double sh[kReduceThreads];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < n_mono; i += kReduceThreads) {
+        a += em2[i];
+        c += em2_0[i];
+    }
+    for (int64_t i = threadIdx.x; i < n_pair; i += kReduceThreads) b += ed2[i];
+    a = block_sum<kReduceThreads>(a, sh);
+    b = block_sum<kReduceThreads>(b, sh);
+    c = block_sum<kReduceThreads>(c, sh);
+    if (threadIdx.x == 0) {
+        ctrl->e_mono = a;
+        ctrl->e_dimer = b;
+        ctrl->e_mono0 = c;
+    }
+}
+
+int grid_for(int64_t n, int threads) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (int)g;
+}
+
+}  // namespace
+
+void launch_fill(double* p, int64_t n, double value, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, value);
+}
+
+void launch_pack(const MonoDesc* monos, int n_mono, const double* raw, double* packed, int max_n,
+                 hipStream_t s) {
+    const int gy = (max_n * max_n + 255) / 256 > 64 ? 64 : (max_n * max_n + 255) / 256;
+    hipLaunchKernelGGL(pack_kernel, dim3(n_mono, gy), dim3(256), 0, s, monos, raw, packed, 1);
+}
+
+void launch_unpack(const MonoDesc* monos, int n_mono, const double* packed, double* raw, int max_n,
+                   hipStream_t s) {
+    const int gy = (max_n * max_n + 255) / 256 > 64 ? 64 : (max_n * max_n + 255) / 256;
+    hipLaunchKernelGGL(pack_kernel, dim3(n_mono, gy), dim3(256), 0, s, monos, packed, raw, 0);
+}
+
+void launch_nonfinite(const double* p, int64_t n, int32_t* flag, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(grid_for(n, 256) > 4096 ? 4096 : grid_for(n, 256)),
+                       dim3(256), 0, s, p, n, flag);
+}
+
+void launch_monomer(int mode, const MonoDesc* monos, int n_mono, const double* eps, const double* K,
+                    const double* G, double* G_zero, double* T, double* M, double* em2,
+                    double* em2_0, double* res, const Ctrl* ctrl, int /*max_np*/, hipStream_t s) {
+    hipLaunchKernelGGL(monomer_kernel, dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, eps, K,
+                       G, G_zero, T, M, em2, em2_0, res, ctrl);
+}
+
+void launch_reduce_sweep(int n_mono, const double* res, Ctrl* ctrl, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_sweep_kernel, dim3(1), dim3(kReduceThreads), 0, s, n_mono, res, ctrl);
+}
+
+void launch_reduce_final(int n_mono, int64_t n_pair, const double* em2, const double* em2_0,
+                         const double* ed2, Ctrl* ctrl, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(kReduceThreads), 0, s, n_mono, n_pair, em2,
+                       em2_0, ed2, ctrl);
+}
+
+}  // namespace mcpt

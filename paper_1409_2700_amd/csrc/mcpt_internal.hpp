@@ -1,0 +1,82 @@
+// Internal declarations of the MCPT(2) HIP path (not part of the C ABI).
+//
+// Device layout of a resident problem:
+//   monomer X: o, v, n = o*v, np = n rounded up to 16; every per-monomer
+//   matrix (K, T, M, G) is np x np, row-major, row (i,a) = i*v + a, column
+//   (j,b) = j*v + b, zero in the padding; matrices of all monomers are
+//   concatenated at mat_off.
+//   pair p = (X, Y): V_XY stored as given, nX x nY row-major (unpadded), at v_off.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mcpt {
+
+constexpr int kTile = 16;              // MFMA tile edge; matrices are padded to a multiple
+constexpr int kMaxSweeps = 4096;       // length of the device residual history
+
+struct MonoDesc {
+    int32_t o, v, n, np;
+    int64_t eps_off;                   // first energy of X in eps
+    int64_t mat_off;                   // first element of X's np x np matrices
+    int64_t raw_off;                   // first element of X's o*o*v*v block in caller layout
+};
+
+struct PairDesc {
+    int32_t x, y;                      // x is the row side (i,a) of V, y the column side (j,b)
+    int64_t v_off;                     // first element of V_XY
+    int64_t orig;                      // index of the pair in the caller's list
+};
+
+// Device-side iteration state.  The reduction kernel of every sweep appends
+// the residual, applies the stopping rules and sets `done`; sweep kernels
+// launched after that return at once, so a batch of sweeps issued ahead of a
+// host check ends exactly at the sweep that met the rule.
+struct Ctrl {
+    int32_t done;
+    int32_t status;                    // 0, or mcpt_status of a finished iteration
+    int32_t sweeps;                    // sweeps completed
+    int32_t fixed;                     // 1: run exactly max_sweeps, no convergence test
+    int32_t max_sweeps;
+    int32_t pad;
+    double tol;
+    double residual;                   // residual of the last sweep
+    double e_mono, e_dimer, e_mono0;   // sums written by the final reduction
+    double hist[kMaxSweeps];
+};
+
+enum MonoMode : int {
+    kMonoInit = 0,      // T = D*K, M, E_M2 -> em2 and em2_0
+    kMonoUpdate = 1,    // T' = D*(K + G + G^T), residual, M', E_M2(T')
+    kMonoFromT = 2,     // M and E_M2 from the T already stored
+    kMonoE0 = 3         // E_M2 of D*K into em2_0 only (warm starts)
+};
+
+// ---- launchers (kernels_common.hip) ----
+void launch_fill(double* p, int64_t n, double value, hipStream_t s);
+void launch_pack(const MonoDesc* monos, int n_mono, const double* raw, double* packed,
+                 int max_n, hipStream_t s);
+void launch_unpack(const MonoDesc* monos, int n_mono, const double* packed, double* raw,
+                   int max_n, hipStream_t s);
+void launch_nonfinite(const double* p, int64_t n, int32_t* flag, hipStream_t s);
+void launch_monomer(int mode, const MonoDesc* monos, int n_mono, const double* eps,
+                    const double* K, const double* G, double* G_zero, double* T, double* M,
+                    double* em2, double* em2_0, double* res, const Ctrl* ctrl, int max_np,
+                    hipStream_t s);
+void launch_reduce_sweep(int n_mono, const double* res, Ctrl* ctrl, hipStream_t s);
+void launch_reduce_final(int n_mono, int64_t n_pair, const double* em2, const double* em2_0,
+                         const double* ed2, Ctrl* ctrl, hipStream_t s);
+
+// ---- FP64 MFMA pair phase (pair_fp64.hip) ----
+// Eq. 59 (Tau from V, M_X, M_Y) and, if couple != 0, the Eq. 58 contractions
+// G_X += Tau V^T, G_Y += Tau^T V for every pair; E_D2 of every pair.
+void launch_pair_fp64(const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
+                      const double* eps, const double* V, const double* M, double* G,
+                      double* scratch, int64_t slot_elems, int grid, double* ed2, int couple,
+                      const Ctrl* ctrl, hipStream_t s);
+int pair_fp64_blocks_per_cu();
+
+}  // namespace mcpt

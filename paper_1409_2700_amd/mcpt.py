@@ -1,0 +1,259 @@
+"""Thin ctypes binding of libmcpt (include/mcpt.h): argument marshalling only.
+
+Every step of the solve runs inside the HIP library; this module only lays out
+the arguments.  Importing it fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmcpt.so")
+
+MCPT_OK = 0
+MCPT_PENDING = 1
+MCPT_ERR_INVALID = -1
+MCPT_ERR_NOMEM = -2
+MCPT_ERR_DEVICE = -3
+MCPT_ERR_NOT_CONVERGED = -4
+MCPT_ERR_DIVERGED = -5
+MCPT_ERR_NONFINITE = -6
+MCPT_ERR_ADMISSION = -7
+MCPT_ERR_UNKNOWN_ID = -8
+
+MCPT_FP64, MCPT_FP32, MCPT_BF16 = 0, 1, 2
+MCPT_HOST, MCPT_DEVICE = 0, 1
+
+STATUS_NAMES = {
+    0: "MCPT_OK", 1: "MCPT_PENDING", -1: "MCPT_ERR_INVALID", -2: "MCPT_ERR_NOMEM",
+    -3: "MCPT_ERR_DEVICE", -4: "MCPT_ERR_NOT_CONVERGED", -5: "MCPT_ERR_DIVERGED",
+    -6: "MCPT_ERR_NONFINITE", -7: "MCPT_ERR_ADMISSION", -8: "MCPT_ERR_UNKNOWN_ID",
+}
+
+# every symbol include/mcpt.h declares
+EXPORTS = [
+    "mcpt_create", "mcpt_destroy", "mcpt_last_error", "mcpt_set_stream", "mcpt_upload", "mcpt_run",
+    "mcpt_solve", "mcpt_energy", "mcpt_release", "mcpt_set_timing", "mcpt_timing_read",
+]
+
+
+class mcpt_problem(C.Structure):
+    _fields_ = [
+        ("n_mono", C.c_int32), ("n_occ", C.c_void_p), ("n_vir", C.c_void_p), ("eps", C.c_void_p),
+        ("k_intra", C.c_void_p), ("n_pair", C.c_int64), ("pair", C.c_void_p), ("v_dimer", C.c_void_p),
+        ("memory", C.c_int32),
+    ]
+
+
+class mcpt_options(C.Structure):
+    _fields_ = [
+        ("tol", C.c_double), ("max_sweeps", C.c_int32), ("precision", C.c_int32),
+        ("polish", C.c_int32), ("deterministic", C.c_int32), ("check_every", C.c_int32),
+        ("reserved", C.c_int32), ("warm_t", C.c_void_p),
+    ]
+
+
+class mcpt_summary(C.Structure):
+    _fields_ = [
+        ("e_total", C.c_double), ("e_mono", C.c_double), ("e_dimer", C.c_double),
+        ("e_mono0", C.c_double), ("residual", C.c_double), ("seconds", C.c_double),
+        ("sweeps", C.c_int32), ("polish_sweeps", C.c_int32), ("status", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class mcpt_timing(C.Structure):
+    _fields_ = [
+        ("pair_ms", C.c_double), ("mono_ms", C.c_double), ("pair_launches", C.c_int64),
+        ("mono_launches", C.c_int64), ("pair_flops", C.c_double), ("pair_v_bytes", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libmcpt.so is not built ({path}); run __graft_entry__.build() first")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    lib.mcpt_create.argtypes = [C.c_int, C.c_size_t, C.POINTER(P)]
+    lib.mcpt_destroy.argtypes = [P]
+    lib.mcpt_destroy.restype = None
+    lib.mcpt_last_error.restype = C.c_char_p
+    lib.mcpt_set_stream.argtypes = [P, P]
+    lib.mcpt_upload.argtypes = [P, C.POINTER(mcpt_problem), C.POINTER(C.c_uint64)]
+    lib.mcpt_run.argtypes = [P, C.c_uint64, C.POINTER(mcpt_options), C.POINTER(mcpt_summary)]
+    lib.mcpt_solve.argtypes = [P, C.POINTER(mcpt_problem), C.POINTER(mcpt_options),
+                               C.POINTER(C.c_uint64), C.POINTER(mcpt_summary)]
+    lib.mcpt_energy.argtypes = [P, C.c_uint64, P, P, P, P]
+    lib.mcpt_release.argtypes = [P, C.c_uint64]
+    lib.mcpt_set_timing.argtypes = [P, C.c_int]
+    lib.mcpt_timing_read.argtypes = [P, C.POINTER(mcpt_timing)]
+    for name in EXPORTS:
+        fn = getattr(lib, name)
+        if name not in ("mcpt_destroy", "mcpt_last_error"):
+            fn.restype = C.c_int
+    return lib
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+class MCPTError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _ptr(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _check(status: int, allow=()) -> int:
+    if status != MCPT_OK and status not in allow:
+        raise MCPTError(status, lib().mcpt_last_error().decode())
+    return status
+
+
+def last_error() -> str:
+    return lib().mcpt_last_error().decode()
+
+
+class HostProblem:
+    """Keeps the host arrays of a problem alive and exposes an mcpt_problem."""
+
+    def __init__(self, prob):
+        self.n_occ = np.ascontiguousarray(prob.n_occ, dtype=np.int32)
+        self.n_vir = np.ascontiguousarray(prob.n_vir, dtype=np.int32)
+        self.eps = np.ascontiguousarray(prob.eps, dtype=np.float64)
+        self.k = np.ascontiguousarray(prob.k, dtype=np.float64)
+        self.pairs = np.ascontiguousarray(prob.pairs, dtype=np.int32).reshape(-1, 2)
+        self.v = np.ascontiguousarray(prob.v, dtype=np.float64)
+        self.c = mcpt_problem(
+            n_mono=len(self.n_occ), n_occ=_ptr(self.n_occ), n_vir=_ptr(self.n_vir), eps=_ptr(self.eps),
+            k_intra=_ptr(self.k), n_pair=len(self.pairs), pair=_ptr(self.pairs), v_dimer=_ptr(self.v),
+            memory=MCPT_HOST)
+
+
+def make_options(tol=1e-10, max_sweeps=200, precision=MCPT_FP64, polish=1, deterministic=0,
+                 check_every=1, warm_t: np.ndarray | None = None):
+    o = mcpt_options(tol=tol, max_sweeps=max_sweeps, precision=precision, polish=polish,
+                     deterministic=deterministic, check_every=check_every, reserved=0,
+                     warm_t=_ptr(warm_t))
+    o._keep = warm_t
+    return o
+
+
+class Context:
+    """One device context (mcpt_create / mcpt_destroy)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        h = C.c_void_p()
+        _check(lib().mcpt_create(device, hbm_budget, C.byref(h)))
+        self.h = h
+        self._sizes = {}
+
+    def close(self):
+        if self.h:
+            lib().mcpt_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream_handle: int | None):
+        _check(lib().mcpt_set_stream(self.h, stream_handle))
+
+    def upload(self, prob) -> int:
+        hp = prob if isinstance(prob, HostProblem) else HostProblem(prob)
+        pid = C.c_uint64()
+        _check(lib().mcpt_upload(self.h, C.byref(hp.c), C.byref(pid)))
+        self._sizes[pid.value] = (hp.n_occ.copy(), hp.n_vir.copy(), len(hp.pairs))
+        return pid.value
+
+    def upload_device(self, n_occ, n_vir, pairs, eps_ptr: int, k_ptr: int, v_ptr: int) -> int:
+        """Upload from device buffers (e.g. torch tensors' data_ptr()); sizes and pairs on the host."""
+        n_occ = np.ascontiguousarray(n_occ, dtype=np.int32)
+        n_vir = np.ascontiguousarray(n_vir, dtype=np.int32)
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        c = mcpt_problem(n_mono=len(n_occ), n_occ=_ptr(n_occ), n_vir=_ptr(n_vir), eps=eps_ptr,
+                         k_intra=k_ptr, n_pair=len(pairs), pair=_ptr(pairs), v_dimer=v_ptr,
+                         memory=MCPT_DEVICE)
+        pid = C.c_uint64()
+        _check(lib().mcpt_upload(self.h, C.byref(c), C.byref(pid)))
+        self._sizes[pid.value] = (n_occ.copy(), n_vir.copy(), len(pairs))
+        return pid.value
+
+    def run(self, pid: int, raise_on_error: bool = True, **opts) -> dict:
+        o = make_options(**opts)
+        s = mcpt_summary()
+        st = lib().mcpt_run(self.h, pid, C.byref(o), C.byref(s))
+        if raise_on_error:
+            _check(st)
+        d = s.as_dict()
+        d["return"] = st
+        return d
+
+    def solve(self, prob, raise_on_error: bool = True, **opts):
+        pid = self.upload(prob)
+        return pid, self.run(pid, raise_on_error=raise_on_error, **opts)
+
+    def energy(self, pid: int, want_t: bool = True) -> dict:
+        n_occ, n_vir, n_pair = self._sizes[pid]
+        N = len(n_occ)
+        e_m2 = np.empty(N)
+        de_m2 = np.empty(N)
+        e_d2 = np.empty(max(n_pair, 1))
+        nt = int(np.sum((n_occ.astype(np.int64) * n_vir) ** 2))
+        t = np.empty(nt) if want_t else None
+        _check(lib().mcpt_energy(self.h, pid, _ptr(e_m2), _ptr(de_m2), _ptr(e_d2), _ptr(t)))
+        out = {"e_m2": e_m2, "de_m2": de_m2, "e_d2": e_d2[:n_pair]}
+        if want_t:
+            out["t"] = t
+        return out
+
+    def release(self, pid: int):
+        _check(lib().mcpt_release(self.h, pid))
+        self._sizes.pop(pid, None)
+
+    def set_timing(self, on: bool):
+        _check(lib().mcpt_set_timing(self.h, 1 if on else 0))
+
+    def timing(self) -> dict:
+        t = mcpt_timing()
+        _check(lib().mcpt_timing_read(self.h, C.byref(t)))
+        return t.as_dict()
+
+
+def split_t(t_flat: np.ndarray, n_occ, n_vir):
+    """Per-monomer views T_X[i, j, a, b] of the t_amp array of mcpt_energy."""
+    out, off = [], 0
+    for o, v in zip(n_occ, n_vir):
+        o, v = int(o), int(v)
+        sz = o * o * v * v
+        out.append(t_flat[off:off + sz].reshape(o, o, v, v))
+        off += sz
+    return out
