@@ -43,13 +43,15 @@ struct Resident {
     int n_mono = 0;
     int64_t n_pair = 0;
     int max_n = 0, max_np = 0;
-    int64_t eps_elems = 0, raw_elems = 0, mat_elems = 0, v_elems = 0, max_slot = 0;
+    int64_t eps_elems = 0, dif_elems = 0, raw_elems = 0, mat_elems = 0, v_elems = 0, max_slot = 0;
     std::vector<MonoDesc> monos;
-    std::vector<PairDesc> pairs;      // sorted for locality; .orig is the caller's index
+    std::vector<PairDesc> pairs;      // LDS-variant pairs, then the others; each range sorted by
+                                      // monomer for locality; .orig is the caller's index
+    int64_t n_lds = 0;                // pairs served by the LDS-resident-V kernel
     // device
     MonoDesc* d_monos = nullptr;
     PairDesc* d_pairs = nullptr;
-    double *d_eps = nullptr, *d_raw = nullptr, *d_K = nullptr, *d_T = nullptr, *d_M = nullptr;
+    double *d_dif = nullptr, *d_raw = nullptr, *d_K = nullptr, *d_T = nullptr, *d_M = nullptr;
     double *d_G[2] = {nullptr, nullptr};
     double* d_V = nullptr;
     double *d_em2 = nullptr, *d_em2_0 = nullptr, *d_ed2 = nullptr, *d_res = nullptr;
@@ -88,7 +90,7 @@ struct mcpt_ctx {
     double* d_scratch = nullptr;
     int64_t scratch_slot = 0;
     int scratch_slots = 0;
-    int pair_grid = 0;
+    int grid_lds = 0, grid_glb = 0;   // persistent grids of the two pair-kernel variants
     Timing timing;
 };
 
@@ -158,13 +160,10 @@ void drain_timing(Timing& t) {
 }
 
 mcpt_status ensure_scratch(mcpt_ctx* c, int64_t slot_elems) {
-    const int per_cu = pair_fp64_blocks_per_cu();
-    int grid = c->n_cu * per_cu;
-    grid = std::max(8, grid / 8 * 8);
-    if (c->d_scratch && c->scratch_slot >= slot_elems && c->scratch_slots >= grid) {
-        c->pair_grid = grid;
-        return MCPT_OK;
-    }
+    c->grid_lds = std::max(8, c->n_cu * pair_fp64_blocks_per_cu(1) / 8 * 8);
+    c->grid_glb = std::max(8, c->n_cu * pair_fp64_blocks_per_cu(0) / 8 * 8);
+    const int grid = std::max(c->grid_lds, c->grid_glb);
+    if (c->d_scratch && c->scratch_slot >= slot_elems && c->scratch_slots >= grid) return MCPT_OK;
     if (c->d_scratch) {
         HIP_TRY(hipStreamSynchronize(c->stream));
         (void)hipFree(c->d_scratch);
@@ -179,7 +178,6 @@ mcpt_status ensure_scratch(mcpt_ctx* c, int64_t slot_elems) {
     }
     c->scratch_slot = slot;
     c->scratch_slots = grid;
-    c->pair_grid = grid;
     return MCPT_OK;
 }
 
@@ -250,7 +248,7 @@ mcpt_status upload(mcpt_ctx* c, const mcpt_problem* pb, uint64_t* id_out) {
     r->n_mono = pb->n_mono;
     r->n_pair = pb->n_pair;
     r->monos.resize(pb->n_mono);
-    int64_t eoff = 0, roff = 0, moff = 0;
+    int64_t eoff = 0, roff = 0, moff = 0, doff = 0;
     for (int x = 0; x < pb->n_mono; ++x) {
         MonoDesc& d = r->monos[x];
         d.o = pb->n_occ[x];
@@ -260,6 +258,8 @@ mcpt_status upload(mcpt_ctx* c, const mcpt_problem* pb, uint64_t* id_out) {
         d.eps_off = eoff;
         d.raw_off = roff;
         d.mat_off = moff;
+        d.dif_off = doff;
+        doff += d.np;
         eoff += d.o + d.v;
         roff += (int64_t)d.n * d.n;
         moff += (int64_t)d.np * d.np;
@@ -267,6 +267,7 @@ mcpt_status upload(mcpt_ctx* c, const mcpt_problem* pb, uint64_t* id_out) {
         r->max_np = std::max(r->max_np, d.np);
     }
     r->eps_elems = eoff;
+    r->dif_elems = doff;
     r->raw_elems = roff;
     r->mat_elems = moff;
     // pairs: caller order gives V offsets; processing order is sorted by (min, max) monomer
@@ -286,11 +287,18 @@ mcpt_status upload(mcpt_ctx* c, const mcpt_problem* pb, uint64_t* id_out) {
         d.orig = p;
         r->max_slot = std::max<int64_t>(r->max_slot, (int64_t)r->monos[d.x].np * r->monos[d.y].np);
     }
-    std::stable_sort(r->pairs.begin(), r->pairs.end(), [](const PairDesc& a, const PairDesc& b) {
-        const int a0 = std::min(a.x, a.y), b0 = std::min(b.x, b.y);
-        if (a0 != b0) return a0 < b0;
-        return std::max(a.x, a.y) < std::max(b.x, b.y);
-    });
+    {
+        const std::vector<MonoDesc>& m = r->monos;
+        auto lds = [&m](const PairDesc& d) { return pair_fits_lds(m[d.x].n, m[d.y].np); };
+        std::stable_sort(r->pairs.begin(), r->pairs.end(), [&](const PairDesc& a, const PairDesc& b) {
+            const bool la = lds(a), lb = lds(b);
+            if (la != lb) return la;
+            const int a0 = std::min(a.x, a.y), b0 = std::min(b.x, b.y);
+            if (a0 != b0) return a0 < b0;
+            return std::max(a.x, a.y) < std::max(b.x, b.y);
+        });
+        r->n_lds = std::count_if(r->pairs.begin(), r->pairs.end(), lds);
+    }
     // energies: validated on the host (small)
     std::vector<double> eps(eoff);
     if (pb->memory == MCPT_HOST) {
@@ -299,8 +307,16 @@ mcpt_status upload(mcpt_ctx* c, const mcpt_problem* pb, uint64_t* id_out) {
         HIP_TRY(hipMemcpy(eps.data(), pb->eps, eoff * sizeof(double), hipMemcpyDeviceToHost));
     }
     if ((st = check_energies(eps, pb)) != MCPT_OK) return st;
+    // orbital-energy differences d[(i,a)] = e_i - e_a (Eqs. 60-61 as d_X + d_Y)
+    std::vector<double> dif(doff, 0.0);
+    for (int x = 0; x < pb->n_mono; ++x) {
+        const MonoDesc& d = r->monos[x];
+        const double* e = eps.data() + d.eps_off;
+        for (int i = 0; i < d.o; ++i)
+            for (int a = 0; a < d.v; ++a) dif[d.dif_off + i * d.v + a] = e[i] - e[d.o + a];
+    }
     // footprint and admission
-    const size_t need = sizeof(double) * ((size_t)eoff + r->raw_elems + 5 * (size_t)r->mat_elems +
+    const size_t need = sizeof(double) * ((size_t)doff + r->raw_elems + 5 * (size_t)r->mat_elems +
                                           r->v_elems + 3 * (size_t)pb->n_mono + pb->n_pair) +
                         r->monos.size() * sizeof(MonoDesc) + r->pairs.size() * sizeof(PairDesc);
     if (c->in_use + need > c->budget)
@@ -316,7 +332,7 @@ mcpt_status upload(mcpt_ctx* c, const mcpt_problem* pb, uint64_t* id_out) {
     } while (0)
     ALLOC(R->d_monos, R->n_mono);
     ALLOC(R->d_pairs, std::max<int64_t>(R->n_pair, 1));
-    ALLOC(R->d_eps, eoff);
+    ALLOC(R->d_dif, doff);
     ALLOC(R->d_raw, R->raw_elems);
     ALLOC(R->d_K, R->mat_elems);
     ALLOC(R->d_T, R->mat_elems);
@@ -342,7 +358,7 @@ mcpt_status upload(mcpt_ctx* c, const mcpt_problem* pb, uint64_t* id_out) {
     DTRY(hipMemcpyAsync(R->d_monos, R->monos.data(), R->monos.size() * sizeof(MonoDesc), hipMemcpyHostToDevice, s));
     if (R->n_pair)
         DTRY(hipMemcpyAsync(R->d_pairs, R->pairs.data(), R->pairs.size() * sizeof(PairDesc), hipMemcpyHostToDevice, s));
-    DTRY(hipMemcpyAsync(R->d_eps, eps.data(), eoff * sizeof(double), hipMemcpyHostToDevice, s));
+    DTRY(hipMemcpyAsync(R->d_dif, dif.data(), doff * sizeof(double), hipMemcpyHostToDevice, s));
     DTRY(hipMemcpyAsync(R->d_raw, pb->k_intra, R->raw_elems * sizeof(double), kind, s));
     if (R->v_elems) DTRY(hipMemcpyAsync(R->d_V, pb->v_dimer, R->v_elems * sizeof(double), kind, s));
     *c->h_flag = 0;
@@ -393,6 +409,15 @@ void record_end(mcpt_ctx* c, hipEvent_t a, int kind, double flops, double vbytes
     c->timing.pending.push_back({a, b, kind, flops, vbytes});
 }
 
+// Pair phase over all pairs: the LDS-resident-V kernel for the pairs that fit,
+// then the L2 variant for the rest (same stream, so G accumulates in order).
+void pair_phase(mcpt_ctx* c, Resident* R, double* G, int couple, const Ctrl* ctrl) {
+    launch_pair_fp64(1, R->d_pairs, R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G, c->d_scratch,
+                     c->scratch_slot, c->grid_lds, R->d_ed2, couple, ctrl, c->stream);
+    launch_pair_fp64(0, R->d_pairs + R->n_lds, R->n_pair - R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G,
+                     c->d_scratch, c->scratch_slot, c->grid_glb, R->d_ed2, couple, ctrl, c->stream);
+}
+
 mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* out) {
     mcpt_status st = validate_options(o);
     if (st != MCPT_OK) return st;
@@ -413,12 +438,12 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
         HIP_TRY(hipMemcpyAsync(R->d_raw, o->warm_t, R->raw_elems * sizeof(double), hipMemcpyHostToDevice, s));
         launch_fill(R->d_T, R->mat_elems, 0.0, s);
         launch_pack(R->d_monos, R->n_mono, R->d_raw, R->d_T, R->max_n, s);
-        launch_monomer(kMonoE0, R->d_monos, R->n_mono, R->d_eps, R->d_K, nullptr, nullptr, R->d_T, R->d_M,
+        launch_monomer(kMonoE0, R->d_monos, R->n_mono, R->d_dif, R->d_K, nullptr, nullptr, R->d_T, R->d_M,
                        R->d_em2, R->d_em2_0, R->d_res, nullptr, R->max_np, s);
-        launch_monomer(kMonoFromT, R->d_monos, R->n_mono, R->d_eps, R->d_K, nullptr, nullptr, R->d_T,
+        launch_monomer(kMonoFromT, R->d_monos, R->n_mono, R->d_dif, R->d_K, nullptr, nullptr, R->d_T,
                        R->d_M, R->d_em2, R->d_em2_0, R->d_res, nullptr, R->max_np, s);
     } else {
-        launch_monomer(kMonoInit, R->d_monos, R->n_mono, R->d_eps, R->d_K, nullptr, nullptr, R->d_T, R->d_M,
+        launch_monomer(kMonoInit, R->d_monos, R->n_mono, R->d_dif, R->d_K, nullptr, nullptr, R->d_T, R->d_M,
                        R->d_em2, R->d_em2_0, R->d_res, nullptr, R->max_np, s);
     }
     HIP_TRY(hipGetLastError());
@@ -431,11 +456,10 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
         for (int k = 0; k < batch; ++k) {
             hipEvent_t a = nullptr;
             record_begin(c, &a);
-            launch_pair_fp64(R->d_pairs, R->n_pair, R->d_monos, R->d_eps, R->d_V, R->d_M, R->d_G[cur],
-                             c->d_scratch, c->scratch_slot, c->pair_grid, R->d_ed2, 1, c->d_ctrl, s);
+            pair_phase(c, R, R->d_G[cur], 1, c->d_ctrl);
             record_end(c, a, 0, fl_sweep, vb);
             record_begin(c, &a);
-            launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->d_eps, R->d_K, R->d_G[cur], R->d_G[cur ^ 1],
+            launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->d_dif, R->d_K, R->d_G[cur], R->d_G[cur ^ 1],
                            R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, c->d_ctrl, R->max_np, s);
             record_end(c, a, 1, 0.0, 0.0);
             launch_reduce_sweep(R->n_mono, R->d_res, c->d_ctrl, s);
@@ -462,8 +486,7 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
     {
         hipEvent_t a = nullptr;
         record_begin(c, &a);
-        launch_pair_fp64(R->d_pairs, R->n_pair, R->d_monos, R->d_eps, R->d_V, R->d_M, R->d_G[cur],
-                         c->d_scratch, c->scratch_slot, c->pair_grid, R->d_ed2, 0, nullptr, s);
+        pair_phase(c, R, R->d_G[cur], 0, nullptr);
         record_end(c, a, 0, fl_final, vb);
     }
     launch_reduce_final(R->n_mono, R->n_pair, R->d_em2, R->d_em2_0, R->d_ed2, c->d_ctrl, s);

@@ -77,11 +77,12 @@ __device__ double block_max(double x, double* sh) {
 
 // Monomer phase, one workgroup per monomer.  For element (r, c) = ((i,a),(j,b))
 // the occupied-swapped partner S(r, c) = ((j,a),(i,b)) has the same denominator
-// e_i + e_j - e_a - e_b (Eqs. 60-61); both T values are formed by the same
+// e_i + e_j - e_a - e_b (Eqs. 60-61), formed as (e_i - e_a) + (e_j - e_b) from the
+// per-monomer differences; both T values are formed by the same
 // thread so M = 2T - S(T) (the spin-adapted combination of Eq. 59) needs no
 // second pass.  E_M2 = <2K - S(K), T> = <K, M> (Eq. 54).
 __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
-    int mode, const MonoDesc* __restrict__ monos, const double* __restrict__ eps,
+    int mode, const MonoDesc* __restrict__ monos, const double* __restrict__ dif,
     const double* __restrict__ K, const double* __restrict__ G, double* __restrict__ Gz,
     double* __restrict__ T, double* __restrict__ M, double* __restrict__ em2,
     double* __restrict__ em2_0, double* __restrict__ res, const Ctrl* __restrict__ ctrl) {
@@ -89,8 +90,8 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
     __shared__ double sh[kMonoThreads];
     const int x = blockIdx.x;
     const MonoDesc d = monos[x];
-    const int o = d.o, v = d.v, n = d.n, np = d.np;
-    const double* e = eps + d.eps_off;
+    const int v = d.v, n = d.n, np = d.np;
+    const double* dx = dif + d.dif_off;
     const double* Kx = K + d.mat_off;
     const double* Gx = G ? G + d.mat_off : nullptr;
     double* Tx = T + d.mat_off;
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
         const int j = c / v, b = c - j * v;
         const int rs = j * v + a, cs = i * v + b;
         const int64_t e_rc = (int64_t)r * np + c, e_s = (int64_t)rs * np + cs;
-        const double dinv = 1.0 / (((e[i] + e[j]) - e[o + a]) - e[o + b]);
+        const double dinv = 1.0 / (dx[r] + dx[c]);
         double tn, ts;
         if (mode == kMonoUpdate) {
             tn = dinv * ((Kx[e_rc] + Gx[e_rc]) + Gx[(int64_t)c * np + r]);
@@ -234,10 +235,10 @@ void launch_nonfinite(const double* p, int64_t n, int32_t* flag, hipStream_t s) 
                        dim3(256), 0, s, p, n, flag);
 }
 
-void launch_monomer(int mode, const MonoDesc* monos, int n_mono, const double* eps, const double* K,
+void launch_monomer(int mode, const MonoDesc* monos, int n_mono, const double* dif, const double* K,
                     const double* G, double* G_zero, double* T, double* M, double* em2,
                     double* em2_0, double* res, const Ctrl* ctrl, int /*max_np*/, hipStream_t s) {
-    hipLaunchKernelGGL(monomer_kernel, dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, eps, K,
+    hipLaunchKernelGGL(monomer_kernel, dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif, K,
                        G, G_zero, T, M, em2, em2_0, res, ctrl);
 }
 

@@ -6,6 +6,8 @@
 //   (j,b) = j*v + b, zero in the padding; matrices of all monomers are
 //   concatenated at mat_off.
 //   pair p = (X, Y): V_XY stored as given, nX x nY row-major (unpadded), at v_off.
+//   dif: per monomer np values d[(i,a)] = e_i - e_a (zero in the padding), so
+//   every denominator of Eqs. 60-61 is 1 / (d_X[(i,a)] + d_Y[(j,b)]).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,6 +25,7 @@ struct MonoDesc {
     int64_t eps_off;                   // first energy of X in eps
     int64_t mat_off;                   // first element of X's np x np matrices
     int64_t raw_off;                   // first element of X's o*o*v*v block in caller layout
+    int64_t dif_off;                   // first element of X's np orbital-energy differences
 };
 
 struct PairDesc {
@@ -62,7 +65,7 @@ void launch_pack(const MonoDesc* monos, int n_mono, const double* raw, double* p
 void launch_unpack(const MonoDesc* monos, int n_mono, const double* packed, double* raw,
                    int max_n, hipStream_t s);
 void launch_nonfinite(const double* p, int64_t n, int32_t* flag, hipStream_t s);
-void launch_monomer(int mode, const MonoDesc* monos, int n_mono, const double* eps,
+void launch_monomer(int mode, const MonoDesc* monos, int n_mono, const double* dif,
                     const double* K, const double* G, double* G_zero, double* T, double* M,
                     double* em2, double* em2_0, double* res, const Ctrl* ctrl, int max_np,
                     hipStream_t s);
@@ -72,11 +75,14 @@ void launch_reduce_final(int n_mono, int64_t n_pair, const double* em2, const do
 
 // ---- FP64 MFMA pair phase (pair_fp64.hip) ----
 // Eq. 59 (Tau from V, M_X, M_Y) and, if couple != 0, the Eq. 58 contractions
-// G_X += Tau V^T, G_Y += Tau^T V for every pair; E_D2 of every pair.
-void launch_pair_fp64(const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
-                      const double* eps, const double* V, const double* M, double* G,
+// G_X += Tau V^T, G_Y += Tau^T V for every pair; E_D2 of every pair.  Two
+// variants: lds_variant = 1 stages V in LDS (pairs with pair_fits_lds), 0 reads
+// V from L2 (any size).
+void launch_pair_fp64(int lds_variant, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
+                      const double* dif, const double* V, const double* M, double* G,
                       double* scratch, int64_t slot_elems, int grid, double* ed2, int couple,
                       const Ctrl* ctrl, hipStream_t s);
-int pair_fp64_blocks_per_cu();
+int pair_fp64_blocks_per_cu(int lds_variant);
+bool pair_fits_lds(int nX, int npY);
 
 }  // namespace mcpt

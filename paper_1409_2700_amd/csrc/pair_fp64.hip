@@ -8,16 +8,33 @@
 //   G_X += Tau V^T,   G_Y += Tau^T V           Eq. 58: the pair term seen from X and from Y
 //
 // (the Eq. 58 pair term of monomer X is G_X + G_X^T; the monomer kernel adds
-// the transpose).  All four products are dense n x n x n contractions, run on
-// v_mfma_f64_16x16x4_f64.  Each wavefront owns a super-block of SB x SB output
-// tiles of 16 x 16 and keeps their accumulators in registers; the 4-deep K
-// step of the instruction is fed from a 16-deep chunk that every lane loads as
-// one contiguous run of 4 values, so lane l covers k = k0 + 4*(l/16) + s at
-// step s for both operands.  Tau lives in a per-workgroup scratch slot (it is
-// needed transposed for G_X and untransposed for G_Y), which the workgroup
-// reuses for every pair it processes.  Workgroups are persistent; workgroup b
-// runs on XCD b % 8, and each XCD is given a contiguous range of the pair list
-// (sorted by monomer), so the monomer matrices it touches stay in its L2.
+// the transpose).  The four products are dense n x n x n contractions on
+// v_mfma_f64_16x16x4_f64.
+//
+// Structure.  Persistent workgroups walk the pair list; workgroup b runs on
+// XCD b % 8 and each XCD takes a contiguous range of the monomer-sorted pairs,
+// so the M and G blocks it touches stay in its L2.  Two variants:
+//  * LDS-resident V (pairs with nX (npY + 2) doubles <= 157,696 B): eight
+//    wavefronts (two per SIMD, so one wave's memory waits are covered by the
+//    other's MFMAs), one workgroup per CU.  V is staged once per pair into LDS
+//    (row stride npY + 2 doubles so column-chunk reads of 16 rows fall on
+//    distinct banks) and every product reads it from there: V is streamed from
+//    HBM once per pass, and the L2 is asked for the next pair's V while the
+//    current pair's second phase runs.
+//  * V from L2 (larger pairs): four wavefronts, two workgroups per CU.
+// M_X, M_Y and Tau (a per-workgroup scratch slot, needed transposed for G_X and
+// untransposed for G_Y) come from L2 with the next k-chunk prefetched into
+// registers.  Output tiles of 16 x 16 are grouped into 3 x 3 super-blocks
+// (accumulators in registers, each operand fragment reused three times); whole
+// super-blocks go round-robin to the wavefronts and the tiles of the remainder
+// one by one, so the SIMDs get (nearly) equal work between barriers.  Task
+// shapes are compile-time (3 x 3 or a single tile) so each MFMA block is
+// straight-line code.
+//
+// Operand layout of the instruction (measured): A lane l = (row l%16, k l/16),
+// B lane l = (k l/16, column l%16), accumulator element t of lane l = (row
+// l/16 + 4t, column l%16).  A 16-deep k chunk is loaded as 4 contiguous values
+// per lane, so lane l covers k = k0 + 4*(l/16) + s at step s for both operands.
 #include "mcpt_internal.hpp"
 
 namespace mcpt {
@@ -25,11 +42,18 @@ namespace mcpt {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
-constexpr int kSB = 3;          // 3 x 3 tiles of 16 x 16 per wavefront
+constexpr int kThreadsL = 512;   // LDS-resident V: eight wavefronts, one workgroup per CU
+constexpr int kThreadsG = 256;   // V from L2: four wavefronts, two workgroups per CU
+constexpr int kSB = 3;           // super-block edge in tiles
 constexpr int kXcds = 8;
+constexpr int kLdsV = 19712;     // LDS doubles for V (157,696 B): nX * (npY + 2) must fit
+
+template <int R, int C>
+struct Shape {
+    static constexpr int NR = R, NC = C;
+};
 
 __device__ inline d4 mfma(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -37,149 +61,314 @@ __device__ inline d4 mfma(double a, double b, d4 c) {
 
 __device__ inline d4 load4(const double* p) { return *reinterpret_cast<const d4*>(p); }
 
-// Position of accumulator element t (0..3) of lane `lane` inside its 16 x 16 tile
-// for v_mfma_f64_16x16x4_f64: rows lane/16, lane/16 + 4, + 8, + 12 of column lane%16
-// (operands: A lane l = (row l%16, k l/16), B lane l = (k l/16, column l%16)).
+// 4 consecutive doubles from LDS at a 16-byte aligned address
+__device__ inline d4 lds4(const double* p) {
+    const d2 lo = *reinterpret_cast<const d2*>(p);
+    const d2 hi = *reinterpret_cast<const d2*>(p + 2);
+    d4 r;
+    r.x = lo.x;
+    r.y = lo.y;
+    r.z = hi.x;
+    r.w = hi.y;
+    return r;
+}
+
+__device__ inline void split(const d4& v, double (&o)[4]) {
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+}
+
 __device__ inline int acc_row(int lane, int t) { return (lane >> 4) + 4 * t; }
-__device__ inline int acc_col(int lane, int t) { return lane & 15; }
+__device__ inline int acc_col(int lane) { return lane & 15; }
+
+template <int NR, int NC>
+__device__ inline void zero(d4 (&acc)[NR][NC]) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) acc[i][j] = d4(0.0);
+}
+
+template <int NR, int NC>
+__device__ inline void mma_block(d4 (&acc)[NR][NC], const double (&a)[NR][4], const double (&b)[NC][4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+#pragma unroll
+            for (int j = 0; j < NC; ++j) acc[i][j] = mfma(a[i][s], b[j][s], acc[i][j]);
+}
 
 struct PairView {
-    const double* V;      // nX x nY, row-major
+    const double* V;      // nX x nY, row-major, global
     const double* MX;     // npX x npX
     const double* MY;     // npY x npY
-    const double* eX;     // oX occupied then vX virtual energies
-    const double* eY;
+    const double* dX;     // e_i - e_a over rows (i,a) of X
+    const double* dY;     // e_j - e_b over columns (j,b) of Y
     double* GX;
     double* GY;
-    int oX, vX, nX, npX;
-    int oY, vY, nY, npY;
+    int nX, npX;
+    int nY, npY;
+    int ldv;              // LDS row stride of V (npY + 2) when staged
 };
 
-// acc[i][j] += sum_k MX[r][k] V[k][c] + sum_k V[r][k] MY[c][k] over the tiles
-// (rb0 + i, cb0 + j) of the npX x npY output.
-__device__ void tau_tiles(const PairView& p, int rb0, int cb0, int RB, int CB, int lane,
-                          d4 (&acc)[kSB][kSB]) {
+// ---------------------------------------------------------------------------
+// V staged in LDS (sV: nX rows, row stride ldv, columns >= nY zero)
+// ---------------------------------------------------------------------------
+
+// acc += M_X V + V M_Y^T on tiles (r0.., c0..) of the npX x npY output
+template <int NR, int NC>
+__device__ void tau_sb_lds(const PairView& p, const double* sV, int r0, int c0, int lane, d4 (&acc)[NR][NC]) {
+    const int lr = lane & 15, lk = (lane >> 4) * 4;
+    d4 an[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) an[i] = load4(p.MX + (int64_t)((r0 + i) * 16 + lr) * p.npX + lk);
+    for (int k0 = 0; k0 < p.npX; k0 += 16) {
+        double a[NR][4], b[NC][4];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) split(an[i], a[i]);
+        if (k0 + 16 < p.npX) {
+#pragma unroll
+            for (int i = 0; i < NR; ++i)
+                an[i] = load4(p.MX + (int64_t)((r0 + i) * 16 + lr) * p.npX + k0 + 16 + lk);
+        }
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            const int c = (c0 + j) * 16 + lr;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int kk = k0 + lk + s;
+                b[j][s] = (kk < p.nX) ? sV[kk * p.ldv + c] : 0.0;
+            }
+        }
+        mma_block(acc, a, b);
+    }
+    d4 bn[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) bn[j] = load4(p.MY + (int64_t)((c0 + j) * 16 + lr) * p.npY + lk);
+    for (int k0 = 0; k0 < p.npY; k0 += 16) {
+        double a[NR][4], b[NC][4];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) split(bn[j], b[j]);
+        if (k0 + 16 < p.npY) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                bn[j] = load4(p.MY + (int64_t)((c0 + j) * 16 + lr) * p.npY + k0 + 16 + lk);
+        }
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const int r = (r0 + i) * 16 + lr;
+            split((r < p.nX) ? lds4(sV + r * p.ldv + k0 + lk) : d4(0.0), a[i]);
+        }
+        mma_block(acc, a, b);
+    }
+}
+
+// acc = sum_c Tau[r][c] V[q][c]   (G_X tiles)
+template <int NR, int NC>
+__device__ void gx_sb_lds(const PairView& p, const double* sV, const double* tau, int r0, int q0, int lane,
+                          d4 (&acc)[NR][NC]) {
+    const int lr = lane & 15, lk = (lane >> 4) * 4;
+    d4 an[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) an[i] = load4(tau + (int64_t)((r0 + i) * 16 + lr) * p.npY + lk);
+    for (int k0 = 0; k0 < p.npY; k0 += 16) {
+        double a[NR][4], b[NC][4];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) split(an[i], a[i]);
+        if (k0 + 16 < p.npY) {
+#pragma unroll
+            for (int i = 0; i < NR; ++i)
+                an[i] = load4(tau + (int64_t)((r0 + i) * 16 + lr) * p.npY + k0 + 16 + lk);
+        }
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            const int q = (q0 + j) * 16 + lr;
+            split((q < p.nX) ? lds4(sV + q * p.ldv + k0 + lk) : d4(0.0), b[j]);
+        }
+        mma_block(acc, a, b);
+    }
+}
+
+// acc = sum_r Tau[r][c] V[r][q]   (G_Y tiles)
+template <int NR, int NC>
+__device__ void gy_sb_lds(const PairView& p, const double* sV, const double* tau, int c0, int q0, int lane,
+                          d4 (&acc)[NR][NC]) {
+    const int lr = lane & 15, lk = (lane >> 4) * 4;
+    double an[NR][4];
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) an[i][s] = tau[(int64_t)(lk + s) * p.npY + (c0 + i) * 16 + lr];
+    for (int k0 = 0; k0 < p.npX; k0 += 16) {
+        double a[NR][4], b[NC][4];
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) a[i][s] = an[i][s];
+        if (k0 + 16 < p.npX) {
+#pragma unroll
+            for (int i = 0; i < NR; ++i)
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    an[i][s] = tau[(int64_t)(k0 + 16 + lk + s) * p.npY + (c0 + i) * 16 + lr];
+        }
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            const int q = (q0 + j) * 16 + lr;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int kk = k0 + lk + s;
+                b[j][s] = (kk < p.nX) ? sV[kk * p.ldv + q] : 0.0;
+            }
+        }
+        mma_block(acc, a, b);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// V read from global memory (pairs too large for LDS)
+// ---------------------------------------------------------------------------
+template <int NR, int NC>
+__device__ void tau_sb_glb(const PairView& p, int r0, int c0, int lane, d4 (&acc)[NR][NC]) {
     const int lr = lane & 15, lk = (lane >> 4) * 4;
     for (int k0 = 0; k0 < p.npX; k0 += 16) {
-        d4 a[kSB];
+        double a[NR][4], b[NC][4];
 #pragma unroll
-        for (int i = 0; i < kSB; ++i)
-            a[i] = (rb0 + i < RB) ? load4(p.MX + (int64_t)((rb0 + i) * 16 + lr) * p.npX + k0 + lk) : d4(0.0);
-        double b[kSB][4];
+        for (int i = 0; i < NR; ++i) split(load4(p.MX + (int64_t)((r0 + i) * 16 + lr) * p.npX + k0 + lk), a[i]);
 #pragma unroll
-        for (int j = 0; j < kSB; ++j) {
-            const int c = (cb0 + j) * 16 + lr;
+        for (int j = 0; j < NC; ++j) {
+            const int c = (c0 + j) * 16 + lr;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int kk = k0 + lk + s;
                 b[j][s] = (kk < p.nX && c < p.nY) ? p.V[(int64_t)kk * p.nY + c] : 0.0;
             }
         }
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int i = 0; i < kSB; ++i)
-#pragma unroll
-                for (int j = 0; j < kSB; ++j)
-                    if (rb0 + i < RB && cb0 + j < CB) acc[i][j] = mfma(a[i][s], b[j][s], acc[i][j]);
+        mma_block(acc, a, b);
     }
     for (int k0 = 0; k0 < p.npY; k0 += 16) {
-        double a[kSB][4];
+        double a[NR][4], b[NC][4];
 #pragma unroll
-        for (int i = 0; i < kSB; ++i) {
-            const int r = (rb0 + i) * 16 + lr;
+        for (int i = 0; i < NR; ++i) {
+            const int r = (r0 + i) * 16 + lr;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int kk = k0 + lk + s;
                 a[i][s] = (r < p.nX && kk < p.nY) ? p.V[(int64_t)r * p.nY + kk] : 0.0;
             }
         }
-        d4 b[kSB];
 #pragma unroll
-        for (int j = 0; j < kSB; ++j)
-            b[j] = (cb0 + j < CB) ? load4(p.MY + (int64_t)((cb0 + j) * 16 + lr) * p.npY + k0 + lk) : d4(0.0);
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int i = 0; i < kSB; ++i)
-#pragma unroll
-                for (int j = 0; j < kSB; ++j)
-                    if (rb0 + i < RB && cb0 + j < CB) acc[i][j] = mfma(a[i][s], b[j][s], acc[i][j]);
+        for (int j = 0; j < NC; ++j) split(load4(p.MY + (int64_t)((c0 + j) * 16 + lr) * p.npY + k0 + lk), b[j]);
+        mma_block(acc, a, b);
     }
 }
 
-// acc[i][j] = sum_c Tau[r][c] V[r'][c]   (G_X tiles (rb0+i, rb'0+j), npX x npX)
-__device__ void gx_tiles(const PairView& p, const double* tau, int rb0, int qb0, int RB, int lane,
-                         d4 (&acc)[kSB][kSB]) {
+template <int NR, int NC>
+__device__ void gx_sb_glb(const PairView& p, const double* tau, int r0, int q0, int lane, d4 (&acc)[NR][NC]) {
     const int lr = lane & 15, lk = (lane >> 4) * 4;
     for (int k0 = 0; k0 < p.npY; k0 += 16) {
-        d4 a[kSB];
+        double a[NR][4], b[NC][4];
 #pragma unroll
-        for (int i = 0; i < kSB; ++i)
-            a[i] = (rb0 + i < RB) ? load4(tau + (int64_t)((rb0 + i) * 16 + lr) * p.npY + k0 + lk) : d4(0.0);
-        double b[kSB][4];
+        for (int i = 0; i < NR; ++i) split(load4(tau + (int64_t)((r0 + i) * 16 + lr) * p.npY + k0 + lk), a[i]);
 #pragma unroll
-        for (int j = 0; j < kSB; ++j) {
-            const int q = (qb0 + j) * 16 + lr;
+        for (int j = 0; j < NC; ++j) {
+            const int q = (q0 + j) * 16 + lr;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int kk = k0 + lk + s;
                 b[j][s] = (q < p.nX && kk < p.nY) ? p.V[(int64_t)q * p.nY + kk] : 0.0;
             }
         }
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int i = 0; i < kSB; ++i)
-#pragma unroll
-                for (int j = 0; j < kSB; ++j)
-                    if (rb0 + i < RB && qb0 + j < RB) acc[i][j] = mfma(a[i][s], b[j][s], acc[i][j]);
+        mma_block(acc, a, b);
     }
 }
 
-// acc[i][j] = sum_r Tau[r][c] V[r][c']   (G_Y tiles (cb0+i, qb0+j), npY x npY)
-__device__ void gy_tiles(const PairView& p, const double* tau, int cb0, int qb0, int CB, int lane,
-                         d4 (&acc)[kSB][kSB]) {
+template <int NR, int NC>
+__device__ void gy_sb_glb(const PairView& p, const double* tau, int c0, int q0, int lane, d4 (&acc)[NR][NC]) {
     const int lr = lane & 15, lk = (lane >> 4) * 4;
     for (int k0 = 0; k0 < p.npX; k0 += 16) {
-        double a[kSB][4];
+        double a[NR][4], b[NC][4];
 #pragma unroll
-        for (int i = 0; i < kSB; ++i) {
-            const int c = (cb0 + i) * 16 + lr;
+        for (int i = 0; i < NR; ++i)
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-                a[i][s] = (cb0 + i < CB) ? tau[(int64_t)(k0 + lk + s) * p.npY + c] : 0.0;
-        }
-        double b[kSB][4];
+            for (int s = 0; s < 4; ++s) a[i][s] = tau[(int64_t)(k0 + lk + s) * p.npY + (c0 + i) * 16 + lr];
 #pragma unroll
-        for (int j = 0; j < kSB; ++j) {
-            const int q = (qb0 + j) * 16 + lr;
+        for (int j = 0; j < NC; ++j) {
+            const int q = (q0 + j) * 16 + lr;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int kk = k0 + lk + s;
                 b[j][s] = (kk < p.nX && q < p.nY) ? p.V[(int64_t)kk * p.nY + q] : 0.0;
             }
         }
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int i = 0; i < kSB; ++i)
-#pragma unroll
-                for (int j = 0; j < kSB; ++j)
-                    if (cb0 + i < CB && qb0 + j < CB) acc[i][j] = mfma(a[i][s], b[j][s], acc[i][j]);
+        mma_block(acc, a, b);
     }
 }
 
-__device__ inline void atomic_flush(double* G, int ld, int n, int rb0, int qb0, int lane,
-                                    const d4 (&acc)[kSB][kSB]) {
+// ---------------------------------------------------------------------------
+// task lists: full super-blocks round-robin over the waves (partial edge
+// super-blocks as single tiles of the same wave), the remainder tile by tile
+// ---------------------------------------------------------------------------
+struct Grid {
+    int RT, CT, SR, SC, n;    // tiles, super-blocks per dimension, super-block count
+};
+
+__device__ inline Grid make_grid(int RT, int CT) {
+    Grid g;
+    g.RT = RT;
+    g.CT = CT;
+    g.SR = (RT + kSB - 1) / kSB;
+    g.SC = (CT + kSB - 1) / kSB;
+    g.n = g.SR * g.SC;
+    return g;
+}
+
+// Visit the tasks of `wave` over the concatenation of grids g0 and g1 (g1 may be
+// empty): f(which, r0, c0, Shape<3,3>{} or Shape<1,1>{}) in tile coordinates.
+template <class F>
+__device__ inline void for_tasks(const Grid& g0, const Grid& g1, int wave, int nwaves, F&& f) {
+    const int total = g0.n + g1.n;
+    const int full = total - total % nwaves;
+    for (int sb = wave; sb < full; sb += nwaves) {
+        const int which = sb >= g0.n ? 1 : 0;
+        const Grid& g = which ? g1 : g0;
+        const int s = which ? sb - g0.n : sb;
+        const int r0 = (s / g.SC) * kSB, c0 = (s % g.SC) * kSB;
+        const int nr = min(kSB, g.RT - r0), nc = min(kSB, g.CT - c0);
+        if (nr == kSB && nc == kSB) {
+            f(which, r0, c0, Shape<kSB, kSB>{});
+        } else {
+            for (int i = 0; i < nr; ++i)
+                for (int j = 0; j < nc; ++j) f(which, r0 + i, c0 + j, Shape<1, 1>{});
+        }
+    }
+    int idx = 0;
+    for (int sb = full; sb < total; ++sb) {
+        const int which = sb >= g0.n ? 1 : 0;
+        const Grid& g = which ? g1 : g0;
+        const int s = which ? sb - g0.n : sb;
+        const int r0 = (s / g.SC) * kSB, c0 = (s % g.SC) * kSB;
+        const int nr = min(kSB, g.RT - r0), nc = min(kSB, g.CT - c0);
+        for (int i = 0; i < nr; ++i)
+            for (int j = 0; j < nc; ++j, ++idx)
+                if (idx % nwaves == wave) f(which, r0 + i, c0 + j, Shape<1, 1>{});
+    }
+}
+
+template <int NR, int NC>
+__device__ inline void atomic_flush(double* G, int ld, int n, int r0, int q0, int lane,
+                                    const d4 (&acc)[NR][NC]) {
 #pragma unroll
-    for (int i = 0; i < kSB; ++i)
+    for (int i = 0; i < NR; ++i)
 #pragma unroll
-        for (int j = 0; j < kSB; ++j) {
+        for (int j = 0; j < NC; ++j) {
+            const int c = (q0 + j) * 16 + acc_col(lane);
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const int c = (qb0 + j) * 16 + acc_col(lane, t);
-                const int r = (rb0 + i) * 16 + acc_row(lane, t);
+                const int r = (r0 + i) * 16 + acc_row(lane, t);
                 if (r < n && c < n) unsafeAtomicAdd(G + (int64_t)r * ld + c, acc[i][j][t]);
             }
         }
@@ -191,7 +380,6 @@ __device__ inline double wave_sum(double x) {
 }
 
 __device__ inline int64_t pair_for(int64_t it, int64_t n_pair) {
-    // XCD-contiguous order: workgroup b runs on XCD b % 8
     const int g = gridDim.x;
     if (g % kXcds != 0) return (int64_t)blockIdx.x + it * g;
     const int xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds, per = g / kXcds;
@@ -200,116 +388,179 @@ __device__ inline int64_t pair_for(int64_t it, int64_t n_pair) {
     return p < end ? p : INT64_MAX;
 }
 
-__global__ __launch_bounds__(kThreads) void pair_fp64_kernel(
-    const PairDesc* __restrict__ pairs, int64_t n_pair, const MonoDesc* __restrict__ monos,
-    const double* __restrict__ eps, const double* __restrict__ V, const double* __restrict__ M,
-    double* __restrict__ G, double* __restrict__ scratch, int64_t slot_elems,
-    double* __restrict__ ed2, int couple, const Ctrl* __restrict__ ctrl) {
-    if (ctrl && ctrl->done) return;
-    __shared__ double red[kWaves];
+__device__ inline PairView make_view(const PairDesc& pd, const MonoDesc* monos, const double* dif,
+                                     const double* V, const double* M, double* G) {
+    const MonoDesc dx = monos[pd.x], dy = monos[pd.y];
+    PairView p;
+    p.V = V + pd.v_off;
+    p.MX = M + dx.mat_off;
+    p.MY = M + dy.mat_off;
+    p.dX = dif + dx.dif_off;
+    p.dY = dif + dy.dif_off;
+    p.GX = G + dx.mat_off;
+    p.GY = G + dy.mat_off;
+    p.nX = dx.n;
+    p.npX = dx.np;
+    p.nY = dy.n;
+    p.npY = dy.np;
+    p.ldv = dy.np + 2;
+    return p;
+}
+
+// One body for both variants: IN_LDS stages V in LDS (the pair list given to
+// it holds only pairs that fit); otherwise V is read from L2.
+template <bool IN_LDS, int NT>
+__device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_pair,
+                                 const MonoDesc* __restrict__ monos, const double* __restrict__ dif,
+                                 const double* __restrict__ V, const double* __restrict__ M,
+                                 double* __restrict__ G, double* __restrict__ scratch, int64_t slot_elems,
+                                 double* __restrict__ ed2, int couple, double* sV, double* red) {
+    constexpr int NW = NT / 64;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double* tau = scratch + (int64_t)blockIdx.x * slot_elems;
+    double sink = 0.0;
     for (int64_t it = 0;; ++it) {
         const int64_t pi = pair_for(it, n_pair);
         if (pi >= n_pair) break;
         const PairDesc pd = pairs[pi];
-        const MonoDesc dx = monos[pd.x], dy = monos[pd.y];
-        PairView p;
-        p.V = V + pd.v_off;
-        p.MX = M + dx.mat_off;
-        p.MY = M + dy.mat_off;
-        p.eX = eps + dx.eps_off;
-        p.eY = eps + dy.eps_off;
-        p.GX = G + dx.mat_off;
-        p.GY = G + dy.mat_off;
-        p.oX = dx.o; p.vX = dx.v; p.nX = dx.n; p.npX = dx.np;
-        p.oY = dy.o; p.vY = dy.v; p.nY = dy.n; p.npY = dy.np;
+        const PairView p = make_view(pd, monos, dif, V, M, G);
         const int RB = p.npX / 16, CB = p.npY / 16;
-        const int SR = (RB + kSB - 1) / kSB, SC = (CB + kSB - 1) / kSB;
-        const int rot = (int)(pi % kWaves);
+
+        if (IN_LDS) {   // stage V: rows of X, columns of Y zero-padded to ldv; loads batched
+            constexpr int kRows = 4, kCols = 3;
+            for (int rb = wave; rb < p.nX; rb += NW * kRows)
+                for (int cb = 0; cb < p.ldv; cb += 64 * kCols) {
+                    double tmp[kRows][kCols];
+#pragma unroll
+                    for (int k = 0; k < kRows; ++k)
+#pragma unroll
+                        for (int m = 0; m < kCols; ++m) {
+                            const int r = rb + NW * k, c = cb + lane + 64 * m;
+                            tmp[k][m] = (r < p.nX && c < p.nY) ? p.V[(int64_t)r * p.nY + c] : 0.0;
+                        }
+#pragma unroll
+                    for (int k = 0; k < kRows; ++k)
+#pragma unroll
+                        for (int m = 0; m < kCols; ++m) {
+                            const int r = rb + NW * k, c = cb + lane + 64 * m;
+                            if (r < p.nX && c < p.ldv) sV[r * p.ldv + c] = tmp[k][m];
+                        }
+                }
+            __syncthreads();
+        }
 
         // ---- Tau = D_XY * (V + M_X V + V M_Y^T), E_D2 = 4 <V, Tau> ----
         double epart = 0.0;
-        for (int sb = (wave + rot) % kWaves; sb < SR * SC; sb += kWaves) {
-            const int rb0 = (sb / SC) * kSB, cb0 = (sb % SC) * kSB;
-            d4 acc[kSB][kSB];
+        for_tasks(make_grid(RB, CB), make_grid(0, 0), wave, NW, [&](int, int r0, int c0, auto shape) {
+            constexpr int NR = decltype(shape)::NR, NC = decltype(shape)::NC;
+            d4 acc[NR][NC];
+            zero(acc);
+            if (IN_LDS) tau_sb_lds(p, sV, r0, c0, lane, acc);
+            else tau_sb_glb(p, r0, c0, lane, acc);
 #pragma unroll
-            for (int i = 0; i < kSB; ++i)
+            for (int j = 0; j < NC; ++j) {
+                const int c = (c0 + j) * 16 + acc_col(lane);
+                const double dc = p.dY[c];
 #pragma unroll
-                for (int j = 0; j < kSB; ++j) acc[i][j] = d4(0.0);
-            tau_tiles(p, rb0, cb0, RB, CB, lane, acc);
-#pragma unroll
-            for (int i = 0; i < kSB; ++i)
-#pragma unroll
-                for (int j = 0; j < kSB; ++j) {
-                    if (rb0 + i >= RB || cb0 + j >= CB) continue;
+                for (int i = 0; i < NR; ++i)
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
-                        const int c = (cb0 + j) * 16 + acc_col(lane, t);
-                        const int jo = c / p.vY, b = c - jo * p.vY;
-                        const int r = (rb0 + i) * 16 + acc_row(lane, t);
+                        const int r = (r0 + i) * 16 + acc_row(lane, t);
                         double tv = 0.0;
                         if (r < p.nX && c < p.nY) {
-                            const int io = r / p.vX, a = r - io * p.vX;
-                            const double dinv =
-                                1.0 / (((p.eX[io] + p.eY[jo]) - p.eX[p.oX + a]) - p.eY[p.oY + b]);
-                            const double v = p.V[(int64_t)r * p.nY + c];
+                            const double dinv = 1.0 / (p.dX[r] + dc);
+                            const double v = IN_LDS ? sV[r * p.ldv + c] : p.V[(int64_t)r * p.nY + c];
                             tv = dinv * (v + acc[i][j][t]);
                             epart += v * tv;
                         }
                         if (couple) tau[(int64_t)r * p.npY + c] = tv;
                     }
-                }
-        }
+            }
+        });
         epart = wave_sum(epart);
         if (lane == 0) red[wave] = epart;
         __syncthreads();
         if (threadIdx.x == 0) {
             double s = 0.0;
-            for (int w = 0; w < kWaves; ++w) s += red[w];
+            for (int w = 0; w < NW; ++w) s += red[w];
             ed2[pd.orig] = 4.0 * s;
         }
-        if (couple) {
-            // ---- G_X += Tau V^T (npX x npX),  G_Y += Tau^T V (npY x npY) ----
-            const int SX = SR * SR, SY = SC * SC;
-            for (int sb = (wave + rot) % kWaves; sb < SX + SY; sb += kWaves) {
-                d4 acc[kSB][kSB];
-#pragma unroll
-                for (int i = 0; i < kSB; ++i)
-#pragma unroll
-                    for (int j = 0; j < kSB; ++j) acc[i][j] = d4(0.0);
-                if (sb < SX) {
-                    const int rb0 = (sb / SR) * kSB, qb0 = (sb % SR) * kSB;
-                    gx_tiles(p, tau, rb0, qb0, RB, lane, acc);
-                    atomic_flush(p.GX, p.npX, p.nX, rb0, qb0, lane, acc);
-                } else {
-                    const int s2 = sb - SX;
-                    const int cb0 = (s2 / SC) * kSB, qb0 = (s2 % SC) * kSB;
-                    gy_tiles(p, tau, cb0, qb0, CB, lane, acc);
-                    atomic_flush(p.GY, p.npY, p.nY, cb0, qb0, lane, acc);
-                }
+        if (IN_LDS) {   // ask the L2 for the next pair's V while this pair finishes
+            const int64_t pn = pair_for(it + 1, n_pair);
+            if (pn < n_pair) {
+                const PairDesc nd = pairs[pn];
+                const int64_t nv = (int64_t)monos[nd.x].n * monos[nd.y].n;
+                const double* vn = V + nd.v_off;
+                for (int64_t e = (int64_t)threadIdx.x * 16; e < nv; e += (int64_t)NT * 16) sink += vn[e];
             }
+        }
+        if (couple) {
+            // ---- G_X += Tau V^T (RB x RB tiles), G_Y += Tau^T V (CB x CB tiles) ----
+            for_tasks(make_grid(RB, RB), make_grid(CB, CB), wave, NW, [&](int which, int r0, int c0, auto shape) {
+                constexpr int NR = decltype(shape)::NR, NC = decltype(shape)::NC;
+                d4 acc[NR][NC];
+                zero(acc);
+                if (which == 0) {
+                    if (IN_LDS) gx_sb_lds(p, sV, tau, r0, c0, lane, acc);
+                    else gx_sb_glb(p, tau, r0, c0, lane, acc);
+                    atomic_flush(p.GX, p.npX, p.nX, r0, c0, lane, acc);
+                } else {
+                    if (IN_LDS) gy_sb_lds(p, sV, tau, r0, c0, lane, acc);
+                    else gy_sb_glb(p, tau, r0, c0, lane, acc);
+                    atomic_flush(p.GY, p.npY, p.nY, r0, c0, lane, acc);
+                }
+            });
         }
         __syncthreads();
     }
+    if (sink == 1.2345e300) ed2[0] = sink;   // keeps the prefetch loads; never true for finite inputs
+}
+
+__global__ __launch_bounds__(kThreadsL) void pair_fp64_lds_kernel(
+    const PairDesc* __restrict__ pairs, int64_t n_pair, const MonoDesc* __restrict__ monos,
+    const double* __restrict__ dif, const double* __restrict__ V, const double* __restrict__ M,
+    double* __restrict__ G, double* __restrict__ scratch, int64_t slot_elems,
+    double* __restrict__ ed2, int couple, const Ctrl* __restrict__ ctrl) {
+    if (ctrl && ctrl->done) return;
+    __shared__ __align__(16) double sV[kLdsV];
+    __shared__ double red[kThreadsL / 64];
+    pair_body<true, kThreadsL>(pairs, n_pair, monos, dif, V, M, G, scratch, slot_elems, ed2, couple, sV, red);
+}
+
+__global__ __launch_bounds__(kThreadsG, 2) void pair_fp64_glb_kernel(
+    const PairDesc* __restrict__ pairs, int64_t n_pair, const MonoDesc* __restrict__ monos,
+    const double* __restrict__ dif, const double* __restrict__ V, const double* __restrict__ M,
+    double* __restrict__ G, double* __restrict__ scratch, int64_t slot_elems,
+    double* __restrict__ ed2, int couple, const Ctrl* __restrict__ ctrl) {
+    if (ctrl && ctrl->done) return;
+    __shared__ double red[kThreadsG / 64];
+    pair_body<false, kThreadsG>(pairs, n_pair, monos, dif, V, M, G, scratch, slot_elems, ed2, couple, nullptr,
+                                red);
 }
 
 }  // namespace
 
-int pair_fp64_blocks_per_cu() {
+int pair_fp64_blocks_per_cu(int lds_variant) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_fp64_kernel, kThreads, 0) != hipSuccess ||
-        n < 1)
-        n = 1;
+    hipError_t e = lds_variant
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_fp64_lds_kernel, kThreadsL, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_fp64_glb_kernel, kThreadsG, 0);
+    if (e != hipSuccess || n < 1) n = 1;
     return n;
 }
 
-void launch_pair_fp64(const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos, const double* eps,
-                      const double* V, const double* M, double* G, double* scratch, int64_t slot_elems,
-                      int grid, double* ed2, int couple, const Ctrl* ctrl, hipStream_t s) {
+bool pair_fits_lds(int nX, int npY) { return (int64_t)nX * (npY + 2) <= kLdsV; }
+
+void launch_pair_fp64(int lds_variant, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
+                      const double* dif, const double* V, const double* M, double* G, double* scratch,
+                      int64_t slot_elems, int grid, double* ed2, int couple, const Ctrl* ctrl, hipStream_t s) {
     if (n_pair <= 0) return;
-    hipLaunchKernelGGL(pair_fp64_kernel, dim3(grid), dim3(kThreads), 0, s, pairs, n_pair, monos, eps,
-                       V, M, G, scratch, slot_elems, ed2, couple, ctrl);
+    if (lds_variant)
+        hipLaunchKernelGGL(pair_fp64_lds_kernel, dim3(grid), dim3(kThreadsL), 0, s, pairs, n_pair, monos, dif, V,
+                           M, G, scratch, slot_elems, ed2, couple, ctrl);
+    else
+        hipLaunchKernelGGL(pair_fp64_glb_kernel, dim3(grid), dim3(kThreadsG), 0, s, pairs, n_pair, monos, dif, V,
+                           M, G, scratch, slot_elems, ed2, couple, ctrl);
 }
 
 }  // namespace mcpt

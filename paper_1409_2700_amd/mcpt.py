@@ -11,7 +11,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmcpt.so")
+LIB_PATH = os.environ.get("MCPT_LIBRARY", os.path.join(_HERE, "libmcpt.so"))
 
 MCPT_OK = 0
 MCPT_PENDING = 1
