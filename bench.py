@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "MCPT(2) solves/s + pair-contraction GB/s at 1000 monomers; p50/p99 served latency"
-PEAK = {"fp64": (78.6, "TFLOP/s"), "fp32": (157.3, "TFLOP/s"), "bf16": (2500.0, "TFLOP/s")}
+PEAK = {"fp64": (78.6, "TFLOP/s"), "fp32": (157.3, "TFLOP/s"), "bf16": (2500.0, "TFLOP/s")}   # MI355X dense
 HBM_PEAK_GBS = 8000.0
 
 
@@ -75,13 +75,62 @@ def cpu_baseline(prob, sweeps: int, budget_s: float = 12.0) -> dict:
     }
 
 
+MODES = {   # name: (precision, polish)
+    "fp64": (0, 1),
+    "bf16+polish": (2, 1),
+    "fp32+polish": (1, 1),
+}
+
+
+def time_mode(ctx, pid, name, steps, warmup, tol, check_every, golden):
+    import numpy as np
+    prec, polish = MODES[name]
+    opts = dict(tol=tol, max_sweeps=200, check_every=check_every, precision=prec, polish=polish)
+    for w in range(warmup):
+        s = ctx.run(pid, **opts)
+        log(f"[bench] {name} warmup {w}: {s['sweeps']} sweeps ({s['polish_sweeps']} FP64) "
+            f"{s['seconds'] * 1e3:.1f} ms E={s['e_total']:.10f}")
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    runs = [ctx.run(pid, **opts) for _ in range(steps)]
+    elapsed = time.perf_counter() - t0
+    tm = ctx.timing()
+    ctx.set_timing(False)
+    s = runs[-1]
+    for k, r in enumerate(runs):
+        log(f"[bench] {name} step {k}: {r['sweeps']} sweeps {r['seconds'] * 1e3:.1f} ms")
+    out = {
+        "solves_per_s": steps / elapsed, "ms_per_solve": elapsed / steps * 1e3, "sweeps": s["sweeps"],
+        "fp64_sweeps": s["sweeps"] if prec == 0 else s["polish_sweeps"], "e_total": s["e_total"],
+        "fp64_pair_avg_ms": tm["pair_ms"] / max(tm["pair_launches"], 1),
+        "fp64_pair_launches_per_solve": tm["pair_launches"] / steps,
+        "lowp_pair_avg_ms": tm["lowp_ms"] / max(tm["lowp_launches"], 1) if tm["lowp_launches"] else None,
+        "lowp_pair_launches_per_solve": tm["lowp_launches"] / steps,
+        "monomer_avg_ms": tm["mono_ms"] / max(tm["mono_launches"], 1),
+        "timing": tm,
+    }
+    if golden is not None:
+        e = ctx.energy(pid, want_t=False)
+        out["error_vs_oracle_Eh"] = {
+            "e_total": abs(s["e_total"] - golden["e_total"]),
+            "e_mono": abs(s["e_mono"] - golden["e_mono"]),
+            "e_dimer": abs(s["e_dimer"] - golden["e_dimer"]),
+            "max_e_m2": float(np.max(np.abs(e["e_m2"] - np.asarray(golden["e_m2"])))),
+            "max_e_d2_sampled": float(np.max(np.abs(np.asarray(e["e_d2"])[golden["pair_index"]]
+                                                    - np.asarray(golden["e_d2"])))),
+        }
+        out["relative_error_e_total"] = out["error_vs_oracle_Eh"]["e_total"] / abs(golden["e_total"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="hf-10x10x10-c3")
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--headline", default="fp64", choices=list(MODES))
+    ap.add_argument("--modes", default=",".join(MODES), help="comma-separated forms to time")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--check-every", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -93,10 +142,14 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import paper_1409_2700_amd as mc
     from synth import make_workload, DEFAULT_COUPLING_SCALE
 
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", f"{args.workload}.json")
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            golden = json.load(f)
     t0 = time.time()
     prob = make_workload(args.workload)
     log(f"[bench] inputs {args.workload}: N={prob.n_mono} P={prob.n_pair} "
@@ -105,52 +158,54 @@ def main():
     t0 = time.time()
     pid = ctx.upload(prob)
     log(f"[bench] upload {time.time() - t0:.1f}s")
-    opts = dict(tol=args.tol, max_sweeps=200, check_every=args.check_every)
-    for w in range(args.warmup):
-        s = ctx.run(pid, **opts)
-        log(f"[bench] warmup {w}: {s['sweeps']} sweeps {s['seconds'] * 1e3:.1f} ms E={s['e_total']:.10f}")
-    ctx.set_timing(True)
-    t0 = time.perf_counter()
-    runs = []
-    for k in range(args.steps):
-        runs.append(ctx.run(pid, **opts))
-    elapsed = time.perf_counter() - t0
-    tm = ctx.timing()
-    ctx.set_timing(False)
-    s = runs[-1]
-    for k, r in enumerate(runs):
-        log(f"[bench] step {k}: {r['sweeps']} sweeps {r['seconds'] * 1e3:.1f} ms")
-    value = args.steps / elapsed
-    pair_avg_ms = tm["pair_ms"] / max(tm["pair_launches"], 1)
-    flops_per_launch = tm["pair_flops"] / max(tm["pair_launches"], 1)
-    achieved_tf = flops_per_launch / (pair_avg_ms * 1e-3) / 1e12
-    peak, unit = PEAK[args.precision]
-    gbs = tm["pair_v_bytes"] / (tm["pair_ms"] * 1e-3) / 1e9
+    modes = [m for m in args.modes.split(",") if m]
+    if args.headline not in modes:
+        modes.insert(0, args.headline)
+    results = {}
+    for name in modes:
+        results[name] = time_mode(ctx, pid, name, args.steps, args.warmup, args.tol, args.check_every, golden)
+    ctx.release(pid)
+    ctx.close()
+
+    h = results[args.headline]
+    tm = h["timing"]
+    prec = MODES[args.headline][0]
+    if prec == 0 or tm["pair_ms"] >= tm["lowp_ms"]:
+        kname, kms, kl, kfl, kvb, kpeak = ("pair_fp64_lds_kernel", tm["pair_ms"], tm["pair_launches"],
+                                           tm["pair_flops"], tm["pair_v_bytes"], PEAK["fp64"][0])
+        dtype = "f64"
+    else:
+        kname, kms, kl, kfl, kvb = ("pair_lowp_kernel", tm["lowp_ms"], tm["lowp_launches"], tm["lowp_flops"],
+                                    tm["lowp_v_bytes"])
+        kpeak = PEAK["bf16" if prec == 2 else "fp32"][0]
+        dtype = "bf16+f64" if prec == 2 else "f32+f64"
+    avg_ms = kms / max(kl, 1)
+    flops_per_launch = kfl / max(kl, 1)
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
     out = {
-        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "metric": METRIC, "value": h["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": h["ms_per_solve"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": {
             "workload": args.workload, "n_mono": prob.n_mono, "n_pair": prob.n_pair, "o": 5, "v": 27,
             "lattice": "simple cubic 3.4 A, open boundaries", "coupling_scale": DEFAULT_COUPLING_SCALE,
-            "tol": args.tol, "precision": args.precision, "sweeps": s["sweeps"],
+            "tol": args.tol, "form": args.headline, "sweeps": h["sweeps"],
         },
-        "pair_contraction_GBps": gbs,
-        "e_total": s["e_total"],
+        "pair_contraction_GBps": kvb / (kms * 1e-3) / 1e9,
+        "e_total": h["e_total"],
         "roofline": {
-            "bound": "mfma", "achieved": achieved_tf, "peak": peak, "unit": unit,
-            "frac": achieved_tf / peak, "traffic": None,
-            "kernel": "pair_fp64_kernel", "avg_launch_ms": pair_avg_ms,
-            "flops_per_launch": flops_per_launch, "launches": tm["pair_launches"],
+            "bound": "mfma", "achieved": achieved, "peak": kpeak, "unit": "TFLOP/s",
+            "frac": achieved / kpeak, "traffic": None, "kernel": kname, "avg_launch_ms": avg_ms,
+            "flops_per_launch": flops_per_launch, "launches": kl,
         },
-        "monomer_phase": {"avg_launch_ms": tm["mono_ms"] / max(tm["mono_launches"], 1),
-                          "launches": tm["mono_launches"]},
+        "forms": {k: {kk: vv for kk, vv in v.items() if kk != "timing"} for k, v in results.items()},
     }
-    ctx.release(pid)
-    ctx.close()
+    if golden is not None:
+        out["oracle_reference"] = {"e_total": golden["e_total"], "sweeps": golden["sweeps"],
+                                   "file": f"tests/golden/{args.workload}.json"}
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a sample ...")
-        out["cpu_baseline"] = cpu_baseline(prob, s["sweeps"], args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(prob, golden["sweeps"] if golden else h["sweeps"], args.cpu_budget)
         log(f"[bench] cpu_baseline {out['cpu_baseline']['value']:.3e} solves/s")
     print(json.dumps(out), flush=True)
 

@@ -52,7 +52,12 @@ typedef enum {
 } mcpt_status;
 
 /* Arithmetic of the pair contractions (Eqs. 58-59).  Denominators, residual,
- * energies and the monomer update are FP64 in every mode. */
+ * energies and the monomer update are FP64 in every mode.  Reduced precision
+ * with polish = 1 is defect correction: each FP64 sweep gives the FP64 residual
+ * r = F(T) - T (the convergence test), then inner_sweeps reduced-precision sweeps
+ * of the homogeneous equation delta = r + L(delta) (no integral source terms)
+ * give the correction T += delta; the final energies come from an FP64 pass.
+ * With polish = 0 the reduced-precision sweeps iterate Eqs. 58-59 directly. */
 typedef enum {
     MCPT_FP64 = 0,               /* FP64 MFMA */
     MCPT_FP32 = 1,               /* FP32 MFMA, FP32 accumulation */
@@ -90,7 +95,7 @@ typedef struct {
                                     FP64 residual < tol; 0 = stop at the reduced-precision residual */
     int32_t        deterministic;/* 1 = no floating-point atomics: bitwise repeatable results */
     int32_t        check_every;  /* sweeps issued between host checks of the device residual (>= 1) */
-    int32_t        reserved;
+    int32_t        inner_sweeps; /* reduced precision + polish: correction sweeps per FP64 sweep (0 = default) */
     const double  *warm_t;       /* NULL, or host T (layout of t_amp in mcpt_energy) to start from */
 } mcpt_options;
 
@@ -117,6 +122,10 @@ typedef struct {
     double  pair_flops;     /* algorithmic flops of the timed pair launches: 4 nX nY (nX + nY) per pair
                                with coupling, 2 nX nY (nX + nY) for energy-only passes */
     double  pair_v_bytes;   /* dimer-block bytes those launches streamed (sizeof element x nX nY per pair) */
+    double  lowp_ms;        /* summed duration of reduced-precision pair-phase launches */
+    int64_t lowp_launches;
+    double  lowp_flops;     /* algorithmic flops of those launches (4 nX nY (nX + nY) per pair) */
+    double  lowp_v_bytes;   /* bytes of the reduced-precision dimer blocks (V and V^T) they read */
 } mcpt_timing;
 
 /* Create a context on HIP device `device`; at most hbm_budget_bytes of device

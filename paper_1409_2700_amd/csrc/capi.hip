@@ -59,13 +59,22 @@ struct Resident {
     size_t bytes = 0;
     bool has_result = false;
     mcpt_summary last{};
+    // reduced-precision copies (mixed-precision form), made on first use of a precision
+    int lo_prec = 0;
+    void *d_Vlo = nullptr, *d_Mlo = nullptr;
+    int64_t *d_lo_off = nullptr, *d_mlo_off = nullptr;
+    double *d_R = nullptr, *d_Dl = nullptr;
+    int64_t lo_slot = 0;          // elements of one low-precision Tau + Tau^T scratch slot
+    double lo_v_bytes = 0.0;      // bytes of the low-precision V and V^T
+    std::vector<void*> lo_allocations;
+    size_t lo_bytes = 0;
 };
 
 struct Timing {
     bool on = false;
     struct Rec {
         hipEvent_t a, b;
-        int kind;   // 0 pair, 1 monomer
+        int kind;   // 0 FP64 pair phase, 1 monomer phase, 2 reduced-precision pair phase
         double flops, vbytes;
     };
     std::vector<Rec> pending;
@@ -91,6 +100,9 @@ struct mcpt_ctx {
     int64_t scratch_slot = 0;
     int scratch_slots = 0;
     int grid_lds = 0, grid_glb = 0;   // persistent grids of the two pair-kernel variants
+    void* d_scratch_lo = nullptr;     // reduced-precision Tau scratch
+    size_t scratch_lo_bytes = 0;
+    int grid_lo = 0;
     Timing timing;
 };
 
@@ -103,11 +115,39 @@ mcpt_status ensure_device(mcpt_ctx* c) {
     return MCPT_OK;
 }
 
+void free_lowp(mcpt_ctx* c, Resident* r) {
+    for (void* p : r->lo_allocations) (void)hipFree(p);
+    r->lo_allocations.clear();
+    c->in_use -= std::min(c->in_use, r->lo_bytes);
+    r->lo_bytes = 0;
+    r->lo_prec = 0;
+    r->d_Vlo = r->d_Mlo = nullptr;
+    r->d_lo_off = r->d_mlo_off = nullptr;
+    r->d_R = r->d_Dl = nullptr;
+}
+
 void free_resident(mcpt_ctx* c, Resident* r) {
+    free_lowp(c, r);
     for (void* p : r->allocations) (void)hipFree(p);
     r->allocations.clear();
     c->in_use -= std::min(c->in_use, r->bytes);
     r->bytes = 0;
+}
+
+mcpt_status lo_alloc(mcpt_ctx* c, Resident* r, void** out, size_t bytes) {
+    bytes = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+    if (c->in_use + bytes > c->budget) return fail(MCPT_ERR_ADMISSION, "reduced-precision copies exceed the budget");
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MCPT_ERR_NOMEM, "hipMalloc of reduced-precision copies failed");
+    }
+    r->lo_allocations.push_back(p);
+    r->lo_bytes += bytes;
+    c->in_use += bytes;
+    *out = p;
+    return MCPT_OK;
 }
 
 template <class T>
@@ -148,6 +188,11 @@ void drain_timing(Timing& t) {
                 t.tot.pair_launches += 1;
                 t.tot.pair_flops += r.flops;
                 t.tot.pair_v_bytes += r.vbytes;
+            } else if (r.kind == 2) {
+                t.tot.lowp_ms += ms;
+                t.tot.lowp_launches += 1;
+                t.tot.lowp_flops += r.flops;
+                t.tot.lowp_v_bytes += r.vbytes;
             } else {
                 t.tot.mono_ms += ms;
                 t.tot.mono_launches += 1;
@@ -390,9 +435,10 @@ mcpt_status validate_options(const mcpt_options* o) {
     if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(MCPT_ERR_INVALID, "tol must be finite and >= 0");
     if (o->max_sweeps < 0 || o->max_sweeps >= kMaxSweeps)
         return fail(MCPT_ERR_INVALID, "max_sweeps must be in [0, " + std::to_string(kMaxSweeps - 1) + "]");
-    if (o->precision != MCPT_FP64)
-        return fail(MCPT_ERR_INVALID, "precision not supported by this build");
+    if (o->precision < MCPT_FP64 || o->precision > MCPT_BF16)
+        return fail(MCPT_ERR_INVALID, "precision must be MCPT_FP64, MCPT_FP32 or MCPT_BF16");
     if (o->check_every < 0) return fail(MCPT_ERR_INVALID, "check_every must be >= 0");
+    if (o->inner_sweeps < 0 || o->inner_sweeps > 64) return fail(MCPT_ERR_INVALID, "inner_sweeps must be in [0, 64]");
     return MCPT_OK;
 }
 
@@ -418,11 +464,100 @@ void pair_phase(mcpt_ctx* c, Resident* R, double* G, int couple, const Ctrl* ctr
                      c->d_scratch, c->scratch_slot, c->grid_glb, R->d_ed2, couple, ctrl, c->stream);
 }
 
+// Reduced-precision copies of a resident problem for `prec` (1 FP32, 2 BF16):
+// V and V^T per pair (rows padded to 16, k padded to the chunk), M per monomer,
+// and FP64 buffers for the polish residual R and correction delta.
+mcpt_status ensure_lowp(mcpt_ctx* c, Resident* R, int prec) {
+    if (R->lo_prec == prec) return MCPT_OK;
+    free_lowp(c, R);
+    const int kc = lowp_chunk(prec);
+    const size_t es = prec == MCPT_BF16 ? 2 : 4;
+    auto ld = [kc](int n) { return (int64_t)((n + kc - 1) / kc * kc); };
+    std::vector<int64_t> lo_off(std::max<int64_t>(R->n_pair, 1), 0), mlo_off(R->n_mono);
+    int64_t vo = 0, slot = 0;
+    for (int64_t p = 0; p < R->n_pair; ++p) {
+        const MonoDesc &dx = R->monos[R->pairs[p].x], &dy = R->monos[R->pairs[p].y];
+        lo_off[p] = vo;
+        const int64_t sz = dx.np * ld(dy.n) + dy.np * ld(dx.n);
+        vo += sz;
+        slot = std::max(slot, sz);
+    }
+    int64_t mo = 0;
+    for (int x = 0; x < R->n_mono; ++x) {
+        mlo_off[x] = mo;
+        mo += R->monos[x].np * ld(R->monos[x].n);
+    }
+    mcpt_status st;
+    void *vlo = nullptr, *mlo = nullptr, *lo_o = nullptr, *mlo_o = nullptr, *rr = nullptr, *dd = nullptr;
+    if ((st = lo_alloc(c, R, &vlo, vo * es)) != MCPT_OK || (st = lo_alloc(c, R, &mlo, mo * es)) != MCPT_OK ||
+        (st = lo_alloc(c, R, &lo_o, lo_off.size() * 8)) != MCPT_OK ||
+        (st = lo_alloc(c, R, &mlo_o, mlo_off.size() * 8)) != MCPT_OK ||
+        (st = lo_alloc(c, R, &rr, R->mat_elems * 8)) != MCPT_OK ||
+        (st = lo_alloc(c, R, &dd, R->mat_elems * 8)) != MCPT_OK) {
+        free_lowp(c, R);
+        return st;
+    }
+    hipStream_t s = c->stream;
+    HIP_TRY(hipMemcpyAsync(lo_o, lo_off.data(), lo_off.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(mlo_o, mlo_off.data(), mlo_off.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(mlo, 0, mo * es, s));   // padding of M stays zero
+    launch_fill(static_cast<double*>(rr), R->mat_elems, 0.0, s);
+    launch_fill(static_cast<double*>(dd), R->mat_elems, 0.0, s);
+    launch_convert_v(prec, R->d_pairs, R->n_pair, R->d_monos, R->d_V, vlo, static_cast<int64_t*>(lo_o), s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    R->d_Vlo = vlo;
+    R->d_Mlo = mlo;
+    R->d_lo_off = static_cast<int64_t*>(lo_o);
+    R->d_mlo_off = static_cast<int64_t*>(mlo_o);
+    R->d_R = static_cast<double*>(rr);
+    R->d_Dl = static_cast<double*>(dd);
+    R->lo_slot = (slot + 63) / 64 * 64;   // keeps every slot 16-byte aligned
+    R->lo_v_bytes = (double)vo * es;
+    R->lo_prec = prec;
+    // scratch for the reduced-precision Tau and Tau^T
+    c->grid_lo = std::max(8, c->n_cu * pair_lowp_blocks_per_cu(prec) / 8 * 8);
+    const size_t need = (size_t)R->lo_slot * es * c->grid_lo;
+    if (need > c->scratch_lo_bytes) {
+        if (c->d_scratch_lo) (void)hipFree(c->d_scratch_lo);
+        c->d_scratch_lo = nullptr;
+        c->scratch_lo_bytes = 0;
+        hipError_t e = hipMalloc(&c->d_scratch_lo, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MCPT_ERR_NOMEM, "reduced-precision scratch allocation failed");
+        }
+        c->scratch_lo_bytes = need;
+    }
+    return MCPT_OK;
+}
+
+void lowp_phase(mcpt_ctx* c, Resident* R, double* G, int source) {
+    launch_pair_lowp(R->lo_prec, R->d_pairs, R->n_pair, R->d_monos, R->d_dif, R->d_Vlo, R->d_lo_off, R->d_Mlo,
+                     R->d_mlo_off, G, c->d_scratch_lo, R->lo_slot, c->grid_lo, R->d_ed2, source, 1, nullptr,
+                     c->stream);
+}
+
+void mixed_mono(mcpt_ctx* c, Resident* R, int mode, const double* G, double* Gz, bool lo_out, const Ctrl* ctrl) {
+    launch_monomer_mixed(mode, R->lo_prec, R->d_monos, R->n_mono, R->d_dif, R->d_K, G, Gz, R->d_T, R->d_M, R->d_R,
+                         R->d_Dl, lo_out ? R->d_Mlo : nullptr, R->d_mlo_off, R->d_em2, R->d_em2_0, R->d_res, ctrl,
+                         c->stream);
+}
+
+mcpt_status sync_ctrl(mcpt_ctx* c) {
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(c->h_ctrl, c->d_ctrl, offsetof(Ctrl, hist), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return MCPT_OK;
+}
+
 mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* out) {
     mcpt_status st = validate_options(o);
     if (st != MCPT_OK) return st;
     if ((st = ensure_device(c)) != MCPT_OK) return st;
     if ((st = ensure_scratch(c, R->max_slot)) != MCPT_OK) return st;
+    const int prec = o->precision;
+    if (prec != MCPT_FP64 && (st = ensure_lowp(c, R, prec)) != MCPT_OK) return st;
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = c->stream;
     R->has_result = false;
@@ -446,43 +581,95 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
         launch_monomer(kMonoInit, R->d_monos, R->n_mono, R->d_dif, R->d_K, nullptr, nullptr, R->d_T, R->d_M,
                        R->d_em2, R->d_em2_0, R->d_res, nullptr, R->max_np, s);
     }
+    if (prec != MCPT_FP64) mixed_mono(c, R, kMonoFromT, nullptr, nullptr, true, nullptr);   // M in low precision
     HIP_TRY(hipGetLastError());
     const double fl_sweep = pair_flops(*R, true), fl_final = pair_flops(*R, false);
     const double vb = (double)R->v_elems * sizeof(double);
     const int every = o->check_every > 0 ? o->check_every : 1;
-    int issued = 0, cur = 0;
-    while (issued < o->max_sweeps) {
-        const int batch = std::min(every, o->max_sweeps - issued);
-        for (int k = 0; k < batch; ++k) {
+    int cur = 0, n_lo = 0, n_hi = 0;
+
+    if (prec == MCPT_FP64 || !o->polish) {
+        // plain Jacobi sweeps: FP64, or reduced precision with the integral source terms
+        int issued = 0;
+        while (issued < o->max_sweeps) {
+            const int batch = std::min(every, o->max_sweeps - issued);
+            for (int k = 0; k < batch; ++k) {
+                hipEvent_t a = nullptr;
+                record_begin(c, &a);
+                if (prec == MCPT_FP64) {
+                    pair_phase(c, R, R->d_G[cur], 1, c->d_ctrl);
+                    record_end(c, a, 0, fl_sweep, vb);
+                } else {
+                    lowp_phase(c, R, R->d_G[cur], 1);
+                    record_end(c, a, 2, fl_sweep, R->lo_v_bytes);
+                }
+                record_begin(c, &a);
+                if (prec == MCPT_FP64)
+                    launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->d_dif, R->d_K, R->d_G[cur],
+                                   R->d_G[cur ^ 1], R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, c->d_ctrl,
+                                   R->max_np, s);
+                else
+                    mixed_mono(c, R, kMonoUpdate, R->d_G[cur], R->d_G[cur ^ 1], true, c->d_ctrl);
+                record_end(c, a, 1, 0.0, 0.0);
+                launch_reduce_sweep(R->n_mono, R->d_res, c->d_ctrl, s);
+                cur ^= 1;
+                ++issued;
+            }
+            if ((st = sync_ctrl(c)) != MCPT_OK) return st;
+            if (h.done) break;
+        }
+        if (prec == MCPT_FP64) n_hi = h.sweeps;
+        else n_lo = h.sweeps;
+    } else {
+        // FP64 defect correction: each FP64 sweep gives r = F(T) - T and the convergence test;
+        // `inner` reduced-precision sweeps solve delta = r + L(delta); then T += delta.
+        const int inner = o->inner_sweeps > 0 ? o->inner_sweeps : (prec == MCPT_BF16 ? 3 : 5);
+        for (int k = 0; k < inner + 1 && k < o->max_sweeps; ++k) {   // a few plain reduced-precision sweeps first
+            hipEvent_t a = nullptr;
+            record_begin(c, &a);
+            lowp_phase(c, R, R->d_G[cur], 1);
+            record_end(c, a, 2, fl_sweep, R->lo_v_bytes);
+            mixed_mono(c, R, kMonoUpdate, R->d_G[cur], R->d_G[cur ^ 1], true, nullptr);
+            cur ^= 1;
+            ++n_lo;
+        }
+        for (;;) {
             hipEvent_t a = nullptr;
             record_begin(c, &a);
             pair_phase(c, R, R->d_G[cur], 1, c->d_ctrl);
             record_end(c, a, 0, fl_sweep, vb);
-            record_begin(c, &a);
-            launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->d_dif, R->d_K, R->d_G[cur], R->d_G[cur ^ 1],
-                           R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, c->d_ctrl, R->max_np, s);
-            record_end(c, a, 1, 0.0, 0.0);
+            mixed_mono(c, R, kMonoUpdateR, R->d_G[cur], R->d_G[cur ^ 1], false, c->d_ctrl);
             launch_reduce_sweep(R->n_mono, R->d_res, c->d_ctrl, s);
             cur ^= 1;
-            ++issued;
+            ++n_hi;
+            if ((st = sync_ctrl(c)) != MCPT_OK) return st;
+            if (h.done) break;
+            mixed_mono(c, R, kMonoRlo, nullptr, nullptr, true, nullptr);
+            for (int k = 0; k < inner; ++k) {
+                record_begin(c, &a);
+                lowp_phase(c, R, R->d_G[cur], 0);
+                record_end(c, a, 2, fl_sweep, R->lo_v_bytes);
+                mixed_mono(c, R, kMonoCorr, R->d_G[cur], R->d_G[cur ^ 1], true, nullptr);
+                cur ^= 1;
+                ++n_lo;
+            }
+            mixed_mono(c, R, kMonoApply, nullptr, nullptr, false, nullptr);
+            mixed_mono(c, R, kMonoFromT, nullptr, nullptr, false, nullptr);
         }
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(&h, c->d_ctrl, offsetof(Ctrl, hist), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (h.done) break;
     }
     if (h.status == MCPT_ERR_DIVERGED) {
         if (c->timing.on) drain_timing(c->timing);
         mcpt_summary sm{};
         sm.residual = h.residual;
-        sm.sweeps = h.sweeps;
+        sm.sweeps = n_lo + n_hi;
+        sm.polish_sweeps = (prec != MCPT_FP64 && o->polish) ? n_hi : 0;
         sm.status = MCPT_ERR_DIVERGED;
         sm.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         R->last = sm;
         if (out) *out = sm;
-        return fail(MCPT_ERR_DIVERGED, "iteration diverged after " + std::to_string(h.sweeps) + " sweeps");
+        return fail(MCPT_ERR_DIVERGED, "iteration diverged after " + std::to_string(sm.sweeps) + " sweeps");
     }
-    // energies of the returned amplitudes: Tau recomputed from the final T
+    // energies of the returned amplitudes: FP64 Tau recomputed from the final T
     {
         hipEvent_t a = nullptr;
         record_begin(c, &a);
@@ -490,9 +677,7 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
         record_end(c, a, 0, fl_final, vb);
     }
     launch_reduce_final(R->n_mono, R->n_pair, R->d_em2, R->d_em2_0, R->d_ed2, c->d_ctrl, s);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(&h, c->d_ctrl, offsetof(Ctrl, hist), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    if ((st = sync_ctrl(c)) != MCPT_OK) return st;
     if (c->timing.on) drain_timing(c->timing);
     mcpt_summary sm{};
     sm.e_mono = h.e_mono;
@@ -500,8 +685,8 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
     sm.e_total = h.e_mono + h.e_dimer;
     sm.e_mono0 = h.e_mono0;
     sm.residual = h.residual;
-    sm.sweeps = h.sweeps;
-    sm.polish_sweeps = 0;
+    sm.sweeps = n_lo + n_hi;
+    sm.polish_sweeps = (prec != MCPT_FP64 && o->polish) ? n_hi : 0;
     if (h.fixed) sm.status = MCPT_OK;
     else if (h.sweeps > 0 && h.residual < o->tol) sm.status = MCPT_OK;
     else sm.status = MCPT_ERR_NOT_CONVERGED;
@@ -510,7 +695,7 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
     R->last = sm;
     if (out) *out = sm;
     if (sm.status != MCPT_OK)
-        return fail((mcpt_status)sm.status, "not converged after " + std::to_string(h.sweeps) + " sweeps");
+        return fail((mcpt_status)sm.status, "not converged after " + std::to_string(sm.sweeps) + " sweeps");
     g_err.clear();
     return MCPT_OK;
 }
@@ -554,6 +739,7 @@ void mcpt_destroy(mcpt_ctx* c) {
     if (c->timing.on) drain_timing(c->timing);
     for (hipEvent_t e : c->timing.pool) (void)hipEventDestroy(e);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
+    if (c->d_scratch_lo) (void)hipFree(c->d_scratch_lo);
     if (c->d_ctrl) (void)hipFree(c->d_ctrl);
     if (c->d_flag) (void)hipFree(c->d_flag);
     if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);

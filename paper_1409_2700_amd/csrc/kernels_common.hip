@@ -78,13 +78,24 @@ __device__ double block_max(double x, double* sh) {
 // Monomer phase, one workgroup per monomer.  For element (r, c) = ((i,a),(j,b))
 // the occupied-swapped partner S(r, c) = ((j,a),(i,b)) has the same denominator
 // e_i + e_j - e_a - e_b (Eqs. 60-61), formed as (e_i - e_a) + (e_j - e_b) from the
-// per-monomer differences; both T values are formed by the same
-// thread so M = 2T - S(T) (the spin-adapted combination of Eq. 59) needs no
-// second pass.  E_M2 = <2K - S(K), T> = <K, M> (Eq. 54).
+// per-monomer differences; both values are formed by the same thread so the
+// spin-adapted combination 2X - S(X) of Eq. 59 needs no second pass (values at
+// S(r, c) are recomputed from inputs, never read from an output).
+// E_M2 = <2K - S(K), T> = <K, M> (Eq. 54).  Modes:
+//   init      T = D K, M, E_M2 -> em2 and em2_0
+//   update    T' = D (K + G + G^T), residual |T' - T|, M', E_M2(T')
+//   from_t    M and E_M2 of the stored T
+//   e0        E_M2 of D K into em2_0 only
+//   update_r  as update, and R = T' - T kept, low-precision copy of 2R - S(R)
+//   corr      delta = R + D (G + G^T) (homogeneous equation), low-precision 2 delta - S(delta)
+//   apply     T += delta - R (elementwise)
+// Mlo (optional) receives the low-precision copy of the combination written.
+template <class E>
 __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
     int mode, const MonoDesc* __restrict__ monos, const double* __restrict__ dif,
     const double* __restrict__ K, const double* __restrict__ G, double* __restrict__ Gz,
-    double* __restrict__ T, double* __restrict__ M, double* __restrict__ em2,
+    double* __restrict__ T, double* __restrict__ M, double* __restrict__ R, double* __restrict__ Dl,
+    E* __restrict__ Mlo, const int64_t* __restrict__ mlo_off, int lo_chunk, double* __restrict__ em2,
     double* __restrict__ em2_0, double* __restrict__ res, const Ctrl* __restrict__ ctrl) {
     if (ctrl && ctrl->done) return;
     __shared__ double sh[kMonoThreads];
@@ -96,6 +107,10 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
     const double* Gx = G ? G + d.mat_off : nullptr;
     double* Tx = T + d.mat_off;
     double* Mx = M + d.mat_off;
+    double* Rx = R ? R + d.mat_off : nullptr;
+    double* Dx = Dl ? Dl + d.mat_off : nullptr;
+    E* Ml = Mlo ? Mlo + mlo_off[x] : nullptr;
+    const int ldl = (n + lo_chunk - 1) / lo_chunk * lo_chunk;
     double rmax = 0.0, esum = 0.0;
     const int nn = n * n;
     for (int idx = threadIdx.x; idx < nn; idx += kMonoThreads) {
@@ -104,13 +119,38 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
         const int j = c / v, b = c - j * v;
         const int rs = j * v + a, cs = i * v + b;
         const int64_t e_rc = (int64_t)r * np + c, e_s = (int64_t)rs * np + cs;
+        const int64_t e_t = (int64_t)c * np + r, e_st = (int64_t)cs * np + rs;
+        if (mode == kMonoApply) {
+            Tx[e_rc] += Dx[e_rc] - Rx[e_rc];
+            continue;
+        }
         const double dinv = 1.0 / (dx[r] + dx[c]);
-        double tn, ts;
-        if (mode == kMonoUpdate) {
-            tn = dinv * ((Kx[e_rc] + Gx[e_rc]) + Gx[(int64_t)c * np + r]);
-            ts = dinv * ((Kx[e_s] + Gx[e_s]) + Gx[(int64_t)cs * np + rs]);
-            const double dt = fabs(tn - Tx[e_rc]);
-            rmax = max_nan(rmax, dt);
+        double tn, ts, lo = 0.0;
+        bool has_lo = false;
+        if (mode == kMonoUpdate || mode == kMonoUpdateR) {
+            tn = dinv * ((Kx[e_rc] + Gx[e_rc]) + Gx[e_t]);
+            ts = dinv * ((Kx[e_s] + Gx[e_s]) + Gx[e_st]);
+            const double told = Tx[e_rc];
+            rmax = max_nan(rmax, fabs(tn - told));
+            if (mode == kMonoUpdateR) {
+                // R at S(r,c) would need the old T there, which its own thread overwrites;
+                // the combination 2R - S(R) is formed by a following rlo launch instead.
+                Rx[e_rc] = tn - told;
+            } else {
+                lo = 2.0 * tn - ts;
+                has_lo = true;
+            }
+        } else if (mode == kMonoCorr) {
+            tn = Rx[e_rc] + dinv * (Gx[e_rc] + Gx[e_t]);
+            ts = Rx[e_s] + dinv * (Gx[e_s] + Gx[e_st]);
+            Dx[e_rc] = tn;
+            lo = 2.0 * tn - ts;
+            has_lo = true;
+        } else if (mode == kMonoRlo) {
+            tn = Rx[e_rc];
+            ts = Rx[e_s];
+            lo = 2.0 * tn - ts;
+            has_lo = true;
         } else if (mode == kMonoFromT) {
             tn = Tx[e_rc];
             ts = Tx[e_s];
@@ -118,20 +158,24 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
             tn = dinv * Kx[e_rc];
             ts = dinv * Kx[e_s];
         }
-        const double m = 2.0 * tn - ts;
-        esum += Kx[e_rc] * m;
-        if (mode == kMonoInit || mode == kMonoUpdate) {
-            Tx[e_rc] = tn;
-            Mx[e_rc] = m;
-        } else if (mode == kMonoFromT) {
-            Mx[e_rc] = m;
+        if (mode != kMonoCorr && mode != kMonoRlo) {
+            const double m = 2.0 * tn - ts;
+            esum += Kx[e_rc] * m;
+            if (mode == kMonoInit || mode == kMonoUpdate || mode == kMonoUpdateR) Tx[e_rc] = tn;
+            if (mode != kMonoE0) Mx[e_rc] = m;
+            if (!has_lo) {
+                lo = m;
+                has_lo = true;
+            }
         }
+        if (Ml && has_lo) Ml[(int64_t)r * ldl + c] = (E)(float)lo;
     }
     if (Gz) {
         double* gz = Gz + d.mat_off;
         const int npp = np * np;
         for (int idx = threadIdx.x; idx < npp; idx += kMonoThreads) gz[idx] = 0.0;
     }
+    if (mode == kMonoApply || mode == kMonoRlo || mode == kMonoCorr) return;
     const double etot = block_sum<kMonoThreads>(esum, sh);
     const double rtot = block_max<kMonoThreads>(rmax, sh);
     if (threadIdx.x == 0) {
@@ -140,7 +184,7 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
         } else {
             em2[x] = etot;
             if (mode == kMonoInit) em2_0[x] = etot;
-            if (mode == kMonoUpdate) res[x] = rtot;
+            if (mode == kMonoUpdate || mode == kMonoUpdateR) res[x] = rtot;
         }
     }
 }
@@ -238,8 +282,21 @@ void launch_nonfinite(const double* p, int64_t n, int32_t* flag, hipStream_t s) 
 void launch_monomer(int mode, const MonoDesc* monos, int n_mono, const double* dif, const double* K,
                     const double* G, double* G_zero, double* T, double* M, double* em2,
                     double* em2_0, double* res, const Ctrl* ctrl, int /*max_np*/, hipStream_t s) {
-    hipLaunchKernelGGL(monomer_kernel, dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif, K,
-                       G, G_zero, T, M, em2, em2_0, res, ctrl);
+    hipLaunchKernelGGL(monomer_kernel<float>, dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif, K, G,
+                       G_zero, T, M, (double*)nullptr, (double*)nullptr, (float*)nullptr, (const int64_t*)nullptr,
+                       16, em2, em2_0, res, ctrl);
+}
+
+void launch_monomer_mixed(int mode, int precision, const MonoDesc* monos, int n_mono, const double* dif,
+                          const double* K, const double* G, double* G_zero, double* T, double* M, double* R,
+                          double* Dl, void* Mlo, const int64_t* mlo_off, double* em2, double* em2_0,
+                          double* res, const Ctrl* ctrl, hipStream_t s) {
+    if (precision == 2)
+        hipLaunchKernelGGL(monomer_kernel<__bf16>, dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif, K, G,
+                           G_zero, T, M, R, Dl, static_cast<__bf16*>(Mlo), mlo_off, 32, em2, em2_0, res, ctrl);
+    else
+        hipLaunchKernelGGL(monomer_kernel<float>, dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif, K, G,
+                           G_zero, T, M, R, Dl, static_cast<float*>(Mlo), mlo_off, 16, em2, em2_0, res, ctrl);
 }
 
 void launch_reduce_sweep(int n_mono, const double* res, Ctrl* ctrl, hipStream_t s) {

@@ -55,7 +55,11 @@ enum MonoMode : int {
     kMonoInit = 0,      // T = D*K, M, E_M2 -> em2 and em2_0
     kMonoUpdate = 1,    // T' = D*(K + G + G^T), residual, M', E_M2(T')
     kMonoFromT = 2,     // M and E_M2 from the T already stored
-    kMonoE0 = 3         // E_M2 of D*K into em2_0 only (warm starts)
+    kMonoE0 = 3,        // E_M2 of D*K into em2_0 only (warm starts)
+    kMonoUpdateR = 4,   // update, keeping R = T' - T (FP64 polish sweep)
+    kMonoCorr = 5,      // delta = R + D*(G + G^T), low-precision 2 delta - S(delta)
+    kMonoApply = 6,     // T += delta - R
+    kMonoRlo = 7        // low-precision 2R - S(R)
 };
 
 // ---- launchers (kernels_common.hip) ----
@@ -69,6 +73,10 @@ void launch_monomer(int mode, const MonoDesc* monos, int n_mono, const double* d
                     const double* K, const double* G, double* G_zero, double* T, double* M,
                     double* em2, double* em2_0, double* res, const Ctrl* ctrl, int max_np,
                     hipStream_t s);
+void launch_monomer_mixed(int mode, int precision, const MonoDesc* monos, int n_mono, const double* dif,
+                          const double* K, const double* G, double* G_zero, double* T, double* M, double* R,
+                          double* Dl, void* Mlo, const int64_t* mlo_off, double* em2, double* em2_0,
+                          double* res, const Ctrl* ctrl, hipStream_t s);
 void launch_reduce_sweep(int n_mono, const double* res, Ctrl* ctrl, hipStream_t s);
 void launch_reduce_final(int n_mono, int64_t n_pair, const double* em2, const double* em2_0,
                          const double* ed2, Ctrl* ctrl, hipStream_t s);
@@ -84,5 +92,15 @@ void launch_pair_fp64(int lds_variant, const PairDesc* pairs, int64_t n_pair, co
                       const Ctrl* ctrl, hipStream_t s);
 int pair_fp64_blocks_per_cu(int lds_variant);
 bool pair_fits_lds(int nX, int npY);
+
+// ---- reduced-precision pair phase (pair_lowp.hip); precision 1 = FP32, 2 = BF16 ----
+int lowp_chunk(int precision);   // k chunk: rows of low-precision operands are padded to it
+void launch_convert_v(int precision, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
+                      const double* V, void* Vlo, const int64_t* lo_off, hipStream_t s);
+int pair_lowp_blocks_per_cu(int precision);
+void launch_pair_lowp(int precision, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
+                      const double* dif, const void* Vlo, const int64_t* lo_off, const void* Mlo,
+                      const int64_t* mlo_off, double* G, void* scratch, int64_t slot_elems, int grid, double* ed2,
+                      int source, int couple, const Ctrl* ctrl, hipStream_t s);
 
 }  // namespace mcpt

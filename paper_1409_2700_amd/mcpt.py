@@ -52,7 +52,7 @@ class mcpt_options(C.Structure):
     _fields_ = [
         ("tol", C.c_double), ("max_sweeps", C.c_int32), ("precision", C.c_int32),
         ("polish", C.c_int32), ("deterministic", C.c_int32), ("check_every", C.c_int32),
-        ("reserved", C.c_int32), ("warm_t", C.c_void_p),
+        ("inner_sweeps", C.c_int32), ("warm_t", C.c_void_p),
     ]
 
 
@@ -72,6 +72,8 @@ class mcpt_timing(C.Structure):
     _fields_ = [
         ("pair_ms", C.c_double), ("mono_ms", C.c_double), ("pair_launches", C.c_int64),
         ("mono_launches", C.c_int64), ("pair_flops", C.c_double), ("pair_v_bytes", C.c_double),
+        ("lowp_ms", C.c_double), ("lowp_launches", C.c_int64), ("lowp_flops", C.c_double),
+        ("lowp_v_bytes", C.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -150,9 +152,9 @@ class HostProblem:
 
 
 def make_options(tol=1e-10, max_sweeps=200, precision=MCPT_FP64, polish=1, deterministic=0,
-                 check_every=1, warm_t: np.ndarray | None = None):
+                 check_every=1, inner_sweeps=0, warm_t: np.ndarray | None = None):
     o = mcpt_options(tol=tol, max_sweeps=max_sweeps, precision=precision, polish=polish,
-                     deterministic=deterministic, check_every=check_every, reserved=0,
+                     deterministic=deterministic, check_every=check_every, inner_sweeps=inner_sweeps,
                      warm_t=_ptr(warm_t))
     o._keep = warm_t
     return o
