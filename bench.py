@@ -82,10 +82,10 @@ MODES = {   # name: (precision, polish)
 }
 
 
-def time_mode(ctx, pid, name, steps, warmup, tol, check_every, golden):
+def time_mode(ctx, pid, name, steps, warmup, tol, check_every, golden, graph=0):
     import numpy as np
     prec, polish = MODES[name]
-    opts = dict(tol=tol, max_sweeps=200, check_every=check_every, precision=prec, polish=polish)
+    opts = dict(tol=tol, max_sweeps=200, check_every=check_every, precision=prec, polish=polish, graph=graph)
     for w in range(warmup):
         s = ctx.run(pid, **opts)
         log(f"[bench] {name} warmup {w}: {s['sweeps']} sweeps ({s['polish_sweeps']} FP64) "
@@ -94,6 +94,13 @@ def time_mode(ctx, pid, name, steps, warmup, tol, check_every, golden):
     t0 = time.perf_counter()
     runs = [ctx.run(pid, **opts) for _ in range(steps)]
     elapsed = time.perf_counter() - t0
+    if graph:   # replayed graphs carry no per-launch events: one eager solve gives the kernel times
+        ctx.set_timing(False)
+        ctx.set_timing(True)
+        ctx.run(pid, **dict(opts, graph=0))
+        steps_timed = 1
+    else:
+        steps_timed = steps
     tm = ctx.timing()
     ctx.set_timing(False)
     s = runs[-1]
@@ -103,9 +110,9 @@ def time_mode(ctx, pid, name, steps, warmup, tol, check_every, golden):
         "solves_per_s": steps / elapsed, "ms_per_solve": elapsed / steps * 1e3, "sweeps": s["sweeps"],
         "fp64_sweeps": s["sweeps"] if prec == 0 else s["polish_sweeps"], "e_total": s["e_total"],
         "fp64_pair_avg_ms": tm["pair_ms"] / max(tm["pair_launches"], 1),
-        "fp64_pair_launches_per_solve": tm["pair_launches"] / steps,
+        "fp64_pair_launches_per_solve": tm["pair_launches"] / steps_timed,
         "lowp_pair_avg_ms": tm["lowp_ms"] / max(tm["lowp_launches"], 1) if tm["lowp_launches"] else None,
-        "lowp_pair_launches_per_solve": tm["lowp_launches"] / steps,
+        "lowp_pair_launches_per_solve": tm["lowp_launches"] / steps_timed,
         "monomer_avg_ms": tm["mono_ms"] / max(tm["mono_launches"], 1),
         "timing": tm,
     }
@@ -133,6 +140,7 @@ def main():
     ap.add_argument("--modes", default=",".join(MODES), help="comma-separated forms to time")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--check-every", type=int, default=1)
+    ap.add_argument("--graph", type=int, default=0, help="1: replay HIP-graph captured sweeps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     args = ap.parse_args()
@@ -163,7 +171,8 @@ def main():
         modes.insert(0, args.headline)
     results = {}
     for name in modes:
-        results[name] = time_mode(ctx, pid, name, args.steps, args.warmup, args.tol, args.check_every, golden)
+        results[name] = time_mode(ctx, pid, name, args.steps, args.warmup, args.tol, args.check_every, golden,
+                                  args.graph)
     ctx.release(pid)
     ctx.close()
 

@@ -93,10 +93,14 @@ typedef struct {
     int32_t        precision;    /* mcpt_precision of the pair contractions */
     int32_t        polish;       /* reduced precision: 1 = FP64 defect-correction sweeps until the
                                     FP64 residual < tol; 0 = stop at the reduced-precision residual */
-    int32_t        deterministic;/* 1 = no floating-point atomics: bitwise repeatable results */
+    int32_t        deterministic;/* must be 0: G is accumulated with FP64 atomics, so results repeat
+                                    to rounding, not bitwise; 1 is rejected with MCPT_ERR_INVALID */
     int32_t        check_every;  /* sweeps issued between host checks of the device residual (>= 1) */
     int32_t        inner_sweeps; /* reduced precision + polish: correction sweeps per FP64 sweep (0 = default) */
     const double  *warm_t;       /* NULL, or host T (layout of t_amp in mcpt_energy) to start from */
+    int32_t        graph;        /* 1: capture the sweeps issued between host checks in a HIP graph and
+                                    replay it (plain sweeps; per-launch timing is not recorded then) */
+    int32_t        reserved;
 } mcpt_options;
 
 typedef struct {
@@ -157,6 +161,26 @@ mcpt_status mcpt_upload(mcpt_ctx *ctx, const mcpt_problem *prob, uint64_t *id);
  * last sweep), MCPT_ERR_DIVERGED (no results), MCPT_ERR_INVALID (options),
  * MCPT_ERR_UNKNOWN_ID, MCPT_ERR_DEVICE. */
 mcpt_status mcpt_run(mcpt_ctx *ctx, uint64_t id, const mcpt_options *opts, mcpt_summary *out);
+
+/* Batching form: upload n independent clusters (probs[0..n-1], e.g. clusters
+ * of different sizes and orbital counts) as one resident problem.  A run then
+ * sweeps all of them together - every pair phase is one persistent launch over
+ * the pairs of every live cluster - while each cluster keeps its own
+ * convergence test, so it stops at the same sweep as it would alone and its
+ * results equal its solo solve.  mcpt_energy returns the clusters' arrays
+ * concatenated in input order; mcpt_cluster_results gives per-cluster
+ * summaries.  Errors as mcpt_upload (the message names the cluster). */
+mcpt_status mcpt_upload_batch(mcpt_ctx *ctx, const mcpt_problem *probs, int32_t n, uint64_t *id);
+
+/* mcpt_upload_batch followed by mcpt_run; per_cluster[n] (may be NULL) receives
+ * each cluster's summary.  Returns the worst cluster status. */
+mcpt_status mcpt_solve_batch(mcpt_ctx *ctx, const mcpt_problem *probs, int32_t n, const mcpt_options *opts,
+                             uint64_t *id, mcpt_summary *per_cluster);
+
+/* Per-cluster summaries of the last run of a resident batch (n = its cluster
+ * count; a single upload is a batch of one).
+ * Errors: MCPT_ERR_UNKNOWN_ID, MCPT_ERR_INVALID (wrong n, never run). */
+mcpt_status mcpt_cluster_results(mcpt_ctx *ctx, uint64_t id, int32_t n, mcpt_summary *out);
 
 /* mcpt_upload followed by mcpt_run; the problem stays resident under *id. */
 mcpt_status mcpt_solve(mcpt_ctx *ctx, const mcpt_problem *prob, const mcpt_options *opts,

@@ -10,6 +10,7 @@
 #include <memory>
 #include <string>
 #include <unordered_set>
+#include <array>
 #include <vector>
 
 #include "../../include/mcpt.h"
@@ -55,6 +56,13 @@ struct Resident {
     double *d_G[2] = {nullptr, nullptr};
     double* d_V = nullptr;
     double *d_em2 = nullptr, *d_em2_0 = nullptr, *d_ed2 = nullptr, *d_res = nullptr;
+    // clusters of a batch: monomer and pair ranges (caller order), per-cluster state and history
+    int n_cl = 1;
+    std::vector<int64_t> cl_mono, cl_pair;
+    int64_t *d_cl_mono = nullptr, *d_cl_pair = nullptr;
+    ClState* d_cl = nullptr;
+    double* d_hist = nullptr;
+    std::vector<mcpt_summary> cl_last;
     std::vector<void*> allocations;
     size_t bytes = 0;
     bool has_result = false;
@@ -68,6 +76,10 @@ struct Resident {
     double lo_v_bytes = 0.0;      // bytes of the low-precision V and V^T
     std::vector<void*> lo_allocations;
     size_t lo_bytes = 0;
+    // captured sweep graph (plain sweeps): valid for one precision and batch size
+    hipGraphExec_t graph = nullptr;
+    int graph_prec = -1, graph_sweeps = 0, graph_parity = 0;
+    std::array<int64_t, 6> graph_key{};   // context buffers and grids baked into the captured launches
 };
 
 struct Timing {
@@ -126,7 +138,14 @@ void free_lowp(mcpt_ctx* c, Resident* r) {
     r->d_R = r->d_Dl = nullptr;
 }
 
+void drop_graph(Resident* r) {
+    if (r->graph) (void)hipGraphExecDestroy(r->graph);
+    r->graph = nullptr;
+    r->graph_prec = -1;
+}
+
 void free_resident(mcpt_ctx* c, Resident* r) {
+    drop_graph(r);
     free_lowp(c, r);
     for (void* p : r->allocations) (void)hipFree(p);
     r->allocations.clear();
@@ -284,54 +303,87 @@ mcpt_status check_energies(const std::vector<double>& eps, const mcpt_problem* p
     return MCPT_OK;
 }
 
-mcpt_status upload(mcpt_ctx* c, const mcpt_problem* pb, uint64_t* id_out) {
-    mcpt_status st = validate_problem(pb);
-    if (st != MCPT_OK) return st;
+// Upload one or more independent clusters as one resident problem: monomers
+// and pairs are concatenated cluster after cluster (pair indices shifted by the
+// cluster's first monomer), each monomer and pair carries its cluster id, and
+// every cluster keeps its own stopping state during a run.
+mcpt_status upload_batch(mcpt_ctx* c, const mcpt_problem* pbs, int n_cl, uint64_t* id_out) {
+    if (!pbs || n_cl < 1) return fail(MCPT_ERR_INVALID, "need at least one problem");
     if (!id_out) return fail(MCPT_ERR_INVALID, "id is NULL");
+    mcpt_status st;
+    for (int q = 0; q < n_cl; ++q) {
+        if ((st = validate_problem(&pbs[q])) != MCPT_OK) {
+            if (n_cl > 1) g_err = "cluster " + std::to_string(q) + ": " + g_err;
+            return st;
+        }
+    }
     if ((st = ensure_device(c)) != MCPT_OK) return st;
     auto r = std::make_unique<Resident>();
-    r->n_mono = pb->n_mono;
-    r->n_pair = pb->n_pair;
-    r->monos.resize(pb->n_mono);
-    int64_t eoff = 0, roff = 0, moff = 0, doff = 0;
-    for (int x = 0; x < pb->n_mono; ++x) {
-        MonoDesc& d = r->monos[x];
-        d.o = pb->n_occ[x];
-        d.v = pb->n_vir[x];
-        d.n = d.o * d.v;
-        d.np = round_up(d.n, kTile);
-        d.eps_off = eoff;
-        d.raw_off = roff;
-        d.mat_off = moff;
-        d.dif_off = doff;
-        doff += d.np;
-        eoff += d.o + d.v;
-        roff += (int64_t)d.n * d.n;
-        moff += (int64_t)d.np * d.np;
-        r->max_n = std::max(r->max_n, d.n);
-        r->max_np = std::max(r->max_np, d.np);
+    r->n_cl = n_cl;
+    r->cl_mono.assign(n_cl + 1, 0);
+    r->cl_pair.assign(n_cl + 1, 0);
+    for (int q = 0; q < n_cl; ++q) {
+        r->cl_mono[q + 1] = r->cl_mono[q] + pbs[q].n_mono;
+        r->cl_pair[q + 1] = r->cl_pair[q] + pbs[q].n_pair;
     }
+    if (r->cl_mono[n_cl] > INT32_MAX) return fail(MCPT_ERR_INVALID, "too many monomers");
+    r->n_mono = (int)r->cl_mono[n_cl];
+    r->n_pair = r->cl_pair[n_cl];
+    r->monos.resize(r->n_mono);
+    int64_t eoff = 0, roff = 0, moff = 0, doff = 0;
+    std::vector<int64_t> eps_cl(n_cl + 1, 0), raw_cl(n_cl + 1, 0), v_cl(n_cl + 1, 0);
+    for (int q = 0; q < n_cl; ++q) {
+        const mcpt_problem* pb = &pbs[q];
+        eps_cl[q] = eoff;
+        raw_cl[q] = roff;
+        for (int lx = 0; lx < pb->n_mono; ++lx) {
+            MonoDesc& d = r->monos[r->cl_mono[q] + lx];
+            d.o = pb->n_occ[lx];
+            d.v = pb->n_vir[lx];
+            d.n = d.o * d.v;
+            d.np = round_up(d.n, kTile);
+            d.eps_off = eoff;
+            d.raw_off = roff;
+            d.mat_off = moff;
+            d.dif_off = doff;
+            d.cluster = q;
+            d.pad = 0;
+            doff += d.np;
+            eoff += d.o + d.v;
+            roff += (int64_t)d.n * d.n;
+            moff += (int64_t)d.np * d.np;
+            r->max_n = std::max(r->max_n, d.n);
+            r->max_np = std::max(r->max_np, d.np);
+        }
+    }
+    eps_cl[n_cl] = eoff;
+    raw_cl[n_cl] = roff;
     r->eps_elems = eoff;
     r->dif_elems = doff;
     r->raw_elems = roff;
     r->mat_elems = moff;
     // pairs: caller order gives V offsets; processing order is sorted by (min, max) monomer
-    std::vector<int64_t> voff(pb->n_pair);
+    r->pairs.resize(r->n_pair);
     int64_t vo = 0;
-    for (int64_t p = 0; p < pb->n_pair; ++p) {
-        voff[p] = vo;
-        vo += (int64_t)r->monos[pb->pair[2 * p]].n * r->monos[pb->pair[2 * p + 1]].n;
+    for (int q = 0; q < n_cl; ++q) {
+        const mcpt_problem* pb = &pbs[q];
+        v_cl[q] = vo;
+        const int base = (int)r->cl_mono[q];
+        for (int64_t lp = 0; lp < pb->n_pair; ++lp) {
+            const int64_t p = r->cl_pair[q] + lp;
+            PairDesc& d = r->pairs[p];
+            d.x = base + pb->pair[2 * lp];
+            d.y = base + pb->pair[2 * lp + 1];
+            d.v_off = vo;
+            d.orig = p;
+            d.cluster = q;
+            d.pad = 0;
+            vo += (int64_t)r->monos[d.x].n * r->monos[d.y].n;
+            r->max_slot = std::max<int64_t>(r->max_slot, (int64_t)r->monos[d.x].np * r->monos[d.y].np);
+        }
     }
+    v_cl[n_cl] = vo;
     r->v_elems = vo;
-    r->pairs.resize(pb->n_pair);
-    for (int64_t p = 0; p < pb->n_pair; ++p) {
-        PairDesc& d = r->pairs[p];
-        d.x = pb->pair[2 * p];
-        d.y = pb->pair[2 * p + 1];
-        d.v_off = voff[p];
-        d.orig = p;
-        r->max_slot = std::max<int64_t>(r->max_slot, (int64_t)r->monos[d.x].np * r->monos[d.y].np);
-    }
     {
         const std::vector<MonoDesc>& m = r->monos;
         auto lds = [&m](const PairDesc& d) { return pair_fits_lds(m[d.x].n, m[d.y].np); };
@@ -346,24 +398,29 @@ mcpt_status upload(mcpt_ctx* c, const mcpt_problem* pb, uint64_t* id_out) {
     }
     // energies: validated on the host (small)
     std::vector<double> eps(eoff);
-    if (pb->memory == MCPT_HOST) {
-        std::memcpy(eps.data(), pb->eps, eoff * sizeof(double));
-    } else {
-        HIP_TRY(hipMemcpy(eps.data(), pb->eps, eoff * sizeof(double), hipMemcpyDeviceToHost));
+    for (int q = 0; q < n_cl; ++q) {
+        const size_t bytes = (eps_cl[q + 1] - eps_cl[q]) * sizeof(double);
+        if (pbs[q].memory == MCPT_HOST) std::memcpy(eps.data() + eps_cl[q], pbs[q].eps, bytes);
+        else HIP_TRY(hipMemcpy(eps.data() + eps_cl[q], pbs[q].eps, bytes, hipMemcpyDeviceToHost));
+        std::vector<double> one(eps.begin() + eps_cl[q], eps.begin() + eps_cl[q + 1]);
+        if ((st = check_energies(one, &pbs[q])) != MCPT_OK) {
+            if (n_cl > 1) g_err = "cluster " + std::to_string(q) + ": " + g_err;
+            return st;
+        }
     }
-    if ((st = check_energies(eps, pb)) != MCPT_OK) return st;
     // orbital-energy differences d[(i,a)] = e_i - e_a (Eqs. 60-61 as d_X + d_Y)
     std::vector<double> dif(doff, 0.0);
-    for (int x = 0; x < pb->n_mono; ++x) {
+    for (int x = 0; x < r->n_mono; ++x) {
         const MonoDesc& d = r->monos[x];
         const double* e = eps.data() + d.eps_off;
         for (int i = 0; i < d.o; ++i)
             for (int a = 0; a < d.v; ++a) dif[d.dif_off + i * d.v + a] = e[i] - e[d.o + a];
     }
     // footprint and admission
-    const size_t need = sizeof(double) * ((size_t)doff + r->raw_elems + 5 * (size_t)r->mat_elems +
-                                          r->v_elems + 3 * (size_t)pb->n_mono + pb->n_pair) +
-                        r->monos.size() * sizeof(MonoDesc) + r->pairs.size() * sizeof(PairDesc);
+    const size_t need = sizeof(double) * ((size_t)doff + r->raw_elems + 5 * (size_t)r->mat_elems + r->v_elems +
+                                          3 * (size_t)r->n_mono + r->n_pair + (size_t)n_cl * kMaxSweeps) +
+                        r->monos.size() * sizeof(MonoDesc) + r->pairs.size() * sizeof(PairDesc) +
+                        n_cl * (sizeof(ClState) + 16);
     if (c->in_use + need > c->budget)
         return fail(MCPT_ERR_ADMISSION, "problem needs " + std::to_string(need) + " bytes; budget " +
                                             std::to_string(c->budget) + ", in use " + std::to_string(c->in_use));
@@ -389,9 +446,12 @@ mcpt_status upload(mcpt_ctx* c, const mcpt_problem* pb, uint64_t* id_out) {
     ALLOC(R->d_em2_0, R->n_mono);
     ALLOC(R->d_res, R->n_mono);
     ALLOC(R->d_ed2, std::max<int64_t>(R->n_pair, 1));
+    ALLOC(R->d_cl, n_cl);
+    ALLOC(R->d_hist, (int64_t)n_cl * kMaxSweeps);
+    ALLOC(R->d_cl_mono, n_cl + 1);
+    ALLOC(R->d_cl_pair, n_cl + 1);
 #undef ALLOC
     hipStream_t s = c->stream;
-    const hipMemcpyKind kind = pb->memory == MCPT_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
 #define DTRY(expr)                   \
     do {                             \
         hipError_t e_ = (expr);      \
@@ -404,8 +464,16 @@ mcpt_status upload(mcpt_ctx* c, const mcpt_problem* pb, uint64_t* id_out) {
     if (R->n_pair)
         DTRY(hipMemcpyAsync(R->d_pairs, R->pairs.data(), R->pairs.size() * sizeof(PairDesc), hipMemcpyHostToDevice, s));
     DTRY(hipMemcpyAsync(R->d_dif, dif.data(), doff * sizeof(double), hipMemcpyHostToDevice, s));
-    DTRY(hipMemcpyAsync(R->d_raw, pb->k_intra, R->raw_elems * sizeof(double), kind, s));
-    if (R->v_elems) DTRY(hipMemcpyAsync(R->d_V, pb->v_dimer, R->v_elems * sizeof(double), kind, s));
+    DTRY(hipMemcpyAsync(R->d_cl_mono, R->cl_mono.data(), (n_cl + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    DTRY(hipMemcpyAsync(R->d_cl_pair, R->cl_pair.data(), (n_cl + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    for (int q = 0; q < n_cl; ++q) {
+        const hipMemcpyKind kind = pbs[q].memory == MCPT_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+        if (raw_cl[q + 1] > raw_cl[q])
+            DTRY(hipMemcpyAsync(R->d_raw + raw_cl[q], pbs[q].k_intra, (raw_cl[q + 1] - raw_cl[q]) * sizeof(double),
+                                kind, s));
+        if (v_cl[q + 1] > v_cl[q])
+            DTRY(hipMemcpyAsync(R->d_V + v_cl[q], pbs[q].v_dimer, (v_cl[q + 1] - v_cl[q]) * sizeof(double), kind, s));
+    }
     *c->h_flag = 0;
     DTRY(hipMemcpyAsync(c->d_flag, c->h_flag, sizeof(int32_t), hipMemcpyHostToDevice, s));
     launch_nonfinite(R->d_raw, R->raw_elems, c->d_flag, s);
@@ -424,6 +492,7 @@ mcpt_status upload(mcpt_ctx* c, const mcpt_problem* pb, uint64_t* id_out) {
         free_resident(c, R);
         return fail(MCPT_ERR_NONFINITE, "non-finite value in k_intra or v_dimer");
     }
+    r->cl_last.assign(n_cl, mcpt_summary{});
     r->id = c->next_id++;
     *id_out = r->id;
     c->res[r->id] = std::move(r);
@@ -439,6 +508,9 @@ mcpt_status validate_options(const mcpt_options* o) {
         return fail(MCPT_ERR_INVALID, "precision must be MCPT_FP64, MCPT_FP32 or MCPT_BF16");
     if (o->check_every < 0) return fail(MCPT_ERR_INVALID, "check_every must be >= 0");
     if (o->inner_sweeps < 0 || o->inner_sweeps > 64) return fail(MCPT_ERR_INVALID, "inner_sweeps must be in [0, 64]");
+    if (o->deterministic != 0)
+        return fail(MCPT_ERR_INVALID, "deterministic (atomic-free) accumulation is not available in this library");
+    if (o->graph != 0 && o->graph != 1) return fail(MCPT_ERR_INVALID, "graph must be 0 or 1");
     return MCPT_OK;
 }
 
@@ -458,10 +530,11 @@ void record_end(mcpt_ctx* c, hipEvent_t a, int kind, double flops, double vbytes
 // Pair phase over all pairs: the LDS-resident-V kernel for the pairs that fit,
 // then the L2 variant for the rest (same stream, so G accumulates in order).
 void pair_phase(mcpt_ctx* c, Resident* R, double* G, int couple, const Ctrl* ctrl) {
+    const ClState* cl = ctrl ? R->d_cl : nullptr;   // the final energy pass covers every cluster
     launch_pair_fp64(1, R->d_pairs, R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G, c->d_scratch,
-                     c->scratch_slot, c->grid_lds, R->d_ed2, couple, ctrl, c->stream);
+                     c->scratch_slot, c->grid_lds, R->d_ed2, couple, ctrl, cl, c->stream);
     launch_pair_fp64(0, R->d_pairs + R->n_lds, R->n_pair - R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G,
-                     c->d_scratch, c->scratch_slot, c->grid_glb, R->d_ed2, couple, ctrl, c->stream);
+                     c->d_scratch, c->scratch_slot, c->grid_glb, R->d_ed2, couple, ctrl, cl, c->stream);
 }
 
 // Reduced-precision copies of a resident problem for `prec` (1 FP32, 2 BF16):
@@ -469,6 +542,7 @@ void pair_phase(mcpt_ctx* c, Resident* R, double* G, int couple, const Ctrl* ctr
 // and FP64 buffers for the polish residual R and correction delta.
 mcpt_status ensure_lowp(mcpt_ctx* c, Resident* R, int prec) {
     if (R->lo_prec == prec) return MCPT_OK;
+    drop_graph(R);
     free_lowp(c, R);
     const int kc = lowp_chunk(prec);
     const size_t es = prec == MCPT_BF16 ? 2 : 4;
@@ -535,18 +609,18 @@ mcpt_status ensure_lowp(mcpt_ctx* c, Resident* R, int prec) {
 void lowp_phase(mcpt_ctx* c, Resident* R, double* G, int source) {
     launch_pair_lowp(R->lo_prec, R->d_pairs, R->n_pair, R->d_monos, R->d_dif, R->d_Vlo, R->d_lo_off, R->d_Mlo,
                      R->d_mlo_off, G, c->d_scratch_lo, R->lo_slot, c->grid_lo, R->d_ed2, source, 1, nullptr,
-                     c->stream);
+                     R->d_cl, c->stream);
 }
 
 void mixed_mono(mcpt_ctx* c, Resident* R, int mode, const double* G, double* Gz, bool lo_out, const Ctrl* ctrl) {
     launch_monomer_mixed(mode, R->lo_prec, R->d_monos, R->n_mono, R->d_dif, R->d_K, G, Gz, R->d_T, R->d_M, R->d_R,
                          R->d_Dl, lo_out ? R->d_Mlo : nullptr, R->d_mlo_off, R->d_em2, R->d_em2_0, R->d_res, ctrl,
-                         c->stream);
+                         R->d_cl, c->stream);
 }
 
 mcpt_status sync_ctrl(mcpt_ctx* c) {
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(c->h_ctrl, c->d_ctrl, offsetof(Ctrl, hist), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->h_ctrl, c->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return MCPT_OK;
 }
@@ -562,11 +636,16 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
     hipStream_t s = c->stream;
     R->has_result = false;
     Ctrl& h = *c->h_ctrl;
-    std::memset(&h, 0, offsetof(Ctrl, hist));
+    std::memset(&h, 0, sizeof(Ctrl));
     h.fixed = o->tol == 0.0;
     h.max_sweeps = o->max_sweeps;
     h.tol = o->tol;
-    HIP_TRY(hipMemcpyAsync(c->d_ctrl, &h, offsetof(Ctrl, hist), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c->d_ctrl, &h, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+    {
+        const std::vector<ClState> zero(R->n_cl, ClState{});
+        HIP_TRY(hipMemcpyAsync(R->d_cl, zero.data(), R->n_cl * sizeof(ClState), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     launch_fill(R->d_G[0], R->mat_elems, 0.0, s);
     launch_fill(R->d_G[1], R->mat_elems, 0.0, s);
     if (o->warm_t) {
@@ -574,12 +653,12 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
         launch_fill(R->d_T, R->mat_elems, 0.0, s);
         launch_pack(R->d_monos, R->n_mono, R->d_raw, R->d_T, R->max_n, s);
         launch_monomer(kMonoE0, R->d_monos, R->n_mono, R->d_dif, R->d_K, nullptr, nullptr, R->d_T, R->d_M,
-                       R->d_em2, R->d_em2_0, R->d_res, nullptr, R->max_np, s);
+                       R->d_em2, R->d_em2_0, R->d_res, nullptr, nullptr, s);
         launch_monomer(kMonoFromT, R->d_monos, R->n_mono, R->d_dif, R->d_K, nullptr, nullptr, R->d_T,
-                       R->d_M, R->d_em2, R->d_em2_0, R->d_res, nullptr, R->max_np, s);
+                       R->d_M, R->d_em2, R->d_em2_0, R->d_res, nullptr, nullptr, s);
     } else {
         launch_monomer(kMonoInit, R->d_monos, R->n_mono, R->d_dif, R->d_K, nullptr, nullptr, R->d_T, R->d_M,
-                       R->d_em2, R->d_em2_0, R->d_res, nullptr, R->max_np, s);
+                       R->d_em2, R->d_em2_0, R->d_res, nullptr, nullptr, s);
     }
     if (prec != MCPT_FP64) mixed_mono(c, R, kMonoFromT, nullptr, nullptr, true, nullptr);   // M in low precision
     HIP_TRY(hipGetLastError());
@@ -587,11 +666,59 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
     const double vb = (double)R->v_elems * sizeof(double);
     const int every = o->check_every > 0 ? o->check_every : 1;
     int cur = 0, n_lo = 0, n_hi = 0;
+    const bool timing_on = c->timing.on && !o->graph;
+    const int inner = o->inner_sweeps > 0 ? o->inner_sweeps : (prec == MCPT_BF16 ? 3 : 5);
+    const int n_pre = std::min(inner + 1, o->max_sweeps);
+    const bool saved_timing = c->timing.on;
+    c->timing.on = timing_on;
 
     if (prec == MCPT_FP64 || !o->polish) {
         // plain Jacobi sweeps: FP64, or reduced precision with the integral source terms
+        auto issue_sweep = [&](bool timed) {
+            if (prec == MCPT_FP64) pair_phase(c, R, R->d_G[cur], 1, c->d_ctrl);
+            else lowp_phase(c, R, R->d_G[cur], 1);
+            if (prec == MCPT_FP64)
+                launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->d_dif, R->d_K, R->d_G[cur], R->d_G[cur ^ 1],
+                               R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, c->d_ctrl, R->d_cl, s);
+            else
+                mixed_mono(c, R, kMonoUpdate, R->d_G[cur], R->d_G[cur ^ 1], true, c->d_ctrl);
+            launch_reduce_sweep(R->n_cl, R->d_cl_mono, R->d_res, R->d_cl, R->d_hist, c->d_ctrl, s);
+            cur ^= 1;
+            (void)timed;
+        };
         int issued = 0;
-        while (issued < o->max_sweeps) {
+        if (o->graph && o->max_sweeps > 0) {
+            // an even number of sweeps per graph keeps the G double-buffer parity of every replay
+            const int gk = (every % 2) ? 2 * every : every;
+            const std::array<int64_t, 6> key{(int64_t)(uintptr_t)c->d_scratch, (int64_t)(uintptr_t)c->d_scratch_lo,
+                                             (int64_t)(uintptr_t)c->d_ctrl, c->scratch_slot,
+                                             (int64_t)c->grid_lds * 1000000 + c->grid_glb, c->grid_lo};
+            if (!R->graph || R->graph_prec != prec || R->graph_sweeps != gk || R->graph_key != key) {
+                drop_graph(R);
+                hipGraph_t g = nullptr;
+                HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                for (int k = 0; k < gk; ++k) issue_sweep(false);
+                const hipError_t ec = hipStreamEndCapture(s, &g);
+                if (ec != hipSuccess) return fail(MCPT_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+                const hipError_t ei = hipGraphInstantiate(&R->graph, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (ei != hipSuccess) {
+                    R->graph = nullptr;
+                    return fail(MCPT_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+                }
+                R->graph_prec = prec;
+                R->graph_sweeps = gk;
+                R->graph_key = key;
+            }
+            cur = 0;
+            while (issued < o->max_sweeps) {
+                HIP_TRY(hipGraphLaunch(R->graph, s));
+                issued += gk;
+                if ((st = sync_ctrl(c)) != MCPT_OK) return st;
+                if (h.done) break;
+            }
+        }
+        while (!o->graph && issued < o->max_sweeps) {
             const int batch = std::min(every, o->max_sweeps - issued);
             for (int k = 0; k < batch; ++k) {
                 hipEvent_t a = nullptr;
@@ -607,11 +734,11 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
                 if (prec == MCPT_FP64)
                     launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->d_dif, R->d_K, R->d_G[cur],
                                    R->d_G[cur ^ 1], R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, c->d_ctrl,
-                                   R->max_np, s);
+                                   R->d_cl, s);
                 else
                     mixed_mono(c, R, kMonoUpdate, R->d_G[cur], R->d_G[cur ^ 1], true, c->d_ctrl);
                 record_end(c, a, 1, 0.0, 0.0);
-                launch_reduce_sweep(R->n_mono, R->d_res, c->d_ctrl, s);
+                launch_reduce_sweep(R->n_cl, R->d_cl_mono, R->d_res, R->d_cl, R->d_hist, c->d_ctrl, s);
                 cur ^= 1;
                 ++issued;
             }
@@ -623,42 +750,88 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
     } else {
         // FP64 defect correction: each FP64 sweep gives r = F(T) - T and the convergence test;
         // `inner` reduced-precision sweeps solve delta = r + L(delta); then T += delta.
-        const int inner = o->inner_sweeps > 0 ? o->inner_sweeps : (prec == MCPT_BF16 ? 3 : 5);
-        for (int k = 0; k < inner + 1 && k < o->max_sweeps; ++k) {   // a few plain reduced-precision sweeps first
+        auto fp64_sweep = [&]() {
+            hipEvent_t a = nullptr;
+            record_begin(c, &a);
+            pair_phase(c, R, R->d_G[cur], 1, c->d_ctrl);
+            record_end(c, a, 0, fl_sweep, vb);
+            mixed_mono(c, R, kMonoUpdateR, R->d_G[cur], R->d_G[cur ^ 1], false, c->d_ctrl);
+            launch_reduce_sweep(R->n_cl, R->d_cl_mono, R->d_res, R->d_cl, R->d_hist, c->d_ctrl, s);
+            cur ^= 1;
+        };
+        auto correction = [&]() {
+            mixed_mono(c, R, kMonoRlo, nullptr, nullptr, true, nullptr);
+            for (int k = 0; k < inner; ++k) {
+                hipEvent_t a = nullptr;
+                record_begin(c, &a);
+                lowp_phase(c, R, R->d_G[cur], 0);
+                record_end(c, a, 2, fl_sweep, R->lo_v_bytes);
+                mixed_mono(c, R, kMonoCorr, R->d_G[cur], R->d_G[cur ^ 1], true, nullptr);
+                cur ^= 1;
+            }
+            mixed_mono(c, R, kMonoApply, nullptr, nullptr, false, nullptr);
+            mixed_mono(c, R, kMonoFromT, nullptr, nullptr, false, nullptr);
+        };
+        for (int k = 0; k < n_pre; ++k) {   // a few plain reduced-precision sweeps first
             hipEvent_t a = nullptr;
             record_begin(c, &a);
             lowp_phase(c, R, R->d_G[cur], 1);
             record_end(c, a, 2, fl_sweep, R->lo_v_bytes);
             mixed_mono(c, R, kMonoUpdate, R->d_G[cur], R->d_G[cur ^ 1], true, nullptr);
             cur ^= 1;
-            ++n_lo;
         }
-        for (;;) {
-            hipEvent_t a = nullptr;
-            record_begin(c, &a);
-            pair_phase(c, R, R->d_G[cur], 1, c->d_ctrl);
-            record_end(c, a, 0, fl_sweep, vb);
-            mixed_mono(c, R, kMonoUpdateR, R->d_G[cur], R->d_G[cur ^ 1], false, c->d_ctrl);
-            launch_reduce_sweep(R->n_mono, R->d_res, c->d_ctrl, s);
-            cur ^= 1;
-            ++n_hi;
-            if ((st = sync_ctrl(c)) != MCPT_OK) return st;
-            if (h.done) break;
-            mixed_mono(c, R, kMonoRlo, nullptr, nullptr, true, nullptr);
-            for (int k = 0; k < inner; ++k) {
-                record_begin(c, &a);
-                lowp_phase(c, R, R->d_G[cur], 0);
-                record_end(c, a, 2, fl_sweep, R->lo_v_bytes);
-                mixed_mono(c, R, kMonoCorr, R->d_G[cur], R->d_G[cur ^ 1], true, nullptr);
-                cur ^= 1;
-                ++n_lo;
+        fp64_sweep();
+        if ((st = sync_ctrl(c)) != MCPT_OK) return st;
+        if (o->graph && !h.done) {
+            // one body = correction + FP64 sweep; bodies per graph chosen so that a replay
+            // returns the G double buffer to the parity it started from
+            int gb = every;
+            if ((gb * (inner + 1)) % 2) gb *= 2;
+            const std::array<int64_t, 6> key{(int64_t)(uintptr_t)c->d_scratch, (int64_t)(uintptr_t)c->d_scratch_lo,
+                                             (int64_t)(uintptr_t)c->d_ctrl, c->scratch_slot,
+                                             (int64_t)c->grid_lds * 1000000 + c->grid_glb,
+                                             (int64_t)c->grid_lo * 1000 + inner};
+            const int gprec = 16 + prec;
+            if (!R->graph || R->graph_prec != gprec || R->graph_sweeps != gb || R->graph_key != key ||
+                R->graph_parity != cur) {
+                drop_graph(R);
+                const int cur0 = cur;
+                hipGraph_t g = nullptr;
+                HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                for (int k = 0; k < gb; ++k) {
+                    correction();
+                    fp64_sweep();
+                }
+                const hipError_t ec = hipStreamEndCapture(s, &g);
+                if (ec != hipSuccess) return fail(MCPT_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+                const hipError_t ei = hipGraphInstantiate(&R->graph, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (ei != hipSuccess) {
+                    R->graph = nullptr;
+                    return fail(MCPT_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+                }
+                R->graph_prec = gprec;
+                R->graph_sweeps = gb;
+                R->graph_key = key;
+                R->graph_parity = cur0;
+                cur = cur0;
             }
-            mixed_mono(c, R, kMonoApply, nullptr, nullptr, false, nullptr);
-            mixed_mono(c, R, kMonoFromT, nullptr, nullptr, false, nullptr);
+            while (!h.done) {
+                HIP_TRY(hipGraphLaunch(R->graph, s));
+                if ((st = sync_ctrl(c)) != MCPT_OK) return st;
+            }
         }
+        while (!h.done) {
+            correction();
+            fp64_sweep();
+            if ((st = sync_ctrl(c)) != MCPT_OK) return st;
+        }
+        n_hi = h.sweeps;
+        n_lo = n_pre + inner * (n_hi - 1);
     }
-    if (h.status == MCPT_ERR_DIVERGED) {
+    if (h.status == MCPT_ERR_DIVERGED && R->n_cl == 1) {
         if (c->timing.on) drain_timing(c->timing);
+        c->timing.on = saved_timing;
         mcpt_summary sm{};
         sm.residual = h.residual;
         sm.sweeps = n_lo + n_hi;
@@ -676,9 +849,36 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
         pair_phase(c, R, R->d_G[cur], 0, nullptr);
         record_end(c, a, 0, fl_final, vb);
     }
-    launch_reduce_final(R->n_mono, R->n_pair, R->d_em2, R->d_em2_0, R->d_ed2, c->d_ctrl, s);
+    launch_reduce_final(R->n_cl, R->d_cl_mono, R->d_cl_pair, R->d_em2, R->d_em2_0, R->d_ed2, R->d_cl, c->d_ctrl, s);
     if ((st = sync_ctrl(c)) != MCPT_OK) return st;
     if (c->timing.on) drain_timing(c->timing);
+    c->timing.on = saved_timing;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    {
+        std::vector<ClState> cs(R->n_cl);
+        HIP_TRY(hipMemcpy(cs.data(), R->d_cl, R->n_cl * sizeof(ClState), hipMemcpyDeviceToHost));
+        for (int q = 0; q < R->n_cl; ++q) {
+            mcpt_summary& cq = R->cl_last[q];
+            cq = mcpt_summary{};
+            cq.e_mono = cs[q].e_mono;
+            cq.e_dimer = cs[q].e_dimer;
+            cq.e_total = cs[q].e_mono + cs[q].e_dimer;
+            cq.e_mono0 = cs[q].e_mono0;
+            cq.residual = cs[q].residual;
+            cq.sweeps = cs[q].sweeps;
+            cq.seconds = secs;
+            if (h.fixed) cq.status = cs[q].status == MCPT_ERR_DIVERGED ? MCPT_ERR_DIVERGED : MCPT_OK;
+            else if (cs[q].status == MCPT_ERR_DIVERGED) cq.status = MCPT_ERR_DIVERGED;
+            else if (cs[q].sweeps > 0 && cs[q].residual < o->tol) cq.status = MCPT_OK;
+            else cq.status = MCPT_ERR_NOT_CONVERGED;
+            if (prec != MCPT_FP64 && o->polish) {   // reduced-precision sweeps are shared by the batch
+                cq.polish_sweeps = cs[q].sweeps;
+                cq.sweeps = n_pre + inner * std::max(cs[q].sweeps - 1, 0) + cs[q].sweeps;
+            } else if (prec != MCPT_FP64) {
+                cq.sweeps = cs[q].sweeps;
+            }
+        }
+    }
     mcpt_summary sm{};
     sm.e_mono = h.e_mono;
     sm.e_dimer = h.e_dimer;
@@ -687,10 +887,11 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
     sm.residual = h.residual;
     sm.sweeps = n_lo + n_hi;
     sm.polish_sweeps = (prec != MCPT_FP64 && o->polish) ? n_hi : 0;
-    if (h.fixed) sm.status = MCPT_OK;
-    else if (h.sweeps > 0 && h.residual < o->tol) sm.status = MCPT_OK;
-    else sm.status = MCPT_ERR_NOT_CONVERGED;
-    sm.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    sm.status = MCPT_OK;
+    for (int q = 0; q < R->n_cl; ++q)
+        if (R->cl_last[q].status == MCPT_ERR_DIVERGED || (R->cl_last[q].status != MCPT_OK && sm.status == MCPT_OK))
+            sm.status = R->cl_last[q].status;
+    sm.seconds = secs;
     R->has_result = true;
     R->last = sm;
     if (out) *out = sm;
@@ -760,10 +961,43 @@ mcpt_status mcpt_set_stream(mcpt_ctx* c, void* hip_stream) {
 mcpt_status mcpt_upload(mcpt_ctx* c, const mcpt_problem* prob, uint64_t* id) {
     if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
     try {
-        return upload(c, prob, id);
+        return upload_batch(c, prob, 1, id);
     } catch (const std::exception& e) {
         return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
     }
+}
+
+mcpt_status mcpt_upload_batch(mcpt_ctx* c, const mcpt_problem* probs, int32_t n, uint64_t* id) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    try {
+        return upload_batch(c, probs, n, id);
+    } catch (const std::exception& e) {
+        return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
+    }
+}
+
+mcpt_status mcpt_cluster_results(mcpt_ctx* c, uint64_t id, int32_t n, mcpt_summary* out) {
+    if (!c || !out) return fail(MCPT_ERR_INVALID, "ctx or out is NULL");
+    auto it = c->res.find(id);
+    if (it == c->res.end()) return fail(MCPT_ERR_UNKNOWN_ID, "unknown problem id " + std::to_string(id));
+    Resident* R = it->second.get();
+    if (n != R->n_cl) return fail(MCPT_ERR_INVALID, "problem holds " + std::to_string(R->n_cl) + " clusters");
+    if (!R->has_result) return fail(MCPT_ERR_INVALID, "problem has no result (not run, or diverged)");
+    for (int q = 0; q < n; ++q) out[q] = R->cl_last[q];
+    return MCPT_OK;
+}
+
+mcpt_status mcpt_solve_batch(mcpt_ctx* c, const mcpt_problem* probs, int32_t n, const mcpt_options* opts,
+                             uint64_t* id, mcpt_summary* per_cluster) {
+    mcpt_status st = validate_options(opts);
+    if (st != MCPT_OK) return st;
+    uint64_t local = 0;
+    st = mcpt_upload_batch(c, probs, n, &local);
+    if (st != MCPT_OK) return st;
+    if (id) *id = local;
+    st = mcpt_run(c, local, opts, nullptr);
+    if (per_cluster && c->res[local]->has_result) mcpt_cluster_results(c, local, n, per_cluster);
+    return st;
 }
 
 mcpt_status mcpt_run(mcpt_ctx* c, uint64_t id, const mcpt_options* opts, mcpt_summary* out) {

@@ -96,11 +96,13 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
     const double* __restrict__ K, const double* __restrict__ G, double* __restrict__ Gz,
     double* __restrict__ T, double* __restrict__ M, double* __restrict__ R, double* __restrict__ Dl,
     E* __restrict__ Mlo, const int64_t* __restrict__ mlo_off, int lo_chunk, double* __restrict__ em2,
-    double* __restrict__ em2_0, double* __restrict__ res, const Ctrl* __restrict__ ctrl) {
+    double* __restrict__ em2_0, double* __restrict__ res, const Ctrl* __restrict__ ctrl,
+    const ClState* __restrict__ cl) {
     if (ctrl && ctrl->done) return;
     __shared__ double sh[kMonoThreads];
     const int x = blockIdx.x;
     const MonoDesc d = monos[x];
+    if (cl && cl[d.cluster].done) return;   // this monomer's cluster has stopped
     const int v = d.v, n = d.n, np = d.np;
     const double* dx = dif + d.dif_off;
     const double* Kx = K + d.mat_off;
@@ -189,22 +191,25 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
     }
 }
 
-// Stopping rule, same as the oracle's: converged when r < tol; diverged when
-// r is not finite, r > 1e6 r_1, or r rose in each of the last three sweeps and
-// exceeds r_1; not converged when max_sweeps sweeps ran.
+// Stopping rule, same as the oracle's, per cluster: converged when r < tol;
+// diverged when r is not finite, r > 1e6 r_1, or r rose in each of the last
+// three sweeps and exceeds r_1; not converged when max_sweeps sweeps ran.
+// Convergence test of one sweep, one workgroup per cluster: max|dT| over the
+// cluster's monomers, its residual history and the stopping rules (tolerance,
+// divergence, sweep limit).  Clusters that have stopped are left untouched.
 __global__ __launch_bounds__(kReduceThreads) void reduce_sweep_kernel(
-    int n_mono, const double* __restrict__ res, Ctrl* __restrict__ ctrl) {
-    if (ctrl->done) return;
+    const int64_t* __restrict__ cl_mono, const double* __restrict__ res, ClState* __restrict__ cl,
+    double* __restrict__ hist_all, const Ctrl* __restrict__ ctrl) {
+    const int q = blockIdx.x;
+    if (ctrl->done || cl[q].done) return;
     __shared__ double sh[kReduceThreads];
     double m = 0.0;
-    for (int i = threadIdx.x; i < n_mono; i += kReduceThreads) m = max_nan(m, res[i]);
+    for (int64_t i = cl_mono[q] + threadIdx.x; i < cl_mono[q + 1]; i += kReduceThreads) m = max_nan(m, res[i]);
     const double r = block_max<kReduceThreads>(m, sh);
     if (threadIdx.x != 0) return;
-    const int s = ctrl->sweeps;
-    ctrl->hist[s] = r;
-    ctrl->sweeps = s + 1;
-    ctrl->residual = r;
-    const double* h = ctrl->hist;
+    double* h = hist_all + (int64_t)q * kMaxSweeps;
+    const int s = cl[q].sweeps;
+    h[s] = r;
     int status = 0, done = 0;
     if (!(r <= DBL_MAX)) {
         status = -5;
@@ -223,28 +228,71 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_sweep_kernel(
     } else if (s + 1 >= ctrl->max_sweeps) {
         done = 1;
     }
-    ctrl->status = status;
-    ctrl->done = done;
+    cl[q].sweeps = s + 1;
+    cl[q].residual = r;
+    cl[q].status = status;
+    cl[q].done = done;
 }
 
+// Batch-wide view of the per-cluster states: done when every cluster is, the
+// worst status (diverged before not converged), the largest sweep count and residual.
+__global__ __launch_bounds__(kReduceThreads) void reduce_ctrl_kernel(int n_cl, const ClState* __restrict__ cl,
+                                                                     Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ double sh[kReduceThreads];
+    double notdone = 0.0, nstat = 0.0, sw = 0.0, rmax = 0.0;
+    for (int q = threadIdx.x; q < n_cl; q += kReduceThreads) {
+        notdone = fmax(notdone, cl[q].done ? 0.0 : 1.0);
+        nstat = fmax(nstat, (double)-cl[q].status);
+        sw = fmax(sw, (double)cl[q].sweeps);
+        rmax = max_nan(rmax, cl[q].residual);
+    }
+    notdone = block_max<kReduceThreads>(notdone, sh);
+    nstat = block_max<kReduceThreads>(nstat, sh);
+    sw = block_max<kReduceThreads>(sw, sh);
+    rmax = block_max<kReduceThreads>(rmax, sh);
+    if (threadIdx.x == 0) {
+        ctrl->sweeps = (int)sw;
+        ctrl->residual = rmax;
+        ctrl->status = -(int)nstat;
+        ctrl->done = notdone == 0.0;
+    }
+}
+
+// Per-cluster energy sums (Eqs. 54-56), one workgroup per cluster.
 __global__ __launch_bounds__(kReduceThreads) void reduce_final_kernel(
-    int n_mono, int64_t n_pair, const double* __restrict__ em2, const double* __restrict__ em2_0,
-    const double* __restrict__ ed2, Ctrl* __restrict__ ctrl) {
+    const int64_t* __restrict__ cl_mono, const int64_t* __restrict__ cl_pair, const double* __restrict__ em2,
+    const double* __restrict__ em2_0, const double* __restrict__ ed2, ClState* __restrict__ cl) {
+    const int q = blockIdx.x;
     __shared__ double sh[kReduceThreads];
     double a = 0.0, b = 0.0, c = 0.0;
-    for (int i = threadIdx.x; i < n_mono; i += kReduceThreads) {
+    for (int64_t i = cl_mono[q] + threadIdx.x; i < cl_mono[q + 1]; i += kReduceThreads) {
         a += em2[i];
         c += em2_0[i];
     }
-    for (int64_t i = threadIdx.x; i < n_pair; i += kReduceThreads) b += ed2[i];
+    for (int64_t i = cl_pair[q] + threadIdx.x; i < cl_pair[q + 1]; i += kReduceThreads) b += ed2[i];
     a = block_sum<kReduceThreads>(a, sh);
     b = block_sum<kReduceThreads>(b, sh);
     c = block_sum<kReduceThreads>(c, sh);
     if (threadIdx.x == 0) {
-        ctrl->e_mono = a;
-        ctrl->e_dimer = b;
-        ctrl->e_mono0 = c;
+        cl[q].e_mono = a;
+        cl[q].e_dimer = b;
+        cl[q].e_mono0 = c;
     }
+}
+
+// Batch totals of the per-cluster energies, summed in cluster order.
+__global__ void reduce_total_kernel(int n_cl, const ClState* __restrict__ cl, Ctrl* __restrict__ ctrl) {
+    if (threadIdx.x != 0) return;
+    double ta = 0.0, tb = 0.0, tc = 0.0;
+    for (int q = 0; q < n_cl; ++q) {
+        ta += cl[q].e_mono;
+        tb += cl[q].e_dimer;
+        tc += cl[q].e_mono0;
+    }
+    ctrl->e_mono = ta;
+    ctrl->e_dimer = tb;
+    ctrl->e_mono0 = tc;
 }
 
 int grid_for(int64_t n, int threads) {
@@ -281,32 +329,35 @@ void launch_nonfinite(const double* p, int64_t n, int32_t* flag, hipStream_t s) 
 
 void launch_monomer(int mode, const MonoDesc* monos, int n_mono, const double* dif, const double* K,
                     const double* G, double* G_zero, double* T, double* M, double* em2,
-                    double* em2_0, double* res, const Ctrl* ctrl, int /*max_np*/, hipStream_t s) {
+                    double* em2_0, double* res, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
     hipLaunchKernelGGL(monomer_kernel<float>, dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif, K, G,
                        G_zero, T, M, (double*)nullptr, (double*)nullptr, (float*)nullptr, (const int64_t*)nullptr,
-                       16, em2, em2_0, res, ctrl);
+                       16, em2, em2_0, res, ctrl, cl);
 }
 
 void launch_monomer_mixed(int mode, int precision, const MonoDesc* monos, int n_mono, const double* dif,
                           const double* K, const double* G, double* G_zero, double* T, double* M, double* R,
                           double* Dl, void* Mlo, const int64_t* mlo_off, double* em2, double* em2_0,
-                          double* res, const Ctrl* ctrl, hipStream_t s) {
+                          double* res, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
     if (precision == 2)
         hipLaunchKernelGGL(monomer_kernel<__bf16>, dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif, K, G,
-                           G_zero, T, M, R, Dl, static_cast<__bf16*>(Mlo), mlo_off, 32, em2, em2_0, res, ctrl);
+                           G_zero, T, M, R, Dl, static_cast<__bf16*>(Mlo), mlo_off, 32, em2, em2_0, res, ctrl, cl);
     else
         hipLaunchKernelGGL(monomer_kernel<float>, dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif, K, G,
-                           G_zero, T, M, R, Dl, static_cast<float*>(Mlo), mlo_off, 16, em2, em2_0, res, ctrl);
+                           G_zero, T, M, R, Dl, static_cast<float*>(Mlo), mlo_off, 16, em2, em2_0, res, ctrl, cl);
 }
 
-void launch_reduce_sweep(int n_mono, const double* res, Ctrl* ctrl, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_sweep_kernel, dim3(1), dim3(kReduceThreads), 0, s, n_mono, res, ctrl);
+void launch_reduce_sweep(int n_cl, const int64_t* cl_mono, const double* res, ClState* cl, double* hist,
+                         Ctrl* ctrl, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_sweep_kernel, dim3(n_cl), dim3(kReduceThreads), 0, s, cl_mono, res, cl, hist, ctrl);
+    hipLaunchKernelGGL(reduce_ctrl_kernel, dim3(1), dim3(kReduceThreads), 0, s, n_cl, cl, ctrl);
 }
 
-void launch_reduce_final(int n_mono, int64_t n_pair, const double* em2, const double* em2_0,
-                         const double* ed2, Ctrl* ctrl, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(kReduceThreads), 0, s, n_mono, n_pair, em2,
-                       em2_0, ed2, ctrl);
+void launch_reduce_final(int n_cl, const int64_t* cl_mono, const int64_t* cl_pair, const double* em2,
+                         const double* em2_0, const double* ed2, ClState* cl, Ctrl* ctrl, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(n_cl), dim3(kReduceThreads), 0, s, cl_mono, cl_pair, em2, em2_0,
+                       ed2, cl);
+    hipLaunchKernelGGL(reduce_total_kernel, dim3(1), dim3(64), 0, s, n_cl, cl, ctrl);
 }
 
 }  // namespace mcpt

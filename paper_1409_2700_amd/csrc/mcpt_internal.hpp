@@ -26,29 +26,45 @@ struct MonoDesc {
     int64_t mat_off;                   // first element of X's np x np matrices
     int64_t raw_off;                   // first element of X's o*o*v*v block in caller layout
     int64_t dif_off;                   // first element of X's np orbital-energy differences
+    int32_t cluster;                   // cluster (request) the monomer belongs to
+    int32_t pad;
 };
 
 struct PairDesc {
     int32_t x, y;                      // x is the row side (i,a) of V, y the column side (j,b)
     int64_t v_off;                     // first element of V_XY
     int64_t orig;                      // index of the pair in the caller's list
+    int32_t cluster;
+    int32_t pad;
+};
+
+// Per-cluster iteration state: a batch holds several independent clusters,
+// each stopping on its own residual exactly as it would alone.
+struct ClState {
+    int32_t done;                      // 1: converged / diverged / out of sweeps; its work is skipped
+    int32_t status;                    // 0, -4 (not converged) or -5 (diverged)
+    int32_t sweeps;
+    int32_t pad;
+    double residual;
+    double e_mono, e_dimer, e_mono0;
 };
 
 // Device-side iteration state.  The reduction kernel of every sweep appends
-// the residual, applies the stopping rules and sets `done`; sweep kernels
-// launched after that return at once, so a batch of sweeps issued ahead of a
-// host check ends exactly at the sweep that met the rule.
+// each live cluster's residual to its history, applies the stopping rules and
+// sets the cluster's `done`; `done` here is set when every cluster is done.
+// Sweep kernels launched after that return at once (or skip the done
+// clusters), so sweeps issued ahead of a host check end exactly at the sweep
+// that met the rule.
 struct Ctrl {
     int32_t done;
-    int32_t status;                    // 0, or mcpt_status of a finished iteration
-    int32_t sweeps;                    // sweeps completed
+    int32_t status;                    // worst cluster status
+    int32_t sweeps;                    // most sweeps of any cluster
     int32_t fixed;                     // 1: run exactly max_sweeps, no convergence test
     int32_t max_sweeps;
     int32_t pad;
     double tol;
-    double residual;                   // residual of the last sweep
+    double residual;                   // largest last residual over clusters
     double e_mono, e_dimer, e_mono0;   // sums written by the final reduction
-    double hist[kMaxSweeps];
 };
 
 enum MonoMode : int {
@@ -71,15 +87,16 @@ void launch_unpack(const MonoDesc* monos, int n_mono, const double* packed, doub
 void launch_nonfinite(const double* p, int64_t n, int32_t* flag, hipStream_t s);
 void launch_monomer(int mode, const MonoDesc* monos, int n_mono, const double* dif,
                     const double* K, const double* G, double* G_zero, double* T, double* M,
-                    double* em2, double* em2_0, double* res, const Ctrl* ctrl, int max_np,
+                    double* em2, double* em2_0, double* res, const Ctrl* ctrl, const ClState* cl,
                     hipStream_t s);
 void launch_monomer_mixed(int mode, int precision, const MonoDesc* monos, int n_mono, const double* dif,
                           const double* K, const double* G, double* G_zero, double* T, double* M, double* R,
                           double* Dl, void* Mlo, const int64_t* mlo_off, double* em2, double* em2_0,
-                          double* res, const Ctrl* ctrl, hipStream_t s);
-void launch_reduce_sweep(int n_mono, const double* res, Ctrl* ctrl, hipStream_t s);
-void launch_reduce_final(int n_mono, int64_t n_pair, const double* em2, const double* em2_0,
-                         const double* ed2, Ctrl* ctrl, hipStream_t s);
+                          double* res, const Ctrl* ctrl, const ClState* cl, hipStream_t s);
+void launch_reduce_sweep(int n_cl, const int64_t* cl_mono, const double* res, ClState* cl, double* hist,
+                         Ctrl* ctrl, hipStream_t s);
+void launch_reduce_final(int n_cl, const int64_t* cl_mono, const int64_t* cl_pair, const double* em2,
+                         const double* em2_0, const double* ed2, ClState* cl, Ctrl* ctrl, hipStream_t s);
 
 // ---- FP64 MFMA pair phase (pair_fp64.hip) ----
 // Eq. 59 (Tau from V, M_X, M_Y) and, if couple != 0, the Eq. 58 contractions
@@ -89,7 +106,7 @@ void launch_reduce_final(int n_mono, int64_t n_pair, const double* em2, const do
 void launch_pair_fp64(int lds_variant, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
                       const double* dif, const double* V, const double* M, double* G,
                       double* scratch, int64_t slot_elems, int grid, double* ed2, int couple,
-                      const Ctrl* ctrl, hipStream_t s);
+                      const Ctrl* ctrl, const ClState* cl, hipStream_t s);
 int pair_fp64_blocks_per_cu(int lds_variant);
 bool pair_fits_lds(int nX, int npY);
 
@@ -101,6 +118,6 @@ int pair_lowp_blocks_per_cu(int precision);
 void launch_pair_lowp(int precision, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
                       const double* dif, const void* Vlo, const int64_t* lo_off, const void* Mlo,
                       const int64_t* mlo_off, double* G, void* scratch, int64_t slot_elems, int grid, double* ed2,
-                      int source, int couple, const Ctrl* ctrl, hipStream_t s);
+                      int source, int couple, const Ctrl* ctrl, const ClState* cl, hipStream_t s);
 
 }  // namespace mcpt

@@ -414,7 +414,8 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
                                  const MonoDesc* __restrict__ monos, const double* __restrict__ dif,
                                  const double* __restrict__ V, const double* __restrict__ M,
                                  double* __restrict__ G, double* __restrict__ scratch, int64_t slot_elems,
-                                 double* __restrict__ ed2, int couple, double* sV, double* red) {
+                                 double* __restrict__ ed2, int couple, const ClState* __restrict__ cl,
+                                 double* sV, double* red) {
     constexpr int NW = NT / 64;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double* tau = scratch + (int64_t)blockIdx.x * slot_elems;
@@ -423,6 +424,7 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
         const int64_t pi = pair_for(it, n_pair);
         if (pi >= n_pair) break;
         const PairDesc pd = pairs[pi];
+        if (cl && cl[pd.cluster].done) continue;   // cluster stopped: uniform over the workgroup
         const PairView p = make_view(pd, monos, dif, V, M, G);
         const int RB = p.npX / 16, CB = p.npY / 16;
 
@@ -520,22 +522,24 @@ __global__ __launch_bounds__(kThreadsL) void pair_fp64_lds_kernel(
     const PairDesc* __restrict__ pairs, int64_t n_pair, const MonoDesc* __restrict__ monos,
     const double* __restrict__ dif, const double* __restrict__ V, const double* __restrict__ M,
     double* __restrict__ G, double* __restrict__ scratch, int64_t slot_elems,
-    double* __restrict__ ed2, int couple, const Ctrl* __restrict__ ctrl) {
+    double* __restrict__ ed2, int couple, const Ctrl* __restrict__ ctrl,
+    const ClState* __restrict__ cl) {
     if (ctrl && ctrl->done) return;
     __shared__ __align__(16) double sV[kLdsV];
     __shared__ double red[kThreadsL / 64];
-    pair_body<true, kThreadsL>(pairs, n_pair, monos, dif, V, M, G, scratch, slot_elems, ed2, couple, sV, red);
+    pair_body<true, kThreadsL>(pairs, n_pair, monos, dif, V, M, G, scratch, slot_elems, ed2, couple, cl, sV, red);
 }
 
 __global__ __launch_bounds__(kThreadsG, 2) void pair_fp64_glb_kernel(
     const PairDesc* __restrict__ pairs, int64_t n_pair, const MonoDesc* __restrict__ monos,
     const double* __restrict__ dif, const double* __restrict__ V, const double* __restrict__ M,
     double* __restrict__ G, double* __restrict__ scratch, int64_t slot_elems,
-    double* __restrict__ ed2, int couple, const Ctrl* __restrict__ ctrl) {
+    double* __restrict__ ed2, int couple, const Ctrl* __restrict__ ctrl,
+    const ClState* __restrict__ cl) {
     if (ctrl && ctrl->done) return;
     __shared__ double red[kThreadsG / 64];
-    pair_body<false, kThreadsG>(pairs, n_pair, monos, dif, V, M, G, scratch, slot_elems, ed2, couple, nullptr,
-                                red);
+    pair_body<false, kThreadsG>(pairs, n_pair, monos, dif, V, M, G, scratch, slot_elems, ed2, couple, cl,
+                                nullptr, red);
 }
 
 }  // namespace
@@ -553,14 +557,15 @@ bool pair_fits_lds(int nX, int npY) { return (int64_t)nX * (npY + 2) <= kLdsV; }
 
 void launch_pair_fp64(int lds_variant, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
                       const double* dif, const double* V, const double* M, double* G, double* scratch,
-                      int64_t slot_elems, int grid, double* ed2, int couple, const Ctrl* ctrl, hipStream_t s) {
+                      int64_t slot_elems, int grid, double* ed2, int couple, const Ctrl* ctrl, const ClState* cl,
+                      hipStream_t s) {
     if (n_pair <= 0) return;
     if (lds_variant)
         hipLaunchKernelGGL(pair_fp64_lds_kernel, dim3(grid), dim3(kThreadsL), 0, s, pairs, n_pair, monos, dif, V,
-                           M, G, scratch, slot_elems, ed2, couple, ctrl);
+                           M, G, scratch, slot_elems, ed2, couple, ctrl, cl);
     else
         hipLaunchKernelGGL(pair_fp64_glb_kernel, dim3(grid), dim3(kThreadsG), 0, s, pairs, n_pair, monos, dif, V,
-                           M, G, scratch, slot_elems, ed2, couple, ctrl);
+                           M, G, scratch, slot_elems, ed2, couple, ctrl, cl);
 }
 
 }  // namespace mcpt

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(kThreads) void pair_lowp_kernel(
     const double* __restrict__ dif, const E* __restrict__ Vlo, const int64_t* __restrict__ lo_off,
     const E* __restrict__ Mlo, const int64_t* __restrict__ mlo_off, double* __restrict__ G,
     E* __restrict__ scratch, int64_t slot_elems, double* __restrict__ ed2, int source, int couple,
-    const Ctrl* __restrict__ ctrl) {
+    const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
     typedef Lowp<E> L;
     if (ctrl && ctrl->done) return;
     __shared__ double red[kWaves];
@@ -234,6 +234,7 @@ __global__ __launch_bounds__(kThreads) void pair_lowp_kernel(
         const int64_t pi = pair_for(it, n_pair);
         if (pi >= n_pair) break;
         const PairDesc pd = pairs[pi];
+        if (cl && cl[pd.cluster].done) continue;   // cluster stopped: uniform over the workgroup
         const MonoDesc dx = monos[pd.x], dy = monos[pd.y];
         const int nX = dx.n, nY = dy.n, npX = dx.np, npY = dy.np;
         const int ldX = (nX + L::KC - 1) / L::KC * L::KC, ldY = (nY + L::KC - 1) / L::KC * L::KC;
@@ -348,16 +349,16 @@ int pair_lowp_blocks_per_cu(int precision) {
 void launch_pair_lowp(int precision, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
                       const double* dif, const void* Vlo, const int64_t* lo_off, const void* Mlo,
                       const int64_t* mlo_off, double* G, void* scratch, int64_t slot_elems, int grid, double* ed2,
-                      int source, int couple, const Ctrl* ctrl, hipStream_t s) {
+                      int source, int couple, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
     if (n_pair <= 0) return;
     if (precision == 2)
         hipLaunchKernelGGL(pair_lowp_kernel<__bf16>, dim3(grid), dim3(kThreads), 0, s, pairs, n_pair, monos, dif,
                            static_cast<const __bf16*>(Vlo), lo_off, static_cast<const __bf16*>(Mlo), mlo_off, G,
-                           static_cast<__bf16*>(scratch), slot_elems, ed2, source, couple, ctrl);
+                           static_cast<__bf16*>(scratch), slot_elems, ed2, source, couple, ctrl, cl);
     else
         hipLaunchKernelGGL(pair_lowp_kernel<float>, dim3(grid), dim3(kThreads), 0, s, pairs, n_pair, monos, dif,
                            static_cast<const float*>(Vlo), lo_off, static_cast<const float*>(Mlo), mlo_off, G,
-                           static_cast<float*>(scratch), slot_elems, ed2, source, couple, ctrl);
+                           static_cast<float*>(scratch), slot_elems, ed2, source, couple, ctrl, cl);
 }
 
 }  // namespace mcpt

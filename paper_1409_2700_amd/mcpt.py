@@ -37,6 +37,7 @@ STATUS_NAMES = {
 EXPORTS = [
     "mcpt_create", "mcpt_destroy", "mcpt_last_error", "mcpt_set_stream", "mcpt_upload", "mcpt_run",
     "mcpt_solve", "mcpt_energy", "mcpt_release", "mcpt_set_timing", "mcpt_timing_read",
+    "mcpt_upload_batch", "mcpt_solve_batch", "mcpt_cluster_results",
 ]
 
 
@@ -52,7 +53,7 @@ class mcpt_options(C.Structure):
     _fields_ = [
         ("tol", C.c_double), ("max_sweeps", C.c_int32), ("precision", C.c_int32),
         ("polish", C.c_int32), ("deterministic", C.c_int32), ("check_every", C.c_int32),
-        ("inner_sweeps", C.c_int32), ("warm_t", C.c_void_p),
+        ("inner_sweeps", C.c_int32), ("warm_t", C.c_void_p), ("graph", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -98,6 +99,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.mcpt_release.argtypes = [P, C.c_uint64]
     lib.mcpt_set_timing.argtypes = [P, C.c_int]
     lib.mcpt_timing_read.argtypes = [P, C.POINTER(mcpt_timing)]
+    lib.mcpt_upload_batch.argtypes = [P, C.POINTER(mcpt_problem), C.c_int32, C.POINTER(C.c_uint64)]
+    lib.mcpt_solve_batch.argtypes = [P, C.POINTER(mcpt_problem), C.c_int32, C.POINTER(mcpt_options),
+                                     C.POINTER(C.c_uint64), C.POINTER(mcpt_summary)]
+    lib.mcpt_cluster_results.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(mcpt_summary)]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if name not in ("mcpt_destroy", "mcpt_last_error"):
@@ -152,10 +157,10 @@ class HostProblem:
 
 
 def make_options(tol=1e-10, max_sweeps=200, precision=MCPT_FP64, polish=1, deterministic=0,
-                 check_every=1, inner_sweeps=0, warm_t: np.ndarray | None = None):
+                 check_every=1, inner_sweeps=0, warm_t: np.ndarray | None = None, graph=0):
     o = mcpt_options(tol=tol, max_sweeps=max_sweeps, precision=precision, polish=polish,
                      deterministic=deterministic, check_every=check_every, inner_sweeps=inner_sweeps,
-                     warm_t=_ptr(warm_t))
+                     warm_t=_ptr(warm_t), graph=graph, reserved=0)
     o._keep = warm_t
     return o
 
@@ -168,6 +173,7 @@ class Context:
         _check(lib().mcpt_create(device, hbm_budget, C.byref(h)))
         self.h = h
         self._sizes = {}
+        self._clusters = {}
 
     def close(self):
         if self.h:
@@ -195,6 +201,33 @@ class Context:
         _check(lib().mcpt_upload(self.h, C.byref(hp.c), C.byref(pid)))
         self._sizes[pid.value] = (hp.n_occ.copy(), hp.n_vir.copy(), len(hp.pairs))
         return pid.value
+
+    def upload_batch(self, probs) -> int:
+        """Several independent clusters as one resident batch (mcpt_upload_batch)."""
+        hps = [p if isinstance(p, HostProblem) else HostProblem(p) for p in probs]
+        arr = (mcpt_problem * len(hps))(*[hp.c for hp in hps])
+        pid = C.c_uint64()
+        _check(lib().mcpt_upload_batch(self.h, arr, len(hps), C.byref(pid)))
+        n_occ = np.concatenate([hp.n_occ for hp in hps])
+        n_vir = np.concatenate([hp.n_vir for hp in hps])
+        self._sizes[pid.value] = (n_occ, n_vir, int(sum(len(hp.pairs) for hp in hps)))
+        self._clusters[pid.value] = [(len(hp.n_occ), len(hp.pairs)) for hp in hps]
+        return pid.value
+
+    def cluster_results(self, pid: int) -> list:
+        n = len(self._clusters.get(pid, [None]))
+        out = (mcpt_summary * n)()
+        _check(lib().mcpt_cluster_results(self.h, pid, n, out))
+        return [s.as_dict() for s in out]
+
+    def cluster_slices(self, pid: int):
+        """(monomer slice, pair slice) of each cluster in the concatenated arrays."""
+        out, m0, p0 = [], 0, 0
+        for nm, np_ in self._clusters.get(pid, [(len(self._sizes[pid][0]), self._sizes[pid][2])]):
+            out.append((slice(m0, m0 + nm), slice(p0, p0 + np_)))
+            m0 += nm
+            p0 += np_
+        return out
 
     def upload_device(self, n_occ, n_vir, pairs, eps_ptr: int, k_ptr: int, v_ptr: int) -> int:
         """Upload from device buffers (e.g. torch tensors' data_ptr()); sizes and pairs on the host."""
