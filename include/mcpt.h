@@ -26,7 +26,8 @@
  *    returns; output arrays are allocated by the caller.
  *  - Device memory and resident problems belong to the context until
  *    mcpt_release() or mcpt_destroy().
- *  - A context is used by one host thread at a time.
+ *  - A context is used by one host thread at a time; the serving calls
+ *    (mcpt_submit ...) run the solves on the context's own worker threads.
  */
 #ifndef MCPT_H
 #define MCPT_H
@@ -47,7 +48,7 @@ typedef enum {
     MCPT_ERR_NOT_CONVERGED = -4, /* max_sweeps reached with residual >= tol */
     MCPT_ERR_DIVERGED = -5,      /* residual non-finite, > 1e6 x first, or 3 rises above first */
     MCPT_ERR_NONFINITE = -6,     /* NaN or Inf in the inputs */
-    MCPT_ERR_ADMISSION = -7,     /* problem larger than the context's HBM budget */
+    MCPT_ERR_ADMISSION = -7,     /* problem larger than the free part of the context's HBM budget */
     MCPT_ERR_UNKNOWN_ID = -8     /* no resident problem / ticket with that id */
 } mcpt_status;
 
@@ -165,7 +166,8 @@ mcpt_status mcpt_run(mcpt_ctx *ctx, uint64_t id, const mcpt_options *opts, mcpt_
 /* Batching form: upload n independent clusters (probs[0..n-1], e.g. clusters
  * of different sizes and orbital counts) as one resident problem.  A run then
  * sweeps all of them together - every pair phase is one persistent launch over
- * the pairs of every live cluster - while each cluster keeps its own
+ * the pairs of every live cluster (FP64: one launch for the pairs whose V
+ * block fits in LDS and one for the rest) - while each cluster keeps its own
  * convergence test, so it stops at the same sweep as it would alone and its
  * results equal its solo solve.  mcpt_energy returns the clusters' arrays
  * concatenated in input order; mcpt_cluster_results gives per-cluster
@@ -202,6 +204,61 @@ mcpt_status mcpt_set_timing(mcpt_ctx *ctx, int enable);
 
 /* Read the timing totals since timing was enabled. */
 mcpt_status mcpt_timing_read(mcpt_ctx *ctx, mcpt_timing *out);
+
+/* ---- Serving form: continuous batching of arriving solves ----
+ *
+ * Requests (clusters of any size, e.g. finite-displacement geometries of the
+ * workflow that sums MCPT(2) energies over displaced structures) are queued
+ * by mcpt_submit and solved by the context's worker threads, each on its own
+ * HIP stream.  A free worker admits the oldest queued request once its device
+ * footprint (the bytes mcpt_upload and, for reduced precision, the
+ * reduced-precision copies would allocate) fits in the HBM budget beside the
+ * resident problems and the reservations of the other workers, and fuses into
+ * the same batch later queued requests with the same options and a pair-phase
+ * cost within a factor of four of it, while they fit.  The batch runs as an
+ * mcpt_upload_batch problem, so each request's result is the one its own
+ * solve gives.  Requests that arrive while batches run are taken by the next
+ * free worker, and the workers' batches run concurrently on the device.
+ * Results stay resident until mcpt_release(ticket); they count against the
+ * budget, so admission waits while released memory is needed.
+ */
+typedef struct {
+    uint64_t completed;         /* requests finished since the scheduler started */
+    uint64_t batches;           /* batches run */
+    uint64_t budget;            /* HBM budget of the context, bytes */
+    uint64_t bytes_in_use;      /* device bytes of resident problems and results */
+    uint64_t bytes_reserved;    /* bytes reserved by workers for uploads in progress */
+    int32_t  queued;            /* requests waiting for admission */
+    int32_t  running_batches;   /* batches on the device now */
+    int32_t  workers;           /* worker threads (0 before the first submission) */
+    int32_t  tickets;           /* live tickets (queued, running or holding results) */
+} mcpt_serve_counters;
+
+/* Scheduler parameters; only before the first mcpt_submit of the context.
+ * workers: concurrent batches (streams), 1..16 (default 4); max_batch:
+ * requests per batch, 1..4096 (default 32); max_batch_pairs: pairs per batch
+ * (default 2^20).  Errors: MCPT_ERR_INVALID (range, scheduler running). */
+mcpt_status mcpt_serve_config(mcpt_ctx *ctx, int32_t workers, int32_t max_batch, int64_t max_batch_pairs);
+
+/* Queue one solve.  The problem (host memory only) and options are checked and
+ * copied before the call returns; *ticket names the request in mcpt_poll,
+ * mcpt_wait, and, once done, mcpt_energy and mcpt_release.
+ * Errors: MCPT_ERR_INVALID, MCPT_ERR_NONFINITE (as mcpt_upload, plus device
+ * memory), MCPT_ERR_ADMISSION (footprint larger than the whole budget). */
+mcpt_status mcpt_submit(mcpt_ctx *ctx, const mcpt_problem *prob, const mcpt_options *opts, uint64_t *ticket);
+
+/* MCPT_PENDING while the request is queued or running; MCPT_OK once done, with
+ * *out (may be NULL) its summary: status is the solve's status (OK,
+ * NOT_CONVERGED, DIVERGED, or the error that stopped its batch, described by
+ * mcpt_last_error after this call) and seconds is the latency from submission
+ * to result.  Errors: MCPT_ERR_UNKNOWN_ID. */
+mcpt_status mcpt_poll(mcpt_ctx *ctx, uint64_t ticket, mcpt_summary *out);
+
+/* As mcpt_poll, blocking up to timeout_ms milliseconds (< 0: no limit). */
+mcpt_status mcpt_wait(mcpt_ctx *ctx, uint64_t ticket, int32_t timeout_ms, mcpt_summary *out);
+
+/* Scheduler counters and memory accounting. */
+mcpt_status mcpt_serve_stats(mcpt_ctx *ctx, mcpt_serve_counters *out);
 
 #ifdef __cplusplus
 }

@@ -15,10 +15,9 @@
 
 #include "../../include/mcpt.h"
 #include "mcpt_internal.hpp"
+#include "runtime.hpp"
 
-using namespace mcpt;
-
-namespace {
+namespace mcpt {
 
 thread_local std::string g_err;
 
@@ -27,98 +26,14 @@ mcpt_status fail(mcpt_status s, const std::string& msg) {
     return s;
 }
 
+const std::string& last_error_text() { return g_err; }
+
 #define HIP_TRY(expr)                                                                          \
     do {                                                                                       \
         hipError_t e_ = (expr);                                                                \
         if (e_ != hipSuccess)                                                                  \
             return fail(MCPT_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
     } while (0)
-
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-};
-
-struct Resident {
-    uint64_t id = 0;
-    int n_mono = 0;
-    int64_t n_pair = 0;
-    int max_n = 0, max_np = 0;
-    int64_t eps_elems = 0, dif_elems = 0, raw_elems = 0, mat_elems = 0, v_elems = 0, max_slot = 0;
-    std::vector<MonoDesc> monos;
-    std::vector<PairDesc> pairs;      // LDS-variant pairs, then the others; each range sorted by
-                                      // monomer for locality; .orig is the caller's index
-    int64_t n_lds = 0;                // pairs served by the LDS-resident-V kernel
-    // device
-    MonoDesc* d_monos = nullptr;
-    PairDesc* d_pairs = nullptr;
-    double *d_dif = nullptr, *d_raw = nullptr, *d_K = nullptr, *d_T = nullptr, *d_M = nullptr;
-    double *d_G[2] = {nullptr, nullptr};
-    double* d_V = nullptr;
-    double *d_em2 = nullptr, *d_em2_0 = nullptr, *d_ed2 = nullptr, *d_res = nullptr;
-    // clusters of a batch: monomer and pair ranges (caller order), per-cluster state and history
-    int n_cl = 1;
-    std::vector<int64_t> cl_mono, cl_pair;
-    int64_t *d_cl_mono = nullptr, *d_cl_pair = nullptr;
-    ClState* d_cl = nullptr;
-    double* d_hist = nullptr;
-    std::vector<mcpt_summary> cl_last;
-    std::vector<void*> allocations;
-    size_t bytes = 0;
-    bool has_result = false;
-    mcpt_summary last{};
-    // reduced-precision copies (mixed-precision form), made on first use of a precision
-    int lo_prec = 0;
-    void *d_Vlo = nullptr, *d_Mlo = nullptr;
-    int64_t *d_lo_off = nullptr, *d_mlo_off = nullptr;
-    double *d_R = nullptr, *d_Dl = nullptr;
-    int64_t lo_slot = 0;          // elements of one low-precision Tau + Tau^T scratch slot
-    double lo_v_bytes = 0.0;      // bytes of the low-precision V and V^T
-    std::vector<void*> lo_allocations;
-    size_t lo_bytes = 0;
-    // captured sweep graph (plain sweeps): valid for one precision and batch size
-    hipGraphExec_t graph = nullptr;
-    int graph_prec = -1, graph_sweeps = 0, graph_parity = 0;
-    std::array<int64_t, 6> graph_key{};   // context buffers and grids baked into the captured launches
-};
-
-struct Timing {
-    bool on = false;
-    struct Rec {
-        hipEvent_t a, b;
-        int kind;   // 0 FP64 pair phase, 1 monomer phase, 2 reduced-precision pair phase
-        double flops, vbytes;
-    };
-    std::vector<Rec> pending;
-    std::vector<hipEvent_t> pool;
-    mcpt_timing tot{};
-};
-
-}  // namespace
-
-struct mcpt_ctx {
-    int device = 0;
-    int n_cu = 0;
-    hipStream_t own = nullptr;
-    hipStream_t stream = nullptr;
-    size_t budget = 0, in_use = 0;
-    uint64_t next_id = 1;
-    std::map<uint64_t, std::unique_ptr<Resident>> res;
-    Ctrl* d_ctrl = nullptr;
-    Ctrl* h_ctrl = nullptr;             // pinned
-    int32_t* d_flag = nullptr;
-    int32_t* h_flag = nullptr;          // pinned
-    double* d_scratch = nullptr;
-    int64_t scratch_slot = 0;
-    int scratch_slots = 0;
-    int grid_lds = 0, grid_glb = 0;   // persistent grids of the two pair-kernel variants
-    void* d_scratch_lo = nullptr;     // reduced-precision Tau scratch
-    size_t scratch_lo_bytes = 0;
-    int grid_lo = 0;
-    Timing timing;
-};
-
-namespace {
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -130,7 +45,10 @@ mcpt_status ensure_device(mcpt_ctx* c) {
 void free_lowp(mcpt_ctx* c, Resident* r) {
     for (void* p : r->lo_allocations) (void)hipFree(p);
     r->lo_allocations.clear();
-    c->in_use -= std::min(c->in_use, r->lo_bytes);
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        c->in_use -= std::min(c->in_use, r->lo_bytes);
+    }
     r->lo_bytes = 0;
     r->lo_prec = 0;
     r->d_Vlo = r->d_Mlo = nullptr;
@@ -149,13 +67,20 @@ void free_resident(mcpt_ctx* c, Resident* r) {
     free_lowp(c, r);
     for (void* p : r->allocations) (void)hipFree(p);
     r->allocations.clear();
-    c->in_use -= std::min(c->in_use, r->bytes);
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        c->in_use -= std::min(c->in_use, r->bytes);
+    }
     r->bytes = 0;
 }
 
-mcpt_status lo_alloc(mcpt_ctx* c, Resident* r, void** out, size_t bytes) {
+mcpt_status lo_alloc(mcpt_ctx* c, Exec& x, Resident* r, void** out, size_t bytes) {
     bytes = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
-    if (c->in_use + bytes > c->budget) return fail(MCPT_ERR_ADMISSION, "reduced-precision copies exceed the budget");
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        if (c->in_use + (c->reserved - x.reserved) + bytes > c->budget)
+            return fail(MCPT_ERR_ADMISSION, "reduced-precision copies exceed the budget");
+    }
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
@@ -164,6 +89,7 @@ mcpt_status lo_alloc(mcpt_ctx* c, Resident* r, void** out, size_t bytes) {
     }
     r->lo_allocations.push_back(p);
     r->lo_bytes += bytes;
+    std::lock_guard<std::mutex> g(c->mu);
     c->in_use += bytes;
     *out = p;
     return MCPT_OK;
@@ -182,6 +108,7 @@ mcpt_status dev_alloc(mcpt_ctx* c, Resident* r, T** out, int64_t count) {
     }
     r->allocations.push_back(p);
     r->bytes += bytes;
+    std::lock_guard<std::mutex> g(c->mu);
     c->in_use += bytes;
     *out = static_cast<T*>(p);
     return MCPT_OK;
@@ -223,25 +150,23 @@ void drain_timing(Timing& t) {
     t.pending.clear();
 }
 
-mcpt_status ensure_scratch(mcpt_ctx* c, int64_t slot_elems) {
-    c->grid_lds = std::max(8, c->n_cu * pair_fp64_blocks_per_cu(1) / 8 * 8);
-    c->grid_glb = std::max(8, c->n_cu * pair_fp64_blocks_per_cu(0) / 8 * 8);
+mcpt_status ensure_scratch(mcpt_ctx* c, Exec& x, int64_t slot_elems) {
     const int grid = std::max(c->grid_lds, c->grid_glb);
-    if (c->d_scratch && c->scratch_slot >= slot_elems && c->scratch_slots >= grid) return MCPT_OK;
-    if (c->d_scratch) {
-        HIP_TRY(hipStreamSynchronize(c->stream));
-        (void)hipFree(c->d_scratch);
-        c->d_scratch = nullptr;
+    if (x.d_scratch && x.scratch_slot >= slot_elems && x.scratch_slots >= grid) return MCPT_OK;
+    if (x.d_scratch) {
+        HIP_TRY(hipStreamSynchronize(x.stream));
+        (void)hipFree(x.d_scratch);
+        x.d_scratch = nullptr;
     }
-    const int64_t slot = std::max<int64_t>(slot_elems, c->scratch_slot);
-    hipError_t e = hipMalloc(&c->d_scratch, (size_t)slot * grid * sizeof(double));
+    const int64_t slot = std::max<int64_t>(slot_elems, x.scratch_slot);
+    hipError_t e = hipMalloc(&x.d_scratch, (size_t)slot * grid * sizeof(double));
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        c->d_scratch = nullptr;
+        x.d_scratch = nullptr;
         return fail(MCPT_ERR_NOMEM, "scratch allocation failed");
     }
-    c->scratch_slot = slot;
-    c->scratch_slots = grid;
+    x.scratch_slot = slot;
+    x.scratch_slots = grid;
     return MCPT_OK;
 }
 
@@ -307,7 +232,7 @@ mcpt_status check_energies(const std::vector<double>& eps, const mcpt_problem* p
 // and pairs are concatenated cluster after cluster (pair indices shifted by the
 // cluster's first monomer), each monomer and pair carries its cluster id, and
 // every cluster keeps its own stopping state during a run.
-mcpt_status upload_batch(mcpt_ctx* c, const mcpt_problem* pbs, int n_cl, uint64_t* id_out) {
+mcpt_status upload_batch(mcpt_ctx* c, Exec& x, const mcpt_problem* pbs, int n_cl, bool internal, uint64_t* id_out) {
     if (!pbs || n_cl < 1) return fail(MCPT_ERR_INVALID, "need at least one problem");
     if (!id_out) return fail(MCPT_ERR_INVALID, "id is NULL");
     mcpt_status st;
@@ -417,13 +342,15 @@ mcpt_status upload_batch(mcpt_ctx* c, const mcpt_problem* pbs, int n_cl, uint64_
             for (int a = 0; a < d.v; ++a) dif[d.dif_off + i * d.v + a] = e[i] - e[d.o + a];
     }
     // footprint and admission
-    const size_t need = sizeof(double) * ((size_t)doff + r->raw_elems + 5 * (size_t)r->mat_elems + r->v_elems +
-                                          3 * (size_t)r->n_mono + r->n_pair + (size_t)n_cl * kMaxSweeps) +
-                        r->monos.size() * sizeof(MonoDesc) + r->pairs.size() * sizeof(PairDesc) +
-                        n_cl * (sizeof(ClState) + 16);
-    if (c->in_use + need > c->budget)
-        return fail(MCPT_ERR_ADMISSION, "problem needs " + std::to_string(need) + " bytes; budget " +
-                                            std::to_string(c->budget) + ", in use " + std::to_string(c->in_use));
+    const size_t need = footprint(pbs, n_cl, MCPT_FP64);
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        const size_t others = c->reserved - x.reserved;
+        if (c->in_use + others + need > c->budget)
+            return fail(MCPT_ERR_ADMISSION, "problem needs " + std::to_string(need) + " bytes; budget " +
+                                                std::to_string(c->budget) + ", in use " +
+                                                std::to_string(c->in_use + others));
+    }
     Resident* R = r.get();
 #define ALLOC(ptr, n)                                          \
     do {                                                       \
@@ -451,7 +378,7 @@ mcpt_status upload_batch(mcpt_ctx* c, const mcpt_problem* pbs, int n_cl, uint64_
     ALLOC(R->d_cl_mono, n_cl + 1);
     ALLOC(R->d_cl_pair, n_cl + 1);
 #undef ALLOC
-    hipStream_t s = c->stream;
+    hipStream_t s = x.stream;
 #define DTRY(expr)                   \
     do {                             \
         hipError_t e_ = (expr);      \
@@ -474,10 +401,10 @@ mcpt_status upload_batch(mcpt_ctx* c, const mcpt_problem* pbs, int n_cl, uint64_
         if (v_cl[q + 1] > v_cl[q])
             DTRY(hipMemcpyAsync(R->d_V + v_cl[q], pbs[q].v_dimer, (v_cl[q + 1] - v_cl[q]) * sizeof(double), kind, s));
     }
-    *c->h_flag = 0;
-    DTRY(hipMemcpyAsync(c->d_flag, c->h_flag, sizeof(int32_t), hipMemcpyHostToDevice, s));
-    launch_nonfinite(R->d_raw, R->raw_elems, c->d_flag, s);
-    launch_nonfinite(R->d_V, R->v_elems, c->d_flag, s);
+    *x.h_flag = 0;
+    DTRY(hipMemcpyAsync(x.d_flag, x.h_flag, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    launch_nonfinite(R->d_raw, R->raw_elems, x.d_flag, s);
+    launch_nonfinite(R->d_V, R->v_elems, x.d_flag, s);
     launch_fill(R->d_K, R->mat_elems, 0.0, s);
     launch_fill(R->d_T, R->mat_elems, 0.0, s);
     launch_fill(R->d_M, R->mat_elems, 0.0, s);
@@ -485,17 +412,125 @@ mcpt_status upload_batch(mcpt_ctx* c, const mcpt_problem* pbs, int n_cl, uint64_
     launch_fill(R->d_G[1], R->mat_elems, 0.0, s);
     launch_pack(R->d_monos, R->n_mono, R->d_raw, R->d_K, R->max_n, s);
     DTRY(hipGetLastError());
-    DTRY(hipMemcpyAsync(c->h_flag, c->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DTRY(hipMemcpyAsync(x.h_flag, x.d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     DTRY(hipStreamSynchronize(s));
 #undef DTRY
-    if (*c->h_flag) {
+    if (*x.h_flag) {
         free_resident(c, R);
         return fail(MCPT_ERR_NONFINITE, "non-finite value in k_intra or v_dimer");
     }
     r->cl_last.assign(n_cl, mcpt_summary{});
+    r->internal = internal;
+    std::lock_guard<std::mutex> g(c->mu);
     r->id = c->next_id++;
     *id_out = r->id;
     c->res[r->id] = std::move(r);
+    return MCPT_OK;
+}
+
+// Device bytes that upload_batch (and, for a reduced precision, ensure_lowp)
+// allocates for these clusters; sizes only, so admission can price a request
+// before anything is allocated.  Every buffer is rounded up to 256 bytes.
+size_t footprint(const mcpt_problem* pbs, int n, int precision) {
+    int64_t n_mono = 0, n_pair = 0, dif = 0, raw = 0, mat = 0, v = 0, vlo = 0, mlo = 0;
+    const int kc = precision == MCPT_FP64 ? 0 : lowp_chunk(precision);
+    auto ld = [kc](int64_t m) { return (m + kc - 1) / kc * kc; };
+    for (int q = 0; q < n; ++q) {
+        const mcpt_problem& p = pbs[q];
+        for (int x = 0; x < p.n_mono; ++x) {
+            const int64_t nx = (int64_t)p.n_occ[x] * p.n_vir[x], np = (nx + kTile - 1) / kTile * kTile;
+            dif += np;
+            raw += nx * nx;
+            mat += np * np;
+            if (kc) mlo += np * ld(nx);
+        }
+        for (int64_t k = 0; k < p.n_pair; ++k) {
+            const int x = p.pair[2 * k], y = p.pair[2 * k + 1];
+            const int64_t nx = (int64_t)p.n_occ[x] * p.n_vir[x], ny = (int64_t)p.n_occ[y] * p.n_vir[y];
+            v += nx * ny;
+            if (kc) vlo += (nx + kTile - 1) / kTile * kTile * ld(ny) + (ny + kTile - 1) / kTile * kTile * ld(nx);
+        }
+        n_mono += p.n_mono;
+        n_pair += p.n_pair;
+    }
+    auto r = [](int64_t bytes) { return (size_t)((std::max<int64_t>(bytes, 1) + 255) / 256 * 256); };
+    size_t b = r(n_mono * (int64_t)sizeof(MonoDesc)) + r(std::max<int64_t>(n_pair, 1) * (int64_t)sizeof(PairDesc)) +
+               r(8 * dif) + r(8 * raw) + 5 * r(8 * mat) + r(8 * std::max<int64_t>(v, 1)) + 3 * r(8 * n_mono) +
+               r(8 * std::max<int64_t>(n_pair, 1)) + r((int64_t)n * (int64_t)sizeof(ClState)) +
+               r(8 * (int64_t)n * kMaxSweeps) + 2 * r(8 * (int64_t)(n + 1));
+    if (kc) {
+        const int64_t es = precision == MCPT_BF16 ? 2 : 4;
+        b += r(es * vlo) + r(es * mlo) + r(8 * std::max<int64_t>(n_pair, 1)) + r(8 * n_mono) + 2 * r(8 * mat);
+    }
+    return b;
+}
+
+mcpt_status exec_init(mcpt_ctx* c, Exec& x) {
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipStreamCreateWithFlags(&x.own, hipStreamNonBlocking));
+    x.stream = x.own;
+    HIP_TRY(hipMalloc(&x.d_ctrl, sizeof(Ctrl)));
+    HIP_TRY(hipHostMalloc(&x.h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
+    HIP_TRY(hipMalloc(&x.d_flag, sizeof(int32_t)));
+    HIP_TRY(hipHostMalloc(&x.h_flag, sizeof(int32_t), hipHostMallocDefault));
+    return MCPT_OK;
+}
+
+void exec_free(mcpt_ctx* c, Exec& x) {
+    (void)hipSetDevice(c->device);
+    if (x.stream) (void)hipStreamSynchronize(x.stream);
+    if (x.timing.on) drain_timing(x.timing);
+    for (hipEvent_t e : x.timing.pool) (void)hipEventDestroy(e);
+    x.timing.pool.clear();
+    if (x.d_scratch) (void)hipFree(x.d_scratch);
+    if (x.d_scratch_lo) (void)hipFree(x.d_scratch_lo);
+    if (x.d_ctrl) (void)hipFree(x.d_ctrl);
+    if (x.d_flag) (void)hipFree(x.d_flag);
+    if (x.h_ctrl) (void)hipHostFree(x.h_ctrl);
+    if (x.h_flag) (void)hipHostFree(x.h_flag);
+    if (x.own) (void)hipStreamDestroy(x.own);
+    x = Exec{};
+}
+
+void release_resident(mcpt_ctx* c, uint64_t id) {
+    std::unique_ptr<Resident> r;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        auto it = c->res.find(id);
+        if (it == c->res.end()) return;
+        r = std::move(it->second);
+        c->res.erase(it);
+    }
+    free_resident(c, r.get());
+}
+
+// Results of cluster q of a resident problem (q < 0: every cluster, concatenated).
+mcpt_status slice_results(mcpt_ctx* c, Exec& x, Resident* R, int q, double* e_m2, double* de_m2, double* e_d2,
+                          double* t_amp) {
+    if (!R->has_result) return fail(MCPT_ERR_INVALID, "problem has no result (not run, or diverged)");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = x.stream;
+    const int64_t m0 = q < 0 ? 0 : R->cl_mono[q], m1 = q < 0 ? R->n_mono : R->cl_mono[q + 1];
+    const int64_t p0 = q < 0 ? 0 : R->cl_pair[q], p1 = q < 0 ? R->n_pair : R->cl_pair[q + 1];
+    std::vector<double> a(m1 - m0), b(m1 - m0);
+    if (m1 > m0) {
+        HIP_TRY(hipMemcpyAsync(a.data(), R->d_em2 + m0, (m1 - m0) * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(b.data(), R->d_em2_0 + m0, (m1 - m0) * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (e_d2 && p1 > p0)
+        HIP_TRY(hipMemcpyAsync(e_d2, R->d_ed2 + p0, (p1 - p0) * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (t_amp && m1 > m0) {
+        launch_unpack(R->d_monos, R->n_mono, R->d_T, R->d_raw, R->max_n, s);
+        HIP_TRY(hipGetLastError());
+        const int64_t r0 = R->monos[m0].raw_off;
+        const int64_t r1 = m1 < R->n_mono ? R->monos[m1].raw_off : R->raw_elems;
+        HIP_TRY(hipMemcpyAsync(t_amp, R->d_raw + r0, (r1 - r0) * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int64_t k = 0; k < m1 - m0; ++k) {
+        if (e_m2) e_m2[k] = a[k];
+        if (de_m2) de_m2[k] = a[k] - b[k];
+    }
     return MCPT_OK;
 }
 
@@ -514,33 +549,33 @@ mcpt_status validate_options(const mcpt_options* o) {
     return MCPT_OK;
 }
 
-void record_begin(mcpt_ctx* c, hipEvent_t* a) {
-    if (!c->timing.on) return;
-    *a = take_event(c->timing);
-    (void)hipEventRecord(*a, c->stream);
+void record_begin(Exec& x, hipEvent_t* a) {
+    if (!x.timing.on) return;
+    *a = take_event(x.timing);
+    (void)hipEventRecord(*a, x.stream);
 }
 
-void record_end(mcpt_ctx* c, hipEvent_t a, int kind, double flops, double vbytes) {
-    if (!c->timing.on) return;
-    hipEvent_t b = take_event(c->timing);
-    (void)hipEventRecord(b, c->stream);
-    c->timing.pending.push_back({a, b, kind, flops, vbytes});
+void record_end(Exec& x, hipEvent_t a, int kind, double flops, double vbytes) {
+    if (!x.timing.on) return;
+    hipEvent_t b = take_event(x.timing);
+    (void)hipEventRecord(b, x.stream);
+    x.timing.pending.push_back({a, b, kind, flops, vbytes});
 }
 
 // Pair phase over all pairs: the LDS-resident-V kernel for the pairs that fit,
 // then the L2 variant for the rest (same stream, so G accumulates in order).
-void pair_phase(mcpt_ctx* c, Resident* R, double* G, int couple, const Ctrl* ctrl) {
+void pair_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int couple, const Ctrl* ctrl) {
     const ClState* cl = ctrl ? R->d_cl : nullptr;   // the final energy pass covers every cluster
-    launch_pair_fp64(1, R->d_pairs, R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G, c->d_scratch,
-                     c->scratch_slot, c->grid_lds, R->d_ed2, couple, ctrl, cl, c->stream);
+    launch_pair_fp64(1, R->d_pairs, R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G, x.d_scratch,
+                     x.scratch_slot, c->grid_lds, R->d_ed2, couple, ctrl, cl, x.stream);
     launch_pair_fp64(0, R->d_pairs + R->n_lds, R->n_pair - R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G,
-                     c->d_scratch, c->scratch_slot, c->grid_glb, R->d_ed2, couple, ctrl, cl, c->stream);
+                     x.d_scratch, x.scratch_slot, c->grid_glb, R->d_ed2, couple, ctrl, cl, x.stream);
 }
 
 // Reduced-precision copies of a resident problem for `prec` (1 FP32, 2 BF16):
 // V and V^T per pair (rows padded to 16, k padded to the chunk), M per monomer,
 // and FP64 buffers for the polish residual R and correction delta.
-mcpt_status ensure_lowp(mcpt_ctx* c, Resident* R, int prec) {
+mcpt_status ensure_lowp(mcpt_ctx* c, Exec& x, Resident* R, int prec) {
     if (R->lo_prec == prec) return MCPT_OK;
     drop_graph(R);
     free_lowp(c, R);
@@ -563,15 +598,15 @@ mcpt_status ensure_lowp(mcpt_ctx* c, Resident* R, int prec) {
     }
     mcpt_status st;
     void *vlo = nullptr, *mlo = nullptr, *lo_o = nullptr, *mlo_o = nullptr, *rr = nullptr, *dd = nullptr;
-    if ((st = lo_alloc(c, R, &vlo, vo * es)) != MCPT_OK || (st = lo_alloc(c, R, &mlo, mo * es)) != MCPT_OK ||
-        (st = lo_alloc(c, R, &lo_o, lo_off.size() * 8)) != MCPT_OK ||
-        (st = lo_alloc(c, R, &mlo_o, mlo_off.size() * 8)) != MCPT_OK ||
-        (st = lo_alloc(c, R, &rr, R->mat_elems * 8)) != MCPT_OK ||
-        (st = lo_alloc(c, R, &dd, R->mat_elems * 8)) != MCPT_OK) {
+    if ((st = lo_alloc(c, x, R, &vlo, vo * es)) != MCPT_OK || (st = lo_alloc(c, x, R, &mlo, mo * es)) != MCPT_OK ||
+        (st = lo_alloc(c, x, R, &lo_o, lo_off.size() * 8)) != MCPT_OK ||
+        (st = lo_alloc(c, x, R, &mlo_o, mlo_off.size() * 8)) != MCPT_OK ||
+        (st = lo_alloc(c, x, R, &rr, R->mat_elems * 8)) != MCPT_OK ||
+        (st = lo_alloc(c, x, R, &dd, R->mat_elems * 8)) != MCPT_OK) {
         free_lowp(c, R);
         return st;
     }
-    hipStream_t s = c->stream;
+    hipStream_t s = x.stream;
     HIP_TRY(hipMemcpyAsync(lo_o, lo_off.data(), lo_off.size() * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(mlo_o, mlo_off.data(), mlo_off.size() * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(mlo, 0, mo * es, s));   // padding of M stays zero
@@ -589,58 +624,67 @@ mcpt_status ensure_lowp(mcpt_ctx* c, Resident* R, int prec) {
     R->lo_slot = (slot + 63) / 64 * 64;   // keeps every slot 16-byte aligned
     R->lo_v_bytes = (double)vo * es;
     R->lo_prec = prec;
-    // scratch for the reduced-precision Tau and Tau^T
-    c->grid_lo = std::max(8, c->n_cu * pair_lowp_blocks_per_cu(prec) / 8 * 8);
-    const size_t need = (size_t)R->lo_slot * es * c->grid_lo;
-    if (need > c->scratch_lo_bytes) {
-        if (c->d_scratch_lo) (void)hipFree(c->d_scratch_lo);
-        c->d_scratch_lo = nullptr;
-        c->scratch_lo_bytes = 0;
-        hipError_t e = hipMalloc(&c->d_scratch_lo, need);
+    return MCPT_OK;
+}
+
+// Per-stream scratch of the reduced-precision pair kernel (Tau and Tau^T per workgroup).
+mcpt_status ensure_scratch_lo(mcpt_ctx* c, Exec& x, const Resident* R, int prec) {
+    const size_t es = prec == MCPT_BF16 ? 2 : 4;
+    x.grid_lo = std::max(8, c->n_cu * pair_lowp_blocks_per_cu(prec) / 8 * 8);
+    const size_t need = (size_t)R->lo_slot * es * x.grid_lo;
+    if (need > x.scratch_lo_bytes) {
+        HIP_TRY(hipStreamSynchronize(x.stream));
+        if (x.d_scratch_lo) (void)hipFree(x.d_scratch_lo);
+        x.d_scratch_lo = nullptr;
+        x.scratch_lo_bytes = 0;
+        hipError_t e = hipMalloc(&x.d_scratch_lo, need);
         if (e != hipSuccess) {
             (void)hipGetLastError();
+            x.d_scratch_lo = nullptr;
             return fail(MCPT_ERR_NOMEM, "reduced-precision scratch allocation failed");
         }
-        c->scratch_lo_bytes = need;
+        x.scratch_lo_bytes = need;
     }
     return MCPT_OK;
 }
 
-void lowp_phase(mcpt_ctx* c, Resident* R, double* G, int source) {
+void lowp_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int source) {
     launch_pair_lowp(R->lo_prec, R->d_pairs, R->n_pair, R->d_monos, R->d_dif, R->d_Vlo, R->d_lo_off, R->d_Mlo,
-                     R->d_mlo_off, G, c->d_scratch_lo, R->lo_slot, c->grid_lo, R->d_ed2, source, 1, nullptr,
-                     R->d_cl, c->stream);
+                     R->d_mlo_off, G, x.d_scratch_lo, R->lo_slot, x.grid_lo, R->d_ed2, source, 1, nullptr,
+                     R->d_cl, x.stream);
 }
 
-void mixed_mono(mcpt_ctx* c, Resident* R, int mode, const double* G, double* Gz, bool lo_out, const Ctrl* ctrl) {
+void mixed_mono(mcpt_ctx* c, Exec& x, Resident* R, int mode, const double* G, double* Gz, bool lo_out, const Ctrl* ctrl) {
     launch_monomer_mixed(mode, R->lo_prec, R->d_monos, R->n_mono, R->d_dif, R->d_K, G, Gz, R->d_T, R->d_M, R->d_R,
                          R->d_Dl, lo_out ? R->d_Mlo : nullptr, R->d_mlo_off, R->d_em2, R->d_em2_0, R->d_res, ctrl,
-                         R->d_cl, c->stream);
+                         R->d_cl, x.stream);
 }
 
-mcpt_status sync_ctrl(mcpt_ctx* c) {
+mcpt_status sync_ctrl(Exec& x) {
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(c->h_ctrl, c->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpyAsync(x.h_ctrl, x.d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, x.stream));
+    HIP_TRY(hipStreamSynchronize(x.stream));
     return MCPT_OK;
 }
 
-mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* out) {
+mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_summary* out) {
     mcpt_status st = validate_options(o);
     if (st != MCPT_OK) return st;
     if ((st = ensure_device(c)) != MCPT_OK) return st;
-    if ((st = ensure_scratch(c, R->max_slot)) != MCPT_OK) return st;
+    if ((st = ensure_scratch(c, x, R->max_slot)) != MCPT_OK) return st;
     const int prec = o->precision;
-    if (prec != MCPT_FP64 && (st = ensure_lowp(c, R, prec)) != MCPT_OK) return st;
+    if (prec != MCPT_FP64 && ((st = ensure_lowp(c, x, R, prec)) != MCPT_OK ||
+                              (st = ensure_scratch_lo(c, x, R, prec)) != MCPT_OK))
+        return st;
     const auto t0 = std::chrono::steady_clock::now();
-    hipStream_t s = c->stream;
+    hipStream_t s = x.stream;
     R->has_result = false;
-    Ctrl& h = *c->h_ctrl;
+    Ctrl& h = *x.h_ctrl;
     std::memset(&h, 0, sizeof(Ctrl));
     h.fixed = o->tol == 0.0;
     h.max_sweeps = o->max_sweeps;
     h.tol = o->tol;
-    HIP_TRY(hipMemcpyAsync(c->d_ctrl, &h, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(x.d_ctrl, &h, sizeof(Ctrl), hipMemcpyHostToDevice, s));
     {
         const std::vector<ClState> zero(R->n_cl, ClState{});
         HIP_TRY(hipMemcpyAsync(R->d_cl, zero.data(), R->n_cl * sizeof(ClState), hipMemcpyHostToDevice, s));
@@ -660,29 +704,29 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
         launch_monomer(kMonoInit, R->d_monos, R->n_mono, R->d_dif, R->d_K, nullptr, nullptr, R->d_T, R->d_M,
                        R->d_em2, R->d_em2_0, R->d_res, nullptr, nullptr, s);
     }
-    if (prec != MCPT_FP64) mixed_mono(c, R, kMonoFromT, nullptr, nullptr, true, nullptr);   // M in low precision
+    if (prec != MCPT_FP64) mixed_mono(c, x, R, kMonoFromT, nullptr, nullptr, true, nullptr);   // M in low precision
     HIP_TRY(hipGetLastError());
     const double fl_sweep = pair_flops(*R, true), fl_final = pair_flops(*R, false);
     const double vb = (double)R->v_elems * sizeof(double);
     const int every = o->check_every > 0 ? o->check_every : 1;
     int cur = 0, n_lo = 0, n_hi = 0;
-    const bool timing_on = c->timing.on && !o->graph;
+    const bool timing_on = x.timing.on && !o->graph;
     const int inner = o->inner_sweeps > 0 ? o->inner_sweeps : (prec == MCPT_BF16 ? 3 : 5);
     const int n_pre = std::min(inner + 1, o->max_sweeps);
-    const bool saved_timing = c->timing.on;
-    c->timing.on = timing_on;
+    const bool saved_timing = x.timing.on;
+    x.timing.on = timing_on;
 
     if (prec == MCPT_FP64 || !o->polish) {
         // plain Jacobi sweeps: FP64, or reduced precision with the integral source terms
         auto issue_sweep = [&](bool timed) {
-            if (prec == MCPT_FP64) pair_phase(c, R, R->d_G[cur], 1, c->d_ctrl);
-            else lowp_phase(c, R, R->d_G[cur], 1);
+            if (prec == MCPT_FP64) pair_phase(c, x, R, R->d_G[cur], 1, x.d_ctrl);
+            else lowp_phase(c, x, R, R->d_G[cur], 1);
             if (prec == MCPT_FP64)
                 launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->d_dif, R->d_K, R->d_G[cur], R->d_G[cur ^ 1],
-                               R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, c->d_ctrl, R->d_cl, s);
+                               R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, x.d_ctrl, R->d_cl, s);
             else
-                mixed_mono(c, R, kMonoUpdate, R->d_G[cur], R->d_G[cur ^ 1], true, c->d_ctrl);
-            launch_reduce_sweep(R->n_cl, R->d_cl_mono, R->d_res, R->d_cl, R->d_hist, c->d_ctrl, s);
+                mixed_mono(c, x, R, kMonoUpdate, R->d_G[cur], R->d_G[cur ^ 1], true, x.d_ctrl);
+            launch_reduce_sweep(R->n_cl, R->d_cl_mono, R->d_res, R->d_cl, R->d_hist, x.d_ctrl, s);
             cur ^= 1;
             (void)timed;
         };
@@ -690,9 +734,9 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
         if (o->graph && o->max_sweeps > 0) {
             // an even number of sweeps per graph keeps the G double-buffer parity of every replay
             const int gk = (every % 2) ? 2 * every : every;
-            const std::array<int64_t, 6> key{(int64_t)(uintptr_t)c->d_scratch, (int64_t)(uintptr_t)c->d_scratch_lo,
-                                             (int64_t)(uintptr_t)c->d_ctrl, c->scratch_slot,
-                                             (int64_t)c->grid_lds * 1000000 + c->grid_glb, c->grid_lo};
+            const std::array<int64_t, 6> key{(int64_t)(uintptr_t)x.d_scratch, (int64_t)(uintptr_t)x.d_scratch_lo,
+                                             (int64_t)(uintptr_t)x.d_ctrl, x.scratch_slot,
+                                             (int64_t)c->grid_lds * 1000000 + c->grid_glb, x.grid_lo};
             if (!R->graph || R->graph_prec != prec || R->graph_sweeps != gk || R->graph_key != key) {
                 drop_graph(R);
                 hipGraph_t g = nullptr;
@@ -714,7 +758,7 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
             while (issued < o->max_sweeps) {
                 HIP_TRY(hipGraphLaunch(R->graph, s));
                 issued += gk;
-                if ((st = sync_ctrl(c)) != MCPT_OK) return st;
+                if ((st = sync_ctrl(x)) != MCPT_OK) return st;
                 if (h.done) break;
             }
         }
@@ -722,27 +766,27 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
             const int batch = std::min(every, o->max_sweeps - issued);
             for (int k = 0; k < batch; ++k) {
                 hipEvent_t a = nullptr;
-                record_begin(c, &a);
+                record_begin(x, &a);
                 if (prec == MCPT_FP64) {
-                    pair_phase(c, R, R->d_G[cur], 1, c->d_ctrl);
-                    record_end(c, a, 0, fl_sweep, vb);
+                    pair_phase(c, x, R, R->d_G[cur], 1, x.d_ctrl);
+                    record_end(x, a, 0, fl_sweep, vb);
                 } else {
-                    lowp_phase(c, R, R->d_G[cur], 1);
-                    record_end(c, a, 2, fl_sweep, R->lo_v_bytes);
+                    lowp_phase(c, x, R, R->d_G[cur], 1);
+                    record_end(x, a, 2, fl_sweep, R->lo_v_bytes);
                 }
-                record_begin(c, &a);
+                record_begin(x, &a);
                 if (prec == MCPT_FP64)
                     launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->d_dif, R->d_K, R->d_G[cur],
-                                   R->d_G[cur ^ 1], R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, c->d_ctrl,
+                                   R->d_G[cur ^ 1], R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, x.d_ctrl,
                                    R->d_cl, s);
                 else
-                    mixed_mono(c, R, kMonoUpdate, R->d_G[cur], R->d_G[cur ^ 1], true, c->d_ctrl);
-                record_end(c, a, 1, 0.0, 0.0);
-                launch_reduce_sweep(R->n_cl, R->d_cl_mono, R->d_res, R->d_cl, R->d_hist, c->d_ctrl, s);
+                    mixed_mono(c, x, R, kMonoUpdate, R->d_G[cur], R->d_G[cur ^ 1], true, x.d_ctrl);
+                record_end(x, a, 1, 0.0, 0.0);
+                launch_reduce_sweep(R->n_cl, R->d_cl_mono, R->d_res, R->d_cl, R->d_hist, x.d_ctrl, s);
                 cur ^= 1;
                 ++issued;
             }
-            if ((st = sync_ctrl(c)) != MCPT_OK) return st;
+            if ((st = sync_ctrl(x)) != MCPT_OK) return st;
             if (h.done) break;
         }
         if (prec == MCPT_FP64) n_hi = h.sweeps;
@@ -752,45 +796,45 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
         // `inner` reduced-precision sweeps solve delta = r + L(delta); then T += delta.
         auto fp64_sweep = [&]() {
             hipEvent_t a = nullptr;
-            record_begin(c, &a);
-            pair_phase(c, R, R->d_G[cur], 1, c->d_ctrl);
-            record_end(c, a, 0, fl_sweep, vb);
-            mixed_mono(c, R, kMonoUpdateR, R->d_G[cur], R->d_G[cur ^ 1], false, c->d_ctrl);
-            launch_reduce_sweep(R->n_cl, R->d_cl_mono, R->d_res, R->d_cl, R->d_hist, c->d_ctrl, s);
+            record_begin(x, &a);
+            pair_phase(c, x, R, R->d_G[cur], 1, x.d_ctrl);
+            record_end(x, a, 0, fl_sweep, vb);
+            mixed_mono(c, x, R, kMonoUpdateR, R->d_G[cur], R->d_G[cur ^ 1], false, x.d_ctrl);
+            launch_reduce_sweep(R->n_cl, R->d_cl_mono, R->d_res, R->d_cl, R->d_hist, x.d_ctrl, s);
             cur ^= 1;
         };
         auto correction = [&]() {
-            mixed_mono(c, R, kMonoRlo, nullptr, nullptr, true, nullptr);
+            mixed_mono(c, x, R, kMonoRlo, nullptr, nullptr, true, nullptr);
             for (int k = 0; k < inner; ++k) {
                 hipEvent_t a = nullptr;
-                record_begin(c, &a);
-                lowp_phase(c, R, R->d_G[cur], 0);
-                record_end(c, a, 2, fl_sweep, R->lo_v_bytes);
-                mixed_mono(c, R, kMonoCorr, R->d_G[cur], R->d_G[cur ^ 1], true, nullptr);
+                record_begin(x, &a);
+                lowp_phase(c, x, R, R->d_G[cur], 0);
+                record_end(x, a, 2, fl_sweep, R->lo_v_bytes);
+                mixed_mono(c, x, R, kMonoCorr, R->d_G[cur], R->d_G[cur ^ 1], true, nullptr);
                 cur ^= 1;
             }
-            mixed_mono(c, R, kMonoApply, nullptr, nullptr, false, nullptr);
-            mixed_mono(c, R, kMonoFromT, nullptr, nullptr, false, nullptr);
+            mixed_mono(c, x, R, kMonoApply, nullptr, nullptr, false, nullptr);
+            mixed_mono(c, x, R, kMonoFromT, nullptr, nullptr, false, nullptr);
         };
         for (int k = 0; k < n_pre; ++k) {   // a few plain reduced-precision sweeps first
             hipEvent_t a = nullptr;
-            record_begin(c, &a);
-            lowp_phase(c, R, R->d_G[cur], 1);
-            record_end(c, a, 2, fl_sweep, R->lo_v_bytes);
-            mixed_mono(c, R, kMonoUpdate, R->d_G[cur], R->d_G[cur ^ 1], true, nullptr);
+            record_begin(x, &a);
+            lowp_phase(c, x, R, R->d_G[cur], 1);
+            record_end(x, a, 2, fl_sweep, R->lo_v_bytes);
+            mixed_mono(c, x, R, kMonoUpdate, R->d_G[cur], R->d_G[cur ^ 1], true, nullptr);
             cur ^= 1;
         }
         fp64_sweep();
-        if ((st = sync_ctrl(c)) != MCPT_OK) return st;
+        if ((st = sync_ctrl(x)) != MCPT_OK) return st;
         if (o->graph && !h.done) {
             // one body = correction + FP64 sweep; bodies per graph chosen so that a replay
             // returns the G double buffer to the parity it started from
             int gb = every;
             if ((gb * (inner + 1)) % 2) gb *= 2;
-            const std::array<int64_t, 6> key{(int64_t)(uintptr_t)c->d_scratch, (int64_t)(uintptr_t)c->d_scratch_lo,
-                                             (int64_t)(uintptr_t)c->d_ctrl, c->scratch_slot,
+            const std::array<int64_t, 6> key{(int64_t)(uintptr_t)x.d_scratch, (int64_t)(uintptr_t)x.d_scratch_lo,
+                                             (int64_t)(uintptr_t)x.d_ctrl, x.scratch_slot,
                                              (int64_t)c->grid_lds * 1000000 + c->grid_glb,
-                                             (int64_t)c->grid_lo * 1000 + inner};
+                                             (int64_t)x.grid_lo * 1000 + inner};
             const int gprec = 16 + prec;
             if (!R->graph || R->graph_prec != gprec || R->graph_sweeps != gb || R->graph_key != key ||
                 R->graph_parity != cur) {
@@ -818,20 +862,20 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
             }
             while (!h.done) {
                 HIP_TRY(hipGraphLaunch(R->graph, s));
-                if ((st = sync_ctrl(c)) != MCPT_OK) return st;
+                if ((st = sync_ctrl(x)) != MCPT_OK) return st;
             }
         }
         while (!h.done) {
             correction();
             fp64_sweep();
-            if ((st = sync_ctrl(c)) != MCPT_OK) return st;
+            if ((st = sync_ctrl(x)) != MCPT_OK) return st;
         }
         n_hi = h.sweeps;
         n_lo = n_pre + inner * (n_hi - 1);
     }
     if (h.status == MCPT_ERR_DIVERGED && R->n_cl == 1) {
-        if (c->timing.on) drain_timing(c->timing);
-        c->timing.on = saved_timing;
+        if (x.timing.on) drain_timing(x.timing);
+        x.timing.on = saved_timing;
         mcpt_summary sm{};
         sm.residual = h.residual;
         sm.sweeps = n_lo + n_hi;
@@ -845,14 +889,14 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
     // energies of the returned amplitudes: FP64 Tau recomputed from the final T
     {
         hipEvent_t a = nullptr;
-        record_begin(c, &a);
-        pair_phase(c, R, R->d_G[cur], 0, nullptr);
-        record_end(c, a, 0, fl_final, vb);
+        record_begin(x, &a);
+        pair_phase(c, x, R, R->d_G[cur], 0, nullptr);
+        record_end(x, a, 0, fl_final, vb);
     }
-    launch_reduce_final(R->n_cl, R->d_cl_mono, R->d_cl_pair, R->d_em2, R->d_em2_0, R->d_ed2, R->d_cl, c->d_ctrl, s);
-    if ((st = sync_ctrl(c)) != MCPT_OK) return st;
-    if (c->timing.on) drain_timing(c->timing);
-    c->timing.on = saved_timing;
+    launch_reduce_final(R->n_cl, R->d_cl_mono, R->d_cl_pair, R->d_em2, R->d_em2_0, R->d_ed2, R->d_cl, x.d_ctrl, s);
+    if ((st = sync_ctrl(x)) != MCPT_OK) return st;
+    if (x.timing.on) drain_timing(x.timing);
+    x.timing.on = saved_timing;
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     {
         std::vector<ClState> cs(R->n_cl);
@@ -901,6 +945,22 @@ mcpt_status run(mcpt_ctx* c, Resident* R, const mcpt_options* o, mcpt_summary* o
     return MCPT_OK;
 }
 
+}  // namespace mcpt
+
+using namespace mcpt;
+
+namespace {
+
+// A caller-visible resident problem (served batches are reached through their tickets).
+Resident* find_resident(mcpt_ctx* c, uint64_t id) {
+    std::lock_guard<std::mutex> g(c->mu);
+    auto it = c->res.find(id);
+    if (it == c->res.end() || it->second->internal) return nullptr;
+    return it->second.get();
+}
+
+mcpt_status unknown(uint64_t id) { return fail(MCPT_ERR_UNKNOWN_ID, "unknown problem id " + std::to_string(id)); }
+
 }  // namespace
 
 extern "C" {
@@ -917,15 +977,16 @@ mcpt_status mcpt_create(int device, size_t hbm_budget_bytes, mcpt_ctx** out) {
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, device));
     c->n_cu = prop.multiProcessorCount;
-    HIP_TRY(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
-    c->stream = c->own;
+    c->grid_lds = std::max(8, c->n_cu * pair_fp64_blocks_per_cu(1) / 8 * 8);
+    c->grid_glb = std::max(8, c->n_cu * pair_fp64_blocks_per_cu(0) / 8 * 8);
     size_t free_b = 0, total_b = 0;
     HIP_TRY(hipMemGetInfo(&free_b, &total_b));
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
-    HIP_TRY(hipMalloc(&c->d_ctrl, sizeof(Ctrl)));
-    HIP_TRY(hipHostMalloc(&c->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
-    HIP_TRY(hipMalloc(&c->d_flag, sizeof(int32_t)));
-    HIP_TRY(hipHostMalloc(&c->h_flag, sizeof(int32_t), hipHostMallocDefault));
+    mcpt_status st = exec_init(c.get(), c->main);
+    if (st != MCPT_OK) {
+        exec_free(c.get(), c->main);
+        return st;
+    }
     g_err.clear();
     *out = c.release();
     return MCPT_OK;
@@ -933,19 +994,12 @@ mcpt_status mcpt_create(int device, size_t hbm_budget_bytes, mcpt_ctx** out) {
 
 void mcpt_destroy(mcpt_ctx* c) {
     if (!c) return;
+    serve_stop(c);
     (void)hipSetDevice(c->device);
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->main.stream) (void)hipStreamSynchronize(c->main.stream);
     for (auto& kv : c->res) free_resident(c, kv.second.get());
     c->res.clear();
-    if (c->timing.on) drain_timing(c->timing);
-    for (hipEvent_t e : c->timing.pool) (void)hipEventDestroy(e);
-    if (c->d_scratch) (void)hipFree(c->d_scratch);
-    if (c->d_scratch_lo) (void)hipFree(c->d_scratch_lo);
-    if (c->d_ctrl) (void)hipFree(c->d_ctrl);
-    if (c->d_flag) (void)hipFree(c->d_flag);
-    if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
-    if (c->h_flag) (void)hipHostFree(c->h_flag);
-    if (c->own) (void)hipStreamDestroy(c->own);
+    exec_free(c, c->main);
     delete c;
 }
 
@@ -953,15 +1007,15 @@ const char* mcpt_last_error(void) { return g_err.c_str(); }
 
 mcpt_status mcpt_set_stream(mcpt_ctx* c, void* hip_stream) {
     if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    c->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->own;
+    HIP_TRY(hipStreamSynchronize(c->main.stream));
+    c->main.stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->main.own;
     return MCPT_OK;
 }
 
 mcpt_status mcpt_upload(mcpt_ctx* c, const mcpt_problem* prob, uint64_t* id) {
     if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
     try {
-        return upload_batch(c, prob, 1, id);
+        return upload_batch(c, c->main, prob, 1, false, id);
     } catch (const std::exception& e) {
         return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
     }
@@ -970,7 +1024,7 @@ mcpt_status mcpt_upload(mcpt_ctx* c, const mcpt_problem* prob, uint64_t* id) {
 mcpt_status mcpt_upload_batch(mcpt_ctx* c, const mcpt_problem* probs, int32_t n, uint64_t* id) {
     if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
     try {
-        return upload_batch(c, probs, n, id);
+        return upload_batch(c, c->main, probs, n, false, id);
     } catch (const std::exception& e) {
         return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
     }
@@ -978,9 +1032,8 @@ mcpt_status mcpt_upload_batch(mcpt_ctx* c, const mcpt_problem* probs, int32_t n,
 
 mcpt_status mcpt_cluster_results(mcpt_ctx* c, uint64_t id, int32_t n, mcpt_summary* out) {
     if (!c || !out) return fail(MCPT_ERR_INVALID, "ctx or out is NULL");
-    auto it = c->res.find(id);
-    if (it == c->res.end()) return fail(MCPT_ERR_UNKNOWN_ID, "unknown problem id " + std::to_string(id));
-    Resident* R = it->second.get();
+    Resident* R = find_resident(c, id);
+    if (!R) return unknown(id);
     if (n != R->n_cl) return fail(MCPT_ERR_INVALID, "problem holds " + std::to_string(R->n_cl) + " clusters");
     if (!R->has_result) return fail(MCPT_ERR_INVALID, "problem has no result (not run, or diverged)");
     for (int q = 0; q < n; ++q) out[q] = R->cl_last[q];
@@ -996,16 +1049,20 @@ mcpt_status mcpt_solve_batch(mcpt_ctx* c, const mcpt_problem* probs, int32_t n, 
     if (st != MCPT_OK) return st;
     if (id) *id = local;
     st = mcpt_run(c, local, opts, nullptr);
-    if (per_cluster && c->res[local]->has_result) mcpt_cluster_results(c, local, n, per_cluster);
+    if (per_cluster) {
+        Resident* R = find_resident(c, local);
+        if (R && R->has_result)
+            for (int q = 0; q < n; ++q) per_cluster[q] = R->cl_last[q];
+    }
     return st;
 }
 
 mcpt_status mcpt_run(mcpt_ctx* c, uint64_t id, const mcpt_options* opts, mcpt_summary* out) {
     if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
-    auto it = c->res.find(id);
-    if (it == c->res.end()) return fail(MCPT_ERR_UNKNOWN_ID, "unknown problem id " + std::to_string(id));
+    Resident* R = find_resident(c, id);
+    if (!R) return unknown(id);
     try {
-        return run(c, it->second.get(), opts, out);
+        return run(c, c->main, R, opts, out);
     } catch (const std::exception& e) {
         return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
     }
@@ -1024,56 +1081,36 @@ mcpt_status mcpt_solve(mcpt_ctx* c, const mcpt_problem* prob, const mcpt_options
 
 mcpt_status mcpt_energy(mcpt_ctx* c, uint64_t id, double* e_m2, double* de_m2, double* e_d2, double* t_amp) {
     if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
-    auto it = c->res.find(id);
-    if (it == c->res.end()) return fail(MCPT_ERR_UNKNOWN_ID, "unknown problem id " + std::to_string(id));
-    Resident* R = it->second.get();
-    if (!R->has_result) return fail(MCPT_ERR_INVALID, "problem has no result (not run, or diverged)");
-    mcpt_status st = ensure_device(c);
-    if (st != MCPT_OK) return st;
-    hipStream_t s = c->stream;
-    std::vector<double> a(R->n_mono), b(R->n_mono);
-    HIP_TRY(hipMemcpyAsync(a.data(), R->d_em2, R->n_mono * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(b.data(), R->d_em2_0, R->n_mono * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (e_d2 && R->n_pair)
-        HIP_TRY(hipMemcpyAsync(e_d2, R->d_ed2, R->n_pair * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (t_amp) {
-        launch_unpack(R->d_monos, R->n_mono, R->d_T, R->d_raw, R->max_n, s);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(t_amp, R->d_raw, R->raw_elems * sizeof(double), hipMemcpyDeviceToHost, s));
-    }
-    HIP_TRY(hipStreamSynchronize(s));
-    for (int x = 0; x < R->n_mono; ++x) {
-        if (e_m2) e_m2[x] = a[x];
-        if (de_m2) de_m2[x] = a[x] - b[x];
-    }
-    return MCPT_OK;
+    if (serve_owns(c, id)) return serve_energy(c, id, e_m2, de_m2, e_d2, t_amp);
+    Resident* R = find_resident(c, id);
+    if (!R) return unknown(id);
+    return slice_results(c, c->main, R, -1, e_m2, de_m2, e_d2, t_amp);
 }
 
 mcpt_status mcpt_release(mcpt_ctx* c, uint64_t id) {
     if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
-    auto it = c->res.find(id);
-    if (it == c->res.end()) return fail(MCPT_ERR_UNKNOWN_ID, "unknown problem id " + std::to_string(id));
+    if (serve_owns(c, id)) return serve_release(c, id);
+    if (!find_resident(c, id)) return unknown(id);
     (void)hipSetDevice(c->device);
-    (void)hipStreamSynchronize(c->stream);
-    free_resident(c, it->second.get());
-    c->res.erase(it);
+    (void)hipStreamSynchronize(c->main.stream);
+    release_resident(c, id);
     return MCPT_OK;
 }
 
 mcpt_status mcpt_set_timing(mcpt_ctx* c, int enable) {
     if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    drain_timing(c->timing);
-    c->timing.on = enable != 0;
-    c->timing.tot = mcpt_timing{};
+    HIP_TRY(hipStreamSynchronize(c->main.stream));
+    drain_timing(c->main.timing);
+    c->main.timing.on = enable != 0;
+    c->main.timing.tot = mcpt_timing{};
     return MCPT_OK;
 }
 
 mcpt_status mcpt_timing_read(mcpt_ctx* c, mcpt_timing* out) {
     if (!c || !out) return fail(MCPT_ERR_INVALID, "ctx or out is NULL");
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    drain_timing(c->timing);
-    *out = c->timing.tot;
+    HIP_TRY(hipStreamSynchronize(c->main.stream));
+    drain_timing(c->main.timing);
+    *out = c->main.timing.tot;
     return MCPT_OK;
 }
 

@@ -1,0 +1,174 @@
+// Host runtime of libmcpt (not part of the C ABI): resident problems, the
+// per-stream execution resources, the context, and the serving scheduler's
+// request table.
+//
+// Threading: every field of mcpt_ctx marked "mu" is read and written under
+// ctx->mu.  A resident problem is used by one thread at a time: the client
+// thread for problems it uploaded, one serving worker for a served batch.
+#pragma once
+
+#include <array>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/mcpt.h"
+#include "mcpt_internal.hpp"
+
+namespace mcpt {
+
+struct Resident {
+    uint64_t id = 0;
+    int n_mono = 0;
+    int64_t n_pair = 0;
+    int max_n = 0, max_np = 0;
+    int64_t eps_elems = 0, dif_elems = 0, raw_elems = 0, mat_elems = 0, v_elems = 0, max_slot = 0;
+    std::vector<MonoDesc> monos;
+    std::vector<PairDesc> pairs;      // LDS-variant pairs, then the others; each range sorted by
+                                      // monomer for locality; .orig is the caller's index
+    int64_t n_lds = 0;                // pairs served by the LDS-resident-V kernel
+    // device
+    MonoDesc* d_monos = nullptr;
+    PairDesc* d_pairs = nullptr;
+    double *d_dif = nullptr, *d_raw = nullptr, *d_K = nullptr, *d_T = nullptr, *d_M = nullptr;
+    double *d_G[2] = {nullptr, nullptr};
+    double* d_V = nullptr;
+    double *d_em2 = nullptr, *d_em2_0 = nullptr, *d_ed2 = nullptr, *d_res = nullptr;
+    // clusters of a batch: monomer and pair ranges (caller order), per-cluster state and history
+    int n_cl = 1;
+    std::vector<int64_t> cl_mono, cl_pair;
+    int64_t *d_cl_mono = nullptr, *d_cl_pair = nullptr;
+    ClState* d_cl = nullptr;
+    double* d_hist = nullptr;
+    std::vector<mcpt_summary> cl_last;
+    std::vector<void*> allocations;
+    size_t bytes = 0;
+    bool has_result = false;
+    mcpt_summary last{};
+    // reduced-precision copies (mixed-precision form), made on first use of a precision
+    int lo_prec = 0;
+    void *d_Vlo = nullptr, *d_Mlo = nullptr;
+    int64_t *d_lo_off = nullptr, *d_mlo_off = nullptr;
+    double *d_R = nullptr, *d_Dl = nullptr;
+    int64_t lo_slot = 0;          // elements of one low-precision Tau + Tau^T scratch slot
+    double lo_v_bytes = 0.0;      // bytes of the low-precision V and V^T
+    std::vector<void*> lo_allocations;
+    size_t lo_bytes = 0;
+    // captured sweep graph: valid for one form, one execution resource set and one body count
+    hipGraphExec_t graph = nullptr;
+    int graph_prec = -1, graph_sweeps = 0, graph_parity = 0;
+    std::array<int64_t, 6> graph_key{};   // buffers and grids baked into the captured launches
+    // served batches: owned by the scheduler, never visible to the caller under this id
+    bool internal = false;
+    int refs = 0;                 // tickets still holding this batch's results
+};
+
+struct Timing {
+    bool on = false;
+    struct Rec {
+        hipEvent_t a, b;
+        int kind;   // 0 FP64 pair phase, 1 monomer phase, 2 reduced-precision pair phase
+        double flops, vbytes;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    mcpt_timing tot{};
+};
+
+// What one stream needs to run solves independently of other streams: the
+// control word (device + pinned host copy), the flag used by input checks, and
+// the per-workgroup Tau scratch of the pair kernels.
+struct Exec {
+    hipStream_t stream = nullptr;
+    hipStream_t own = nullptr;
+    Ctrl* d_ctrl = nullptr;
+    Ctrl* h_ctrl = nullptr;             // pinned
+    int32_t* d_flag = nullptr;
+    int32_t* h_flag = nullptr;          // pinned
+    double* d_scratch = nullptr;        // FP64 Tau, one slot per workgroup
+    int64_t scratch_slot = 0;
+    int scratch_slots = 0;
+    void* d_scratch_lo = nullptr;       // reduced-precision Tau and Tau^T
+    size_t scratch_lo_bytes = 0;
+    int grid_lo = 0;
+    Timing timing;
+    size_t reserved = 0;                // HBM reserved by admission for the upload in progress (mu)
+};
+
+// One served request: inputs copied at submission, then its place in a batch.
+struct Request {
+    uint64_t ticket = 0;
+    int state = 0;                      // 0 queued, 1 running, 2 done
+    std::vector<int32_t> n_occ, n_vir, pair;
+    std::vector<double> eps, k_intra, v_dimer, warm_t;
+    mcpt_problem prob{};                // points into the vectors above
+    mcpt_options opts{};
+    size_t footprint = 0;               // device bytes of the request alone
+    double t_submit = 0.0;              // steady-clock seconds
+    mcpt_summary sum{};
+    uint64_t batch = 0;                 // internal resident id of the batch once run
+    int cluster = 0;                    // index of the request in that batch
+    std::string error;                  // message of a failed request
+};
+
+struct ServeParams {
+    int workers = 4;                    // concurrent streams, each running one batch at a time
+    int max_batch = 32;                 // requests fused into one batch
+    int64_t max_batch_pairs = 1 << 20;  // pair budget of one batch
+};
+
+struct Server {
+    ServeParams params;
+    std::deque<uint64_t> queue;         // queued tickets in arrival order (mu)
+    std::map<uint64_t, std::unique_ptr<Request>> reqs;   // every live ticket (mu)
+    std::vector<std::thread> workers;
+    std::vector<std::unique_ptr<Exec>> execs;
+    std::condition_variable cv;         // queue, memory or stop changed
+    std::condition_variable done_cv;    // a request finished
+    bool stop = false;
+    int busy = 0;                       // workers running a batch (mu)
+    uint64_t batches = 0, served = 0;   // counters (mu)
+};
+
+}  // namespace mcpt
+
+struct mcpt_ctx {
+    int device = 0;
+    int n_cu = 0;
+    std::mutex mu;
+    size_t budget = 0, in_use = 0;      // mu
+    size_t reserved = 0;                // sum of Exec::reserved (mu)
+    uint64_t next_id = 1;               // mu
+    std::map<uint64_t, std::unique_ptr<mcpt::Resident>> res;   // mu
+    int grid_lds = 0, grid_glb = 0;     // persistent grids of the two FP64 pair-kernel variants
+    mcpt::Exec main;                    // the caller's stream (mcpt_run, mcpt_energy, ...)
+    std::unique_ptr<mcpt::Server> server;
+};
+
+namespace mcpt {
+
+// shared between the solver runtime and the serving scheduler
+mcpt_status fail(mcpt_status s, const std::string& msg);
+const std::string& last_error_text();
+mcpt_status exec_init(mcpt_ctx* c, Exec& x);
+void exec_free(mcpt_ctx* c, Exec& x);
+mcpt_status validate_problem(const mcpt_problem* pb);
+mcpt_status validate_options(const mcpt_options* o);
+size_t footprint(const mcpt_problem* pbs, int n, int precision);
+mcpt_status upload_batch(mcpt_ctx* c, Exec& x, const mcpt_problem* pbs, int n_cl, bool internal, uint64_t* id);
+mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_summary* out);
+void release_resident(mcpt_ctx* c, uint64_t id);   // takes mu itself
+mcpt_status slice_results(mcpt_ctx* c, Exec& x, Resident* R, int q, double* e_m2, double* de_m2, double* e_d2,
+                          double* t_amp);
+void serve_stop(mcpt_ctx* c);
+bool serve_owns(mcpt_ctx* c, uint64_t ticket);
+mcpt_status serve_energy(mcpt_ctx* c, uint64_t ticket, double* e_m2, double* de_m2, double* e_d2, double* t_amp);
+mcpt_status serve_release(mcpt_ctx* c, uint64_t ticket);
+
+}  // namespace mcpt

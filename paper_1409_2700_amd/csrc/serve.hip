@@ -1,0 +1,405 @@
+// Serving: MCPT(2) solves submitted as independent requests (clusters of
+// different sizes, displaced geometries) and run by a pool of worker streams.
+//
+// Scheduling.  A worker that is free takes the request at the head of the
+// queue if its device footprint fits next to what is resident and reserved,
+// then fuses into the same batch the later queued requests that share its
+// options and size class and still fit (at most max_batch requests and
+// max_batch_pairs pairs).  The batch is uploaded as one resident problem with
+// one cluster per request and solved with per-cluster stopping, so each
+// request's result is the one its own solve gives.  Requests that arrive while
+// batches run are taken by the next free worker: the workers' streams run
+// concurrently, so batches overlap on the device, and a request never waits
+// for the whole queue to drain.  Results stay resident on the device until the
+// ticket is released; the memory they hold counts against the admission budget.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "runtime.hpp"
+
+namespace mcpt {
+
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+bool same_options(const mcpt_options& a, const mcpt_options& b) {
+    return a.tol == b.tol && a.max_sweeps == b.max_sweeps && a.precision == b.precision && a.polish == b.polish &&
+           a.check_every == b.check_every && a.inner_sweeps == b.inner_sweeps && a.graph == b.graph &&
+           !a.warm_t && !b.warm_t;
+}
+
+// log2 of the pair-phase flops of one sweep: requests within one class of the
+// batch head are fused, so a batch is not held back by a much larger member
+int size_class(const mcpt_problem& p) {
+    double f = 0.0;
+    for (int64_t k = 0; k < p.n_pair; ++k) {
+        const double nx = (double)p.n_occ[p.pair[2 * k]] * p.n_vir[p.pair[2 * k]];
+        const double ny = (double)p.n_occ[p.pair[2 * k + 1]] * p.n_vir[p.pair[2 * k + 1]];
+        f += 4.0 * nx * ny * (nx + ny);
+    }
+    return f > 1.0 ? (int)std::floor(std::log2(f)) : 0;
+}
+
+bool head_fits(mcpt_ctx* c, Server& S) {
+    if (S.queue.empty()) return false;
+    const Request* h = S.reqs[S.queue.front()].get();
+    return c->in_use + c->reserved + h->footprint <= c->budget;
+}
+
+void worker_loop(mcpt_ctx* c, int w) {
+    Server& S = *c->server;
+    Exec& x = *S.execs[w];
+    (void)hipSetDevice(c->device);
+    std::unique_lock<std::mutex> lk(c->mu);
+    for (;;) {
+        S.cv.wait(lk, [&] { return S.stop || head_fits(c, S); });
+        if (S.stop) break;
+        // ---- form a batch: the head, then compatible queued requests that fit ----
+        std::vector<Request*> group;
+        size_t reserve = 0;
+        int64_t pairs = 0;
+        Request* head = S.reqs[S.queue.front()].get();
+        const int cls0 = size_class(head->prob);
+        for (auto it = S.queue.begin(); it != S.queue.end();) {
+            Request* r = S.reqs[*it].get();
+            const bool first = group.empty();
+            if (!first && ((int)group.size() >= S.params.max_batch || !same_options(r->opts, head->opts) ||
+                           std::abs(size_class(r->prob) - cls0) > 1 ||
+                           pairs + r->prob.n_pair > S.params.max_batch_pairs)) {
+                ++it;
+                continue;
+            }
+            if (!first && c->in_use + c->reserved + reserve + r->footprint > c->budget) break;
+            group.push_back(r);
+            reserve += r->footprint;
+            pairs += r->prob.n_pair;
+            r->state = 1;
+            it = S.queue.erase(it);
+            if (head->opts.warm_t) break;   // a warm start runs alone
+        }
+        x.reserved = reserve;
+        c->reserved += reserve;
+        ++S.busy;
+        lk.unlock();
+
+        // ---- upload and solve the batch on this worker's stream ----
+        std::vector<mcpt_problem> probs;
+        probs.reserve(group.size());
+        for (Request* r : group) probs.push_back(r->prob);
+        mcpt_options opts = head->opts;
+        uint64_t bid = 0;
+        mcpt_summary sm{};
+        mcpt_status st = MCPT_OK;
+        Resident* R = nullptr;
+        std::string err;
+        try {
+            st = upload_batch(c, x, probs.data(), (int)probs.size(), true, &bid);
+            for (Request* r : group) {   // the device holds the inputs now
+                std::vector<double>().swap(r->k_intra);
+                std::vector<double>().swap(r->v_dimer);
+                r->prob.k_intra = r->prob.v_dimer = nullptr;
+            }
+            if (st == MCPT_OK) {
+                {
+                    std::lock_guard<std::mutex> g(c->mu);
+                    R = c->res[bid].get();
+                }
+                st = run(c, x, R, &opts, &sm);
+            }
+        } catch (const std::exception& e) {
+            st = fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
+        }
+        if (st != MCPT_OK) err = last_error_text();
+        const bool results = R && R->has_result;
+        const double t_done = now_s();
+
+        lk.lock();
+        c->reserved -= std::min(c->reserved, x.reserved);
+        x.reserved = 0;
+        int holders = 0;
+        for (size_t q = 0; q < group.size(); ++q) {
+            Request* r = group[q];
+            if (results) {
+                r->sum = R->cl_last[q];
+                r->batch = bid;
+                r->cluster = (int)q;
+                if (r->sum.status == MCPT_ERR_DIVERGED) r->batch = 0;
+                else ++holders;
+            } else {
+                r->sum = sm;
+                r->sum.status = st == MCPT_OK ? MCPT_ERR_DEVICE : st;
+                r->batch = 0;
+            }
+            if (r->sum.status != MCPT_OK) r->error = err.empty() ? "request did not converge" : err;
+            r->sum.seconds = t_done - r->t_submit;   // latency: submission to result
+            r->state = 2;
+        }
+        if (R) R->refs = holders;
+        --S.busy;
+        ++S.batches;
+        S.served += group.size();
+        const bool drop = R && holders == 0;
+        if (drop) {   // nothing to keep: free the batch now
+            lk.unlock();
+            release_resident(c, bid);
+            lk.lock();
+        }
+        S.done_cv.notify_all();
+        S.cv.notify_all();
+    }
+}
+
+// Host-side checks of a submitted problem: everything upload would check,
+// so that a bad request fails at submission and never inside a shared batch.
+mcpt_status check_request(const mcpt_problem* pb) {
+    mcpt_status st = validate_problem(pb);
+    if (st != MCPT_OK) return st;
+    if (pb->memory != MCPT_HOST) return fail(MCPT_ERR_INVALID, "served requests take host memory");
+    int64_t e = 0, k = 0, v = 0;
+    for (int x = 0; x < pb->n_mono; ++x) {
+        const int o = pb->n_occ[x], nv = pb->n_vir[x];
+        double omax = -INFINITY, vmin = INFINITY;
+        for (int i = 0; i < o + nv; ++i) {
+            const double ei = pb->eps[e + i];
+            if (!std::isfinite(ei)) return fail(MCPT_ERR_NONFINITE, "non-finite orbital energy");
+            if (i < o) omax = std::max(omax, ei);
+            else vmin = std::min(vmin, ei);
+        }
+        if (!(omax < vmin))
+            return fail(MCPT_ERR_INVALID, "monomer " + std::to_string(x) +
+                                              ": max occupied energy >= min virtual energy (denominator >= 0)");
+        e += o + nv;
+        k += (int64_t)o * o * nv * nv;
+    }
+    for (int64_t p = 0; p < pb->n_pair; ++p) {
+        const int x = pb->pair[2 * p], y = pb->pair[2 * p + 1];
+        v += (int64_t)pb->n_occ[x] * pb->n_vir[x] * pb->n_occ[y] * pb->n_vir[y];
+    }
+    for (int64_t i = 0; i < k; ++i)
+        if (!std::isfinite(pb->k_intra[i])) return fail(MCPT_ERR_NONFINITE, "non-finite value in k_intra");
+    for (int64_t i = 0; i < v; ++i)
+        if (!std::isfinite(pb->v_dimer[i])) return fail(MCPT_ERR_NONFINITE, "non-finite value in v_dimer");
+    return MCPT_OK;
+}
+
+mcpt_status start_server(mcpt_ctx* c) {
+    Server& S = *c->server;
+    if (!S.workers.empty()) return MCPT_OK;
+    for (int w = 0; w < S.params.workers; ++w) {
+        auto x = std::make_unique<Exec>();
+        mcpt_status st = exec_init(c, *x);
+        if (st != MCPT_OK) {
+            exec_free(c, *x);
+            return st;
+        }
+        S.execs.push_back(std::move(x));
+    }
+    for (int w = 0; w < S.params.workers; ++w) S.workers.emplace_back(worker_loop, c, w);
+    return MCPT_OK;
+}
+
+Server& server_of(mcpt_ctx* c) {
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!c->server) c->server = std::make_unique<Server>();
+    return *c->server;
+}
+
+}  // namespace
+
+void serve_stop(mcpt_ctx* c) {
+    if (!c->server) return;
+    Server& S = *c->server;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        S.stop = true;
+        for (uint64_t t : S.queue) {
+            Request* r = S.reqs[t].get();
+            r->state = 2;
+            r->sum.status = MCPT_ERR_INVALID;
+            r->error = "context destroyed before the request ran";
+        }
+        S.queue.clear();
+        S.cv.notify_all();
+        S.done_cv.notify_all();
+    }
+    for (auto& t : S.workers) t.join();
+    S.workers.clear();
+    for (auto& x : S.execs) exec_free(c, *x);
+    S.execs.clear();
+}
+
+bool serve_owns(mcpt_ctx* c, uint64_t ticket) {
+    std::lock_guard<std::mutex> g(c->mu);
+    return c->server && c->server->reqs.count(ticket) != 0;
+}
+
+mcpt_status serve_energy(mcpt_ctx* c, uint64_t ticket, double* e_m2, double* de_m2, double* e_d2, double* t_amp) {
+    Resident* R = nullptr;
+    int q = 0;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        auto it = c->server->reqs.find(ticket);
+        if (it == c->server->reqs.end()) return fail(MCPT_ERR_UNKNOWN_ID, "unknown ticket");
+        Request* r = it->second.get();
+        if (r->state != 2) return fail(MCPT_PENDING, "request is still queued or running");
+        if (!r->batch) return fail(MCPT_ERR_INVALID, "request has no result: " + r->error);
+        R = c->res[r->batch].get();
+        q = r->cluster;
+    }
+    return slice_results(c, c->main, R, q, e_m2, de_m2, e_d2, t_amp);
+}
+
+mcpt_status serve_release(mcpt_ctx* c, uint64_t ticket) {
+    uint64_t drop = 0;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        Server& S = *c->server;
+        auto it = S.reqs.find(ticket);
+        if (it == S.reqs.end()) return fail(MCPT_ERR_UNKNOWN_ID, "unknown ticket");
+        Request* r = it->second.get();
+        if (r->state == 1) return fail(MCPT_PENDING, "request is running; release it once it is done");
+        if (r->state == 0) S.queue.erase(std::find(S.queue.begin(), S.queue.end(), ticket));
+        if (r->state == 2 && r->batch) {
+            Resident* R = c->res[r->batch].get();
+            if (--R->refs == 0) drop = r->batch;
+        }
+        S.reqs.erase(it);
+    }
+    if (drop) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->main.stream);
+        release_resident(c, drop);
+    }
+    std::lock_guard<std::mutex> g(c->mu);
+    c->server->cv.notify_all();   // memory or the queue head changed
+    return MCPT_OK;
+}
+
+}  // namespace mcpt
+
+using namespace mcpt;
+
+extern "C" {
+
+mcpt_status mcpt_serve_config(mcpt_ctx* c, int32_t workers, int32_t max_batch, int64_t max_batch_pairs) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    if (workers < 1 || workers > 16) return fail(MCPT_ERR_INVALID, "workers must be in [1, 16]");
+    if (max_batch < 1 || max_batch > 4096) return fail(MCPT_ERR_INVALID, "max_batch must be in [1, 4096]");
+    if (max_batch_pairs < 1) return fail(MCPT_ERR_INVALID, "max_batch_pairs must be >= 1");
+    Server& S = server_of(c);
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!S.workers.empty()) return fail(MCPT_ERR_INVALID, "the scheduler is already running");
+    S.params.workers = workers;
+    S.params.max_batch = max_batch;
+    S.params.max_batch_pairs = max_batch_pairs;
+    return MCPT_OK;
+}
+
+mcpt_status mcpt_submit(mcpt_ctx* c, const mcpt_problem* prob, const mcpt_options* opts, uint64_t* ticket) {
+    if (!c || !ticket) return fail(MCPT_ERR_INVALID, "ctx or ticket is NULL");
+    mcpt_status st = validate_options(opts);
+    if (st != MCPT_OK) return st;
+    if ((st = check_request(prob)) != MCPT_OK) return st;
+    try {
+        auto r = std::make_unique<Request>();
+        const mcpt_problem& p = *prob;
+        int64_t ne = 0, nk = 0, nv = 0;
+        for (int x = 0; x < p.n_mono; ++x) {
+            ne += p.n_occ[x] + p.n_vir[x];
+            nk += (int64_t)p.n_occ[x] * p.n_occ[x] * p.n_vir[x] * p.n_vir[x];
+        }
+        for (int64_t k = 0; k < p.n_pair; ++k) {
+            const int x = p.pair[2 * k], y = p.pair[2 * k + 1];
+            nv += (int64_t)p.n_occ[x] * p.n_vir[x] * p.n_occ[y] * p.n_vir[y];
+        }
+        r->n_occ.assign(p.n_occ, p.n_occ + p.n_mono);
+        r->n_vir.assign(p.n_vir, p.n_vir + p.n_mono);
+        r->pair.assign(p.pair ? p.pair : nullptr, p.pair ? p.pair + 2 * p.n_pair : nullptr);
+        r->eps.assign(p.eps, p.eps + ne);
+        r->k_intra.assign(p.k_intra, p.k_intra + nk);
+        if (nv) r->v_dimer.assign(p.v_dimer, p.v_dimer + nv);
+        int64_t nt = 0;
+        for (int x = 0; x < p.n_mono; ++x) nt += (int64_t)p.n_occ[x] * p.n_vir[x] * p.n_occ[x] * p.n_vir[x];
+        if (opts->warm_t) r->warm_t.assign(opts->warm_t, opts->warm_t + nt);
+        r->prob = mcpt_problem{p.n_mono, r->n_occ.data(), r->n_vir.data(), r->eps.data(), r->k_intra.data(),
+                               p.n_pair, r->pair.empty() ? nullptr : r->pair.data(),
+                               r->v_dimer.empty() ? nullptr : r->v_dimer.data(), MCPT_HOST};
+        r->opts = *opts;
+        r->opts.warm_t = opts->warm_t ? r->warm_t.data() : nullptr;
+        r->footprint = footprint(&r->prob, 1, opts->precision);
+        r->t_submit = now_s();
+        Server& S = server_of(c);
+        std::lock_guard<std::mutex> g(c->mu);
+        if (r->footprint > c->budget)
+            return fail(MCPT_ERR_ADMISSION, "request needs " + std::to_string(r->footprint) +
+                                                " bytes of HBM; the budget is " + std::to_string(c->budget));
+        if (S.stop) return fail(MCPT_ERR_INVALID, "context is shutting down");
+        if ((st = start_server(c)) != MCPT_OK) return st;
+        r->ticket = c->next_id++;
+        *ticket = r->ticket;
+        S.queue.push_back(r->ticket);
+        S.reqs[r->ticket] = std::move(r);
+        S.cv.notify_all();
+        return MCPT_OK;
+    } catch (const std::exception& e) {
+        return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
+    }
+}
+
+mcpt_status mcpt_poll(mcpt_ctx* c, uint64_t ticket, mcpt_summary* out) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!c->server) return fail(MCPT_ERR_UNKNOWN_ID, "unknown ticket");
+    auto it = c->server->reqs.find(ticket);
+    if (it == c->server->reqs.end()) return fail(MCPT_ERR_UNKNOWN_ID, "unknown ticket");
+    const Request* r = it->second.get();
+    if (r->state != 2) return MCPT_PENDING;
+    if (out) *out = r->sum;
+    if (r->sum.status != MCPT_OK) fail(MCPT_OK, r->error);
+    return MCPT_OK;
+}
+
+mcpt_status mcpt_wait(mcpt_ctx* c, uint64_t ticket, int32_t timeout_ms, mcpt_summary* out) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    std::unique_lock<std::mutex> lk(c->mu);
+    if (!c->server) return fail(MCPT_ERR_UNKNOWN_ID, "unknown ticket");
+    Server& S = *c->server;
+    auto ready = [&] {
+        auto it = S.reqs.find(ticket);
+        return it == S.reqs.end() || it->second->state == 2;
+    };
+    if (timeout_ms < 0) S.done_cv.wait(lk, ready);
+    else if (!S.done_cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready)) return MCPT_PENDING;
+    auto it = S.reqs.find(ticket);
+    if (it == S.reqs.end()) return fail(MCPT_ERR_UNKNOWN_ID, "unknown ticket");
+    if (out) *out = it->second->sum;
+    if (it->second->sum.status != MCPT_OK) fail(MCPT_OK, it->second->error);
+    return MCPT_OK;
+}
+
+mcpt_status mcpt_serve_stats(mcpt_ctx* c, mcpt_serve_counters* out) {
+    if (!c || !out) return fail(MCPT_ERR_INVALID, "ctx or out is NULL");
+    std::lock_guard<std::mutex> g(c->mu);
+    *out = mcpt_serve_counters{};
+    out->budget = c->budget;
+    out->bytes_in_use = c->in_use;
+    out->bytes_reserved = c->reserved;
+    if (!c->server) return MCPT_OK;
+    const Server& S = *c->server;
+    out->batches = S.batches;
+    out->completed = S.served;
+    out->queued = (int32_t)S.queue.size();
+    out->running_batches = S.busy;
+    out->workers = (int32_t)S.workers.size();
+    for (const auto& kv : S.reqs) out->tickets += 1;
+    return MCPT_OK;
+}
+
+}  // extern "C"

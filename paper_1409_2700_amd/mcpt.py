@@ -38,6 +38,7 @@ EXPORTS = [
     "mcpt_create", "mcpt_destroy", "mcpt_last_error", "mcpt_set_stream", "mcpt_upload", "mcpt_run",
     "mcpt_solve", "mcpt_energy", "mcpt_release", "mcpt_set_timing", "mcpt_timing_read",
     "mcpt_upload_batch", "mcpt_solve_batch", "mcpt_cluster_results",
+    "mcpt_serve_config", "mcpt_submit", "mcpt_poll", "mcpt_wait", "mcpt_serve_stats",
 ]
 
 
@@ -81,6 +82,17 @@ class mcpt_timing(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class mcpt_serve_counters(C.Structure):
+    _fields_ = [
+        ("completed", C.c_uint64), ("batches", C.c_uint64), ("budget", C.c_uint64),
+        ("bytes_in_use", C.c_uint64), ("bytes_reserved", C.c_uint64), ("queued", C.c_int32),
+        ("running_batches", C.c_int32), ("workers", C.c_int32), ("tickets", C.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"libmcpt.so is not built ({path}); run __graft_entry__.build() first")
@@ -103,6 +115,11 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.mcpt_solve_batch.argtypes = [P, C.POINTER(mcpt_problem), C.c_int32, C.POINTER(mcpt_options),
                                      C.POINTER(C.c_uint64), C.POINTER(mcpt_summary)]
     lib.mcpt_cluster_results.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(mcpt_summary)]
+    lib.mcpt_serve_config.argtypes = [P, C.c_int32, C.c_int32, C.c_int64]
+    lib.mcpt_submit.argtypes = [P, C.POINTER(mcpt_problem), C.POINTER(mcpt_options), C.POINTER(C.c_uint64)]
+    lib.mcpt_poll.argtypes = [P, C.c_uint64, C.POINTER(mcpt_summary)]
+    lib.mcpt_wait.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(mcpt_summary)]
+    lib.mcpt_serve_stats.argtypes = [P, C.POINTER(mcpt_serve_counters)]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if name not in ("mcpt_destroy", "mcpt_last_error"):
@@ -257,6 +274,8 @@ class Context:
         return pid, self.run(pid, raise_on_error=raise_on_error, **opts)
 
     def energy(self, pid: int, want_t: bool = True) -> dict:
+        if pid not in self._sizes:
+            raise MCPTError(MCPT_ERR_UNKNOWN_ID, f"unknown problem id or ticket {pid}")
         n_occ, n_vir, n_pair = self._sizes[pid]
         N = len(n_occ)
         e_m2 = np.empty(N)
@@ -281,6 +300,41 @@ class Context:
         t = mcpt_timing()
         _check(lib().mcpt_timing_read(self.h, C.byref(t)))
         return t.as_dict()
+
+    # ---- serving (mcpt_submit / mcpt_poll) ----
+    def serve_config(self, workers: int = 4, max_batch: int = 32, max_batch_pairs: int = 1 << 20):
+        _check(lib().mcpt_serve_config(self.h, workers, max_batch, max_batch_pairs))
+
+    def submit(self, prob, **opts) -> int:
+        """Queue one solve; returns its ticket (usable with energy / release once done)."""
+        hp = prob if isinstance(prob, HostProblem) else HostProblem(prob)
+        o = make_options(**opts)
+        t = C.c_uint64()
+        _check(lib().mcpt_submit(self.h, C.byref(hp.c), C.byref(o), C.byref(t)))
+        self._sizes[t.value] = (hp.n_occ.copy(), hp.n_vir.copy(), len(hp.pairs))
+        return t.value
+
+    def _finished(self, st: int, s: mcpt_summary):
+        if st == MCPT_PENDING:
+            return None
+        _check(st)
+        d = s.as_dict()
+        d["error"] = last_error() if d["status"] != MCPT_OK else ""
+        return d
+
+    def poll(self, ticket: int):
+        """None while queued or running, else the request's summary (seconds = latency)."""
+        s = mcpt_summary()
+        return self._finished(lib().mcpt_poll(self.h, ticket, C.byref(s)), s)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        s = mcpt_summary()
+        return self._finished(lib().mcpt_wait(self.h, ticket, timeout_ms, C.byref(s)), s)
+
+    def serve_stats(self) -> dict:
+        s = mcpt_serve_counters()
+        _check(lib().mcpt_serve_stats(self.h, C.byref(s)))
+        return s.as_dict()
 
 
 def split_t(t_flat: np.ndarray, n_occ, n_vir):

@@ -1,0 +1,184 @@
+"""Serving form: requests submitted while others run, fused into batches by the
+scheduler, admitted by HBM footprint.  Each served result must be the one the
+same problem gives alone (mcpt_run on the caller's stream): sweep counts equal,
+energies within 1e-12 relative (the atomics order of G aside, the arithmetic
+is the same), and the FP64 oracle within 1e-10 relative.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import mcpt_oracle
+from synth import make_served_request, make_workload
+import paper_1409_2700_amd as mc
+
+pytestmark = pytest.mark.gpu
+
+SAME_RTOL = 1e-12
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b))) / max(float(np.max(np.abs(b))), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def requests():
+    return [make_served_request(r, max_mono=40) for r in range(10)]
+
+
+def alone(prob, **opts):
+    with mc.Context(0) as c:
+        pid, s = c.solve(prob, raise_on_error=False, **opts)
+        e = c.energy(pid) if s["status"] != mc.MCPT_ERR_DIVERGED else None
+    return s, e
+
+
+def wait_all(ctx, tickets, timeout_s=120.0):
+    out = {}
+    t0 = time.time()
+    for t in tickets:
+        left = max(1, int((timeout_s - (time.time() - t0)) * 1000))
+        s = ctx.wait(t, left)
+        assert s is not None, f"ticket {t} did not finish"
+        out[t] = s
+    return out
+
+
+def check_served(ctx, probs, tickets, done, **opts):
+    for p, t in zip(probs, tickets):
+        s = done[t]
+        s1, e1 = alone(p, **opts)
+        assert s["status"] == s1["status"], (p.meta["name"], s, s1)
+        assert s["sweeps"] == s1["sweeps"] and s["polish_sweeps"] == s1["polish_sweeps"]
+        if s["status"] == mc.MCPT_ERR_DIVERGED:
+            with pytest.raises(mc.MCPTError):
+                ctx.energy(t)
+            continue
+        for k in ("e_total", "e_mono", "e_dimer", "e_mono0"):
+            assert abs(s[k] - s1[k]) <= SAME_RTOL * abs(s1[k]), (p.meta["name"], k)
+        e = ctx.energy(t)
+        assert rel(e["e_m2"], e1["e_m2"]) <= SAME_RTOL
+        assert rel(e["e_d2"], e1["e_d2"]) <= 1e-11
+        assert rel(e["t"], e1["t"]) <= 1e-10
+        assert s["seconds"] > 0.0
+
+
+@pytest.mark.parametrize("prec", [mc.MCPT_FP64, mc.MCPT_FP32], ids=["fp64", "fp32polish"])
+def test_served_mix_equals_alone(requests, prec):
+    opts = dict(tol=1e-10, precision=prec, polish=1)
+    with mc.Context(0) as ctx:
+        ctx.serve_config(workers=3, max_batch=4)
+        print(f"[gpu] serve {len(requests)} requests sizes {[p.n_mono for p in requests]} prec={prec}", flush=True)
+        tickets = []
+        for k, p in enumerate(requests):   # arrivals spread out: later ones land while earlier ones run
+            tickets.append(ctx.submit(p, **opts))
+            if k % 3 == 2:
+                time.sleep(0.01)
+        done = wait_all(ctx, tickets)
+        st = ctx.serve_stats()
+        assert st["completed"] == len(requests)
+        assert st["batches"] <= len(requests)
+        check_served(ctx, requests, tickets, done, **opts)
+        for t in tickets:
+            ctx.release(t)
+        assert ctx.serve_stats()["tickets"] == 0
+
+
+def test_served_against_oracle(requests):
+    p = requests[0]
+    with mc.Context(0) as ctx:
+        t = ctx.submit(p, tol=1e-10)
+        s = ctx.wait(t, 60000)
+        r = mcpt_oracle.solve(p, tol=1e-10, max_sweeps=200)
+        assert s["status"] == mc.MCPT_OK and s["sweeps"] == r.sweeps
+        assert abs(s["e_total"] - r.e_total) <= 1e-10 * abs(r.e_total)
+        e = ctx.energy(t)
+        assert rel(e["e_m2"], r.e_m2) <= 1e-10
+
+
+def test_late_small_requests_overtake_a_large_one():
+    """Small requests submitted while a large one is on the GPU are admitted by
+    another worker and finish first."""
+    big = make_served_request(1000, min_mono=300, max_mono=300, cutoff=2.0)
+    small = [make_served_request(1001 + k, min_mono=8, max_mono=8) for k in range(3)]
+    with mc.Context(0) as ctx:
+        ctx.serve_config(workers=2, max_batch=8)
+        tb = ctx.submit(big, tol=1e-12)
+        t0 = time.time()
+        while ctx.serve_stats()["running_batches"] == 0 and ctx.poll(tb) is None and time.time() - t0 < 10:
+            time.sleep(0.0005)
+        ts = [ctx.submit(p, tol=1e-10) for p in small]
+        done_small = wait_all(ctx, ts)
+        assert ctx.poll(tb) is None, "the large request finished before the small ones"
+        sb = ctx.wait(tb, 120000)
+        assert sb["status"] == mc.MCPT_OK
+        for t, p in zip(ts, small):
+            assert done_small[t]["status"] == mc.MCPT_OK
+            s1, _ = alone(p, tol=1e-10)
+            assert abs(done_small[t]["e_total"] - s1["e_total"]) <= SAME_RTOL * abs(s1["e_total"])
+
+
+def test_admission_waits_for_memory():
+    probs = [make_served_request(2000, min_mono=30, max_mono=30)] * 3
+    with mc.Context(0) as probe:
+        t = probe.submit(probs[0], tol=1e-10)
+        probe.wait(t, 60000)
+        one = probe.serve_stats()["bytes_in_use"]
+    assert one > 0
+    with mc.Context(0, hbm_budget=int(2.5 * one)) as ctx:
+        ctx.serve_config(workers=3, max_batch=1)
+        ts = [ctx.submit(p, tol=1e-10) for p in probs]
+        a = ctx.wait(ts[0], 60000)
+        b = ctx.wait(ts[1], 60000)
+        assert a["status"] == b["status"] == mc.MCPT_OK
+        # both results are held: the third request cannot be admitted
+        assert ctx.wait(ts[2], 300) is None
+        st = ctx.serve_stats()
+        assert st["queued"] == 1 and st["bytes_in_use"] <= st["budget"]
+        ctx.release(ts[0])
+        c = ctx.wait(ts[2], 60000)
+        assert c is not None and c["status"] == mc.MCPT_OK
+        assert abs(c["e_total"] - a["e_total"]) <= SAME_RTOL * abs(a["e_total"])
+        assert ctx.serve_stats()["bytes_in_use"] <= ctx.serve_stats()["budget"]
+
+
+def test_submit_errors_and_cancel(requests):
+    p = requests[1]
+    with mc.Context(0, hbm_budget=1 << 20) as small:
+        with pytest.raises(mc.MCPTError) as ei:
+            small.submit(p, tol=1e-10)
+        assert ei.value.status == mc.MCPT_ERR_ADMISSION
+    with mc.Context(0) as ctx:
+        bad = make_workload("hf-2x2x2")
+        bad.v = bad.v.copy()
+        bad.v[5] = np.nan
+        with pytest.raises(mc.MCPTError) as ei:
+            ctx.submit(bad, tol=1e-10)
+        assert ei.value.status == mc.MCPT_ERR_NONFINITE
+        with pytest.raises(mc.MCPTError) as ei:
+            ctx.submit(p, tol=1e-10, deterministic=1)
+        assert ei.value.status == mc.MCPT_ERR_INVALID
+        with pytest.raises(mc.MCPTError) as ei:
+            ctx.poll(123456789)
+        assert ei.value.status == mc.MCPT_ERR_UNKNOWN_ID
+        t = ctx.submit(p, tol=1e-10)
+        s = ctx.wait(t, 60000)
+        assert s["status"] == mc.MCPT_OK
+        ctx.release(t)
+        with pytest.raises(mc.MCPTError):
+            ctx.energy(t)
+
+
+def test_diverging_request_does_not_disturb_the_mix(requests):
+    bad = make_workload("hf-2x2x2", coupling_scale=1.0)
+    probs = [requests[2], bad, requests[3]]
+    opts = dict(tol=1e-10, max_sweeps=60)
+    with mc.Context(0) as ctx:
+        ctx.serve_config(workers=1, max_batch=8)
+        ts = [ctx.submit(p, **opts) for p in probs]
+        done = wait_all(ctx, ts)
+        assert done[ts[1]]["status"] == mc.MCPT_ERR_DIVERGED
+        check_served(ctx, probs, ts, done, **opts)
