@@ -130,6 +130,94 @@ def time_mode(ctx, pid, name, steps, warmup, tol, check_every, golden, graph=0):
     return out
 
 
+def pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def serving(base, n_req, loads, workers, max_batch, tol):
+    """Served stream: requests carved from the resident crystal (sizes
+    log-uniform in [8, N], one monomer displaced), first solved alone one at a
+    time on the plain FP64 path (upload + solve), then submitted with Poisson
+    arrivals at the given fractions of the alone capacity, and as one burst."""
+    import threading
+    import numpy as np
+    import paper_1409_2700_amd as mc
+    from synth import carve_served_request, SEED_ROOT
+
+    t0 = time.time()
+    reqs = [carve_served_request(base, r) for r in range(n_req)]
+    sizes = [p.n_mono for p in reqs]
+    log(f"[serve] {n_req} requests, monomers {min(sizes)}..{max(sizes)} (mean {np.mean(sizes):.0f}), "
+        f"pairs mean {np.mean([p.n_pair for p in reqs]):.0f}, made in {time.time() - t0:.1f}s")
+    alone = []
+    with mc.Context(0) as ctx:
+        pid, _ = ctx.solve(reqs[0], tol=tol)   # untimed warm-up
+        ctx.release(pid)
+        for p in reqs:
+            t1 = time.perf_counter()
+            pid, s = ctx.solve(p, tol=tol)
+            alone.append((time.perf_counter() - t1, s["e_total"], s["sweeps"]))
+            ctx.release(pid)
+    alone_lat = [a[0] for a in alone]
+    mean_alone = float(np.mean(alone_lat))
+    out = {
+        "requests": n_req, "monomers": {"min": int(min(sizes)), "mean": float(np.mean(sizes)),
+                                         "max": int(max(sizes))},
+        "workload": f"carved from {base.n_mono}-monomer crystal, sizes log-uniform [8, {base.n_mono}], "
+                    f"one monomer displaced +-0.01 A",
+        "alone": {"p50_s": pct(alone_lat, 50), "p99_s": pct(alone_lat, 99), "mean_s": mean_alone,
+                  "solves_per_s": 1.0 / mean_alone, "path": "mcpt_solve, one at a time (upload + FP64 solve)"},
+        "workers": workers, "max_batch": max_batch, "loads": {},
+    }
+    log(f"[serve] alone: mean {mean_alone * 1e3:.1f} ms, p50 {pct(alone_lat, 50) * 1e3:.1f} ms")
+    for load in loads:
+        rng = np.random.default_rng([SEED_ROOT, 5, 0 if load == "burst" else int(round(load * 1000))])
+        if load == "burst":
+            arrivals = np.zeros(n_req)
+        else:
+            arrivals = np.cumsum(rng.exponential(mean_alone / load, n_req))
+        lat, err, worst = [], [], []
+        with mc.Context(0) as ctx:
+            ctx.serve_config(workers=workers, max_batch=max_batch)
+            tickets = [None] * n_req
+            ready = threading.Semaphore(0)
+            done_t = []
+
+            def waiter():
+                for k in range(n_req):
+                    ready.acquire()
+                    s = ctx.wait(tickets[k], 600000)
+                    done_t.append(time.perf_counter())
+                    lat.append(s["seconds"])
+                    worst.append(s["status"])
+                    err.append(abs(s["e_total"] - alone[k][1]) / abs(alone[k][1]))
+                    ctx.release(tickets[k])
+
+            th = threading.Thread(target=waiter)
+            th.start()
+            start = time.perf_counter()
+            for k in range(n_req):
+                delay = start + arrivals[k] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                tickets[k] = ctx.submit(reqs[k], tol=tol)
+                ready.release()
+            th.join()
+            st = ctx.serve_stats()
+        wall = max(done_t) - start
+        key = load if load == "burst" else f"{load:.2f}"
+        out["loads"][key] = {
+            "offered_solves_per_s": None if load == "burst" else load / mean_alone,
+            "solves_per_s": n_req / wall, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99),
+            "mean_s": float(np.mean(lat)), "batches": st["batches"],
+            "all_ok": all(w == 0 for w in worst), "max_rel_err_vs_alone": float(max(err)),
+        }
+        log(f"[serve] load {key}: {n_req / wall:.2f} solves/s, p50 {pct(lat, 50) * 1e3:.1f} ms, "
+            f"p99 {pct(lat, 99) * 1e3:.1f} ms, {st['batches']} batches, max rel err {max(err):.1e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +231,9 @@ def main():
     ap.add_argument("--graph", type=int, default=0, help="1: replay HIP-graph captured sweeps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--serve-requests", type=int, default=32, help="served-stream sample (0: skip)")
+    ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-batch", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the MCPT(2) path is built and measured on a single "
@@ -175,6 +266,10 @@ def main():
                                   args.graph)
     ctx.release(pid)
     ctx.close()
+    served = None
+    if args.serve_requests > 0:
+        served = serving(prob, args.serve_requests, [0.5, 0.8, "burst"], args.serve_workers, args.serve_batch,
+                         args.tol)
 
     h = results[args.headline]
     tm = h["timing"]
@@ -209,6 +304,8 @@ def main():
         },
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "timing"} for k, v in results.items()},
     }
+    if served is not None:
+        out["serving"] = served
     if golden is not None:
         out["oracle_reference"] = {"e_total": golden["e_total"], "sweeps": golden["sweeps"],
                                    "file": f"tests/golden/{args.workload}.json"}

@@ -401,10 +401,17 @@ mcpt_status upload_batch(mcpt_ctx* c, Exec& x, const mcpt_problem* pbs, int n_cl
         if (v_cl[q + 1] > v_cl[q])
             DTRY(hipMemcpyAsync(R->d_V + v_cl[q], pbs[q].v_dimer, (v_cl[q + 1] - v_cl[q]) * sizeof(double), kind, s));
     }
-    *x.h_flag = 0;
-    DTRY(hipMemcpyAsync(x.d_flag, x.h_flag, sizeof(int32_t), hipMemcpyHostToDevice, s));
-    launch_nonfinite(R->d_raw, R->raw_elems, x.d_flag, s);
-    launch_nonfinite(R->d_V, R->v_elems, x.d_flag, s);
+    // non-finite inputs, flagged per cluster
+    int32_t* d_bad = nullptr;
+    if ((st = dev_alloc(c, R, &d_bad, n_cl)) != MCPT_OK) {
+        free_resident(c, R);
+        return st;
+    }
+    DTRY(hipMemsetAsync(d_bad, 0, n_cl * sizeof(int32_t), s));
+    for (int q = 0; q < n_cl; ++q) {
+        launch_nonfinite(R->d_raw + raw_cl[q], raw_cl[q + 1] - raw_cl[q], d_bad + q, s);
+        launch_nonfinite(R->d_V + v_cl[q], v_cl[q + 1] - v_cl[q], d_bad + q, s);
+    }
     launch_fill(R->d_K, R->mat_elems, 0.0, s);
     launch_fill(R->d_T, R->mat_elems, 0.0, s);
     launch_fill(R->d_M, R->mat_elems, 0.0, s);
@@ -412,12 +419,17 @@ mcpt_status upload_batch(mcpt_ctx* c, Exec& x, const mcpt_problem* pbs, int n_cl
     launch_fill(R->d_G[1], R->mat_elems, 0.0, s);
     launch_pack(R->d_monos, R->n_mono, R->d_raw, R->d_K, R->max_n, s);
     DTRY(hipGetLastError());
-    DTRY(hipMemcpyAsync(x.h_flag, x.d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    R->cl_bad.assign(n_cl, 0);
+    DTRY(hipMemcpyAsync(R->cl_bad.data(), d_bad, n_cl * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     DTRY(hipStreamSynchronize(s));
 #undef DTRY
-    if (*x.h_flag) {
-        free_resident(c, R);
-        return fail(MCPT_ERR_NONFINITE, "non-finite value in k_intra or v_dimer");
+    for (int q = 0; q < n_cl; ++q) {
+        // a caller's upload fails as a whole; a served batch keeps the other clusters
+        if (R->cl_bad[q] && !internal) {
+            free_resident(c, R);
+            return fail(MCPT_ERR_NONFINITE, (n_cl > 1 ? "cluster " + std::to_string(q) + ": " : std::string()) +
+                                                "non-finite value in k_intra or v_dimer");
+        }
     }
     r->cl_last.assign(n_cl, mcpt_summary{});
     r->internal = internal;
@@ -457,7 +469,7 @@ size_t footprint(const mcpt_problem* pbs, int n, int precision) {
     size_t b = r(n_mono * (int64_t)sizeof(MonoDesc)) + r(std::max<int64_t>(n_pair, 1) * (int64_t)sizeof(PairDesc)) +
                r(8 * dif) + r(8 * raw) + 5 * r(8 * mat) + r(8 * std::max<int64_t>(v, 1)) + 3 * r(8 * n_mono) +
                r(8 * std::max<int64_t>(n_pair, 1)) + r((int64_t)n * (int64_t)sizeof(ClState)) +
-               r(8 * (int64_t)n * kMaxSweeps) + 2 * r(8 * (int64_t)(n + 1));
+               r(8 * (int64_t)n * kMaxSweeps) + 2 * r(8 * (int64_t)(n + 1)) + r(4 * (int64_t)n);
     if (kc) {
         const int64_t es = precision == MCPT_BF16 ? 2 : 4;
         b += r(es * vlo) + r(es * mlo) + r(8 * std::max<int64_t>(n_pair, 1)) + r(8 * n_mono) + 2 * r(8 * mat);
@@ -686,7 +698,12 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
     h.tol = o->tol;
     HIP_TRY(hipMemcpyAsync(x.d_ctrl, &h, sizeof(Ctrl), hipMemcpyHostToDevice, s));
     {
-        const std::vector<ClState> zero(R->n_cl, ClState{});
+        std::vector<ClState> zero(R->n_cl, ClState{});
+        for (int q = 0; q < R->n_cl; ++q)
+            if (!R->cl_bad.empty() && R->cl_bad[q]) {   // never swept; reported as non-finite input
+                zero[q].done = 1;
+                zero[q].status = MCPT_ERR_NONFINITE;
+            }
         HIP_TRY(hipMemcpyAsync(R->d_cl, zero.data(), R->n_cl * sizeof(ClState), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
     }
@@ -911,7 +928,8 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
             cq.residual = cs[q].residual;
             cq.sweeps = cs[q].sweeps;
             cq.seconds = secs;
-            if (h.fixed) cq.status = cs[q].status == MCPT_ERR_DIVERGED ? MCPT_ERR_DIVERGED : MCPT_OK;
+            if (cs[q].status == MCPT_ERR_NONFINITE) cq.status = MCPT_ERR_NONFINITE;
+            else if (h.fixed) cq.status = cs[q].status == MCPT_ERR_DIVERGED ? MCPT_ERR_DIVERGED : MCPT_OK;
             else if (cs[q].status == MCPT_ERR_DIVERGED) cq.status = MCPT_ERR_DIVERGED;
             else if (cs[q].sweeps > 0 && cs[q].residual < o->tol) cq.status = MCPT_OK;
             else cq.status = MCPT_ERR_NOT_CONVERGED;

@@ -47,6 +47,7 @@ struct Resident {
     ClState* d_cl = nullptr;
     double* d_hist = nullptr;
     std::vector<mcpt_summary> cl_last;
+    std::vector<int32_t> cl_bad;      // cluster has a non-finite input (served batches only)
     std::vector<void*> allocations;
     size_t bytes = 0;
     bool has_result = false;
@@ -106,7 +107,8 @@ struct Request {
     uint64_t ticket = 0;
     int state = 0;                      // 0 queued, 1 running, 2 done
     std::vector<int32_t> n_occ, n_vir, pair;
-    std::vector<double> eps, k_intra, v_dimer, warm_t;
+    std::vector<double> eps, warm_t;
+    std::unique_ptr<double[]> k_intra, v_dimer;
     mcpt_problem prob{};                // points into the vectors above
     mcpt_options opts{};
     size_t footprint = 0;               // device bytes of the request alone

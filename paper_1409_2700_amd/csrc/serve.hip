@@ -102,8 +102,8 @@ void worker_loop(mcpt_ctx* c, int w) {
         try {
             st = upload_batch(c, x, probs.data(), (int)probs.size(), true, &bid);
             for (Request* r : group) {   // the device holds the inputs now
-                std::vector<double>().swap(r->k_intra);
-                std::vector<double>().swap(r->v_dimer);
+                r->k_intra.reset();
+                r->v_dimer.reset();
                 r->prob.k_intra = r->prob.v_dimer = nullptr;
             }
             if (st == MCPT_OK) {
@@ -130,7 +130,7 @@ void worker_loop(mcpt_ctx* c, int w) {
                 r->sum = R->cl_last[q];
                 r->batch = bid;
                 r->cluster = (int)q;
-                if (r->sum.status == MCPT_ERR_DIVERGED) r->batch = 0;
+                if (r->sum.status == MCPT_ERR_DIVERGED || r->sum.status == MCPT_ERR_NONFINITE) r->batch = 0;
                 else ++holders;
             } else {
                 r->sum = sm;
@@ -156,13 +156,15 @@ void worker_loop(mcpt_ctx* c, int w) {
     }
 }
 
-// Host-side checks of a submitted problem: everything upload would check,
-// so that a bad request fails at submission and never inside a shared batch.
+// Host-side checks of a submitted problem: sizes, pairs and orbital energies
+// (everything upload checks on the host), so that a bad request fails at
+// submission and never inside a shared batch.  Non-finite integrals are found
+// on the device per request: that request alone fails, with MCPT_ERR_NONFINITE.
 mcpt_status check_request(const mcpt_problem* pb) {
     mcpt_status st = validate_problem(pb);
     if (st != MCPT_OK) return st;
     if (pb->memory != MCPT_HOST) return fail(MCPT_ERR_INVALID, "served requests take host memory");
-    int64_t e = 0, k = 0, v = 0;
+    int64_t e = 0;
     for (int x = 0; x < pb->n_mono; ++x) {
         const int o = pb->n_occ[x], nv = pb->n_vir[x];
         double omax = -INFINITY, vmin = INFINITY;
@@ -176,17 +178,27 @@ mcpt_status check_request(const mcpt_problem* pb) {
             return fail(MCPT_ERR_INVALID, "monomer " + std::to_string(x) +
                                               ": max occupied energy >= min virtual energy (denominator >= 0)");
         e += o + nv;
-        k += (int64_t)o * o * nv * nv;
     }
-    for (int64_t p = 0; p < pb->n_pair; ++p) {
-        const int x = pb->pair[2 * p], y = pb->pair[2 * p + 1];
-        v += (int64_t)pb->n_occ[x] * pb->n_vir[x] * pb->n_occ[y] * pb->n_vir[y];
-    }
-    for (int64_t i = 0; i < k; ++i)
-        if (!std::isfinite(pb->k_intra[i])) return fail(MCPT_ERR_NONFINITE, "non-finite value in k_intra");
-    for (int64_t i = 0; i < v; ++i)
-        if (!std::isfinite(pb->v_dimer[i])) return fail(MCPT_ERR_NONFINITE, "non-finite value in v_dimer");
     return MCPT_OK;
+}
+
+// Copy of a large caller array, split over threads so that the first touch of
+// the new pages (most of the cost) proceeds in parallel.
+std::unique_ptr<double[]> copy_of(const double* src, int64_t n) {
+    std::unique_ptr<double[]> dst(new double[std::max<int64_t>(n, 1)]);
+    const int64_t chunk = int64_t(8) << 20;   // 64 MiB
+    const int nt = (int)std::min<int64_t>(8, (n + chunk - 1) / chunk);
+    if (nt <= 1) {
+        if (n) std::memcpy(dst.get(), src, n * sizeof(double));
+        return dst;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) {
+        const int64_t b = n * t / nt, e = n * (t + 1) / nt;
+        th.emplace_back([&, b, e] { std::memcpy(dst.get() + b, src + b, (e - b) * sizeof(double)); });
+    }
+    for (auto& t : th) t.join();
+    return dst;
 }
 
 mcpt_status start_server(mcpt_ctx* c) {
@@ -323,14 +335,14 @@ mcpt_status mcpt_submit(mcpt_ctx* c, const mcpt_problem* prob, const mcpt_option
         r->n_vir.assign(p.n_vir, p.n_vir + p.n_mono);
         r->pair.assign(p.pair ? p.pair : nullptr, p.pair ? p.pair + 2 * p.n_pair : nullptr);
         r->eps.assign(p.eps, p.eps + ne);
-        r->k_intra.assign(p.k_intra, p.k_intra + nk);
-        if (nv) r->v_dimer.assign(p.v_dimer, p.v_dimer + nv);
+        r->k_intra = copy_of(p.k_intra, nk);
+        r->v_dimer = copy_of(p.v_dimer, nv);
         int64_t nt = 0;
         for (int x = 0; x < p.n_mono; ++x) nt += (int64_t)p.n_occ[x] * p.n_vir[x] * p.n_occ[x] * p.n_vir[x];
         if (opts->warm_t) r->warm_t.assign(opts->warm_t, opts->warm_t + nt);
-        r->prob = mcpt_problem{p.n_mono, r->n_occ.data(), r->n_vir.data(), r->eps.data(), r->k_intra.data(),
+        r->prob = mcpt_problem{p.n_mono, r->n_occ.data(), r->n_vir.data(), r->eps.data(), r->k_intra.get(),
                                p.n_pair, r->pair.empty() ? nullptr : r->pair.data(),
-                               r->v_dimer.empty() ? nullptr : r->v_dimer.data(), MCPT_HOST};
+                               nv ? r->v_dimer.get() : nullptr, MCPT_HOST};
         r->opts = *opts;
         r->opts.warm_t = opts->warm_t ? r->warm_t.data() : nullptr;
         r->footprint = footprint(&r->prob, 1, opts->precision);

@@ -325,3 +325,52 @@ def make_served_request(r: int, *, workload: int = 5, min_mono: int = 8, max_mon
                              displacement=(mono, axis, sign * step_angstrom))
     p.meta["name"] = f"request-{r}"
     return p
+
+
+def carve_served_request(base: Problem, r: int, *, workload: int = 5, min_mono: int = 8,
+                         max_mono: int | None = None, step_angstrom: float = 0.01) -> Problem:
+    """Request r of a served stream carved out of a resident crystal `base`:
+    the n monomers nearest the crystal's centre (n log-uniform in
+    [min_mono, max_mono], ties by index), every pair of `base` between them with
+    its block, and one of them displaced by +-step along a seeded axis (blocks
+    of its pairs rescaled by (R0 / R)^3, pair list unchanged).  Cheap to make,
+    since nothing is drawn but the size and the displacement."""
+    sites = np.asarray(base.sites, dtype=np.int64)
+    N = base.n_mono
+    max_mono = N if max_mono is None else min(max_mono, N)
+    rng = _rng(workload, r, KIND_STREAM)
+    n = int(round(math.exp(rng.uniform(math.log(min_mono), math.log(max_mono)))))
+    n = max(1, min(n, N))
+    d2 = ((sites - sites.mean(axis=0)) ** 2).sum(axis=1)
+    order = np.lexsort((np.arange(N), d2))[:n]
+    order.sort()
+    new_of = -np.ones(N, dtype=np.int64)
+    new_of[order] = np.arange(n)
+    nxv = base.n_occ.astype(np.int64) * base.n_vir
+    psz = nxv[base.pairs[:, 0]] * nxv[base.pairs[:, 1]] if base.n_pair else np.zeros(0, np.int64)
+    poff = np.concatenate([[0], np.cumsum(psz)])
+    keep = np.flatnonzero((new_of[base.pairs[:, 0]] >= 0) & (new_of[base.pairs[:, 1]] >= 0)) \
+        if base.n_pair else np.zeros(0, np.int64)
+    pairs = new_of[base.pairs[keep]].astype(np.int32).reshape(-1, 2)
+    mono = int(rng.integers(0, n))
+    axis = int(rng.integers(0, 3))
+    sign = 1.0 if rng.random() < 0.5 else -1.0
+    pos = sites[order].astype(np.float64) * SPACING_A
+    moved = pos.copy()
+    moved[mono, axis] += sign * step_angstrom
+    blocks = []
+    for p, (x, y) in zip(keep, pairs):
+        blk = base.v[poff[p]:poff[p + 1]]
+        if x == mono or y == mono:
+            r0 = float(np.linalg.norm(pos[x] - pos[y]))
+            r1 = float(np.linalg.norm(moved[x] - moved[y]))
+            blk = blk * (r0 / r1) ** 3
+        blocks.append(blk)
+    v = np.concatenate(blocks) if blocks else np.zeros(0)
+    eoff = np.concatenate([[0], np.cumsum(base.n_occ.astype(np.int64) + base.n_vir)])
+    koff = np.concatenate([[0], np.cumsum(nxv * nxv)])
+    eps = np.concatenate([base.eps[eoff[x]:eoff[x + 1]] for x in order])
+    k = np.concatenate([base.k[koff[x]:koff[x + 1]] for x in order])
+    meta = dict(base.meta)
+    meta.update(name=f"served-{r}", displacement=(mono, axis, sign * step_angstrom), carved_from=base.n_mono)
+    return Problem(base.n_occ[order].copy(), base.n_vir[order].copy(), eps, k, pairs, v, sites[order], meta)

@@ -152,11 +152,11 @@ def test_submit_errors_and_cancel(requests):
             small.submit(p, tol=1e-10)
         assert ei.value.status == mc.MCPT_ERR_ADMISSION
     with mc.Context(0) as ctx:
-        bad = make_workload("hf-2x2x2")
-        bad.v = bad.v.copy()
-        bad.v[5] = np.nan
+        bad_eps = make_workload("hf-2x2x2")
+        bad_eps.eps = bad_eps.eps.copy()
+        bad_eps.eps[3] = np.inf
         with pytest.raises(mc.MCPTError) as ei:
-            ctx.submit(bad, tol=1e-10)
+            ctx.submit(bad_eps, tol=1e-10)
         assert ei.value.status == mc.MCPT_ERR_NONFINITE
         with pytest.raises(mc.MCPTError) as ei:
             ctx.submit(p, tol=1e-10, deterministic=1)
@@ -182,3 +182,21 @@ def test_diverging_request_does_not_disturb_the_mix(requests):
         done = wait_all(ctx, ts)
         assert done[ts[1]]["status"] == mc.MCPT_ERR_DIVERGED
         check_served(ctx, probs, ts, done, **opts)
+
+
+def test_nonfinite_request_fails_alone(requests):
+    """A NaN in one request's dimer blocks is found on the device: that request
+    fails with MCPT_ERR_NONFINITE, the requests batched with it are unaffected."""
+    bad = make_workload("hf-2x2x2")
+    bad.v = bad.v.copy()
+    bad.v[5] = np.nan
+    probs = [requests[4], bad, requests[5]]
+    opts = dict(tol=1e-10)
+    with mc.Context(0) as ctx:
+        ctx.serve_config(workers=1, max_batch=8)
+        ts = [ctx.submit(p, **opts) for p in probs]
+        done = wait_all(ctx, ts)
+        assert done[ts[1]]["status"] == mc.MCPT_ERR_NONFINITE
+        with pytest.raises(mc.MCPTError):
+            ctx.energy(ts[1])
+        check_served(ctx, [probs[0], probs[2]], [ts[0], ts[2]], done, **opts)
