@@ -218,6 +218,81 @@ def serving(base, n_req, loads, workers, max_batch, tol):
     return out
 
 
+def _make_cluster(c):
+    from synth import make_cluster_batch
+    return make_cluster_batch(1, first=c)[0]
+
+
+def batched(n_clusters, tol):
+    """Batching form: uneven cubic-lattice clusters (27..512 monomers, o5v27 /
+    o8v56 half and half) uploaded as one batch; tile shape autotuned, sweeps
+    graph-captured; FP32 polish and plain FP64 timed on the same batch."""
+    from concurrent.futures import ProcessPoolExecutor
+    import numpy as np
+    import paper_1409_2700_amd as mc
+
+    t0 = time.time()
+    probs = []
+    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        for p in ex.map(_make_cluster, range(n_clusters)):
+            probs.append(p)
+            if len(probs) % 8 == 0:
+                log(f"[batch] generated {len(probs)}/{n_clusters} clusters ({time.time() - t0:.0f}s)")
+    n_mono = sum(p.n_mono for p in probs)
+    n_pair = sum(p.n_pair for p in probs)
+    vbytes = sum(p.v.nbytes for p in probs)
+    log(f"[batch] {n_clusters} clusters, {n_mono} monomers, {n_pair} pairs, V {vbytes / 1e9:.1f} GB "
+        f"made in {time.time() - t0:.0f}s")
+    out = {"clusters": n_clusters, "monomers": n_mono, "pairs": n_pair, "v_fp64_GB": vbytes / 1e9,
+           "sizes": [p.n_mono for p in probs], "forms": {}}
+    with mc.Context(0) as ctx:
+        t0 = time.time()
+        pid = ctx.upload_batch(probs)
+        out["upload_s"] = time.time() - t0
+        t0 = time.time()
+        out["tuning"] = ctx.autotune(pid, mc.MCPT_FP32)
+        out["tuning"]["seconds"] = time.time() - t0
+        log(f"[batch] tuned: " + ", ".join(f"{v['sb']}x{v['nw']}:{v['ms']:.1f}ms" for v in out["tuning"]["variants"]))
+        for name, prec in (("fp32+polish", mc.MCPT_FP32), ("fp64", mc.MCPT_FP64)):
+            opts = dict(tol=tol, precision=prec, polish=1, graph=1, autotune=1)
+            ctx.run(pid, **opts)   # warm-up (captures the graph)
+            t1 = time.perf_counter()
+            s = ctx.run(pid, **opts)
+            secs = time.perf_counter() - t1
+            ctx.set_timing(True)
+            ctx.run(pid, **dict(opts, graph=0))   # per-launch kernel times
+            tm = ctx.timing()
+            ctx.set_timing(False)
+            per = ctx.cluster_results(pid)
+            f = {"seconds": secs, "clusters_per_s": n_clusters / secs, "sweeps": s["sweeps"],
+                 "fp64_sweeps": s["polish_sweeps"] if prec else s["sweeps"], "e_total": s["e_total"],
+                 "all_ok": all(c["status"] == 0 for c in per)}
+            if tm["lowp_launches"]:
+                ms = tm["lowp_ms"] / tm["lowp_launches"]
+                tf = tm["lowp_flops"] / (tm["lowp_ms"] * 1e-3) / 1e12
+                f["lowp_pair"] = {"avg_ms": ms, "TFLOPs": tf, "frac_fp32_peak": tf / PEAK["fp32"][0]}
+            if tm["pair_launches"]:
+                tf = tm["pair_flops"] / (tm["pair_ms"] * 1e-3) / 1e12
+                f["fp64_pair"] = {"avg_ms": tm["pair_ms"] / tm["pair_launches"], "TFLOPs": tf,
+                                  "frac_fp64_peak": tf / PEAK["fp64"][0]}
+            out["forms"][name] = f
+            f["per_cluster_e"] = [c["e_total"] for c in per]
+            log(f"[batch] {name}: {secs:.2f}s per batch solve ({n_clusters / secs:.2f} clusters/s), "
+                f"{s['sweeps']} sweeps")
+        ctx.release(pid)
+        a = np.asarray(out["forms"]["fp32+polish"].pop("per_cluster_e"))
+        b = np.asarray(out["forms"]["fp64"].pop("per_cluster_e"))
+        out["max_rel_diff_fp32polish_vs_fp64"] = float(np.max(np.abs(a - b) / np.abs(b)))
+        # the smallest clusters solved alone must match their batch results
+        small = sorted(range(n_clusters), key=lambda q: probs[q].n_mono)[:4]
+        diffs = []
+        for q in small:
+            _, s1 = ctx.solve(probs[q], tol=tol)
+            diffs.append(abs(s1["e_total"] - b[q]) / abs(b[q]))
+        out["max_rel_diff_solo_vs_batch_fp64"] = float(max(diffs))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,6 +309,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=32, help="served-stream sample (0: skip)")
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=16)
+    ap.add_argument("--batched", type=int, default=0,
+                    help="also time the batching form on this many uneven clusters (64 = full set)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the MCPT(2) path is built and measured on a single "
@@ -306,6 +383,8 @@ def main():
     }
     if served is not None:
         out["serving"] = served
+    if args.batched > 0:
+        out["batched"] = batched(args.batched, args.tol)
     if golden is not None:
         out["oracle_reference"] = {"e_total": golden["e_total"], "sweeps": golden["sweeps"],
                                    "file": f"tests/golden/{args.workload}.json"}

@@ -100,8 +100,10 @@ typedef struct {
     int32_t        inner_sweeps; /* reduced precision + polish: correction sweeps per FP64 sweep (0 = default) */
     const double  *warm_t;       /* NULL, or host T (layout of t_amp in mcpt_energy) to start from */
     int32_t        graph;        /* 1: capture the sweeps issued between host checks in a HIP graph and
-                                    replay it (plain sweeps; per-launch timing is not recorded then) */
-    int32_t        reserved;
+                                    replay it (per-launch timing is not recorded then) */
+    int32_t        autotune;     /* reduced precision: 1 = if the context has no tile choice for this
+                                    problem's pair-shape mix, run mcpt_autotune first; 0 = use the
+                                    context's choice or the default tile shape */
 } mcpt_options;
 
 typedef struct {
@@ -198,6 +200,32 @@ mcpt_status mcpt_energy(mcpt_ctx *ctx, uint64_t id, double *e_m2, double *de_m2,
 
 /* Free a resident problem. Errors: MCPT_ERR_UNKNOWN_ID. */
 mcpt_status mcpt_release(mcpt_ctx *ctx, uint64_t id);
+
+/* ---- Tile autotuner of the reduced-precision pair kernel ----
+ * The kernel exists in several tile shapes: each wave computes sb x sb output
+ * tiles of 16 x 16 per task, nw waves per workgroup.  mcpt_autotune times one
+ * coupled pair phase of the resident problem per shape and keeps the fastest,
+ * for this problem and, under its pair-shape key (block shapes and their share
+ * of the flops, pair count to a power of two), for every later problem of the
+ * context with the same key.  It overwrites the problem's last results (run it
+ * again afterwards).  The table can be saved and restored as text lines
+ * "key sb nw". */
+typedef struct {
+    int32_t n_variants;     /* shapes timed */
+    int32_t best;           /* index of the fastest */
+    int32_t sb[16], nw[16]; /* shape of each */
+    double  ms[16];         /* one coupled pair phase, milliseconds */
+} mcpt_tune_result;
+
+/* Errors: MCPT_ERR_INVALID (precision not FP32 / BF16), MCPT_ERR_UNKNOWN_ID, MCPT_ERR_DEVICE. */
+mcpt_status mcpt_autotune(mcpt_ctx *ctx, uint64_t id, int32_t precision, mcpt_tune_result *out);
+
+/* Write the tuning table as text into buf (capacity cap, may be NULL); *len = bytes needed
+ * including the terminating NUL.  Errors: MCPT_ERR_INVALID (buffer too small). */
+mcpt_status mcpt_tune_export(mcpt_ctx *ctx, char *buf, size_t cap, size_t *len);
+
+/* Add the lines of an exported table.  Errors: MCPT_ERR_INVALID (malformed line, unknown shape). */
+mcpt_status mcpt_tune_import(mcpt_ctx *ctx, const char *text);
 
 /* Enable (1) or disable (0) per-launch kernel timing; enabling resets the totals. */
 mcpt_status mcpt_set_timing(mcpt_ctx *ctx, int enable);

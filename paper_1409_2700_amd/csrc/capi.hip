@@ -408,6 +408,7 @@ mcpt_status upload_batch(mcpt_ctx* c, Exec& x, const mcpt_problem* pbs, int n_cl
         return st;
     }
     DTRY(hipMemsetAsync(d_bad, 0, n_cl * sizeof(int32_t), s));
+    DTRY(hipMemsetAsync(R->d_cl, 0, n_cl * sizeof(ClState), s));
     for (int q = 0; q < n_cl; ++q) {
         launch_nonfinite(R->d_raw + raw_cl[q], raw_cl[q + 1] - raw_cl[q], d_bad + q, s);
         launch_nonfinite(R->d_V + v_cl[q], v_cl[q + 1] - v_cl[q], d_bad + q, s);
@@ -558,6 +559,7 @@ mcpt_status validate_options(const mcpt_options* o) {
     if (o->deterministic != 0)
         return fail(MCPT_ERR_INVALID, "deterministic (atomic-free) accumulation is not available in this library");
     if (o->graph != 0 && o->graph != 1) return fail(MCPT_ERR_INVALID, "graph must be 0 or 1");
+    if (o->autotune != 0 && o->autotune != 1) return fail(MCPT_ERR_INVALID, "autotune must be 0 or 1");
     return MCPT_OK;
 }
 
@@ -642,7 +644,7 @@ mcpt_status ensure_lowp(mcpt_ctx* c, Exec& x, Resident* R, int prec) {
 // Per-stream scratch of the reduced-precision pair kernel (Tau and Tau^T per workgroup).
 mcpt_status ensure_scratch_lo(mcpt_ctx* c, Exec& x, const Resident* R, int prec) {
     const size_t es = prec == MCPT_BF16 ? 2 : 4;
-    x.grid_lo = std::max(8, c->n_cu * pair_lowp_blocks_per_cu(prec) / 8 * 8);
+    x.grid_lo = std::max(8, c->n_cu * pair_lowp_blocks_per_cu(prec, R->lo_variant) / 8 * 8);
     const size_t need = (size_t)R->lo_slot * es * x.grid_lo;
     if (need > x.scratch_lo_bytes) {
         HIP_TRY(hipStreamSynchronize(x.stream));
@@ -660,10 +662,11 @@ mcpt_status ensure_scratch_lo(mcpt_ctx* c, Exec& x, const Resident* R, int prec)
     return MCPT_OK;
 }
 
-void lowp_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int source) {
-    launch_pair_lowp(R->lo_prec, R->d_pairs, R->n_pair, R->d_monos, R->d_dif, R->d_Vlo, R->d_lo_off, R->d_Mlo,
-                     R->d_mlo_off, G, x.d_scratch_lo, R->lo_slot, x.grid_lo, R->d_ed2, source, 1, nullptr,
-                     R->d_cl, x.stream);
+// `every`: cover the pairs of every cluster (the autotuner), not only those still iterating
+void lowp_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int source, bool every = false) {
+    launch_pair_lowp(R->lo_prec, R->lo_variant, R->d_pairs, R->n_pair, R->d_monos, R->d_dif, R->d_Vlo, R->d_lo_off,
+                     R->d_Mlo, R->d_mlo_off, G, x.d_scratch_lo, R->lo_slot, x.grid_lo, R->d_ed2, source, 1, nullptr,
+                     every ? nullptr : R->d_cl, x.stream);
 }
 
 void mixed_mono(mcpt_ctx* c, Exec& x, Resident* R, int mode, const double* G, double* Gz, bool lo_out, const Ctrl* ctrl) {
@@ -679,15 +682,96 @@ mcpt_status sync_ctrl(Exec& x) {
     return MCPT_OK;
 }
 
+// Signature of a problem's pair phase for the tile autotuner: the distinct
+// padded block shapes (npX x npY, smaller first) with their share of the
+// pair-phase flops in tenths, and the pair count to a power of two.
+std::string shape_key(const Resident* R, int prec) {
+    std::map<std::pair<int, int>, double> w;
+    double tot = 0.0;
+    for (const PairDesc& p : R->pairs) {
+        int a = R->monos[p.x].np, b = R->monos[p.y].np;
+        if (a > b) std::swap(a, b);
+        const double f = (double)a * b * (a + b);
+        w[{a, b}] += f;
+        tot += f;
+    }
+    std::string k = std::string(prec == MCPT_BF16 ? "bf16" : "fp32");
+    for (const auto& kv : w)
+        k += "/" + std::to_string(kv.first.first) + "x" + std::to_string(kv.first.second) + ":" +
+             std::to_string((int)std::lround(10.0 * kv.second / std::max(tot, 1.0)));
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= R->n_pair) ++lg;
+    return k + "/p2^" + std::to_string(lg);
+}
+
+// Time one coupled reduced-precision pair phase per tile-shape variant on the
+// resident problem and keep the fastest (for this problem and, under its shape
+// key, for later problems of the context).  Clobbers G and E_D2: the problem's
+// previous results are invalidated.
+mcpt_status autotune(mcpt_ctx* c, Exec& x, Resident* R, int prec, mcpt_tune_result* out) {
+    mcpt_status st;
+    if ((st = ensure_device(c)) != MCPT_OK || (st = ensure_lowp(c, x, R, prec)) != MCPT_OK) return st;
+    R->has_result = false;
+    const int nv = std::min(lowp_variants(), 16);
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    std::vector<double> ms(nv, 0.0);
+    int best = 0;
+    for (int v = 0; v < nv; ++v) {
+        R->lo_variant = v;
+        if ((st = ensure_scratch_lo(c, x, R, prec)) != MCPT_OK) break;
+        lowp_phase(c, x, R, R->d_G[0], 1, true);   // warm-up
+        HIP_TRY(hipEventRecord(a, x.stream));
+        constexpr int reps = 3;
+        for (int k = 0; k < reps; ++k) lowp_phase(c, x, R, R->d_G[0], 1, true);
+        HIP_TRY(hipEventRecord(b, x.stream));
+        HIP_TRY(hipEventSynchronize(b));
+        HIP_TRY(hipGetLastError());
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, a, b));
+        ms[v] = t / reps;
+        if (ms[v] < ms[best]) best = v;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != MCPT_OK) return st;
+    R->lo_variant = best;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        c->tune[shape_key(R, prec)] = best;
+    }
+    if (out) {
+        *out = mcpt_tune_result{};
+        out->n_variants = nv;
+        out->best = best;
+        for (int v = 0; v < nv; ++v) {
+            lowp_variant_shape(v, &out->sb[v], &out->nw[v]);
+            out->ms[v] = ms[v];
+        }
+    }
+    return ensure_scratch_lo(c, x, R, prec);
+}
+
 mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_summary* out) {
     mcpt_status st = validate_options(o);
     if (st != MCPT_OK) return st;
     if ((st = ensure_device(c)) != MCPT_OK) return st;
     if ((st = ensure_scratch(c, x, R->max_slot)) != MCPT_OK) return st;
     const int prec = o->precision;
-    if (prec != MCPT_FP64 && ((st = ensure_lowp(c, x, R, prec)) != MCPT_OK ||
-                              (st = ensure_scratch_lo(c, x, R, prec)) != MCPT_OK))
-        return st;
+    if (prec != MCPT_FP64) {
+        if ((st = ensure_lowp(c, x, R, prec)) != MCPT_OK) return st;
+        const std::string key = shape_key(R, prec);
+        int tuned = -1;
+        {
+            std::lock_guard<std::mutex> g(c->mu);
+            auto it = c->tune.find(key);
+            if (it != c->tune.end()) tuned = it->second;
+        }
+        if (tuned >= 0 && tuned < lowp_variants()) R->lo_variant = tuned;
+        else if (o->autotune && (st = autotune(c, x, R, prec, nullptr)) != MCPT_OK) return st;
+        if ((st = ensure_scratch_lo(c, x, R, prec)) != MCPT_OK) return st;
+    }
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = x.stream;
     R->has_result = false;
@@ -753,7 +837,8 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
             const int gk = (every % 2) ? 2 * every : every;
             const std::array<int64_t, 6> key{(int64_t)(uintptr_t)x.d_scratch, (int64_t)(uintptr_t)x.d_scratch_lo,
                                              (int64_t)(uintptr_t)x.d_ctrl, x.scratch_slot,
-                                             (int64_t)c->grid_lds * 1000000 + c->grid_glb, x.grid_lo};
+                                             (int64_t)c->grid_lds * 1000000 + c->grid_glb,
+                                             (int64_t)x.grid_lo * 1000 + R->lo_variant};
             if (!R->graph || R->graph_prec != prec || R->graph_sweeps != gk || R->graph_key != key) {
                 drop_graph(R);
                 hipGraph_t g = nullptr;
@@ -851,7 +936,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
             const std::array<int64_t, 6> key{(int64_t)(uintptr_t)x.d_scratch, (int64_t)(uintptr_t)x.d_scratch_lo,
                                              (int64_t)(uintptr_t)x.d_ctrl, x.scratch_slot,
                                              (int64_t)c->grid_lds * 1000000 + c->grid_glb,
-                                             (int64_t)x.grid_lo * 1000 + inner};
+                                             ((int64_t)x.grid_lo * 1000 + R->lo_variant) * 1000 + inner};
             const int gprec = 16 + prec;
             if (!R->graph || R->graph_prec != gprec || R->graph_sweeps != gb || R->graph_key != key ||
                 R->graph_parity != cur) {
@@ -1112,6 +1197,65 @@ mcpt_status mcpt_release(mcpt_ctx* c, uint64_t id) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->main.stream);
     release_resident(c, id);
+    return MCPT_OK;
+}
+
+mcpt_status mcpt_autotune(mcpt_ctx* c, uint64_t id, int32_t precision, mcpt_tune_result* out) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    if (precision != MCPT_FP32 && precision != MCPT_BF16)
+        return fail(MCPT_ERR_INVALID, "tile variants exist for MCPT_FP32 and MCPT_BF16 only");
+    Resident* R = find_resident(c, id);
+    if (!R) return unknown(id);
+    try {
+        return autotune(c, c->main, R, precision, out);
+    } catch (const std::exception& e) {
+        return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
+    }
+}
+
+mcpt_status mcpt_tune_export(mcpt_ctx* c, char* buf, size_t cap, size_t* len) {
+    if (!c || !len) return fail(MCPT_ERR_INVALID, "ctx or len is NULL");
+    std::string text;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        for (const auto& kv : c->tune) {
+            int sb = 0, nw = 0;
+            lowp_variant_shape(kv.second, &sb, &nw);
+            text += kv.first + " " + std::to_string(sb) + " " + std::to_string(nw) + "\n";
+        }
+    }
+    *len = text.size() + 1;
+    if (buf && cap >= text.size() + 1) std::memcpy(buf, text.c_str(), text.size() + 1);
+    else if (buf) return fail(MCPT_ERR_INVALID, "buffer too small: " + std::to_string(text.size() + 1) + " bytes");
+    return MCPT_OK;
+}
+
+mcpt_status mcpt_tune_import(mcpt_ctx* c, const char* text) {
+    if (!c || !text) return fail(MCPT_ERR_INVALID, "ctx or text is NULL");
+    std::map<std::string, int> add;
+    const std::string t(text);
+    size_t pos = 0;
+    while (pos < t.size()) {
+        size_t e = t.find('\n', pos);
+        if (e == std::string::npos) e = t.size();
+        const std::string line = t.substr(pos, e - pos);
+        pos = e + 1;
+        if (line.empty()) continue;
+        char key[512];
+        int sb = 0, nw = 0;
+        if (line.size() >= sizeof(key) || std::sscanf(line.c_str(), "%511s %d %d", key, &sb, &nw) != 3)
+            return fail(MCPT_ERR_INVALID, "bad tuning line: " + line);
+        int v = -1;
+        for (int k = 0; k < lowp_variants(); ++k) {
+            int a = 0, b = 0;
+            lowp_variant_shape(k, &a, &b);
+            if (a == sb && b == nw) v = k;
+        }
+        if (v < 0) return fail(MCPT_ERR_INVALID, "no tile variant " + std::to_string(sb) + " x " + std::to_string(nw));
+        add[key] = v;
+    }
+    std::lock_guard<std::mutex> g(c->mu);
+    for (const auto& kv : add) c->tune[kv.first] = kv.second;
     return MCPT_OK;
 }
 

@@ -114,8 +114,11 @@ bool pair_fits_lds(int nX, int npY);
 int lowp_chunk(int precision);   // k chunk: rows of low-precision operands are padded to it
 void launch_convert_v(int precision, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
                       const double* V, void* Vlo, const int64_t* lo_off, hipStream_t s);
-int pair_lowp_blocks_per_cu(int precision);
-void launch_pair_lowp(int precision, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
+// reduced-precision pair kernel: `variant` selects one of lowp_variants() tile shapes
+int lowp_variants();
+void lowp_variant_shape(int variant, int* sb, int* nw);
+int pair_lowp_blocks_per_cu(int precision, int variant);
+void launch_pair_lowp(int precision, int variant, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
                       const double* dif, const void* Vlo, const int64_t* lo_off, const void* Mlo,
                       const int64_t* mlo_off, double* G, void* scratch, int64_t slot_elems, int grid, double* ed2,
                       int source, int couple, const Ctrl* ctrl, const ClState* cl, hipStream_t s);

@@ -17,6 +17,8 @@
 // with lane l holding rows 4*(l/16) + t of column l%16 (measured), and lane l
 // supplies k = k0 + KL*(l/16) + e of both operands (KL = 4 or 8 contiguous
 // values).
+#include <utility>
+
 #include "mcpt_internal.hpp"
 
 namespace mcpt {
@@ -27,10 +29,16 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
-constexpr int kSB = 3;
+constexpr int kThreads = 256;   // conversion kernel
 constexpr int kXcds = 8;
+
+// Tunable shapes of the pair kernel: super-block edge SB (a wave computes SB x SB
+// output tiles of 16 x 16 per task) and waves per workgroup NW.
+struct Variant {
+    int sb, nw;
+};
+constexpr Variant kVariants[] = {{3, 4}, {2, 4}, {4, 4}, {3, 8}, {2, 8}, {4, 8}};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 template <class E>
 struct Lowp;
@@ -121,18 +129,22 @@ struct Grid {
     int RT, CT, SR, SC, n;
 };
 
+template <int SB>
 __device__ inline Grid make_grid(int RT, int CT) {
     Grid g;
     g.RT = RT;
     g.CT = CT;
-    g.SR = (RT + kSB - 1) / kSB;
-    g.SC = (CT + kSB - 1) / kSB;
+    g.SR = (RT + SB - 1) / SB;
+    g.SC = (CT + SB - 1) / SB;
     g.n = g.SR * g.SC;
     return g;
 }
 
-template <class F>
+// Wave tasks over one or two tile grids: full SB x SB super-blocks are dealt
+// round-robin; the tiles of the ragged remainder are dealt one by one.
+template <int SB, int NW, class F>
 __device__ inline void for_tasks(const Grid& g0, const Grid& g1, int wave, F&& f) {
+    constexpr int kSB = SB, kWaves = NW;
     const int total = g0.n + g1.n;
     const int full = total - total % kWaves;
     for (int sb = wave; sb < full; sb += kWaves) {
@@ -218,16 +230,17 @@ __global__ __launch_bounds__(kThreads) void convert_v_kernel(const PairDesc* __r
     }
 }
 
-template <class E>
-__global__ __launch_bounds__(kThreads) void pair_lowp_kernel(
+template <class E, int SB, int NW>
+__global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
     const PairDesc* __restrict__ pairs, int64_t n_pair, const MonoDesc* __restrict__ monos,
     const double* __restrict__ dif, const E* __restrict__ Vlo, const int64_t* __restrict__ lo_off,
     const E* __restrict__ Mlo, const int64_t* __restrict__ mlo_off, double* __restrict__ G,
     E* __restrict__ scratch, int64_t slot_elems, double* __restrict__ ed2, int source, int couple,
     const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
     typedef Lowp<E> L;
+    constexpr int kThreadsK = NW * 64;
     if (ctrl && ctrl->done) return;
-    __shared__ double red[kWaves];
+    __shared__ double red[NW];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     E* tau = scratch + (int64_t)blockIdx.x * slot_elems;
     for (int64_t it = 0;; ++it) {
@@ -249,7 +262,7 @@ __global__ __launch_bounds__(kThreads) void pair_lowp_kernel(
 
         // ---- Tau = D_XY * (source V + M_X V + V M_Y^T), E_D2 = 4 <V, Tau> ----
         double epart = 0.0;
-        for_tasks(make_grid(RB, CB), make_grid(0, 0), wave, [&](int, int r0, int c0, auto shape) {
+        for_tasks<SB, NW>(make_grid<SB>(RB, CB), make_grid<SB>(0, 0), wave, [&](int, int r0, int c0, auto shape) {
             constexpr int NR = decltype(shape)::NR, NC = decltype(shape)::NC;
             f4 acc[NR][NC];
             zero(acc);
@@ -284,11 +297,11 @@ __global__ __launch_bounds__(kThreads) void pair_lowp_kernel(
             }
         });
         if (couple) {   // zero the k padding of Tau (columns npY..ldY) and Tau^T (columns npX..ldX)
-            for (int idx = threadIdx.x; idx < npX * (ldY - npY); idx += kThreads) {
+            for (int idx = threadIdx.x; idx < npX * (ldY - npY); idx += kThreadsK) {
                 const int r = idx / (ldY - npY), c = npY + idx % (ldY - npY);
                 tau[(int64_t)r * ldY + c] = L::from(0.0);
             }
-            for (int idx = threadIdx.x; idx < npY * (ldX - npX); idx += kThreads) {
+            for (int idx = threadIdx.x; idx < npY * (ldX - npX); idx += kThreadsK) {
                 const int r = idx / (ldX - npX), c = npX + idx % (ldX - npX);
                 tauT[(int64_t)r * ldX + c] = L::from(0.0);
             }
@@ -298,14 +311,15 @@ __global__ __launch_bounds__(kThreads) void pair_lowp_kernel(
         __syncthreads();
         if (threadIdx.x == 0) {
             double s = 0.0;
-            for (int w = 0; w < kWaves; ++w) s += red[w];
+            for (int w = 0; w < NW; ++w) s += red[w];
             ed2[pd.orig] = 4.0 * s;
         }
         if (couple) {
             double* GX = G + dx.mat_off;
             double* GY = G + dy.mat_off;
             // ---- G_X += Tau V^T (contract over Y index), G_Y += Tau^T V (contract over X index) ----
-            for_tasks(make_grid(RB, RB), make_grid(CB, CB), wave, [&](int which, int r0, int c0, auto shape) {
+            for_tasks<SB, NW>(make_grid<SB>(RB, RB), make_grid<SB>(CB, CB), wave,
+                              [&](int which, int r0, int c0, auto shape) {
                 constexpr int NR = decltype(shape)::NR, NC = decltype(shape)::NC;
                 f4 acc[NR][NC];
                 zero(acc);
@@ -337,28 +351,50 @@ void launch_convert_v(int precision, const PairDesc* pairs, int64_t n_pair, cons
                            static_cast<float*>(Vlo), lo_off);
 }
 
-int pair_lowp_blocks_per_cu(int precision) {
+template <class E, int V>
+const void* kernel_of() {
+    return reinterpret_cast<const void*>(pair_lowp_kernel<E, kVariants[V].sb, kVariants[V].nw>);
+}
+
+template <class E, int... V>
+const void* pick(int v, std::integer_sequence<int, V...>) {
+    const void* k = nullptr;
+    ((k = (v == V ? kernel_of<E, V>() : k)), ...);
+    return k;
+}
+
+const void* lowp_kernel(int precision, int variant) {
+    const auto seq = std::make_integer_sequence<int, kNumVariants>{};
+    return precision == 2 ? pick<__bf16>(variant, seq) : pick<float>(variant, seq);
+}
+
+int lowp_variants() { return kNumVariants; }
+
+int lowp_variant_threads(int variant) { return kVariants[variant].nw * 64; }
+
+void lowp_variant_shape(int variant, int* sb, int* nw) {
+    *sb = kVariants[variant].sb;
+    *nw = kVariants[variant].nw;
+}
+
+int pair_lowp_blocks_per_cu(int precision, int variant) {
     int n = 0;
-    hipError_t e = precision == 2
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_lowp_kernel<__bf16>, kThreads, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_lowp_kernel<float>, kThreads, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, lowp_kernel(precision, variant),
+                                                                lowp_variant_threads(variant), 0);
     if (e != hipSuccess || n < 1) n = 1;
     return n;
 }
 
-void launch_pair_lowp(int precision, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
+void launch_pair_lowp(int precision, int variant, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
                       const double* dif, const void* Vlo, const int64_t* lo_off, const void* Mlo,
                       const int64_t* mlo_off, double* G, void* scratch, int64_t slot_elems, int grid, double* ed2,
                       int source, int couple, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
     if (n_pair <= 0) return;
-    if (precision == 2)
-        hipLaunchKernelGGL(pair_lowp_kernel<__bf16>, dim3(grid), dim3(kThreads), 0, s, pairs, n_pair, monos, dif,
-                           static_cast<const __bf16*>(Vlo), lo_off, static_cast<const __bf16*>(Mlo), mlo_off, G,
-                           static_cast<__bf16*>(scratch), slot_elems, ed2, source, couple, ctrl, cl);
-    else
-        hipLaunchKernelGGL(pair_lowp_kernel<float>, dim3(grid), dim3(kThreads), 0, s, pairs, n_pair, monos, dif,
-                           static_cast<const float*>(Vlo), lo_off, static_cast<const float*>(Mlo), mlo_off, G,
-                           static_cast<float*>(scratch), slot_elems, ed2, source, couple, ctrl, cl);
+    void* args[] = {(void*)&pairs, (void*)&n_pair, (void*)&monos, (void*)&dif, (void*)&Vlo, (void*)&lo_off,
+                    (void*)&Mlo, (void*)&mlo_off, (void*)&G, (void*)&scratch, (void*)&slot_elems, (void*)&ed2,
+                    (void*)&source, (void*)&couple, (void*)&ctrl, (void*)&cl};
+    (void)hipLaunchKernel(lowp_kernel(precision, variant), dim3(grid), dim3(lowp_variant_threads(variant)), args, 0,
+                          s);
 }
 
 }  // namespace mcpt

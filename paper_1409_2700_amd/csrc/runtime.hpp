@@ -54,6 +54,8 @@ struct Resident {
     mcpt_summary last{};
     // reduced-precision copies (mixed-precision form), made on first use of a precision
     int lo_prec = 0;
+    int lo_variant = 0;           // tile shape of the reduced-precision pair kernel
+    std::string shape_key;        // pair-shape signature used by the tile autotuner
     void *d_Vlo = nullptr, *d_Mlo = nullptr;
     int64_t *d_lo_off = nullptr, *d_mlo_off = nullptr;
     double *d_R = nullptr, *d_Dl = nullptr;
@@ -150,6 +152,7 @@ struct mcpt_ctx {
     std::map<uint64_t, std::unique_ptr<mcpt::Resident>> res;   // mu
     int grid_lds = 0, grid_glb = 0;     // persistent grids of the two FP64 pair-kernel variants
     mcpt::Exec main;                    // the caller's stream (mcpt_run, mcpt_energy, ...)
+    std::map<std::string, int> tune;    // autotuned lowp variant per "precision/shape key" (mu)
     std::unique_ptr<mcpt::Server> server;
 };
 

@@ -39,6 +39,7 @@ EXPORTS = [
     "mcpt_solve", "mcpt_energy", "mcpt_release", "mcpt_set_timing", "mcpt_timing_read",
     "mcpt_upload_batch", "mcpt_solve_batch", "mcpt_cluster_results",
     "mcpt_serve_config", "mcpt_submit", "mcpt_poll", "mcpt_wait", "mcpt_serve_stats",
+    "mcpt_autotune", "mcpt_tune_export", "mcpt_tune_import",
 ]
 
 
@@ -54,7 +55,7 @@ class mcpt_options(C.Structure):
     _fields_ = [
         ("tol", C.c_double), ("max_sweeps", C.c_int32), ("precision", C.c_int32),
         ("polish", C.c_int32), ("deterministic", C.c_int32), ("check_every", C.c_int32),
-        ("inner_sweeps", C.c_int32), ("warm_t", C.c_void_p), ("graph", C.c_int32), ("reserved", C.c_int32),
+        ("inner_sweeps", C.c_int32), ("warm_t", C.c_void_p), ("graph", C.c_int32), ("autotune", C.c_int32),
     ]
 
 
@@ -93,6 +94,18 @@ class mcpt_serve_counters(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class mcpt_tune_result(C.Structure):
+    _fields_ = [
+        ("n_variants", C.c_int32), ("best", C.c_int32), ("sb", C.c_int32 * 16), ("nw", C.c_int32 * 16),
+        ("ms", C.c_double * 16),
+    ]
+
+    def as_dict(self) -> dict:
+        n = self.n_variants
+        return {"best": self.best, "variants": [{"sb": self.sb[k], "nw": self.nw[k], "ms": self.ms[k]}
+                                                for k in range(n)]}
+
+
 def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"libmcpt.so is not built ({path}); run __graft_entry__.build() first")
@@ -120,6 +133,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.mcpt_poll.argtypes = [P, C.c_uint64, C.POINTER(mcpt_summary)]
     lib.mcpt_wait.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(mcpt_summary)]
     lib.mcpt_serve_stats.argtypes = [P, C.POINTER(mcpt_serve_counters)]
+    lib.mcpt_autotune.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(mcpt_tune_result)]
+    lib.mcpt_tune_export.argtypes = [P, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
+    lib.mcpt_tune_import.argtypes = [P, C.c_char_p]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if name not in ("mcpt_destroy", "mcpt_last_error"):
@@ -174,10 +190,10 @@ class HostProblem:
 
 
 def make_options(tol=1e-10, max_sweeps=200, precision=MCPT_FP64, polish=1, deterministic=0,
-                 check_every=1, inner_sweeps=0, warm_t: np.ndarray | None = None, graph=0):
+                 check_every=1, inner_sweeps=0, warm_t: np.ndarray | None = None, graph=0, autotune=0):
     o = mcpt_options(tol=tol, max_sweeps=max_sweeps, precision=precision, polish=polish,
                      deterministic=deterministic, check_every=check_every, inner_sweeps=inner_sweeps,
-                     warm_t=_ptr(warm_t), graph=graph, reserved=0)
+                     warm_t=_ptr(warm_t), graph=graph, autotune=autotune)
     o._keep = warm_t
     return o
 
@@ -300,6 +316,22 @@ class Context:
         t = mcpt_timing()
         _check(lib().mcpt_timing_read(self.h, C.byref(t)))
         return t.as_dict()
+
+    # ---- tile autotuner ----
+    def autotune(self, pid: int, precision: int) -> dict:
+        r = mcpt_tune_result()
+        _check(lib().mcpt_autotune(self.h, pid, precision, C.byref(r)))
+        return r.as_dict()
+
+    def tune_table(self) -> str:
+        n = C.c_size_t()
+        _check(lib().mcpt_tune_export(self.h, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().mcpt_tune_export(self.h, buf, n.value, C.byref(n)))
+        return buf.value.decode()
+
+    def load_tune_table(self, text: str):
+        _check(lib().mcpt_tune_import(self.h, text.encode()))
 
     # ---- serving (mcpt_submit / mcpt_poll) ----
     def serve_config(self, workers: int = 4, max_batch: int = 32, max_batch_pairs: int = 1 << 20):
