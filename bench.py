@@ -293,6 +293,28 @@ def batched(n_clusters, tol):
     return out
 
 
+def pmc_pass(workload: str, sweeps: int = 2):
+    """Counter pass for rocprofv3 --pmc: one device copy of a known size
+    (the calibration kernel), then `sweeps` fixed FP64 sweeps of the resident
+    workload and its final energy pass; nothing else is launched."""
+    import torch
+    import paper_1409_2700_amd as mc
+    from synth import make_workload
+    prob = make_workload(workload)
+    n = 1 << 27   # 1 GiB of FP64
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[pmc] calibration copy: {n * 8} bytes read and written")
+    del src, dst
+    with mc.Context(0) as ctx:
+        pid = ctx.upload(prob)
+        s = ctx.run(pid, tol=0.0, max_sweeps=sweeps)
+        log(f"[pmc] {workload}: {s['sweeps']} fixed sweeps + final pass, E={s['e_total']:.10f}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -309,6 +331,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=32, help="served-stream sample (0: skip)")
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=16)
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="only launch a calibration copy and two FP64 sweeps (for rocprofv3 --pmc)")
     ap.add_argument("--batched", type=int, default=0,
                     help="also time the batching form on this many uneven clusters (64 = full set)")
     args = ap.parse_args()
@@ -318,6 +342,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.pmc_pass:
+        pmc_pass(args.workload)
+        return
     import paper_1409_2700_amd as mc
     from synth import make_workload, DEFAULT_COUPLING_SCALE
 
