@@ -85,7 +85,8 @@ MODES = {   # name: (precision, polish)
 def time_mode(ctx, pid, name, steps, warmup, tol, check_every, golden, graph=0):
     import numpy as np
     prec, polish = MODES[name]
-    opts = dict(tol=tol, max_sweeps=200, check_every=check_every, precision=prec, polish=polish, graph=graph)
+    opts = dict(tol=tol, max_sweeps=200, check_every=check_every, precision=prec, polish=polish, graph=graph,
+                autotune=1)
     for w in range(warmup):
         s = ctx.run(pid, **opts)
         log(f"[bench] {name} warmup {w}: {s['sweeps']} sweeps ({s['polish_sweeps']} FP64) "

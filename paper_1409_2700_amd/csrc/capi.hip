@@ -638,14 +638,26 @@ mcpt_status ensure_lowp(mcpt_ctx* c, Exec& x, Resident* R, int prec) {
     R->lo_slot = (slot + 63) / 64 * 64;   // keeps every slot 16-byte aligned
     R->lo_v_bytes = (double)vo * es;
     R->lo_prec = prec;
+    // leading pairs whose V (and, for BF16, V^T) fit in LDS run in the LDS-resident kernel
+    R->lo_n_lds = 0;
+    R->lo_lds_bytes = 0;
+    while (R->lo_n_lds < R->n_pair) {
+        const PairDesc& d = R->pairs[R->lo_n_lds];
+        const int64_t b = lowp_lds_bytes(prec, R->monos[d.x].n, R->monos[d.y].n);
+        if (b > lowp_lds_limit()) break;
+        R->lo_lds_bytes = std::max(R->lo_lds_bytes, b);
+        ++R->lo_n_lds;
+    }
     return MCPT_OK;
 }
 
 // Per-stream scratch of the reduced-precision pair kernel (Tau and Tau^T per workgroup).
 mcpt_status ensure_scratch_lo(mcpt_ctx* c, Exec& x, const Resident* R, int prec) {
     const size_t es = prec == MCPT_BF16 ? 2 : 4;
-    x.grid_lo = std::max(8, c->n_cu * pair_lowp_blocks_per_cu(prec, R->lo_variant) / 8 * 8);
-    const size_t need = (size_t)R->lo_slot * es * x.grid_lo;
+    x.grid_lo = std::max(8, c->n_cu * pair_lowp_blocks_per_cu(prec, R->lo_variant, 0) / 8 * 8);
+    x.grid_lo_lds = R->lo_n_lds ? std::max(8, c->n_cu * pair_lowp_blocks_per_cu(prec, R->lo_variant, R->lo_lds_bytes) / 8 * 8)
+                                : 0;
+    const size_t need = (size_t)R->lo_slot * es * std::max(x.grid_lo, x.grid_lo_lds);
     if (need > x.scratch_lo_bytes) {
         HIP_TRY(hipStreamSynchronize(x.stream));
         if (x.d_scratch_lo) (void)hipFree(x.d_scratch_lo);
@@ -663,10 +675,17 @@ mcpt_status ensure_scratch_lo(mcpt_ctx* c, Exec& x, const Resident* R, int prec)
 }
 
 // `every`: cover the pairs of every cluster (the autotuner), not only those still iterating
+// Reduced-precision pair phase: the LDS-resident-V kernel for the leading pairs
+// that fit, then the L2 variant for the rest (same stream, so G accumulates in order).
 void lowp_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int source, bool every = false) {
-    launch_pair_lowp(R->lo_prec, R->lo_variant, R->d_pairs, R->n_pair, R->d_monos, R->d_dif, R->d_Vlo, R->d_lo_off,
-                     R->d_Mlo, R->d_mlo_off, G, x.d_scratch_lo, R->lo_slot, x.grid_lo, R->d_ed2, source, 1, nullptr,
-                     every ? nullptr : R->d_cl, x.stream);
+    const ClState* cl = every ? nullptr : R->d_cl;
+    const int64_t nl = R->lo_n_lds;
+    launch_pair_lowp(R->lo_prec, R->lo_variant, R->lo_lds_bytes, R->d_pairs, nl, R->d_monos, R->d_dif, R->d_Vlo,
+                     R->d_lo_off, R->d_Mlo, R->d_mlo_off, G, x.d_scratch_lo, R->lo_slot, x.grid_lo_lds, R->d_ed2,
+                     source, 1, nullptr, cl, x.stream);
+    launch_pair_lowp(R->lo_prec, R->lo_variant, 0, R->d_pairs + nl, R->n_pair - nl, R->d_monos, R->d_dif, R->d_Vlo,
+                     R->d_lo_off + nl, R->d_Mlo, R->d_mlo_off, G, x.d_scratch_lo, R->lo_slot, x.grid_lo, R->d_ed2,
+                     source, 1, nullptr, cl, x.stream);
 }
 
 void mixed_mono(mcpt_ctx* c, Exec& x, Resident* R, int mode, const double* G, double* Gz, bool lo_out, const Ctrl* ctrl) {
@@ -838,7 +857,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
             const std::array<int64_t, 6> key{(int64_t)(uintptr_t)x.d_scratch, (int64_t)(uintptr_t)x.d_scratch_lo,
                                              (int64_t)(uintptr_t)x.d_ctrl, x.scratch_slot,
                                              (int64_t)c->grid_lds * 1000000 + c->grid_glb,
-                                             (int64_t)x.grid_lo * 1000 + R->lo_variant};
+                                             ((int64_t)x.grid_lo * 10000 + x.grid_lo_lds) * 1000 + R->lo_variant};
             if (!R->graph || R->graph_prec != prec || R->graph_sweeps != gk || R->graph_key != key) {
                 drop_graph(R);
                 hipGraph_t g = nullptr;
@@ -936,7 +955,8 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
             const std::array<int64_t, 6> key{(int64_t)(uintptr_t)x.d_scratch, (int64_t)(uintptr_t)x.d_scratch_lo,
                                              (int64_t)(uintptr_t)x.d_ctrl, x.scratch_slot,
                                              (int64_t)c->grid_lds * 1000000 + c->grid_glb,
-                                             ((int64_t)x.grid_lo * 1000 + R->lo_variant) * 1000 + inner};
+                                             (((int64_t)x.grid_lo * 10000 + x.grid_lo_lds) * 1000 + R->lo_variant) * 1000 +
+                                                 inner};
             const int gprec = 16 + prec;
             if (!R->graph || R->graph_prec != gprec || R->graph_sweeps != gb || R->graph_key != key ||
                 R->graph_parity != cur) {

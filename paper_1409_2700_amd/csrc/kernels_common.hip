@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
             Tx[e_rc] += Dx[e_rc] - Rx[e_rc];
             continue;
         }
-        const double dinv = 1.0 / (dx[r] + dx[c]);
+        const double dinv = recip(dx[r] + dx[c]);
         double tn, ts, lo = 0.0;
         bool has_lo = false;
         if (mode == kMonoUpdate || mode == kMonoUpdateR) {

@@ -20,6 +20,19 @@ namespace mcpt {
 constexpr int kTile = 16;              // MFMA tile edge; matrices are padded to a multiple
 constexpr int kMaxSweeps = 4096;       // length of the device residual history
 
+// 1 / d for the denominators of Eqs. 60-61 (negative, |d| well above zero):
+// the hardware reciprocal estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - d r), each of which squares the relative error, so the
+// result is within an ulp or so of the quotient at a fraction of the cost of
+// an IEEE division.
+__device__ inline double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
 struct MonoDesc {
     int32_t o, v, n, np;
     int64_t eps_off;                   // first energy of X in eps
@@ -114,13 +127,17 @@ bool pair_fits_lds(int nX, int npY);
 int lowp_chunk(int precision);   // k chunk: rows of low-precision operands are padded to it
 void launch_convert_v(int precision, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
                       const double* V, void* Vlo, const int64_t* lo_off, hipStream_t s);
-// reduced-precision pair kernel: `variant` selects one of lowp_variants() tile shapes
+// reduced-precision pair kernel: `variant` selects one of lowp_variants() tile shapes;
+// lds_bytes > 0 selects the LDS-resident-V kernel with that much dynamic LDS
+// (every pair of the launch must need at most that much: lowp_lds_bytes)
 int lowp_variants();
 void lowp_variant_shape(int variant, int* sb, int* nw);
-int pair_lowp_blocks_per_cu(int precision, int variant);
-void launch_pair_lowp(int precision, int variant, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
-                      const double* dif, const void* Vlo, const int64_t* lo_off, const void* Mlo,
-                      const int64_t* mlo_off, double* G, void* scratch, int64_t slot_elems, int grid, double* ed2,
-                      int source, int couple, const Ctrl* ctrl, const ClState* cl, hipStream_t s);
+int64_t lowp_lds_bytes(int precision, int nX, int nY);
+int64_t lowp_lds_limit();
+int pair_lowp_blocks_per_cu(int precision, int variant, int64_t lds_bytes);
+void launch_pair_lowp(int precision, int variant, int64_t lds_bytes, const PairDesc* pairs, int64_t n_pair,
+                      const MonoDesc* monos, const double* dif, const void* Vlo, const int64_t* lo_off,
+                      const void* Mlo, const int64_t* mlo_off, double* G, void* scratch, int64_t slot_elems, int grid,
+                      double* ed2, int source, int couple, const Ctrl* ctrl, const ClState* cl, hipStream_t s);
 
 }  // namespace mcpt

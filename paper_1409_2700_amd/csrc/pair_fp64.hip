@@ -470,7 +470,7 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
                         const int r = (r0 + i) * 16 + acc_row(lane, t);
                         double tv = 0.0;
                         if (r < p.nX && c < p.nY) {
-                            const double dinv = 1.0 / (p.dX[r] + dc);
+                            const double dinv = recip(p.dX[r] + dc);
                             const double v = IN_LDS ? sV[r * p.ldv + c] : p.V[(int64_t)r * p.nY + c];
                             tv = dinv * (v + acc[i][j][t]);
                             epart += v * tv;

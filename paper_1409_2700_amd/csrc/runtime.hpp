@@ -55,6 +55,8 @@ struct Resident {
     // reduced-precision copies (mixed-precision form), made on first use of a precision
     int lo_prec = 0;
     int lo_variant = 0;           // tile shape of the reduced-precision pair kernel
+    int64_t lo_n_lds = 0;         // leading pairs served by the LDS-resident reduced-precision kernel
+    int64_t lo_lds_bytes = 0;     // dynamic LDS of that kernel (largest pair of the range)
     std::string shape_key;        // pair-shape signature used by the tile autotuner
     void *d_Vlo = nullptr, *d_Mlo = nullptr;
     int64_t *d_lo_off = nullptr, *d_mlo_off = nullptr;
@@ -99,7 +101,7 @@ struct Exec {
     int scratch_slots = 0;
     void* d_scratch_lo = nullptr;       // reduced-precision Tau and Tau^T
     size_t scratch_lo_bytes = 0;
-    int grid_lo = 0;
+    int grid_lo = 0, grid_lo_lds = 0;   // persistent grids of the reduced-precision kernels
     Timing timing;
     size_t reserved = 0;                // HBM reserved by admission for the upload in progress (mu)
 };
