@@ -26,6 +26,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def counted_traffic(sweeps: int):
+    """HBM-side bytes per pair-kernel launch from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (calibrated by a plain copy), averaged over
+    the timed launch mix (`sweeps` coupled launches and one energy pass); None
+    once the kernel sources differ from the ones the counters were taken on."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "pair_fp64_counters_hf-10x10x10-c3.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    for name, digest in re.findall(r"sha256 (\S+) ([0-9a-f]{64})", text):
+        src = os.path.join(ROOT, "paper_1409_2700_amd", "csrc", name)
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != digest:
+            return None
+    c = re.search(r"coupled_bytes_per_launch: ([0-9.e+]+)", text)
+    e = re.search(r"energy_bytes_per_launch: ([0-9.e+]+)", text)
+    if not (c and e):
+        return None
+    return (sweeps * float(c.group(1)) + float(e.group(1))) / (sweeps + 1)
+
+
 def cpu_baseline(prob, sweeps: int, budget_s: float = 12.0) -> dict:
     """The FP64 oracle as it stands, on a bounded sample of the same workload:
     bulk monomers and every pair touching them; Eq. 59 timed per pair and the
@@ -294,10 +316,11 @@ def batched(n_clusters, tol):
     return out
 
 
-def pmc_pass(workload: str, sweeps: int = 2):
+def pmc_pass(workload: str, precision: int = 0, sweeps: int = 2):
     """Counter pass for rocprofv3 --pmc: one device copy of a known size
-    (the calibration kernel), then `sweeps` fixed FP64 sweeps of the resident
-    workload and its final energy pass; nothing else is launched."""
+    (the calibration kernel), then `sweeps` fixed sweeps of the resident
+    workload in the given precision (no polish) and the final FP64 energy
+    pass; nothing else is launched."""
     import torch
     import paper_1409_2700_amd as mc
     from synth import make_workload
@@ -312,8 +335,9 @@ def pmc_pass(workload: str, sweeps: int = 2):
     del src, dst
     with mc.Context(0) as ctx:
         pid = ctx.upload(prob)
-        s = ctx.run(pid, tol=0.0, max_sweeps=sweeps)
-        log(f"[pmc] {workload}: {s['sweeps']} fixed sweeps + final pass, E={s['e_total']:.10f}")
+        s = ctx.run(pid, tol=0.0, max_sweeps=sweeps, precision=precision, polish=0)
+        log(f"[pmc] {workload}: {s['sweeps']} fixed sweeps (precision {precision}) + final pass, "
+            f"E={s['e_total']:.10f}")
 
 
 def main():
@@ -333,7 +357,8 @@ def main():
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=16)
     ap.add_argument("--pmc-pass", action="store_true",
-                    help="only launch a calibration copy and two FP64 sweeps (for rocprofv3 --pmc)")
+                    help="only launch a calibration copy and two fixed sweeps (for rocprofv3 --pmc)")
+    ap.add_argument("--pmc-precision", type=int, default=0, help="0 FP64, 1 FP32, 2 BF16 sweeps in --pmc-pass")
     ap.add_argument("--batched", type=int, default=0,
                     help="also time the batching form on this many uneven clusters (64 = full set)")
     args = ap.parse_args()
@@ -344,7 +369,7 @@ def main():
         sys.exit(2)
 
     if args.pmc_pass:
-        pmc_pass(args.workload)
+        pmc_pass(args.workload, args.pmc_precision)
         return
     import paper_1409_2700_amd as mc
     from synth import make_workload, DEFAULT_COUPLING_SCALE
@@ -404,7 +429,10 @@ def main():
         "e_total": h["e_total"],
         "roofline": {
             "bound": "mfma", "achieved": achieved, "peak": kpeak, "unit": "TFLOP/s",
-            "frac": achieved / kpeak, "traffic": None, "kernel": kname, "avg_launch_ms": avg_ms,
+            "frac": achieved / kpeak,
+            "traffic": counted_traffic(h["sweeps"]) if kname == "pair_fp64_lds_kernel" and args.workload == "hf-10x10x10-c3" else None,
+            "traffic_unit": "bytes per launch (L2-fabric, counters calibrated by a 1 GiB copy)",
+            "kernel": kname, "avg_launch_ms": avg_ms,
             "flops_per_launch": flops_per_launch, "launches": kl,
         },
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "timing"} for k, v in results.items()},

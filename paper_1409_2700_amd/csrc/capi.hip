@@ -603,7 +603,7 @@ mcpt_status ensure_lowp(mcpt_ctx* c, Exec& x, Resident* R, int prec) {
         lo_off[p] = vo;
         const int64_t sz = dx.np * ld(dy.n) + dy.np * ld(dx.n);
         vo += sz;
-        slot = std::max(slot, sz);
+        slot = std::max(slot, sz);   // scratch slot: Tau and Tau^T
     }
     int64_t mo = 0;
     for (int x = 0; x < R->n_mono; ++x) {

@@ -250,22 +250,24 @@ __global__ __launch_bounds__(kThreads) void convert_v_kernel(const PairDesc* __r
 }
 
 // Bytes of LDS the LDS-resident variant needs for a pair: V (npX rows) and,
-// for BF16, V^T (npY rows), each row padded by 16 bytes so that the 16-byte
-// fragment reads of 8 consecutive rows fall on distinct bank groups.
+// for BF16, V^T (npY rows) and Tau (npX rows), each row padded by 16 bytes so
+// that the 16-byte fragment reads of 8 consecutive rows fall on distinct bank
+// groups.
 template <class E>
 __host__ __device__ inline int lds_row(int ld) { return ld + 16 / (int)sizeof(E); }
 
 template <class E>
 __host__ __device__ inline int64_t lds_bytes(int npX, int npY, int ldX, int ldY) {
     int64_t b = (int64_t)npX * lds_row<E>(ldY) * sizeof(E);
-    if (sizeof(E) == 2) b += (int64_t)npY * lds_row<E>(ldX) * sizeof(E);
+    if (sizeof(E) == 2) b += (int64_t)npY * lds_row<E>(ldX) * sizeof(E) + (int64_t)npX * lds_row<E>(ldY) * sizeof(E);
     return b;
 }
 
 // One pair per workgroup iteration.  IN_LDS: V is staged in LDS once per pair
-// (BF16 also V^T; FP32 reads V^T fragments as columns of the staged V) and
-// every product takes one operand from LDS and the other (M_X, M_Y, Tau, Tau^T)
-// from L2; otherwise both operands come from L2.
+// (BF16 also V^T, and Tau is kept in LDS; FP32 reads V^T fragments as columns
+// of the staged V) and every product takes one operand from LDS and the other
+// (M_X, M_Y, Tau^T, and Tau for FP32) from L2 (BF16 G_X: both from LDS);
+// otherwise both operands come from L2.
 template <class E, int SB, int NW, bool IN_LDS>
 __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
     const PairDesc* __restrict__ pairs, int64_t n_pair, const MonoDesc* __restrict__ monos,
@@ -301,6 +303,7 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
         const int RB = npX / 16, CB = npY / 16;
         const int sldY = lds_row<E>(ldY), sldX = lds_row<E>(ldX);
         E* sVt = sV + (int64_t)npX * sldY;
+        E* sTau = sVt + (int64_t)npY * sldX;   // BF16 only
 
         if (IN_LDS) {   // stage V (and V^T) with 16-byte copies; padding rows and columns come zero
             constexpr int VE = 16 / sizeof(E);
@@ -355,7 +358,10 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
                             epart += v * tv;
                         }
                         tv4[t] = L::from(tv);
-                        if (couple) tau[(int64_t)r * ldY + c] = tv4[t];
+                        if (couple) {
+                            if (kVtLds) sTau[r * sldY + c] = tv4[t];
+                            else tau[(int64_t)r * ldY + c] = tv4[t];
+                        }
                     }
                     if (couple) {   // Tau^T row c, 4 consecutive columns
                         E* q = tauT + (int64_t)c * ldX + (r0 + i) * 16 + acc_row(lane, 0);
@@ -368,7 +374,8 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
         if (couple) {   // zero the k padding of Tau (columns npY..ldY) and Tau^T (columns npX..ldX)
             for (int idx = threadIdx.x; idx < npX * (ldY - npY); idx += kThreadsK) {
                 const int r = idx / (ldY - npY), c = npY + idx % (ldY - npY);
-                tau[(int64_t)r * ldY + c] = L::from(0.0);
+                if (kVtLds) sTau[r * sldY + c] = L::from(0.0);
+                else tau[(int64_t)r * ldY + c] = L::from(0.0);
             }
             for (int idx = threadIdx.x; idx < npY * (ldX - npX); idx += kThreadsK) {
                 const int r = idx / (ldX - npX), c = npX + idx % (ldX - npX);
@@ -405,7 +412,8 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
                 f4 acc[NR][NC];
                 zero(acc);
                 if (which == 0) {
-                    gemm<E, NR, NC>(Rows<E>{tau, ldY}, vrows(), ldY, r0, c0, lane, acc);
+                    if (kVtLds) gemm<E, NR, NC>(Rows<E>{sTau, sldY}, vrows(), ldY, r0, c0, lane, acc);
+                    else gemm<E, NR, NC>(Rows<E>{tau, ldY}, vrows(), ldY, r0, c0, lane, acc);
                     atomic_flush(GX, npX, nX, r0, c0, lane, acc);
                 } else {
                     if (kVtLds) gemm<E, NR, NC>(Rows<E>{tauT, ldX}, Rows<E>{sVt, sldX}, ldX, r0, c0, lane, acc);
