@@ -94,8 +94,10 @@ typedef struct {
     int32_t        precision;    /* mcpt_precision of the pair contractions */
     int32_t        polish;       /* reduced precision: 1 = FP64 defect-correction sweeps until the
                                     FP64 residual < tol; 0 = stop at the reduced-precision residual */
-    int32_t        deterministic;/* must be 0: G is accumulated with FP64 atomics, so results repeat
-                                    to rounding, not bitwise; 1 is rejected with MCPT_ERR_INVALID */
+    int32_t        deterministic;/* 0: the pair contributions to G (Eq. 58) are added with FP64 atomics,
+                                    results repeat to rounding; 1: each pair stores its blocks and a
+                                    per-monomer pass sums them in pair order, results repeat bitwise
+                                    (extra HBM: sum over pairs of (npX^2 + npY^2) doubles) */
     int32_t        check_every;  /* sweeps issued between host checks of the device residual (>= 1) */
     int32_t        inner_sweeps; /* reduced precision + polish: correction sweeps per FP64 sweep (0 = default) */
     const double  *warm_t;       /* NULL, or host T (layout of t_amp in mcpt_energy) to start from */

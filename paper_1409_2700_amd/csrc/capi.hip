@@ -37,6 +37,11 @@ const std::string& last_error_text() { return g_err; }
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+#ifndef MCPT_PAIR_BLOCK
+#define MCPT_PAIR_BLOCK 8
+#endif
+constexpr int kPairBlock = MCPT_PAIR_BLOCK;   // monomer block edge of the pair order (1: plain (min, max) order)
+
 mcpt_status ensure_device(mcpt_ctx* c) {
     HIP_TRY(hipSetDevice(c->device));
     return MCPT_OK;
@@ -56,6 +61,18 @@ void free_lowp(mcpt_ctx* c, Resident* r) {
     r->d_R = r->d_Dl = nullptr;
 }
 
+void free_det(mcpt_ctx* c, Resident* r) {
+    for (void* p : r->det_allocations) (void)hipFree(p);
+    r->det_allocations.clear();
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        c->in_use -= std::min(c->in_use, r->det_bytes);
+    }
+    r->det_bytes = 0;
+    r->d_part = nullptr;
+    r->d_part_off = r->d_csr_off = r->d_csr = nullptr;
+}
+
 void drop_graph(Resident* r) {
     if (r->graph) (void)hipGraphExecDestroy(r->graph);
     r->graph = nullptr;
@@ -64,6 +81,7 @@ void drop_graph(Resident* r) {
 
 void free_resident(mcpt_ctx* c, Resident* r) {
     drop_graph(r);
+    free_det(c, r);
     free_lowp(c, r);
     for (void* p : r->allocations) (void)hipFree(p);
     r->allocations.clear();
@@ -312,12 +330,18 @@ mcpt_status upload_batch(mcpt_ctx* c, Exec& x, const mcpt_problem* pbs, int n_cl
     {
         const std::vector<MonoDesc>& m = r->monos;
         auto lds = [&m](const PairDesc& d) { return pair_fits_lds(m[d.x].n, m[d.y].np); };
+        // within each range: blocks of kPairBlock x kPairBlock monomers (lower, upper index), so
+        // that the pairs an XCD works on at a time share few monomers' M and G blocks
+        const int B = kPairBlock;
         std::stable_sort(r->pairs.begin(), r->pairs.end(), [&](const PairDesc& a, const PairDesc& b) {
             const bool la = lds(a), lb = lds(b);
             if (la != lb) return la;
             const int a0 = std::min(a.x, a.y), b0 = std::min(b.x, b.y);
+            const int a1 = std::max(a.x, a.y), b1 = std::max(b.x, b.y);
+            if (a0 / B != b0 / B) return a0 / B < b0 / B;
+            if (a1 / B != b1 / B) return a1 / B < b1 / B;
             if (a0 != b0) return a0 < b0;
-            return std::max(a.x, a.y) < std::max(b.x, b.y);
+            return a1 < b1;
         });
         r->n_lds = std::count_if(r->pairs.begin(), r->pairs.end(), lds);
     }
@@ -556,8 +580,7 @@ mcpt_status validate_options(const mcpt_options* o) {
         return fail(MCPT_ERR_INVALID, "precision must be MCPT_FP64, MCPT_FP32 or MCPT_BF16");
     if (o->check_every < 0) return fail(MCPT_ERR_INVALID, "check_every must be >= 0");
     if (o->inner_sweeps < 0 || o->inner_sweeps > 64) return fail(MCPT_ERR_INVALID, "inner_sweeps must be in [0, 64]");
-    if (o->deterministic != 0)
-        return fail(MCPT_ERR_INVALID, "deterministic (atomic-free) accumulation is not available in this library");
+    if (o->deterministic != 0 && o->deterministic != 1) return fail(MCPT_ERR_INVALID, "deterministic must be 0 or 1");
     if (o->graph != 0 && o->graph != 1) return fail(MCPT_ERR_INVALID, "graph must be 0 or 1");
     if (o->autotune != 0 && o->autotune != 1) return fail(MCPT_ERR_INVALID, "autotune must be 0 or 1");
     return MCPT_OK;
@@ -580,10 +603,75 @@ void record_end(Exec& x, hipEvent_t a, int kind, double flops, double vbytes) {
 // then the L2 variant for the rest (same stream, so G accumulates in order).
 void pair_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int couple, const Ctrl* ctrl) {
     const ClState* cl = ctrl ? R->d_cl : nullptr;   // the final energy pass covers every cluster
-    launch_pair_fp64(1, R->d_pairs, R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G, x.d_scratch,
+    const bool det = R->det_on && couple;
+    const PartOut p0{det ? R->d_part : nullptr, R->d_part_off};
+    const PartOut p1{det ? R->d_part : nullptr, R->d_part_off ? R->d_part_off + R->n_lds : nullptr};
+    launch_pair_fp64(1, p0, R->d_pairs, R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G, x.d_scratch,
                      x.scratch_slot, c->grid_lds, R->d_ed2, couple, ctrl, cl, x.stream);
-    launch_pair_fp64(0, R->d_pairs + R->n_lds, R->n_pair - R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G,
+    launch_pair_fp64(0, p1, R->d_pairs + R->n_lds, R->n_pair - R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G,
                      x.d_scratch, x.scratch_slot, c->grid_glb, R->d_ed2, couple, ctrl, cl, x.stream);
+    if (det) launch_reduce_parts(R->d_monos, R->n_mono, R->d_csr_off, R->d_csr, R->d_part, G, R->d_cl, ctrl, x.stream);
+}
+
+// Buffers of the deterministic mode: a partial G_X and G_Y block per pair and,
+// per monomer, the offsets of its blocks in pair order (the summation order).
+mcpt_status ensure_det(mcpt_ctx* c, Exec& x, Resident* R) {
+    if (R->d_part) return MCPT_OK;
+    std::vector<int64_t> off(std::max<int64_t>(R->n_pair, 1), 0);
+    std::vector<std::vector<std::pair<int64_t, int64_t>>> per(R->n_mono);   // (caller pair index, offset)
+    int64_t tot = 0;
+    for (int64_t p = 0; p < R->n_pair; ++p) {
+        const PairDesc& d = R->pairs[p];
+        const int64_t nx = R->monos[d.x].np, ny = R->monos[d.y].np;
+        off[p] = tot;
+        per[d.x].push_back({d.orig, tot});
+        per[d.y].push_back({d.orig, tot + nx * nx});
+        tot += nx * nx + ny * ny;
+    }
+    std::vector<int64_t> csr_off(R->n_mono + 1, 0), csr;
+    csr.reserve(2 * R->n_pair);
+    for (int m = 0; m < R->n_mono; ++m) {
+        std::sort(per[m].begin(), per[m].end());
+        for (const auto& e : per[m]) csr.push_back(e.second);
+        csr_off[m + 1] = (int64_t)csr.size();
+    }
+    if (csr.empty()) csr.push_back(0);
+    void *part = nullptr, *o = nullptr, *co = nullptr, *cs = nullptr;
+    mcpt_status st;
+    auto alloc = [&](void** out, size_t bytes) -> mcpt_status {
+        bytes = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+        {
+            std::lock_guard<std::mutex> g(c->mu);
+            if (c->in_use + (c->reserved - x.reserved) + bytes > c->budget)
+                return fail(MCPT_ERR_ADMISSION, "deterministic-mode partials (" + std::to_string(bytes) +
+                                                    " bytes) exceed the HBM budget");
+        }
+        hipError_t e = hipMalloc(out, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MCPT_ERR_NOMEM, "hipMalloc of deterministic-mode partials failed");
+        }
+        R->det_allocations.push_back(*out);
+        R->det_bytes += bytes;
+        std::lock_guard<std::mutex> g(c->mu);
+        c->in_use += bytes;
+        return MCPT_OK;
+    };
+    if ((st = alloc(&part, (size_t)std::max<int64_t>(tot, 1) * 8)) != MCPT_OK ||
+        (st = alloc(&o, off.size() * 8)) != MCPT_OK || (st = alloc(&co, csr_off.size() * 8)) != MCPT_OK ||
+        (st = alloc(&cs, csr.size() * 8)) != MCPT_OK) {
+        free_det(c, R);
+        return st;
+    }
+    HIP_TRY(hipMemcpyAsync(o, off.data(), off.size() * 8, hipMemcpyHostToDevice, x.stream));
+    HIP_TRY(hipMemcpyAsync(co, csr_off.data(), csr_off.size() * 8, hipMemcpyHostToDevice, x.stream));
+    HIP_TRY(hipMemcpyAsync(cs, csr.data(), csr.size() * 8, hipMemcpyHostToDevice, x.stream));
+    HIP_TRY(hipStreamSynchronize(x.stream));
+    R->d_part = static_cast<double*>(part);
+    R->d_part_off = static_cast<int64_t*>(o);
+    R->d_csr_off = static_cast<int64_t*>(co);
+    R->d_csr = static_cast<int64_t*>(cs);
+    return MCPT_OK;
 }
 
 // Reduced-precision copies of a resident problem for `prec` (1 FP32, 2 BF16):
@@ -680,12 +768,16 @@ mcpt_status ensure_scratch_lo(mcpt_ctx* c, Exec& x, const Resident* R, int prec)
 void lowp_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int source, bool every = false) {
     const ClState* cl = every ? nullptr : R->d_cl;
     const int64_t nl = R->lo_n_lds;
-    launch_pair_lowp(R->lo_prec, R->lo_variant, R->lo_lds_bytes, R->d_pairs, nl, R->d_monos, R->d_dif, R->d_Vlo,
+    const bool det = R->det_on && !every;
+    const PartOut p0{det ? R->d_part : nullptr, R->d_part_off};
+    const PartOut p1{det ? R->d_part : nullptr, R->d_part_off ? R->d_part_off + nl : nullptr};
+    launch_pair_lowp(R->lo_prec, R->lo_variant, R->lo_lds_bytes, p0, R->d_pairs, nl, R->d_monos, R->d_dif, R->d_Vlo,
                      R->d_lo_off, R->d_Mlo, R->d_mlo_off, G, x.d_scratch_lo, R->lo_slot, x.grid_lo_lds, R->d_ed2,
                      source, 1, nullptr, cl, x.stream);
-    launch_pair_lowp(R->lo_prec, R->lo_variant, 0, R->d_pairs + nl, R->n_pair - nl, R->d_monos, R->d_dif, R->d_Vlo,
+    launch_pair_lowp(R->lo_prec, R->lo_variant, 0, p1, R->d_pairs + nl, R->n_pair - nl, R->d_monos, R->d_dif, R->d_Vlo,
                      R->d_lo_off + nl, R->d_Mlo, R->d_mlo_off, G, x.d_scratch_lo, R->lo_slot, x.grid_lo, R->d_ed2,
                      source, 1, nullptr, cl, x.stream);
+    if (det) launch_reduce_parts(R->d_monos, R->n_mono, R->d_csr_off, R->d_csr, R->d_part, G, R->d_cl, nullptr, x.stream);
 }
 
 void mixed_mono(mcpt_ctx* c, Exec& x, Resident* R, int mode, const double* G, double* Gz, bool lo_out, const Ctrl* ctrl) {
@@ -777,6 +869,8 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
     if (st != MCPT_OK) return st;
     if ((st = ensure_device(c)) != MCPT_OK) return st;
     if ((st = ensure_scratch(c, x, R->max_slot)) != MCPT_OK) return st;
+    R->det_on = o->deterministic != 0;
+    if (R->det_on && (st = ensure_det(c, x, R)) != MCPT_OK) return st;
     const int prec = o->precision;
     if (prec != MCPT_FP64) {
         if ((st = ensure_lowp(c, x, R, prec)) != MCPT_OK) return st;
@@ -858,7 +952,8 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
                                              (int64_t)(uintptr_t)x.d_ctrl, x.scratch_slot,
                                              (int64_t)c->grid_lds * 1000000 + c->grid_glb,
                                              ((int64_t)x.grid_lo * 10000 + x.grid_lo_lds) * 1000 + R->lo_variant};
-            if (!R->graph || R->graph_prec != prec || R->graph_sweeps != gk || R->graph_key != key) {
+            const int gprec = prec + (R->det_on ? 8 : 0);
+            if (!R->graph || R->graph_prec != gprec || R->graph_sweeps != gk || R->graph_key != key) {
                 drop_graph(R);
                 hipGraph_t g = nullptr;
                 HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -871,7 +966,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
                     R->graph = nullptr;
                     return fail(MCPT_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
                 }
-                R->graph_prec = prec;
+                R->graph_prec = gprec;
                 R->graph_sweeps = gk;
                 R->graph_key = key;
             }
@@ -957,7 +1052,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
                                              (int64_t)c->grid_lds * 1000000 + c->grid_glb,
                                              (((int64_t)x.grid_lo * 10000 + x.grid_lo_lds) * 1000 + R->lo_variant) * 1000 +
                                                  inner};
-            const int gprec = 16 + prec;
+            const int gprec = 16 + prec + (R->det_on ? 8 : 0);
             if (!R->graph || R->graph_prec != gprec || R->graph_sweeps != gb || R->graph_key != key ||
                 R->graph_parity != cur) {
                 drop_graph(R);

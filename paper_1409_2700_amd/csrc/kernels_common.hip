@@ -295,6 +295,27 @@ __global__ void reduce_total_kernel(int n_cl, const ClState* __restrict__ cl, Ct
     ctrl->e_mono0 = tc;
 }
 
+// Deterministic G: G_X[e] = sum over the monomer's stored partial blocks, in
+// pair order (one workgroup per monomer, threads over the np^2 elements).
+__global__ __launch_bounds__(256) void reduce_parts_kernel(const MonoDesc* __restrict__ monos,
+                                                           const int64_t* __restrict__ csr_off,
+                                                           const int64_t* __restrict__ csr,
+                                                           const double* __restrict__ part, double* __restrict__ G,
+                                                           const ClState* __restrict__ cl,
+                                                           const Ctrl* __restrict__ ctrl) {
+    if (ctrl && ctrl->done) return;
+    const MonoDesc d = monos[blockIdx.x];
+    if (cl && cl[d.cluster].done) return;
+    const int64_t e0 = csr_off[blockIdx.x], e1 = csr_off[blockIdx.x + 1];
+    const int64_t nn = (int64_t)d.np * d.np;
+    double* g = G + d.mat_off;
+    for (int64_t k = threadIdx.x; k < nn; k += 256) {
+        double sum = 0.0;
+        for (int64_t e = e0; e < e1; ++e) sum += part[csr[e] + k];
+        g[k] = sum;
+    }
+}
+
 int grid_for(int64_t n, int threads) {
     int64_t g = (n + threads - 1) / threads;
     if (g < 1) g = 1;
@@ -351,6 +372,12 @@ void launch_reduce_sweep(int n_cl, const int64_t* cl_mono, const double* res, Cl
                          Ctrl* ctrl, hipStream_t s) {
     hipLaunchKernelGGL(reduce_sweep_kernel, dim3(n_cl), dim3(kReduceThreads), 0, s, cl_mono, res, cl, hist, ctrl);
     hipLaunchKernelGGL(reduce_ctrl_kernel, dim3(1), dim3(kReduceThreads), 0, s, n_cl, cl, ctrl);
+}
+
+void launch_reduce_parts(const MonoDesc* monos, int n_mono, const int64_t* csr_off, const int64_t* csr,
+                         const double* part, double* G, const ClState* cl, const Ctrl* ctrl, hipStream_t s) {
+    if (n_mono <= 0) return;
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(n_mono), dim3(256), 0, s, monos, csr_off, csr, part, G, cl, ctrl);
 }
 
 void launch_reduce_final(int n_cl, const int64_t* cl_mono, const int64_t* cl_pair, const double* em2,

@@ -33,6 +33,14 @@ __device__ inline double recip(double d) {
     return __builtin_fma(r, e, r);
 }
 
+// Deterministic accumulation: instead of adding its G_X and G_Y blocks to G
+// with atomics, pair p stores them at part + off[p] (np_X^2 values, then
+// np_Y^2), and a per-monomer kernel sums the stored blocks in pair order.
+struct PartOut {
+    double* part;            // nullptr: FP64 atomics into G
+    const int64_t* off;      // per pair of the launch
+};
+
 struct MonoDesc {
     int32_t o, v, n, np;
     int64_t eps_off;                   // first energy of X in eps
@@ -108,6 +116,10 @@ void launch_monomer_mixed(int mode, int precision, const MonoDesc* monos, int n_
                           double* res, const Ctrl* ctrl, const ClState* cl, hipStream_t s);
 void launch_reduce_sweep(int n_cl, const int64_t* cl_mono, const double* res, ClState* cl, double* hist,
                          Ctrl* ctrl, hipStream_t s);
+// G_X = sum of the stored partial blocks of monomer X (csr[csr_off[X] .. csr_off[X+1]):
+// offsets into part, in pair order); skips stopped clusters
+void launch_reduce_parts(const MonoDesc* monos, int n_mono, const int64_t* csr_off, const int64_t* csr,
+                         const double* part, double* G, const ClState* cl, const Ctrl* ctrl, hipStream_t s);
 void launch_reduce_final(int n_cl, const int64_t* cl_mono, const int64_t* cl_pair, const double* em2,
                          const double* em2_0, const double* ed2, ClState* cl, Ctrl* ctrl, hipStream_t s);
 
@@ -116,7 +128,7 @@ void launch_reduce_final(int n_cl, const int64_t* cl_mono, const int64_t* cl_pai
 // G_X += Tau V^T, G_Y += Tau^T V for every pair; E_D2 of every pair.  Two
 // variants: lds_variant = 1 stages V in LDS (pairs with pair_fits_lds), 0 reads
 // V from L2 (any size).
-void launch_pair_fp64(int lds_variant, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
+void launch_pair_fp64(int lds_variant, PartOut po, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
                       const double* dif, const double* V, const double* M, double* G,
                       double* scratch, int64_t slot_elems, int grid, double* ed2, int couple,
                       const Ctrl* ctrl, const ClState* cl, hipStream_t s);
@@ -135,7 +147,7 @@ void lowp_variant_shape(int variant, int* sb, int* nw);
 int64_t lowp_lds_bytes(int precision, int nX, int nY);
 int64_t lowp_lds_limit();
 int pair_lowp_blocks_per_cu(int precision, int variant, int64_t lds_bytes);
-void launch_pair_lowp(int precision, int variant, int64_t lds_bytes, const PairDesc* pairs, int64_t n_pair,
+void launch_pair_lowp(int precision, int variant, int64_t lds_bytes, PartOut po, const PairDesc* pairs, int64_t n_pair,
                       const MonoDesc* monos, const double* dif, const void* Vlo, const int64_t* lo_off,
                       const void* Mlo, const int64_t* mlo_off, double* G, void* scratch, int64_t slot_elems, int grid,
                       double* ed2, int source, int couple, const Ctrl* ctrl, const ClState* cl, hipStream_t s);

@@ -358,8 +358,10 @@ __device__ inline void for_tasks(const Grid& g0, const Grid& g1, int wave, int n
     }
 }
 
+// G block contributions: FP64 atomics into G, or (deterministic mode) plain
+// stores of the whole padded block into the pair's partial slot
 template <int NR, int NC>
-__device__ inline void atomic_flush(double* G, int ld, int n, int r0, int q0, int lane,
+__device__ inline void atomic_flush(double* G, double* part, int ld, int n, int r0, int q0, int lane,
                                     const d4 (&acc)[NR][NC]) {
 #pragma unroll
     for (int i = 0; i < NR; ++i)
@@ -369,7 +371,8 @@ __device__ inline void atomic_flush(double* G, int ld, int n, int r0, int q0, in
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int r = (r0 + i) * 16 + acc_row(lane, t);
-                if (r < n && c < n) unsafeAtomicAdd(G + (int64_t)r * ld + c, acc[i][j][t]);
+                if (part) part[(int64_t)r * ld + c] = acc[i][j][t];
+                else if (r < n && c < n) unsafeAtomicAdd(G + (int64_t)r * ld + c, acc[i][j][t]);
             }
         }
 }
@@ -415,7 +418,7 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
                                  const double* __restrict__ V, const double* __restrict__ M,
                                  double* __restrict__ G, double* __restrict__ scratch, int64_t slot_elems,
                                  double* __restrict__ ed2, int couple, const ClState* __restrict__ cl,
-                                 double* sV, double* red) {
+                                 PartOut po, double* sV, double* red) {
     constexpr int NW = NT / 64;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double* tau = scratch + (int64_t)blockIdx.x * slot_elems;
@@ -505,11 +508,12 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
                 if (which == 0) {
                     if (IN_LDS) gx_sb_lds(p, sV, tau, r0, c0, lane, acc);
                     else gx_sb_glb(p, tau, r0, c0, lane, acc);
-                    atomic_flush(p.GX, p.npX, p.nX, r0, c0, lane, acc);
+                    atomic_flush(p.GX, po.part ? po.part + po.off[pi] : nullptr, p.npX, p.nX, r0, c0, lane, acc);
                 } else {
                     if (IN_LDS) gy_sb_lds(p, sV, tau, r0, c0, lane, acc);
                     else gy_sb_glb(p, tau, r0, c0, lane, acc);
-                    atomic_flush(p.GY, p.npY, p.nY, r0, c0, lane, acc);
+                    atomic_flush(p.GY, po.part ? po.part + po.off[pi] + (int64_t)p.npX * p.npX : nullptr, p.npY,
+                                 p.nY, r0, c0, lane, acc);
                 }
             });
         }
@@ -523,11 +527,12 @@ __global__ __launch_bounds__(kThreadsL) void pair_fp64_lds_kernel(
     const double* __restrict__ dif, const double* __restrict__ V, const double* __restrict__ M,
     double* __restrict__ G, double* __restrict__ scratch, int64_t slot_elems,
     double* __restrict__ ed2, int couple, const Ctrl* __restrict__ ctrl,
-    const ClState* __restrict__ cl) {
+    const ClState* __restrict__ cl, PartOut po) {
     if (ctrl && ctrl->done) return;
     __shared__ __align__(16) double sV[kLdsV];
     __shared__ double red[kThreadsL / 64];
-    pair_body<true, kThreadsL>(pairs, n_pair, monos, dif, V, M, G, scratch, slot_elems, ed2, couple, cl, sV, red);
+    pair_body<true, kThreadsL>(pairs, n_pair, monos, dif, V, M, G, scratch, slot_elems, ed2, couple, cl, po, sV,
+                               red);
 }
 
 __global__ __launch_bounds__(kThreadsG, 2) void pair_fp64_glb_kernel(
@@ -535,10 +540,10 @@ __global__ __launch_bounds__(kThreadsG, 2) void pair_fp64_glb_kernel(
     const double* __restrict__ dif, const double* __restrict__ V, const double* __restrict__ M,
     double* __restrict__ G, double* __restrict__ scratch, int64_t slot_elems,
     double* __restrict__ ed2, int couple, const Ctrl* __restrict__ ctrl,
-    const ClState* __restrict__ cl) {
+    const ClState* __restrict__ cl, PartOut po) {
     if (ctrl && ctrl->done) return;
     __shared__ double red[kThreadsG / 64];
-    pair_body<false, kThreadsG>(pairs, n_pair, monos, dif, V, M, G, scratch, slot_elems, ed2, couple, cl,
+    pair_body<false, kThreadsG>(pairs, n_pair, monos, dif, V, M, G, scratch, slot_elems, ed2, couple, cl, po,
                                 nullptr, red);
 }
 
@@ -555,17 +560,17 @@ int pair_fp64_blocks_per_cu(int lds_variant) {
 
 bool pair_fits_lds(int nX, int npY) { return (int64_t)nX * (npY + 2) <= kLdsV; }
 
-void launch_pair_fp64(int lds_variant, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
+void launch_pair_fp64(int lds_variant, PartOut po, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
                       const double* dif, const double* V, const double* M, double* G, double* scratch,
                       int64_t slot_elems, int grid, double* ed2, int couple, const Ctrl* ctrl, const ClState* cl,
                       hipStream_t s) {
     if (n_pair <= 0) return;
     if (lds_variant)
         hipLaunchKernelGGL(pair_fp64_lds_kernel, dim3(grid), dim3(kThreadsL), 0, s, pairs, n_pair, monos, dif, V,
-                           M, G, scratch, slot_elems, ed2, couple, ctrl, cl);
+                           M, G, scratch, slot_elems, ed2, couple, ctrl, cl, po);
     else
         hipLaunchKernelGGL(pair_fp64_glb_kernel, dim3(grid), dim3(kThreadsG), 0, s, pairs, n_pair, monos, dif, V,
-                           M, G, scratch, slot_elems, ed2, couple, ctrl, cl);
+                           M, G, scratch, slot_elems, ed2, couple, ctrl, cl, po);
 }
 
 }  // namespace mcpt

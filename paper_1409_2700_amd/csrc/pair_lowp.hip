@@ -196,7 +196,8 @@ __device__ inline int acc_row(int lane, int t) { return ((lane >> 4) << 2) + t; 
 __device__ inline int acc_col(int lane) { return lane & 15; }
 
 template <int NR, int NC>
-__device__ inline void atomic_flush(double* G, int ld, int n, int r0, int q0, int lane, const f4 (&acc)[NR][NC]) {
+__device__ inline void atomic_flush(double* G, double* part, int ld, int n, int r0, int q0, int lane,
+                                    const f4 (&acc)[NR][NC]) {
 #pragma unroll
     for (int i = 0; i < NR; ++i)
 #pragma unroll
@@ -205,7 +206,8 @@ __device__ inline void atomic_flush(double* G, int ld, int n, int r0, int q0, in
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int r = (r0 + i) * 16 + acc_row(lane, t);
-                if (r < n && c < n) unsafeAtomicAdd(G + (int64_t)r * ld + c, (double)acc[i][j][t]);
+                if (part) part[(int64_t)r * ld + c] = (double)acc[i][j][t];
+                else if (r < n && c < n) unsafeAtomicAdd(G + (int64_t)r * ld + c, (double)acc[i][j][t]);
             }
         }
 }
@@ -274,7 +276,7 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
     const double* __restrict__ dif, const E* __restrict__ Vlo, const int64_t* __restrict__ lo_off,
     const E* __restrict__ Mlo, const int64_t* __restrict__ mlo_off, double* __restrict__ G,
     E* __restrict__ scratch, int64_t slot_elems, double* __restrict__ ed2, int source, int couple,
-    const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
+    const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl, PartOut po) {
     typedef Lowp<E> L;
     constexpr int kThreadsK = NW * 64;
     constexpr bool kVtLds = IN_LDS && sizeof(E) == 2;
@@ -414,12 +416,13 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
                 if (which == 0) {
                     if (kVtLds) gemm<E, NR, NC>(Rows<E>{sTau, sldY}, vrows(), ldY, r0, c0, lane, acc);
                     else gemm<E, NR, NC>(Rows<E>{tau, ldY}, vrows(), ldY, r0, c0, lane, acc);
-                    atomic_flush(GX, npX, nX, r0, c0, lane, acc);
+                    atomic_flush(GX, po.part ? po.part + po.off[pi] : nullptr, npX, nX, r0, c0, lane, acc);
                 } else {
                     if (kVtLds) gemm<E, NR, NC>(Rows<E>{tauT, ldX}, Rows<E>{sVt, sldX}, ldX, r0, c0, lane, acc);
                     else if (IN_LDS) gemm<E, NR, NC>(Rows<E>{tauT, ldX}, Cols<E>{sV, sldY}, ldX, r0, c0, lane, acc);
                     else gemm<E, NR, NC>(Rows<E>{tauT, ldX}, Rows<E>{Vt, ldX}, ldX, r0, c0, lane, acc);
-                    atomic_flush(GY, npY, nY, r0, c0, lane, acc);
+                    atomic_flush(GY, po.part ? po.part + po.off[pi] + (int64_t)npX * npX : nullptr, npY, nY, r0, c0,
+                                 lane, acc);
                 }
             });
         }
@@ -491,14 +494,14 @@ void launch_convert_v(int precision, const PairDesc* pairs, int64_t n_pair, cons
                            static_cast<float*>(Vlo), lo_off);
 }
 
-void launch_pair_lowp(int precision, int variant, int64_t lds_bytes, const PairDesc* pairs, int64_t n_pair,
+void launch_pair_lowp(int precision, int variant, int64_t lds_bytes, PartOut po, const PairDesc* pairs, int64_t n_pair,
                       const MonoDesc* monos, const double* dif, const void* Vlo, const int64_t* lo_off,
                       const void* Mlo, const int64_t* mlo_off, double* G, void* scratch, int64_t slot_elems, int grid,
                       double* ed2, int source, int couple, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
     if (n_pair <= 0) return;
     void* args[] = {(void*)&pairs, (void*)&n_pair, (void*)&monos, (void*)&dif, (void*)&Vlo, (void*)&lo_off,
                     (void*)&Mlo, (void*)&mlo_off, (void*)&G, (void*)&scratch, (void*)&slot_elems, (void*)&ed2,
-                    (void*)&source, (void*)&couple, (void*)&ctrl, (void*)&cl};
+                    (void*)&source, (void*)&couple, (void*)&ctrl, (void*)&cl, (void*)&po};
     (void)hipLaunchKernel(lowp_kernel(precision, variant, lds_bytes > 0), dim3(grid),
                           dim3(lowp_variant_threads(variant)), args, (size_t)std::max<int64_t>(lds_bytes, 0), s);
 }

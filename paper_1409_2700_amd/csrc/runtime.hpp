@@ -69,6 +69,12 @@ struct Resident {
     hipGraphExec_t graph = nullptr;
     int graph_prec = -1, graph_sweeps = 0, graph_parity = 0;
     std::array<int64_t, 6> graph_key{};   // buffers and grids baked into the captured launches
+    // deterministic mode: per-pair partial G blocks and their per-monomer summation lists
+    bool det_on = false;
+    double* d_part = nullptr;
+    int64_t *d_part_off = nullptr, *d_csr_off = nullptr, *d_csr = nullptr;
+    std::vector<void*> det_allocations;
+    size_t det_bytes = 0;
     // served batches: owned by the scheduler, never visible to the caller under this id
     bool internal = false;
     int refs = 0;                 // tickets still holding this batch's results

@@ -154,7 +154,7 @@ def test_graph_fixed_sweeps_odd_count(ctx, clusters):
 
 def test_options_rejected(ctx, clusters):
     pid = ctx.upload(clusters[0])
-    for bad in (dict(deterministic=1), dict(graph=2)):
+    for bad in (dict(deterministic=2), dict(graph=2)):
         with pytest.raises(mc.MCPTError) as ei:
             ctx.run(pid, tol=1e-10, **bad)
         assert ei.value.status == mc.MCPT_ERR_INVALID

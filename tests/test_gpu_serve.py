@@ -159,7 +159,7 @@ def test_submit_errors_and_cancel(requests):
             ctx.submit(bad_eps, tol=1e-10)
         assert ei.value.status == mc.MCPT_ERR_NONFINITE
         with pytest.raises(mc.MCPTError) as ei:
-            ctx.submit(p, tol=1e-10, deterministic=1)
+            ctx.submit(p, tol=1e-10, deterministic=2)
         assert ei.value.status == mc.MCPT_ERR_INVALID
         with pytest.raises(mc.MCPTError) as ei:
             ctx.poll(123456789)
