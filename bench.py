@@ -275,7 +275,8 @@ def batched(n_clusters, tol):
         t0 = time.time()
         out["tuning"] = ctx.autotune(pid, mc.MCPT_FP32)
         out["tuning"]["seconds"] = time.time() - t0
-        log(f"[batch] tuned: " + ", ".join(f"{v['sb']}x{v['nw']}:{v['ms']:.1f}ms" for v in out["tuning"]["variants"]))
+        log(f"[batch] tuned: " + ", ".join(f"{v['sb']}x{v['nw']}/{v['pd']}:{v['ms']:.1f}ms"
+                                          for v in out["tuning"]["variants"]))
         for name, prec in (("fp32+polish", mc.MCPT_FP32), ("fp64", mc.MCPT_FP64)):
             opts = dict(tol=tol, precision=prec, polish=1, graph=1, autotune=1)
             ctx.run(pid, **opts)   # warm-up (captures the graph)

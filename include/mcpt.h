@@ -99,7 +99,8 @@ typedef struct {
                                     per-monomer pass sums them in pair order, results repeat bitwise
                                     (extra HBM: sum over pairs of (npX^2 + npY^2) doubles) */
     int32_t        check_every;  /* sweeps issued between host checks of the device residual (>= 1) */
-    int32_t        inner_sweeps; /* reduced precision + polish: correction sweeps per FP64 sweep (0 = default) */
+    int32_t        inner_sweeps; /* reduced precision + polish: correction sweeps per FP64 sweep
+                                    (0 = default: 4 for BF16, 6 for FP32) */
     const double  *warm_t;       /* NULL, or host T (layout of t_amp in mcpt_energy) to start from */
     int32_t        graph;        /* 1: capture the sweeps issued between host checks in a HIP graph and
                                     replay it (per-launch timing is not recorded then) */
@@ -205,17 +206,19 @@ mcpt_status mcpt_release(mcpt_ctx *ctx, uint64_t id);
 
 /* ---- Tile autotuner of the reduced-precision pair kernel ----
  * The kernel exists in several tile shapes: each wave computes sb x sb output
- * tiles of 16 x 16 per task, nw waves per workgroup.  mcpt_autotune times one
+ * tiles of 16 x 16 per task, nw waves per workgroup, pd k chunks loaded ahead.  mcpt_autotune times one
  * coupled pair phase of the resident problem per shape and keeps the fastest,
  * for this problem and, under its pair-shape key (block shapes and their share
  * of the flops, pair count to a power of two), for every later problem of the
  * context with the same key.  It overwrites the problem's last results (run it
  * again afterwards).  The table can be saved and restored as text lines
- * "key sb nw". */
+ * "key sb nw pd". */
 typedef struct {
     int32_t n_variants;     /* shapes timed */
     int32_t best;           /* index of the fastest */
-    int32_t sb[16], nw[16]; /* shape of each */
+    int32_t sb[16], nw[16]; /* tiles per task edge and waves per workgroup of each */
+    int32_t pd[16];         /* k chunks of operand fragments loaded ahead of the MFMAs */
+    int32_t reserved;
     double  ms[16];         /* one coupled pair phase, milliseconds */
 } mcpt_tune_result;
 

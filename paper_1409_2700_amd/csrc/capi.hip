@@ -857,7 +857,7 @@ mcpt_status autotune(mcpt_ctx* c, Exec& x, Resident* R, int prec, mcpt_tune_resu
         out->n_variants = nv;
         out->best = best;
         for (int v = 0; v < nv; ++v) {
-            lowp_variant_shape(v, &out->sb[v], &out->nw[v]);
+            lowp_variant_shape(v, &out->sb[v], &out->nw[v], &out->pd[v]);
             out->ms[v] = ms[v];
         }
     }
@@ -925,7 +925,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
     const int every = o->check_every > 0 ? o->check_every : 1;
     int cur = 0, n_lo = 0, n_hi = 0;
     const bool timing_on = x.timing.on && !o->graph;
-    const int inner = o->inner_sweeps > 0 ? o->inner_sweeps : (prec == MCPT_BF16 ? 3 : 5);
+    const int inner = o->inner_sweeps > 0 ? o->inner_sweeps : (prec == MCPT_BF16 ? 4 : 6);   // measured best at 1000 monomers
     const int n_pre = std::min(inner + 1, o->max_sweeps);
     const bool saved_timing = x.timing.on;
     x.timing.on = timing_on;
@@ -1334,9 +1334,9 @@ mcpt_status mcpt_tune_export(mcpt_ctx* c, char* buf, size_t cap, size_t* len) {
     {
         std::lock_guard<std::mutex> g(c->mu);
         for (const auto& kv : c->tune) {
-            int sb = 0, nw = 0;
-            lowp_variant_shape(kv.second, &sb, &nw);
-            text += kv.first + " " + std::to_string(sb) + " " + std::to_string(nw) + "\n";
+            int sb = 0, nw = 0, pd = 0;
+            lowp_variant_shape(kv.second, &sb, &nw, &pd);
+            text += kv.first + " " + std::to_string(sb) + " " + std::to_string(nw) + " " + std::to_string(pd) + "\n";
         }
     }
     *len = text.size() + 1;
@@ -1357,16 +1357,18 @@ mcpt_status mcpt_tune_import(mcpt_ctx* c, const char* text) {
         pos = e + 1;
         if (line.empty()) continue;
         char key[512];
-        int sb = 0, nw = 0;
-        if (line.size() >= sizeof(key) || std::sscanf(line.c_str(), "%511s %d %d", key, &sb, &nw) != 3)
+        int sb = 0, nw = 0, pd = 0;
+        if (line.size() >= sizeof(key) || std::sscanf(line.c_str(), "%511s %d %d %d", key, &sb, &nw, &pd) != 4)
             return fail(MCPT_ERR_INVALID, "bad tuning line: " + line);
         int v = -1;
         for (int k = 0; k < lowp_variants(); ++k) {
-            int a = 0, b = 0;
-            lowp_variant_shape(k, &a, &b);
-            if (a == sb && b == nw) v = k;
+            int a = 0, b = 0, d = 0;
+            lowp_variant_shape(k, &a, &b, &d);
+            if (a == sb && b == nw && d == pd) v = k;
         }
-        if (v < 0) return fail(MCPT_ERR_INVALID, "no tile variant " + std::to_string(sb) + " x " + std::to_string(nw));
+        if (v < 0)
+            return fail(MCPT_ERR_INVALID, "no tile variant " + std::to_string(sb) + " x " + std::to_string(nw) +
+                                              " depth " + std::to_string(pd));
         add[key] = v;
     }
     std::lock_guard<std::mutex> g(c->mu);

@@ -143,7 +143,7 @@ void launch_convert_v(int precision, const PairDesc* pairs, int64_t n_pair, cons
 // lds_bytes > 0 selects the LDS-resident-V kernel with that much dynamic LDS
 // (every pair of the launch must need at most that much: lowp_lds_bytes)
 int lowp_variants();
-void lowp_variant_shape(int variant, int* sb, int* nw);
+void lowp_variant_shape(int variant, int* sb, int* nw, int* pd);
 int64_t lowp_lds_bytes(int precision, int nX, int nY);
 int64_t lowp_lds_limit();
 int pair_lowp_blocks_per_cu(int precision, int variant, int64_t lds_bytes);

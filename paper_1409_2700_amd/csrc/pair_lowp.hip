@@ -33,11 +33,13 @@ constexpr int kThreads = 256;   // conversion kernel
 constexpr int kXcds = 8;
 
 // Tunable shapes of the pair kernel: super-block edge SB (a wave computes SB x SB
-// output tiles of 16 x 16 per task) and waves per workgroup NW.
+// output tiles of 16 x 16 per task), waves per workgroup NW, and how many k
+// chunks of operand fragments are in flight ahead of the MFMAs (PD).
 struct Variant {
-    int sb, nw;
+    int sb, nw, pd;
 };
-constexpr Variant kVariants[] = {{3, 8}, {2, 8}, {4, 8}, {3, 4}, {2, 4}, {4, 4}, {2, 16}};
+constexpr Variant kVariants[] = {{3, 8, 1}, {3, 8, 2}, {3, 8, 3}, {2, 8, 2}, {2, 8, 3}, {4, 8, 1},
+                                 {3, 4, 2}, {2, 16, 1}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 template <class E>
@@ -107,32 +109,44 @@ struct Cols {
     }
 };
 
-// acc[i][j] += sum_k A(m0 + i)[row][k] * B(n0 + j)[col][k] for k < K, the next
-// chunk's fragments loaded while the current chunk's MFMAs run.
-template <class E, int NR, int NC, class SA, class SB_>
+// acc[i][j] += sum_k A(m0 + i)[row][k] * B(n0 + j)[col][k] for k < K, with the
+// fragments of the PD chunks after the current one in flight (a ring of PD
+// register slots, the loop unrolled by PD so every slot index is static).
+template <class E, int NR, int NC, int PD, class SA, class SB_>
 __device__ inline void gemm(const SA& A, const SB_& B, int K, int m0, int n0, int lane, f4 (&acc)[NR][NC]) {
     typedef Lowp<E> L;
-    typename L::Frag an[NR], bn[NC];
+    typename L::Frag ra[PD][NR], rb[PD][NC];
 #pragma unroll
-    for (int i = 0; i < NR; ++i) an[i] = A(m0 + i, 0, lane);
+    for (int d = 0; d < PD; ++d)
+        if (d * L::KC < K) {
 #pragma unroll
-    for (int j = 0; j < NC; ++j) bn[j] = B(n0 + j, 0, lane);
-    for (int k0 = 0; k0 < K; k0 += L::KC) {
-        typename L::Frag a[NR], b[NC];
+            for (int i = 0; i < NR; ++i) ra[d][i] = A(m0 + i, d * L::KC, lane);
 #pragma unroll
-        for (int i = 0; i < NR; ++i) a[i] = an[i];
-#pragma unroll
-        for (int j = 0; j < NC; ++j) b[j] = bn[j];
-        if (k0 + L::KC < K) {
-#pragma unroll
-            for (int i = 0; i < NR; ++i) an[i] = A(m0 + i, k0 + L::KC, lane);
-#pragma unroll
-            for (int j = 0; j < NC; ++j) bn[j] = B(n0 + j, k0 + L::KC, lane);
+            for (int j = 0; j < NC; ++j) rb[d][j] = B(n0 + j, d * L::KC, lane);
         }
+    for (int k0 = 0; k0 < K; k0 += PD * L::KC) {
 #pragma unroll
-        for (int i = 0; i < NR; ++i)
+        for (int d = 0; d < PD; ++d) {
+            const int kc = k0 + d * L::KC;
+            if (kc < K) {
+                typename L::Frag a[NR], b[NC];
 #pragma unroll
-            for (int j = 0; j < NC; ++j) acc[i][j] = L::mma(a[i], b[j], acc[i][j]);
+                for (int i = 0; i < NR; ++i) a[i] = ra[d][i];
+#pragma unroll
+                for (int j = 0; j < NC; ++j) b[j] = rb[d][j];
+                const int kn = kc + PD * L::KC;
+                if (kn < K) {
+#pragma unroll
+                    for (int i = 0; i < NR; ++i) ra[d][i] = A(m0 + i, kn, lane);
+#pragma unroll
+                    for (int j = 0; j < NC; ++j) rb[d][j] = B(n0 + j, kn, lane);
+                }
+#pragma unroll
+                for (int i = 0; i < NR; ++i)
+#pragma unroll
+                    for (int j = 0; j < NC; ++j) acc[i][j] = L::mma(a[i], b[j], acc[i][j]);
+            }
+        }
     }
 }
 
@@ -270,7 +284,7 @@ __host__ __device__ inline int64_t lds_bytes(int npX, int npY, int ldX, int ldY)
 // of the staged V) and every product takes one operand from LDS and the other
 // (M_X, M_Y, Tau^T, and Tau for FP32) from L2 (BF16 G_X: both from LDS);
 // otherwise both operands come from L2.
-template <class E, int SB, int NW, bool IN_LDS>
+template <class E, int SB, int NW, int PD, bool IN_LDS>
 __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
     const PairDesc* __restrict__ pairs, int64_t n_pair, const MonoDesc* __restrict__ monos,
     const double* __restrict__ dif, const E* __restrict__ Vlo, const int64_t* __restrict__ lo_off,
@@ -338,10 +352,10 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
             constexpr int NR = decltype(shape)::NR, NC = decltype(shape)::NC;
             f4 acc[NR][NC];
             zero(acc);
-            if (kVtLds) gemm<E, NR, NC>(Rows<E>{MX, ldX}, Rows<E>{sVt, sldX}, ldX, r0, c0, lane, acc);   // M_X V
-            else if (IN_LDS) gemm<E, NR, NC>(Rows<E>{MX, ldX}, Cols<E>{sV, sldY}, ldX, r0, c0, lane, acc);
-            else gemm<E, NR, NC>(Rows<E>{MX, ldX}, Rows<E>{Vt, ldX}, ldX, r0, c0, lane, acc);
-            gemm<E, NR, NC>(vrows(), Rows<E>{MY, ldY}, ldY, r0, c0, lane, acc);                        // V M_Y^T
+            if (kVtLds) gemm<E, NR, NC, PD>(Rows<E>{MX, ldX}, Rows<E>{sVt, sldX}, ldX, r0, c0, lane, acc);   // M_X V
+            else if (IN_LDS) gemm<E, NR, NC, PD>(Rows<E>{MX, ldX}, Cols<E>{sV, sldY}, ldX, r0, c0, lane, acc);
+            else gemm<E, NR, NC, PD>(Rows<E>{MX, ldX}, Rows<E>{Vt, ldX}, ldX, r0, c0, lane, acc);
+            gemm<E, NR, NC, PD>(vrows(), Rows<E>{MY, ldY}, ldY, r0, c0, lane, acc);                        // V M_Y^T
 #pragma unroll
             for (int j = 0; j < NC; ++j) {
                 const int c = (c0 + j) * 16 + acc_col(lane);
@@ -414,13 +428,13 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
                 f4 acc[NR][NC];
                 zero(acc);
                 if (which == 0) {
-                    if (kVtLds) gemm<E, NR, NC>(Rows<E>{sTau, sldY}, vrows(), ldY, r0, c0, lane, acc);
-                    else gemm<E, NR, NC>(Rows<E>{tau, ldY}, vrows(), ldY, r0, c0, lane, acc);
+                    if (kVtLds) gemm<E, NR, NC, PD>(Rows<E>{sTau, sldY}, vrows(), ldY, r0, c0, lane, acc);
+                    else gemm<E, NR, NC, PD>(Rows<E>{tau, ldY}, vrows(), ldY, r0, c0, lane, acc);
                     atomic_flush(GX, po.part ? po.part + po.off[pi] : nullptr, npX, nX, r0, c0, lane, acc);
                 } else {
-                    if (kVtLds) gemm<E, NR, NC>(Rows<E>{tauT, ldX}, Rows<E>{sVt, sldX}, ldX, r0, c0, lane, acc);
-                    else if (IN_LDS) gemm<E, NR, NC>(Rows<E>{tauT, ldX}, Cols<E>{sV, sldY}, ldX, r0, c0, lane, acc);
-                    else gemm<E, NR, NC>(Rows<E>{tauT, ldX}, Rows<E>{Vt, ldX}, ldX, r0, c0, lane, acc);
+                    if (kVtLds) gemm<E, NR, NC, PD>(Rows<E>{tauT, ldX}, Rows<E>{sVt, sldX}, ldX, r0, c0, lane, acc);
+                    else if (IN_LDS) gemm<E, NR, NC, PD>(Rows<E>{tauT, ldX}, Cols<E>{sV, sldY}, ldX, r0, c0, lane, acc);
+                    else gemm<E, NR, NC, PD>(Rows<E>{tauT, ldX}, Rows<E>{Vt, ldX}, ldX, r0, c0, lane, acc);
                     atomic_flush(GY, po.part ? po.part + po.off[pi] + (int64_t)npX * npX : nullptr, npY, nY, r0, c0,
                                  lane, acc);
                 }
@@ -433,7 +447,8 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
 
 template <class E, int V, bool IN_LDS>
 const void* kernel_of() {
-    return reinterpret_cast<const void*>(pair_lowp_kernel<E, kVariants[V].sb, kVariants[V].nw, IN_LDS>);
+    return reinterpret_cast<const void*>(
+        pair_lowp_kernel<E, kVariants[V].sb, kVariants[V].nw, kVariants[V].pd, IN_LDS>);
 }
 
 template <class E, bool IN_LDS, int... V>
@@ -457,9 +472,10 @@ int lowp_chunk(int precision) { return precision == 2 ? Lowp<__bf16>::KC : Lowp<
 
 int lowp_variants() { return kNumVariants; }
 
-void lowp_variant_shape(int variant, int* sb, int* nw) {
+void lowp_variant_shape(int variant, int* sb, int* nw, int* pd) {
     *sb = kVariants[variant].sb;
     *nw = kVariants[variant].nw;
+    *pd = kVariants[variant].pd;
 }
 
 int64_t lowp_lds_bytes(int precision, int nX, int nY) {

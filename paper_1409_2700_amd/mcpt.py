@@ -97,13 +97,13 @@ class mcpt_serve_counters(C.Structure):
 class mcpt_tune_result(C.Structure):
     _fields_ = [
         ("n_variants", C.c_int32), ("best", C.c_int32), ("sb", C.c_int32 * 16), ("nw", C.c_int32 * 16),
-        ("ms", C.c_double * 16),
+        ("pd", C.c_int32 * 16), ("reserved", C.c_int32), ("ms", C.c_double * 16),
     ]
 
     def as_dict(self) -> dict:
         n = self.n_variants
-        return {"best": self.best, "variants": [{"sb": self.sb[k], "nw": self.nw[k], "ms": self.ms[k]}
-                                                for k in range(n)]}
+        return {"best": self.best, "variants": [{"sb": self.sb[k], "nw": self.nw[k], "pd": self.pd[k],
+                                                 "ms": self.ms[k]} for k in range(n)]}
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:

@@ -22,13 +22,13 @@ def golden125():
         return json.load(f)
 
 
-def forced(ctx, pid, prec, sb, nw):
+def forced(ctx, pid, prec, sb, nw, pd):
     """Point the context's table entry for this problem at one tile shape."""
     ctx.autotune(pid, prec)   # creates the entry (and times every shape)
     lines = [l for l in ctx.tune_table().splitlines() if l]
     key = [l.split()[0] for l in lines if l.startswith("fp32/" if prec == mc.MCPT_FP32 else "bf16/")]
     assert len(key) == 1
-    ctx.load_tune_table(f"{key[0]} {sb} {nw}\n")
+    ctx.load_tune_table(f"{key[0]} {sb} {nw} {pd}\n")
 
 
 @pytest.mark.parametrize("prec", [mc.MCPT_FP32, mc.MCPT_BF16], ids=["fp32", "bf16"])
@@ -39,11 +39,11 @@ def test_every_tile_shape_is_exact_after_polish(golden125, prec):
         rep = ctx.autotune(pid, prec)
         assert rep["variants"] and 0 <= rep["best"] < len(rep["variants"])
         assert all(v["ms"] > 0.02 for v in rep["variants"])   # every shape did the whole pair phase
-        print(f"[gpu] tune prec={prec}: " + ", ".join(f"{v['sb']}x{v['nw']}={v['ms']:.3f}ms"
+        print(f"[gpu] tune prec={prec}: " + ", ".join(f"{v['sb']}x{v['nw']}/{v['pd']}={v['ms']:.3f}ms"
                                                       for v in rep["variants"]), flush=True)
         energies = []
         for v in rep["variants"]:
-            forced(ctx, pid, prec, v["sb"], v["nw"])
+            forced(ctx, pid, prec, v["sb"], v["nw"], v["pd"])
             s = ctx.run(pid, tol=1e-10, precision=prec, polish=1)
             assert s["status"] == mc.MCPT_OK
             assert abs(s["e_total"] - golden125["e_total"]) <= 1e-10 * abs(golden125["e_total"]), v
@@ -61,7 +61,7 @@ def test_shapes_agree_without_polish_on_uneven_batch():
         rep = ctx.autotune(pid, mc.MCPT_FP32)
         ref = None
         for v in rep["variants"]:
-            forced(ctx, pid, mc.MCPT_FP32, v["sb"], v["nw"])
+            forced(ctx, pid, mc.MCPT_FP32, v["sb"], v["nw"], v["pd"])
             s = ctx.run(pid, tol=0.0, max_sweeps=6, precision=mc.MCPT_FP32, polish=0)
             e = ctx.energy(pid)
             if ref is None:
@@ -86,7 +86,7 @@ def test_autotune_option_and_table_round_trip():
     with mc.Context(0) as other:
         other.load_tune_table(table)
         assert other.tune_table() == table
-        for bad in ("fp32/x 7 7\n", "nonsense\n"):
+        for bad in ("fp32/x 7 7 1\n", "fp32/x 3 8\n", "nonsense\n"):
             with pytest.raises(mc.MCPTError) as ei:
                 other.load_tune_table(bad)
             assert ei.value.status == mc.MCPT_ERR_INVALID
