@@ -417,6 +417,10 @@ def main():
     avg_ms = kms / max(kl, 1)
     flops_per_launch = kfl / max(kl, 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    # monomer phase (Eq. 58 update, elementwise): reads K, G, T and writes T, M and the cleared G buffer,
+    # 6 n^2 doubles per monomer (algorithmic, unpadded n)
+    mono_bytes = 6.0 * 8.0 * float(sum(int(o) * int(v) * int(o) * int(v) for o, v in zip(prob.n_occ, prob.n_vir)))
+    mono_ms = results["fp64"]["monomer_avg_ms"] if "fp64" in results else None
     out = {
         "metric": METRIC, "value": h["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": h["ms_per_solve"], "higher_is_better": True,
@@ -436,6 +440,10 @@ def main():
             "kernel": kname, "avg_launch_ms": avg_ms,
             "flops_per_launch": flops_per_launch, "launches": kl,
         },
+        "monomer_phase": None if not mono_ms else {
+            "bound": "hbm", "algorithmic_bytes_per_launch": mono_bytes, "avg_launch_ms": mono_ms,
+            "achieved_GBps": mono_bytes / (mono_ms * 1e-3) / 1e9, "peak_GBps": HBM_PEAK_GBS,
+            "frac": mono_bytes / (mono_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "timing"} for k, v in results.items()},
     }
     if served is not None:

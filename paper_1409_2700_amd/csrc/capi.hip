@@ -296,6 +296,7 @@ mcpt_status upload_batch(mcpt_ctx* c, Exec& x, const mcpt_problem* pbs, int n_cl
             roff += (int64_t)d.n * d.n;
             moff += (int64_t)d.np * d.np;
             r->max_n = std::max(r->max_n, d.n);
+            r->max_v = std::max(r->max_v, d.v);
             r->max_np = std::max(r->max_np, d.np);
         }
     }
@@ -781,7 +782,7 @@ void lowp_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int source, bool e
 }
 
 void mixed_mono(mcpt_ctx* c, Exec& x, Resident* R, int mode, const double* G, double* Gz, bool lo_out, const Ctrl* ctrl) {
-    launch_monomer_mixed(mode, R->lo_prec, R->d_monos, R->n_mono, R->d_dif, R->d_K, G, Gz, R->d_T, R->d_M, R->d_R,
+    launch_monomer_mixed(mode, R->lo_prec, R->d_monos, R->n_mono, R->max_v, R->d_dif, R->d_K, G, Gz, R->d_T, R->d_M, R->d_R,
                          R->d_Dl, lo_out ? R->d_Mlo : nullptr, R->d_mlo_off, R->d_em2, R->d_em2_0, R->d_res, ctrl,
                          R->d_cl, x.stream);
 }
@@ -910,12 +911,12 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
         HIP_TRY(hipMemcpyAsync(R->d_raw, o->warm_t, R->raw_elems * sizeof(double), hipMemcpyHostToDevice, s));
         launch_fill(R->d_T, R->mat_elems, 0.0, s);
         launch_pack(R->d_monos, R->n_mono, R->d_raw, R->d_T, R->max_n, s);
-        launch_monomer(kMonoE0, R->d_monos, R->n_mono, R->d_dif, R->d_K, nullptr, nullptr, R->d_T, R->d_M,
+        launch_monomer(kMonoE0, R->d_monos, R->n_mono, R->max_v, R->d_dif, R->d_K, nullptr, nullptr, R->d_T, R->d_M,
                        R->d_em2, R->d_em2_0, R->d_res, nullptr, nullptr, s);
-        launch_monomer(kMonoFromT, R->d_monos, R->n_mono, R->d_dif, R->d_K, nullptr, nullptr, R->d_T,
+        launch_monomer(kMonoFromT, R->d_monos, R->n_mono, R->max_v, R->d_dif, R->d_K, nullptr, nullptr, R->d_T,
                        R->d_M, R->d_em2, R->d_em2_0, R->d_res, nullptr, nullptr, s);
     } else {
-        launch_monomer(kMonoInit, R->d_monos, R->n_mono, R->d_dif, R->d_K, nullptr, nullptr, R->d_T, R->d_M,
+        launch_monomer(kMonoInit, R->d_monos, R->n_mono, R->max_v, R->d_dif, R->d_K, nullptr, nullptr, R->d_T, R->d_M,
                        R->d_em2, R->d_em2_0, R->d_res, nullptr, nullptr, s);
     }
     if (prec != MCPT_FP64) mixed_mono(c, x, R, kMonoFromT, nullptr, nullptr, true, nullptr);   // M in low precision
@@ -936,7 +937,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
             if (prec == MCPT_FP64) pair_phase(c, x, R, R->d_G[cur], 1, x.d_ctrl);
             else lowp_phase(c, x, R, R->d_G[cur], 1);
             if (prec == MCPT_FP64)
-                launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->d_dif, R->d_K, R->d_G[cur], R->d_G[cur ^ 1],
+                launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->max_v, R->d_dif, R->d_K, R->d_G[cur], R->d_G[cur ^ 1],
                                R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, x.d_ctrl, R->d_cl, s);
             else
                 mixed_mono(c, x, R, kMonoUpdate, R->d_G[cur], R->d_G[cur ^ 1], true, x.d_ctrl);
@@ -992,7 +993,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
                 }
                 record_begin(x, &a);
                 if (prec == MCPT_FP64)
-                    launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->d_dif, R->d_K, R->d_G[cur],
+                    launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->max_v, R->d_dif, R->d_K, R->d_G[cur],
                                    R->d_G[cur ^ 1], R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, x.d_ctrl,
                                    R->d_cl, s);
                 else

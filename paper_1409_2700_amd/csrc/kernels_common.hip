@@ -194,6 +194,141 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
 // Stopping rule, same as the oracle's, per cluster: converged when r < tol;
 // diverged when r is not finite, r > 1e6 r_1, or r rose in each of the last
 // three sweeps and exceeds r_1; not converged when max_sweeps sweeps ran.
+// The same monomer phase organised by v x v blocks.  In the (i,a),(j,b) layout
+// the occupied swap S maps block (i,j) onto block (j,i) element for element
+// ((a,b) -> (a,b)), and G^T at (i,a),(j,b) is element (b,a) of block (j,i).  One
+// pass over the block pair {(i,j), (j,i)} therefore reads every element once:
+// K, T and R along contiguous block rows, G through LDS for the transposed
+// read.  Results are bitwise those of monomer_kernel (same operations in the
+// same order per element).
+template <class E, int VMAX>
+__global__ __launch_bounds__(kMonoThreads) void monomer_blocks_kernel(
+    int mode, const MonoDesc* __restrict__ monos, const double* __restrict__ dif,
+    const double* __restrict__ K, const double* __restrict__ G, double* __restrict__ Gz,
+    double* __restrict__ T, double* __restrict__ M, double* __restrict__ R, double* __restrict__ Dl,
+    E* __restrict__ Mlo, const int64_t* __restrict__ mlo_off, int lo_chunk, double* __restrict__ em2,
+    double* __restrict__ em2_0, double* __restrict__ res, const Ctrl* __restrict__ ctrl,
+    const ClState* __restrict__ cl) {
+    if (ctrl && ctrl->done) return;
+    __shared__ double sh[kMonoThreads];
+    __shared__ double sg[2][VMAX][VMAX + 1];
+    const int x = blockIdx.x;
+    const MonoDesc d = monos[x];
+    if (cl && cl[d.cluster].done) return;   // this monomer's cluster has stopped
+    const int o = d.o, v = d.v, n = d.n, np = d.np;
+    const double* dx = dif + d.dif_off;
+    const double* Kx = K + d.mat_off;
+    const double* Gx = G ? G + d.mat_off : nullptr;
+    double* Tx = T + d.mat_off;
+    double* Mx = M + d.mat_off;
+    double* Rx = R ? R + d.mat_off : nullptr;
+    double* Dx = Dl ? Dl + d.mat_off : nullptr;
+    E* Ml = Mlo ? Mlo + mlo_off[x] : nullptr;
+    const int ldl = (n + lo_chunk - 1) / lo_chunk * lo_chunk;
+    const bool need_g = mode == kMonoUpdate || mode == kMonoUpdateR || mode == kMonoCorr;
+    double rmax = 0.0, esum = 0.0;
+    for (int i = 0; i < o; ++i)
+        for (int j = i; j < o; ++j) {
+            const bool diag = i == j;
+            if (need_g) {
+                __syncthreads();   // the previous block pair is done with sg
+                for (int idx = threadIdx.x; idx < v * v; idx += kMonoThreads) {
+                    const int a = idx / v, b = idx - a * v;
+                    sg[0][a][b] = Gx[(int64_t)(i * v + a) * np + j * v + b];
+                    sg[1][a][b] = Gx[(int64_t)(j * v + a) * np + i * v + b];
+                }
+                __syncthreads();
+            }
+            for (int idx = threadIdx.x; idx < v * v; idx += kMonoThreads) {
+                const int a = idx / v, b = idx - a * v;
+                const int r1 = i * v + a, c1 = j * v + b, r2 = j * v + a, c2 = i * v + b;
+                const int64_t e1 = (int64_t)r1 * np + c1, e2 = (int64_t)r2 * np + c2;
+                if (mode == kMonoApply) {
+                    Tx[e1] += Dx[e1] - Rx[e1];
+                    if (!diag) Tx[e2] += Dx[e2] - Rx[e2];
+                    continue;
+                }
+                const double d1 = recip(dx[r1] + dx[c1]), d2 = recip(dx[r2] + dx[c2]);
+                double t1, t2, lo1 = 0.0, lo2 = 0.0;
+                bool has_lo = false;
+                if (mode == kMonoUpdate || mode == kMonoUpdateR) {
+                    t1 = d1 * ((Kx[e1] + sg[0][a][b]) + sg[1][b][a]);
+                    t2 = d2 * ((Kx[e2] + sg[1][a][b]) + sg[0][b][a]);
+                    const double o1 = Tx[e1], o2 = Tx[e2];
+                    rmax = max_nan(rmax, fabs(t1 - o1));
+                    if (!diag) rmax = max_nan(rmax, fabs(t2 - o2));
+                    if (mode == kMonoUpdateR) {
+                        Rx[e1] = t1 - o1;
+                        if (!diag) Rx[e2] = t2 - o2;
+                    } else {
+                        lo1 = 2.0 * t1 - t2;
+                        lo2 = 2.0 * t2 - t1;
+                        has_lo = true;
+                    }
+                } else if (mode == kMonoCorr) {
+                    t1 = Rx[e1] + d1 * (sg[0][a][b] + sg[1][b][a]);
+                    t2 = Rx[e2] + d2 * (sg[1][a][b] + sg[0][b][a]);
+                    Dx[e1] = t1;
+                    if (!diag) Dx[e2] = t2;
+                    lo1 = 2.0 * t1 - t2;
+                    lo2 = 2.0 * t2 - t1;
+                    has_lo = true;
+                } else if (mode == kMonoRlo) {
+                    t1 = Rx[e1];
+                    t2 = Rx[e2];
+                    lo1 = 2.0 * t1 - t2;
+                    lo2 = 2.0 * t2 - t1;
+                    has_lo = true;
+                } else if (mode == kMonoFromT) {
+                    t1 = Tx[e1];
+                    t2 = Tx[e2];
+                } else {
+                    t1 = d1 * Kx[e1];
+                    t2 = d2 * Kx[e2];
+                }
+                if (mode != kMonoCorr && mode != kMonoRlo) {
+                    const double m1 = 2.0 * t1 - t2, m2 = 2.0 * t2 - t1;
+                    esum += Kx[e1] * m1;
+                    if (!diag) esum += Kx[e2] * m2;
+                    if (mode == kMonoInit || mode == kMonoUpdate || mode == kMonoUpdateR) {
+                        Tx[e1] = t1;
+                        if (!diag) Tx[e2] = t2;
+                    }
+                    if (mode != kMonoE0) {
+                        Mx[e1] = m1;
+                        if (!diag) Mx[e2] = m2;
+                    }
+                    if (!has_lo) {
+                        lo1 = m1;
+                        lo2 = m2;
+                        has_lo = true;
+                    }
+                }
+                if (Ml && has_lo) {
+                    Ml[(int64_t)r1 * ldl + c1] = (E)(float)lo1;
+                    if (!diag) Ml[(int64_t)r2 * ldl + c2] = (E)(float)lo2;
+                }
+            }
+        }
+    if (Gz) {
+        double* gz = Gz + d.mat_off;
+        const int npp = np * np;
+        for (int idx = threadIdx.x; idx < npp; idx += kMonoThreads) gz[idx] = 0.0;
+    }
+    if (mode == kMonoApply || mode == kMonoRlo || mode == kMonoCorr) return;
+    const double etot = block_sum<kMonoThreads>(esum, sh);
+    const double rtot = block_max<kMonoThreads>(rmax, sh);
+    if (threadIdx.x == 0) {
+        if (mode == kMonoE0) {
+            em2_0[x] = etot;
+        } else {
+            em2[x] = etot;
+            if (mode == kMonoInit) em2_0[x] = etot;
+            if (mode == kMonoUpdate || mode == kMonoUpdateR) res[x] = rtot;
+        }
+    }
+}
+
 // Convergence test of one sweep, one workgroup per cluster: max|dT| over the
 // cluster's monomers, its residual history and the stopping rules (tolerance,
 // divergence, sweep limit).  Clusters that have stopped are left untouched.
@@ -348,24 +483,41 @@ void launch_nonfinite(const double* p, int64_t n, int32_t* flag, hipStream_t s) 
                        dim3(256), 0, s, p, n, flag);
 }
 
-void launch_monomer(int mode, const MonoDesc* monos, int n_mono, const double* dif, const double* K,
-                    const double* G, double* G_zero, double* T, double* M, double* em2,
-                    double* em2_0, double* res, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
-    hipLaunchKernelGGL(monomer_kernel<float>, dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif, K, G,
-                       G_zero, T, M, (double*)nullptr, (double*)nullptr, (float*)nullptr, (const int64_t*)nullptr,
-                       16, em2, em2_0, res, ctrl, cl);
+// Blocked kernel when every monomer's v fits its LDS tiles, the element-wise one otherwise.
+template <class E>
+void monomer_dispatch(int max_v, int mode, const MonoDesc* monos, int n_mono, const double* dif, const double* K,
+                      const double* G, double* G_zero, double* T, double* M, double* R, double* Dl, E* Mlo,
+                      const int64_t* mlo_off, int chunk, double* em2, double* em2_0, double* res, const Ctrl* ctrl,
+                      const ClState* cl, hipStream_t s) {
+    if (n_mono <= 0) return;
+    if (max_v <= 32)
+        hipLaunchKernelGGL((monomer_blocks_kernel<E, 32>), dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif,
+                           K, G, G_zero, T, M, R, Dl, Mlo, mlo_off, chunk, em2, em2_0, res, ctrl, cl);
+    else if (max_v <= 64)
+        hipLaunchKernelGGL((monomer_blocks_kernel<E, 64>), dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif,
+                           K, G, G_zero, T, M, R, Dl, Mlo, mlo_off, chunk, em2, em2_0, res, ctrl, cl);
+    else
+        hipLaunchKernelGGL(monomer_kernel<E>, dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif, K, G,
+                           G_zero, T, M, R, Dl, Mlo, mlo_off, chunk, em2, em2_0, res, ctrl, cl);
 }
 
-void launch_monomer_mixed(int mode, int precision, const MonoDesc* monos, int n_mono, const double* dif,
+void launch_monomer(int mode, const MonoDesc* monos, int n_mono, int max_v, const double* dif, const double* K,
+                    const double* G, double* G_zero, double* T, double* M, double* em2,
+                    double* em2_0, double* res, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
+    monomer_dispatch<float>(max_v, mode, monos, n_mono, dif, K, G, G_zero, T, M, nullptr, nullptr, nullptr, nullptr,
+                            16, em2, em2_0, res, ctrl, cl, s);
+}
+
+void launch_monomer_mixed(int mode, int precision, const MonoDesc* monos, int n_mono, int max_v, const double* dif,
                           const double* K, const double* G, double* G_zero, double* T, double* M, double* R,
                           double* Dl, void* Mlo, const int64_t* mlo_off, double* em2, double* em2_0,
                           double* res, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
     if (precision == 2)
-        hipLaunchKernelGGL(monomer_kernel<__bf16>, dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif, K, G,
-                           G_zero, T, M, R, Dl, static_cast<__bf16*>(Mlo), mlo_off, 32, em2, em2_0, res, ctrl, cl);
+        monomer_dispatch<__bf16>(max_v, mode, monos, n_mono, dif, K, G, G_zero, T, M, R, Dl,
+                                 static_cast<__bf16*>(Mlo), mlo_off, 32, em2, em2_0, res, ctrl, cl, s);
     else
-        hipLaunchKernelGGL(monomer_kernel<float>, dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif, K, G,
-                           G_zero, T, M, R, Dl, static_cast<float*>(Mlo), mlo_off, 16, em2, em2_0, res, ctrl, cl);
+        monomer_dispatch<float>(max_v, mode, monos, n_mono, dif, K, G, G_zero, T, M, R, Dl, static_cast<float*>(Mlo),
+                                mlo_off, 16, em2, em2_0, res, ctrl, cl, s);
 }
 
 void launch_reduce_sweep(int n_cl, const int64_t* cl_mono, const double* res, ClState* cl, double* hist,

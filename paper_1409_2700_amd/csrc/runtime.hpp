@@ -27,7 +27,7 @@ struct Resident {
     uint64_t id = 0;
     int n_mono = 0;
     int64_t n_pair = 0;
-    int max_n = 0, max_np = 0;
+    int max_n = 0, max_np = 0, max_v = 0;   // largest n, padded n and virtual count over monomers
     int64_t eps_elems = 0, dif_elems = 0, raw_elems = 0, mat_elems = 0, v_elems = 0, max_slot = 0;
     std::vector<MonoDesc> monos;
     std::vector<PairDesc> pairs;      // LDS-variant pairs, then the others; each range sorted by
