@@ -100,11 +100,13 @@ template <class E>
 struct Cols {
     const E* p;
     int ld;
+    int kmax;   // rows k >= kmax read as zero (the matrix stores only kmax rows)
     __device__ typename Lowp<E>::Frag operator()(int tile, int k0, int lane) const {
         typename Lowp<E>::Frag f;
-        const E* q = p + (int64_t)(k0 + (lane >> 4) * Lowp<E>::KL) * ld + tile * 16 + (lane & 15);
+        const int k = k0 + (lane >> 4) * Lowp<E>::KL;
+        const E* q = p + (int64_t)k * ld + tile * 16 + (lane & 15);
 #pragma unroll
-        for (int e = 0; e < Lowp<E>::KL; ++e) f[e] = q[(int64_t)e * ld];
+        for (int e = 0; e < Lowp<E>::KL; ++e) f[e] = k + e < kmax ? q[(int64_t)e * ld] : E(0.0f);
         return f;
     }
 };
@@ -353,7 +355,7 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
             f4 acc[NR][NC];
             zero(acc);
             if (kVtLds) gemm<E, NR, NC, PD>(Rows<E>{MX, ldX}, Rows<E>{sVt, sldX}, ldX, r0, c0, lane, acc);   // M_X V
-            else if (IN_LDS) gemm<E, NR, NC, PD>(Rows<E>{MX, ldX}, Cols<E>{sV, sldY}, ldX, r0, c0, lane, acc);
+            else if (IN_LDS) gemm<E, NR, NC, PD>(Rows<E>{MX, ldX}, Cols<E>{sV, sldY, npX}, ldX, r0, c0, lane, acc);
             else gemm<E, NR, NC, PD>(Rows<E>{MX, ldX}, Rows<E>{Vt, ldX}, ldX, r0, c0, lane, acc);
             gemm<E, NR, NC, PD>(vrows(), Rows<E>{MY, ldY}, ldY, r0, c0, lane, acc);                        // V M_Y^T
 #pragma unroll
@@ -379,7 +381,7 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
                             else tau[(int64_t)r * ldY + c] = tv4[t];
                         }
                     }
-                    if (couple) {   // Tau^T row c, 4 consecutive columns
+                    if (couple && !kVtLds) {   // Tau^T row c, 4 consecutive columns (BF16 reads Tau from LDS)
                         E* q = tauT + (int64_t)c * ldX + (r0 + i) * 16 + acc_row(lane, 0);
 #pragma unroll
                         for (int t = 0; t < 4; ++t) q[t] = tv4[t];
@@ -393,7 +395,7 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
                 if (kVtLds) sTau[r * sldY + c] = L::from(0.0);
                 else tau[(int64_t)r * ldY + c] = L::from(0.0);
             }
-            for (int idx = threadIdx.x; idx < npY * (ldX - npX); idx += kThreadsK) {
+            for (int idx = threadIdx.x; !kVtLds && idx < npY * (ldX - npX); idx += kThreadsK) {
                 const int r = idx / (ldX - npX), c = npX + idx % (ldX - npX);
                 tauT[(int64_t)r * ldX + c] = L::from(0.0);
             }
@@ -432,8 +434,10 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
                     else gemm<E, NR, NC, PD>(Rows<E>{tau, ldY}, vrows(), ldY, r0, c0, lane, acc);
                     atomic_flush(GX, po.part ? po.part + po.off[pi] : nullptr, npX, nX, r0, c0, lane, acc);
                 } else {
-                    if (kVtLds) gemm<E, NR, NC, PD>(Rows<E>{tauT, ldX}, Rows<E>{sVt, sldX}, ldX, r0, c0, lane, acc);
-                    else if (IN_LDS) gemm<E, NR, NC, PD>(Rows<E>{tauT, ldX}, Cols<E>{sV, sldY}, ldX, r0, c0, lane, acc);
+                    if (kVtLds)   // Tau^T fragments as columns of the Tau kept in LDS
+                        gemm<E, NR, NC, PD>(Cols<E>{sTau, sldY, npX}, Rows<E>{sVt, sldX}, ldX, r0, c0, lane, acc);
+                    else if (IN_LDS)
+                        gemm<E, NR, NC, PD>(Rows<E>{tauT, ldX}, Cols<E>{sV, sldY, npX}, ldX, r0, c0, lane, acc);
                     else gemm<E, NR, NC, PD>(Rows<E>{tauT, ldX}, Rows<E>{Vt, ldX}, ldX, r0, c0, lane, acc);
                     atomic_flush(GY, po.part ? po.part + po.off[pi] + (int64_t)npX * npX : nullptr, npY, nY, r0, c0,
                                  lane, acc);
