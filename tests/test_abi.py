@@ -77,3 +77,23 @@ def test_host_problem_marshalling():
     assert hp.k.size == 2 * 2 * 3 * 3 + 1 * 1 * 4 * 4
     assert hp.v.size == 6 * 4
     assert hp.pairs.dtype == np.int32 and hp.pairs.shape == (1, 2)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """With the HIP library absent the binding raises instead of computing anything."""
+    code = ("import paper_1409_2700_amd as mc\n"
+            "try:\n    mc.Context(0)\nexcept ImportError as e:\n    print('IMPORT-ERROR', e)\n")
+    env = dict(os.environ, MCPT_LIBRARY=str(tmp_path / "absent" / "libmcpt.so"))
+    out = subprocess.run([os.sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                         timeout=120)
+    assert "IMPORT-ERROR" in out.stdout, out.stdout + out.stderr
+
+
+def test_no_cpu_fallback_in_product():
+    """The product package never imports the oracle or computes the method on the host."""
+    pkg = os.path.join(ROOT, "paper_1409_2700_amd")
+    for name in os.listdir(pkg):
+        if name.endswith(".py"):
+            text = open(os.path.join(pkg, name)).read()
+            assert "oracle" not in text, name
+            assert "einsum" not in text and "numpy.linalg" not in text, name
