@@ -59,6 +59,7 @@ void free_lowp(mcpt_ctx* c, Resident* r) {
     r->d_Vlo = r->d_Mlo = nullptr;
     r->d_lo_off = r->d_mlo_off = nullptr;
     r->d_R = r->d_Dl = nullptr;
+    r->d_G32[0] = r->d_G32[1] = nullptr;
 }
 
 void free_det(mcpt_ctx* c, Resident* r) {
@@ -499,6 +500,7 @@ size_t footprint(const mcpt_problem* pbs, int n, int precision) {
     if (kc) {
         const int64_t es = precision == MCPT_BF16 ? 2 : 4;
         b += r(es * vlo) + r(es * mlo) + r(8 * std::max<int64_t>(n_pair, 1)) + r(8 * n_mono) + 2 * r(8 * mat);
+        if (precision == MCPT_BF16) b += r(8 * mat);   // two FP32 G buffers
     }
     return b;
 }
@@ -700,12 +702,14 @@ mcpt_status ensure_lowp(mcpt_ctx* c, Exec& x, Resident* R, int prec) {
         mo += R->monos[x].np * ld(R->monos[x].n);
     }
     mcpt_status st;
-    void *vlo = nullptr, *mlo = nullptr, *lo_o = nullptr, *mlo_o = nullptr, *rr = nullptr, *dd = nullptr;
+    void *vlo = nullptr, *mlo = nullptr, *lo_o = nullptr, *mlo_o = nullptr, *rr = nullptr, *dd = nullptr,
+         *g32 = nullptr;
     if ((st = lo_alloc(c, x, R, &vlo, vo * es)) != MCPT_OK || (st = lo_alloc(c, x, R, &mlo, mo * es)) != MCPT_OK ||
         (st = lo_alloc(c, x, R, &lo_o, lo_off.size() * 8)) != MCPT_OK ||
         (st = lo_alloc(c, x, R, &mlo_o, mlo_off.size() * 8)) != MCPT_OK ||
         (st = lo_alloc(c, x, R, &rr, R->mat_elems * 8)) != MCPT_OK ||
-        (st = lo_alloc(c, x, R, &dd, R->mat_elems * 8)) != MCPT_OK) {
+        (st = lo_alloc(c, x, R, &dd, R->mat_elems * 8)) != MCPT_OK ||
+        (prec == MCPT_BF16 && (st = lo_alloc(c, x, R, &g32, R->mat_elems * 8)) != MCPT_OK)) {
         free_lowp(c, R);
         return st;
     }
@@ -724,6 +728,11 @@ mcpt_status ensure_lowp(mcpt_ctx* c, Exec& x, Resident* R, int prec) {
     R->d_mlo_off = static_cast<int64_t*>(mlo_o);
     R->d_R = static_cast<double*>(rr);
     R->d_Dl = static_cast<double*>(dd);
+    if (g32) {
+        launch_fill(static_cast<double*>(g32), R->mat_elems, 0.0, s);   // 2 x mat_elems floats
+        R->d_G32[0] = static_cast<float*>(g32);
+        R->d_G32[1] = R->d_G32[0] + R->mat_elems;
+    }
     R->lo_slot = (slot + 63) / 64 * 64;   // keeps every slot 16-byte aligned
     R->lo_v_bytes = (double)vo * es;
     R->lo_prec = prec;
@@ -766,25 +775,27 @@ mcpt_status ensure_scratch_lo(mcpt_ctx* c, Exec& x, const Resident* R, int prec)
 // `every`: cover the pairs of every cluster (the autotuner), not only those still iterating
 // Reduced-precision pair phase: the LDS-resident-V kernel for the leading pairs
 // that fit, then the L2 variant for the rest (same stream, so G accumulates in order).
-void lowp_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int source, bool every = false) {
+// Gf non-null: G contributions go to that FP32 buffer (not in deterministic mode).
+void lowp_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, float* Gf, int source, bool every = false) {
     const ClState* cl = every ? nullptr : R->d_cl;
     const int64_t nl = R->lo_n_lds;
     const bool det = R->det_on && !every;
     const PartOut p0{det ? R->d_part : nullptr, R->d_part_off};
     const PartOut p1{det ? R->d_part : nullptr, R->d_part_off ? R->d_part_off + nl : nullptr};
     launch_pair_lowp(R->lo_prec, R->lo_variant, R->lo_lds_bytes, p0, R->d_pairs, nl, R->d_monos, R->d_dif, R->d_Vlo,
-                     R->d_lo_off, R->d_Mlo, R->d_mlo_off, G, x.d_scratch_lo, R->lo_slot, x.grid_lo_lds, R->d_ed2,
+                     R->d_lo_off, R->d_Mlo, R->d_mlo_off, G, Gf, x.d_scratch_lo, R->lo_slot, x.grid_lo_lds, R->d_ed2,
                      source, 1, nullptr, cl, x.stream);
     launch_pair_lowp(R->lo_prec, R->lo_variant, 0, p1, R->d_pairs + nl, R->n_pair - nl, R->d_monos, R->d_dif, R->d_Vlo,
-                     R->d_lo_off + nl, R->d_Mlo, R->d_mlo_off, G, x.d_scratch_lo, R->lo_slot, x.grid_lo, R->d_ed2,
+                     R->d_lo_off + nl, R->d_Mlo, R->d_mlo_off, G, Gf, x.d_scratch_lo, R->lo_slot, x.grid_lo, R->d_ed2,
                      source, 1, nullptr, cl, x.stream);
     if (det) launch_reduce_parts(R->d_monos, R->n_mono, R->d_csr_off, R->d_csr, R->d_part, G, R->d_cl, nullptr, x.stream);
 }
 
-void mixed_mono(mcpt_ctx* c, Exec& x, Resident* R, int mode, const double* G, double* Gz, bool lo_out, const Ctrl* ctrl) {
+void mixed_mono(mcpt_ctx* c, Exec& x, Resident* R, int mode, const double* G, double* Gz, bool lo_out, const Ctrl* ctrl,
+                const float* Gf = nullptr, float* Gfz = nullptr) {
     launch_monomer_mixed(mode, R->lo_prec, R->d_monos, R->n_mono, R->max_v, R->d_dif, R->d_K, G, Gz, R->d_T, R->d_M, R->d_R,
                          R->d_Dl, lo_out ? R->d_Mlo : nullptr, R->d_mlo_off, R->d_em2, R->d_em2_0, R->d_res, ctrl,
-                         R->d_cl, x.stream);
+                         R->d_cl, x.stream, Gf, Gfz);
 }
 
 mcpt_status sync_ctrl(Exec& x) {
@@ -833,10 +844,10 @@ mcpt_status autotune(mcpt_ctx* c, Exec& x, Resident* R, int prec, mcpt_tune_resu
     for (int v = 0; v < nv; ++v) {
         R->lo_variant = v;
         if ((st = ensure_scratch_lo(c, x, R, prec)) != MCPT_OK) break;
-        lowp_phase(c, x, R, R->d_G[0], 1, true);   // warm-up
+        lowp_phase(c, x, R, R->d_G[0], R->d_G32[0], 1, true);   // warm-up
         HIP_TRY(hipEventRecord(a, x.stream));
         constexpr int reps = 3;
-        for (int k = 0; k < reps; ++k) lowp_phase(c, x, R, R->d_G[0], 1, true);
+        for (int k = 0; k < reps; ++k) lowp_phase(c, x, R, R->d_G[0], R->d_G32[0], 1, true);
         HIP_TRY(hipEventRecord(b, x.stream));
         HIP_TRY(hipEventSynchronize(b));
         HIP_TRY(hipGetLastError());
@@ -907,6 +918,10 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
     }
     launch_fill(R->d_G[0], R->mat_elems, 0.0, s);
     launch_fill(R->d_G[1], R->mat_elems, 0.0, s);
+    // BF16 sweeps accumulate G in FP32 (its rounding is far below the BF16 products');
+    // deterministic mode keeps the FP64 partial-block path
+    const bool g32 = prec == MCPT_BF16 && !R->det_on && R->d_G32[0];
+    if (g32) launch_fill(reinterpret_cast<double*>(R->d_G32[0]), R->mat_elems, 0.0, s);   // both FP32 buffers
     if (o->warm_t) {
         HIP_TRY(hipMemcpyAsync(R->d_raw, o->warm_t, R->raw_elems * sizeof(double), hipMemcpyHostToDevice, s));
         launch_fill(R->d_T, R->mat_elems, 0.0, s);
@@ -924,7 +939,22 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
     const double fl_sweep = pair_flops(*R, true), fl_final = pair_flops(*R, false);
     const double vb = (double)R->v_elems * sizeof(double);
     const int every = o->check_every > 0 ? o->check_every : 1;
-    int cur = 0, n_lo = 0, n_hi = 0;
+    int cur = 0, cur32 = 0, n_lo = 0, n_hi = 0;
+    // one reduced-precision sweep: pair products into G (FP64 or FP32 buffer of the current
+    // parity), then the monomer pass that reads it and clears the other buffer of the pair
+    auto lo_pair = [&](int source) {
+        if (g32) lowp_phase(c, x, R, nullptr, R->d_G32[cur32], source);
+        else lowp_phase(c, x, R, R->d_G[cur], nullptr, source);
+    };
+    auto lo_mono = [&](int mode, const Ctrl* ctrl) {
+        if (g32) {
+            mixed_mono(c, x, R, mode, nullptr, nullptr, true, ctrl, R->d_G32[cur32], R->d_G32[cur32 ^ 1]);
+            cur32 ^= 1;
+        } else {
+            mixed_mono(c, x, R, mode, R->d_G[cur], R->d_G[cur ^ 1], true, ctrl);
+            cur ^= 1;
+        }
+    };
     const bool timing_on = x.timing.on && !o->graph;
     const int inner = o->inner_sweeps > 0 ? o->inner_sweeps : (prec == MCPT_BF16 ? 4 : 6);   // measured best at 1000 monomers
     const int n_pre = std::min(inner + 1, o->max_sweeps);
@@ -933,17 +963,17 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
 
     if (prec == MCPT_FP64 || !o->polish) {
         // plain Jacobi sweeps: FP64, or reduced precision with the integral source terms
-        auto issue_sweep = [&](bool timed) {
-            if (prec == MCPT_FP64) pair_phase(c, x, R, R->d_G[cur], 1, x.d_ctrl);
-            else lowp_phase(c, x, R, R->d_G[cur], 1);
-            if (prec == MCPT_FP64)
+        auto issue_sweep = [&]() {
+            if (prec == MCPT_FP64) {
+                pair_phase(c, x, R, R->d_G[cur], 1, x.d_ctrl);
                 launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->max_v, R->d_dif, R->d_K, R->d_G[cur], R->d_G[cur ^ 1],
                                R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, x.d_ctrl, R->d_cl, s);
-            else
-                mixed_mono(c, x, R, kMonoUpdate, R->d_G[cur], R->d_G[cur ^ 1], true, x.d_ctrl);
+                cur ^= 1;
+            } else {
+                lo_pair(1);
+                lo_mono(kMonoUpdate, x.d_ctrl);
+            }
             launch_reduce_sweep(R->n_cl, R->d_cl_mono, R->d_res, R->d_cl, R->d_hist, x.d_ctrl, s);
-            cur ^= 1;
-            (void)timed;
         };
         int issued = 0;
         if (o->graph && o->max_sweeps > 0) {
@@ -958,7 +988,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
                 drop_graph(R);
                 hipGraph_t g = nullptr;
                 HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                for (int k = 0; k < gk; ++k) issue_sweep(false);
+                for (int k = 0; k < gk; ++k) issue_sweep();
                 const hipError_t ec = hipStreamEndCapture(s, &g);
                 if (ec != hipSuccess) return fail(MCPT_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
                 const hipError_t ei = hipGraphInstantiate(&R->graph, g, nullptr, nullptr, 0);
@@ -971,7 +1001,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
                 R->graph_sweeps = gk;
                 R->graph_key = key;
             }
-            cur = 0;
+            cur = cur32 = 0;
             while (issued < o->max_sweeps) {
                 HIP_TRY(hipGraphLaunch(R->graph, s));
                 issued += gk;
@@ -988,19 +1018,20 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
                     pair_phase(c, x, R, R->d_G[cur], 1, x.d_ctrl);
                     record_end(x, a, 0, fl_sweep, vb);
                 } else {
-                    lowp_phase(c, x, R, R->d_G[cur], 1);
+                    lo_pair(1);
                     record_end(x, a, 2, fl_sweep, R->lo_v_bytes);
                 }
                 record_begin(x, &a);
-                if (prec == MCPT_FP64)
+                if (prec == MCPT_FP64) {
                     launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->max_v, R->d_dif, R->d_K, R->d_G[cur],
                                    R->d_G[cur ^ 1], R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, x.d_ctrl,
                                    R->d_cl, s);
-                else
-                    mixed_mono(c, x, R, kMonoUpdate, R->d_G[cur], R->d_G[cur ^ 1], true, x.d_ctrl);
+                    cur ^= 1;
+                } else {
+                    lo_mono(kMonoUpdate, x.d_ctrl);
+                }
                 record_end(x, a, 1, 0.0, 0.0);
                 launch_reduce_sweep(R->n_cl, R->d_cl_mono, R->d_res, R->d_cl, R->d_hist, x.d_ctrl, s);
-                cur ^= 1;
                 ++issued;
             }
             if ((st = sync_ctrl(x)) != MCPT_OK) return st;
@@ -1025,10 +1056,9 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
             for (int k = 0; k < inner; ++k) {
                 hipEvent_t a = nullptr;
                 record_begin(x, &a);
-                lowp_phase(c, x, R, R->d_G[cur], 0);
+                lo_pair(0);
                 record_end(x, a, 2, fl_sweep, R->lo_v_bytes);
-                mixed_mono(c, x, R, kMonoCorr, R->d_G[cur], R->d_G[cur ^ 1], true, nullptr);
-                cur ^= 1;
+                lo_mono(kMonoCorr, nullptr);
             }
             mixed_mono(c, x, R, kMonoApply, nullptr, nullptr, false, nullptr);
             mixed_mono(c, x, R, kMonoFromT, nullptr, nullptr, false, nullptr);
@@ -1036,28 +1066,28 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
         for (int k = 0; k < n_pre; ++k) {   // a few plain reduced-precision sweeps first
             hipEvent_t a = nullptr;
             record_begin(x, &a);
-            lowp_phase(c, x, R, R->d_G[cur], 1);
+            lo_pair(1);
             record_end(x, a, 2, fl_sweep, R->lo_v_bytes);
-            mixed_mono(c, x, R, kMonoUpdate, R->d_G[cur], R->d_G[cur ^ 1], true, nullptr);
-            cur ^= 1;
+            lo_mono(kMonoUpdate, nullptr);
         }
         fp64_sweep();
         if ((st = sync_ctrl(x)) != MCPT_OK) return st;
         if (o->graph && !h.done) {
             // one body = correction + FP64 sweep; bodies per graph chosen so that a replay
-            // returns the G double buffer to the parity it started from
+            // returns the G double buffers to the parities they started from
             int gb = every;
-            if ((gb * (inner + 1)) % 2) gb *= 2;
+            if (g32 ? gb % 2 : (gb * (inner + 1)) % 2) gb *= 2;
             const std::array<int64_t, 6> key{(int64_t)(uintptr_t)x.d_scratch, (int64_t)(uintptr_t)x.d_scratch_lo,
                                              (int64_t)(uintptr_t)x.d_ctrl, x.scratch_slot,
                                              (int64_t)c->grid_lds * 1000000 + c->grid_glb,
                                              (((int64_t)x.grid_lo * 10000 + x.grid_lo_lds) * 1000 + R->lo_variant) * 1000 +
                                                  inner};
             const int gprec = 16 + prec + (R->det_on ? 8 : 0);
+            const int parity = cur + 2 * cur32;
             if (!R->graph || R->graph_prec != gprec || R->graph_sweeps != gb || R->graph_key != key ||
-                R->graph_parity != cur) {
+                R->graph_parity != parity) {
                 drop_graph(R);
-                const int cur0 = cur;
+                const int cur0 = cur, cur32_0 = cur32;
                 hipGraph_t g = nullptr;
                 HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
                 for (int k = 0; k < gb; ++k) {
@@ -1075,8 +1105,9 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
                 R->graph_prec = gprec;
                 R->graph_sweeps = gb;
                 R->graph_key = key;
-                R->graph_parity = cur0;
+                R->graph_parity = parity;
                 cur = cur0;
+                cur32 = cur32_0;
             }
             while (!h.done) {
                 HIP_TRY(hipGraphLaunch(R->graph, s));

@@ -90,10 +90,12 @@ __device__ double block_max(double x, double* sh) {
 //   corr      delta = R + D (G + G^T) (homogeneous equation), low-precision 2 delta - S(delta)
 //   apply     T += delta - R (elementwise)
 // Mlo (optional) receives the low-precision copy of the combination written.
-template <class E>
+// G is read, and Gz cleared, in GT: double, or float for the FP32 accumulation
+// buffers of BF16 sweeps.
+template <class E, class GT>
 __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
     int mode, const MonoDesc* __restrict__ monos, const double* __restrict__ dif,
-    const double* __restrict__ K, const double* __restrict__ G, double* __restrict__ Gz,
+    const double* __restrict__ K, const GT* __restrict__ G, GT* __restrict__ Gz,
     double* __restrict__ T, double* __restrict__ M, double* __restrict__ R, double* __restrict__ Dl,
     E* __restrict__ Mlo, const int64_t* __restrict__ mlo_off, int lo_chunk, double* __restrict__ em2,
     double* __restrict__ em2_0, double* __restrict__ res, const Ctrl* __restrict__ ctrl,
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
     const int v = d.v, n = d.n, np = d.np;
     const double* dx = dif + d.dif_off;
     const double* Kx = K + d.mat_off;
-    const double* Gx = G ? G + d.mat_off : nullptr;
+    const GT* Gx = G ? G + d.mat_off : nullptr;
     double* Tx = T + d.mat_off;
     double* Mx = M + d.mat_off;
     double* Rx = R ? R + d.mat_off : nullptr;
@@ -130,8 +132,8 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
         double tn, ts, lo = 0.0;
         bool has_lo = false;
         if (mode == kMonoUpdate || mode == kMonoUpdateR) {
-            tn = dinv * ((Kx[e_rc] + Gx[e_rc]) + Gx[e_t]);
-            ts = dinv * ((Kx[e_s] + Gx[e_s]) + Gx[e_st]);
+            tn = dinv * ((Kx[e_rc] + (double)Gx[e_rc]) + (double)Gx[e_t]);
+            ts = dinv * ((Kx[e_s] + (double)Gx[e_s]) + (double)Gx[e_st]);
             const double told = Tx[e_rc];
             rmax = max_nan(rmax, fabs(tn - told));
             if (mode == kMonoUpdateR) {
@@ -143,8 +145,8 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
                 has_lo = true;
             }
         } else if (mode == kMonoCorr) {
-            tn = Rx[e_rc] + dinv * (Gx[e_rc] + Gx[e_t]);
-            ts = Rx[e_s] + dinv * (Gx[e_s] + Gx[e_st]);
+            tn = Rx[e_rc] + dinv * ((double)Gx[e_rc] + (double)Gx[e_t]);
+            ts = Rx[e_s] + dinv * ((double)Gx[e_s] + (double)Gx[e_st]);
             Dx[e_rc] = tn;
             lo = 2.0 * tn - ts;
             has_lo = true;
@@ -173,9 +175,9 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
         if (Ml && has_lo) Ml[(int64_t)r * ldl + c] = (E)(float)lo;
     }
     if (Gz) {
-        double* gz = Gz + d.mat_off;
+        GT* gz = Gz + d.mat_off;
         const int npp = np * np;
-        for (int idx = threadIdx.x; idx < npp; idx += kMonoThreads) gz[idx] = 0.0;
+        for (int idx = threadIdx.x; idx < npp; idx += kMonoThreads) gz[idx] = GT(0);
     }
     if (mode == kMonoApply || mode == kMonoRlo || mode == kMonoCorr) return;
     const double etot = block_sum<kMonoThreads>(esum, sh);
@@ -201,10 +203,10 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
 // K, T and R along contiguous block rows, G through LDS for the transposed
 // read.  Results are bitwise those of monomer_kernel (same operations in the
 // same order per element).
-template <class E, int VMAX>
+template <class E, int VMAX, class GT>
 __global__ __launch_bounds__(kMonoThreads) void monomer_blocks_kernel(
     int mode, const MonoDesc* __restrict__ monos, const double* __restrict__ dif,
-    const double* __restrict__ K, const double* __restrict__ G, double* __restrict__ Gz,
+    const double* __restrict__ K, const GT* __restrict__ G, GT* __restrict__ Gz,
     double* __restrict__ T, double* __restrict__ M, double* __restrict__ R, double* __restrict__ Dl,
     E* __restrict__ Mlo, const int64_t* __restrict__ mlo_off, int lo_chunk, double* __restrict__ em2,
     double* __restrict__ em2_0, double* __restrict__ res, const Ctrl* __restrict__ ctrl,
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_blocks_kernel(
     const int o = d.o, v = d.v, n = d.n, np = d.np;
     const double* dx = dif + d.dif_off;
     const double* Kx = K + d.mat_off;
-    const double* Gx = G ? G + d.mat_off : nullptr;
+    const GT* Gx = G ? G + d.mat_off : nullptr;
     double* Tx = T + d.mat_off;
     double* Mx = M + d.mat_off;
     double* Rx = R ? R + d.mat_off : nullptr;
@@ -234,8 +236,8 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_blocks_kernel(
                 __syncthreads();   // the previous block pair is done with sg
                 for (int idx = threadIdx.x; idx < v * v; idx += kMonoThreads) {
                     const int a = idx / v, b = idx - a * v;
-                    sg[0][a][b] = Gx[(int64_t)(i * v + a) * np + j * v + b];
-                    sg[1][a][b] = Gx[(int64_t)(j * v + a) * np + i * v + b];
+                    sg[0][a][b] = (double)Gx[(int64_t)(i * v + a) * np + j * v + b];
+                    sg[1][a][b] = (double)Gx[(int64_t)(j * v + a) * np + i * v + b];
                 }
                 __syncthreads();
             }
@@ -311,9 +313,9 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_blocks_kernel(
             }
         }
     if (Gz) {
-        double* gz = Gz + d.mat_off;
+        GT* gz = Gz + d.mat_off;
         const int npp = np * np;
-        for (int idx = threadIdx.x; idx < npp; idx += kMonoThreads) gz[idx] = 0.0;
+        for (int idx = threadIdx.x; idx < npp; idx += kMonoThreads) gz[idx] = GT(0);
     }
     if (mode == kMonoApply || mode == kMonoRlo || mode == kMonoCorr) return;
     const double etot = block_sum<kMonoThreads>(esum, sh);
@@ -484,40 +486,44 @@ void launch_nonfinite(const double* p, int64_t n, int32_t* flag, hipStream_t s) 
 }
 
 // Blocked kernel when every monomer's v fits its LDS tiles, the element-wise one otherwise.
-template <class E>
+template <class E, class GT>
 void monomer_dispatch(int max_v, int mode, const MonoDesc* monos, int n_mono, const double* dif, const double* K,
-                      const double* G, double* G_zero, double* T, double* M, double* R, double* Dl, E* Mlo,
+                      const GT* G, GT* G_zero, double* T, double* M, double* R, double* Dl, E* Mlo,
                       const int64_t* mlo_off, int chunk, double* em2, double* em2_0, double* res, const Ctrl* ctrl,
                       const ClState* cl, hipStream_t s) {
     if (n_mono <= 0) return;
     if (max_v <= 32)
-        hipLaunchKernelGGL((monomer_blocks_kernel<E, 32>), dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif,
-                           K, G, G_zero, T, M, R, Dl, Mlo, mlo_off, chunk, em2, em2_0, res, ctrl, cl);
+        hipLaunchKernelGGL((monomer_blocks_kernel<E, 32, GT>), dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos,
+                           dif, K, G, G_zero, T, M, R, Dl, Mlo, mlo_off, chunk, em2, em2_0, res, ctrl, cl);
     else if (max_v <= 64)
-        hipLaunchKernelGGL((monomer_blocks_kernel<E, 64>), dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif,
-                           K, G, G_zero, T, M, R, Dl, Mlo, mlo_off, chunk, em2, em2_0, res, ctrl, cl);
+        hipLaunchKernelGGL((monomer_blocks_kernel<E, 64, GT>), dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos,
+                           dif, K, G, G_zero, T, M, R, Dl, Mlo, mlo_off, chunk, em2, em2_0, res, ctrl, cl);
     else
-        hipLaunchKernelGGL(monomer_kernel<E>, dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif, K, G,
+        hipLaunchKernelGGL((monomer_kernel<E, GT>), dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif, K, G,
                            G_zero, T, M, R, Dl, Mlo, mlo_off, chunk, em2, em2_0, res, ctrl, cl);
 }
 
 void launch_monomer(int mode, const MonoDesc* monos, int n_mono, int max_v, const double* dif, const double* K,
                     const double* G, double* G_zero, double* T, double* M, double* em2,
                     double* em2_0, double* res, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
-    monomer_dispatch<float>(max_v, mode, monos, n_mono, dif, K, G, G_zero, T, M, nullptr, nullptr, nullptr, nullptr,
-                            16, em2, em2_0, res, ctrl, cl, s);
+    monomer_dispatch<float, double>(max_v, mode, monos, n_mono, dif, K, G, G_zero, T, M, nullptr, nullptr, nullptr,
+                                    nullptr, 16, em2, em2_0, res, ctrl, cl, s);
 }
 
 void launch_monomer_mixed(int mode, int precision, const MonoDesc* monos, int n_mono, int max_v, const double* dif,
                           const double* K, const double* G, double* G_zero, double* T, double* M, double* R,
                           double* Dl, void* Mlo, const int64_t* mlo_off, double* em2, double* em2_0,
-                          double* res, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
-    if (precision == 2)
-        monomer_dispatch<__bf16>(max_v, mode, monos, n_mono, dif, K, G, G_zero, T, M, R, Dl,
-                                 static_cast<__bf16*>(Mlo), mlo_off, 32, em2, em2_0, res, ctrl, cl, s);
+                          double* res, const Ctrl* ctrl, const ClState* cl, hipStream_t s, const float* Gf,
+                          float* Gf_zero) {
+    if (precision == 2 && (Gf || Gf_zero))
+        monomer_dispatch<__bf16, float>(max_v, mode, monos, n_mono, dif, K, Gf, Gf_zero, T, M, R, Dl,
+                                        static_cast<__bf16*>(Mlo), mlo_off, 32, em2, em2_0, res, ctrl, cl, s);
+    else if (precision == 2)
+        monomer_dispatch<__bf16, double>(max_v, mode, monos, n_mono, dif, K, G, G_zero, T, M, R, Dl,
+                                         static_cast<__bf16*>(Mlo), mlo_off, 32, em2, em2_0, res, ctrl, cl, s);
     else
-        monomer_dispatch<float>(max_v, mode, monos, n_mono, dif, K, G, G_zero, T, M, R, Dl, static_cast<float*>(Mlo),
-                                mlo_off, 16, em2, em2_0, res, ctrl, cl, s);
+        monomer_dispatch<float, double>(max_v, mode, monos, n_mono, dif, K, G, G_zero, T, M, R, Dl,
+                                        static_cast<float*>(Mlo), mlo_off, 16, em2, em2_0, res, ctrl, cl, s);
 }
 
 void launch_reduce_sweep(int n_cl, const int64_t* cl_mono, const double* res, ClState* cl, double* hist,

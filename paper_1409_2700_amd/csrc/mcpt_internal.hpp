@@ -110,10 +110,12 @@ void launch_monomer(int mode, const MonoDesc* monos, int n_mono, int max_v, cons
                     const double* K, const double* G, double* G_zero, double* T, double* M,
                     double* em2, double* em2_0, double* res, const Ctrl* ctrl, const ClState* cl,
                     hipStream_t s);
+// Gf / Gf_zero: the FP32 accumulation buffers of BF16 sweeps, read and cleared instead of G / G_zero
 void launch_monomer_mixed(int mode, int precision, const MonoDesc* monos, int n_mono, int max_v, const double* dif,
                           const double* K, const double* G, double* G_zero, double* T, double* M, double* R,
                           double* Dl, void* Mlo, const int64_t* mlo_off, double* em2, double* em2_0,
-                          double* res, const Ctrl* ctrl, const ClState* cl, hipStream_t s);
+                          double* res, const Ctrl* ctrl, const ClState* cl, hipStream_t s,
+                          const float* Gf = nullptr, float* Gf_zero = nullptr);
 void launch_reduce_sweep(int n_cl, const int64_t* cl_mono, const double* res, ClState* cl, double* hist,
                          Ctrl* ctrl, hipStream_t s);
 // G_X = sum of the stored partial blocks of monomer X (csr[csr_off[X] .. csr_off[X+1]):
@@ -149,7 +151,8 @@ int64_t lowp_lds_limit();
 int pair_lowp_blocks_per_cu(int precision, int variant, int64_t lds_bytes);
 void launch_pair_lowp(int precision, int variant, int64_t lds_bytes, PartOut po, const PairDesc* pairs, int64_t n_pair,
                       const MonoDesc* monos, const double* dif, const void* Vlo, const int64_t* lo_off,
-                      const void* Mlo, const int64_t* mlo_off, double* G, void* scratch, int64_t slot_elems, int grid,
-                      double* ed2, int source, int couple, const Ctrl* ctrl, const ClState* cl, hipStream_t s);
+                      const void* Mlo, const int64_t* mlo_off, double* G, float* Gf, void* scratch, int64_t slot_elems,
+                      int grid, double* ed2, int source, int couple, const Ctrl* ctrl, const ClState* cl,
+                      hipStream_t s);   // Gf non-null: G contributions in FP32 (G unused)
 
 }  // namespace mcpt

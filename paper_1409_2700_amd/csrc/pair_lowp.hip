@@ -9,7 +9,8 @@
 //     scratch), each row padded to a multiple of the k chunk and zero there;
 //     every operand fragment is then one 16-byte load per lane;
 //   * the epilogue in FP64: denominators 1 / (d_X + d_Y) (Eqs. 60-61), the
-//     source term, Tau and 4 <V, Tau> (Eq. 55); G accumulated in FP64;
+//     source term, Tau and 4 <V, Tau> (Eq. 55); G accumulated in FP64, or
+//     in FP32 when the caller passes an FP32 buffer (BF16 sweeps);
 //   * `source` = 0 drops the integral term V from Tau (the homogeneous
 //     correction equation of the FP64 polish).
 // FP32 runs v_mfma_f32_16x16x4_f32 four times per 16-deep chunk; BF16 runs one
@@ -211,8 +212,10 @@ __device__ inline void for_tasks(const Grid& g0, const Grid& g1, int wave, F&& f
 __device__ inline int acc_row(int lane, int t) { return ((lane >> 4) << 2) + t; }
 __device__ inline int acc_col(int lane) { return lane & 15; }
 
+// G block contributions: stored partials (deterministic mode), FP32 atomics
+// into the FP32 accumulation buffer (BF16 sweeps), or FP64 atomics into G
 template <int NR, int NC>
-__device__ inline void atomic_flush(double* G, double* part, int ld, int n, int r0, int q0, int lane,
+__device__ inline void atomic_flush(double* G, float* Gf, double* part, int ld, int n, int r0, int q0, int lane,
                                     const f4 (&acc)[NR][NC]) {
 #pragma unroll
     for (int i = 0; i < NR; ++i)
@@ -223,7 +226,10 @@ __device__ inline void atomic_flush(double* G, double* part, int ld, int n, int 
             for (int t = 0; t < 4; ++t) {
                 const int r = (r0 + i) * 16 + acc_row(lane, t);
                 if (part) part[(int64_t)r * ld + c] = (double)acc[i][j][t];
-                else if (r < n && c < n) unsafeAtomicAdd(G + (int64_t)r * ld + c, (double)acc[i][j][t]);
+                else if (r < n && c < n) {
+                    if (Gf) unsafeAtomicAdd(Gf + (int64_t)r * ld + c, acc[i][j][t]);
+                    else unsafeAtomicAdd(G + (int64_t)r * ld + c, (double)acc[i][j][t]);
+                }
             }
         }
 }
@@ -290,7 +296,7 @@ template <class E, int SB, int NW, int PD, bool IN_LDS>
 __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
     const PairDesc* __restrict__ pairs, int64_t n_pair, const MonoDesc* __restrict__ monos,
     const double* __restrict__ dif, const E* __restrict__ Vlo, const int64_t* __restrict__ lo_off,
-    const E* __restrict__ Mlo, const int64_t* __restrict__ mlo_off, double* __restrict__ G,
+    const E* __restrict__ Mlo, const int64_t* __restrict__ mlo_off, double* __restrict__ G, float* __restrict__ Gf,
     E* __restrict__ scratch, int64_t slot_elems, double* __restrict__ ed2, int source, int couple,
     const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl, PartOut po) {
     typedef Lowp<E> L;
@@ -421,8 +427,10 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
             }
         }
         if (couple) {
-            double* GX = G + dx.mat_off;
-            double* GY = G + dy.mat_off;
+            double* GX = G ? G + dx.mat_off : nullptr;
+            double* GY = G ? G + dy.mat_off : nullptr;
+            float* GfX = Gf ? Gf + dx.mat_off : nullptr;
+            float* GfY = Gf ? Gf + dy.mat_off : nullptr;
             // ---- G_X += Tau V^T (contract over Y index), G_Y += Tau^T V (contract over X index) ----
             for_tasks<SB, NW>(make_grid<SB>(RB, RB), make_grid<SB>(CB, CB), wave,
                               [&](int which, int r0, int c0, auto shape) {
@@ -432,15 +440,15 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
                 if (which == 0) {
                     if (kVtLds) gemm<E, NR, NC, PD>(Rows<E>{sTau, sldY}, vrows(), ldY, r0, c0, lane, acc);
                     else gemm<E, NR, NC, PD>(Rows<E>{tau, ldY}, vrows(), ldY, r0, c0, lane, acc);
-                    atomic_flush(GX, po.part ? po.part + po.off[pi] : nullptr, npX, nX, r0, c0, lane, acc);
+                    atomic_flush(GX, GfX, po.part ? po.part + po.off[pi] : nullptr, npX, nX, r0, c0, lane, acc);
                 } else {
                     if (kVtLds)   // Tau^T fragments as columns of the Tau kept in LDS
                         gemm<E, NR, NC, PD>(Cols<E>{sTau, sldY, npX}, Rows<E>{sVt, sldX}, ldX, r0, c0, lane, acc);
                     else if (IN_LDS)
                         gemm<E, NR, NC, PD>(Rows<E>{tauT, ldX}, Cols<E>{sV, sldY, npX}, ldX, r0, c0, lane, acc);
                     else gemm<E, NR, NC, PD>(Rows<E>{tauT, ldX}, Rows<E>{Vt, ldX}, ldX, r0, c0, lane, acc);
-                    atomic_flush(GY, po.part ? po.part + po.off[pi] + (int64_t)npX * npX : nullptr, npY, nY, r0, c0,
-                                 lane, acc);
+                    atomic_flush(GY, GfY, po.part ? po.part + po.off[pi] + (int64_t)npX * npX : nullptr, npY, nY, r0,
+                                 c0, lane, acc);
                 }
             });
         }
@@ -516,11 +524,12 @@ void launch_convert_v(int precision, const PairDesc* pairs, int64_t n_pair, cons
 
 void launch_pair_lowp(int precision, int variant, int64_t lds_bytes, PartOut po, const PairDesc* pairs, int64_t n_pair,
                       const MonoDesc* monos, const double* dif, const void* Vlo, const int64_t* lo_off,
-                      const void* Mlo, const int64_t* mlo_off, double* G, void* scratch, int64_t slot_elems, int grid,
-                      double* ed2, int source, int couple, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
+                      const void* Mlo, const int64_t* mlo_off, double* G, float* Gf, void* scratch, int64_t slot_elems,
+                      int grid, double* ed2, int source, int couple, const Ctrl* ctrl, const ClState* cl,
+                      hipStream_t s) {
     if (n_pair <= 0) return;
     void* args[] = {(void*)&pairs, (void*)&n_pair, (void*)&monos, (void*)&dif, (void*)&Vlo, (void*)&lo_off,
-                    (void*)&Mlo, (void*)&mlo_off, (void*)&G, (void*)&scratch, (void*)&slot_elems, (void*)&ed2,
+                    (void*)&Mlo, (void*)&mlo_off, (void*)&G, (void*)&Gf, (void*)&scratch, (void*)&slot_elems, (void*)&ed2,
                     (void*)&source, (void*)&couple, (void*)&ctrl, (void*)&cl, (void*)&po};
     (void)hipLaunchKernel(lowp_kernel(precision, variant, lds_bytes > 0), dim3(grid),
                           dim3(lowp_variant_threads(variant)), args, (size_t)std::max<int64_t>(lds_bytes, 0), s);

@@ -61,6 +61,7 @@ struct Resident {
     void *d_Vlo = nullptr, *d_Mlo = nullptr;
     int64_t *d_lo_off = nullptr, *d_mlo_off = nullptr;
     double *d_R = nullptr, *d_Dl = nullptr;
+    float* d_G32[2] = {nullptr, nullptr};   // BF16 sweeps: G accumulated in FP32 (double-buffered like d_G)
     int64_t lo_slot = 0;          // elements of one low-precision Tau + Tau^T scratch slot
     double lo_v_bytes = 0.0;      // bytes of the low-precision V and V^T
     std::vector<void*> lo_allocations;
