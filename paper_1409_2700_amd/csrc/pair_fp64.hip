@@ -26,10 +26,13 @@
 // untransposed for G_Y) come from L2 with the next k-chunk prefetched into
 // registers.  Output tiles of 16 x 16 are grouped into 3 x 3 super-blocks
 // (accumulators in registers, each operand fragment reused three times); whole
-// super-blocks go round-robin to the wavefronts and the tiles of the remainder
-// one by one, so the SIMDs get (nearly) equal work between barriers.  Task
-// shapes are compile-time (3 x 3 or a single tile) so each MFMA block is
-// straight-line code.
+// super-blocks go round-robin to the wavefronts and the super-blocks left over
+// as 1 x 3 row strips, so the SIMDs get (nearly) equal work between barriers.
+// Task shapes are compile-time (3 x 3, 1 x 3 or a single tile) so each MFMA
+// block is straight-line code.  A wave raises its issue priority while it runs
+// an MFMA block, so the two waves of a SIMD tend to alternate whole blocks (one
+// computes while the other's operand loads are in flight) instead of
+// interleaving single instructions.
 //
 // Operand layout of the instruction (measured): A lane l = (row l%16, k l/16),
 // B lane l = (k l/16, column l%16), accumulator element t of lane l = (row
@@ -93,12 +96,14 @@ __device__ inline void zero(d4 (&acc)[NR][NC]) {
 
 template <int NR, int NC>
 __device__ inline void mma_block(d4 (&acc)[NR][NC], const double (&a)[NR][4], const double (&b)[NC][4]) {
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int i = 0; i < NR; ++i)
 #pragma unroll
             for (int j = 0; j < NC; ++j) acc[i][j] = mfma(a[i][s], b[j][s], acc[i][j]);
+    __builtin_amdgcn_s_setprio(0);
 }
 
 struct PairView {
@@ -327,7 +332,12 @@ __device__ inline Grid make_grid(int RT, int CT) {
 }
 
 // Visit the tasks of `wave` over the concatenation of grids g0 and g1 (g1 may be
-// empty): f(which, r0, c0, Shape<3,3>{} or Shape<1,1>{}) in tile coordinates.
+// empty): f(which, r0, c0, shape) in tile coordinates, shape Shape<3,3>,
+// Shape<1,3> or Shape<1,1>.  Full super-blocks go round-robin to the waves; the
+// super-blocks left over after the last full round are cut into 1 x 3 row
+// strips (three independent accumulators keep the MFMA pipe busy, where single
+// tiles would wait on each k chunk) and dealt out one by one.  Edge super-blocks
+// narrower than three tiles run as single tiles.
 template <class F>
 __device__ inline void for_tasks(const Grid& g0, const Grid& g1, int wave, int nwaves, F&& f) {
     const int total = g0.n + g1.n;
@@ -341,8 +351,11 @@ __device__ inline void for_tasks(const Grid& g0, const Grid& g1, int wave, int n
         if (nr == kSB && nc == kSB) {
             f(which, r0, c0, Shape<kSB, kSB>{});
         } else {
-            for (int i = 0; i < nr; ++i)
-                for (int j = 0; j < nc; ++j) f(which, r0 + i, c0 + j, Shape<1, 1>{});
+            for (int i = 0; i < nr; ++i) {
+                if (nc == kSB) f(which, r0 + i, c0, Shape<1, kSB>{});
+                else
+                    for (int j = 0; j < nc; ++j) f(which, r0 + i, c0 + j, Shape<1, 1>{});
+            }
         }
     }
     int idx = 0;
@@ -352,9 +365,14 @@ __device__ inline void for_tasks(const Grid& g0, const Grid& g1, int wave, int n
         const int s = which ? sb - g0.n : sb;
         const int r0 = (s / g.SC) * kSB, c0 = (s % g.SC) * kSB;
         const int nr = min(kSB, g.RT - r0), nc = min(kSB, g.CT - c0);
-        for (int i = 0; i < nr; ++i)
-            for (int j = 0; j < nc; ++j, ++idx)
-                if (idx % nwaves == wave) f(which, r0 + i, c0 + j, Shape<1, 1>{});
+        for (int i = 0; i < nr; ++i) {
+            if (nc == kSB) {
+                if (idx++ % nwaves == wave) f(which, r0 + i, c0, Shape<1, kSB>{});
+            } else {
+                for (int j = 0; j < nc; ++j, ++idx)
+                    if (idx % nwaves == wave) f(which, r0 + i, c0 + j, Shape<1, 1>{});
+            }
+        }
     }
 }
 
