@@ -177,10 +177,15 @@ __device__ inline Grid make_grid(int RT, int CT) {
 }
 
 // Wave tasks over one or two tile grids: full SB x SB super-blocks are dealt
-// round-robin; the tiles of the ragged remainder are dealt one by one.
+// round-robin; the super-blocks left over after the last full round, and edge
+// super-blocks, are cut into 1 x SB row strips where they are SB tiles wide
+// (several accumulators in flight instead of one) and into single tiles
+// otherwise, dealt one by one.  Shapes with 16 waves (128 registers per lane)
+// use single tiles only: the strip code paths would spill there.
 template <int SB, int NW, class F>
 __device__ inline void for_tasks(const Grid& g0, const Grid& g1, int wave, F&& f) {
     constexpr int kSB = SB, kWaves = NW;
+    constexpr bool kStrips = NW <= 8;
     const int total = g0.n + g1.n;
     const int full = total - total % kWaves;
     for (int sb = wave; sb < full; sb += kWaves) {
@@ -192,8 +197,11 @@ __device__ inline void for_tasks(const Grid& g0, const Grid& g1, int wave, F&& f
         if (nr == kSB && nc == kSB) {
             f(which, r0, c0, Shape<kSB, kSB>{});
         } else {
-            for (int i = 0; i < nr; ++i)
-                for (int j = 0; j < nc; ++j) f(which, r0 + i, c0 + j, Shape<1, 1>{});
+            for (int i = 0; i < nr; ++i) {
+                if (kStrips && nc == kSB) f(which, r0 + i, c0, Shape<1, kStrips ? kSB : 1>{});
+                else
+                    for (int j = 0; j < nc; ++j) f(which, r0 + i, c0 + j, Shape<1, 1>{});
+            }
         }
     }
     int idx = 0;
@@ -203,9 +211,14 @@ __device__ inline void for_tasks(const Grid& g0, const Grid& g1, int wave, F&& f
         const int s = which ? sb - g0.n : sb;
         const int r0 = (s / g.SC) * kSB, c0 = (s % g.SC) * kSB;
         const int nr = min(kSB, g.RT - r0), nc = min(kSB, g.CT - c0);
-        for (int i = 0; i < nr; ++i)
-            for (int j = 0; j < nc; ++j, ++idx)
-                if (idx % kWaves == wave) f(which, r0 + i, c0 + j, Shape<1, 1>{});
+        for (int i = 0; i < nr; ++i) {
+            if (kStrips && nc == kSB) {
+                if (idx++ % kWaves == wave) f(which, r0 + i, c0, Shape<1, kStrips ? kSB : 1>{});
+            } else {
+                for (int j = 0; j < nc; ++j, ++idx)
+                    if (idx % kWaves == wave) f(which, r0 + i, c0 + j, Shape<1, 1>{});
+            }
+        }
     }
 }
 
