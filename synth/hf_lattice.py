@@ -42,6 +42,8 @@ KIND_MONOMER = 0
 KIND_PAIR = 1
 KIND_CLUSTER = 2
 KIND_STREAM = 3
+KIND_SINGLES = 4
+SIGMA_W = 0.05
 
 
 @dataclasses.dataclass
@@ -374,3 +376,20 @@ def carve_served_request(base: Problem, r: int, *, workload: int = 5, min_mono: 
     meta = dict(base.meta)
     meta.update(name=f"served-{r}", displacement=(mono, axis, sign * step_angstrom), carved_from=base.n_mono)
     return Problem(base.n_occ[order].copy(), base.n_vir[order].copy(), eps, k, pairs, v, sites[order], meta)
+
+
+def singles_source(prob: Problem, *, workload: int | None = None, cluster: int | None = None,
+                   sigma: float = SIGMA_W) -> np.ndarray:
+    """Seeded stand-in for the embedding one-electron term w^a_i of each monomer
+    (Eq. 26; its nuclear-attraction and Coulomb parts need geometries and AO
+    integrals that are not available): w_X[i, a] ~ N(0, sigma^2), concatenated
+    over monomers, row-major (o_X, v_X).  Keyed by the workload, the cluster and
+    the monomer's lattice site (its index when the problem has no sites)."""
+    wl = int(prob.meta.get("workload", 0) if workload is None else workload)
+    cl = int(prob.meta.get("cluster", 0) if cluster is None else cluster)
+    parts = []
+    for x in range(prob.n_mono):
+        key = prob.sites[x] if prob.sites is not None else (x, 0, 0)
+        rng = _rng(wl, cl, KIND_SINGLES, *key)
+        parts.append(rng.normal(0.0, sigma, size=prob.n_ov(x)))
+    return np.concatenate(parts) if parts else np.zeros(0)

@@ -248,3 +248,45 @@ def supersystem_mp2(prob) -> float:
                     ibja = cl.chem(I, B, J, A)
                     e += iajb * (2 * iajb - ibja) / (cl.e(I) + cl.e(J) - cl.e(A) - cl.e(B))
     return e
+
+
+def brute_singles_first_order(cl: Cluster, w):
+    """t^a_i = w^a_i / eps^i_a (the singles start of step 4, first order)."""
+    t = []
+    for X in range(cl.N):
+        tx = np.zeros((len(cl.occ[X]), len(cl.vir[X])))
+        for i in cl.occ[X]:
+            for a in cl.vir[X]:
+                tx[i.idx, a.idx] = w[X][i.idx, a.idx] / (cl.e(i) - cl.e(a))
+        t.append(tx)
+    return t
+
+
+def brute_singles_sweep(cl: Cluster, w, t):
+    """One Jacobi sweep of Eq. (57), source and pair terms:
+    eps^i_a t^a_i = w^a_i + sum over neighbours Y, k, c in Y of v^{ak}_{ic} t^c_k."""
+    out = []
+    for X in range(cl.N):
+        tx = np.zeros((len(cl.occ[X]), len(cl.vir[X])))
+        for i in cl.occ[X]:
+            for a in cl.vir[X]:
+                rhs = w[X][i.idx, a.idx]
+                for Y in cl.neighbours[X]:
+                    for k in cl.occ[Y]:
+                        for c in cl.vir[Y]:
+                            rhs += cl.v(a, k, i, c) * t[Y][k.idx, c.idx]      # v^{ak}_{ic}
+                tx[i.idx, a.idx] = rhs / (cl.e(i) - cl.e(a))
+        out.append(tx)
+    return out
+
+
+def brute_singles_energy(cl: Cluster, w, t):
+    """E_M1(X) = 2 w^i_a t^a_i (Eq. 53), per monomer."""
+    e = []
+    for X in range(cl.N):
+        s = 0.0
+        for i in cl.occ[X]:
+            for a in cl.vir[X]:
+                s += 2.0 * w[X][i.idx, a.idx] * t[X][i.idx, a.idx]
+        e.append(s)
+    return np.array(e)
