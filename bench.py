@@ -341,6 +341,71 @@ def pmc_pass(workload: str, precision: int = 0, sweeps: int = 2):
             f"E={s['e_total']:.10f}")
 
 
+def singles_mode(ctx, pid, prob, steps, warmup, tol):
+    """Singles solves (Eq. 57 pair coupling, Eq. 53 energy) of the resident
+    workload from the seeded source w: solves/s, the pair kernel against the
+    HBM roofline (algorithmic bytes = the V stream, 8 nX nY per pair), the
+    error against the stored singles-oracle result, and the oracle's own cost
+    on a sample of pairs scaled to one solve."""
+    import numpy as np
+    from synth import singles_source
+    w = singles_source(prob)
+    gpath = os.path.join(ROOT, "tests", "golden", f"singles-{prob.meta.get('name', '')}.json")
+    golden = json.load(open(gpath)) if os.path.exists(gpath) else None
+    for _ in range(warmup):
+        ctx.singles(pid, w, tol=tol)
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s = ctx.singles(pid, w, tol=tol)
+    dt = (time.perf_counter() - t0) / max(steps, 1)
+    tm = ctx.timing()
+    ctx.set_timing(False)
+    kl = max(tm["singles_launches"], 1)
+    ms = tm["singles_ms"] / kl
+    vb = tm["singles_v_bytes"] / kl
+    out = {
+        "solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "sweeps": s["sweeps"], "e_m1": s["e_m1"],
+        "pair_kernel": {"kernel": "singles_pair_kernel", "bound": "hbm", "avg_launch_ms": ms,
+                        "algorithmic_bytes_per_launch": vb, "achieved_GBps": vb / (ms * 1e-3) / 1e9,
+                        "peak_GBps": HBM_PEAK_GBS, "frac": vb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "launches": tm["singles_launches"]},
+    }
+    if golden is not None:
+        e = ctx.singles_result(pid)
+        out["oracle_reference"] = {"e_m1": golden["e_m1_total"], "sweeps": golden["sweeps"],
+                                   "file": os.path.relpath(gpath, ROOT)}
+        out["relative_error_e_m1"] = abs(s["e_m1"] - golden["e_m1_total"]) / abs(golden["e_m1_total"])
+        out["max_rel_error_per_monomer"] = float(np.max(np.abs(e["e_m1"] - np.asarray(golden["e_m1"]))) /
+                                                 np.max(np.abs(golden["e_m1"])))
+    log(f"[bench] singles: {s['sweeps']} sweeps, {dt * 1e3:.1f} ms per solve, pair kernel {ms:.3f} ms = "
+        f"{vb / (ms * 1e-3) / 1e9:.0f} GB/s")
+    return out
+
+
+def singles_cpu(prob, sweeps: int, sample_pairs: int = 4096) -> dict:
+    """The singles oracle's pair sum timed on the first sample_pairs pairs,
+    scaled to one solve (sweeps x all pairs)."""
+    import numpy as np
+    from oracle import mcpt_singles
+    from synth import singles_source
+    w = singles_source(prob)
+    t, off = [], 0
+    for x in range(prob.n_mono):
+        n = prob.n_ov(x)
+        t.append(w[off:off + n].reshape(int(prob.n_occ[x]), int(prob.n_vir[x])))
+        off += n
+    k = min(sample_pairs, prob.n_pair)
+    sub = prob.subset_pairs(np.arange(prob.n_pair) < k)
+    t0 = time.perf_counter()
+    mcpt_singles.coupling(sub, t)
+    per_pair = (time.perf_counter() - t0) / max(k, 1)
+    solve_s = per_pair * prob.n_pair * sweeps
+    return {"value": 1.0 / solve_s, "unit": "solves/s", "kind": "oracle",
+            "sample": f"pair sum of the first {k} pairs ({per_pair * 1e6:.0f} us per pair), scaled to "
+                      f"{prob.n_pair} pairs x {sweeps} sweeps ({solve_s:.0f} s per solve)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -360,6 +425,7 @@ def main():
     ap.add_argument("--pmc-pass", action="store_true",
                     help="only launch a calibration copy and two fixed sweeps (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-precision", type=int, default=0, help="0 FP64, 1 FP32, 2 BF16 sweeps in --pmc-pass")
+    ap.add_argument("--singles-steps", type=int, default=3, help="timed singles solves (0: skip)")
     ap.add_argument("--batched", type=int, default=0,
                     help="also time the batching form on this many uneven clusters (64 = full set)")
     args = ap.parse_args()
@@ -395,6 +461,9 @@ def main():
     for name in modes:
         results[name] = time_mode(ctx, pid, name, args.steps, args.warmup, args.tol, args.check_every, golden,
                                   args.graph)
+    singles = None
+    if args.singles_steps > 0:
+        singles = singles_mode(ctx, pid, prob, args.singles_steps, 1, args.tol)
     ctx.release(pid)
     ctx.close()
     served = None
@@ -446,6 +515,8 @@ def main():
             "frac": mono_bytes / (mono_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "timing"} for k, v in results.items()},
     }
+    if singles is not None:
+        out["singles"] = singles
     if served is not None:
         out["serving"] = served
     if args.batched > 0:
@@ -457,6 +528,9 @@ def main():
         log("[bench] timing the CPU oracle on a sample ...")
         out["cpu_baseline"] = cpu_baseline(prob, golden["sweeps"] if golden else h["sweeps"], args.cpu_budget)
         log(f"[bench] cpu_baseline {out['cpu_baseline']['value']:.3e} solves/s")
+        if singles is not None:
+            singles["cpu_oracle"] = singles_cpu(prob, singles["sweeps"])
+            log(f"[bench] singles cpu oracle {singles['cpu_oracle']['value']:.3e} solves/s")
     print(json.dumps(out), flush=True)
 
 

@@ -136,6 +136,9 @@ typedef struct {
     int64_t lowp_launches;
     double  lowp_flops;     /* algorithmic flops of those launches (4 nX nY (nX + nY) per pair) */
     double  lowp_v_bytes;   /* bytes of the reduced-precision dimer blocks (V and V^T) they read */
+    double  singles_ms;     /* summed duration of singles pair-phase launches (mcpt_singles) */
+    int64_t singles_launches;
+    double  singles_v_bytes;/* dimer-block bytes those launches streamed (8 nX nY per pair) */
 } mcpt_timing;
 
 /* Create a context on HIP device `device`; at most hbm_budget_bytes of device
@@ -203,6 +206,48 @@ mcpt_status mcpt_energy(mcpt_ctx *ctx, uint64_t id, double *e_m2, double *de_m2,
 
 /* Free a resident problem. Errors: MCPT_ERR_UNKNOWN_ID. */
 mcpt_status mcpt_release(mcpt_ctx *ctx, uint64_t id);
+
+/* ---- Singles amplitudes (Eq. 57, program-flow step 4) ----
+ * With the terms the inputs can form - the embedding source w and the pair sum
+ * over neighbours Y of v^{ak}_{ic} t^c_k, where v^{ak}_{ic} = (ai|ck) =
+ * V_XY[i][a][k][c] is the resident dimer block (the reversed pair uses V_XY^T);
+ * the intramonomer term needs an integral class that is not an input and is
+ * not formed - a sweep is t_X = (w_X + sum_Y V_XY t_Y) / (e_i - e_a) for every
+ * monomer from the previous t (Jacobi), from the first-order start
+ * t = w / (e_i - e_a).  Each cluster of a batch stops on its own
+ * max|t_new - t| < tol (tol == 0: exactly max_sweeps sweeps) under the divergence
+ * rule of mcpt_run; then E_M1(X) = 2 w.t_X (Eq. 53).  Singles and doubles are
+ * independent equations: mcpt_singles neither reads nor changes the doubles
+ * amplitudes or results of the problem. */
+typedef struct {
+    double  e_m1;        /* sum over monomers of E_M1(X) */
+    double  e_m1_0;      /* the same at the first-order amplitudes (zero coupling) */
+    double  residual;    /* largest last residual over clusters */
+    double  seconds;     /* wall time of the call */
+    int32_t sweeps;      /* most sweeps of any cluster */
+    int32_t status;      /* mcpt_status of the solve (worst cluster) */
+} mcpt_singles_summary;
+
+/* Solve the singles of a resident problem.  w: sum_X o_X v_X values
+ * w_X[i][a] = w^a_i (the occupied-virtual block of the embedding operator of
+ * Eq. 26), monomers concatenated in upload order, on the host or (memory =
+ * MCPT_DEVICE) on the context's GPU; read before the call returns.  opts: tol,
+ * max_sweeps and check_every are used; precision must be MCPT_FP64 and
+ * deterministic 0; the other fields are ignored.  Writes *out (may be NULL).
+ * Returns the solve status as mcpt_run does; also MCPT_ERR_NONFINITE (w not
+ * finite), MCPT_ERR_ADMISSION (the singles buffers - three vectors of
+ * sum_X n_X doubles padded as the monomer matrices' rows, three of N doubles
+ * and a 32 KiB residual history per cluster, made on the first call and kept
+ * with the problem - exceed the budget), MCPT_ERR_INVALID (options, a monomer
+ * with o_X v_X above 16384), MCPT_ERR_UNKNOWN_ID, MCPT_ERR_DEVICE. */
+mcpt_status mcpt_singles(mcpt_ctx *ctx, uint64_t id, const double *w, int32_t memory, const mcpt_options *opts,
+                         mcpt_singles_summary *out);
+
+/* Results of the last mcpt_singles of a resident problem: e_m1[N] = E_M1(X)
+ * and t1[sum_X o_X v_X] = t_X[i][a] = t^a_i, monomers concatenated; either may
+ * be NULL.  Errors: MCPT_ERR_UNKNOWN_ID, MCPT_ERR_INVALID (no singles result:
+ * never solved, or diverged), MCPT_ERR_DEVICE. */
+mcpt_status mcpt_singles_result(mcpt_ctx *ctx, uint64_t id, double *e_m1, double *t1);
 
 /* ---- Tile autotuner of the reduced-precision pair kernel ----
  * The kernel exists in several tile shapes: each wave computes sb x sb output

@@ -158,6 +158,10 @@ void drain_timing(Timing& t) {
                 t.tot.lowp_launches += 1;
                 t.tot.lowp_flops += r.flops;
                 t.tot.lowp_v_bytes += r.vbytes;
+            } else if (r.kind == 3) {
+                t.tot.singles_ms += ms;
+                t.tot.singles_launches += 1;
+                t.tot.singles_v_bytes += r.vbytes;
             } else {
                 t.tot.mono_ms += ms;
                 t.tot.mono_launches += 1;
@@ -876,6 +880,134 @@ mcpt_status autotune(mcpt_ctx* c, Exec& x, Resident* R, int prec, mcpt_tune_resu
     return ensure_scratch_lo(c, x, R, prec);
 }
 
+// Singles buffers of a resident problem, made once and kept with it.
+mcpt_status ensure_singles(mcpt_ctx* c, Exec& x, Resident* R) {
+    if (R->d_w1) return MCPT_OK;
+    auto rnd = [](int64_t bytes) { return (size_t)((std::max<int64_t>(bytes, 1) + 255) / 256 * 256); };
+    const size_t need = 3 * rnd(8 * R->dif_elems) + 3 * rnd(8 * (int64_t)R->n_mono) +
+                        rnd(8 * (int64_t)R->n_cl * kMaxSweeps) + rnd((int64_t)R->n_cl * (int64_t)sizeof(ClState)) +
+                        rnd(8 * (int64_t)(R->n_mono + 1));
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        if (c->in_use + (c->reserved - x.reserved) + need > c->budget)
+            return fail(MCPT_ERR_ADMISSION, "singles buffers exceed the budget");
+    }
+    mcpt_status st;
+    if ((st = dev_alloc(c, R, &R->d_w1, R->dif_elems)) != MCPT_OK ||
+        (st = dev_alloc(c, R, &R->d_t1, R->dif_elems)) != MCPT_OK ||
+        (st = dev_alloc(c, R, &R->d_u1, R->dif_elems)) != MCPT_OK ||
+        (st = dev_alloc(c, R, &R->d_em1, R->n_mono)) != MCPT_OK ||
+        (st = dev_alloc(c, R, &R->d_em1_0, R->n_mono)) != MCPT_OK ||
+        (st = dev_alloc(c, R, &R->d_res1, R->n_mono)) != MCPT_OK ||
+        (st = dev_alloc(c, R, &R->d_hist1, (int64_t)R->n_cl * kMaxSweeps)) != MCPT_OK ||
+        (st = dev_alloc(c, R, &R->d_cl1, R->n_cl)) != MCPT_OK ||
+        (st = dev_alloc(c, R, &R->d_woff, (int64_t)R->n_mono + 1)) != MCPT_OK) {
+        R->d_w1 = nullptr;   // the pieces already made stay with the problem and are freed with it
+        return st;
+    }
+    std::vector<int64_t> woff(R->n_mono + 1, 0);
+    for (int m = 0; m < R->n_mono; ++m) woff[m + 1] = woff[m] + R->monos[m].n;
+    HIP_TRY(hipMemcpyAsync(R->d_woff, woff.data(), woff.size() * sizeof(int64_t), hipMemcpyHostToDevice, x.stream));
+    HIP_TRY(hipStreamSynchronize(x.stream));
+    return MCPT_OK;
+}
+
+// Singles solve of a resident problem (Eq. 57 pair coupling, Eq. 53 energies).
+mcpt_status singles(mcpt_ctx* c, Exec& x, Resident* R, const double* w, int32_t memory, const mcpt_options* o,
+                    mcpt_singles_summary* out) {
+    mcpt_status st = validate_options(o);
+    if (st != MCPT_OK) return st;
+    if (o->precision != MCPT_FP64) return fail(MCPT_ERR_INVALID, "singles run in FP64 only");
+    if (o->deterministic) return fail(MCPT_ERR_INVALID, "singles have no deterministic mode");
+    if (memory != MCPT_HOST && memory != MCPT_DEVICE) return fail(MCPT_ERR_INVALID, "memory must be MCPT_HOST or MCPT_DEVICE");
+    if (R->max_n > 16384) return fail(MCPT_ERR_INVALID, "a monomer has o*v above 16384 (singles row sums in LDS)");
+    int64_t nw = 0;
+    for (const MonoDesc& m : R->monos) nw += m.n;
+    if (!w && nw > 0) return fail(MCPT_ERR_INVALID, "w is NULL");
+    if ((st = ensure_device(c)) != MCPT_OK || (st = ensure_singles(c, x, R)) != MCPT_OK) return st;
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = x.stream;
+    R->has_singles = false;
+    // w: checked, then scattered into the padded layout (d_u1 stages the compact copy)
+    if (nw > 0) {
+        if (memory == MCPT_HOST) {
+            for (int64_t k = 0; k < nw; ++k)
+                if (!std::isfinite(w[k])) return fail(MCPT_ERR_NONFINITE, "w has a non-finite value");
+            HIP_TRY(hipMemcpyAsync(R->d_u1, w, nw * sizeof(double), hipMemcpyHostToDevice, s));
+        } else {
+            HIP_TRY(hipMemcpyAsync(R->d_u1, w, nw * sizeof(double), hipMemcpyDeviceToDevice, s));
+            *x.h_flag = 0;
+            HIP_TRY(hipMemcpyAsync(x.d_flag, x.h_flag, sizeof(int32_t), hipMemcpyHostToDevice, s));
+            launch_nonfinite(R->d_u1, nw, x.d_flag, s);
+            HIP_TRY(hipMemcpyAsync(x.h_flag, x.d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (*x.h_flag) return fail(MCPT_ERR_NONFINITE, "w has a non-finite value");
+        }
+        launch_singles_scatter(R->d_monos, R->n_mono, R->d_woff, R->d_u1, R->d_w1, s);
+    }
+    launch_fill(R->d_u1, R->dif_elems, 0.0, s);
+    Ctrl& h = *x.h_ctrl;
+    std::memset(&h, 0, sizeof(Ctrl));
+    h.fixed = o->tol == 0.0;
+    h.max_sweeps = o->max_sweeps;
+    h.tol = o->tol;
+    HIP_TRY(hipMemcpyAsync(x.d_ctrl, &h, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+    {
+        std::vector<ClState> zero(R->n_cl, ClState{});
+        for (int q = 0; q < R->n_cl; ++q)
+            if (!R->cl_bad.empty() && R->cl_bad[q]) {
+                zero[q].done = 1;
+                zero[q].status = MCPT_ERR_NONFINITE;
+            }
+        HIP_TRY(hipMemcpyAsync(R->d_cl1, zero.data(), R->n_cl * sizeof(ClState), hipMemcpyHostToDevice, s));
+    }
+    launch_singles_mono(1, R->d_monos, R->n_mono, R->d_dif, R->d_w1, R->d_u1, R->d_t1, R->d_em1, R->d_em1_0,
+                        R->d_res1, nullptr, R->d_cl1, s);
+    HIP_TRY(hipGetLastError());
+    const int grid = singles_pair_grid(c->n_cu, R->max_n);
+    const double vb = (double)R->v_elems * sizeof(double);
+    const int every = o->check_every > 0 ? o->check_every : 1;
+    int issued = 0;
+    while (issued < o->max_sweeps) {
+        const int batch = std::min(every, o->max_sweeps - issued);
+        for (int k = 0; k < batch; ++k) {
+            hipEvent_t a = nullptr;
+            record_begin(x, &a);
+            launch_singles_pair(R->d_pairs, R->n_pair, R->d_monos, R->d_V, R->d_t1, R->d_u1, R->max_n, grid, x.d_ctrl,
+                                R->d_cl1, s);
+            record_end(x, a, 3, 0.0, vb);
+            launch_singles_mono(0, R->d_monos, R->n_mono, R->d_dif, R->d_w1, R->d_u1, R->d_t1, R->d_em1, R->d_em1_0,
+                                R->d_res1, x.d_ctrl, R->d_cl1, s);
+            launch_reduce_sweep(R->n_cl, R->d_cl_mono, R->d_res1, R->d_cl1, R->d_hist1, x.d_ctrl, s);
+            ++issued;
+        }
+        if ((st = sync_ctrl(x)) != MCPT_OK) return st;
+        if (h.done) break;
+    }
+    launch_singles_clusters(R->n_cl, R->d_cl_mono, R->d_em1, R->d_em1_0, R->d_cl1, s);
+    std::vector<ClState> cs(R->n_cl);
+    HIP_TRY(hipMemcpyAsync(cs.data(), R->d_cl1, R->n_cl * sizeof(ClState), hipMemcpyDeviceToHost, s));
+    if ((st = sync_ctrl(x)) != MCPT_OK) return st;
+    if (x.timing.on) drain_timing(x.timing);
+    mcpt_singles_summary sm{};
+    for (const ClState& q : cs) {
+        sm.e_m1 += q.e_mono;
+        sm.e_m1_0 += q.e_mono0;
+    }
+    sm.residual = h.residual;
+    sm.sweeps = h.sweeps;
+    sm.status = h.status;
+    sm.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    R->singles_last = sm;
+    if (out) *out = sm;
+    if (sm.status == MCPT_ERR_DIVERGED && R->n_cl == 1)
+        return fail(MCPT_ERR_DIVERGED, "singles iteration diverged after " + std::to_string(sm.sweeps) + " sweeps");
+    R->has_singles = true;
+    if (sm.status == MCPT_ERR_NOT_CONVERGED)
+        return fail(MCPT_ERR_NOT_CONVERGED, "singles not converged in " + std::to_string(o->max_sweeps) + " sweeps");
+    return (mcpt_status)sm.status;
+}
+
 mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_summary* out) {
     mcpt_status st = validate_options(o);
     if (st != MCPT_OK) return st;
@@ -1344,6 +1476,41 @@ mcpt_status mcpt_release(mcpt_ctx* c, uint64_t id) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->main.stream);
     release_resident(c, id);
+    return MCPT_OK;
+}
+
+mcpt_status mcpt_singles(mcpt_ctx* c, uint64_t id, const double* w, int32_t memory, const mcpt_options* opts,
+                         mcpt_singles_summary* out) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    Resident* R = find_resident(c, id);
+    if (!R) return unknown(id);
+    try {
+        return singles(c, c->main, R, w, memory, opts, out);
+    } catch (const std::exception& e) {
+        return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
+    }
+}
+
+mcpt_status mcpt_singles_result(mcpt_ctx* c, uint64_t id, double* e_m1, double* t1) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    Resident* R = find_resident(c, id);
+    if (!R) return unknown(id);
+    if (!R->has_singles) return fail(MCPT_ERR_INVALID, "problem has no singles result (not solved, or diverged)");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = c->main.stream;
+    if (e_m1 && R->n_mono > 0)
+        HIP_TRY(hipMemcpyAsync(e_m1, R->d_em1, R->n_mono * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<double> tp;
+    if (t1 && R->dif_elems > 0) {
+        tp.resize(R->dif_elems);
+        HIP_TRY(hipMemcpyAsync(tp.data(), R->d_t1, R->dif_elems * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    if (t1) {
+        int64_t k = 0;
+        for (const MonoDesc& m : R->monos)
+            for (int e = 0; e < m.n; ++e) t1[k++] = tp[m.dif_off + e];
+    }
     return MCPT_OK;
 }
 

@@ -66,6 +66,14 @@ struct Resident {
     double lo_v_bytes = 0.0;      // bytes of the low-precision V and V^T
     std::vector<void*> lo_allocations;
     size_t lo_bytes = 0;
+    // singles (made on the first mcpt_singles; freed with the problem): vectors in the padded
+    // dif layout, per-monomer energies and residuals, per-cluster state and history
+    double *d_w1 = nullptr, *d_t1 = nullptr, *d_u1 = nullptr;
+    double *d_em1 = nullptr, *d_em1_0 = nullptr, *d_res1 = nullptr, *d_hist1 = nullptr;
+    ClState* d_cl1 = nullptr;
+    int64_t* d_woff = nullptr;        // compact offsets of w per monomer (N + 1)
+    bool has_singles = false;
+    mcpt_singles_summary singles_last{};
     // captured sweep graph: valid for one form, one execution resource set and one body count
     hipGraphExec_t graph = nullptr;
     int graph_prec = -1, graph_sweeps = 0, graph_parity = 0;
@@ -85,7 +93,7 @@ struct Timing {
     bool on = false;
     struct Rec {
         hipEvent_t a, b;
-        int kind;   // 0 FP64 pair phase, 1 monomer phase, 2 reduced-precision pair phase
+        int kind;   // 0 FP64 pair phase, 1 monomer phase, 2 reduced-precision pair phase, 3 singles pair phase
         double flops, vbytes;
     };
     std::vector<Rec> pending;

@@ -39,7 +39,7 @@ EXPORTS = [
     "mcpt_solve", "mcpt_energy", "mcpt_release", "mcpt_set_timing", "mcpt_timing_read",
     "mcpt_upload_batch", "mcpt_solve_batch", "mcpt_cluster_results",
     "mcpt_serve_config", "mcpt_submit", "mcpt_poll", "mcpt_wait", "mcpt_serve_stats",
-    "mcpt_autotune", "mcpt_tune_export", "mcpt_tune_import",
+    "mcpt_autotune", "mcpt_tune_export", "mcpt_tune_import", "mcpt_singles", "mcpt_singles_result",
 ]
 
 
@@ -76,7 +76,18 @@ class mcpt_timing(C.Structure):
         ("pair_ms", C.c_double), ("mono_ms", C.c_double), ("pair_launches", C.c_int64),
         ("mono_launches", C.c_int64), ("pair_flops", C.c_double), ("pair_v_bytes", C.c_double),
         ("lowp_ms", C.c_double), ("lowp_launches", C.c_int64), ("lowp_flops", C.c_double),
-        ("lowp_v_bytes", C.c_double),
+        ("lowp_v_bytes", C.c_double), ("singles_ms", C.c_double), ("singles_launches", C.c_int64),
+        ("singles_v_bytes", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class mcpt_singles_summary(C.Structure):
+    _fields_ = [
+        ("e_m1", C.c_double), ("e_m1_0", C.c_double), ("residual", C.c_double), ("seconds", C.c_double),
+        ("sweeps", C.c_int32), ("status", C.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -136,6 +147,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.mcpt_autotune.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(mcpt_tune_result)]
     lib.mcpt_tune_export.argtypes = [P, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
     lib.mcpt_tune_import.argtypes = [P, C.c_char_p]
+    lib.mcpt_singles.argtypes = [P, C.c_uint64, P, C.c_int32, C.POINTER(mcpt_options),
+                                 C.POINTER(mcpt_singles_summary)]
+    lib.mcpt_singles_result.argtypes = [P, C.c_uint64, P, P]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if name not in ("mcpt_destroy", "mcpt_last_error"):
@@ -304,6 +318,33 @@ class Context:
         if want_t:
             out["t"] = t
         return out
+
+    # ---- singles (mcpt_singles / mcpt_singles_result) ----
+    def singles(self, pid: int, w, raise_on_error: bool = True, tol=1e-10, max_sweeps=500, check_every=1,
+                device_ptr: int | None = None) -> dict:
+        """Singles of a resident problem from the source w (host array of
+        sum_X o_X v_X values, or device_ptr of such a device buffer)."""
+        o = make_options(tol=tol, max_sweeps=max_sweeps, check_every=check_every)
+        s = mcpt_singles_summary()
+        if device_ptr is not None:
+            st = lib().mcpt_singles(self.h, pid, device_ptr, MCPT_DEVICE, C.byref(o), C.byref(s))
+        else:
+            wa = np.ascontiguousarray(w, dtype=np.float64)
+            st = lib().mcpt_singles(self.h, pid, _ptr(wa), MCPT_HOST, C.byref(o), C.byref(s))
+        if raise_on_error:
+            _check(st)
+        d = s.as_dict()
+        d["return"] = st
+        return d
+
+    def singles_result(self, pid: int) -> dict:
+        if pid not in self._sizes:
+            raise MCPTError(MCPT_ERR_UNKNOWN_ID, f"unknown problem id {pid}")
+        n_occ, n_vir, _ = self._sizes[pid]
+        e = np.empty(len(n_occ))
+        t = np.empty(int(np.sum(n_occ.astype(np.int64) * n_vir)))
+        _check(lib().mcpt_singles_result(self.h, pid, _ptr(e), _ptr(t)))
+        return {"e_m1": e, "t1": t}
 
     def release(self, pid: int):
         _check(lib().mcpt_release(self.h, pid))

@@ -1,0 +1,215 @@
+"""Singles path (Eq. 57 pair coupling, Eq. 53 energy) on the GPU against the
+singles oracle: fixed sweep counts element by element on tiny ragged clusters,
+the converged cubes (the 1000-monomer cube at full size against the stored
+oracle results), batches against solo solves, device-resident sources, error
+paths, and independence from the doubles results.  Bar: 1e-10 relative, the
+FP64 tolerance of the doubles path; sweep counts equal."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mcpt_singles
+from synth import (concat_problems, cubic_sites, make_cluster_batch, make_lattice_problem, make_workload,
+                   singles_source)
+import paper_1409_2700_amd as mc
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = mc.Context(0)
+    yield c
+    c.close()
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)) if b.size else 0.0
+
+
+def flat_t(r):
+    return np.concatenate([t.ravel() for t in r.t]) if r.t else np.zeros(0)
+
+
+def ragged(n_sizes=((2, 3), (5, 27), (3, 17), (1, 1), (8, 56), (4, 9)), scale=1.0, cutoff=None, workload=910):
+    sites = cubic_sites(len(n_sizes), 1, 1)
+    return make_lattice_problem(sites, cutoff, sizes=list(n_sizes), workload=workload, coupling_scale=scale)
+
+
+@pytest.mark.parametrize("sweeps", [0, 1, 3])
+def test_fixed_sweeps_elementwise(ctx, sweeps):
+    p = ragged()
+    w = singles_source(p)
+    print(f"[gpu] singles fixed sweeps={sweeps} N={p.n_mono} P={p.n_pair}", flush=True)
+    ref = mcpt_singles.solve(p, w, tol=0.0, max_sweeps=sweeps)
+    pid = ctx.upload(p)
+    s = ctx.singles(pid, w, tol=0.0, max_sweeps=sweeps)
+    out = ctx.singles_result(pid)
+    ctx.release(pid)
+    assert s["status"] == mc.MCPT_OK and s["sweeps"] == sweeps
+    assert rel(out["t1"], flat_t(ref)) <= TOL
+    assert rel(out["e_m1"], ref.e_m1) <= TOL
+    assert abs(s["e_m1"] - ref.e_total) <= TOL * abs(ref.e_total)
+    assert abs(s["e_m1_0"] - ref.e_total0) <= TOL * abs(ref.e_total0)
+
+
+def test_wide_monomers_cross_column_passes(ctx):
+    """o v above 256 (several 256-column passes per row) and pairs of mixed widths."""
+    p = ragged(n_sizes=((6, 60), (2, 150), (5, 27), (3, 100)), scale=0.5, workload=911)
+    w = singles_source(p)
+    ref = mcpt_singles.solve(p, w, tol=TOL, max_sweeps=300)
+    pid = ctx.upload(p)
+    s = ctx.singles(pid, w, tol=TOL, max_sweeps=300)
+    out = ctx.singles_result(pid)
+    ctx.release(pid)
+    assert s["status"] == ref.status == 0 and s["sweeps"] == ref.sweeps
+    assert rel(out["e_m1"], ref.e_m1) <= TOL and rel(out["t1"], flat_t(ref)) <= TOL
+
+
+@pytest.mark.parametrize("name", ["hf-2x2x2", "hf-5x5x5-c2", "hf-10x10x10-c3"])
+def test_converged_cubes_match_stored_oracle(ctx, name):
+    with open(os.path.join(GOLDEN, f"singles-{name}.json")) as f:
+        g = json.load(f)
+    p = make_workload(name)
+    w = singles_source(p)
+    print(f"[gpu] singles converged {name} N={p.n_mono} P={p.n_pair}", flush=True)
+    pid = ctx.upload(p)
+    s = ctx.singles(pid, w, tol=g["tol"], max_sweeps=500)
+    out = ctx.singles_result(pid)
+    ctx.release(pid)
+    assert s["status"] == g["status"] == 0
+    assert s["sweeps"] == g["sweeps"]
+    assert abs(s["e_m1"] - g["e_m1_total"]) <= TOL * abs(g["e_m1_total"])
+    assert rel(out["e_m1"], g["e_m1"]) <= TOL
+    assert rel(out["t1"][g["t_index"]], g["t"]) <= TOL
+
+
+def test_batch_clusters_equal_solo(ctx):
+    probs = make_cluster_batch(4, min_mono=3, max_mono=20, first=700)
+    ws = [singles_source(p) for p in probs]
+    pid = ctx.upload_batch(probs)
+    s = ctx.singles(pid, np.concatenate(ws), tol=TOL)
+    out = ctx.singles_result(pid)
+    sl = ctx.cluster_slices(pid)
+    ctx.release(pid)
+    assert s["status"] == mc.MCPT_OK
+    worst = 0
+    total = 0.0
+    for q, (p, w) in enumerate(zip(probs, ws)):
+        ref = mcpt_singles.solve(p, w, tol=TOL)
+        worst = max(worst, ref.sweeps)
+        total += ref.e_total
+        assert rel(out["e_m1"][sl[q][0]], ref.e_m1) <= TOL, q
+    assert s["sweeps"] == worst
+    assert abs(s["e_m1"] - total) <= TOL * abs(total)
+
+
+def test_device_source_equals_host(ctx):
+    """w in device memory (allocated with the HIP runtime the library links)."""
+    import ctypes
+    hip = ctypes.CDLL(os.path.join("/opt/rocm/lib", "libamdhip64.so"))
+    p = make_workload("hf-2x2x2")
+    w = np.ascontiguousarray(singles_source(p))
+    pid = ctx.upload(p)
+    a = ctx.singles(pid, w, tol=TOL)
+    ea = ctx.singles_result(pid)
+    dptr = ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(dptr), ctypes.c_size_t(w.nbytes)) == 0
+    try:
+        assert hip.hipMemcpy(dptr, w.ctypes.data_as(ctypes.c_void_p), ctypes.c_size_t(w.nbytes), 1) == 0
+        b = ctx.singles(pid, None, tol=TOL, device_ptr=dptr.value)
+        eb = ctx.singles_result(pid)
+    finally:
+        hip.hipFree(dptr)
+        ctx.release(pid)
+    assert a["sweeps"] == b["sweeps"]
+    assert rel(eb["e_m1"], ea["e_m1"]) <= 1e-13 and rel(eb["t1"], ea["t1"]) <= 1e-13
+
+
+def test_doubles_results_untouched(ctx):
+    p = make_workload("hf-2x2x2")
+    pid = ctx.upload(p)
+    d0 = ctx.run(pid, tol=TOL)
+    e0 = ctx.energy(pid)
+    ctx.singles(pid, singles_source(p), tol=TOL)
+    e1 = ctx.energy(pid)
+    d1 = ctx.run(pid, tol=TOL)
+    ctx.release(pid)
+    for k in ("e_m2", "de_m2", "e_d2", "t"):
+        assert np.array_equal(e0[k], e1[k]), k
+    assert d1["sweeps"] == d0["sweeps"] and abs(d1["e_total"] - d0["e_total"]) <= 1e-12 * abs(d0["e_total"])
+
+
+def test_errors(ctx):
+    p = make_workload("hf-2x2x2")
+    w = singles_source(p)
+    pid = ctx.upload(p)
+    with pytest.raises(mc.MCPTError) as ei:
+        ctx.singles_result(pid)
+    assert ei.value.status == mc.MCPT_ERR_INVALID
+    bad = w.copy()
+    bad[5] = np.nan
+    with pytest.raises(mc.MCPTError) as ei:
+        ctx.singles(pid, bad)
+    assert ei.value.status == mc.MCPT_ERR_NONFINITE
+    import ctypes
+    from paper_1409_2700_amd import mcpt as binding
+    o = mc.make_options(tol=TOL, precision=mc.MCPT_BF16)
+    s = binding.mcpt_singles_summary()
+    wa = np.ascontiguousarray(w)
+    st = mc.lib().mcpt_singles(ctx.h, pid, wa.ctypes.data, mc.MCPT_HOST, ctypes.byref(o), ctypes.byref(s))
+    assert st == mc.MCPT_ERR_INVALID
+    with pytest.raises(mc.MCPTError) as ei:
+        ctx.singles(pid + 10**6, w)
+    assert ei.value.status == mc.MCPT_ERR_UNKNOWN_ID
+    r = ctx.singles(pid, w, tol=TOL, max_sweeps=3, raise_on_error=False)
+    assert r["return"] == mc.MCPT_ERR_NOT_CONVERGED and r["sweeps"] == 3
+    ctx.release(pid)
+
+
+def test_divergence_detected(ctx):
+    sites = cubic_sites(4, 1, 1)
+    p = make_lattice_problem(sites, None, sizes=[(2, 3), (2, 4), (3, 2), (1, 3)], workload=900,
+                             coupling_scale=400.0)
+    w = singles_source(p)
+    ref = mcpt_singles.solve(p, w, tol=TOL, max_sweeps=200)
+    pid = ctx.upload(p)
+    r = ctx.singles(pid, w, tol=TOL, max_sweeps=200, raise_on_error=False)
+    ctx.release(pid)
+    assert ref.status == mc.MCPT_ERR_DIVERGED
+    assert r["return"] == mc.MCPT_ERR_DIVERGED and r["sweeps"] == ref.sweeps
+
+
+def test_relabelled_and_reversed_pairs(ctx):
+    p = ragged(scale=1.0)
+    w = singles_source(p)
+    perm = [3, 0, 5, 1, 4, 2]
+    q = p.relabel(perm, np.arange(p.n_pair) % 3 == 0)
+    off = np.concatenate([[0], np.cumsum([p.n_ov(x) for x in range(p.n_mono)])])
+    wq = np.concatenate([w[off[x]:off[x + 1]] for x in perm])
+    pa, pb = ctx.upload(p), ctx.upload(q)
+    a = ctx.singles(pa, w, tol=TOL)
+    b = ctx.singles(pb, wq, tol=TOL)
+    ea, eb = ctx.singles_result(pa)["e_m1"], ctx.singles_result(pb)["e_m1"]
+    ctx.release(pa)
+    ctx.release(pb)
+    assert a["sweeps"] == b["sweeps"]
+    assert rel(eb, ea[perm]) <= TOL
+
+
+def test_no_pairs_closed_form(ctx):
+    p = ragged().subset_pairs(np.zeros(15, dtype=bool))
+    w = singles_source(p)
+    ref = mcpt_singles.solve(p, w, tol=TOL)
+    pid = ctx.upload(p)
+    s = ctx.singles(pid, w, tol=TOL)
+    out = ctx.singles_result(pid)
+    ctx.release(pid)
+    assert s["sweeps"] == ref.sweeps == 1
+    assert rel(out["e_m1"], ref.e_m1) <= TOL
