@@ -317,7 +317,7 @@ def batched(n_clusters, tol):
     return out
 
 
-def pmc_pass(workload: str, precision: int = 0, sweeps: int = 2):
+def pmc_pass(workload: str, precision: int = 0, sweeps: int = 2, singles: bool = False):
     """Counter pass for rocprofv3 --pmc: one device copy of a known size
     (the calibration kernel), then `sweeps` fixed sweeps of the resident
     workload in the given precision (no polish) and the final FP64 energy
@@ -336,6 +336,11 @@ def pmc_pass(workload: str, precision: int = 0, sweeps: int = 2):
     del src, dst
     with mc.Context(0) as ctx:
         pid = ctx.upload(prob)
+        if singles:
+            from synth import singles_source
+            s = ctx.singles(pid, singles_source(prob), tol=0.0, max_sweeps=sweeps)
+            log(f"[pmc] {workload}: {s['sweeps']} fixed singles sweeps, E_M1={s['e_m1']:.10f}")
+            return
         s = ctx.run(pid, tol=0.0, max_sweeps=sweeps, precision=precision, polish=0)
         log(f"[pmc] {workload}: {s['sweeps']} fixed sweeps (precision {precision}) + final pass, "
             f"E={s['e_total']:.10f}")
@@ -425,6 +430,7 @@ def main():
     ap.add_argument("--pmc-pass", action="store_true",
                     help="only launch a calibration copy and two fixed sweeps (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-precision", type=int, default=0, help="0 FP64, 1 FP32, 2 BF16 sweeps in --pmc-pass")
+    ap.add_argument("--pmc-singles", action="store_true", help="--pmc-pass runs two singles sweeps instead")
     ap.add_argument("--singles-steps", type=int, default=3, help="timed singles solves (0: skip)")
     ap.add_argument("--batched", type=int, default=0,
                     help="also time the batching form on this many uneven clusters (64 = full set)")
@@ -436,7 +442,7 @@ def main():
         sys.exit(2)
 
     if args.pmc_pass:
-        pmc_pass(args.workload, args.pmc_precision)
+        pmc_pass(args.workload, args.pmc_precision, singles=args.pmc_singles)
         return
     import paper_1409_2700_amd as mc
     from synth import make_workload, DEFAULT_COUPLING_SCALE

@@ -238,8 +238,8 @@ typedef struct {
  * finite), MCPT_ERR_ADMISSION (the singles buffers - three vectors of
  * sum_X n_X doubles padded as the monomer matrices' rows, three of N doubles
  * and a 32 KiB residual history per cluster, made on the first call and kept
- * with the problem - exceed the budget), MCPT_ERR_INVALID (options, a monomer
- * with o_X v_X above 16384), MCPT_ERR_UNKNOWN_ID, MCPT_ERR_DEVICE. */
+ * with the problem - exceed the budget), MCPT_ERR_INVALID (options),
+ * MCPT_ERR_UNKNOWN_ID, MCPT_ERR_DEVICE. */
 mcpt_status mcpt_singles(mcpt_ctx *ctx, uint64_t id, const double *w, int32_t memory, const mcpt_options *opts,
                          mcpt_singles_summary *out);
 

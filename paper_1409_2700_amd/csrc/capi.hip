@@ -16,6 +16,7 @@
 #include "../../include/mcpt.h"
 #include "mcpt_internal.hpp"
 #include "runtime.hpp"
+#include "singles.hpp"
 
 namespace mcpt {
 
@@ -920,7 +921,6 @@ mcpt_status singles(mcpt_ctx* c, Exec& x, Resident* R, const double* w, int32_t 
     if (o->precision != MCPT_FP64) return fail(MCPT_ERR_INVALID, "singles run in FP64 only");
     if (o->deterministic) return fail(MCPT_ERR_INVALID, "singles have no deterministic mode");
     if (memory != MCPT_HOST && memory != MCPT_DEVICE) return fail(MCPT_ERR_INVALID, "memory must be MCPT_HOST or MCPT_DEVICE");
-    if (R->max_n > 16384) return fail(MCPT_ERR_INVALID, "a monomer has o*v above 16384 (singles row sums in LDS)");
     int64_t nw = 0;
     for (const MonoDesc& m : R->monos) nw += m.n;
     if (!w && nw > 0) return fail(MCPT_ERR_INVALID, "w is NULL");
@@ -964,7 +964,7 @@ mcpt_status singles(mcpt_ctx* c, Exec& x, Resident* R, const double* w, int32_t 
     launch_singles_mono(1, R->d_monos, R->n_mono, R->d_dif, R->d_w1, R->d_u1, R->d_t1, R->d_em1, R->d_em1_0,
                         R->d_res1, nullptr, R->d_cl1, s);
     HIP_TRY(hipGetLastError());
-    const int grid = singles_pair_grid(c->n_cu, R->max_n);
+    const int grid = singles_pair_grid(c->n_cu);
     const double vb = (double)R->v_elems * sizeof(double);
     const int every = o->check_every > 0 ? o->check_every : 1;
     int issued = 0;
@@ -973,8 +973,8 @@ mcpt_status singles(mcpt_ctx* c, Exec& x, Resident* R, const double* w, int32_t 
         for (int k = 0; k < batch; ++k) {
             hipEvent_t a = nullptr;
             record_begin(x, &a);
-            launch_singles_pair(R->d_pairs, R->n_pair, R->d_monos, R->d_V, R->d_t1, R->d_u1, R->max_n, grid, x.d_ctrl,
-                                R->d_cl1, s);
+            launch_singles_pair(R->d_pairs, R->n_pair, R->d_monos, R->d_V, R->d_t1, R->d_u1, grid, x.d_ctrl, R->d_cl1,
+                                s);
             record_end(x, a, 3, 0.0, vb);
             launch_singles_mono(0, R->d_monos, R->n_mono, R->d_dif, R->d_w1, R->d_u1, R->d_t1, R->d_em1, R->d_em1_0,
                                 R->d_res1, x.d_ctrl, R->d_cl1, s);

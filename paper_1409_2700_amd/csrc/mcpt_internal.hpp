@@ -155,19 +155,4 @@ void launch_pair_lowp(int precision, int variant, int64_t lds_bytes, PartOut po,
                       int grid, double* ed2, int source, int couple, const Ctrl* ctrl, const ClState* cl,
                       hipStream_t s);   // Gf non-null: G contributions in FP32 (G unused)
 
-// ---- singles sweep (singles.hip) ----
-int64_t singles_lds_bytes(int max_n);
-int singles_pair_grid(int n_cu, int max_n);
-void launch_singles_pair(const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos, const double* V,
-                         const double* t, double* u, int max_n, int grid, const Ctrl* ctrl, const ClState* cl,
-                         hipStream_t s);
-// init = 1: t = w / d; 0: t = (w + u) / d with the residual, u cleared
-void launch_singles_mono(int init, const MonoDesc* monos, int n_mono, const double* dif, const double* w, double* u,
-                         double* t, double* em1, double* em1_0, double* res, const Ctrl* ctrl, const ClState* cl,
-                         hipStream_t s);
-void launch_singles_clusters(int n_cl, const int64_t* cl_mono, const double* em1, const double* em1_0, ClState* cl,
-                             hipStream_t s);
-void launch_singles_scatter(const MonoDesc* monos, int n_mono, const int64_t* woff, const double* compact,
-                            double* padded, hipStream_t s);
-
 }  // namespace mcpt

@@ -11,35 +11,31 @@
 // doubles use; each stored pair feeds both of its monomers, u_X += V_XY t_Y and
 // u_Y += V_XY^T t_X.  The pair phase is two matrix-vector products per block:
 // 4 flops per 8-byte element, so it is bound by streaming V from HBM once per
-// sweep (6.1 GB at 1000 monomers) and the kernel is built for that: every V
-// element is read exactly once, by coalesced 8-byte loads (a wave reads 64
-// consecutive elements of one row), with four rows times up to four 64-column
-// chunks in flight per wave and several workgroups per CU.  A wave owns rows
-// r = wave (mod 4): its lanes sum V[r][c] t_Y[c] over their columns and a wave
-// reduction gives the row's share of u_X; the same loads add V[r][c] t_X[r]
-// into per-lane column sums, combined over the waves in LDS, for u_Y.  Partial
-// sums reach u by FP64 atomics, one per row and column per pair.
+// sweep (6.1 GB at 1000 monomers) and the kernel is built for that.  Each wave
+// owns a pair (no barriers, no LDS): its four 16-lane groups read four rows at
+// a time, a lane taking columns l, l + 16, ... (each group reads 128
+// consecutive bytes of its row per load: four row segments per load
+// instruction), with four such row quadruples - thirty-six loads of a 144-column
+// pass - in flight per wave.  A row's sum V[r][:] t_Y is finished by a
+// 16-lane shuffle reduction (four steps for four rows at once); the same loads
+// add V[r][c] t_X[r] into per-lane column sums, combined over the four groups
+// once per pair.  Sums reach u by FP64 atomics: one per row and column per pair
+// (and per 144-column pass for wider monomers).
 //
 // Vectors t, u and w use the padded per-monomer layout of the energy
 // differences (dif_off, element (i,a) = i v + a), so the denominator of element
 // e is 1 / dif[e].
-#include "mcpt_internal.hpp"
+#include "singles.hpp"
 
 namespace mcpt {
 
 namespace {
 
-constexpr int kSThreads = 256;               // four waves
+constexpr int kSThreads = 256;               // four waves, each on its own pair
 constexpr int kSWaves = kSThreads / 64;
-constexpr int kColChunks = 4;                // 64-column chunks per lane per pass: 256 columns
-constexpr int kRowUnroll = 4;                // rows of one wave in flight together
+constexpr int kSlots = 9;                    // 16-column chunks per lane per pass: 144 columns
+constexpr int kRowIters = 4;                 // four-row groups of one wave in flight together
 constexpr int kMonoThreadsS = 256;
-static_assert(kColChunks * 64 == kSThreads, "one column-sum slot per thread");
-
-__device__ inline double wave_sum(double x) {
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
-}
 
 __device__ inline double max_nan(double a, double b) { return (a != a || b != b) ? NAN : (a > b ? a : b); }
 
@@ -57,73 +53,81 @@ __device__ double block_reduce(double x, double* sh, bool is_max) {
     return r;
 }
 
-// u_X += V_XY t_Y and u_Y += V_XY^T t_X for every stored pair of a live cluster.
-// Dynamic LDS: max_n doubles for the row sums of the current pair.
+// u_X += V_XY t_Y and u_Y += V_XY^T t_X for every stored pair of a live cluster,
+// one pair per wave.
 __global__ __launch_bounds__(kSThreads) void singles_pair_kernel(
     const PairDesc* __restrict__ pairs, int64_t n_pair, const MonoDesc* __restrict__ monos,
     const double* __restrict__ V, const double* __restrict__ t, double* __restrict__ u,
     const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
     if (ctrl && ctrl->done) return;
-    extern __shared__ double s_rows[];
-    __shared__ double s_cols[kColChunks * 64];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int64_t pi = blockIdx.x; pi < n_pair; pi += gridDim.x) {
+    // the wave index is uniform over the wave: with it in a scalar register the pair and
+    // monomer descriptors are scalar loads and every V address is a scalar base + lane offset
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, l = lane & 15;
+    const int64_t stride = (int64_t)gridDim.x * kSWaves;
+    for (int64_t pi = (int64_t)blockIdx.x * kSWaves + wave; pi < n_pair; pi += stride) {
         const PairDesc pd = pairs[pi];
-        if (cl && cl[pd.cluster].done) continue;   // uniform over the workgroup
+        if (cl && cl[pd.cluster].done) continue;   // uniform over the wave
         const MonoDesc dx = monos[pd.x], dy = monos[pd.y];
         const int nX = dx.n, nY = dy.n;
         const double* v = V + pd.v_off;
         const double* tX = t + dx.dif_off;
         const double* tY = t + dy.dif_off;
-        for (int r = threadIdx.x; r < nX; r += kSThreads) s_rows[r] = 0.0;
-        s_cols[threadIdx.x] = 0.0;   // kColChunks * 64 == kSThreads
-        __syncthreads();
-        for (int c0 = 0; c0 < nY; c0 += 64 * kColChunks) {
-            double ty[kColChunks], cy[kColChunks];
+        double* uX = u + dx.dif_off;
+        double* uY = u + dy.dif_off;
+        for (int c0 = 0; c0 < nY; c0 += 16 * kSlots) {
+            double ty[kSlots], cy[kSlots];
 #pragma unroll
-            for (int k = 0; k < kColChunks; ++k) {
-                const int c = c0 + 64 * k + lane;
+            for (int k = 0; k < kSlots; ++k) {
+                const int c = c0 + 16 * k + l;
                 ty[k] = c < nY ? tY[c] : 0.0;
                 cy[k] = 0.0;
             }
-            for (int r0 = wave; r0 < nX; r0 += kSWaves * kRowUnroll) {
-                double vv[kRowUnroll][kColChunks], tx[kRowUnroll];
+            for (int r0 = 0; r0 < nX; r0 += 4 * kRowIters) {
+                double vv[kRowIters][kSlots], tx[kRowIters];
 #pragma unroll
-                for (int j = 0; j < kRowUnroll; ++j) {
-                    const int r = r0 + j * kSWaves;
-                    tx[j] = r < nX ? tX[r] : 0.0;
+                for (int i = 0; i < kRowIters; ++i) {
+                    const int r = r0 + 4 * i + g;
+                    tx[i] = r < nX ? tX[r] : 0.0;
 #pragma unroll
-                    for (int k = 0; k < kColChunks; ++k) {
-                        const int c = c0 + 64 * k + lane;
-                        vv[j][k] = (r < nX && c < nY) ? v[(int64_t)r * nY + c] : 0.0;
+                    for (int k = 0; k < kSlots; ++k) {
+                        const int c = c0 + 16 * k + l;
+                        // 32-bit element offset (a block holds far fewer than 2^29 values): scalar base + lane offset
+                        vv[i][k] = (r < nX && c < nY) ? __builtin_nontemporal_load(v + (unsigned)(r * nY + c)) : 0.0;
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < kRowUnroll; ++j) {
+                for (int i = 0; i < kRowIters; ++i) {
                     double p = 0.0;
 #pragma unroll
-                    for (int k = 0; k < kColChunks; ++k) {
-                        p = fma(vv[j][k], ty[k], p);
-                        cy[k] = fma(vv[j][k], tx[j], cy[k]);
+                    for (int k = 0; k < kSlots; ++k) {
+                        p = fma(vv[i][k], ty[k], p);
+                        cy[k] = fma(vv[i][k], tx[i], cy[k]);
                     }
-                    p = wave_sum(p);
-                    const int r = r0 + j * kSWaves;
-                    if (lane == 0 && r < nX) s_rows[r] += p;   // row r belongs to this wave only
+                    // sum over the 16 lanes of the group (xor masks below 16 stay inside it)
+                    p += __shfl_xor(p, 8, 64);
+                    p += __shfl_xor(p, 4, 64);
+                    p += __shfl_xor(p, 2, 64);
+                    p += __shfl_xor(p, 1, 64);
+                    const int r = r0 + 4 * i + g;
+                    if (l == 0 && r < nX) unsafeAtomicAdd(uX + r, p);
                 }
             }
+            // column sums over the four row groups
 #pragma unroll
-            for (int k = 0; k < kColChunks; ++k)
-                if (c0 + 64 * k + lane < nY) atomicAdd(&s_cols[64 * k + lane], cy[k]);
-            __syncthreads();
-            {
-                const int c = c0 + threadIdx.x;
-                if (c < nY) unsafeAtomicAdd(u + dy.dif_off + c, s_cols[threadIdx.x]);
-                s_cols[threadIdx.x] = 0.0;
+            for (int k = 0; k < kSlots; ++k) {
+                cy[k] += __shfl_xor(cy[k], 16, 64);
+                cy[k] += __shfl_xor(cy[k], 32, 64);
             }
-            __syncthreads();
+            if (g == 0) {
+#pragma unroll
+                for (int k = 0; k < kSlots; ++k) {
+                    const int c = c0 + 16 * k + l;
+                    if (c < nY) unsafeAtomicAdd(uY + c, cy[k]);
+                }
+            }
         }
-        for (int r = threadIdx.x; r < nX; r += kSThreads) unsafeAtomicAdd(u + dx.dif_off + r, s_rows[r]);
-        __syncthreads();   // s_rows is reset for the next pair
     }
 }
 
@@ -199,24 +203,18 @@ __global__ __launch_bounds__(kMonoThreadsS) void singles_scatter_kernel(const Mo
 
 }  // namespace
 
-int64_t singles_lds_bytes(int max_n) { return (int64_t)max_n * (int64_t)sizeof(double); }
-
-int singles_pair_grid(int n_cu, int max_n) {
+int singles_pair_grid(int n_cu) {
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, singles_pair_kernel, kSThreads,
-                                                     (size_t)singles_lds_bytes(max_n)) != hipSuccess ||
-        per < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, singles_pair_kernel, kSThreads, 0) != hipSuccess || per < 1)
         per = 1;
-    per = per > 8 ? 8 : per;
     return n_cu * per;
 }
 
 void launch_singles_pair(const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos, const double* V,
-                         const double* t, double* u, int max_n, int grid, const Ctrl* ctrl, const ClState* cl,
-                         hipStream_t s) {
+                         const double* t, double* u, int grid, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
     if (n_pair <= 0) return;
-    hipLaunchKernelGGL(singles_pair_kernel, dim3(grid), dim3(kSThreads), (size_t)singles_lds_bytes(max_n), s, pairs,
-                       n_pair, monos, V, t, u, ctrl, cl);
+    hipLaunchKernelGGL(singles_pair_kernel, dim3(grid), dim3(kSThreads), 0, s, pairs, n_pair, monos, V, t, u, ctrl,
+                       cl);
 }
 
 void launch_singles_mono(int init, const MonoDesc* monos, int n_mono, const double* dif, const double* w, double* u,
