@@ -44,6 +44,12 @@ KIND_CLUSTER = 2
 KIND_STREAM = 3
 KIND_SINGLES = 4
 SIGMA_W = 0.05
+KIND_LCCD = 5
+SIGMA_LCCD = 0.01
+# the full monomer equation's ring terms contract K with the amplitudes; at the
+# stated sigma 0.05 of K the sweep map of random blocks has a dominant eigenvalue
+# > 1, so workloads with the intramonomer terms draw K at 0.2 x 0.05 = 0.01
+LCCD_K_SCALE = 0.2
 
 
 @dataclasses.dataclass
@@ -230,13 +236,14 @@ def make_lattice_problem(sites: np.ndarray, cutoff_spacings: float | None, *, o:
                          v: int = 27, workload: int = 0, cluster: int = 0,
                          coupling_scale: float = DEFAULT_COUPLING_SCALE,
                          mixed_sizes: bool = False, displacement=None,
-                         dtype_v=np.float64, sizes=None) -> Problem:
+                         dtype_v=np.float64, sizes=None, k_scale: float = 1.0) -> Problem:
     """Build a problem on the given integer lattice sites.
 
     displacement: None or (monomer index, axis 0..2, signed shift in Angstrom);
     the displaced monomer keeps its energies and intra block, its pair blocks
     are rescaled by (R0 / R)^3 and the pair list stays that of the undisplaced
-    lattice (fixed topology).  sizes: optional per-monomer (o, v) list."""
+    lattice (fixed topology).  sizes: optional per-monomer (o, v) list.
+    k_scale multiplies every intra block (the same seeded draw, rescaled)."""
     sites = np.asarray(sites, dtype=np.int64)
     n = len(sites)
     n_occ = np.empty(n, dtype=np.int32)
@@ -247,7 +254,7 @@ def make_lattice_problem(sites: np.ndarray, cutoff_spacings: float | None, *, o:
         ox, vx, e, k = _monomer_draw(workload, cluster, sites[x], so, sv, mixed_sizes)
         n_occ[x], n_vir[x] = ox, vx
         eps_parts.append(e)
-        k_parts.append(k.ravel())
+        k_parts.append(k.ravel() * k_scale if k_scale != 1.0 else k.ravel())
     pairs = pair_list(sites, cutoff_spacings)
     pos = sites.astype(np.float64) * SPACING_A
     if displacement is not None:
@@ -274,7 +281,7 @@ def make_lattice_problem(sites: np.ndarray, cutoff_spacings: float | None, *, o:
     k = np.concatenate(k_parts) if k_parts else np.zeros(0)
     return Problem(n_occ, n_vir, eps, k, pairs, vflat, sites,
                    dict(workload=workload, cluster=cluster, cutoff=cutoff_spacings,
-                        coupling_scale=coupling_scale, displacement=displacement))
+                        coupling_scale=coupling_scale, displacement=displacement, k_scale=k_scale))
 
 
 # named workloads: the HF-crystal-shaped cubes (o=5, v=27, 32 orbitals/monomer)
@@ -393,3 +400,105 @@ def singles_source(prob: Problem, *, workload: int | None = None, cluster: int |
         rng = _rng(wl, cl, KIND_SINGLES, *key)
         parts.append(rng.normal(0.0, sigma, size=prob.n_ov(x)))
     return np.concatenate(parts) if parts else np.zeros(0)
+
+
+# ---------------------------------------------------------------------------
+# intramonomer integral classes of the full monomer equation (Eq. 58)
+# ---------------------------------------------------------------------------
+_GROUP8 = [(0, 1, 2, 3), (1, 0, 2, 3), (0, 1, 3, 2), (1, 0, 3, 2),
+           (2, 3, 0, 1), (3, 2, 0, 1), (2, 3, 1, 0), (3, 2, 1, 0)]
+_GROUP4 = [(0, 1, 2, 3), (1, 0, 2, 3), (0, 1, 3, 2), (1, 0, 3, 2)]
+
+
+def _symmetrised(rng, shape, group, sigma):
+    """Normal draws averaged over a permutation group of the Mulliken indices
+    (pr|qs), rescaled so that an element with distinct indices has standard
+    deviation sigma."""
+    g = rng.standard_normal(size=shape)
+    s = np.zeros(shape)
+    for perm in group:
+        s += g.transpose(perm)
+    return s * (sigma / math.sqrt(len(group)))
+
+
+@dataclasses.dataclass
+class LccdIntegrals:
+    """Per-monomer integral classes of the intramonomer terms of Eq. 58, flat and
+    concatenated over monomers (the layout the C ABI takes):
+
+    w: W_X[a][b][c][d] = <ab|cd>, row-major (v, v, v, v)
+    q: Q_X[i][j][k][l] = <ij|kl>, row-major (o, o, o, o)
+    j: J_X[i][j][a][b] = <ia|jb> = (ij|ab), row-major (o, o, v, v)
+    """
+    n_occ: np.ndarray
+    n_vir: np.ndarray
+    w: np.ndarray
+    q: np.ndarray
+    j: np.ndarray
+
+    def __post_init__(self):
+        o = np.asarray(self.n_occ, dtype=np.int64)
+        v = np.asarray(self.n_vir, dtype=np.int64)
+        self.w_off = np.concatenate([[0], np.cumsum(v ** 4)])
+        self.q_off = np.concatenate([[0], np.cumsum(o ** 4)])
+        self.j_off = np.concatenate([[0], np.cumsum(o * o * v * v)])
+
+    def w_of(self, x: int) -> np.ndarray:
+        v = int(self.n_vir[x])
+        return self.w[self.w_off[x]:self.w_off[x + 1]].reshape(v, v, v, v)
+
+    def q_of(self, x: int) -> np.ndarray:
+        o = int(self.n_occ[x])
+        return self.q[self.q_off[x]:self.q_off[x + 1]].reshape(o, o, o, o)
+
+    def j_of(self, x: int) -> np.ndarray:
+        o, v = int(self.n_occ[x]), int(self.n_vir[x])
+        return self.j[self.j_off[x]:self.j_off[x + 1]].reshape(o, o, v, v)
+
+    def nbytes(self) -> int:
+        return int(self.w.nbytes + self.q.nbytes + self.j.nbytes)
+
+    def subset(self, monomers) -> "LccdIntegrals":
+        ms = list(monomers)
+        cat = lambda arr, off: np.concatenate([arr[off[x]:off[x + 1]] for x in ms]) if ms else np.zeros(0)
+        return LccdIntegrals(np.asarray(self.n_occ)[ms], np.asarray(self.n_vir)[ms],
+                             cat(self.w, self.w_off), cat(self.q, self.q_off), cat(self.j, self.j_off))
+
+
+def concat_lccd(parts) -> LccdIntegrals:
+    return LccdIntegrals(np.concatenate([p.n_occ for p in parts]), np.concatenate([p.n_vir for p in parts]),
+                         np.concatenate([p.w for p in parts]), np.concatenate([p.q for p in parts]),
+                         np.concatenate([p.j for p in parts]))
+
+
+def lccd_integrals(prob: Problem, *, workload: int | None = None, cluster: int | None = None,
+                   sigma: float = SIGMA_LCCD) -> LccdIntegrals:
+    """Seeded stand-ins for the intramonomer integral classes (vv|vv), (oo|oo)
+    and (oo|vv) of each monomer, drawn N(0, sigma^2) and symmetrised as real
+    orbitals require within each class ((pr|qs) = (rp|qs) = (pr|sq) = (qs|pr)
+    for (vv|vv) and (oo|oo); (ij|ab) = (ji|ab) = (ij|ba) for (oo|vv)).  Keyed by
+    the workload, the cluster and the monomer's lattice site (its index when the
+    problem has no sites)."""
+    wl = int(prob.meta.get("workload", 0) if workload is None else workload)
+    cl = int(prob.meta.get("cluster", 0) if cluster is None else cluster)
+    ws, qs, js = [], [], []
+    for x in range(prob.n_mono):
+        o, v = int(prob.n_occ[x]), int(prob.n_vir[x])
+        key = prob.sites[x] if prob.sites is not None else (x, 0, 0)
+        rng = _rng(wl, cl, KIND_LCCD, *key)
+        g_vv = _symmetrised(rng, (v, v, v, v), _GROUP8, sigma)     # (ac|bd)
+        g_oo = _symmetrised(rng, (o, o, o, o), _GROUP8, sigma)     # (ik|jl)
+        g_ov = _symmetrised(rng, (o, o, v, v), _GROUP4, sigma)     # (ij|ab)
+        ws.append(np.ascontiguousarray(g_vv.transpose(0, 2, 1, 3)).ravel())   # <ab|cd> = (ac|bd)
+        qs.append(np.ascontiguousarray(g_oo.transpose(0, 2, 1, 3)).ravel())   # <ij|kl> = (ik|jl)
+        js.append(g_ov.ravel())                                               # <ia|jb> = (ij|ab)
+    cat = lambda parts: np.concatenate(parts) if parts else np.zeros(0)
+    return LccdIntegrals(prob.n_occ.copy(), prob.n_vir.copy(), cat(ws), cat(qs), cat(js))
+
+
+def make_lccd_workload(name: str, coupling_scale: float = DEFAULT_COUPLING_SCALE, **kw):
+    """A named cube with the intramonomer integral classes of the full monomer
+    equation: K drawn at LCCD_K_SCALE x its sigma and (vv|vv), (oo|oo), (oo|vv)
+    at SIGMA_LCCD.  Returns (problem, integrals)."""
+    p = make_workload(name, coupling_scale=coupling_scale, k_scale=LCCD_K_SCALE, **kw)
+    return p, lccd_integrals(p)
