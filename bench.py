@@ -411,6 +411,79 @@ def singles_cpu(prob, sweeps: int, sample_pairs: int = 4096) -> dict:
                       f"{prob.n_pair} pairs x {sweeps} sweeps ({solve_s:.0f} s per solve)"}
 
 
+def lccd_mode(ctx, prob, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: bool = True):
+    """Full monomer equation (Eq. 58 with its intramonomer terms; step 5 then
+    step 6) on the same crystal with K and the (vv|vv), (oo|oo), (oo|vv)
+    classes at the workload's scale: solves/s, the ladder kernel against the
+    HBM roofline (algorithmic bytes = the packed <ab|cd> stream, 8 v^2 x
+    round16(v^2) per monomer), the error against the stored oracle result, and
+    the oracle's intramonomer terms timed on a sample of monomers."""
+    import numpy as np
+    from synth import LCCD_K_SCALE, Problem, lccd_integrals
+    t0 = time.time()
+    pl = Problem(prob.n_occ, prob.n_vir, prob.eps, prob.k * LCCD_K_SCALE, prob.pairs, prob.v, prob.sites,
+                 dict(prob.meta, k_scale=LCCD_K_SCALE))
+    ints = lccd_integrals(pl)
+    log(f"[lccd] integrals {ints.nbytes() / 1e9:.2f} GB made in {time.time() - t0:.1f}s")
+    pid = ctx.upload(pl)
+    t0 = time.time()
+    ctx.lccd_attach(pid, ints)
+    attach_s = time.time() - t0
+    gpath = os.path.join(ROOT, "tests", "golden", f"lccd-{prob.meta.get('name', '')}.json")
+    golden = json.load(open(gpath)) if os.path.exists(gpath) else None
+    opts = dict(tol=tol, max_sweeps=400, check_every=4)
+    for _ in range(warmup):
+        ctx.run(pid, **opts)
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s = ctx.run(pid, **opts)
+    dt = (time.perf_counter() - t0) / max(steps, 1)
+    tm = ctx.timing()
+    ctx.set_timing(False)
+    kl = max(tm["lccd_launches"], 1)
+    ms = tm["lccd_ladder_ms"] / kl
+    wb = tm["lccd_w_bytes"] / kl
+    fl = tm["lccd_ladder_flops"] / kl
+    out = {
+        "solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "iso_sweeps": s["iso_sweeps"], "sweeps": s["sweeps"],
+        "e_total": s["e_total"], "e_lccd_total": s["e_mono0"], "attach_s": attach_s,
+        "workload": f"{prob.meta.get('name', '')} with K x {LCCD_K_SCALE} and intramonomer classes at sigma 0.01",
+        "ladder_kernel": {"kernel": "lccd_ladder_kernel", "bound": "hbm", "avg_launch_ms": ms,
+                          "algorithmic_bytes_per_launch": wb, "achieved_GBps": wb / (ms * 1e-3) / 1e9,
+                          "peak_GBps": HBM_PEAK_GBS, "frac": wb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "ladder_TFLOPs": fl / (ms * 1e-3) / 1e12, "launches": tm["lccd_launches"]},
+        "ring_kernel_avg_ms": tm["lccd_ring_ms"] / kl,
+        "pair_kernel_avg_ms": tm["pair_ms"] / max(tm["pair_launches"], 1),
+        "monomer_avg_ms": tm["mono_ms"] / max(tm["mono_launches"], 1),
+    }
+    if golden is not None:
+        e = ctx.energy(pid, want_t=False)
+        out["oracle_reference"] = {"e_total": golden["e_total"], "iso_sweeps": golden["iso_sweeps"],
+                                   "sweeps": golden["sweeps"], "file": os.path.relpath(gpath, ROOT)}
+        out["relative_error_e_total"] = abs(s["e_total"] - golden["e_total"]) / abs(golden["e_total"])
+        out["max_abs_error_e_m2_Eh"] = float(np.max(np.abs(e["e_m2"] - np.asarray(golden["e_m2"]))))
+        out["max_abs_error_e_lccd_Eh"] = float(np.max(np.abs(e["e_m2"] - e["de_m2"] - np.asarray(golden["e_lccd"]))))
+    ctx.release(pid)
+    log(f"[lccd] {s['iso_sweeps']} + {s['sweeps']} sweeps, {dt * 1e3:.1f} ms per solve, ladder {ms:.3f} ms = "
+        f"{wb / (ms * 1e-3) / 1e9:.0f} GB/s, ring {out['ring_kernel_avg_ms']:.3f} ms")
+    if with_cpu:
+        from oracle import mcpt_lccd
+        orc = mcpt_lccd.LccdOracle(pl.subset_pairs(np.zeros(pl.n_pair, dtype=bool)), ints)
+        T = orc.first_order()
+        k, t0 = 0, time.perf_counter()
+        while k < pl.n_mono and time.perf_counter() - t0 < cpu_budget:
+            mcpt_lccd.intramonomer_terms(orc.v[k], T[k])
+            k += 1
+        per = (time.perf_counter() - t0) / max(k, 1)
+        sweeps = (golden["iso_sweeps"] + golden["sweeps"]) if golden else s["iso_sweeps"] + s["sweeps"]
+        out["cpu_oracle_intramonomer"] = {
+            "seconds_per_solve": per * pl.n_mono * sweeps, "unit": "s", "kind": "oracle",
+            "sample": f"intramonomer terms of {k} monomers ({per * 1e3:.1f} ms each), scaled to "
+                      f"{pl.n_mono} monomers x {sweeps} sweeps (the pair part is cpu_baseline's)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -432,6 +505,8 @@ def main():
     ap.add_argument("--pmc-precision", type=int, default=0, help="0 FP64, 1 FP32, 2 BF16 sweeps in --pmc-pass")
     ap.add_argument("--pmc-singles", action="store_true", help="--pmc-pass runs two singles sweeps instead")
     ap.add_argument("--singles-steps", type=int, default=3, help="timed singles solves (0: skip)")
+    ap.add_argument("--lccd-steps", type=int, default=2,
+                    help="timed solves of the full monomer equation (0: skip)")
     ap.add_argument("--batched", type=int, default=0,
                     help="also time the batching form on this many uneven clusters (64 = full set)")
     args = ap.parse_args()
@@ -471,6 +546,9 @@ def main():
     if args.singles_steps > 0:
         singles = singles_mode(ctx, pid, prob, args.singles_steps, 1, args.tol)
     ctx.release(pid)
+    lccd = None
+    if args.lccd_steps > 0:
+        lccd = lccd_mode(ctx, prob, args.lccd_steps, 1, args.tol, with_cpu=not args.no_cpu_baseline)
     ctx.close()
     served = None
     if args.serve_requests > 0:
@@ -523,6 +601,8 @@ def main():
     }
     if singles is not None:
         out["singles"] = singles
+    if lccd is not None:
+        out["full_monomer_equation"] = lccd
     if served is not None:
         out["serving"] = served
     if args.batched > 0:

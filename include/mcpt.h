@@ -119,7 +119,8 @@ typedef struct {
     int32_t sweeps;         /* sweeps run (reduced-precision + FP64 polish) */
     int32_t polish_sweeps;  /* of which FP64 residual sweeps in polish mode */
     int32_t status;         /* mcpt_status of this solve */
-    int32_t reserved;
+    int32_t iso_sweeps;     /* full monomer equation (mcpt_lccd_attach): sweeps of the isolated-monomer
+                               LCCD of step 5; 0 otherwise */
 } mcpt_summary;
 
 /* Per-launch kernel timing, recorded with HIP events on the context's stream
@@ -139,6 +140,13 @@ typedef struct {
     double  singles_ms;     /* summed duration of singles pair-phase launches (mcpt_singles) */
     int64_t singles_launches;
     double  singles_v_bytes;/* dimer-block bytes those launches streamed (8 nX nY per pair) */
+    double  lccd_ring_ms;   /* full monomer equation: summed duration of the ring-product launches */
+    double  lccd_ladder_ms; /* summed duration of the ladder launches (particle-particle ladder, hole-hole
+                               ladder and assembly of the intramonomer terms) */
+    int64_t lccd_launches;  /* ladder launches */
+    double  lccd_w_bytes;   /* <ab|cd> integral bytes those launches streamed (8 v^4 per monomer, rows
+                               padded to 16) */
+    double  lccd_ladder_flops; /* algorithmic flops of their particle-particle ladders (2 o^2 v^4 per monomer) */
 } mcpt_timing;
 
 /* Create a context on HIP device `device`; at most hbm_budget_bytes of device
@@ -248,6 +256,42 @@ mcpt_status mcpt_singles(mcpt_ctx *ctx, uint64_t id, const double *w, int32_t me
  * be NULL.  Errors: MCPT_ERR_UNKNOWN_ID, MCPT_ERR_INVALID (no singles result:
  * never solved, or diverged), MCPT_ERR_DEVICE. */
 mcpt_status mcpt_singles_result(mcpt_ctx *ctx, uint64_t id, double *e_m1, double *t1);
+
+/* ---- Full monomer equation (Eq. 58 with its intramonomer terms; step 5) ----
+ * With these integral classes attached, mcpt_run solves the monomer doubles of
+ * Eq. 58 with every printed term: besides the source and the pair term, the
+ * particle-particle ladder v^{a a1}_{a2 a3} T^{a2 a3}_{i i1}, the hole-hole
+ * ladder v^{i2 i3}_{i i1} T^{a a1}_{i2 i3} and the four ring combinations,
+ * whose exchange-type integrals v^{a i2}_{i a2} = v^{i2 a}_{a2 i} are read from
+ * K (real orbitals: (ai|kc) = (ai|ck)) and whose Coulomb-type integrals
+ * v^{a i2}_{a2 i} = (a a2|i2 i) from J.  Each run first iterates every
+ * monomer's equation without the pair term (step 5, the isolated-monomer LCCD,
+ * same tol, max_sweeps and stopping rule), keeps E_LCCD(X) = E_M2 of that
+ * solution as the reference of Eq. 56 (mcpt_energy's de_m2 and the summary's
+ * e_mono0), then runs the coupled sweeps (step 6) from the first-order
+ * amplitudes: pair phase (Eq. 59), intramonomer terms from the current T,
+ * monomer update.  FP64 only, not in deterministic mode; HIP-graph capture and
+ * batches work as for mcpt_run.  Dimer amplitudes keep the terms of Eq. 59
+ * listed at the top (its dimer-internal terms need dimer integral classes that
+ * are not inputs).  Sizes per monomer: v <= 64 and o v <= 1024. */
+typedef struct {
+    const double *w_vvvv;   /* sum_X v_X^4: W_X[a][b][c][d] = <ab|cd>, row-major, monomers in upload order */
+    const double *q_oooo;   /* sum_X o_X^4: Q_X[i][j][k][l] = <ij|kl> */
+    const double *j_oovv;   /* sum_X o_X^2 v_X^2: J_X[i][j][a][b] = <ia|jb> = (ij|ab) */
+    int32_t       memory;   /* mcpt_memory of the three arrays */
+} mcpt_lccd_integrals;
+
+/* Attach (ints != NULL) or detach (NULL) the intramonomer integral classes of
+ * a resident problem.  The arrays are read before the call returns; the packed
+ * copies (W as v^2 x v^2 rows padded to 16: ~8 v^4 bytes per monomer), Q, the
+ * packed J and three np x np term buffers per monomer stay with the problem
+ * and count against the budget.  The problem's last results are dropped.
+ * Errors: MCPT_ERR_INVALID (NULL array, memory, monomer sizes),
+ * MCPT_ERR_NONFINITE, MCPT_ERR_ADMISSION, MCPT_ERR_NOMEM, MCPT_ERR_UNKNOWN_ID,
+ * MCPT_ERR_DEVICE.  mcpt_run of an attached problem returns MCPT_ERR_INVALID
+ * for reduced precision or deterministic = 1, and MCPT_ERR_DIVERGED (no
+ * results) when step 5 diverges for any cluster. */
+mcpt_status mcpt_lccd_attach(mcpt_ctx *ctx, uint64_t id, const mcpt_lccd_integrals *ints);
 
 /* ---- Tile autotuner of the reduced-precision pair kernel ----
  * The kernel exists in several tile shapes: each wave computes sb x sb output

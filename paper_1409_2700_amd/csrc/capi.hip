@@ -81,8 +81,23 @@ void drop_graph(Resident* r) {
     r->graph_prec = -1;
 }
 
+void free_lccd(mcpt_ctx* c, Resident* r) {
+    for (void* p : r->lccd_allocations) (void)hipFree(p);
+    r->lccd_allocations.clear();
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        c->in_use -= std::min(c->in_use, r->lccd_bytes);
+    }
+    r->lccd_bytes = 0;
+    r->lccd = false;
+    r->lccd_desc.clear();
+    r->d_lccd = nullptr;
+    r->d_W = r->d_Q = r->d_J = r->d_L = r->d_R12 = r->d_Y = r->d_elccd = nullptr;
+}
+
 void free_resident(mcpt_ctx* c, Resident* r) {
     drop_graph(r);
+    free_lccd(c, r);
     free_det(c, r);
     free_lowp(c, r);
     for (void* p : r->allocations) (void)hipFree(p);
@@ -163,6 +178,13 @@ void drain_timing(Timing& t) {
                 t.tot.singles_ms += ms;
                 t.tot.singles_launches += 1;
                 t.tot.singles_v_bytes += r.vbytes;
+            } else if (r.kind == 4) {
+                t.tot.lccd_ring_ms += ms;
+            } else if (r.kind == 5) {
+                t.tot.lccd_ladder_ms += ms;
+                t.tot.lccd_launches += 1;
+                t.tot.lccd_w_bytes += r.vbytes;
+                t.tot.lccd_ladder_flops += r.flops;
             } else {
                 t.tot.mono_ms += ms;
                 t.tot.mono_launches += 1;
@@ -1008,11 +1030,149 @@ mcpt_status singles(mcpt_ctx* c, Exec& x, Resident* R, const double* w, int32_t 
     return (mcpt_status)sm.status;
 }
 
+// Intramonomer integral classes of the full monomer equation (Eq. 58):
+// validated, copied, packed and kept with the problem; in == nullptr detaches.
+mcpt_status lccd_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_lccd_integrals* in) {
+    mcpt_status st;
+    if ((st = ensure_device(c)) != MCPT_OK) return st;
+    hipStream_t s = x.stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    drop_graph(R);
+    free_lccd(c, R);
+    if (!in) return MCPT_OK;
+    if (in->memory != MCPT_HOST && in->memory != MCPT_DEVICE)
+        return fail(MCPT_ERR_INVALID, "memory must be MCPT_HOST or MCPT_DEVICE");
+    std::vector<LccdDesc> ld(R->n_mono);
+    int64_t nw = 0, nq = 0, w_pack = 0;
+    int max_rows = 16, max_o = 1, max_np = 16;
+    for (int m = 0; m < R->n_mono; ++m) {
+        const MonoDesc& d = R->monos[m];
+        if (d.v > 64 || d.np > kLccdMaxNp)
+            return fail(MCPT_ERR_INVALID, "monomer " + std::to_string(m) +
+                                              ": the full monomer equation supports v <= 64 and o v <= 1024");
+        const int v2 = d.v * d.v, rows = round_up(v2, 16);
+        ld[m] = LccdDesc{w_pack, nw, nq, rows, rows};
+        w_pack += (int64_t)rows * rows;
+        nw += (int64_t)v2 * v2;
+        nq += (int64_t)d.o * d.o * d.o * d.o;
+        max_rows = std::max(max_rows, rows);
+        max_o = std::max(max_o, d.o);
+        max_np = std::max(max_np, d.np);
+    }
+    const int64_t nj = R->raw_elems;
+    if ((nw > 0 && !in->w_vvvv) || (nq > 0 && !in->q_oooo) || (nj > 0 && !in->j_oovv))
+        return fail(MCPT_ERR_INVALID, "an integral array is NULL");
+    const bool host = in->memory == MCPT_HOST;
+    if (host) {
+        auto finite = [](const double* p, int64_t n) {
+            for (int64_t k = 0; k < n; ++k)
+                if (!std::isfinite(p[k])) return false;
+            return true;
+        };
+        if (!finite(in->w_vvvv, nw) || !finite(in->q_oooo, nq) || !finite(in->j_oovv, nj))
+            return fail(MCPT_ERR_NONFINITE, "intramonomer integrals have a non-finite value");
+    } else {
+        *x.h_flag = 0;
+        HIP_TRY(hipMemcpyAsync(x.d_flag, x.h_flag, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        launch_nonfinite(in->w_vvvv, nw, x.d_flag, s);
+        launch_nonfinite(in->q_oooo, nq, x.d_flag, s);
+        launch_nonfinite(in->j_oovv, nj, x.d_flag, s);
+        HIP_TRY(hipMemcpyAsync(x.h_flag, x.d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (*x.h_flag) return fail(MCPT_ERR_NONFINITE, "intramonomer integrals have a non-finite value");
+    }
+    auto rnd = [](int64_t bytes) { return (size_t)((std::max<int64_t>(bytes, 1) + 255) / 256 * 256); };
+    const size_t keep = rnd(8 * w_pack) + rnd(8 * nq) + 4 * rnd(8 * R->mat_elems) + rnd(8 * (int64_t)R->n_mono) +
+                        rnd((int64_t)sizeof(LccdDesc) * R->n_mono);
+    const size_t staging = host ? rnd(8 * std::max(nw, nj)) : 0;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        if (c->in_use + (c->reserved - x.reserved) + keep + staging > c->budget)
+            return fail(MCPT_ERR_ADMISSION, "intramonomer integrals exceed the budget");
+    }
+    auto alloc = [&](void** out, size_t bytes) -> mcpt_status {
+        void* p = nullptr;
+        const hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MCPT_ERR_NOMEM, "hipMalloc of intramonomer buffers failed");
+        }
+        R->lccd_allocations.push_back(p);
+        R->lccd_bytes += bytes;
+        std::lock_guard<std::mutex> g(c->mu);
+        c->in_use += bytes;
+        *out = p;
+        return MCPT_OK;
+    };
+    void* pv[8] = {};
+    if ((st = alloc(&pv[0], rnd(8 * w_pack))) != MCPT_OK || (st = alloc(&pv[1], rnd(8 * nq))) != MCPT_OK ||
+        (st = alloc(&pv[2], rnd(8 * R->mat_elems))) != MCPT_OK ||
+        (st = alloc(&pv[3], rnd(8 * R->mat_elems))) != MCPT_OK ||
+        (st = alloc(&pv[4], rnd(8 * R->mat_elems))) != MCPT_OK ||
+        (st = alloc(&pv[5], rnd(8 * R->mat_elems))) != MCPT_OK ||
+        (st = alloc(&pv[6], rnd(8 * (int64_t)R->n_mono))) != MCPT_OK ||
+        (st = alloc(&pv[7], rnd((int64_t)sizeof(LccdDesc) * R->n_mono))) != MCPT_OK) {
+        free_lccd(c, R);
+        return st;
+    }
+    R->d_W = static_cast<double*>(pv[0]);
+    R->d_Q = static_cast<double*>(pv[1]);
+    R->d_J = static_cast<double*>(pv[2]);
+    R->d_L = static_cast<double*>(pv[3]);
+    R->d_R12 = static_cast<double*>(pv[4]);
+    R->d_Y = static_cast<double*>(pv[5]);
+    R->d_elccd = static_cast<double*>(pv[6]);
+    R->d_lccd = static_cast<LccdDesc*>(pv[7]);
+    R->lccd_desc = ld;
+    auto fail_free = [&](mcpt_status e) {
+        free_lccd(c, R);
+        return e;
+    };
+    const hipMemcpyKind kind = host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    if (hipMemcpyAsync(R->d_lccd, ld.data(), ld.size() * sizeof(LccdDesc), hipMemcpyHostToDevice, s) != hipSuccess ||
+        (nq > 0 && hipMemcpyAsync(R->d_Q, in->q_oooo, nq * sizeof(double), kind, s) != hipSuccess))
+        return fail_free(fail(MCPT_ERR_DEVICE, "copy of intramonomer integrals failed"));
+    launch_fill(R->d_L, R->mat_elems, 0.0, s);
+    launch_fill(R->d_R12, R->mat_elems, 0.0, s);
+    launch_fill(R->d_Y, R->mat_elems, 0.0, s);
+    if (host) {
+        // host arrays go through one temporary device buffer, W and then J
+        void* stage = nullptr;
+        if (hipMalloc(&stage, staging) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail_free(fail(MCPT_ERR_NOMEM, "hipMalloc of the integral staging buffer failed"));
+        }
+        hipError_t e = hipMemcpyAsync(stage, in->w_vvvv, nw * sizeof(double), hipMemcpyHostToDevice, s);
+        launch_lccd_pack(R->d_monos, R->d_lccd, R->n_mono, static_cast<double*>(stage), nullptr, R->d_W, nullptr, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(stage, in->j_oovv, nj * sizeof(double), hipMemcpyHostToDevice, s);
+        launch_lccd_pack(R->d_monos, R->d_lccd, R->n_mono, nullptr, static_cast<double*>(stage), nullptr, R->d_J, s);
+        const hipError_t e2 = hipStreamSynchronize(s);
+        (void)hipFree(stage);
+        if (e != hipSuccess || e2 != hipSuccess)
+            return fail_free(fail(MCPT_ERR_DEVICE, "upload of intramonomer integrals failed"));
+    } else {
+        launch_lccd_pack(R->d_monos, R->d_lccd, R->n_mono, in->w_vvvv, in->j_oovv, R->d_W, R->d_J, s);
+    }
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return fail_free(fail(MCPT_ERR_DEVICE, "packing of intramonomer integrals failed"));
+    R->lccd_ring_blocks = lccd_ring_blocks(max_np);
+    R->lccd_ladder_blocks = lccd_ladder_blocks(max_rows, max_o);
+    R->lccd_w_bytes = 8.0 * (double)w_pack;
+    double fl = 0.0;
+    for (const MonoDesc& d : R->monos) fl += 2.0 * (double)d.o * d.o * (double)d.v * d.v * (double)d.v * d.v;
+    R->lccd_w_flops = fl;
+    R->lccd = true;
+    R->has_result = false;
+    return MCPT_OK;
+}
+
 mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_summary* out) {
     mcpt_status st = validate_options(o);
     if (st != MCPT_OK) return st;
     if ((st = ensure_device(c)) != MCPT_OK) return st;
     if ((st = ensure_scratch(c, x, R->max_slot)) != MCPT_OK) return st;
+    if (R->lccd && (o->precision != MCPT_FP64 || o->deterministic))
+        return fail(MCPT_ERR_INVALID, "the full monomer equation runs in FP64 without the deterministic mode");
     R->det_on = o->deterministic != 0;
     if (R->det_on && (st = ensure_det(c, x, R)) != MCPT_OK) return st;
     const int prec = o->precision;
@@ -1033,12 +1193,12 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
     hipStream_t s = x.stream;
     R->has_result = false;
     Ctrl& h = *x.h_ctrl;
-    std::memset(&h, 0, sizeof(Ctrl));
-    h.fixed = o->tol == 0.0;
-    h.max_sweeps = o->max_sweeps;
-    h.tol = o->tol;
-    HIP_TRY(hipMemcpyAsync(x.d_ctrl, &h, sizeof(Ctrl), hipMemcpyHostToDevice, s));
-    {
+    auto reset_state = [&]() -> mcpt_status {
+        std::memset(&h, 0, sizeof(Ctrl));
+        h.fixed = o->tol == 0.0;
+        h.max_sweeps = o->max_sweeps;
+        h.tol = o->tol;
+        HIP_TRY(hipMemcpyAsync(x.d_ctrl, &h, sizeof(Ctrl), hipMemcpyHostToDevice, s));
         std::vector<ClState> zero(R->n_cl, ClState{});
         for (int q = 0; q < R->n_cl; ++q)
             if (!R->cl_bad.empty() && R->cl_bad[q]) {   // never swept; reported as non-finite input
@@ -1047,9 +1207,59 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
             }
         HIP_TRY(hipMemcpyAsync(R->d_cl, zero.data(), R->n_cl * sizeof(ClState), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
-    }
+        return MCPT_OK;
+    };
+    if ((st = reset_state()) != MCPT_OK) return st;
     launch_fill(R->d_G[0], R->mat_elems, 0.0, s);
     launch_fill(R->d_G[1], R->mat_elems, 0.0, s);
+    // intramonomer terms of the full monomer equation, L = P + H + R + R^T from the current T and M
+    auto lccd_terms = [&](const Ctrl* ctrl) {
+        hipEvent_t a = nullptr;
+        record_begin(x, &a);
+        launch_lccd_ring(R->d_monos, R->n_mono, R->lccd_ring_blocks, R->d_K, R->d_J, R->d_T, R->d_M, R->d_R12, R->d_Y,
+                         ctrl, R->d_cl, s);
+        record_end(x, a, 4, 0.0, 0.0);
+        record_begin(x, &a);
+        launch_lccd_ladder(R->d_monos, R->d_lccd, R->n_mono, R->lccd_ladder_blocks, R->d_W, R->d_Q, R->d_T, R->d_R12,
+                           R->d_Y, R->d_L, ctrl, R->d_cl, s);
+        record_end(x, a, 5, R->lccd_w_flops, R->lccd_w_bytes);
+    };
+    std::vector<int32_t> iso_sweeps(R->n_cl, 0);
+    int iso_max = 0;
+    if (R->lccd) {
+        // step 5: every monomer's LCCD without its environment (no pair phase, G stays zero),
+        // same stopping rule; E_LCCD(X) is kept as the reference of Eq. 56
+        launch_monomer(kMonoInit, R->d_monos, R->n_mono, R->max_v, R->d_dif, R->d_K, nullptr, nullptr, R->d_T, R->d_M,
+                       R->d_em2, R->d_em2_0, R->d_res, nullptr, nullptr, s);
+        const int every5 = o->check_every > 0 ? o->check_every : 1;
+        int issued = 0;
+        while (issued < o->max_sweeps) {
+            const int batch = std::min(every5, o->max_sweeps - issued);
+            for (int k = 0; k < batch; ++k) {
+                lccd_terms(x.d_ctrl);
+                launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->max_v, R->d_dif, R->d_K, R->d_G[0], R->d_G[1],
+                               R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, x.d_ctrl, R->d_cl, s, R->d_L);
+                launch_reduce_sweep(R->n_cl, R->d_cl_mono, R->d_res, R->d_cl, R->d_hist, x.d_ctrl, s);
+                ++issued;
+            }
+            if ((st = sync_ctrl(x)) != MCPT_OK) return st;
+            if (h.done) break;
+        }
+        std::vector<ClState> cs(R->n_cl);
+        HIP_TRY(hipMemcpyAsync(cs.data(), R->d_cl, R->n_cl * sizeof(ClState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(R->d_elccd, R->d_em2, R->n_mono * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int q = 0; q < R->n_cl; ++q) {
+            iso_sweeps[q] = cs[q].sweeps;
+            if (cs[q].status == MCPT_ERR_DIVERGED) {
+                if (x.timing.on) drain_timing(x.timing);
+                return fail(MCPT_ERR_DIVERGED, "isolated-monomer LCCD (step 5) of cluster " + std::to_string(q) +
+                                                   " diverged after " + std::to_string(cs[q].sweeps) + " sweeps");
+            }
+        }
+        iso_max = h.sweeps;
+        if ((st = reset_state()) != MCPT_OK) return st;
+    }
     // BF16 sweeps accumulate G in FP32 (its rounding is far below the BF16 products');
     // deterministic mode keeps the FP64 partial-block path
     const bool g32 = prec == MCPT_BF16 && !R->det_on && R->d_G32[0];
@@ -1098,8 +1308,10 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
         auto issue_sweep = [&]() {
             if (prec == MCPT_FP64) {
                 pair_phase(c, x, R, R->d_G[cur], 1, x.d_ctrl);
+                if (R->lccd) lccd_terms(x.d_ctrl);
                 launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->max_v, R->d_dif, R->d_K, R->d_G[cur], R->d_G[cur ^ 1],
-                               R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, x.d_ctrl, R->d_cl, s);
+                               R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, x.d_ctrl, R->d_cl, s,
+                               R->lccd ? R->d_L : nullptr);
                 cur ^= 1;
             } else {
                 lo_pair(1);
@@ -1115,7 +1327,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
                                              (int64_t)(uintptr_t)x.d_ctrl, x.scratch_slot,
                                              (int64_t)c->grid_lds * 1000000 + c->grid_glb,
                                              ((int64_t)x.grid_lo * 10000 + x.grid_lo_lds) * 1000 + R->lo_variant};
-            const int gprec = prec + (R->det_on ? 8 : 0);
+            const int gprec = prec + (R->det_on ? 8 : 0) + (R->lccd ? 32 : 0);
             if (!R->graph || R->graph_prec != gprec || R->graph_sweeps != gk || R->graph_key != key) {
                 drop_graph(R);
                 hipGraph_t g = nullptr;
@@ -1149,6 +1361,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
                 if (prec == MCPT_FP64) {
                     pair_phase(c, x, R, R->d_G[cur], 1, x.d_ctrl);
                     record_end(x, a, 0, fl_sweep, vb);
+                    if (R->lccd) lccd_terms(x.d_ctrl);
                 } else {
                     lo_pair(1);
                     record_end(x, a, 2, fl_sweep, R->lo_v_bytes);
@@ -1157,7 +1370,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
                 if (prec == MCPT_FP64) {
                     launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->max_v, R->d_dif, R->d_K, R->d_G[cur],
                                    R->d_G[cur ^ 1], R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, x.d_ctrl,
-                                   R->d_cl, s);
+                                   R->d_cl, s, R->lccd ? R->d_L : nullptr);
                     cur ^= 1;
                 } else {
                     lo_mono(kMonoUpdate, x.d_ctrl);
@@ -1274,6 +1487,8 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
         pair_phase(c, x, R, R->d_G[cur], 0, nullptr);
         record_end(x, a, 0, fl_final, vb);
     }
+    if (R->lccd)   // the reference of Eq. 56 is the isolated-monomer LCCD energy of step 5
+        HIP_TRY(hipMemcpyAsync(R->d_em2_0, R->d_elccd, R->n_mono * sizeof(double), hipMemcpyDeviceToDevice, s));
     launch_reduce_final(R->n_cl, R->d_cl_mono, R->d_cl_pair, R->d_em2, R->d_em2_0, R->d_ed2, R->d_cl, x.d_ctrl, s);
     if ((st = sync_ctrl(x)) != MCPT_OK) return st;
     if (x.timing.on) drain_timing(x.timing);
@@ -1291,6 +1506,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
             cq.e_mono0 = cs[q].e_mono0;
             cq.residual = cs[q].residual;
             cq.sweeps = cs[q].sweeps;
+            cq.iso_sweeps = iso_sweeps[q];
             cq.seconds = secs;
             if (cs[q].status == MCPT_ERR_NONFINITE) cq.status = MCPT_ERR_NONFINITE;
             else if (h.fixed) cq.status = cs[q].status == MCPT_ERR_DIVERGED ? MCPT_ERR_DIVERGED : MCPT_OK;
@@ -1313,6 +1529,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
     sm.residual = h.residual;
     sm.sweeps = n_lo + n_hi;
     sm.polish_sweeps = (prec != MCPT_FP64 && o->polish) ? n_hi : 0;
+    sm.iso_sweeps = iso_max;
     sm.status = MCPT_OK;
     for (int q = 0; q < R->n_cl; ++q)
         if (R->cl_last[q].status == MCPT_ERR_DIVERGED || (R->cl_last[q].status != MCPT_OK && sm.status == MCPT_OK))
@@ -1477,6 +1694,17 @@ mcpt_status mcpt_release(mcpt_ctx* c, uint64_t id) {
     (void)hipStreamSynchronize(c->main.stream);
     release_resident(c, id);
     return MCPT_OK;
+}
+
+mcpt_status mcpt_lccd_attach(mcpt_ctx* c, uint64_t id, const mcpt_lccd_integrals* ints) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    Resident* R = find_resident(c, id);
+    if (!R) return unknown(id);
+    try {
+        return lccd_attach(c, c->main, R, ints);
+    } catch (const std::exception& e) {
+        return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
+    }
 }
 
 mcpt_status mcpt_singles(mcpt_ctx* c, uint64_t id, const double* w, int32_t memory, const mcpt_options* opts,

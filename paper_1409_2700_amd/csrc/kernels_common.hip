@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
     double* __restrict__ T, double* __restrict__ M, double* __restrict__ R, double* __restrict__ Dl,
     E* __restrict__ Mlo, const int64_t* __restrict__ mlo_off, int lo_chunk, double* __restrict__ em2,
     double* __restrict__ em2_0, double* __restrict__ res, const Ctrl* __restrict__ ctrl,
-    const ClState* __restrict__ cl) {
+    const ClState* __restrict__ cl, const double* __restrict__ Lt) {
     if (ctrl && ctrl->done) return;
     __shared__ double sh[kMonoThreads];
     const int x = blockIdx.x;
@@ -132,8 +132,14 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
         double tn, ts, lo = 0.0;
         bool has_lo = false;
         if (mode == kMonoUpdate || mode == kMonoUpdateR) {
-            tn = dinv * ((Kx[e_rc] + (double)Gx[e_rc]) + (double)Gx[e_t]);
-            ts = dinv * ((Kx[e_s] + (double)Gx[e_s]) + (double)Gx[e_st]);
+            if (Lt) {   // intramonomer terms of the full monomer equation
+                const double* Lx = Lt + d.mat_off;
+                tn = dinv * (((Kx[e_rc] + (double)Gx[e_rc]) + (double)Gx[e_t]) + Lx[e_rc]);
+                ts = dinv * (((Kx[e_s] + (double)Gx[e_s]) + (double)Gx[e_st]) + Lx[e_s]);
+            } else {
+                tn = dinv * ((Kx[e_rc] + (double)Gx[e_rc]) + (double)Gx[e_t]);
+                ts = dinv * ((Kx[e_s] + (double)Gx[e_s]) + (double)Gx[e_st]);
+            }
             const double told = Tx[e_rc];
             rmax = max_nan(rmax, fabs(tn - told));
             if (mode == kMonoUpdateR) {
@@ -210,7 +216,7 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_blocks_kernel(
     double* __restrict__ T, double* __restrict__ M, double* __restrict__ R, double* __restrict__ Dl,
     E* __restrict__ Mlo, const int64_t* __restrict__ mlo_off, int lo_chunk, double* __restrict__ em2,
     double* __restrict__ em2_0, double* __restrict__ res, const Ctrl* __restrict__ ctrl,
-    const ClState* __restrict__ cl) {
+    const ClState* __restrict__ cl, const double* __restrict__ Lt) {
     if (ctrl && ctrl->done) return;
     __shared__ double sh[kMonoThreads];
     __shared__ double sg[2][VMAX][VMAX + 1];
@@ -254,8 +260,14 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_blocks_kernel(
                 double t1, t2, lo1 = 0.0, lo2 = 0.0;
                 bool has_lo = false;
                 if (mode == kMonoUpdate || mode == kMonoUpdateR) {
-                    t1 = d1 * ((Kx[e1] + sg[0][a][b]) + sg[1][b][a]);
-                    t2 = d2 * ((Kx[e2] + sg[1][a][b]) + sg[0][b][a]);
+                    if (Lt) {   // intramonomer terms of the full monomer equation
+                        const double* Lx = Lt + d.mat_off;
+                        t1 = d1 * (((Kx[e1] + sg[0][a][b]) + sg[1][b][a]) + Lx[e1]);
+                        t2 = d2 * (((Kx[e2] + sg[1][a][b]) + sg[0][b][a]) + Lx[e2]);
+                    } else {
+                        t1 = d1 * ((Kx[e1] + sg[0][a][b]) + sg[1][b][a]);
+                        t2 = d2 * ((Kx[e2] + sg[1][a][b]) + sg[0][b][a]);
+                    }
                     const double o1 = Tx[e1], o2 = Tx[e2];
                     rmax = max_nan(rmax, fabs(t1 - o1));
                     if (!diag) rmax = max_nan(rmax, fabs(t2 - o2));
@@ -490,24 +502,25 @@ template <class E, class GT>
 void monomer_dispatch(int max_v, int mode, const MonoDesc* monos, int n_mono, const double* dif, const double* K,
                       const GT* G, GT* G_zero, double* T, double* M, double* R, double* Dl, E* Mlo,
                       const int64_t* mlo_off, int chunk, double* em2, double* em2_0, double* res, const Ctrl* ctrl,
-                      const ClState* cl, hipStream_t s) {
+                      const ClState* cl, hipStream_t s, const double* Lt = nullptr) {
     if (n_mono <= 0) return;
     if (max_v <= 32)
         hipLaunchKernelGGL((monomer_blocks_kernel<E, 32, GT>), dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos,
-                           dif, K, G, G_zero, T, M, R, Dl, Mlo, mlo_off, chunk, em2, em2_0, res, ctrl, cl);
+                           dif, K, G, G_zero, T, M, R, Dl, Mlo, mlo_off, chunk, em2, em2_0, res, ctrl, cl, Lt);
     else if (max_v <= 64)
         hipLaunchKernelGGL((monomer_blocks_kernel<E, 64, GT>), dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos,
-                           dif, K, G, G_zero, T, M, R, Dl, Mlo, mlo_off, chunk, em2, em2_0, res, ctrl, cl);
+                           dif, K, G, G_zero, T, M, R, Dl, Mlo, mlo_off, chunk, em2, em2_0, res, ctrl, cl, Lt);
     else
         hipLaunchKernelGGL((monomer_kernel<E, GT>), dim3(n_mono), dim3(kMonoThreads), 0, s, mode, monos, dif, K, G,
-                           G_zero, T, M, R, Dl, Mlo, mlo_off, chunk, em2, em2_0, res, ctrl, cl);
+                           G_zero, T, M, R, Dl, Mlo, mlo_off, chunk, em2, em2_0, res, ctrl, cl, Lt);
 }
 
 void launch_monomer(int mode, const MonoDesc* monos, int n_mono, int max_v, const double* dif, const double* K,
                     const double* G, double* G_zero, double* T, double* M, double* em2,
-                    double* em2_0, double* res, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
+                    double* em2_0, double* res, const Ctrl* ctrl, const ClState* cl, hipStream_t s,
+                    const double* L) {
     monomer_dispatch<float, double>(max_v, mode, monos, n_mono, dif, K, G, G_zero, T, M, nullptr, nullptr, nullptr,
-                                    nullptr, 16, em2, em2_0, res, ctrl, cl, s);
+                                    nullptr, 16, em2, em2_0, res, ctrl, cl, s, L);
 }
 
 void launch_monomer_mixed(int mode, int precision, const MonoDesc* monos, int n_mono, int max_v, const double* dif,

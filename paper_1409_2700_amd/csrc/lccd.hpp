@@ -1,0 +1,35 @@
+// Intramonomer terms of Eq. 58 (full monomer equation): device layout and
+// launchers (not part of the C ABI).
+#pragma once
+
+#include "mcpt_internal.hpp"
+
+namespace mcpt {
+
+constexpr int kLccdMaxNp = 1024;     // padded o v of a monomer the ring kernel's offset table holds
+constexpr int kLccdMaxLdw = 4096;    // padded v^2 the ladder kernel's offset table holds (v <= 64)
+
+// Per monomer: where its packed integral matrix W (w_rows x ldw, rows (a,b),
+// columns (c,d), both zero-padded to 16) and its raw <kl|ij> block sit.
+struct LccdDesc {
+    int64_t w_off;       // first element of the packed W in the device buffer
+    int64_t w_raw_off;   // first element of W_X in the caller's concatenated layout
+    int64_t q_off;       // first element of Q_X (o^4, caller layout) in the device buffer
+    int32_t w_rows;      // v^2 rounded up to 16
+    int32_t ldw;         // v^2 rounded up to 16
+};
+
+void launch_lccd_pack(const MonoDesc* monos, const LccdDesc* ld, int n_mono, const double* w_raw,
+                      const double* j_raw, double* W, double* J, hipStream_t s);
+int lccd_ring_blocks(int max_np);
+int lccd_ladder_blocks(int max_w_rows, int max_o);
+// R12 = K M - J T and Y = J Vs(T) for every live monomer
+void launch_lccd_ring(const MonoDesc* monos, int n_mono, int ring_blocks, const double* K, const double* J,
+                      const double* T, const double* M, double* R12, double* Y, const Ctrl* ctrl, const ClState* cl,
+                      hipStream_t s);
+// L = P + H + R + R^T (R = R12 - Vs(Y)) for every live monomer
+void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, int ladder_blocks, const double* W,
+                        const double* Q, const double* T, const double* R12, const double* Y, double* L,
+                        const Ctrl* ctrl, const ClState* cl, hipStream_t s);
+
+}  // namespace mcpt

@@ -109,7 +109,7 @@ void launch_nonfinite(const double* p, int64_t n, int32_t* flag, hipStream_t s);
 void launch_monomer(int mode, const MonoDesc* monos, int n_mono, int max_v, const double* dif,
                     const double* K, const double* G, double* G_zero, double* T, double* M,
                     double* em2, double* em2_0, double* res, const Ctrl* ctrl, const ClState* cl,
-                    hipStream_t s);
+                    hipStream_t s, const double* L = nullptr);   // L: extra term of the update (full monomer equation)
 // Gf / Gf_zero: the FP32 accumulation buffers of BF16 sweeps, read and cleared instead of G / G_zero
 void launch_monomer_mixed(int mode, int precision, const MonoDesc* monos, int n_mono, int max_v, const double* dif,
                           const double* K, const double* G, double* G_zero, double* T, double* M, double* R,

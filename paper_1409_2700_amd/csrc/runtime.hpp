@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/mcpt.h"
+#include "lccd.hpp"
 #include "mcpt_internal.hpp"
 
 namespace mcpt {
@@ -74,6 +75,18 @@ struct Resident {
     int64_t* d_woff = nullptr;        // compact offsets of w per monomer (N + 1)
     bool has_singles = false;
     mcpt_singles_summary singles_last{};
+    // full monomer equation (mcpt_lccd_attach): packed intramonomer integrals, the per-sweep
+    // term buffers and E_LCCD of step 5; freed by a detach or with the problem
+    bool lccd = false;
+    std::vector<LccdDesc> lccd_desc;
+    LccdDesc* d_lccd = nullptr;
+    double *d_W = nullptr, *d_Q = nullptr, *d_J = nullptr;
+    double *d_L = nullptr, *d_R12 = nullptr, *d_Y = nullptr, *d_elccd = nullptr;
+    int lccd_ring_blocks = 0, lccd_ladder_blocks = 0;
+    double lccd_w_bytes = 0.0;        // packed-integral bytes the ladder kernel streams per sweep
+    double lccd_w_flops = 0.0;        // algorithmic flops of the particle-particle ladder per sweep
+    std::vector<void*> lccd_allocations;
+    size_t lccd_bytes = 0;
     // captured sweep graph: valid for one form, one execution resource set and one body count
     hipGraphExec_t graph = nullptr;
     int graph_prec = -1, graph_sweeps = 0, graph_parity = 0;
@@ -93,7 +106,8 @@ struct Timing {
     bool on = false;
     struct Rec {
         hipEvent_t a, b;
-        int kind;   // 0 FP64 pair phase, 1 monomer phase, 2 reduced-precision pair phase, 3 singles pair phase
+        int kind;   // 0 FP64 pair phase, 1 monomer phase, 2 reduced-precision pair phase, 3 singles pair phase,
+                    // 4 intramonomer ring products, 5 intramonomer ladders and assembly
         double flops, vbytes;
     };
     std::vector<Rec> pending;

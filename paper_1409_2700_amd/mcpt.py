@@ -40,6 +40,7 @@ EXPORTS = [
     "mcpt_upload_batch", "mcpt_solve_batch", "mcpt_cluster_results",
     "mcpt_serve_config", "mcpt_submit", "mcpt_poll", "mcpt_wait", "mcpt_serve_stats",
     "mcpt_autotune", "mcpt_tune_export", "mcpt_tune_import", "mcpt_singles", "mcpt_singles_result",
+    "mcpt_lccd_attach",
 ]
 
 
@@ -64,11 +65,11 @@ class mcpt_summary(C.Structure):
         ("e_total", C.c_double), ("e_mono", C.c_double), ("e_dimer", C.c_double),
         ("e_mono0", C.c_double), ("residual", C.c_double), ("seconds", C.c_double),
         ("sweeps", C.c_int32), ("polish_sweeps", C.c_int32), ("status", C.c_int32),
-        ("reserved", C.c_int32),
+        ("iso_sweeps", C.c_int32),
     ]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class mcpt_timing(C.Structure):
@@ -77,11 +78,16 @@ class mcpt_timing(C.Structure):
         ("mono_launches", C.c_int64), ("pair_flops", C.c_double), ("pair_v_bytes", C.c_double),
         ("lowp_ms", C.c_double), ("lowp_launches", C.c_int64), ("lowp_flops", C.c_double),
         ("lowp_v_bytes", C.c_double), ("singles_ms", C.c_double), ("singles_launches", C.c_int64),
-        ("singles_v_bytes", C.c_double),
+        ("singles_v_bytes", C.c_double), ("lccd_ring_ms", C.c_double), ("lccd_ladder_ms", C.c_double),
+        ("lccd_launches", C.c_int64), ("lccd_w_bytes", C.c_double), ("lccd_ladder_flops", C.c_double),
     ]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class mcpt_lccd_integrals(C.Structure):
+    _fields_ = [("w_vvvv", C.c_void_p), ("q_oooo", C.c_void_p), ("j_oovv", C.c_void_p), ("memory", C.c_int32)]
 
 
 class mcpt_singles_summary(C.Structure):
@@ -150,6 +156,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.mcpt_singles.argtypes = [P, C.c_uint64, P, C.c_int32, C.POINTER(mcpt_options),
                                  C.POINTER(mcpt_singles_summary)]
     lib.mcpt_singles_result.argtypes = [P, C.c_uint64, P, P]
+    lib.mcpt_lccd_attach.argtypes = [P, C.c_uint64, C.POINTER(mcpt_lccd_integrals)]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if name not in ("mcpt_destroy", "mcpt_last_error"):
@@ -345,6 +352,23 @@ class Context:
         t = np.empty(int(np.sum(n_occ.astype(np.int64) * n_vir)))
         _check(lib().mcpt_singles_result(self.h, pid, _ptr(e), _ptr(t)))
         return {"e_m1": e, "t1": t}
+
+    # ---- full monomer equation (mcpt_lccd_attach) ----
+    def lccd_attach(self, pid: int, ints, device_ptrs: tuple | None = None):
+        """Attach the intramonomer integrals (an object with flat w, q, j arrays,
+        or device_ptrs = (w, q, j) of device buffers); ints None detaches."""
+        if ints is None and device_ptrs is None:
+            _check(lib().mcpt_lccd_attach(self.h, pid, None))
+            return
+        if device_ptrs is not None:
+            li = mcpt_lccd_integrals(device_ptrs[0], device_ptrs[1], device_ptrs[2], MCPT_DEVICE)
+            _check(lib().mcpt_lccd_attach(self.h, pid, C.byref(li)))
+            return
+        w = np.ascontiguousarray(ints.w, dtype=np.float64)
+        q = np.ascontiguousarray(ints.q, dtype=np.float64)
+        j = np.ascontiguousarray(ints.j, dtype=np.float64)
+        li = mcpt_lccd_integrals(_ptr(w), _ptr(q), _ptr(j), MCPT_HOST)
+        _check(lib().mcpt_lccd_attach(self.h, pid, C.byref(li)))
 
     def release(self, pid: int):
         _check(lib().mcpt_release(self.h, pid))
