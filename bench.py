@@ -317,7 +317,7 @@ def batched(n_clusters, tol):
     return out
 
 
-def pmc_pass(workload: str, precision: int = 0, sweeps: int = 2, singles: bool = False):
+def pmc_pass(workload: str, precision: int = 0, sweeps: int = 2, singles: bool = False, lccd: bool = False):
     """Counter pass for rocprofv3 --pmc: one device copy of a known size
     (the calibration kernel), then `sweeps` fixed sweeps of the resident
     workload in the given precision (no polish) and the final FP64 energy
@@ -335,6 +335,15 @@ def pmc_pass(workload: str, precision: int = 0, sweeps: int = 2, singles: bool =
     log(f"[pmc] calibration copy: {n * 8} bytes read and written")
     del src, dst
     with mc.Context(0) as ctx:
+        if lccd:
+            from synth import LCCD_K_SCALE, lccd_integrals
+            prob.k *= LCCD_K_SCALE
+            pid = ctx.upload(prob)
+            ctx.lccd_attach(pid, lccd_integrals(prob))
+            s = ctx.run(pid, tol=0.0, max_sweeps=sweeps)
+            log(f"[pmc] {workload}: {sweeps} fixed sweeps of step 5 and of step 6 (full monomer equation), "
+                f"E={s['e_total']:.10f}")
+            return
         pid = ctx.upload(prob)
         if singles:
             from synth import singles_source
@@ -504,6 +513,8 @@ def main():
                     help="only launch a calibration copy and two fixed sweeps (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-precision", type=int, default=0, help="0 FP64, 1 FP32, 2 BF16 sweeps in --pmc-pass")
     ap.add_argument("--pmc-singles", action="store_true", help="--pmc-pass runs two singles sweeps instead")
+    ap.add_argument("--pmc-lccd", action="store_true",
+                    help="--pmc-pass runs two sweeps of step 5 and two of step 6 of the full monomer equation")
     ap.add_argument("--singles-steps", type=int, default=3, help="timed singles solves (0: skip)")
     ap.add_argument("--lccd-steps", type=int, default=2,
                     help="timed solves of the full monomer equation (0: skip)")
@@ -517,7 +528,7 @@ def main():
         sys.exit(2)
 
     if args.pmc_pass:
-        pmc_pass(args.workload, args.pmc_precision, singles=args.pmc_singles)
+        pmc_pass(args.workload, args.pmc_precision, singles=args.pmc_singles, lccd=args.pmc_lccd)
         return
     import paper_1409_2700_amd as mc
     from synth import make_workload, DEFAULT_COUPLING_SCALE

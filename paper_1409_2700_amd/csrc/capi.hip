@@ -1157,6 +1157,7 @@ mcpt_status lccd_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_lccd_integ
         return fail_free(fail(MCPT_ERR_DEVICE, "packing of intramonomer integrals failed"));
     R->lccd_ring_blocks = lccd_ring_blocks(max_np);
     R->lccd_ladder_blocks = lccd_ladder_blocks(max_rows, max_o);
+    R->lccd_ct = lccd_ladder_ct(max_o);
     R->lccd_w_bytes = 8.0 * (double)w_pack;
     double fl = 0.0;
     for (const MonoDesc& d : R->monos) fl += 2.0 * (double)d.o * d.o * (double)d.v * d.v * (double)d.v * d.v;
@@ -1220,8 +1221,8 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
                          ctrl, R->d_cl, s);
         record_end(x, a, 4, 0.0, 0.0);
         record_begin(x, &a);
-        launch_lccd_ladder(R->d_monos, R->d_lccd, R->n_mono, R->lccd_ladder_blocks, R->d_W, R->d_Q, R->d_T, R->d_R12,
-                           R->d_Y, R->d_L, ctrl, R->d_cl, s);
+        launch_lccd_ladder(R->d_monos, R->d_lccd, R->n_mono, R->lccd_ladder_blocks, R->lccd_ct, R->d_W, R->d_Q, R->d_T,
+                           R->d_R12, R->d_Y, R->d_L, ctrl, R->d_cl, s);
         record_end(x, a, 5, R->lccd_w_flops, R->lccd_w_bytes);
     };
     std::vector<int32_t> iso_sweeps(R->n_cl, 0);

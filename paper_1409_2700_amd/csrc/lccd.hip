@@ -21,9 +21,11 @@
 //  * lccd_ladder_kernel: P as the product W[(a,b),(c,d)] x T[(i,c),(j,d)] of
 //    the v^2 x v^2 integral matrix (streamed from HBM once per sweep, rows
 //    padded to 16) with the o^2 amplitude columns gathered from T through an LDS
-//    offset table; its epilogue adds H, R12 and Y at the (r, c) and (c, r)
-//    positions and writes L.  This is the HBM-bound part: v^4 integrals per
-//    monomer, each used o^2 times.
+//    offset table, then H on the same accumulators (k over the o^2 hole pairs,
+//    A = T gathered, B = <kl|ij>); its epilogue adds R12 and Y at the (r, c)
+//    and (c, r) positions and writes L.  This is the HBM-bound part: v^4
+//    integrals per monomer, each used o^2 times.
+//  Both kernels place every workgroup of a monomer on one XCD.
 #include "lccd.hpp"
 
 namespace mcpt {
@@ -34,8 +36,9 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLccdThreads = 256;   // four wavefronts
 constexpr int kRingSB = 3;          // ring super-block edge in tiles
-constexpr int kLadRT = 2;           // ladder row tiles per wave task
-constexpr int kLadCT = 4;           // ladder column tiles per pass (o^2 <= 64 in one pass)
+constexpr int kLadRT = 4;           // ladder row tiles per wave task
+constexpr int kLadCT = 4;           // ladder column tiles per task at most (the launch takes ceil(o^2 / 16))
+constexpr int kXcds = 8;            // XCDs of the chip; workgroup b runs on XCD b % 8
 
 __device__ inline d4 mfma(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -85,12 +88,15 @@ __global__ void lccd_pack_kernel(const MonoDesc* __restrict__ monos, const LccdD
 // R12 = K M - J T (kind 0) or Y = J Vs(T) (kind 1).  Rows or columns past the
 // padded edge are clamped for the loads and skipped for the stores.
 __global__ __launch_bounds__(kLccdThreads) void lccd_ring_kernel(
-    const MonoDesc* __restrict__ monos, int blocks_per_mono, const double* __restrict__ K,
+    const MonoDesc* __restrict__ monos, int n_mono, int blocks_per_mono, const double* __restrict__ K,
     const double* __restrict__ J, const double* __restrict__ T, const double* __restrict__ M,
     double* __restrict__ R12, double* __restrict__ Y, const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
     if (ctrl && ctrl->done) return;
-    const int x = blockIdx.x / blocks_per_mono;
-    const int part = blockIdx.x - x * blocks_per_mono;
+    // all blocks of one monomer on one XCD (block b runs on XCD b % 8): its matrices are fetched once
+    const int q = blockIdx.x / kXcds;
+    const int part = q % blocks_per_mono;
+    const int x = (q / blocks_per_mono) * kXcds + (int)(blockIdx.x % kXcds);
+    if (x >= n_mono) return;
     const MonoDesc d = monos[x];
     if (cl && cl[d.cluster].done) return;
     __shared__ int kofs[kLccdMaxNp];   // Vs(T) row k = (i2, a2) -> i2 v np + a2 (0 past n)
@@ -180,114 +186,167 @@ __global__ __launch_bounds__(kLccdThreads) void lccd_ring_kernel(
 // ---------------------------------------------------------------------------
 // ladders and assembly of L
 // ---------------------------------------------------------------------------
-// Wave task: kLadRT row tiles of W (rows (a,b)) against up to kLadCT column
-// tiles of the gathered amplitudes (columns (i,j)); passes over column groups
-// when o^2 > 64.  The epilogue writes L[(i,a),(j,b)].
-__global__ __launch_bounds__(kLccdThreads) void lccd_ladder_kernel(
-    const MonoDesc* __restrict__ monos, const LccdDesc* __restrict__ ld, int blocks_per_mono,
+struct LadderView {
+    const double* W;     // packed integral matrix of the monomer (w_rows x ldw)
+    const double* Q;     // <kl|ij> as an o^2 x o^2 matrix, rows (k,l), columns (i,j)
+    const double* T;
+    const double* R12;
+    const double* Y;
+    double* L;
+    const int* kofs;     // W column k = (c,d) -> T offset c np + d
+    const int* hofs;     // hole pair kk = (k,l) -> T offset k v np + l v
+    int ldw, w_rows, np, o, v, o2, v2;
+};
+
+// One wave task: kLadRT row tiles (rows m = (a,b) of W) x CT column tiles
+// (columns n = (i,j)).  acc = sum_{(c,d)} W[m][(c,d)] T[(i,c),(j,d)]
+//                           + sum_{(k,l)} T[(k,a),(l,b)] <kl|ij>      (P + H)
+// then L[(i,a),(j,b)] = acc + R[(i,a),(j,b)] + R[(j,b),(i,a)].
+template <int CT>
+__device__ void ladder_task(const LadderView& g, int tr0, int tc0, int lane) {
+    const int lr = lane & 15, lk = (lane >> 4) * 4;
+    int arow[kLadRT], hrow[kLadRT], bbase[CT], ncol[CT];
+#pragma unroll
+    for (int u = 0; u < kLadRT; ++u) {
+        const int m = (tr0 + u) * 16 + lr;
+        arow[u] = m < g.w_rows ? m : 0;
+        const int a = m / g.v, b = m - a * g.v;
+        hrow[u] = m < g.v2 ? a * g.np + b : 0;
+    }
+#pragma unroll
+    for (int w = 0; w < CT; ++w) {
+        const int n = (tc0 + w) * 16 + lr;
+        const int i = n / g.o, j = n - i * g.o;
+        bbase[w] = n < g.o2 ? i * g.v * g.np + j * g.v : 0;
+        ncol[w] = n;
+    }
+    d4 acc[kLadRT][CT];
+#pragma unroll
+    for (int u = 0; u < kLadRT; ++u)
+#pragma unroll
+        for (int w = 0; w < CT; ++w) acc[u][w] = d4(0.0);
+    // particle-particle ladder: W streamed once; the next k chunk of both
+    // operands (W rows and the gathered amplitude columns) in flight
+    d4 an[kLadRT];
+    double bn[CT][4];
+#pragma unroll
+    for (int u = 0; u < kLadRT; ++u) an[u] = load4(g.W + (int64_t)arow[u] * g.ldw + lk);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int ko = g.kofs[lk + s];
+#pragma unroll
+        for (int w = 0; w < CT; ++w) bn[w][s] = g.T[ko + bbase[w]];
+    }
+    for (int k0 = 0; k0 < g.ldw; k0 += 16) {
+        double a[kLadRT][4], b[CT][4];
+#pragma unroll
+        for (int u = 0; u < kLadRT; ++u) {
+            a[u][0] = an[u].x;
+            a[u][1] = an[u].y;
+            a[u][2] = an[u].z;
+            a[u][3] = an[u].w;
+        }
+#pragma unroll
+        for (int w = 0; w < CT; ++w)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) b[w][s] = bn[w][s];
+        if (k0 + 16 < g.ldw) {
+#pragma unroll
+            for (int u = 0; u < kLadRT; ++u) an[u] = load4(g.W + (int64_t)arow[u] * g.ldw + k0 + 16 + lk);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int ko = g.kofs[k0 + 16 + lk + s];
+#pragma unroll
+                for (int w = 0; w < CT; ++w) bn[w][s] = g.T[ko + bbase[w]];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int u = 0; u < kLadRT; ++u)
+#pragma unroll
+                for (int w = 0; w < CT; ++w) acc[u][w] = mfma(a[u][s], b[w][s], acc[u][w]);
+    }
+    // hole-hole ladder on the same accumulators: k runs over the o^2 hole pairs (k,l)
+    for (int k0 = 0; k0 < g.o2; k0 += 16) {
+        double a[kLadRT][4], b[CT][4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int kk = k0 + lk + s;
+            const bool ok = kk < g.o2;
+            const int ho = g.hofs[kk];
+#pragma unroll
+            for (int u = 0; u < kLadRT; ++u) a[u][s] = g.T[ho + hrow[u]];
+#pragma unroll
+            for (int w = 0; w < CT; ++w) b[w][s] = (ok && ncol[w] < g.o2) ? g.Q[kk * g.o2 + ncol[w]] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int u = 0; u < kLadRT; ++u)
+#pragma unroll
+                for (int w = 0; w < CT; ++w) acc[u][w] = mfma(a[u][s], b[w][s], acc[u][w]);
+    }
+    // epilogue: element (m = (a,b), n = (i,j)) -> L[(i,a),(j,b)]
+#pragma unroll
+    for (int w = 0; w < CT; ++w) {
+        const int n = ncol[w];
+        if (n >= g.o2) continue;
+        const int i = n / g.o, j = n - i * g.o;
+#pragma unroll
+        for (int u = 0; u < kLadRT; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int m = (tr0 + u) * 16 + acc_row(lane, t);
+                if (m >= g.v2) continue;
+                const int a = m / g.v, b = m - a * g.v;
+                const int r = i * g.v + a, c = j * g.v + b;
+                const double rr = g.R12[(int64_t)r * g.np + c] - g.Y[(int64_t)(i * g.v + b) * g.np + j * g.v + a];
+                const double rt = g.R12[(int64_t)c * g.np + r] - g.Y[(int64_t)(j * g.v + a) * g.np + i * g.v + b];
+                g.L[(int64_t)r * g.np + c] = (acc[u][w][t] + rr) + rt;
+            }
+    }
+}
+
+// All blocks of one monomer run on one XCD (block b -> XCD b % 8), so the
+// monomer's T, R12 and Y are fetched into one L2 once per sweep while its W
+// streams through.  Grid: n_mono rounded up to 8, times blocks_per_mono.
+template <int CT>
+__global__ __launch_bounds__(kLccdThreads, 2) void lccd_ladder_kernel(
+    const MonoDesc* __restrict__ monos, const LccdDesc* __restrict__ ld, int n_mono, int blocks_per_mono,
     const double* __restrict__ W, const double* __restrict__ Q, const double* __restrict__ T,
     const double* __restrict__ R12, const double* __restrict__ Y, double* __restrict__ L,
     const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
     if (ctrl && ctrl->done) return;
-    const int x = blockIdx.x / blocks_per_mono;
-    const int part = blockIdx.x - x * blocks_per_mono;
+    const int q = blockIdx.x / kXcds;
+    const int part = q % blocks_per_mono;
+    const int x = (q / blocks_per_mono) * kXcds + (int)(blockIdx.x % kXcds);
+    if (x >= n_mono) return;
     const MonoDesc d = monos[x];
     if (cl && cl[d.cluster].done) return;
     const LccdDesc l = ld[x];
-    __shared__ int kofs[kLccdMaxLdw];   // W column k = (c, d) -> T offset c np + d (0 past v^2)
-    const int np = d.np, n = d.n, o = d.o, v = d.v, v2 = v * v, o2 = o * o;
+    __shared__ int kofs[kLccdMaxLdw];
+    __shared__ int hofs[64];
+    const int np = d.np, o = d.o, v = d.v, v2 = v * v, o2 = o * o;
     for (int k = threadIdx.x; k < l.ldw; k += kLccdThreads) {
         const int c = k / v, dd = k - c * v;
         kofs[k] = k < v2 ? c * np + dd : 0;
     }
+    for (int k = threadIdx.x; k < 64; k += kLccdThreads) {
+        const int kk = k / o, ll = k - kk * o;
+        hofs[k] = k < o2 ? kk * v * np + ll * v : 0;
+    }
     __syncthreads();
-    const double* Wx = W + l.w_off;
-    const double* Qx = Q + l.q_off;
-    const double* Tx = T + d.mat_off;
-    const double* Rx = R12 + d.mat_off;
-    const double* Yx = Y + d.mat_off;
-    double* Lx = L + d.mat_off;
+    LadderView g{W + l.w_off, Q + l.q_off, T + d.mat_off, R12 + d.mat_off, Y + d.mat_off, L + d.mat_off,
+                 kofs, hofs, l.ldw, l.w_rows, np, o, v, o2, v2};
     const int nrt = l.w_rows / 16;
     const int ntask_r = (nrt + kLadRT - 1) / kLadRT;
     const int nct = (o2 + 15) / 16;
-    const int ngroups = (nct + kLadCT - 1) / kLadCT;
+    const int ngroups = (nct + CT - 1) / CT;
     const int tasks = ntask_r * ngroups;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int lr = lane & 15, lk = (lane >> 4) * 4;
-    for (int task = part * (kLccdThreads / 64) + wave; task < tasks; task += blocks_per_mono * (kLccdThreads / 64)) {
-        const int tr0 = (task / ngroups) * kLadRT;
-        const int tc0 = (task % ngroups) * kLadCT;
-        int arow[kLadRT], bbase[kLadCT];
-#pragma unroll
-        for (int u = 0; u < kLadRT; ++u) {
-            const int r = (tr0 + u) * 16 + lr;
-            arow[u] = r < l.w_rows ? r : 0;
-        }
-#pragma unroll
-        for (int w = 0; w < kLadCT; ++w) {
-            const int col = (tc0 + w) * 16 + lr;   // (i, j)
-            const int i = col / o, j = col - i * o;
-            bbase[w] = col < o2 ? i * v * np + j * v : 0;
-        }
-        d4 acc[kLadRT][kLadCT];
-#pragma unroll
-        for (int u = 0; u < kLadRT; ++u)
-#pragma unroll
-            for (int w = 0; w < kLadCT; ++w) acc[u][w] = d4(0.0);
-        d4 an[kLadRT];
-#pragma unroll
-        for (int u = 0; u < kLadRT; ++u) an[u] = load4(Wx + (int64_t)arow[u] * l.ldw + lk);
-        for (int k0 = 0; k0 < l.ldw; k0 += 16) {
-            double a[kLadRT][4], b[kLadCT][4];
-#pragma unroll
-            for (int u = 0; u < kLadRT; ++u) {
-                a[u][0] = an[u].x;
-                a[u][1] = an[u].y;
-                a[u][2] = an[u].z;
-                a[u][3] = an[u].w;
-            }
-            if (k0 + 16 < l.ldw) {
-#pragma unroll
-                for (int u = 0; u < kLadRT; ++u) an[u] = load4(Wx + (int64_t)arow[u] * l.ldw + k0 + 16 + lk);
-            }
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int ko = kofs[k0 + lk + s];
-#pragma unroll
-                for (int w = 0; w < kLadCT; ++w) b[w][s] = Tx[ko + bbase[w]];
-            }
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int u = 0; u < kLadRT; ++u)
-#pragma unroll
-                    for (int w = 0; w < kLadCT; ++w) acc[u][w] = mfma(a[u][s], b[w][s], acc[u][w]);
-        }
-        // epilogue: element (m = (a,b), col = (i,j)) -> L[(i,a),(j,b)]
-#pragma unroll
-        for (int w = 0; w < kLadCT; ++w) {
-            const int col = (tc0 + w) * 16 + lr;
-            if (col >= o2) continue;
-            const int i = col / o, j = col - i * o;
-#pragma unroll
-            for (int u = 0; u < kLadRT; ++u)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int m = (tr0 + u) * 16 + acc_row(lane, t);
-                    if (m >= v2) continue;
-                    const int a = m / v, b = m - a * v;
-                    const int r = i * v + a, c = j * v + b;
-                    double h = 0.0;   // sum_{k,l} <kl|ij> T[(k,a),(l,b)]
-                    for (int k = 0; k < o; ++k)
-                        for (int q = 0; q < o; ++q)
-                            h += Qx[((k * o + q) * o + i) * o + j] * Tx[(int64_t)(k * v + a) * np + q * v + b];
-                    const double rr = Rx[(int64_t)r * np + c] - Yx[(int64_t)(i * v + b) * np + j * v + a];
-                    const double rt = Rx[(int64_t)c * np + r] - Yx[(int64_t)(j * v + a) * np + i * v + b];
-                    Lx[(int64_t)r * np + c] = ((acc[u][w][t] + h) + rr) + rt;
-                }
-        }
-    }
-    (void)n;
+    for (int task = part * (kLccdThreads / 64) + wave; task < tasks; task += blocks_per_mono * (kLccdThreads / 64))
+        ladder_task<CT>(g, (task / ngroups) * kLadRT, (task % ngroups) * CT, lane);
 }
 
 }  // namespace
@@ -305,9 +364,14 @@ int lccd_ring_blocks(int max_np) {
     return b < 8 ? b : 8;
 }
 
+int lccd_ladder_ct(int max_o) {
+    const int nct = (max_o * max_o + 15) / 16;
+    return nct < kLadCT ? nct : kLadCT;
+}
+
 int lccd_ladder_blocks(int max_w_rows, int max_o) {
     const int nrt = max_w_rows / 16, ntr = (nrt + kLadRT - 1) / kLadRT;
-    const int nct = (max_o * max_o + 15) / 16, ng = (nct + kLadCT - 1) / kLadCT;
+    const int nct = (max_o * max_o + 15) / 16, ct = lccd_ladder_ct(max_o), ng = (nct + ct - 1) / ct;
     const int tasks = ntr * ng, per_block = kLccdThreads / 64;
     const int b = (tasks + per_block - 1) / per_block;
     return b < 64 ? b : 64;
@@ -317,16 +381,34 @@ void launch_lccd_ring(const MonoDesc* monos, int n_mono, int ring_blocks, const 
                       const double* T, const double* M, double* R12, double* Y, const Ctrl* ctrl, const ClState* cl,
                       hipStream_t s) {
     if (n_mono <= 0 || ring_blocks <= 0) return;
-    hipLaunchKernelGGL(lccd_ring_kernel, dim3(n_mono * ring_blocks), dim3(kLccdThreads), 0, s, monos, ring_blocks, K,
-                       J, T, M, R12, Y, ctrl, cl);
+    const int groups = (n_mono + kXcds - 1) / kXcds;
+    hipLaunchKernelGGL(lccd_ring_kernel, dim3(groups * kXcds * ring_blocks), dim3(kLccdThreads), 0, s, monos, n_mono,
+                       ring_blocks, K, J, T, M, R12, Y, ctrl, cl);
 }
 
-void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, int ladder_blocks, const double* W,
-                        const double* Q, const double* T, const double* R12, const double* Y, double* L,
-                        const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
+void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, int ladder_blocks, int ct,
+                        const double* W, const double* Q, const double* T, const double* R12, const double* Y,
+                        double* L, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
     if (n_mono <= 0 || ladder_blocks <= 0) return;
-    hipLaunchKernelGGL(lccd_ladder_kernel, dim3(n_mono * ladder_blocks), dim3(kLccdThreads), 0, s, monos, ld,
-                       ladder_blocks, W, Q, T, R12, Y, L, ctrl, cl);
+    const dim3 grid(((n_mono + kXcds - 1) / kXcds) * kXcds * ladder_blocks), block(kLccdThreads);
+    switch (ct) {
+        case 1:
+            hipLaunchKernelGGL(lccd_ladder_kernel<1>, grid, block, 0, s, monos, ld, n_mono, ladder_blocks, W, Q, T,
+                               R12, Y, L, ctrl, cl);
+            break;
+        case 2:
+            hipLaunchKernelGGL(lccd_ladder_kernel<2>, grid, block, 0, s, monos, ld, n_mono, ladder_blocks, W, Q, T,
+                               R12, Y, L, ctrl, cl);
+            break;
+        case 3:
+            hipLaunchKernelGGL(lccd_ladder_kernel<3>, grid, block, 0, s, monos, ld, n_mono, ladder_blocks, W, Q, T,
+                               R12, Y, L, ctrl, cl);
+            break;
+        default:
+            hipLaunchKernelGGL(lccd_ladder_kernel<4>, grid, block, 0, s, monos, ld, n_mono, ladder_blocks, W, Q, T,
+                               R12, Y, L, ctrl, cl);
+            break;
+    }
 }
 
 }  // namespace mcpt

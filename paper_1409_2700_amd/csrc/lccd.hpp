@@ -23,13 +23,14 @@ void launch_lccd_pack(const MonoDesc* monos, const LccdDesc* ld, int n_mono, con
                       const double* j_raw, double* W, double* J, hipStream_t s);
 int lccd_ring_blocks(int max_np);
 int lccd_ladder_blocks(int max_w_rows, int max_o);
+int lccd_ladder_ct(int max_o);   // column tiles per ladder task: ceil(max_o^2 / 16), at most 4
 // R12 = K M - J T and Y = J Vs(T) for every live monomer
 void launch_lccd_ring(const MonoDesc* monos, int n_mono, int ring_blocks, const double* K, const double* J,
                       const double* T, const double* M, double* R12, double* Y, const Ctrl* ctrl, const ClState* cl,
                       hipStream_t s);
 // L = P + H + R + R^T (R = R12 - Vs(Y)) for every live monomer
-void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, int ladder_blocks, const double* W,
-                        const double* Q, const double* T, const double* R12, const double* Y, double* L,
-                        const Ctrl* ctrl, const ClState* cl, hipStream_t s);
+void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, int ladder_blocks, int ct,
+                        const double* W, const double* Q, const double* T, const double* R12, const double* Y,
+                        double* L, const Ctrl* ctrl, const ClState* cl, hipStream_t s);
 
 }  // namespace mcpt
