@@ -420,6 +420,29 @@ def singles_cpu(prob, sweeps: int, sample_pairs: int = 4096) -> dict:
                       f"{prob.n_pair} pairs x {sweeps} sweeps ({solve_s:.0f} s per solve)"}
 
 
+def fd_mode(ctx, pid, prob, tol, step=0.01, with_singles=True):
+    """Finite-displacement workflow (Sec. IV.A): the four stretch modes of the
+    central 2 x 2 x 1 cell, five-point grid at 0.01 A, unit energy of Eq. 66
+    (E_M2 + E_M1 over the cell); 16 displaced geometries built on the device
+    from the resident crystal and solved from its converged amplitudes."""
+    from synth import central_cell, singles_source, stretch_modes
+    cell = central_cell(prob)
+    modes = stretch_modes(prob, cell, step_angstrom=step)
+    w = singles_source(prob) if with_singles else None
+    ctx.fd_stencil(pid, [(a, f) for _, a, f in modes[:1]], cell, step, w=w, tol=tol)   # warm-up
+    t0 = time.perf_counter()
+    res = ctx.fd_stencil(pid, [(a, f) for _, a, f in modes], cell, step, w=w, tol=tol)
+    secs = time.perf_counter() - t0
+    n_solves = 1 + 4 * len(modes)
+    out = {"seconds": secs, "geometries": n_solves, "geometries_per_s": n_solves / secs,
+           "step_angstrom": step, "tol": tol, "cell": [int(c) for c in cell], "singles": with_singles,
+           "modes": {n: {"d2e_Eh_per_A2": r["d2e"], "sweeps": r["sweeps"], "pairs_rescaled": int(len(a))}
+                     for (n, a, _), r in zip(modes, res)}}
+    log(f"[fd] {n_solves} geometries in {secs:.2f}s: " +
+        ", ".join(f"{n} {r['d2e']:.6f}" for (n, _, _), r in zip(modes, res)))
+    return out
+
+
 def lccd_mode(ctx, prob, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: bool = True):
     """Full monomer equation (Eq. 58 with its intramonomer terms; step 5 then
     step 6) on the same crystal with K and the (vv|vv), (oo|oo), (oo|vv)
@@ -516,6 +539,7 @@ def main():
     ap.add_argument("--pmc-lccd", action="store_true",
                     help="--pmc-pass runs two sweeps of step 5 and two of step 6 of the full monomer equation")
     ap.add_argument("--singles-steps", type=int, default=3, help="timed singles solves (0: skip)")
+    ap.add_argument("--fd", type=int, default=1, help="1: time the finite-displacement workflow (0: skip)")
     ap.add_argument("--lccd-steps", type=int, default=2,
                     help="timed solves of the full monomer equation (0: skip)")
     ap.add_argument("--batched", type=int, default=0,
@@ -556,6 +580,7 @@ def main():
     singles = None
     if args.singles_steps > 0:
         singles = singles_mode(ctx, pid, prob, args.singles_steps, 1, args.tol)
+    fd = fd_mode(ctx, pid, prob, 1e-12) if args.fd else None
     ctx.release(pid)
     lccd = None
     if args.lccd_steps > 0:
@@ -614,6 +639,8 @@ def main():
         out["singles"] = singles
     if lccd is not None:
         out["full_monomer_equation"] = lccd
+    if fd is not None:
+        out["finite_displacement"] = fd
     if served is not None:
         out["serving"] = served
     if args.batched > 0:
@@ -625,6 +652,9 @@ def main():
         log("[bench] timing the CPU oracle on a sample ...")
         out["cpu_baseline"] = cpu_baseline(prob, golden["sweeps"] if golden else h["sweeps"], args.cpu_budget)
         log(f"[bench] cpu_baseline {out['cpu_baseline']['value']:.3e} solves/s")
+        if fd is not None:
+            # the oracle's cost of the same geometries: each an FP64 solve at the cpu_baseline rate
+            fd["cpu_oracle_estimate_s"] = fd["geometries"] / out["cpu_baseline"]["value"]
         if singles is not None:
             singles["cpu_oracle"] = singles_cpu(prob, singles["sweeps"])
             log(f"[bench] singles cpu oracle {singles['cpu_oracle']['value']:.3e} solves/s")

@@ -293,6 +293,54 @@ typedef struct {
  * results) when step 5 diverges for any cluster. */
 mcpt_status mcpt_lccd_attach(mcpt_ctx *ctx, uint64_t id, const mcpt_lccd_integrals *ints);
 
+/* ---- Finite-displacement geometries (Sec. IV.A: harmonic frequencies from
+ * single points on a five-point grid, step 0.01 A in the paper) ----
+ * A displaced geometry keeps every monomer's energies and intra block and the
+ * undisplaced pair list; only the dimer couplings of the moved monomers
+ * change, V_XY -> (R0 / R)^3 V_XY for the caller's coupling model.  Both calls
+ * build displaced problems on the device from a resident base problem, with
+ * no host upload. */
+
+/* New resident problem *id: the resident problem `base` with the blocks of the
+ * listed pairs (indices into base's pair list, each at most once) multiplied
+ * by scale[k] (finite).  Arrays are read before the call returns.  The copy
+ * holds its own device memory (as much as the base's plain upload) until
+ * mcpt_release.  Errors: MCPT_ERR_INVALID (NULL array, index out of range or
+ * repeated), MCPT_ERR_NONFINITE, MCPT_ERR_ADMISSION, MCPT_ERR_NOMEM,
+ * MCPT_ERR_UNKNOWN_ID, MCPT_ERR_DEVICE. */
+mcpt_status mcpt_upload_scaled(mcpt_ctx *ctx, uint64_t base, int64_t n, const int64_t *pair, const double *scale,
+                               uint64_t *id);
+
+typedef struct {
+    int64_t        n_pair;   /* pairs whose blocks the displacement rescales */
+    const int64_t *pair;     /* [n_pair] indices into the base problem's pair list */
+    const double  *scale;    /* [4][n_pair] factors at the displacements -2h, -h, +h, +2h */
+} mcpt_fd_mode;
+
+typedef struct {
+    double  e[5];            /* unit energy at -2h, -h, 0, +h, +2h, Eh */
+    double  d2e;             /* (-e[4] + 16 e[3] - 30 e[2] + 16 e[1] - e[0]) / (12 step^2) */
+    int32_t sweeps[5];       /* doubles sweeps of each point */
+    int32_t status;          /* mcpt_status of the mode */
+    int32_t reserved;
+} mcpt_fd_result;
+
+/* Five-point second derivatives of the unit energy of Eq. 66 along
+ * displacement modes.  The unit energy of a geometry is the sum over the n_cell
+ * listed monomers of E_M2(X) (Eq. 54) and, when w is not NULL (host, the
+ * singles source of mcpt_singles), of E_M1(X) (Eq. 53); the E_SCF(X) of Eq. 66
+ * does not change with these displacements (monomer integrals are fixed) and
+ * is left out.  The base problem is solved first (opts; its results stay, as
+ * after mcpt_run); each displaced point is a scaled copy (mcpt_upload_scaled)
+ * solved from the base's converged amplitudes (warm start), then released.
+ * opts->warm_t must be NULL.  step is the displacement h (any length unit; d2e
+ * is per unit squared).  out[n_modes] receives the results.  Returns the first
+ * failing status (the message names mode and point); a base problem with
+ * intramonomer integrals attached is rejected (MCPT_ERR_INVALID). */
+mcpt_status mcpt_fd_stencil(mcpt_ctx *ctx, uint64_t base, int32_t n_modes, const mcpt_fd_mode *modes,
+                            int32_t n_cell, const int32_t *cell, double step, const double *w,
+                            const mcpt_options *opts, mcpt_fd_result *out);
+
 /* ---- Tile autotuner of the reduced-precision pair kernel ----
  * The kernel exists in several tile shapes: each wave computes sb x sb output
  * tiles of 16 x 16 per task, nw waves per workgroup, pd k chunks loaded ahead.  mcpt_autotune times one

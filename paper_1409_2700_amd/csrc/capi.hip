@@ -1050,9 +1050,9 @@ mcpt_status lccd_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_lccd_integ
         if (d.v > 64 || d.np > kLccdMaxNp)
             return fail(MCPT_ERR_INVALID, "monomer " + std::to_string(m) +
                                               ": the full monomer equation supports v <= 64 and o v <= 1024");
-        const int v2 = d.v * d.v, rows = round_up(v2, 16);
-        ld[m] = LccdDesc{w_pack, nw, nq, rows, rows};
-        w_pack += (int64_t)rows * rows;
+        const int v2 = d.v * d.v, rows = round_up(v2, 16), cols = round_up(v2, 32);
+        ld[m] = LccdDesc{w_pack, nw, nq, rows, cols};
+        w_pack += (int64_t)rows * cols;
         nw += (int64_t)v2 * v2;
         nq += (int64_t)d.o * d.o * d.o * d.o;
         max_rows = std::max(max_rows, rows);
@@ -1164,6 +1164,218 @@ mcpt_status lccd_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_lccd_integ
     R->lccd_w_flops = fl;
     R->lccd = true;
     R->has_result = false;
+    return MCPT_OK;
+}
+
+// A new resident problem that is the resident problem B with the blocks of the
+// listed pairs (caller indices) multiplied by their factors: a displaced
+// geometry whose couplings are rescaled (Sec. IV.A), made on the device from
+// B's packed inputs without a host upload.
+mcpt_status clone_scaled(mcpt_ctx* c, Exec& x, Resident* B, int64_t n, const int64_t* pair, const double* scale,
+                         uint64_t* id_out) {
+    if (!id_out) return fail(MCPT_ERR_INVALID, "id is NULL");
+    if (n < 0 || (n > 0 && (!pair || !scale))) return fail(MCPT_ERR_INVALID, "pair or scale is NULL");
+    mcpt_status st;
+    if ((st = ensure_device(c)) != MCPT_OK) return st;
+    std::vector<int64_t> where(B->n_pair, -1);
+    for (int64_t q = 0; q < B->n_pair; ++q) where[B->pairs[q].orig] = q;
+    std::vector<int64_t> off(n), len(n);
+    std::unordered_set<int64_t> seen;
+    for (int64_t k = 0; k < n; ++k) {
+        if (pair[k] < 0 || pair[k] >= B->n_pair)
+            return fail(MCPT_ERR_INVALID, "pair index " + std::to_string(pair[k]) + " out of range");
+        if (!seen.insert(pair[k]).second)
+            return fail(MCPT_ERR_INVALID, "pair " + std::to_string(pair[k]) + " listed twice");
+        if (!std::isfinite(scale[k])) return fail(MCPT_ERR_NONFINITE, "non-finite scale factor");
+        const PairDesc& d = B->pairs[where[pair[k]]];
+        off[k] = d.v_off;
+        len[k] = (int64_t)B->monos[d.x].n * B->monos[d.y].n;
+    }
+    auto rnd = [](int64_t bytes) { return (size_t)((std::max<int64_t>(bytes, 1) + 255) / 256 * 256); };
+    const size_t need = rnd(sizeof(MonoDesc) * (int64_t)B->n_mono) + rnd(sizeof(PairDesc) * B->n_pair) +
+                        rnd(8 * B->dif_elems) + rnd(8 * B->raw_elems) + 5 * rnd(8 * B->mat_elems) +
+                        rnd(8 * B->v_elems) + 3 * rnd(8 * (int64_t)B->n_mono) + rnd(8 * B->n_pair) +
+                        rnd((int64_t)sizeof(ClState) * B->n_cl) + rnd(8 * (int64_t)B->n_cl * kMaxSweeps) +
+                        2 * rnd(8 * (int64_t)(B->n_cl + 1)) + 3 * rnd(8 * n);
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        if (c->in_use + (c->reserved - x.reserved) + need > c->budget)
+            return fail(MCPT_ERR_ADMISSION, "displaced copy needs " + std::to_string(need) + " bytes beyond the budget");
+    }
+    auto r = std::make_unique<Resident>();
+    Resident* R = r.get();
+    R->n_mono = B->n_mono;
+    R->n_pair = B->n_pair;
+    R->max_n = B->max_n;
+    R->max_np = B->max_np;
+    R->max_v = B->max_v;
+    R->eps_elems = B->eps_elems;
+    R->dif_elems = B->dif_elems;
+    R->raw_elems = B->raw_elems;
+    R->mat_elems = B->mat_elems;
+    R->v_elems = B->v_elems;
+    R->max_slot = B->max_slot;
+    R->monos = B->monos;
+    R->pairs = B->pairs;
+    R->n_lds = B->n_lds;
+    R->n_cl = B->n_cl;
+    R->cl_mono = B->cl_mono;
+    R->cl_pair = B->cl_pair;
+    R->cl_bad = B->cl_bad;
+    R->cl_last.assign(R->n_cl, mcpt_summary{});
+#define ALLOC(ptr, cnt)                                          \
+    do {                                                         \
+        if ((st = dev_alloc(c, R, &(ptr), (cnt))) != MCPT_OK) { \
+            free_resident(c, R);                                 \
+            return st;                                           \
+        }                                                        \
+    } while (0)
+    int64_t *d_off = nullptr, *d_len = nullptr;
+    double* d_f = nullptr;
+    ALLOC(R->d_monos, R->n_mono);
+    ALLOC(R->d_pairs, std::max<int64_t>(R->n_pair, 1));
+    ALLOC(R->d_dif, R->dif_elems);
+    ALLOC(R->d_raw, R->raw_elems);
+    ALLOC(R->d_K, R->mat_elems);
+    ALLOC(R->d_T, R->mat_elems);
+    ALLOC(R->d_M, R->mat_elems);
+    ALLOC(R->d_G[0], R->mat_elems);
+    ALLOC(R->d_G[1], R->mat_elems);
+    ALLOC(R->d_V, std::max<int64_t>(R->v_elems, 1));
+    ALLOC(R->d_em2, R->n_mono);
+    ALLOC(R->d_em2_0, R->n_mono);
+    ALLOC(R->d_res, R->n_mono);
+    ALLOC(R->d_ed2, std::max<int64_t>(R->n_pair, 1));
+    ALLOC(R->d_cl, R->n_cl);
+    ALLOC(R->d_hist, (int64_t)R->n_cl * kMaxSweeps);
+    ALLOC(R->d_cl_mono, R->n_cl + 1);
+    ALLOC(R->d_cl_pair, R->n_cl + 1);
+    ALLOC(d_off, std::max<int64_t>(n, 1));
+    ALLOC(d_len, std::max<int64_t>(n, 1));
+    ALLOC(d_f, std::max<int64_t>(n, 1));
+#undef ALLOC
+    hipStream_t s = x.stream;
+    const hipMemcpyKind dd = hipMemcpyDeviceToDevice;
+    auto copy = [&](void* dst, const void* src, int64_t bytes) {
+        return bytes > 0 ? hipMemcpyAsync(dst, src, bytes, dd, s) : hipSuccess;
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = copy(R->d_monos, B->d_monos, sizeof(MonoDesc) * (int64_t)R->n_mono);
+    if (e == hipSuccess) e = copy(R->d_pairs, B->d_pairs, sizeof(PairDesc) * R->n_pair);
+    if (e == hipSuccess) e = copy(R->d_dif, B->d_dif, 8 * R->dif_elems);
+    if (e == hipSuccess) e = copy(R->d_K, B->d_K, 8 * R->mat_elems);
+    if (e == hipSuccess) e = copy(R->d_V, B->d_V, 8 * R->v_elems);
+    if (e == hipSuccess) e = copy(R->d_cl_mono, B->d_cl_mono, 8 * (int64_t)(R->n_cl + 1));
+    if (e == hipSuccess) e = copy(R->d_cl_pair, B->d_cl_pair, 8 * (int64_t)(R->n_cl + 1));
+    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(d_off, off.data(), 8 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(d_len, len.data(), 8 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(d_f, scale, 8 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        launch_scale_blocks(d_off, d_len, d_f, n, R->d_V, s);
+        launch_fill(R->d_T, R->mat_elems, 0.0, s);
+        launch_fill(R->d_M, R->mat_elems, 0.0, s);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        free_resident(c, R);
+        return fail(MCPT_ERR_DEVICE, std::string("displaced copy: ") + hipGetErrorString(e));
+    }
+    std::lock_guard<std::mutex> g(c->mu);
+    r->id = c->next_id++;
+    *id_out = r->id;
+    c->res[r->id] = std::move(r);
+    return MCPT_OK;
+}
+
+// Unit energy of Eq. 66 over the listed monomers from the last results of R:
+// E_M2 (Eq. 54) and, after a singles solve, E_M1 (Eq. 53).
+mcpt_status unit_energy(Exec& x, Resident* R, int32_t n_cell, const int32_t* cell, bool with_singles, double* e) {
+    std::vector<double> a(R->n_mono), b;
+    HIP_TRY(hipMemcpyAsync(a.data(), R->d_em2, 8 * (int64_t)R->n_mono, hipMemcpyDeviceToHost, x.stream));
+    if (with_singles) {
+        b.resize(R->n_mono);
+        HIP_TRY(hipMemcpyAsync(b.data(), R->d_em1, 8 * (int64_t)R->n_mono, hipMemcpyDeviceToHost, x.stream));
+    }
+    HIP_TRY(hipStreamSynchronize(x.stream));
+    double sum = 0.0;
+    for (int32_t k = 0; k < n_cell; ++k) {
+        sum += a[cell[k]];
+        if (with_singles) sum += b[cell[k]];
+    }
+    *e = sum;
+    return MCPT_OK;
+}
+
+// Five-point finite-difference second derivatives of the unit energy along
+// displacement modes (Sec. IV.A): the base geometry and, per mode, the four
+// displaced geometries -2h, -h, +h, +2h as rescaled copies of the base, each
+// solved from the base's converged amplitudes.
+mcpt_status fd_stencil(mcpt_ctx* c, Exec& x, Resident* B, int32_t n_modes, const mcpt_fd_mode* modes, int32_t n_cell,
+                       const int32_t* cell, double step, const double* w, const mcpt_options* o,
+                       mcpt_fd_result* out) {
+    if (n_modes < 1 || !modes || !out) return fail(MCPT_ERR_INVALID, "need at least one mode and an output array");
+    if (n_cell < 1 || !cell) return fail(MCPT_ERR_INVALID, "need at least one unit-cell monomer");
+    if (!(step > 0.0) || !std::isfinite(step)) return fail(MCPT_ERR_INVALID, "step must be positive");
+    for (int32_t k = 0; k < n_cell; ++k)
+        if (cell[k] < 0 || cell[k] >= B->n_mono) return fail(MCPT_ERR_INVALID, "unit-cell monomer out of range");
+    if (B->lccd) return fail(MCPT_ERR_INVALID, "finite differences run on problems without intramonomer integrals");
+    mcpt_status st = validate_options(o);
+    if (st != MCPT_OK) return st;
+    if (o->warm_t) return fail(MCPT_ERR_INVALID, "warm_t is set by the finite-difference driver");
+    const bool sg = w != nullptr;
+    const auto point = [&](Resident* R, const mcpt_options* oo, double* e, int32_t* sweeps) -> mcpt_status {
+        mcpt_summary sm{};
+        mcpt_status r = run(c, x, R, oo, &sm);
+        if (r != MCPT_OK) return r;
+        *sweeps = sm.sweeps;
+        if (sg) {
+            mcpt_options os = *oo;
+            os.warm_t = nullptr;
+            os.precision = MCPT_FP64;
+            os.deterministic = 0;
+            mcpt_singles_summary ss{};
+            if ((r = singles(c, x, R, w, MCPT_HOST, &os, &ss)) != MCPT_OK) return r;
+        }
+        return unit_energy(x, R, n_cell, cell, sg, e);
+    };
+    double e0 = 0.0;
+    int32_t sw0 = 0;
+    if ((st = point(B, o, &e0, &sw0)) != MCPT_OK) return st;
+    std::vector<double> t0(B->raw_elems);
+    if ((st = slice_results(c, x, B, -1, nullptr, nullptr, nullptr, t0.data())) != MCPT_OK) return st;
+    mcpt_options ow = *o;
+    ow.warm_t = t0.data();
+    for (int32_t m = 0; m < n_modes; ++m) {
+        mcpt_fd_result& r = out[m];
+        r = mcpt_fd_result{};
+        r.e[2] = e0;
+        r.sweeps[2] = sw0;
+        static const int slot[4] = {0, 1, 3, 4};   // -2h, -h, +h, +2h
+        for (int k = 0; k < 4; ++k) {
+            uint64_t id = 0;
+            if ((st = clone_scaled(c, x, B, modes[m].n_pair, modes[m].pair,
+                                   modes[m].scale ? modes[m].scale + (int64_t)k * modes[m].n_pair : nullptr, &id)) !=
+                MCPT_OK)
+                return st;
+            Resident* R = nullptr;
+            {
+                std::lock_guard<std::mutex> g(c->mu);
+                R = c->res[id].get();
+            }
+            st = point(R, &ow, &r.e[slot[k]], &r.sweeps[slot[k]]);
+            const std::string msg = last_error_text();
+            (void)hipStreamSynchronize(x.stream);
+            release_resident(c, id);
+            if (st != MCPT_OK) {
+                r.status = st;
+                return fail(st, "mode " + std::to_string(m) + ", point " + std::to_string(k) + ": " + msg);
+            }
+        }
+        r.d2e = (-r.e[4] + 16.0 * r.e[3] - 30.0 * r.e[2] + 16.0 * r.e[1] - r.e[0]) / (12.0 * step * step);
+        r.status = MCPT_OK;
+    }
+    g_err.clear();
     return MCPT_OK;
 }
 
@@ -1695,6 +1907,31 @@ mcpt_status mcpt_release(mcpt_ctx* c, uint64_t id) {
     (void)hipStreamSynchronize(c->main.stream);
     release_resident(c, id);
     return MCPT_OK;
+}
+
+mcpt_status mcpt_upload_scaled(mcpt_ctx* c, uint64_t base, int64_t n, const int64_t* pair, const double* scale,
+                               uint64_t* id) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    Resident* B = find_resident(c, base);
+    if (!B) return unknown(base);
+    try {
+        return clone_scaled(c, c->main, B, n, pair, scale, id);
+    } catch (const std::exception& e) {
+        return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
+    }
+}
+
+mcpt_status mcpt_fd_stencil(mcpt_ctx* c, uint64_t base, int32_t n_modes, const mcpt_fd_mode* modes, int32_t n_cell,
+                            const int32_t* cell, double step, const double* w, const mcpt_options* opts,
+                            mcpt_fd_result* out) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    Resident* B = find_resident(c, base);
+    if (!B) return unknown(base);
+    try {
+        return fd_stencil(c, c->main, B, n_modes, modes, n_cell, cell, step, w, opts, out);
+    } catch (const std::exception& e) {
+        return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
+    }
 }
 
 mcpt_status mcpt_lccd_attach(mcpt_ctx* c, uint64_t id, const mcpt_lccd_integrals* ints) {

@@ -46,6 +46,15 @@ __global__ void nonfinite_kernel(const double* __restrict__ p, int64_t n, int32_
     if (bad) *flag = 1;
 }
 
+// V blocks of listed pairs multiplied by their factors (finite-displacement
+// geometries: couplings rescaled by (R0 / R)^3); block b covers pair b.
+__global__ void scale_blocks_kernel(const int64_t* __restrict__ off, const int64_t* __restrict__ len,
+                                    const double* __restrict__ f, double* __restrict__ V) {
+    const int64_t o = off[blockIdx.x], n = len[blockIdx.x];
+    const double s = f[blockIdx.x];
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) V[o + i] *= s;
+}
+
 template <int NT>
 __device__ double block_sum(double x, double* sh) {
     sh[threadIdx.x] = x;
@@ -489,6 +498,12 @@ void launch_unpack(const MonoDesc* monos, int n_mono, const double* packed, doub
                    hipStream_t s) {
     const int gy = (max_n * max_n + 255) / 256 > 64 ? 64 : (max_n * max_n + 255) / 256;
     hipLaunchKernelGGL(pack_kernel, dim3(n_mono, gy), dim3(256), 0, s, monos, packed, raw, 0);
+}
+
+void launch_scale_blocks(const int64_t* off, const int64_t* len, const double* f, int64_t n, double* V,
+                         hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(scale_blocks_kernel, dim3((unsigned)n), dim3(256), 0, s, off, len, f, V);
 }
 
 void launch_nonfinite(const double* p, int64_t n, int32_t* flag, hipStream_t s) {

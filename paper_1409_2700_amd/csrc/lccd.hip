@@ -53,8 +53,8 @@ __device__ inline int acc_row(int lane, int t) { return (lane >> 4) + 4 * t; }
 // ---------------------------------------------------------------------------
 // packing
 // ---------------------------------------------------------------------------
-// W_X (v^2 x v^2, caller layout) -> rows of ldw doubles, rows and columns
-// zero-padded to multiples of 16; J_X[i][j][a][b] = <ia|jb> -> J-hat[(i,a),(j,b)]
+// W_X (v^2 x v^2, caller layout) -> w_rows rows of ldw doubles, zero-padded
+// (rows to a multiple of 16, columns to a multiple of 32); J_X[i][j][a][b] = <ia|jb> -> J-hat[(i,a),(j,b)]
 // = J_X[j][i][a][b] in the np x np monomer layout.  A null source skips its part.
 __global__ void lccd_pack_kernel(const MonoDesc* __restrict__ monos, const LccdDesc* __restrict__ ld,
                                  const double* __restrict__ w_raw, const double* __restrict__ j_raw,
@@ -225,47 +225,68 @@ __device__ void ladder_task(const LadderView& g, int tr0, int tc0, int lane) {
     for (int u = 0; u < kLadRT; ++u)
 #pragma unroll
         for (int w = 0; w < CT; ++w) acc[u][w] = d4(0.0);
-    // particle-particle ladder: W streamed once; the next k chunk of both
-    // operands (W rows and the gathered amplitude columns) in flight
-    d4 an[kLadRT];
-    double bn[CT][4];
+    // particle-particle ladder: W streamed once with two k chunks in flight
+    // (p0 / p1 hold the even / odd chunks), the gathered amplitude columns of
+    // the next chunk in flight from L2.  Loads past the last chunk are
+    // redirected to chunk 0 (in bounds, values unused) instead of branched
+    // around, so the memory counters are waited on in issue order: the gathers
+    // of a chunk are issued before the W rows two chunks ahead, and waiting for
+    // them leaves those W loads in flight.
+    d4 p0[kLadRT], p1[kLadRT];
+    double bn[CT][4], b[CT][4];
+    const double* wrow[kLadRT];
 #pragma unroll
-    for (int u = 0; u < kLadRT; ++u) an[u] = load4(g.W + (int64_t)arow[u] * g.ldw + lk);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int ko = g.kofs[lk + s];
-#pragma unroll
-        for (int w = 0; w < CT; ++w) bn[w][s] = g.T[ko + bbase[w]];
+    for (int u = 0; u < kLadRT; ++u) {
+        wrow[u] = g.W + (int64_t)arow[u] * g.ldw + lk;
+        p0[u] = load4(wrow[u]);
+        p1[u] = load4(wrow[u] + (16 < g.ldw ? 16 : 0));
     }
-    for (int k0 = 0; k0 < g.ldw; k0 += 16) {
-        double a[kLadRT][4], b[CT][4];
+    auto gather = [&](int k0) {
+        const int kb = k0 < g.ldw ? k0 : 0;
 #pragma unroll
-        for (int u = 0; u < kLadRT; ++u) {
-            a[u][0] = an[u].x;
-            a[u][1] = an[u].y;
-            a[u][2] = an[u].z;
-            a[u][3] = an[u].w;
+        for (int s = 0; s < 4; ++s) {
+            const int ko = g.kofs[kb + lk + s];
+#pragma unroll
+            for (int w = 0; w < CT; ++w) bn[w][s] = g.T[ko + bbase[w]];
         }
-#pragma unroll
-        for (int w = 0; w < CT; ++w)
-#pragma unroll
-            for (int s = 0; s < 4; ++s) b[w][s] = bn[w][s];
-        if (k0 + 16 < g.ldw) {
-#pragma unroll
-            for (int u = 0; u < kLadRT; ++u) an[u] = load4(g.W + (int64_t)arow[u] * g.ldw + k0 + 16 + lk);
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int ko = g.kofs[k0 + 16 + lk + s];
-#pragma unroll
-                for (int w = 0; w < CT; ++w) bn[w][s] = g.T[ko + bbase[w]];
-            }
-        }
+    };
+    auto block = [&](const d4 (&pa)[kLadRT]) {
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
             for (int u = 0; u < kLadRT; ++u)
 #pragma unroll
-                for (int w = 0; w < CT; ++w) acc[u][w] = mfma(a[u][s], b[w][s], acc[u][w]);
+                for (int w = 0; w < CT; ++w) acc[u][w] = mfma(pa[u][s], b[w][s], acc[u][w]);
+    };
+    gather(0);
+    // ldw is a multiple of 32: chunks come in (even, odd) pairs.  Scheduling
+    // barriers keep the issue order (gathers, MFMA block, W prefetch) so the
+    // prefetched rows stay in flight across a whole MFMA block.
+    for (int k0 = 0; k0 < g.ldw; k0 += 32) {
+#pragma unroll
+        for (int w = 0; w < CT; ++w)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) b[w][s] = bn[w][s];
+        gather(k0 + 16);
+        __builtin_amdgcn_sched_barrier(0);
+        block(p0);
+        __builtin_amdgcn_sched_barrier(0);
+        const int n0 = k0 + 32 < g.ldw ? k0 + 32 : 0;
+#pragma unroll
+        for (int u = 0; u < kLadRT; ++u) p0[u] = load4(wrow[u] + n0);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int w = 0; w < CT; ++w)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) b[w][s] = bn[w][s];
+        gather(k0 + 32);
+        __builtin_amdgcn_sched_barrier(0);
+        block(p1);
+        __builtin_amdgcn_sched_barrier(0);
+        const int n1 = k0 + 48 < g.ldw ? k0 + 48 : 0;
+#pragma unroll
+        for (int u = 0; u < kLadRT; ++u) p1[u] = load4(wrow[u] + n1);
+        __builtin_amdgcn_sched_barrier(0);
     }
     // hole-hole ladder on the same accumulators: k runs over the o^2 hole pairs (k,l)
     for (int k0 = 0; k0 < g.o2; k0 += 16) {

@@ -9,14 +9,14 @@ namespace mcpt {
 constexpr int kLccdMaxNp = 1024;     // padded o v of a monomer the ring kernel's offset table holds
 constexpr int kLccdMaxLdw = 4096;    // padded v^2 the ladder kernel's offset table holds (v <= 64)
 
-// Per monomer: where its packed integral matrix W (w_rows x ldw, rows (a,b),
-// columns (c,d), both zero-padded to 16) and its raw <kl|ij> block sit.
+// Per monomer: where its packed integral matrix W (w_rows x ldw, rows (a,b)
+// zero-padded to 16, columns (c,d) to 32) and its raw <kl|ij> block sit.
 struct LccdDesc {
     int64_t w_off;       // first element of the packed W in the device buffer
     int64_t w_raw_off;   // first element of W_X in the caller's concatenated layout
     int64_t q_off;       // first element of Q_X (o^4, caller layout) in the device buffer
     int32_t w_rows;      // v^2 rounded up to 16
-    int32_t ldw;         // v^2 rounded up to 16
+    int32_t ldw;         // v^2 rounded up to 32
 };
 
 void launch_lccd_pack(const MonoDesc* monos, const LccdDesc* ld, int n_mono, const double* w_raw,

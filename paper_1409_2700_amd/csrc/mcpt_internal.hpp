@@ -106,6 +106,9 @@ void launch_pack(const MonoDesc* monos, int n_mono, const double* raw, double* p
 void launch_unpack(const MonoDesc* monos, int n_mono, const double* packed, double* raw,
                    int max_n, hipStream_t s);
 void launch_nonfinite(const double* p, int64_t n, int32_t* flag, hipStream_t s);
+// V[off[b] .. off[b] + len[b]) *= f[b] for b < n
+void launch_scale_blocks(const int64_t* off, const int64_t* len, const double* f, int64_t n, double* V,
+                         hipStream_t s);
 void launch_monomer(int mode, const MonoDesc* monos, int n_mono, int max_v, const double* dif,
                     const double* K, const double* G, double* G_zero, double* T, double* M,
                     double* em2, double* em2_0, double* res, const Ctrl* ctrl, const ClState* cl,

@@ -40,7 +40,7 @@ EXPORTS = [
     "mcpt_upload_batch", "mcpt_solve_batch", "mcpt_cluster_results",
     "mcpt_serve_config", "mcpt_submit", "mcpt_poll", "mcpt_wait", "mcpt_serve_stats",
     "mcpt_autotune", "mcpt_tune_export", "mcpt_tune_import", "mcpt_singles", "mcpt_singles_result",
-    "mcpt_lccd_attach",
+    "mcpt_lccd_attach", "mcpt_upload_scaled", "mcpt_fd_stencil",
 ]
 
 
@@ -88,6 +88,18 @@ class mcpt_timing(C.Structure):
 
 class mcpt_lccd_integrals(C.Structure):
     _fields_ = [("w_vvvv", C.c_void_p), ("q_oooo", C.c_void_p), ("j_oovv", C.c_void_p), ("memory", C.c_int32)]
+
+
+class mcpt_fd_mode(C.Structure):
+    _fields_ = [("n_pair", C.c_int64), ("pair", C.c_void_p), ("scale", C.c_void_p)]
+
+
+class mcpt_fd_result(C.Structure):
+    _fields_ = [("e", C.c_double * 5), ("d2e", C.c_double), ("sweeps", C.c_int32 * 5), ("status", C.c_int32),
+                ("reserved", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {"e": list(self.e), "d2e": self.d2e, "sweeps": list(self.sweeps), "status": self.status}
 
 
 class mcpt_singles_summary(C.Structure):
@@ -157,6 +169,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                  C.POINTER(mcpt_singles_summary)]
     lib.mcpt_singles_result.argtypes = [P, C.c_uint64, P, P]
     lib.mcpt_lccd_attach.argtypes = [P, C.c_uint64, C.POINTER(mcpt_lccd_integrals)]
+    lib.mcpt_upload_scaled.argtypes = [P, C.c_uint64, C.c_int64, P, P, C.POINTER(C.c_uint64)]
+    lib.mcpt_fd_stencil.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(mcpt_fd_mode), C.c_int32, P, C.c_double, P,
+                                    C.POINTER(mcpt_options), C.POINTER(mcpt_fd_result)]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if name not in ("mcpt_destroy", "mcpt_last_error"):
@@ -369,6 +384,36 @@ class Context:
         j = np.ascontiguousarray(ints.j, dtype=np.float64)
         li = mcpt_lccd_integrals(_ptr(w), _ptr(q), _ptr(j), MCPT_HOST)
         _check(lib().mcpt_lccd_attach(self.h, pid, C.byref(li)))
+
+    # ---- finite-displacement geometries (mcpt_upload_scaled / mcpt_fd_stencil) ----
+    def upload_scaled(self, base: int, pairs, scale) -> int:
+        """Resident copy of `base` with the listed pair blocks scaled."""
+        pa = np.ascontiguousarray(pairs, dtype=np.int64)
+        sa = np.ascontiguousarray(scale, dtype=np.float64)
+        pid = C.c_uint64()
+        _check(lib().mcpt_upload_scaled(self.h, base, len(pa), _ptr(pa), _ptr(sa), C.byref(pid)))
+        self._sizes[pid.value] = self._sizes[base]
+        if base in self._clusters:
+            self._clusters[pid.value] = self._clusters[base]
+        return pid.value
+
+    def fd_stencil(self, base: int, modes, cell, step: float, w=None, **opts) -> list:
+        """modes: list of (pair indices, scale array [4][n]) for -2h, -h, +h, +2h;
+        cell: unit-cell monomer indices.  Returns one result dict per mode."""
+        keep = []
+        arr = (mcpt_fd_mode * len(modes))()
+        for m, (pairs, scale) in enumerate(modes):
+            pa = np.ascontiguousarray(pairs, dtype=np.int64)
+            sa = np.ascontiguousarray(scale, dtype=np.float64).reshape(4, len(pa))
+            keep += [pa, sa]
+            arr[m] = mcpt_fd_mode(len(pa), _ptr(pa), _ptr(sa))
+        ca = np.ascontiguousarray(cell, dtype=np.int32)
+        wa = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+        o = make_options(**opts)
+        res = (mcpt_fd_result * len(modes))()
+        _check(lib().mcpt_fd_stencil(self.h, base, len(modes), arr, len(ca), _ptr(ca), float(step), _ptr(wa),
+                                     C.byref(o), res))
+        return [r.as_dict() for r in res]
 
     def release(self, pid: int):
         _check(lib().mcpt_release(self.h, pid))

@@ -502,3 +502,68 @@ def make_lccd_workload(name: str, coupling_scale: float = DEFAULT_COUPLING_SCALE
     at SIGMA_LCCD.  Returns (problem, integrals)."""
     p = make_workload(name, coupling_scale=coupling_scale, k_scale=LCCD_K_SCALE, **kw)
     return p, lccd_integrals(p)
+
+
+# ---------------------------------------------------------------------------
+# finite-displacement modes (Sec. IV.A: symmetric stretches of the molecules of
+# a unit cell, five-point grid)
+# ---------------------------------------------------------------------------
+# sign patterns of the four cell molecules for the four stretch modes, in the
+# spirit of S(Ag), S(B3u), S(B2u), S(B1g) of the orthorhombic cell
+STRETCH_PATTERNS = {"Ag": (1, 1, 1, 1), "B3u": (1, -1, 1, -1), "B2u": (1, 1, -1, -1), "B1g": (1, -1, -1, 1)}
+
+
+def central_cell(prob: Problem) -> np.ndarray:
+    """Indices of the 2 x 2 x 1 block of monomers nearest the centre of the
+    problem's lattice (the 'unit cell' whose energy is differentiated)."""
+    sites = np.asarray(prob.sites, dtype=np.int64)
+    lo = np.floor((sites.max(axis=0) - 1) / 2.0).astype(np.int64)
+    want = [tuple(lo + np.array(d)) for d in ((0, 0, 0), (0, 1, 0), (1, 0, 0), (1, 1, 0))]
+    index = {tuple(s): k for k, s in enumerate(sites)}
+    return np.array([index[w] for w in want], dtype=np.int32)
+
+
+def displacement_scales(prob: Problem, shifts: dict, points=(-2, -1, 1, 2), step_angstrom: float = 0.01):
+    """Coupling factors (R0 / R)^3 of every pair that a displacement changes.
+
+    shifts: monomer index -> unit direction (3-vector); at grid point s the
+    monomer moves by s * step along it.  Returns (pair indices, factors
+    [len(points)][n]) for the pairs with at least one moved monomer (the pair
+    list of the undisplaced lattice is kept)."""
+    pos = np.asarray(prob.sites, dtype=np.float64) * SPACING_A
+    moved = np.zeros(prob.n_mono, dtype=bool)
+    u = np.zeros((prob.n_mono, 3))
+    for x, d in shifts.items():
+        moved[int(x)] = True
+        u[int(x)] = np.asarray(d, dtype=np.float64)
+    idx = np.flatnonzero(moved[prob.pairs[:, 0]] | moved[prob.pairs[:, 1]]) if prob.n_pair else np.zeros(0, int)
+    x, y = prob.pairs[idx, 0], prob.pairs[idx, 1]
+    r0 = np.linalg.norm(pos[x] - pos[y], axis=1)
+    out = np.empty((len(points), len(idx)))
+    for k, s in enumerate(points):
+        d = (pos[x] + s * step_angstrom * u[x]) - (pos[y] + s * step_angstrom * u[y])
+        out[k] = (r0 / np.linalg.norm(d, axis=1)) ** 3
+    return idx.astype(np.int64), out
+
+
+def stretch_modes(prob: Problem, cell=None, axis: int = 0, step_angstrom: float = 0.01):
+    """The four stretch modes of the cell: each cell monomer moved along `axis`
+    with the sign of its pattern.  Returns [(name, pairs, factors[4][n])] for
+    the grid points -2h, -h, +h, +2h."""
+    cell = central_cell(prob) if cell is None else np.asarray(cell)
+    e = np.zeros(3)
+    e[axis] = 1.0
+    modes = []
+    for name, signs in STRETCH_PATTERNS.items():
+        shifts = {int(c): sgn * e for c, sgn in zip(cell, signs)}
+        pairs, f = displacement_scales(prob, shifts, step_angstrom=step_angstrom)
+        modes.append((name, pairs, f))
+    return modes
+
+
+def scaled_problem(prob: Problem, pairs, factors) -> Problem:
+    """A copy of prob with the blocks of the listed pairs multiplied by factors."""
+    v = prob.v.copy()
+    for p, f in zip(pairs, factors):
+        v[prob.v_off[p]:prob.v_off[p + 1]] *= f
+    return Problem(prob.n_occ, prob.n_vir, prob.eps, prob.k, prob.pairs, v, prob.sites, dict(prob.meta))
