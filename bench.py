@@ -463,7 +463,8 @@ def lccd_mode(ctx, prob, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: 
     attach_s = time.time() - t0
     gpath = os.path.join(ROOT, "tests", "golden", f"lccd-{prob.meta.get('name', '')}.json")
     golden = json.load(open(gpath)) if os.path.exists(gpath) else None
-    opts = dict(tol=tol, max_sweeps=400, check_every=4)
+    # check_every = 1: no sweep is issued past convergence, so every timed ladder launch does full work
+    opts = dict(tol=tol, max_sweeps=400, check_every=1)
     for _ in range(warmup):
         ctx.run(pid, **opts)
     ctx.set_timing(True)

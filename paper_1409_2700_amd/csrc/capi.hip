@@ -1158,6 +1158,11 @@ mcpt_status lccd_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_lccd_integ
     R->lccd_ring_blocks = lccd_ring_blocks(max_np);
     R->lccd_ladder_blocks = lccd_ladder_blocks(max_rows, max_o);
     R->lccd_ct = lccd_ladder_ct(max_o);
+    // the LDS-staged ladder when every monomer's amplitudes fit one workgroup's LDS
+    R->lccd_lds_bytes = 0;
+    for (int m = 0; m < R->n_mono; ++m)
+        R->lccd_lds_bytes = std::max(R->lccd_lds_bytes, lccd_ladder_lds_bytes(R->monos[m].n, ld[m].ldw));
+    if (R->lccd_lds_bytes > lccd_lds_limit() || R->lccd_ct > 3) R->lccd_lds_bytes = 0;
     R->lccd_w_bytes = 8.0 * (double)w_pack;
     double fl = 0.0;
     for (const MonoDesc& d : R->monos) fl += 2.0 * (double)d.o * d.o * (double)d.v * d.v * (double)d.v * d.v;
@@ -1433,8 +1438,8 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
                          ctrl, R->d_cl, s);
         record_end(x, a, 4, 0.0, 0.0);
         record_begin(x, &a);
-        launch_lccd_ladder(R->d_monos, R->d_lccd, R->n_mono, R->lccd_ladder_blocks, R->lccd_ct, R->d_W, R->d_Q, R->d_T,
-                           R->d_R12, R->d_Y, R->d_L, ctrl, R->d_cl, s);
+        launch_lccd_ladder(R->d_monos, R->d_lccd, R->n_mono, R->lccd_ladder_blocks, R->lccd_ct, R->lccd_lds_bytes,
+                           R->d_W, R->d_Q, R->d_T, R->d_R12, R->d_Y, R->d_L, ctrl, R->d_cl, s);
         record_end(x, a, 5, R->lccd_w_flops, R->lccd_w_bytes);
     };
     std::vector<int32_t> iso_sweeps(R->n_cl, 0);

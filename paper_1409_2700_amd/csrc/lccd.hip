@@ -39,6 +39,7 @@ constexpr int kRingSB = 3;          // ring super-block edge in tiles
 constexpr int kLadRT = 4;           // ladder row tiles per wave task
 constexpr int kLadCT = 4;           // ladder column tiles per task at most (the launch takes ceil(o^2 / 16))
 constexpr int kXcds = 8;            // XCDs of the chip; workgroup b runs on XCD b % 8
+constexpr int kLadLdsThreads = 512; // LDS-staged ladder: eight wavefronts, one workgroup per CU
 
 __device__ inline d4 mfma(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -193,54 +194,55 @@ struct LadderView {
     const double* R12;
     const double* Y;
     double* L;
-    const int* kofs;     // W column k = (c,d) -> T offset c np + d
-    const int* hofs;     // hole pair kk = (k,l) -> T offset k v np + l v
+    const int* kofs;     // W column k = (c,d) -> T offset c ldt + d
+    const int* hofs;     // hole pair kk = (k,l) -> T offset k v ldt + l v
     int ldw, w_rows, np, o, v, o2, v2;
+    int ldt;             // row stride of T: np in global memory, n when staged in LDS
 };
 
 // One wave task: kLadRT row tiles (rows m = (a,b) of W) x CT column tiles
 // (columns n = (i,j)).  acc = sum_{(c,d)} W[m][(c,d)] T[(i,c),(j,d)]
 //                           + sum_{(k,l)} T[(k,a),(l,b)] <kl|ij>      (P + H)
 // then L[(i,a),(j,b)] = acc + R[(i,a),(j,b)] + R[(j,b),(i,a)].
-template <int CT>
+template <int RT, int CT, int PD>
 __device__ void ladder_task(const LadderView& g, int tr0, int tc0, int lane) {
     const int lr = lane & 15, lk = (lane >> 4) * 4;
-    int arow[kLadRT], hrow[kLadRT], bbase[CT], ncol[CT];
+    int arow[RT], hrow[RT], bbase[CT], ncol[CT];
 #pragma unroll
-    for (int u = 0; u < kLadRT; ++u) {
+    for (int u = 0; u < RT; ++u) {
         const int m = (tr0 + u) * 16 + lr;
         arow[u] = m < g.w_rows ? m : 0;
         const int a = m / g.v, b = m - a * g.v;
-        hrow[u] = m < g.v2 ? a * g.np + b : 0;
+        hrow[u] = m < g.v2 ? a * g.ldt + b : 0;
     }
 #pragma unroll
     for (int w = 0; w < CT; ++w) {
         const int n = (tc0 + w) * 16 + lr;
         const int i = n / g.o, j = n - i * g.o;
-        bbase[w] = n < g.o2 ? i * g.v * g.np + j * g.v : 0;
+        bbase[w] = n < g.o2 ? i * g.v * g.ldt + j * g.v : 0;
         ncol[w] = n;
     }
-    d4 acc[kLadRT][CT];
+    d4 acc[RT][CT];
 #pragma unroll
-    for (int u = 0; u < kLadRT; ++u)
+    for (int u = 0; u < RT; ++u)
 #pragma unroll
         for (int w = 0; w < CT; ++w) acc[u][w] = d4(0.0);
-    // particle-particle ladder: W streamed once with two k chunks in flight
-    // (p0 / p1 hold the even / odd chunks), the gathered amplitude columns of
-    // the next chunk in flight from L2.  Loads past the last chunk are
-    // redirected to chunk 0 (in bounds, values unused) instead of branched
+    // particle-particle ladder: W streamed once with PD k chunks in flight
+    // (pf[q] holds chunk q modulo PD), the gathered amplitude columns of the
+    // next chunk in flight.  Loads past the last chunk are redirected to chunk 0
+    // (in bounds) and their products multiplied by zero instead of branched
     // around, so the memory counters are waited on in issue order: the gathers
-    // of a chunk are issued before the W rows two chunks ahead, and waiting for
-    // them leaves those W loads in flight.
-    d4 p0[kLadRT], p1[kLadRT];
+    // of a chunk are issued before the W rows PD chunks ahead, and waiting for
+    // them leaves those W loads in flight.  Scheduling barriers keep that order.
+    d4 pf[PD][RT];
     double bn[CT][4], b[CT][4];
-    const double* wrow[kLadRT];
+    const double* wrow[RT];
 #pragma unroll
-    for (int u = 0; u < kLadRT; ++u) {
-        wrow[u] = g.W + (int64_t)arow[u] * g.ldw + lk;
-        p0[u] = load4(wrow[u]);
-        p1[u] = load4(wrow[u] + (16 < g.ldw ? 16 : 0));
-    }
+    for (int u = 0; u < RT; ++u) wrow[u] = g.W + (int64_t)arow[u] * g.ldw + lk;
+#pragma unroll
+    for (int q = 0; q < PD; ++q)
+#pragma unroll
+        for (int u = 0; u < RT; ++u) pf[q][u] = load4(wrow[u] + (16 * q < g.ldw ? 16 * q : 0));
     auto gather = [&](int k0) {
         const int kb = k0 < g.ldw ? k0 : 0;
 #pragma unroll
@@ -250,61 +252,48 @@ __device__ void ladder_task(const LadderView& g, int tr0, int tc0, int lane) {
             for (int w = 0; w < CT; ++w) bn[w][s] = g.T[ko + bbase[w]];
         }
     };
-    auto block = [&](const d4 (&pa)[kLadRT]) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int u = 0; u < kLadRT; ++u)
-#pragma unroll
-                for (int w = 0; w < CT; ++w) acc[u][w] = mfma(pa[u][s], b[w][s], acc[u][w]);
-    };
     gather(0);
-    // ldw is a multiple of 32: chunks come in (even, odd) pairs.  Scheduling
-    // barriers keep the issue order (gathers, MFMA block, W prefetch) so the
-    // prefetched rows stay in flight across a whole MFMA block.
-    for (int k0 = 0; k0 < g.ldw; k0 += 32) {
+    for (int k0 = 0; k0 < g.ldw; k0 += 16 * PD) {
 #pragma unroll
-        for (int w = 0; w < CT; ++w)
+        for (int q = 0; q < PD; ++q) {
+            const int kc = k0 + 16 * q;
+            const double live = kc < g.ldw ? 1.0 : 0.0;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) b[w][s] = bn[w][s];
-        gather(k0 + 16);
-        __builtin_amdgcn_sched_barrier(0);
-        block(p0);
-        __builtin_amdgcn_sched_barrier(0);
-        const int n0 = k0 + 32 < g.ldw ? k0 + 32 : 0;
+            for (int w = 0; w < CT; ++w)
 #pragma unroll
-        for (int u = 0; u < kLadRT; ++u) p0[u] = load4(wrow[u] + n0);
-        __builtin_amdgcn_sched_barrier(0);
+                for (int s = 0; s < 4; ++s) b[w][s] = live * bn[w][s];
+            gather(kc + 16);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int w = 0; w < CT; ++w)
+            for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int s = 0; s < 4; ++s) b[w][s] = bn[w][s];
-        gather(k0 + 32);
-        __builtin_amdgcn_sched_barrier(0);
-        block(p1);
-        __builtin_amdgcn_sched_barrier(0);
-        const int n1 = k0 + 48 < g.ldw ? k0 + 48 : 0;
+                for (int u = 0; u < RT; ++u)
 #pragma unroll
-        for (int u = 0; u < kLadRT; ++u) p1[u] = load4(wrow[u] + n1);
-        __builtin_amdgcn_sched_barrier(0);
+                    for (int w = 0; w < CT; ++w) acc[u][w] = mfma(pf[q][u][s], b[w][s], acc[u][w]);
+            __builtin_amdgcn_sched_barrier(0);
+            const int nx = kc + 16 * PD < g.ldw ? kc + 16 * PD : 0;
+#pragma unroll
+            for (int u = 0; u < RT; ++u) pf[q][u] = load4(wrow[u] + nx);
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
     // hole-hole ladder on the same accumulators: k runs over the o^2 hole pairs (k,l)
     for (int k0 = 0; k0 < g.o2; k0 += 16) {
-        double a[kLadRT][4], b[CT][4];
+        double a[RT][4], b[CT][4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int kk = k0 + lk + s;
             const bool ok = kk < g.o2;
             const int ho = g.hofs[kk];
 #pragma unroll
-            for (int u = 0; u < kLadRT; ++u) a[u][s] = g.T[ho + hrow[u]];
+            for (int u = 0; u < RT; ++u) a[u][s] = g.T[ho + hrow[u]];
 #pragma unroll
             for (int w = 0; w < CT; ++w) b[w][s] = (ok && ncol[w] < g.o2) ? g.Q[kk * g.o2 + ncol[w]] : 0.0;
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int u = 0; u < kLadRT; ++u)
+            for (int u = 0; u < RT; ++u)
 #pragma unroll
                 for (int w = 0; w < CT; ++w) acc[u][w] = mfma(a[u][s], b[w][s], acc[u][w]);
     }
@@ -315,7 +304,7 @@ __device__ void ladder_task(const LadderView& g, int tr0, int tc0, int lane) {
         if (n >= g.o2) continue;
         const int i = n / g.o, j = n - i * g.o;
 #pragma unroll
-        for (int u = 0; u < kLadRT; ++u)
+        for (int u = 0; u < RT; ++u)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int m = (tr0 + u) * 16 + acc_row(lane, t);
@@ -359,7 +348,7 @@ __global__ __launch_bounds__(kLccdThreads, 2) void lccd_ladder_kernel(
     }
     __syncthreads();
     LadderView g{W + l.w_off, Q + l.q_off, T + d.mat_off, R12 + d.mat_off, Y + d.mat_off, L + d.mat_off,
-                 kofs, hofs, l.ldw, l.w_rows, np, o, v, o2, v2};
+                 kofs, hofs, l.ldw, l.w_rows, np, o, v, o2, v2, np};
     const int nrt = l.w_rows / 16;
     const int ntask_r = (nrt + kLadRT - 1) / kLadRT;
     const int nct = (o2 + 15) / 16;
@@ -367,7 +356,67 @@ __global__ __launch_bounds__(kLccdThreads, 2) void lccd_ladder_kernel(
     const int tasks = ntask_r * ngroups;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int task = part * (kLccdThreads / 64) + wave; task < tasks; task += blocks_per_mono * (kLccdThreads / 64))
-        ladder_task<CT>(g, (task / ngroups) * kLadRT, (task % ngroups) * CT, lane);
+        ladder_task<kLadRT, CT, 2>(g, (task / ngroups) * kLadRT, (task % ngroups) * CT, lane);
+}
+
+// The same with the monomer's amplitudes staged in LDS (n x n doubles, row
+// stride n; 146 KB at o = 5, v = 27): one workgroup of eight waves per monomer,
+// so the B operand gathers and the hole-ladder operands read LDS, and the L2
+// holds the W stream and the R12 / Y reads of the epilogue only.
+template <int CT>
+__global__ __launch_bounds__(kLadLdsThreads) void lccd_ladder_lds_kernel(
+    const MonoDesc* __restrict__ monos, const LccdDesc* __restrict__ ld,
+    const double* __restrict__ W, const double* __restrict__ Q, const double* __restrict__ T,
+    const double* __restrict__ R12, const double* __restrict__ Y, double* __restrict__ L,
+    const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
+    if (ctrl && ctrl->done) return;
+    const int x = blockIdx.x;
+    const MonoDesc d = monos[x];
+    if (cl && cl[d.cluster].done) return;
+    const LccdDesc l = ld[x];
+    extern __shared__ double lds[];
+    const int np = d.np, n = d.n, o = d.o, v = d.v, v2 = v * v, o2 = o * o;
+    double* sT = lds;
+    int* kofs = reinterpret_cast<int*>(lds + n * n);
+    int* hofs = kofs + l.ldw;
+    const double* Tx = T + d.mat_off;
+    // staging: eight independent loads in flight per thread before the LDS stores
+    constexpr int U = 8;
+    const int nn = n * n;
+    for (int e0 = threadIdx.x; e0 < nn; e0 += U * kLadLdsThreads) {
+        double t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * kLadLdsThreads;
+            const int r = e / n, c = e - r * n;
+            t[u] = e < nn ? Tx[(int64_t)r * np + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * kLadLdsThreads;
+            if (e < nn) sT[e] = t[u];
+        }
+    }
+    for (int k = threadIdx.x; k < l.ldw; k += kLadLdsThreads) {
+        const int c = k / v, dd = k - c * v;
+        kofs[k] = k < v2 ? c * n + dd : 0;
+    }
+    for (int k = threadIdx.x; k < 64; k += kLadLdsThreads) {
+        const int kk = k / o, ll = k - kk * o;
+        hofs[k] = k < o2 ? kk * v * n + ll * v : 0;
+    }
+    __syncthreads();
+    LadderView g{W + l.w_off, Q + l.q_off, sT, R12 + d.mat_off, Y + d.mat_off, L + d.mat_off,
+                 kofs, hofs, l.ldw, l.w_rows, np, o, v, o2, v2, n};
+    constexpr int RT = 2;
+    const int nrt = l.w_rows / 16;
+    const int ntask_r = (nrt + RT - 1) / RT;
+    const int nct = (o2 + 15) / 16;
+    const int ngroups = (nct + CT - 1) / CT;
+    const int tasks = ntask_r * ngroups;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int task = wave; task < tasks; task += kLadLdsThreads / 64)
+        ladder_task<RT, CT, 4>(g, (task / ngroups) * RT, (task % ngroups) * CT, lane);
 }
 
 }  // namespace
@@ -407,10 +456,37 @@ void launch_lccd_ring(const MonoDesc* monos, int n_mono, int ring_blocks, const 
                        ring_blocks, K, J, T, M, R12, Y, ctrl, cl);
 }
 
+int64_t lccd_ladder_lds_bytes(int n, int ldw) { return (int64_t)n * n * 8 + (int64_t)(ldw + 64) * 4; }
+
+int64_t lccd_lds_limit() { return 160 * 1024; }
+
 void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, int ladder_blocks, int ct,
-                        const double* W, const double* Q, const double* T, const double* R12, const double* Y,
-                        double* L, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
+                        int64_t lds_bytes, const double* W, const double* Q, const double* T, const double* R12,
+                        const double* Y, double* L, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
     if (n_mono <= 0 || ladder_blocks <= 0) return;
+    if (lds_bytes > 0) {
+        const dim3 grid(n_mono), block(kLadLdsThreads);
+        switch (ct) {
+#define LDS_CASE(C)                                                                                              \
+    case C: {                                                                                                    \
+        static bool attr = false;                                                                                \
+        if (!attr) {                                                                                             \
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&lccd_ladder_lds_kernel<C>),                 \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lccd_lds_limit());         \
+            attr = true;                                                                                         \
+        }                                                                                                        \
+        hipLaunchKernelGGL(lccd_ladder_lds_kernel<C>, grid, block, (size_t)lds_bytes, s, monos, ld, W, Q, T, R12, \
+                           Y, L, ctrl, cl);                                                                      \
+        return;                                                                                                  \
+    }
+            LDS_CASE(1)
+            LDS_CASE(2)
+            LDS_CASE(3)
+            default:
+                break;
+#undef LDS_CASE
+        }
+    }
     const dim3 grid(((n_mono + kXcds - 1) / kXcds) * kXcds * ladder_blocks), block(kLccdThreads);
     switch (ct) {
         case 1:

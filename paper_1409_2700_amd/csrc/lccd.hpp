@@ -28,9 +28,14 @@ int lccd_ladder_ct(int max_o);   // column tiles per ladder task: ceil(max_o^2 /
 void launch_lccd_ring(const MonoDesc* monos, int n_mono, int ring_blocks, const double* K, const double* J,
                       const double* T, const double* M, double* R12, double* Y, const Ctrl* ctrl, const ClState* cl,
                       hipStream_t s);
-// L = P + H + R + R^T (R = R12 - Vs(Y)) for every live monomer
+// LDS bytes of the LDS-staged ladder kernel for a monomer (its n x n amplitudes
+// and offset tables), and the per-workgroup limit
+int64_t lccd_ladder_lds_bytes(int n, int ldw);
+int64_t lccd_lds_limit();
+// L = P + H + R + R^T (R = R12 - Vs(Y)) for every live monomer; lds_bytes > 0
+// selects the LDS-staged kernel (every monomer must need at most that much)
 void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, int ladder_blocks, int ct,
-                        const double* W, const double* Q, const double* T, const double* R12, const double* Y,
-                        double* L, const Ctrl* ctrl, const ClState* cl, hipStream_t s);
+                        int64_t lds_bytes, const double* W, const double* Q, const double* T, const double* R12,
+                        const double* Y, double* L, const Ctrl* ctrl, const ClState* cl, hipStream_t s);
 
 }  // namespace mcpt

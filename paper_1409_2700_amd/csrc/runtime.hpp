@@ -83,6 +83,7 @@ struct Resident {
     double *d_W = nullptr, *d_Q = nullptr, *d_J = nullptr;
     double *d_L = nullptr, *d_R12 = nullptr, *d_Y = nullptr, *d_elccd = nullptr;
     int lccd_ring_blocks = 0, lccd_ladder_blocks = 0, lccd_ct = 1;
+    int64_t lccd_lds_bytes = 0;       // > 0: the LDS-staged ladder kernel with this much dynamic LDS
     double lccd_w_bytes = 0.0;        // packed-integral bytes the ladder kernel streams per sweep
     double lccd_w_flops = 0.0;        // algorithmic flops of the particle-particle ladder per sweep
     std::vector<void*> lccd_allocations;

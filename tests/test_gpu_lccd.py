@@ -81,6 +81,19 @@ def test_fixed_sweeps_elementwise(ctx, general, sweeps):
     assert abs(s["e_mono0"] - ref.e_mono0) <= TOL * abs(ref.e_mono0)
 
 
+@pytest.mark.parametrize("general", [False, True])
+def test_fixed_sweeps_lds_staged_ladder(ctx, general):
+    """Monomers whose amplitudes fit one workgroup's LDS (o v <= 135 here): the
+    ladder kernel that stages T in LDS; element by element after 2 sweeps."""
+    p, ints = ragged(sizes=((2, 3), (5, 27), (3, 17), (1, 1), (4, 9), (5, 27)), general=general, workload=921)
+    ref = mcpt_lccd.solve(p, ints, tol=0.0, max_sweeps=2)
+    s, e = run_gpu(ctx, p, ints, tol=0.0, max_sweeps=2)
+    assert s["return"] == mc.MCPT_OK, s["error"]
+    assert rel(e["t"], flat_t(ref)) <= TOL
+    assert rel(e["e_m2"], ref.e_m2) <= TOL
+    assert rel(e["e_m2"] - e["de_m2"], ref.e_m2_0) <= TOL
+
+
 def test_converged_ragged(ctx):
     p, ints = ragged(scale=0.5)
     ref = mcpt_lccd.solve(p, ints, tol=TOL, max_sweeps=300)
