@@ -1161,7 +1161,8 @@ mcpt_status lccd_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_lccd_integ
     // the LDS-staged ladder when every monomer's amplitudes fit one workgroup's LDS
     R->lccd_lds_bytes = 0;
     for (int m = 0; m < R->n_mono; ++m)
-        R->lccd_lds_bytes = std::max(R->lccd_lds_bytes, lccd_ladder_lds_bytes(R->monos[m].n, ld[m].ldw));
+        R->lccd_lds_bytes =
+            std::max(R->lccd_lds_bytes, lccd_ladder_lds_bytes(R->monos[m].n, R->monos[m].v, ld[m].ldw));
     if (R->lccd_lds_bytes > lccd_lds_limit() || R->lccd_ct > 3) R->lccd_lds_bytes = 0;
     R->lccd_w_bytes = 8.0 * (double)w_pack;
     double fl = 0.0;

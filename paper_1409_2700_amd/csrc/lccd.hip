@@ -204,7 +204,7 @@ struct LadderView {
 // (columns n = (i,j)).  acc = sum_{(c,d)} W[m][(c,d)] T[(i,c),(j,d)]
 //                           + sum_{(k,l)} T[(k,a),(l,b)] <kl|ij>      (P + H)
 // then L[(i,a),(j,b)] = acc + R[(i,a),(j,b)] + R[(j,b),(i,a)].
-template <int RT, int CT, int PD>
+template <int RT, int CT, int PD, bool WITH_R>
 __device__ void ladder_task(const LadderView& g, int tr0, int tc0, int lane) {
     const int lr = lane & 15, lk = (lane >> 4) * 4;
     int arow[RT], hrow[RT], bbase[CT], ncol[CT];
@@ -311,11 +311,50 @@ __device__ void ladder_task(const LadderView& g, int tr0, int tc0, int lane) {
                 if (m >= g.v2) continue;
                 const int a = m / g.v, b = m - a * g.v;
                 const int r = i * g.v + a, c = j * g.v + b;
-                const double rr = g.R12[(int64_t)r * g.np + c] - g.Y[(int64_t)(i * g.v + b) * g.np + j * g.v + a];
-                const double rt = g.R12[(int64_t)c * g.np + r] - g.Y[(int64_t)(j * g.v + a) * g.np + i * g.v + b];
-                g.L[(int64_t)r * g.np + c] = (acc[u][w][t] + rr) + rt;
+                if (WITH_R) {
+                    const double rr = g.R12[(int64_t)r * g.np + c] - g.Y[(int64_t)(i * g.v + b) * g.np + j * g.v + a];
+                    const double rt = g.R12[(int64_t)c * g.np + r] - g.Y[(int64_t)(j * g.v + a) * g.np + i * g.v + b];
+                    g.L[(int64_t)r * g.np + c] = (acc[u][w][t] + rr) + rt;
+                } else {
+                    g.L[(int64_t)r * g.np + c] = acc[u][w][t];
+                }
             }
     }
+}
+
+// L += R + R^T with R = R12 - Vs(Y), by v x v block pairs {(i,j), (j,i)}: the
+// four blocks of R12 and Y are read once, row-contiguous, and the transposed
+// elements come from LDS (sbuf: 4 v (v + 1) doubles), as in the monomer update.
+__device__ void add_rings(const LadderView& g, double* sbuf) {
+    const int o = g.o, v = g.v, np = g.np, vs = v + 1;
+    double* r0 = sbuf;                 // R12 block (i,j)
+    double* r1 = r0 + v * vs;          // R12 block (j,i)
+    double* y0 = r1 + v * vs;          // Y block (i,j)
+    double* y1 = y0 + v * vs;          // Y block (j,i)
+    for (int i = 0; i < o; ++i)
+        for (int j = i; j < o; ++j) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < v * v; e += blockDim.x) {
+                const int a = e / v, b = e - a * v;
+                const int64_t ij = (int64_t)(i * v + a) * np + j * v + b, ji = (int64_t)(j * v + a) * np + i * v + b;
+                r0[a * vs + b] = g.R12[ij];
+                r1[a * vs + b] = g.R12[ji];
+                y0[a * vs + b] = g.Y[ij];
+                y1[a * vs + b] = g.Y[ji];
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < v * v; e += blockDim.x) {
+                const int a = e / v, b = e - a * v;
+                const int64_t e1 = (int64_t)(i * v + a) * np + j * v + b;
+                // (i,a),(j,b): R12[(i,a),(j,b)] - Y[(i,b),(j,a)] + R12[(j,b),(i,a)] - Y[(j,a),(i,b)]
+                g.L[e1] += (r0[a * vs + b] - y0[b * vs + a]) + (r1[b * vs + a] - y1[a * vs + b]);
+                if (i != j) {
+                    const int64_t e2 = (int64_t)(j * v + a) * np + i * v + b;
+                    // (j,a),(i,b): R12[(j,a),(i,b)] - Y[(j,b),(i,a)] + R12[(i,b),(j,a)] - Y[(i,a),(j,b)]
+                    g.L[e2] += (r1[a * vs + b] - y1[b * vs + a]) + (r0[b * vs + a] - y0[a * vs + b]);
+                }
+            }
+        }
 }
 
 // All blocks of one monomer run on one XCD (block b -> XCD b % 8), so the
@@ -356,13 +395,15 @@ __global__ __launch_bounds__(kLccdThreads, 2) void lccd_ladder_kernel(
     const int tasks = ntask_r * ngroups;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int task = part * (kLccdThreads / 64) + wave; task < tasks; task += blocks_per_mono * (kLccdThreads / 64))
-        ladder_task<kLadRT, CT, 2>(g, (task / ngroups) * kLadRT, (task % ngroups) * CT, lane);
+        ladder_task<kLadRT, CT, 2, true>(g, (task / ngroups) * kLadRT, (task % ngroups) * CT, lane);
 }
 
 // The same with the monomer's amplitudes staged in LDS (n x n doubles, row
 // stride n; 146 KB at o = 5, v = 27): one workgroup of eight waves per monomer,
-// so the B operand gathers and the hole-ladder operands read LDS, and the L2
-// holds the W stream and the R12 / Y reads of the epilogue only.
+// so the B operand gathers and the hole-ladder operands read LDS.  The tasks
+// write L = P + H; a final pass over block pairs adds the ring terms with
+// row-contiguous reads of R12 and Y (their scattered reads in the task
+// epilogues fetched a 128-byte line for every 8 bytes used).
 template <int CT>
 __global__ __launch_bounds__(kLadLdsThreads) void lccd_ladder_lds_kernel(
     const MonoDesc* __restrict__ monos, const LccdDesc* __restrict__ ld,
@@ -416,7 +457,10 @@ __global__ __launch_bounds__(kLadLdsThreads) void lccd_ladder_lds_kernel(
     const int tasks = ntask_r * ngroups;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int task = wave; task < tasks; task += kLadLdsThreads / 64)
-        ladder_task<RT, CT, 4>(g, (task / ngroups) * RT, (task % ngroups) * CT, lane);
+        ladder_task<RT, CT, 4, false>(g, (task / ngroups) * RT, (task % ngroups) * CT, lane);
+    // every wave is done with the staged amplitudes and its L stores are visible to the workgroup
+    __syncthreads();
+    add_rings(g, lds);
 }
 
 }  // namespace
@@ -456,7 +500,11 @@ void launch_lccd_ring(const MonoDesc* monos, int n_mono, int ring_blocks, const 
                        ring_blocks, K, J, T, M, R12, Y, ctrl, cl);
 }
 
-int64_t lccd_ladder_lds_bytes(int n, int ldw) { return (int64_t)n * n * 8 + (int64_t)(ldw + 64) * 4; }
+int64_t lccd_ladder_lds_bytes(int n, int v, int ldw) {
+    const int64_t stage = (int64_t)n * n * 8 + (int64_t)(ldw + 64) * 4;
+    const int64_t rings = (int64_t)4 * v * (v + 1) * 8;
+    return stage > rings ? stage : rings;
+}
 
 int64_t lccd_lds_limit() { return 160 * 1024; }
 

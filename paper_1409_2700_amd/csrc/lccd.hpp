@@ -29,8 +29,8 @@ void launch_lccd_ring(const MonoDesc* monos, int n_mono, int ring_blocks, const 
                       const double* T, const double* M, double* R12, double* Y, const Ctrl* ctrl, const ClState* cl,
                       hipStream_t s);
 // LDS bytes of the LDS-staged ladder kernel for a monomer (its n x n amplitudes
-// and offset tables), and the per-workgroup limit
-int64_t lccd_ladder_lds_bytes(int n, int ldw);
+// and offset tables, later four v x (v + 1) ring blocks), and the per-workgroup limit
+int64_t lccd_ladder_lds_bytes(int n, int v, int ldw);
 int64_t lccd_lds_limit();
 // L = P + H + R + R^T (R = R12 - Vs(Y)) for every live monomer; lds_bytes > 0
 // selects the LDS-staged kernel (every monomer must need at most that much)
