@@ -482,7 +482,7 @@ def lccd_mode(ctx, prob, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: 
         "solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "iso_sweeps": s["iso_sweeps"], "sweeps": s["sweeps"],
         "e_total": s["e_total"], "e_lccd_total": s["e_mono0"], "attach_s": attach_s,
         "workload": f"{prob.meta.get('name', '')} with K x {LCCD_K_SCALE} and intramonomer classes at sigma 0.01",
-        "ladder_kernel": {"kernel": "lccd_ladder_kernel", "bound": "hbm", "avg_launch_ms": ms,
+        "ladder_kernel": {"kernel": "lccd_ladder_lds_kernel", "bound": "hbm", "avg_launch_ms": ms,
                           "algorithmic_bytes_per_launch": wb, "achieved_GBps": wb / (ms * 1e-3) / 1e9,
                           "peak_GBps": HBM_PEAK_GBS, "frac": wb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                           "ladder_TFLOPs": fl / (ms * 1e-3) / 1e12, "launches": tm["lccd_launches"]},
