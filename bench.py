@@ -474,8 +474,16 @@ def lccd_mode(ctx, prob, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: 
     dt = (time.perf_counter() - t0) / max(steps, 1)
     tm = ctx.timing()
     ctx.set_timing(False)
+    e_fp64 = ctx.energy(pid, want_t=False)
     kl = max(tm["lccd_launches"], 1)
     ms = tm["lccd_ladder_ms"] / kl
+    # the mixed-precision form on the same problem: BF16 pair products, FP64 polish (and FP64 intramonomer terms)
+    ob = dict(opts, precision=2, polish=1, autotune=1)
+    ctx.run(pid, **ob)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sb = ctx.run(pid, **ob)
+    dtb = (time.perf_counter() - t0) / max(steps, 1)
     wb = tm["lccd_w_bytes"] / kl
     fl = tm["lccd_ladder_flops"] / kl
     out = {
@@ -489,9 +497,12 @@ def lccd_mode(ctx, prob, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: 
         "ring_kernel_avg_ms": tm["lccd_ring_ms"] / kl,
         "pair_kernel_avg_ms": tm["pair_ms"] / max(tm["pair_launches"], 1),
         "monomer_avg_ms": tm["mono_ms"] / max(tm["mono_launches"], 1),
+        "bf16_polish": {"solves_per_s": 1.0 / dtb, "ms_per_solve": dtb * 1e3, "sweeps": sb["sweeps"],
+                        "fp64_sweeps": sb["polish_sweeps"], "e_total": sb["e_total"],
+                        "rel_diff_vs_fp64": abs(sb["e_total"] - s["e_total"]) / abs(s["e_total"])},
     }
     if golden is not None:
-        e = ctx.energy(pid, want_t=False)
+        e = e_fp64
         out["oracle_reference"] = {"e_total": golden["e_total"], "iso_sweeps": golden["iso_sweeps"],
                                    "sweeps": golden["sweeps"], "file": os.path.relpath(gpath, ROOT)}
         out["relative_error_e_total"] = abs(s["e_total"] - golden["e_total"]) / abs(golden["e_total"])
@@ -499,7 +510,8 @@ def lccd_mode(ctx, prob, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: 
         out["max_abs_error_e_lccd_Eh"] = float(np.max(np.abs(e["e_m2"] - e["de_m2"] - np.asarray(golden["e_lccd"]))))
     ctx.release(pid)
     log(f"[lccd] {s['iso_sweeps']} + {s['sweeps']} sweeps, {dt * 1e3:.1f} ms per solve, ladder {ms:.3f} ms = "
-        f"{wb / (ms * 1e-3) / 1e9:.0f} GB/s, ring {out['ring_kernel_avg_ms']:.3f} ms")
+        f"{wb / (ms * 1e-3) / 1e9:.0f} GB/s, ring {out['ring_kernel_avg_ms']:.3f} ms; BF16 + polish "
+        f"{dtb * 1e3:.1f} ms ({sb['sweeps']} sweeps, {sb['polish_sweeps']} FP64)")
     if with_cpu:
         from oracle import mcpt_lccd
         orc = mcpt_lccd.LccdOracle(pl.subset_pairs(np.zeros(pl.n_pair, dtype=bool)), ints)

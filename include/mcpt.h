@@ -270,8 +270,10 @@ mcpt_status mcpt_singles_result(mcpt_ctx *ctx, uint64_t id, double *e_m1, double
  * solution as the reference of Eq. 56 (mcpt_energy's de_m2 and the summary's
  * e_mono0), then runs the coupled sweeps (step 6) from the first-order
  * amplitudes: pair phase (Eq. 59), intramonomer terms from the current T,
- * monomer update.  FP64 only, not in deterministic mode; HIP-graph capture and
- * batches work as for mcpt_run.  Dimer amplitudes keep the terms of Eq. 59
+ * monomer update.  Reduced precision (with or without polish), HIP-graph
+ * capture and batches work as for mcpt_run; the intramonomer terms are formed
+ * in FP64 in every sweep, and in polish mode also for each correction (of the
+ * correction's own amplitudes); step 5 runs in FP64.  No deterministic mode.  Dimer amplitudes keep the terms of Eq. 59
  * listed at the top (its dimer-internal terms need dimer integral classes that
  * are not inputs).  Sizes per monomer: v <= 64 and o v <= 1024. */
 typedef struct {
@@ -289,8 +291,8 @@ typedef struct {
  * Errors: MCPT_ERR_INVALID (NULL array, memory, monomer sizes),
  * MCPT_ERR_NONFINITE, MCPT_ERR_ADMISSION, MCPT_ERR_NOMEM, MCPT_ERR_UNKNOWN_ID,
  * MCPT_ERR_DEVICE.  mcpt_run of an attached problem returns MCPT_ERR_INVALID
- * for reduced precision or deterministic = 1, and MCPT_ERR_DIVERGED (no
- * results) when step 5 diverges for any cluster. */
+ * for deterministic = 1, and MCPT_ERR_DIVERGED (no results) when step 5
+ * diverges for any cluster. */
 mcpt_status mcpt_lccd_attach(mcpt_ctx *ctx, uint64_t id, const mcpt_lccd_integrals *ints);
 
 /* ---- Finite-displacement geometries (Sec. IV.A: harmonic frequencies from

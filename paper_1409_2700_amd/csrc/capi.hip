@@ -820,9 +820,11 @@ void lowp_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, float* Gf, int sou
 
 void mixed_mono(mcpt_ctx* c, Exec& x, Resident* R, int mode, const double* G, double* Gz, bool lo_out, const Ctrl* ctrl,
                 const float* Gf = nullptr, float* Gfz = nullptr) {
+    // full monomer equation: the update and correction modes add the intramonomer terms held in L
+    const bool with_l = R->lccd && (mode == kMonoUpdate || mode == kMonoUpdateR || mode == kMonoCorr || mode == kMonoRlo);
     launch_monomer_mixed(mode, R->lo_prec, R->d_monos, R->n_mono, R->max_v, R->d_dif, R->d_K, G, Gz, R->d_T, R->d_M, R->d_R,
                          R->d_Dl, lo_out ? R->d_Mlo : nullptr, R->d_mlo_off, R->d_em2, R->d_em2_0, R->d_res, ctrl,
-                         R->d_cl, x.stream, Gf, Gfz);
+                         R->d_cl, x.stream, Gf, Gfz, with_l ? R->d_L : nullptr);
 }
 
 mcpt_status sync_ctrl(Exec& x) {
@@ -1390,8 +1392,8 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
     if (st != MCPT_OK) return st;
     if ((st = ensure_device(c)) != MCPT_OK) return st;
     if ((st = ensure_scratch(c, x, R->max_slot)) != MCPT_OK) return st;
-    if (R->lccd && (o->precision != MCPT_FP64 || o->deterministic))
-        return fail(MCPT_ERR_INVALID, "the full monomer equation runs in FP64 without the deterministic mode");
+    if (R->lccd && o->deterministic)
+        return fail(MCPT_ERR_INVALID, "the full monomer equation has no deterministic mode");
     R->det_on = o->deterministic != 0;
     if (R->det_on && (st = ensure_det(c, x, R)) != MCPT_OK) return st;
     const int prec = o->precision;
@@ -1432,15 +1434,17 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
     launch_fill(R->d_G[0], R->mat_elems, 0.0, s);
     launch_fill(R->d_G[1], R->mat_elems, 0.0, s);
     // intramonomer terms of the full monomer equation, L = P + H + R + R^T from the current T and M
-    auto lccd_terms = [&](const Ctrl* ctrl) {
+    // (of amplitudes Tin with Min = 2 Tin - S(Tin): T itself, or a defect correction in the polish form)
+    auto lccd_terms = [&](const Ctrl* ctrl, const double* Tin = nullptr) {
+        if (!Tin) Tin = R->d_T;
         hipEvent_t a = nullptr;
         record_begin(x, &a);
-        launch_lccd_ring(R->d_monos, R->n_mono, R->lccd_ring_blocks, R->d_K, R->d_J, R->d_T, R->d_M, R->d_R12, R->d_Y,
+        launch_lccd_ring(R->d_monos, R->n_mono, R->lccd_ring_blocks, R->d_K, R->d_J, Tin, R->d_M, R->d_R12, R->d_Y,
                          ctrl, R->d_cl, s);
         record_end(x, a, 4, 0.0, 0.0);
         record_begin(x, &a);
         launch_lccd_ladder(R->d_monos, R->d_lccd, R->n_mono, R->lccd_ladder_blocks, R->lccd_ct, R->lccd_lds_bytes,
-                           R->d_W, R->d_Q, R->d_T, R->d_R12, R->d_Y, R->d_L, ctrl, R->d_cl, s);
+                           R->d_W, R->d_Q, Tin, R->d_R12, R->d_Y, R->d_L, ctrl, R->d_cl, s);
         record_end(x, a, 5, R->lccd_w_flops, R->lccd_w_bytes);
     };
     std::vector<int32_t> iso_sweeps(R->n_cl, 0);
@@ -1507,7 +1511,10 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
         if (g32) lowp_phase(c, x, R, nullptr, R->d_G32[cur32], source);
         else lowp_phase(c, x, R, R->d_G[cur], nullptr, source);
     };
+    const double* corr_src = nullptr;   // amplitudes of the current correction (R, then delta)
     auto lo_mono = [&](int mode, const Ctrl* ctrl) {
+        if (R->lccd && mode == kMonoUpdate) lccd_terms(ctrl);
+        if (R->lccd && mode == kMonoCorr) lccd_terms(ctrl, corr_src);
         if (g32) {
             mixed_mono(c, x, R, mode, nullptr, nullptr, true, ctrl, R->d_G32[cur32], R->d_G32[cur32 ^ 1]);
             cur32 ^= 1;
@@ -1611,6 +1618,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
             record_begin(x, &a);
             pair_phase(c, x, R, R->d_G[cur], 1, x.d_ctrl);
             record_end(x, a, 0, fl_sweep, vb);
+            if (R->lccd) lccd_terms(x.d_ctrl);
             mixed_mono(c, x, R, kMonoUpdateR, R->d_G[cur], R->d_G[cur ^ 1], false, x.d_ctrl);
             launch_reduce_sweep(R->n_cl, R->d_cl_mono, R->d_res, R->d_cl, R->d_hist, x.d_ctrl, s);
             cur ^= 1;
@@ -1622,6 +1630,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
                 record_begin(x, &a);
                 lo_pair(0);
                 record_end(x, a, 2, fl_sweep, R->lo_v_bytes);
+                corr_src = k == 0 ? R->d_R : R->d_Dl;   // delta_0 = R, then the last correction
                 lo_mono(kMonoCorr, nullptr);
             }
             mixed_mono(c, x, R, kMonoApply, nullptr, nullptr, false, nullptr);
@@ -1646,7 +1655,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
                                              (int64_t)c->grid_lds * 1000000 + c->grid_glb,
                                              (((int64_t)x.grid_lo * 10000 + x.grid_lo_lds) * 1000 + R->lo_variant) * 1000 +
                                                  inner};
-            const int gprec = 16 + prec + (R->det_on ? 8 : 0);
+            const int gprec = 16 + prec + (R->det_on ? 8 : 0) + (R->lccd ? 32 : 0);
             const int parity = cur + 2 * cur32;
             if (!R->graph || R->graph_prec != gprec || R->graph_sweeps != gb || R->graph_key != key ||
                 R->graph_parity != parity) {

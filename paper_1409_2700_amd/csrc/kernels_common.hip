@@ -160,16 +160,24 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
                 has_lo = true;
             }
         } else if (mode == kMonoCorr) {
-            tn = Rx[e_rc] + dinv * ((double)Gx[e_rc] + (double)Gx[e_t]);
-            ts = Rx[e_s] + dinv * ((double)Gx[e_s] + (double)Gx[e_st]);
+            if (Lt) {   // intramonomer terms of the correction (full monomer equation)
+                const double* Lx = Lt + d.mat_off;
+                tn = Rx[e_rc] + dinv * (((double)Gx[e_rc] + (double)Gx[e_t]) + Lx[e_rc]);
+                ts = Rx[e_s] + dinv * (((double)Gx[e_s] + (double)Gx[e_st]) + Lx[e_s]);
+            } else {
+                tn = Rx[e_rc] + dinv * ((double)Gx[e_rc] + (double)Gx[e_t]);
+                ts = Rx[e_s] + dinv * ((double)Gx[e_s] + (double)Gx[e_st]);
+            }
             Dx[e_rc] = tn;
             lo = 2.0 * tn - ts;
             has_lo = true;
+            if (Lt) Mx[e_rc] = lo;   // FP64 2 delta - S(delta) for the next intramonomer terms
         } else if (mode == kMonoRlo) {
             tn = Rx[e_rc];
             ts = Rx[e_s];
             lo = 2.0 * tn - ts;
             has_lo = true;
+            if (Lt) Mx[e_rc] = lo;
         } else if (mode == kMonoFromT) {
             tn = Tx[e_rc];
             ts = Tx[e_s];
@@ -289,19 +297,33 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_blocks_kernel(
                         has_lo = true;
                     }
                 } else if (mode == kMonoCorr) {
-                    t1 = Rx[e1] + d1 * (sg[0][a][b] + sg[1][b][a]);
-                    t2 = Rx[e2] + d2 * (sg[1][a][b] + sg[0][b][a]);
+                    if (Lt) {   // intramonomer terms of the correction (full monomer equation)
+                        const double* Lx = Lt + d.mat_off;
+                        t1 = Rx[e1] + d1 * ((sg[0][a][b] + sg[1][b][a]) + Lx[e1]);
+                        t2 = Rx[e2] + d2 * ((sg[1][a][b] + sg[0][b][a]) + Lx[e2]);
+                    } else {
+                        t1 = Rx[e1] + d1 * (sg[0][a][b] + sg[1][b][a]);
+                        t2 = Rx[e2] + d2 * (sg[1][a][b] + sg[0][b][a]);
+                    }
                     Dx[e1] = t1;
                     if (!diag) Dx[e2] = t2;
                     lo1 = 2.0 * t1 - t2;
                     lo2 = 2.0 * t2 - t1;
                     has_lo = true;
+                    if (Lt) {   // FP64 2 delta - S(delta) for the next intramonomer terms
+                        Mx[e1] = lo1;
+                        if (!diag) Mx[e2] = lo2;
+                    }
                 } else if (mode == kMonoRlo) {
                     t1 = Rx[e1];
                     t2 = Rx[e2];
                     lo1 = 2.0 * t1 - t2;
                     lo2 = 2.0 * t2 - t1;
                     has_lo = true;
+                    if (Lt) {
+                        Mx[e1] = lo1;
+                        if (!diag) Mx[e2] = lo2;
+                    }
                 } else if (mode == kMonoFromT) {
                     t1 = Tx[e1];
                     t2 = Tx[e2];
@@ -542,16 +564,16 @@ void launch_monomer_mixed(int mode, int precision, const MonoDesc* monos, int n_
                           const double* K, const double* G, double* G_zero, double* T, double* M, double* R,
                           double* Dl, void* Mlo, const int64_t* mlo_off, double* em2, double* em2_0,
                           double* res, const Ctrl* ctrl, const ClState* cl, hipStream_t s, const float* Gf,
-                          float* Gf_zero) {
+                          float* Gf_zero, const double* L) {
     if (precision == 2 && (Gf || Gf_zero))
         monomer_dispatch<__bf16, float>(max_v, mode, monos, n_mono, dif, K, Gf, Gf_zero, T, M, R, Dl,
-                                        static_cast<__bf16*>(Mlo), mlo_off, 32, em2, em2_0, res, ctrl, cl, s);
+                                        static_cast<__bf16*>(Mlo), mlo_off, 32, em2, em2_0, res, ctrl, cl, s, L);
     else if (precision == 2)
         monomer_dispatch<__bf16, double>(max_v, mode, monos, n_mono, dif, K, G, G_zero, T, M, R, Dl,
-                                         static_cast<__bf16*>(Mlo), mlo_off, 32, em2, em2_0, res, ctrl, cl, s);
+                                         static_cast<__bf16*>(Mlo), mlo_off, 32, em2, em2_0, res, ctrl, cl, s, L);
     else
         monomer_dispatch<float, double>(max_v, mode, monos, n_mono, dif, K, G, G_zero, T, M, R, Dl,
-                                        static_cast<float*>(Mlo), mlo_off, 16, em2, em2_0, res, ctrl, cl, s);
+                                        static_cast<float*>(Mlo), mlo_off, 16, em2, em2_0, res, ctrl, cl, s, L);
 }
 
 void launch_reduce_sweep(int n_cl, const int64_t* cl_mono, const double* res, ClState* cl, double* hist,

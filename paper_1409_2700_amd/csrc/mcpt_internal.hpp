@@ -118,7 +118,9 @@ void launch_monomer_mixed(int mode, int precision, const MonoDesc* monos, int n_
                           const double* K, const double* G, double* G_zero, double* T, double* M, double* R,
                           double* Dl, void* Mlo, const int64_t* mlo_off, double* em2, double* em2_0,
                           double* res, const Ctrl* ctrl, const ClState* cl, hipStream_t s,
-                          const float* Gf = nullptr, float* Gf_zero = nullptr);
+                          const float* Gf = nullptr, float* Gf_zero = nullptr, const double* L = nullptr);
+// (L: the intramonomer terms of the full monomer equation, added by the update and correction modes;
+//  with L, the rlo and corr modes also store the FP64 2 delta - S(delta) in M)
 void launch_reduce_sweep(int n_cl, const int64_t* cl_mono, const double* res, ClState* cl, double* hist,
                          Ctrl* ctrl, hipStream_t s);
 // G_X = sum of the stored partial blocks of monomer X (csr[csr_off[X] .. csr_off[X+1]):

@@ -121,6 +121,34 @@ def test_converged_cubes_match_stored_oracle(ctx, name):
     assert rel(e["e_d2"][g["pair_index"]], g["e_d2"]) <= TOL
 
 
+@pytest.mark.parametrize("precision", [mc.MCPT_FP32, mc.MCPT_BF16])
+@pytest.mark.parametrize("graph", [0, 1])
+def test_mixed_precision_polish_matches_oracle(ctx, precision, graph):
+    """Reduced-precision pair products with FP64 defect correction (the
+    intramonomer terms of each correction applied in FP64): converged to the FP64
+    tolerance, so within the FP64 bar of the oracle."""
+    p, ints = ragged(sizes=((2, 3), (5, 27), (3, 17), (1, 1), (4, 9), (5, 27)), workload=922)
+    ref = mcpt_lccd.solve(p, ints, tol=TOL, max_sweeps=300)
+    s, e = run_gpu(ctx, p, ints, tol=TOL, max_sweeps=300, precision=precision, polish=1, graph=graph,
+                   check_every=2)
+    assert s["return"] == mc.MCPT_OK, s["error"]
+    assert rel(e["e_m2"], ref.e_m2) <= TOL and rel(e["e_d2"], ref.e_d2) <= TOL
+    assert rel(e["e_m2"] - e["de_m2"], ref.e_m2_0) <= TOL
+    assert abs(s["e_total"] - ref.e_total) <= TOL * abs(ref.e_total)
+    assert s["polish_sweeps"] < ref.sweeps
+
+
+def test_mixed_precision_polish_cube(ctx):
+    with open(os.path.join(GOLDEN, "lccd-hf-5x5x5-c2.json")) as f:
+        g = json.load(f)
+    p, ints = make_lccd_workload("hf-5x5x5-c2")
+    s, e = run_gpu(ctx, p, ints, tol=g["tol"], max_sweeps=400, precision=mc.MCPT_BF16, polish=1)
+    assert s["return"] == mc.MCPT_OK, s["error"]
+    assert s["iso_sweeps"] == g["iso_sweeps"]
+    assert abs(s["e_total"] - g["e_total"]) <= TOL * abs(g["e_total"])
+    assert rel(e["e_m2"], g["e_m2"]) <= TOL and rel(e["e_m2"] - e["de_m2"], g["e_lccd"]) <= TOL
+
+
 def test_no_pairs_shift_is_zero(ctx):
     p, ints = ragged()
     q = p.subset_pairs(np.zeros(p.n_pair, dtype=bool))
@@ -193,9 +221,8 @@ def test_errors(ctx):
         ctx.lccd_attach(pid, bad)
     assert ei.value.status == mc.MCPT_ERR_NONFINITE
     ctx.lccd_attach(pid, ints)
-    for opts in (dict(precision=mc.MCPT_BF16), dict(precision=mc.MCPT_FP32), dict(deterministic=1)):
-        r = ctx.run(pid, tol=TOL, raise_on_error=False, **opts)
-        assert r["return"] == mc.MCPT_ERR_INVALID, opts
+    r = ctx.run(pid, tol=TOL, raise_on_error=False, deterministic=1)
+    assert r["return"] == mc.MCPT_ERR_INVALID
     r = ctx.run(pid, tol=TOL, max_sweeps=3, raise_on_error=False)
     assert r["return"] == mc.MCPT_ERR_NOT_CONVERGED and r["sweeps"] == 3
     with pytest.raises(mc.MCPTError) as ei:
