@@ -275,7 +275,7 @@ mcpt_status mcpt_singles_result(mcpt_ctx *ctx, uint64_t id, double *e_m1, double
  * in FP64 in every sweep, and in polish mode also for each correction (of the
  * correction's own amplitudes); step 5 runs in FP64.  No deterministic mode.  Dimer amplitudes keep the terms of Eq. 59
  * listed at the top (its dimer-internal terms need dimer integral classes that
- * are not inputs).  Sizes per monomer: v <= 64 and o v <= 1024. */
+ * are not inputs).  Sizes per monomer: o <= 8, v <= 64 and o v <= 1024. */
 typedef struct {
     const double *w_vvvv;   /* sum_X v_X^4: W_X[a][b][c][d] = <ab|cd>, row-major, monomers in upload order */
     const double *q_oooo;   /* sum_X o_X^4: Q_X[i][j][k][l] = <ij|kl> */

@@ -1049,9 +1049,9 @@ mcpt_status lccd_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_lccd_integ
     int max_rows = 16, max_o = 1, max_np = 16;
     for (int m = 0; m < R->n_mono; ++m) {
         const MonoDesc& d = R->monos[m];
-        if (d.v > 64 || d.np > kLccdMaxNp)
+        if (d.o > 8 || d.v > 64 || d.np > kLccdMaxNp)
             return fail(MCPT_ERR_INVALID, "monomer " + std::to_string(m) +
-                                              ": the full monomer equation supports v <= 64 and o v <= 1024");
+                                              ": the full monomer equation supports o <= 8, v <= 64, o v <= 1024");
         const int v2 = d.v * d.v, rows = round_up(v2, 16), cols = round_up(v2, 32);
         ld[m] = LccdDesc{w_pack, nw, nq, rows, cols};
         w_pack += (int64_t)rows * cols;

@@ -229,12 +229,13 @@ def test_errors(ctx):
         ctx.lccd_attach(pid + 10**6, ints)
     assert ei.value.status == mc.MCPT_ERR_UNKNOWN_ID
     ctx.release(pid)
-    wide, wi = ragged(sizes=((1, 65),))
-    pid = ctx.upload(wide)
-    with pytest.raises(mc.MCPTError) as ei:
-        ctx.lccd_attach(pid, wi)
-    assert ei.value.status == mc.MCPT_ERR_INVALID
-    ctx.release(pid)
+    for sizes in (((1, 65),), ((9, 3),)):   # v above 64, o above 8
+        wide, wi = ragged(sizes=sizes)
+        pid = ctx.upload(wide)
+        with pytest.raises(mc.MCPTError) as ei:
+            ctx.lccd_attach(pid, wi)
+        assert ei.value.status == mc.MCPT_ERR_INVALID
+        ctx.release(pid)
 
 
 def test_step5_divergence_detected(ctx):
