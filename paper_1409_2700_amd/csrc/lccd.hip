@@ -322,39 +322,59 @@ __device__ void ladder_task(const LadderView& g, int tr0, int tc0, int lane) {
     }
 }
 
-// L += R + R^T with R = R12 - Vs(Y), by v x v block pairs {(i,j), (j,i)}: the
-// four blocks of R12 and Y are read once, row-contiguous, and the transposed
-// elements come from LDS (sbuf: 4 v (v + 1) doubles), as in the monomer update.
-__device__ void add_rings(const LadderView& g, double* sbuf) {
-    const int o = g.o, v = g.v, np = g.np, vs = v + 1;
-    double* r0 = sbuf;                 // R12 block (i,j)
-    double* r1 = r0 + v * vs;          // R12 block (j,i)
-    double* y0 = r1 + v * vs;          // Y block (i,j)
-    double* y1 = y0 + v * vs;          // Y block (j,i)
-    for (int i = 0; i < o; ++i)
-        for (int j = i; j < o; ++j) {
-            __syncthreads();
-            for (int e = threadIdx.x; e < v * v; e += blockDim.x) {
-                const int a = e / v, b = e - a * v;
-                const int64_t ij = (int64_t)(i * v + a) * np + j * v + b, ji = (int64_t)(j * v + a) * np + i * v + b;
-                r0[a * vs + b] = g.R12[ij];
-                r1[a * vs + b] = g.R12[ji];
-                y0[a * vs + b] = g.Y[ij];
-                y1[a * vs + b] = g.Y[ji];
-            }
-            __syncthreads();
-            for (int e = threadIdx.x; e < v * v; e += blockDim.x) {
-                const int a = e / v, b = e - a * v;
-                const int64_t e1 = (int64_t)(i * v + a) * np + j * v + b;
-                // (i,a),(j,b): R12[(i,a),(j,b)] - Y[(i,b),(j,a)] + R12[(j,b),(i,a)] - Y[(j,a),(i,b)]
-                g.L[e1] += (r0[a * vs + b] - y0[b * vs + a]) + (r1[b * vs + a] - y1[a * vs + b]);
-                if (i != j) {
-                    const int64_t e2 = (int64_t)(j * v + a) * np + i * v + b;
-                    // (j,a),(i,b): R12[(j,a),(i,b)] - Y[(j,b),(i,a)] + R12[(i,b),(j,a)] - Y[(i,a),(j,b)]
-                    g.L[e2] += (r1[a * vs + b] - y1[b * vs + a]) + (r0[b * vs + a] - y0[a * vs + b]);
-                }
+// L += R + R^T with R = R12 - Vs(Y), by v x v block pairs {(i,j), (j,i)}, i <= j:
+// the four blocks of R12 and Y of a block pair are read once, row-contiguous,
+// and the transposed elements come from LDS (4 v (v + 1) doubles per block
+// pair); as many block pairs as fit in lds_doubles go per round, so the loads
+// of a round are all in flight together.
+__device__ inline void block_pair(int p, int o, int* i, int* j) {
+    int r = 0;
+    while (p >= o - r) {   // row r of the upper triangle holds o - r pairs
+        p -= o - r;
+        ++r;
+    }
+    *i = r;
+    *j = r + p;
+}
+
+__device__ void add_rings(const LadderView& g, double* sbuf, int lds_doubles) {
+    const int o = g.o, v = g.v, np = g.np, vs = v + 1, vv = v * v;
+    const int per = 4 * v * vs;
+    const int npairs = o * (o + 1) / 2;
+    const int cap = lds_doubles / per > 0 ? lds_doubles / per : 1;
+    for (int p0 = 0; p0 < npairs; p0 += cap) {
+        const int cnt = npairs - p0 < cap ? npairs - p0 : cap;
+        __syncthreads();
+        for (int e = threadIdx.x; e < cnt * vv; e += blockDim.x) {
+            const int q = e / vv, ab = e - q * vv, a = ab / v, b = ab - a * v;
+            int i, j;
+            block_pair(p0 + q, o, &i, &j);
+            double* r0 = sbuf + (int64_t)q * per;   // R12 block (i,j), R12 block (j,i), Y (i,j), Y (j,i)
+            const int64_t ij = (int64_t)(i * v + a) * np + j * v + b, ji = (int64_t)(j * v + a) * np + i * v + b;
+            r0[a * vs + b] = g.R12[ij];
+            r0[v * vs + a * vs + b] = g.R12[ji];
+            r0[2 * v * vs + a * vs + b] = g.Y[ij];
+            r0[3 * v * vs + a * vs + b] = g.Y[ji];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < cnt * vv; e += blockDim.x) {
+            const int q = e / vv, ab = e - q * vv, a = ab / v, b = ab - a * v;
+            int i, j;
+            block_pair(p0 + q, o, &i, &j);
+            const double* r0 = sbuf + (int64_t)q * per;
+            const double* r1 = r0 + v * vs;
+            const double* y0 = r1 + v * vs;
+            const double* y1 = y0 + v * vs;
+            const int64_t e1 = (int64_t)(i * v + a) * np + j * v + b;
+            // (i,a),(j,b): R12[(i,a),(j,b)] - Y[(i,b),(j,a)] + R12[(j,b),(i,a)] - Y[(j,a),(i,b)]
+            g.L[e1] += (r0[a * vs + b] - y0[b * vs + a]) + (r1[b * vs + a] - y1[a * vs + b]);
+            if (i != j) {
+                const int64_t e2 = (int64_t)(j * v + a) * np + i * v + b;
+                // (j,a),(i,b): R12[(j,a),(i,b)] - Y[(j,b),(i,a)] + R12[(i,b),(j,a)] - Y[(i,a),(j,b)]
+                g.L[e2] += (r1[a * vs + b] - y1[b * vs + a]) + (r0[b * vs + a] - y0[a * vs + b]);
             }
         }
+    }
 }
 
 // All blocks of one monomer run on one XCD (block b -> XCD b % 8), so the
@@ -406,7 +426,7 @@ __global__ __launch_bounds__(kLccdThreads, 2) void lccd_ladder_kernel(
 // epilogues fetched a 128-byte line for every 8 bytes used).
 template <int CT>
 __global__ __launch_bounds__(kLadLdsThreads) void lccd_ladder_lds_kernel(
-    const MonoDesc* __restrict__ monos, const LccdDesc* __restrict__ ld,
+    const MonoDesc* __restrict__ monos, const LccdDesc* __restrict__ ld, int lds_doubles,
     const double* __restrict__ W, const double* __restrict__ Q, const double* __restrict__ T,
     const double* __restrict__ R12, const double* __restrict__ Y, double* __restrict__ L,
     const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
@@ -460,7 +480,7 @@ __global__ __launch_bounds__(kLadLdsThreads) void lccd_ladder_lds_kernel(
         ladder_task<RT, CT, 4, false>(g, (task / ngroups) * RT, (task % ngroups) * CT, lane);
     // every wave is done with the staged amplitudes and its L stores are visible to the workgroup
     __syncthreads();
-    add_rings(g, lds);
+    add_rings(g, lds, lds_doubles);
 }
 
 }  // namespace
@@ -523,8 +543,8 @@ void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, i
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lccd_lds_limit());         \
             attr = true;                                                                                         \
         }                                                                                                        \
-        hipLaunchKernelGGL(lccd_ladder_lds_kernel<C>, grid, block, (size_t)lds_bytes, s, monos, ld, W, Q, T, R12, \
-                           Y, L, ctrl, cl);                                                                      \
+        hipLaunchKernelGGL(lccd_ladder_lds_kernel<C>, grid, block, (size_t)lds_bytes, s, monos, ld,            \
+                           (int)(lds_bytes / 8), W, Q, T, R12, Y, L, ctrl, cl);                                  \
         return;                                                                                                  \
     }
             LDS_CASE(1)
