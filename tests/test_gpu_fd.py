@@ -118,3 +118,33 @@ def test_base_results_kept_and_errors(ctx):
         ctx.fd_stencil(base, modes, cell, 0.01, tol=SOLVE_TOL)
     assert ei.value.status == mc.MCPT_ERR_INVALID
     ctx.release(base)
+
+
+def test_degenerate_mode_and_batch_copy(ctx):
+    """A mode that moves nothing (no pairs rescaled) has five equal energies and
+    a zero second derivative; a scaled copy of a batch equals the host-scaled batch."""
+    p = make_workload("hf-2x2x2")
+    cell = central_cell(p)
+    base = ctx.upload(p)
+    empty = np.zeros((4, 0))
+    r = ctx.fd_stencil(base, [(np.zeros(0, dtype=np.int64), empty)], cell, 0.01, tol=SOLVE_TOL)[0]
+    ctx.release(base)
+    assert r["status"] == mc.MCPT_OK
+    assert max(r["e"]) - min(r["e"]) <= 1e-12 * abs(r["e"][2])
+    assert abs(r["d2e"]) <= 1e-6
+    a = make_lattice_problem(cubic_sites(2, 2, 1), None, sizes=[(2, 3), (3, 4), (2, 2), (1, 5)], workload=930,
+                             coupling_scale=1.0)
+    b = make_workload("hf-2x2x2")
+    pairs = np.array([a.n_pair + 1, a.n_pair + 5, 2], dtype=np.int64)   # two pairs of the second cluster, one of the first
+    f = np.array([1.01, 0.97, 1.03])
+    pid = ctx.upload_batch([a, b])
+    dev = ctx.upload_scaled(pid, pairs, f)
+    host = ctx.upload_batch([scaled_problem(a, [2], [1.03]), scaled_problem(b, [1, 5], [1.01, 0.97])])
+    sd = ctx.run(dev, tol=SOLVE_TOL)
+    ed = ctx.energy(dev)
+    sh = ctx.run(host, tol=SOLVE_TOL)
+    eh = ctx.energy(host)
+    for q in (dev, host, pid):
+        ctx.release(q)
+    assert sd["sweeps"] == sh["sweeps"]
+    assert rel(ed["e_m2"], eh["e_m2"]) <= 1e-14 and rel(ed["e_d2"], eh["e_d2"]) <= 1e-14
