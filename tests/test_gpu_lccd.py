@@ -245,3 +245,24 @@ def test_step5_divergence_detected(ctx):
     s, _ = run_gpu(ctx, p, ints, tol=TOL, max_sweeps=200)
     assert st == mc.MCPT_ERR_DIVERGED
     assert s["return"] == mc.MCPT_ERR_DIVERGED
+
+
+def test_relabelling_and_power_of_two_scaling(ctx):
+    """Monomers relabelled with every other pair stored reversed give the same
+    energies (permuted); eps and every integral times 8 give T unchanged and
+    energies times 8 (to rounding: the pair contributions are added by atomics)."""
+    p, ints = ragged(sizes=((2, 3), (5, 27), (3, 17), (4, 9)), workload=923)
+    perm = np.array([2, 0, 3, 1])
+    q = p.relabel(perm, np.arange(p.n_pair) % 2 == 0)
+    s0, e0 = run_gpu(ctx, p, ints, tol=1e-12, max_sweeps=300)
+    s1, e1 = run_gpu(ctx, q, ints.subset(perm), tol=1e-12, max_sweeps=300)
+    assert s0["return"] == s1["return"] == mc.MCPT_OK
+    assert abs(s1["e_total"] - s0["e_total"]) <= 1e-12 * abs(s0["e_total"])
+    assert rel(e1["e_m2"], e0["e_m2"][perm]) <= 1e-12 and rel(e1["de_m2"], e0["de_m2"][perm]) <= 1e-10
+    p8, i8 = ragged(sizes=((2, 3), (5, 27), (3, 17), (4, 9)), workload=923)
+    for a in (p8.eps, p8.k, p8.v, i8.w, i8.q, i8.j):
+        a *= 8.0
+    s8, e8 = run_gpu(ctx, p8, i8, tol=0.0, max_sweeps=4)
+    s0f, e0f = run_gpu(ctx, p, ints, tol=0.0, max_sweeps=4)
+    assert rel(e8["t"], e0f["t"]) <= 1e-13
+    assert rel(e8["e_m2"], 8.0 * e0f["e_m2"]) <= 1e-13 and rel(e8["e_d2"], 8.0 * e0f["e_d2"]) <= 1e-13
