@@ -266,3 +266,18 @@ def test_relabelling_and_power_of_two_scaling(ctx):
     s0f, e0f = run_gpu(ctx, p, ints, tol=0.0, max_sweeps=4)
     assert rel(e8["t"], e0f["t"]) <= 1e-13
     assert rel(e8["e_m2"], 8.0 * e0f["e_m2"]) <= 1e-13 and rel(e8["e_d2"], 8.0 * e0f["e_d2"]) <= 1e-13
+
+
+def test_largest_supported_monomer(ctx):
+    """The size limits of the full monomer equation: o = 8 (64 hole pairs, four
+    column tiles) and v = 64 (v^2 = 4096 columns, the whole offset table; o v =
+    512, 32 tiles per edge with a ragged super-block row), beside the smallest
+    monomer; one sweep element by element."""
+    p, ints = ragged(sizes=((8, 64), (1, 1), (5, 27)), scale=0.3, workload=924)
+    print(f"[gpu] lccd largest monomer N={p.n_mono} P={p.n_pair}", flush=True)
+    ref = mcpt_lccd.solve(p, ints, tol=0.0, max_sweeps=1)
+    s, e = run_gpu(ctx, p, ints, tol=0.0, max_sweeps=1)
+    assert s["return"] == mc.MCPT_OK, s["error"]
+    assert rel(e["t"], flat_t(ref)) <= TOL
+    assert rel(e["e_m2"], ref.e_m2) <= TOL and rel(e["e_d2"], ref.e_d2) <= TOL
+    assert rel(e["e_m2"] - e["de_m2"], ref.e_m2_0) <= TOL
