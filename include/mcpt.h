@@ -307,7 +307,8 @@ mcpt_status mcpt_lccd_attach(mcpt_ctx *ctx, uint64_t id, const mcpt_lccd_integra
  * listed pairs (indices into base's pair list, each at most once) multiplied
  * by scale[k] (finite).  Arrays are read before the call returns.  The copy
  * holds its own device memory (as much as the base's plain upload) until
- * mcpt_release.  Errors: MCPT_ERR_INVALID (NULL array, index out of range or
+ * mcpt_release; it carries the base's inputs only (not its results, singles
+ * source or attached intramonomer integrals).  Errors: MCPT_ERR_INVALID (NULL array, index out of range or
  * repeated), MCPT_ERR_NONFINITE, MCPT_ERR_ADMISSION, MCPT_ERR_NOMEM,
  * MCPT_ERR_UNKNOWN_ID, MCPT_ERR_DEVICE. */
 mcpt_status mcpt_upload_scaled(mcpt_ctx *ctx, uint64_t base, int64_t n, const int64_t *pair, const double *scale,
