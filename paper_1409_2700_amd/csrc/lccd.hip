@@ -88,7 +88,7 @@ __global__ void lccd_pack_kernel(const MonoDesc* __restrict__ monos, const LccdD
 // One wave task: a super-block of up to 3 x 3 output tiles of either
 // R12 = K M - J T (kind 0) or Y = J Vs(T) (kind 1).  Rows or columns past the
 // padded edge are clamped for the loads and skipped for the stores.
-__global__ __launch_bounds__(kLccdThreads) void lccd_ring_kernel(
+__global__ __launch_bounds__(kLccdThreads, 2) void lccd_ring_kernel(
     const MonoDesc* __restrict__ monos, int n_mono, int blocks_per_mono, const double* __restrict__ K,
     const double* __restrict__ J, const double* __restrict__ T, const double* __restrict__ M,
     double* __restrict__ R12, double* __restrict__ Y, const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
@@ -134,40 +134,54 @@ __global__ __launch_bounds__(kLccdThreads) void lccd_ring_kernel(
         for (int u = 0; u < kRingSB; ++u)
 #pragma unroll
             for (int w = 0; w < kRingSB; ++w) acc[u][w] = d4(0.0);
-        // kind 0: two products into one accumulator, the second with -J
-        const int nprod = kind == 0 ? 2 : 1;
-        for (int pr = 0; pr < nprod; ++pr) {
+        // kind 0: two products into one accumulator, the second with -J.  The k
+        // chunks of the products run as one sequence with the next chunk's
+        // operands in flight (the load past the last chunk repeats the last one
+        // instead of being branched around, so waits stay in issue order).
+        const int nk = np / 16;
+        const int nchunk = (kind == 0 ? 2 : 1) * nk;
+        d4 an[kRingSB];
+        double bn[kRingSB][4];
+        auto load_chunk = [&](int ch) {
+            const int pr = ch / nk, k0 = (ch - pr * nk) * 16;
             const double* A = (kind == 0 && pr == 0) ? Kx : Jx;
-            const double sgn = (kind == 0 && pr == 1) ? -1.0 : 1.0;
-            const double* B = (kind == 0 && pr == 0) ? Mx : Tx;
-            for (int k0 = 0; k0 < np; k0 += 16) {
-                double a[kRingSB][4], b[kRingSB][4];
 #pragma unroll
-                for (int u = 0; u < kRingSB; ++u) {
-                    const d4 av = load4(A + (int64_t)arow[u] * np + k0 + lk);
-                    a[u][0] = sgn * av.x;
-                    a[u][1] = sgn * av.y;
-                    a[u][2] = sgn * av.z;
-                    a[u][3] = sgn * av.w;
-                }
-                if (kind == 0) {
+            for (int u = 0; u < kRingSB; ++u) an[u] = load4(A + (int64_t)arow[u] * np + k0 + lk);
+            if (kind == 0) {
+                const double* B = pr == 0 ? Mx : Tx;
 #pragma unroll
-                    for (int w = 0; w < kRingSB; ++w)
+                for (int w = 0; w < kRingSB; ++w)
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) b[w][s] = B[(int64_t)(k0 + lk + s) * np + bcol[w]];
-                } else {
+                    for (int s = 0; s < 4; ++s) bn[w][s] = B[(int64_t)(k0 + lk + s) * np + bcol[w]];
+            } else {
 #pragma unroll
-                    for (int w = 0; w < kRingSB; ++w)
+                for (int w = 0; w < kRingSB; ++w)
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) b[w][s] = Tx[kofs[k0 + lk + s] + ycol[w]];
-                }
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-#pragma unroll
-                    for (int u = 0; u < kRingSB; ++u)
-#pragma unroll
-                        for (int w = 0; w < kRingSB; ++w) acc[u][w] = mfma(a[u][s], b[w][s], acc[u][w]);
+                    for (int s = 0; s < 4; ++s) bn[w][s] = Tx[kofs[k0 + lk + s] + ycol[w]];
             }
+        };
+        load_chunk(0);
+        for (int ch = 0; ch < nchunk; ++ch) {
+            const double sgn = (kind == 0 && ch >= nk) ? -1.0 : 1.0;
+            double a[kRingSB][4], b[kRingSB][4];
+#pragma unroll
+            for (int u = 0; u < kRingSB; ++u) {
+                a[u][0] = sgn * an[u].x;
+                a[u][1] = sgn * an[u].y;
+                a[u][2] = sgn * an[u].z;
+                a[u][3] = sgn * an[u].w;
+            }
+#pragma unroll
+            for (int w = 0; w < kRingSB; ++w)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) b[w][s] = bn[w][s];
+            load_chunk(ch + 1 < nchunk ? ch + 1 : ch);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int u = 0; u < kRingSB; ++u)
+#pragma unroll
+                    for (int w = 0; w < kRingSB; ++w) acc[u][w] = mfma(a[u][s], b[w][s], acc[u][w]);
         }
         double* out = (kind == 0 ? R12 : Y) + d.mat_off;
 #pragma unroll
