@@ -39,7 +39,7 @@ constexpr int kRingSB = 3;          // ring super-block edge in tiles
 constexpr int kLadRT = 4;           // ladder row tiles per wave task
 constexpr int kLadCT = 4;           // ladder column tiles per task at most (the launch takes ceil(o^2 / 16))
 constexpr int kXcds = 8;            // XCDs of the chip; workgroup b runs on XCD b % 8
-constexpr int kLadLdsThreads = 512; // LDS-staged ladder: eight wavefronts, one workgroup per CU
+constexpr int kLadLdsThreads = 768; // LDS-staged ladder: twelve wavefronts (three per SIMD), one workgroup per CU
 
 __device__ inline d4 mfma(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -491,7 +491,7 @@ __global__ __launch_bounds__(kLadLdsThreads) void lccd_ladder_lds_kernel(
     const int tasks = ntask_r * ngroups;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int task = wave; task < tasks; task += kLadLdsThreads / 64)
-        ladder_task<RT, CT, 4, false>(g, (task / ngroups) * RT, (task % ngroups) * CT, lane);
+        ladder_task<RT, CT, 2, false>(g, (task / ngroups) * RT, (task % ngroups) * CT, lane);
     // every wave is done with the staged amplitudes and its L stores are visible to the workgroup
     __syncthreads();
     add_rings(g, lds, lds_doubles);
