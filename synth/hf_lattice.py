@@ -505,6 +505,96 @@ def make_lccd_workload(name: str, coupling_scale: float = DEFAULT_COUPLING_SCALE
 
 
 # ---------------------------------------------------------------------------
+# dimer integral classes of the dimer-internal terms (Eq. 59)
+# ---------------------------------------------------------------------------
+KIND_DIMER = 6
+SIGMA_DIMER = 0.01
+
+
+@dataclasses.dataclass
+class DimerIntegrals:
+    """Per-pair integral classes of the dimer-internal terms of Eq. 59, flat and
+    concatenated over the stored pairs (X = the first monomer of the pair), the
+    layout the C ABI takes:
+
+    w:  W_XY[a][b][a1][b1]   = <a b|a1 b1> = (a a1|b b1), (vX, vY, vX, vY)
+    q:  Q_XY[i1][j1][i][j]   = <i1 j1|i j> = (i1 i|j1 j), (oX, oY, oX, oY)
+    cx: C_X[i1][i][b][b1]    = (i1 i|b b1), X occupied and Y virtual, (oX, oX, vY, vY)
+    cy: C_Y[j1][j][a][a1]    = (j1 j|a a1), Y occupied and X virtual, (oY, oY, vX, vX)
+    """
+    shapes: np.ndarray    # (n_pair, 4): oX, vX, oY, vY
+    w: np.ndarray
+    q: np.ndarray
+    cx: np.ndarray
+    cy: np.ndarray
+
+    def __post_init__(self):
+        sh = np.asarray(self.shapes, dtype=np.int64).reshape(-1, 4)
+        ox, vx, oy, vy = sh[:, 0], sh[:, 1], sh[:, 2], sh[:, 3]
+        off = lambda n: np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+        self.w_off = off(vx * vy * vx * vy)
+        self.q_off = off(ox * oy * ox * oy)
+        self.cx_off = off(ox * ox * vy * vy)
+        self.cy_off = off(oy * oy * vx * vx)
+
+    @property
+    def n_pair(self) -> int:
+        return int(np.asarray(self.shapes).reshape(-1, 4).shape[0])
+
+    def _sh(self, p):
+        return (int(t) for t in np.asarray(self.shapes).reshape(-1, 4)[p])
+
+    def w_of(self, p: int) -> np.ndarray:
+        ox, vx, oy, vy = self._sh(p)
+        return self.w[self.w_off[p]:self.w_off[p + 1]].reshape(vx, vy, vx, vy)
+
+    def q_of(self, p: int) -> np.ndarray:
+        ox, vx, oy, vy = self._sh(p)
+        return self.q[self.q_off[p]:self.q_off[p + 1]].reshape(ox, oy, ox, oy)
+
+    def cx_of(self, p: int) -> np.ndarray:
+        ox, vx, oy, vy = self._sh(p)
+        return self.cx[self.cx_off[p]:self.cx_off[p + 1]].reshape(ox, ox, vy, vy)
+
+    def cy_of(self, p: int) -> np.ndarray:
+        ox, vx, oy, vy = self._sh(p)
+        return self.cy[self.cy_off[p]:self.cy_off[p + 1]].reshape(oy, oy, vx, vx)
+
+    def nbytes(self) -> int:
+        return int(self.w.nbytes + self.q.nbytes + self.cx.nbytes + self.cy.nbytes)
+
+
+def dimer_integrals(prob: Problem, *, workload: int | None = None, cluster: int | None = None,
+                    sigma: float = SIGMA_DIMER) -> DimerIntegrals:
+    """Seeded stand-ins for the dimer classes (vX vX|vY vY), (oX oX|oY oY),
+    (oX oX|vY vY) and (oY oY|vX vX) of every stored pair, drawn N(0, s^2) with
+    s = sigma (R_nn / R)^3 like the pair blocks and symmetrised as real orbitals
+    require within each charge distribution ((pr|qs) = (rp|qs) = (pr|sq)).  Keyed
+    by the workload, the cluster and the two lattice sites."""
+    wl = int(prob.meta.get("workload", 0) if workload is None else workload)
+    cl = int(prob.meta.get("cluster", 0) if cluster is None else cluster)
+    sites = prob.sites if prob.sites is not None else np.stack([np.arange(prob.n_mono), np.zeros(prob.n_mono),
+                                                                np.zeros(prob.n_mono)], axis=1).astype(np.int64)
+    shapes, ws, qs, cxs, cys = [], [], [], [], []
+    for (x, y) in prob.pairs:
+        ox, vx, oy, vy = int(prob.n_occ[x]), int(prob.n_vir[x]), int(prob.n_occ[y]), int(prob.n_vir[y])
+        r = float(np.linalg.norm((np.asarray(sites[x]) - np.asarray(sites[y])).astype(np.float64))) or 1.0
+        s = sigma / r ** 3
+        rng = _rng(wl, cl, KIND_DIMER, *sites[x], *sites[y])
+        g_vv = _symmetrised(rng, (vx, vx, vy, vy), _GROUP4, s)      # (a a1|b b1)
+        g_oo = _symmetrised(rng, (ox, ox, oy, oy), _GROUP4, s)      # (i1 i|j1 j)
+        g_ov = _symmetrised(rng, (ox, ox, vy, vy), _GROUP4, s)      # (i1 i|b b1)
+        g_vo = _symmetrised(rng, (oy, oy, vx, vx), _GROUP4, s)      # (j1 j|a a1)
+        shapes.append((ox, vx, oy, vy))
+        ws.append(np.ascontiguousarray(g_vv.transpose(0, 2, 1, 3)).ravel())   # <a b|a1 b1>
+        qs.append(np.ascontiguousarray(g_oo.transpose(0, 2, 1, 3)).ravel())   # <i1 j1|i j>
+        cxs.append(g_ov.ravel())
+        cys.append(g_vo.ravel())
+    cat = lambda parts: np.concatenate(parts) if parts else np.zeros(0)
+    return DimerIntegrals(np.asarray(shapes, dtype=np.int64).reshape(-1, 4), cat(ws), cat(qs), cat(cxs), cat(cys))
+
+
+# ---------------------------------------------------------------------------
 # finite-displacement modes (Sec. IV.A: symmetric stretches of the molecules of
 # a unit cell, five-point grid)
 # ---------------------------------------------------------------------------
