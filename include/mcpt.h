@@ -147,6 +147,13 @@ typedef struct {
     double  lccd_w_bytes;   /* <ab|cd> integral bytes those launches streamed (8 v^4 per monomer, rows
                                padded to 16) */
     double  lccd_ladder_flops; /* algorithmic flops of their particle-particle ladders (2 o^2 v^4 per monomer) */
+    double  dimer_ladder_ms;/* dimer-internal terms (mcpt_dimer_attach): summed duration of the pair ladder
+                               launches (X-vv|Y-vv and oo|oo ladders of Eq. 59) */
+    double  dimer_ring_ms;  /* summed duration of the dimer ring launches (monomer and cross rings of Eq. 59) */
+    int64_t dimer_launches; /* pair ladder launches */
+    double  dimer_w_bytes;  /* <a b|a1 b1> integral bytes those launches streamed (8 vX vY vX vY per pair,
+                               rows padded to 16) */
+    double  dimer_ladder_flops; /* algorithmic flops of their X-vv|Y-vv ladders (2 oX oY vX^2 vY^2 per pair) */
 } mcpt_timing;
 
 /* Create a context on HIP device `device`; at most hbm_budget_bytes of device
@@ -294,6 +301,41 @@ typedef struct {
  * for deterministic = 1, and MCPT_ERR_DIVERGED (no results) when step 5
  * diverges for any cluster. */
 mcpt_status mcpt_lccd_attach(mcpt_ctx *ctx, uint64_t id, const mcpt_lccd_integrals *ints);
+
+/* ---- Dimer-internal terms of the dimer equation (Eq. 59) ----
+ * The terms of Eq. 59 that act on the dimer amplitudes themselves: the
+ * X-vv|Y-vv ladder v^{ab}_{a1 b1} Tau^{a1 b1}_{ij}, the oo|oo ladder
+ * v^{i1 j1}_{ij} Tau^{ab}_{i1 j1}, the cross rings -v^{b i1}_{b1 i} Tau^{a b1}_{i1 j}
+ * and -v^{a j1}_{a1 j} Tau^{a1 b}_{i j1}, and the monomer rings
+ * (2 v^{i1 a}_{a1 i} - v^{a i1}_{a1 i}) Tau^{a1 b}_{i1 j} and their Y mirror (K and
+ * the J of mcpt_lccd_attach).  With them Tau is an unknown of its own: each
+ * coupled sweep forms Eq. 59 from the current T and the previous sweep's Tau
+ * (zero before the first), then Eq. 58 from the new Tau; the final energies use
+ * one more Eq. 59 step.  Per stored pair (X its first monomer), all row-major
+ * FP64, concatenated over the pairs in the caller's pair order: */
+typedef struct {
+    const double *w_vvvv;   /* vX vY vX vY: W_XY[a][b][a1][b1] = <a b|a1 b1> = (a a1|b b1) */
+    const double *q_oooo;   /* oX oY oX oY: Q_XY[i1][j1][i][j] = <i1 j1|i j> = (i1 i|j1 j) */
+    const double *c_x;      /* oX oX vY vY: C_X[i1][i][b][b1] = (i1 i|b b1) */
+    const double *c_y;      /* oY oY vX vX: C_Y[j1][j][a][a1] = (j1 j|a a1) */
+    int32_t       memory;   /* mcpt_memory of the four arrays */
+} mcpt_dimer_integrals;
+
+/* Attach (ints != NULL) or detach (NULL) the dimer classes of a resident
+ * problem whose intramonomer integrals are attached (mcpt_lccd_attach; detaching
+ * those, or attaching them again, detaches these too).  Every monomer must have
+ * the same o <= 6 and v <= 64 with its n x n amplitudes within 160 KiB (o = 5,
+ * v = 27 is 146 KB) and the problem at most 65,535 pairs.  The arrays are read
+ * before the call returns; the packed copies (W_XY as vX vY rows padded to 16,
+ * columns to 32: ~8 v^4 bytes per pair), Q_XY, the packed C_X and C_Y and two
+ * np x np matrices per pair (Tau and its source) stay with the problem and
+ * count against the budget.  The problem's last results are dropped.  mcpt_run
+ * of an attached problem accepts only the FP64 form (precision MCPT_FP64);
+ * results are reproducible to rounding (the ring terms add with atomics).
+ * Errors: MCPT_ERR_INVALID (NULL array, memory, no intramonomer integrals,
+ * sizes), MCPT_ERR_NONFINITE, MCPT_ERR_ADMISSION, MCPT_ERR_NOMEM,
+ * MCPT_ERR_UNKNOWN_ID, MCPT_ERR_DEVICE. */
+mcpt_status mcpt_dimer_attach(mcpt_ctx *ctx, uint64_t id, const mcpt_dimer_integrals *ints);
 
 /* ---- Finite-displacement geometries (Sec. IV.A: harmonic frequencies from
  * single points on a five-point grid, step 0.01 A in the paper) ----

@@ -81,7 +81,23 @@ void drop_graph(Resident* r) {
     r->graph_prec = -1;
 }
 
+void free_dimer(mcpt_ctx* c, Resident* r) {
+    for (void* p : r->dimer_allocations) (void)hipFree(p);
+    r->dimer_allocations.clear();
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        c->in_use -= std::min(c->in_use, r->dimer_bytes);
+    }
+    r->dimer_bytes = 0;
+    r->dimer = false;
+    r->d_dd = nullptr;
+    r->d_pmono = nullptr;
+    r->d_plccd = nullptr;
+    r->d_DW = r->d_DQ = r->d_DCX = r->d_DCY = r->d_Tau = r->d_S = nullptr;
+}
+
 void free_lccd(mcpt_ctx* c, Resident* r) {
+    free_dimer(c, r);
     for (void* p : r->lccd_allocations) (void)hipFree(p);
     r->lccd_allocations.clear();
     {
@@ -185,6 +201,13 @@ void drain_timing(Timing& t) {
                 t.tot.lccd_launches += 1;
                 t.tot.lccd_w_bytes += r.vbytes;
                 t.tot.lccd_ladder_flops += r.flops;
+            } else if (r.kind == 6) {
+                t.tot.dimer_ladder_ms += ms;
+                t.tot.dimer_launches += 1;
+                t.tot.dimer_w_bytes += r.vbytes;
+                t.tot.dimer_ladder_flops += r.flops;
+            } else if (r.kind == 7) {
+                t.tot.dimer_ring_ms += ms;
             } else {
                 t.tot.mono_ms += ms;
                 t.tot.mono_launches += 1;
@@ -634,8 +657,24 @@ void record_end(Exec& x, hipEvent_t a, int kind, double flops, double vbytes) {
 void pair_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int couple, const Ctrl* ctrl) {
     const ClState* cl = ctrl ? R->d_cl : nullptr;   // the final energy pass covers every cluster
     const bool det = R->det_on && couple;
-    const PartOut p0{det ? R->d_part : nullptr, R->d_part_off};
-    const PartOut p1{det ? R->d_part : nullptr, R->d_part_off ? R->d_part_off + R->n_lds : nullptr};
+    PartOut p0{det ? R->d_part : nullptr, R->d_part_off};
+    PartOut p1{det ? R->d_part : nullptr, R->d_part_off ? R->d_part_off + R->n_lds : nullptr};
+    if (R->dimer) {
+        // dimer-internal terms of Eq. 59 from the previous Tau into S: the two ladders (stored), then the
+        // rings (added); the pair kernels add S into the numerator of Tau and keep the new Tau
+        hipEvent_t a = nullptr;
+        record_begin(x, &a);
+        launch_lccd_ladder(R->d_pmono, R->d_plccd, (int)R->n_pair, 1, R->dimer_ct, R->dimer_lds_bytes, R->d_DW,
+                           R->d_DQ, R->d_Tau, nullptr, nullptr, R->d_S, ctrl, cl, x.stream, 0);
+        record_end(x, a, 6, R->dimer_w_flops, R->dimer_w_bytes);
+        record_begin(x, &a);
+        launch_dimer_ring(R->d_dd, R->d_monos, R->d_pmono, (int)R->n_pair, R->dimer_ring_blocks, R->d_K, R->d_J,
+                          R->d_DCX, R->d_DCY, R->d_Tau, R->d_S, ctrl, cl, x.stream);
+        record_end(x, a, 7, 0.0, 0.0);
+        p0.S = p1.S = R->d_S;
+        p0.tau_out = p1.tau_out = R->d_Tau;
+        p0.mat_stride = p1.mat_stride = R->dimer_mat;
+    }
     launch_pair_fp64(1, p0, R->d_pairs, R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G, x.d_scratch,
                      x.scratch_slot, c->grid_lds, R->d_ed2, couple, ctrl, cl, x.stream);
     launch_pair_fp64(0, p1, R->d_pairs + R->n_lds, R->n_pair - R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G,
@@ -1175,6 +1214,167 @@ mcpt_status lccd_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_lccd_integ
     return MCPT_OK;
 }
 
+// Dimer classes of the dimer-internal terms of Eq. 59: validated, copied, packed
+// and kept with the problem; in == nullptr detaches.  Each pair is described to
+// the ladder kernel as a monomer would be: n = o v, its n x n matrices at
+// p np^2, its W_XY packed like a monomer's W.
+mcpt_status dimer_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_dimer_integrals* in) {
+    mcpt_status st;
+    if ((st = ensure_device(c)) != MCPT_OK) return st;
+    hipStream_t s = x.stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    drop_graph(R);
+    free_dimer(c, R);
+    R->has_result = false;
+    if (!in) return MCPT_OK;
+    if (!R->lccd) return fail(MCPT_ERR_INVALID, "the dimer-internal terms need the intramonomer integrals attached");
+    if (in->memory != MCPT_HOST && in->memory != MCPT_DEVICE)
+        return fail(MCPT_ERR_INVALID, "memory must be MCPT_HOST or MCPT_DEVICE");
+    if (R->n_mono <= 0 || R->n_pair <= 0) return fail(MCPT_ERR_INVALID, "the problem has no pairs");
+    if (R->n_pair > 65535) return fail(MCPT_ERR_INVALID, "the dimer-internal terms support at most 65,535 pairs");
+    const MonoDesc m0 = R->monos[0];
+    for (int m = 1; m < R->n_mono; ++m)
+        if (R->monos[m].o != m0.o || R->monos[m].v != m0.v)
+            return fail(MCPT_ERR_INVALID, "the dimer-internal terms need every monomer of one size (o, v)");
+    const int o = m0.o, v = m0.v, n = m0.n, np = m0.np, v2 = v * v;
+    const int rows = round_up(v2, 16), cols = round_up(v2, 32);
+    const int ct = lccd_ladder_ct(o);
+    const int64_t lds = lccd_ladder_lds_bytes(n, v, cols);
+    if (o > 6 || v > 64 || ct > 3 || lds > lccd_lds_limit())
+        return fail(MCPT_ERR_INVALID, "the dimer-internal terms support o <= 6, v <= 64 and n x n amplitudes "
+                                      "within 160 KiB");
+    const int64_t P = R->n_pair, mat = (int64_t)np * np;
+    const int64_t nw = P * v2 * v2, nq = P * o * o * o * o, nc = P * (int64_t)o * o * v2;
+    if (!in->w_vvvv || !in->q_oooo || !in->c_x || !in->c_y) return fail(MCPT_ERR_INVALID, "an integral array is NULL");
+    const bool host = in->memory == MCPT_HOST;
+    if (host) {
+        auto finite = [](const double* p, int64_t k) {
+            for (int64_t e = 0; e < k; ++e)
+                if (!std::isfinite(p[e])) return false;
+            return true;
+        };
+        if (!finite(in->w_vvvv, nw) || !finite(in->q_oooo, nq) || !finite(in->c_x, nc) || !finite(in->c_y, nc))
+            return fail(MCPT_ERR_NONFINITE, "dimer integrals have a non-finite value");
+    } else {
+        *x.h_flag = 0;
+        HIP_TRY(hipMemcpyAsync(x.d_flag, x.h_flag, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        launch_nonfinite(in->w_vvvv, nw, x.d_flag, s);
+        launch_nonfinite(in->q_oooo, nq, x.d_flag, s);
+        launch_nonfinite(in->c_x, nc, x.d_flag, s);
+        launch_nonfinite(in->c_y, nc, x.d_flag, s);
+        HIP_TRY(hipMemcpyAsync(x.h_flag, x.d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (*x.h_flag) return fail(MCPT_ERR_NONFINITE, "dimer integrals have a non-finite value");
+    }
+    // per pair (caller order): a monomer-like descriptor for the ladder and pack kernels
+    std::vector<int64_t> cl_of(P, 0);
+    std::vector<DimerDesc> dd(P);
+    for (const PairDesc& pd : R->pairs) {
+        dd[pd.orig] = DimerDesc{pd.x, pd.y};
+        cl_of[pd.orig] = pd.cluster;
+    }
+    std::vector<MonoDesc> pm(P);
+    std::vector<LccdDesc> pl(P);
+    for (int64_t p = 0; p < P; ++p) {
+        MonoDesc d{};
+        d.o = o;
+        d.v = v;
+        d.n = n;
+        d.np = np;
+        d.mat_off = p * mat;
+        d.raw_off = p * (int64_t)o * o * v2;
+        d.cluster = (int32_t)cl_of[p];
+        pm[p] = d;
+        pl[p] = LccdDesc{p * rows * cols, p * v2 * v2, p * o * o * o * o, rows, cols};
+    }
+    auto rnd = [](int64_t bytes) { return (size_t)((std::max<int64_t>(bytes, 1) + 255) / 256 * 256); };
+    const int64_t w_pack = P * rows * cols;
+    const size_t keep = rnd(8 * w_pack) + rnd(8 * nq) + 4 * rnd(8 * P * mat) + rnd(sizeof(DimerDesc) * P) +
+                        rnd(sizeof(MonoDesc) * P) + rnd(sizeof(LccdDesc) * P);
+    const size_t staging = host ? rnd(8 * std::max(nw, nc)) : 0;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        if (c->in_use + (c->reserved - x.reserved) + keep + staging > c->budget)
+            return fail(MCPT_ERR_ADMISSION, "dimer integrals exceed the budget");
+    }
+    auto alloc = [&](void** out, size_t bytes) -> mcpt_status {
+        void* p = nullptr;
+        const hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MCPT_ERR_NOMEM, "hipMalloc of dimer buffers failed");
+        }
+        R->dimer_allocations.push_back(p);
+        R->dimer_bytes += bytes;
+        std::lock_guard<std::mutex> g(c->mu);
+        c->in_use += bytes;
+        *out = p;
+        return MCPT_OK;
+    };
+    void* pv[9] = {};
+    const size_t sizes[9] = {rnd(8 * w_pack), rnd(8 * nq), rnd(8 * P * mat), rnd(8 * P * mat), rnd(8 * P * mat),
+                             rnd(8 * P * mat), rnd(sizeof(DimerDesc) * P), rnd(sizeof(MonoDesc) * P),
+                             rnd(sizeof(LccdDesc) * P)};
+    for (int k = 0; k < 9; ++k)
+        if ((st = alloc(&pv[k], sizes[k])) != MCPT_OK) {
+            free_dimer(c, R);
+            return st;
+        }
+    R->d_DW = static_cast<double*>(pv[0]);
+    R->d_DQ = static_cast<double*>(pv[1]);
+    R->d_DCX = static_cast<double*>(pv[2]);
+    R->d_DCY = static_cast<double*>(pv[3]);
+    R->d_Tau = static_cast<double*>(pv[4]);
+    R->d_S = static_cast<double*>(pv[5]);
+    R->d_dd = static_cast<DimerDesc*>(pv[6]);
+    R->d_pmono = static_cast<MonoDesc*>(pv[7]);
+    R->d_plccd = static_cast<LccdDesc*>(pv[8]);
+    auto fail_free = [&](mcpt_status e) {
+        free_dimer(c, R);
+        return e;
+    };
+    const hipMemcpyKind kind = host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    if (hipMemcpyAsync(R->d_dd, dd.data(), P * sizeof(DimerDesc), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(R->d_pmono, pm.data(), P * sizeof(MonoDesc), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(R->d_plccd, pl.data(), P * sizeof(LccdDesc), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(R->d_DQ, in->q_oooo, nq * sizeof(double), kind, s) != hipSuccess)
+        return fail_free(fail(MCPT_ERR_DEVICE, "copy of dimer integrals failed"));
+    launch_fill(R->d_Tau, P * mat, 0.0, s);
+    launch_fill(R->d_S, P * mat, 0.0, s);
+    const int pn = (int)P;
+    if (host) {
+        // host arrays go through one temporary device buffer: W, then C_X, then C_Y
+        void* stage = nullptr;
+        if (hipMalloc(&stage, staging) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail_free(fail(MCPT_ERR_NOMEM, "hipMalloc of the integral staging buffer failed"));
+        }
+        double* sd = static_cast<double*>(stage);
+        hipError_t e = hipMemcpyAsync(stage, in->w_vvvv, nw * sizeof(double), hipMemcpyHostToDevice, s);
+        launch_lccd_pack(R->d_pmono, R->d_plccd, pn, sd, nullptr, R->d_DW, nullptr, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(stage, in->c_x, nc * sizeof(double), hipMemcpyHostToDevice, s);
+        launch_lccd_pack(R->d_pmono, R->d_plccd, pn, nullptr, sd, nullptr, R->d_DCX, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(stage, in->c_y, nc * sizeof(double), hipMemcpyHostToDevice, s);
+        launch_lccd_pack(R->d_pmono, R->d_plccd, pn, nullptr, sd, nullptr, R->d_DCY, s);
+        const hipError_t e2 = hipStreamSynchronize(s);
+        (void)hipFree(stage);
+        if (e != hipSuccess || e2 != hipSuccess) return fail_free(fail(MCPT_ERR_DEVICE, "upload of dimer integrals failed"));
+    } else {
+        launch_lccd_pack(R->d_pmono, R->d_plccd, pn, in->w_vvvv, in->c_x, R->d_DW, R->d_DCX, s);
+        launch_lccd_pack(R->d_pmono, R->d_plccd, pn, nullptr, in->c_y, nullptr, R->d_DCY, s);
+    }
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return fail_free(fail(MCPT_ERR_DEVICE, "packing of dimer integrals failed"));
+    R->dimer_mat = mat;
+    R->dimer_ct = ct;
+    R->dimer_lds_bytes = lds;
+    R->dimer_ring_blocks = dimer_ring_blocks(np);
+    R->dimer_w_bytes = 8.0 * (double)w_pack;
+    R->dimer_w_flops = 2.0 * (double)P * o * o * (double)v2 * v2;
+    R->dimer = true;
+    return MCPT_OK;
+}
+
 // A new resident problem that is the resident problem B with the blocks of the
 // listed pairs (caller indices) multiplied by their factors: a displaced
 // geometry whose couplings are rescaled (Sec. IV.A), made on the device from
@@ -1392,6 +1592,8 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
     if (st != MCPT_OK) return st;
     if ((st = ensure_device(c)) != MCPT_OK) return st;
     if ((st = ensure_scratch(c, x, R->max_slot)) != MCPT_OK) return st;
+    if (R->dimer && o->precision != MCPT_FP64)
+        return fail(MCPT_ERR_INVALID, "a problem with dimer-internal terms runs in FP64 only");
     if (R->lccd && o->deterministic)
         return fail(MCPT_ERR_INVALID, "the full monomer equation has no deterministic mode");
     R->det_on = o->deterministic != 0;
@@ -1431,6 +1633,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
         return MCPT_OK;
     };
     if ((st = reset_state()) != MCPT_OK) return st;
+    if (R->dimer) launch_fill(R->d_Tau, R->n_pair * R->dimer_mat, 0.0, s);   // Tau before the first sweep
     launch_fill(R->d_G[0], R->mat_elems, 0.0, s);
     launch_fill(R->d_G[1], R->mat_elems, 0.0, s);
     // intramonomer terms of the full monomer equation, L = P + H + R + R^T from the current T and M
@@ -1955,6 +2158,17 @@ mcpt_status mcpt_lccd_attach(mcpt_ctx* c, uint64_t id, const mcpt_lccd_integrals
     if (!R) return unknown(id);
     try {
         return lccd_attach(c, c->main, R, ints);
+    } catch (const std::exception& e) {
+        return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
+    }
+}
+
+mcpt_status mcpt_dimer_attach(mcpt_ctx* c, uint64_t id, const mcpt_dimer_integrals* ints) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    Resident* R = find_resident(c, id);
+    if (!R) return unknown(id);
+    try {
+        return dimer_attach(c, c->main, R, ints);
     } catch (const std::exception& e) {
         return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
     }

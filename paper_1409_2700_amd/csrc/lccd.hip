@@ -442,7 +442,7 @@ template <int CT>
 __global__ __launch_bounds__(kLadLdsThreads) void lccd_ladder_lds_kernel(
     const MonoDesc* __restrict__ monos, const LccdDesc* __restrict__ ld, int lds_doubles,
     const double* __restrict__ W, const double* __restrict__ Q, const double* __restrict__ T,
-    const double* __restrict__ R12, const double* __restrict__ Y, double* __restrict__ L,
+    const double* __restrict__ R12, const double* __restrict__ Y, double* __restrict__ L, int rings,
     const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
     if (ctrl && ctrl->done) return;
     const int x = blockIdx.x;
@@ -492,9 +492,136 @@ __global__ __launch_bounds__(kLadLdsThreads) void lccd_ladder_lds_kernel(
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int task = wave; task < tasks; task += kLadLdsThreads / 64)
         ladder_task<RT, CT, 2, false>(g, (task / ngroups) * RT, (task % ngroups) * CT, lane);
+    if (!rings) return;
     // every wave is done with the staged amplitudes and its L stores are visible to the workgroup
     __syncthreads();
     add_rings(g, lds, lds_doubles);
+}
+
+// ---------------------------------------------------------------------------
+// ring terms of the dimer equation (Eq. 59)
+// ---------------------------------------------------------------------------
+// For a pair with amplitudes Tau (np x np, rows (i,a) of X, columns (j,b) of Y)
+// the monomer rings and the cross rings are four products, each output element
+// added into the pair's source S with an FP64 atomic (S already holds the two
+// ladders, stored before this launch):
+//   kind 0, side 0:  (2 K_X - J_X) Tau           at ((i,a),(j,b))  ->  + S[(i,a),(j,b)]
+//   kind 0, side 1:  (2 K_Y - J_Y) Tau^T         at ((j,b),(i,a))  ->  + S[(i,a),(j,b)]
+//   kind 1, side 0:  C_X Vs(Tau)                 at ((i,b),(j,a))  ->  - S[(i,a),(j,b)]
+//   kind 1, side 1:  C_Y Vs(Tau^T)               at ((j,a),(i,b))  ->  - S[(i,a),(j,b)]
+// with K-hat[(i,a),(i1,a1)] = K[i,i1,a,a1] and J-hat[(i,a),(i1,a1)] = J[i1,i,a,a1] of
+// the monomer, C-hat packed from the pair's class the way J-hat is, and Vs the
+// swap of the two virtual indices.  All blocks of a pair run on one XCD.
+__global__ __launch_bounds__(kLccdThreads, 2) void dimer_ring_kernel(
+    const DimerDesc* __restrict__ dd, const MonoDesc* __restrict__ monos, const MonoDesc* __restrict__ pseudo,
+    int n_pair, int blocks_per_pair, const double* __restrict__ K, const double* __restrict__ J,
+    const double* __restrict__ CX, const double* __restrict__ CY, const double* __restrict__ Tau,
+    double* __restrict__ S, const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
+    if (ctrl && ctrl->done) return;
+    const int q = blockIdx.x / kXcds;
+    const int part = q % blocks_per_pair;
+    const int p = (q / blocks_per_pair) * kXcds + (int)(blockIdx.x % kXcds);
+    if (p >= n_pair) return;
+    const MonoDesc d = pseudo[p];
+    if (cl && cl[d.cluster].done) return;
+    const DimerDesc e = dd[p];
+    __shared__ int kofs[2][kLccdMaxNp];   // Vs gathers: row k of Vs(Tau) / Vs(Tau^T)
+    const int np = d.np, n = d.n, v = d.v;
+    for (int k = threadIdx.x; k < np; k += kLccdThreads) {
+        const int i2 = k / v, a2 = k - i2 * v;
+        kofs[0][k] = k < n ? i2 * v * np + a2 : 0;
+        kofs[1][k] = k < n ? a2 * np + i2 * v : 0;
+    }
+    __syncthreads();
+    const double* Tp = Tau + d.mat_off;
+    double* Sp = S + d.mat_off;
+    const int nt = np / 16;
+    const int nsb = (nt + kRingSB - 1) / kRingSB;
+    const int tasks = 4 * nsb * nsb;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = (lane >> 4) * 4;
+    for (int task = part * (kLccdThreads / 64) + wave; task < tasks; task += blocks_per_pair * (kLccdThreads / 64)) {
+        const int ks = task / (nsb * nsb);        // kind * 2 + side
+        const int kind = ks >> 1, side = ks & 1;
+        const int sb = task - ks * nsb * nsb;
+        const int tr0 = (sb / nsb) * kRingSB, tc0 = (sb % nsb) * kRingSB;
+        const MonoDesc m = monos[side ? e.y : e.x];
+        const double* A0 = kind == 0 ? K + m.mat_off : (side ? CY : CX) + d.mat_off;
+        const double* A1 = J + m.mat_off;
+        int arow[kRingSB], bcol[kRingSB], ycol[kRingSB];
+#pragma unroll
+        for (int u = 0; u < kRingSB; ++u) {
+            const int r = (tr0 + u) * 16 + lr, c = (tc0 + u) * 16 + lr;
+            arow[u] = r < np ? r : 0;
+            bcol[u] = c < np ? c : 0;
+            const int i1 = c / v, a = c - i1 * v;
+            ycol[u] = c < n ? (side ? i1 * v * np + a : a * np + i1 * v) : 0;
+        }
+        d4 acc[kRingSB][kRingSB];
+#pragma unroll
+        for (int u = 0; u < kRingSB; ++u)
+#pragma unroll
+            for (int w = 0; w < kRingSB; ++w) acc[u][w] = d4(0.0);
+        for (int k0 = 0; k0 < np; k0 += 16) {
+            double a[kRingSB][4], b[kRingSB][4];
+#pragma unroll
+            for (int u = 0; u < kRingSB; ++u) {
+                const d4 x = load4(A0 + (int64_t)arow[u] * np + k0 + lk);
+                if (kind == 0) {
+                    const d4 y = load4(A1 + (int64_t)arow[u] * np + k0 + lk);
+                    a[u][0] = 2.0 * x.x - y.x;
+                    a[u][1] = 2.0 * x.y - y.y;
+                    a[u][2] = 2.0 * x.z - y.z;
+                    a[u][3] = 2.0 * x.w - y.w;
+                } else {
+                    a[u][0] = x.x;
+                    a[u][1] = x.y;
+                    a[u][2] = x.z;
+                    a[u][3] = x.w;
+                }
+            }
+#pragma unroll
+            for (int w = 0; w < kRingSB; ++w) {
+                if (kind == 0 && side == 1) {
+                    const d4 t = load4(Tp + (int64_t)bcol[w] * np + k0 + lk);
+                    b[w][0] = t.x;
+                    b[w][1] = t.y;
+                    b[w][2] = t.z;
+                    b[w][3] = t.w;
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const int k = k0 + lk + s;
+                        b[w][s] = kind == 0 ? Tp[(int64_t)k * np + bcol[w]] : Tp[kofs[side][k] + ycol[w]];
+                    }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int u = 0; u < kRingSB; ++u)
+#pragma unroll
+                    for (int w = 0; w < kRingSB; ++w) acc[u][w] = mfma(a[u][s], b[w][s], acc[u][w]);
+        }
+        const double sgn = kind == 0 ? 1.0 : -1.0;
+#pragma unroll
+        for (int u = 0; u < kRingSB; ++u)
+#pragma unroll
+            for (int w = 0; w < kRingSB; ++w) {
+                const int c = (tc0 + w) * 16 + lr;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int r = (tr0 + u) * 16 + acc_row(lane, t);
+                    if (r >= n || c >= n) continue;
+                    const int ri = r / v, ra = r - ri * v, ci = c / v, ca = c - ci * v;
+                    int64_t dst;
+                    if (kind == 0) dst = side ? (int64_t)c * np + r : (int64_t)r * np + c;
+                    else if (side == 0) dst = (int64_t)(ri * v + ca) * np + ci * v + ra;   // r = (i,b), c = (j,a)
+                    else dst = (int64_t)(ci * v + ra) * np + ri * v + ca;                  // r = (j,a), c = (i,b)
+                    unsafeAtomicAdd(Sp + dst, sgn * acc[u][w][t]);
+                }
+            }
+    }
 }
 
 }  // namespace
@@ -544,7 +671,7 @@ int64_t lccd_lds_limit() { return 160 * 1024; }
 
 void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, int ladder_blocks, int ct,
                         int64_t lds_bytes, const double* W, const double* Q, const double* T, const double* R12,
-                        const double* Y, double* L, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
+                        const double* Y, double* L, const Ctrl* ctrl, const ClState* cl, hipStream_t s, int rings) {
     if (n_mono <= 0 || ladder_blocks <= 0) return;
     if (lds_bytes > 0) {
         const dim3 grid(n_mono), block(kLadLdsThreads);
@@ -558,7 +685,7 @@ void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, i
             attr = true;                                                                                         \
         }                                                                                                        \
         hipLaunchKernelGGL(lccd_ladder_lds_kernel<C>, grid, block, (size_t)lds_bytes, s, monos, ld,            \
-                           (int)(lds_bytes / 8), W, Q, T, R12, Y, L, ctrl, cl);                                  \
+                           (int)(lds_bytes / 8), W, Q, T, R12, Y, L, rings, ctrl, cl);                           \
         return;                                                                                                  \
     }
             LDS_CASE(1)
@@ -588,6 +715,22 @@ void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, i
                                R12, Y, L, ctrl, cl);
             break;
     }
+}
+
+int dimer_ring_blocks(int np) {
+    const int nt = np / 16, nsb = (nt + kRingSB - 1) / kRingSB;
+    const int tasks = 4 * nsb * nsb, per_block = kLccdThreads / 64;
+    const int b = (tasks + per_block - 1) / per_block;
+    return b < 8 ? b : 8;
+}
+
+void launch_dimer_ring(const DimerDesc* dd, const MonoDesc* monos, const MonoDesc* pseudo, int n_pair, int blocks,
+                       const double* K, const double* J, const double* CX, const double* CY, const double* Tau,
+                       double* S, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
+    if (n_pair <= 0 || blocks <= 0) return;
+    const int groups = (n_pair + kXcds - 1) / kXcds;
+    hipLaunchKernelGGL(dimer_ring_kernel, dim3(groups * kXcds * blocks), dim3(kLccdThreads), 0, s, dd, monos, pseudo,
+                       n_pair, blocks, K, J, CX, CY, Tau, S, ctrl, cl);
 }
 
 }  // namespace mcpt

@@ -19,6 +19,14 @@ struct LccdDesc {
     int32_t ldw;         // v^2 rounded up to 32
 };
 
+// Per stored pair of the dimer-internal terms of Eq. 59: its two monomers.  The
+// pair's own n x n matrices (amplitudes, source, packed cross-ring classes) sit
+// at the mat_off of a per-pair MonoDesc, and its packed W_XY and Q_XY at the
+// offsets of a per-pair LccdDesc, so the monomer ladder kernel runs on pairs.
+struct DimerDesc {
+    int32_t x, y;
+};
+
 void launch_lccd_pack(const MonoDesc* monos, const LccdDesc* ld, int n_mono, const double* w_raw,
                       const double* j_raw, double* W, double* J, hipStream_t s);
 int lccd_ring_blocks(int max_np);
@@ -36,6 +44,13 @@ int64_t lccd_lds_limit();
 // selects the LDS-staged kernel (every monomer must need at most that much)
 void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, int ladder_blocks, int ct,
                         int64_t lds_bytes, const double* W, const double* Q, const double* T, const double* R12,
-                        const double* Y, double* L, const Ctrl* ctrl, const ClState* cl, hipStream_t s);
+                        const double* Y, double* L, const Ctrl* ctrl, const ClState* cl, hipStream_t s,
+                        int rings = 1);
+
+// The ring terms of the dimer equation, added into S with atomics (S must hold the ladders)
+int dimer_ring_blocks(int np);
+void launch_dimer_ring(const DimerDesc* dd, const MonoDesc* monos, const MonoDesc* pseudo, int n_pair, int blocks,
+                       const double* K, const double* J, const double* CX, const double* CY, const double* Tau,
+                       double* S, const Ctrl* ctrl, const ClState* cl, hipStream_t s);
 
 }  // namespace mcpt

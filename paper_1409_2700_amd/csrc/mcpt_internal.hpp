@@ -39,6 +39,11 @@ __device__ inline double recip(double d) {
 struct PartOut {
     double* part;            // nullptr: FP64 atomics into G
     const int64_t* off;      // per pair of the launch
+    // dimer-internal terms (FP64 kernel only): S adds into the numerator of Tau and
+    // Tau is kept in tau_out, both np_X x np_Y at orig * mat_stride; nullptr: neither
+    const double* S = nullptr;
+    double* tau_out = nullptr;
+    int64_t mat_stride = 0;
 };
 
 struct MonoDesc {

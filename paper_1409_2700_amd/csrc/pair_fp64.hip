@@ -474,6 +474,8 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
 
         // ---- Tau = D_XY * (V + M_X V + V M_Y^T), E_D2 = 4 <V, Tau> ----
         double epart = 0.0;
+        const double* Sp = po.S ? po.S + pd.orig * po.mat_stride : nullptr;
+        double* Tp = po.tau_out ? po.tau_out + pd.orig * po.mat_stride : nullptr;
         for_tasks(make_grid(RB, CB), make_grid(0, 0), wave, NW, [&](int, int r0, int c0, auto shape) {
             constexpr int NR = decltype(shape)::NR, NC = decltype(shape)::NC;
             d4 acc[NR][NC];
@@ -493,10 +495,12 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
                         if (r < p.nX && c < p.nY) {
                             const double dinv = recip(p.dX[r] + dc);
                             const double v = IN_LDS ? sV[r * p.ldv + c] : p.V[(int64_t)r * p.nY + c];
-                            tv = dinv * (v + acc[i][j][t]);
+                            const double src = Sp ? v + Sp[(int64_t)r * p.npY + c] : v;
+                            tv = dinv * (src + acc[i][j][t]);
                             epart += v * tv;
                         }
                         if (couple) tau[(int64_t)r * p.npY + c] = tv;
+                        if (Tp) Tp[(int64_t)r * p.npY + c] = tv;
                     }
             }
         });

@@ -88,6 +88,19 @@ struct Resident {
     double lccd_w_flops = 0.0;        // algorithmic flops of the particle-particle ladder per sweep
     std::vector<void*> lccd_allocations;
     size_t lccd_bytes = 0;
+    // dimer-internal terms of Eq. 59 (mcpt_dimer_attach): per pair a MonoDesc / LccdDesc
+    // placing its n x n matrices and packed W_XY, Q_XY, so the monomer ladder kernel runs on pairs
+    bool dimer = false;
+    DimerDesc* d_dd = nullptr;
+    MonoDesc* d_pmono = nullptr;
+    LccdDesc* d_plccd = nullptr;
+    double *d_DW = nullptr, *d_DQ = nullptr, *d_DCX = nullptr, *d_DCY = nullptr, *d_Tau = nullptr, *d_S = nullptr;
+    int64_t dimer_mat = 0;            // np^2: elements of one pair's matrix
+    int dimer_ring_blocks = 0, dimer_ct = 1;
+    int64_t dimer_lds_bytes = 0;
+    double dimer_w_bytes = 0.0, dimer_w_flops = 0.0;
+    std::vector<void*> dimer_allocations;
+    size_t dimer_bytes = 0;
     // captured sweep graph: valid for one form, one execution resource set and one body count
     hipGraphExec_t graph = nullptr;
     int graph_prec = -1, graph_sweeps = 0, graph_parity = 0;

@@ -40,7 +40,7 @@ EXPORTS = [
     "mcpt_upload_batch", "mcpt_solve_batch", "mcpt_cluster_results",
     "mcpt_serve_config", "mcpt_submit", "mcpt_poll", "mcpt_wait", "mcpt_serve_stats",
     "mcpt_autotune", "mcpt_tune_export", "mcpt_tune_import", "mcpt_singles", "mcpt_singles_result",
-    "mcpt_lccd_attach", "mcpt_upload_scaled", "mcpt_fd_stencil",
+    "mcpt_lccd_attach", "mcpt_upload_scaled", "mcpt_fd_stencil", "mcpt_dimer_attach",
 ]
 
 
@@ -80,6 +80,8 @@ class mcpt_timing(C.Structure):
         ("lowp_v_bytes", C.c_double), ("singles_ms", C.c_double), ("singles_launches", C.c_int64),
         ("singles_v_bytes", C.c_double), ("lccd_ring_ms", C.c_double), ("lccd_ladder_ms", C.c_double),
         ("lccd_launches", C.c_int64), ("lccd_w_bytes", C.c_double), ("lccd_ladder_flops", C.c_double),
+        ("dimer_ladder_ms", C.c_double), ("dimer_ring_ms", C.c_double), ("dimer_launches", C.c_int64),
+        ("dimer_w_bytes", C.c_double), ("dimer_ladder_flops", C.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -88,6 +90,11 @@ class mcpt_timing(C.Structure):
 
 class mcpt_lccd_integrals(C.Structure):
     _fields_ = [("w_vvvv", C.c_void_p), ("q_oooo", C.c_void_p), ("j_oovv", C.c_void_p), ("memory", C.c_int32)]
+
+
+class mcpt_dimer_integrals(C.Structure):
+    _fields_ = [("w_vvvv", C.c_void_p), ("q_oooo", C.c_void_p), ("c_x", C.c_void_p), ("c_y", C.c_void_p),
+                ("memory", C.c_int32)]
 
 
 class mcpt_fd_mode(C.Structure):
@@ -169,6 +176,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                  C.POINTER(mcpt_singles_summary)]
     lib.mcpt_singles_result.argtypes = [P, C.c_uint64, P, P]
     lib.mcpt_lccd_attach.argtypes = [P, C.c_uint64, C.POINTER(mcpt_lccd_integrals)]
+    lib.mcpt_dimer_attach.argtypes = [P, C.c_uint64, C.POINTER(mcpt_dimer_integrals)]
     lib.mcpt_upload_scaled.argtypes = [P, C.c_uint64, C.c_int64, P, P, C.POINTER(C.c_uint64)]
     lib.mcpt_fd_stencil.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(mcpt_fd_mode), C.c_int32, P, C.c_double, P,
                                     C.POINTER(mcpt_options), C.POINTER(mcpt_fd_result)]
@@ -384,6 +392,21 @@ class Context:
         j = np.ascontiguousarray(ints.j, dtype=np.float64)
         li = mcpt_lccd_integrals(_ptr(w), _ptr(q), _ptr(j), MCPT_HOST)
         _check(lib().mcpt_lccd_attach(self.h, pid, C.byref(li)))
+
+    # ---- dimer-internal terms (mcpt_dimer_attach) ----
+    def dimer_attach(self, pid: int, dints, device_ptrs: tuple | None = None):
+        """Attach the dimer classes of Eq. 59 (an object with flat w, q, cx, cy
+        arrays, or device_ptrs = (w, q, cx, cy) of device buffers); dints None detaches."""
+        if dints is None and device_ptrs is None:
+            _check(lib().mcpt_dimer_attach(self.h, pid, None))
+            return
+        if device_ptrs is not None:
+            di = mcpt_dimer_integrals(*device_ptrs, MCPT_DEVICE)
+            _check(lib().mcpt_dimer_attach(self.h, pid, C.byref(di)))
+            return
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (dints.w, dints.q, dints.cx, dints.cy)]
+        di = mcpt_dimer_integrals(*[_ptr(a) for a in arrs], MCPT_HOST)
+        _check(lib().mcpt_dimer_attach(self.h, pid, C.byref(di)))
 
     # ---- finite-displacement geometries (mcpt_upload_scaled / mcpt_fd_stencil) ----
     def upload_scaled(self, base: int, pairs, scale) -> int:

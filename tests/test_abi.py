@@ -45,7 +45,8 @@ def _c_layout(tmp_path):
     from paper_1409_2700_amd import mcpt as m
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mcpt.h"', "int main(void) {"]
     for cname in ("mcpt_problem", "mcpt_options", "mcpt_summary", "mcpt_timing", "mcpt_serve_counters", "mcpt_tune_result",
-                  "mcpt_singles_summary", "mcpt_lccd_integrals", "mcpt_fd_mode", "mcpt_fd_result"):
+                  "mcpt_singles_summary", "mcpt_lccd_integrals", "mcpt_fd_mode", "mcpt_fd_result",
+                  "mcpt_dimer_integrals"):
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
         for fname, _ in getattr(m, cname)._fields_:
             lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
@@ -63,7 +64,8 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_1409_2700_amd import mcpt as m
     lay = _c_layout(tmp_path)
     for cname in ("mcpt_problem", "mcpt_options", "mcpt_summary", "mcpt_timing", "mcpt_serve_counters", "mcpt_tune_result",
-                  "mcpt_singles_summary", "mcpt_lccd_integrals", "mcpt_fd_mode", "mcpt_fd_result"):
+                  "mcpt_singles_summary", "mcpt_lccd_integrals", "mcpt_fd_mode", "mcpt_fd_result",
+                  "mcpt_dimer_integrals"):
         st = getattr(m, cname)
         assert ctypes.sizeof(st) == lay[(cname, "size")], cname
         for fname, _ in st._fields_:

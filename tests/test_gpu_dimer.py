@@ -1,0 +1,107 @@
+"""Dimer-internal terms of Eq. 59 (ladders, cross rings, monomer rings, Tau
+iterated) on the GPU against the oracle: fixed sweep counts element by element
+on uniform clusters of one to nine MFMA tiles per edge (n = 6, 51, 135, the
+last two with ragged tails), with physical-symmetry and with general
+integrals, the converged solve with equal sweep counts, graph replay, and the
+error paths.  Bar: 1e-10 relative (FP64), sweep counts equal."""
+import numpy as np
+import pytest
+
+from oracle import mcpt_dimer
+from synth import LCCD_K_SCALE, cubic_sites, dimer_integrals, lccd_integrals, make_lattice_problem
+import paper_1409_2700_amd as mc
+from paper_1409_2700_amd import mcpt as binding
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = mc.Context(0)
+    yield c
+    c.close()
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)) if b.size else 0.0
+
+
+def flat_t(r):
+    return np.concatenate([t.ravel() for t in r.T])
+
+
+def cluster(o, v, dims=(2, 2, 1), scale=0.5, workload=940, general=False):
+    p = make_lattice_problem(cubic_sites(*dims), None, o=o, v=v, workload=workload, coupling_scale=scale,
+                             k_scale=LCCD_K_SCALE)
+    ints = lccd_integrals(p)
+    dints = dimer_integrals(p)
+    if general:   # no permutational symmetry in any dimer class
+        rng = np.random.default_rng(workload)
+        for arr in (dints.w, dints.q, dints.cx, dints.cy):
+            arr[:] = rng.normal(0.0, 0.01, size=arr.shape)
+    return p, ints, dints
+
+
+def run_gpu(ctx, p, ints, dints, **opts):
+    pid = ctx.upload(p)
+    ctx.lccd_attach(pid, ints)
+    ctx.dimer_attach(pid, dints)
+    s = ctx.run(pid, raise_on_error=False, **opts)
+    s["error"] = binding.last_error() if s["return"] != mc.MCPT_OK else ""
+    e = ctx.energy(pid) if s["return"] in (mc.MCPT_OK, mc.MCPT_ERR_NOT_CONVERGED) else None
+    ctx.release(pid)
+    return s, e
+
+
+@pytest.mark.parametrize("o,v,general,sweeps", [(2, 3, False, 1), (2, 3, True, 3), (3, 17, False, 2),
+                                                (3, 17, True, 2), (5, 27, False, 2), (5, 27, True, 3)])
+def test_fixed_sweeps_elementwise(ctx, o, v, general, sweeps):
+    p, ints, dints = cluster(o, v, general=general)
+    print(f"[gpu] dimer fixed sweeps={sweeps} o={o} v={v} general={general} P={p.n_pair}", flush=True)
+    ref = mcpt_dimer.solve(p, ints, dints, tol=0.0, max_sweeps=sweeps)
+    s, e = run_gpu(ctx, p, ints, dints, tol=0.0, max_sweeps=sweeps)
+    assert s["return"] == mc.MCPT_OK, s["error"]
+    assert s["sweeps"] == sweeps
+    assert rel(e["t"], flat_t(ref)) <= TOL
+    assert rel(e["e_m2"], ref.e_m2) <= TOL
+    assert rel(e["e_d2"], ref.e_d2) <= TOL
+    assert abs(s["e_total"] - ref.e_total) <= TOL * abs(ref.e_total)
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_converged_matches_oracle(ctx, graph):
+    p, ints, dints = cluster(5, 27, dims=(3, 1, 1), workload=941)
+    print(f"[gpu] dimer converged graph={graph} P={p.n_pair}", flush=True)
+    ref = mcpt_dimer.solve(p, ints, dints, tol=TOL, max_sweeps=200)
+    s, e = run_gpu(ctx, p, ints, dints, tol=TOL, max_sweeps=200, graph=graph)
+    assert ref.status == 0 and s["return"] == mc.MCPT_OK, s["error"]
+    assert s["sweeps"] == ref.sweeps
+    assert rel(e["e_m2"], ref.e_m2) <= TOL and rel(e["e_d2"], ref.e_d2) <= TOL
+    assert rel(e["e_m2"] - e["de_m2"], ref.e_m2_0) <= TOL
+    assert abs(s["e_total"] - ref.e_total) <= TOL * abs(ref.e_total)
+
+
+def test_errors_and_detach(ctx):
+    p, ints, dints = cluster(2, 3)
+    pid = ctx.upload(p)
+    with pytest.raises(mc.MCPTError):              # needs the intramonomer integrals
+        ctx.dimer_attach(pid, dints)
+    ctx.lccd_attach(pid, ints)
+    ctx.dimer_attach(pid, dints)
+    s = ctx.run(pid, raise_on_error=False, precision=mc.MCPT_FP32)
+    assert s["return"] == mc.MCPT_ERR_INVALID       # FP64 only
+    ctx.dimer_attach(pid, None)                     # detached: the full monomer equation alone
+    s = ctx.run(pid, tol=0.0, max_sweeps=2)
+    from oracle import mcpt_lccd
+    ref = mcpt_lccd.solve(p, ints, tol=0.0, max_sweeps=2)
+    assert rel(ctx.energy(pid)["e_d2"], ref.e_d2) <= TOL
+    ctx.release(pid)
+    q = make_lattice_problem(cubic_sites(2, 1, 1), None, sizes=[(2, 3), (2, 4)], workload=942)
+    pid = ctx.upload(q)
+    ctx.lccd_attach(pid, lccd_integrals(q))
+    with pytest.raises(mc.MCPTError):              # monomers of different sizes
+        ctx.dimer_attach(pid, dimer_integrals(q))
+    ctx.release(pid)
