@@ -317,7 +317,8 @@ def batched(n_clusters, tol):
     return out
 
 
-def pmc_pass(workload: str, precision: int = 0, sweeps: int = 2, singles: bool = False, lccd: bool = False):
+def pmc_pass(workload: str, precision: int = 0, sweeps: int = 2, singles: bool = False, lccd: bool = False,
+             dimer: bool = False):
     """Counter pass for rocprofv3 --pmc: one device copy of a known size
     (the calibration kernel), then `sweeps` fixed sweeps of the resident
     workload in the given precision (no polish) and the final FP64 energy
@@ -335,6 +336,15 @@ def pmc_pass(workload: str, precision: int = 0, sweeps: int = 2, singles: bool =
     log(f"[pmc] calibration copy: {n * 8} bytes read and written")
     del src, dst
     with mc.Context(0) as ctx:
+        if dimer:
+            p, ints, dints = dimer_problem()
+            pid = ctx.upload(p)
+            ctx.lccd_attach(pid, ints)
+            ctx.dimer_attach(pid, dints)
+            s = ctx.run(pid, tol=0.0, max_sweeps=sweeps)
+            log(f"[pmc] {DIMER_WORKLOAD}: {sweeps} fixed sweeps of step 5 and of step 6 with the dimer-internal "
+                f"terms, E={s['e_total']:.10f}")
+            return
         if lccd:
             from synth import LCCD_K_SCALE, lccd_integrals
             prob.k *= LCCD_K_SCALE
@@ -529,6 +539,89 @@ def lccd_mode(ctx, prob, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: 
     return out
 
 
+DIMER_WORKLOAD = "hf-10x10x10-c1"
+
+
+def dimer_problem():
+    """The 1000-monomer crystal with nearest-neighbour pairs only (2,700 pairs, the
+    c3 crystal's blocks of those pairs), K at LCCD_K_SCALE, with the intramonomer
+    and the dimer classes: the dimer class (vv|vv) alone is 4.25 MB per pair."""
+    from synth import LCCD_K_SCALE, cubic_sites, dimer_integrals, lccd_integrals, make_lattice_problem
+    p = make_lattice_problem(cubic_sites(10, 10, 10), 1.0, workload=3, k_scale=LCCD_K_SCALE)
+    p.meta["name"] = DIMER_WORKLOAD
+    return p, lccd_integrals(p), dimer_integrals(p)
+
+
+def dimer_mode(ctx, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: bool = True):
+    """Full equations with the dimer-internal terms of Eq. 59 (Tau iterated):
+    solves/s, the pair-ladder launch against the HBM roofline (algorithmic
+    bytes = the packed <a b|a1 b1> stream, 8 round16(v^2) round32(v^2) per
+    pair), the ring launch, and the oracle's dimer-internal terms timed on a
+    sample of pairs."""
+    import numpy as np
+    t0 = time.time()
+    p, ints, dints = dimer_problem()
+    log(f"[dimer] {DIMER_WORKLOAD}: N={p.n_mono} P={p.n_pair}, dimer classes {dints.nbytes() / 1e9:.2f} GB "
+        f"made in {time.time() - t0:.1f}s")
+    pid = ctx.upload(p)
+    ctx.lccd_attach(pid, ints)
+    t0 = time.time()
+    ctx.dimer_attach(pid, dints)
+    attach_s = time.time() - t0
+    opts = dict(tol=tol, max_sweeps=400, check_every=1)
+    for _ in range(warmup):
+        ctx.run(pid, **opts)
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s = ctx.run(pid, **opts)
+    dt = (time.perf_counter() - t0) / max(steps, 1)
+    tm = ctx.timing()
+    ctx.set_timing(False)
+    ctx.release(pid)
+    kl = max(tm["dimer_launches"], 1)
+    ms = tm["dimer_ladder_ms"] / kl
+    wb = tm["dimer_w_bytes"] / kl
+    fl = tm["dimer_ladder_flops"] / kl
+    o, v = int(p.n_occ[0]), int(p.n_vir[0])
+    npad = (o * v + 15) // 16 * 16
+    ring_flops = 4 * 2.0 * (o * v) ** 3 * p.n_pair
+    rms = tm["dimer_ring_ms"] / kl
+    out = {
+        "workload": f"{DIMER_WORKLOAD}: 1000 monomers, {p.n_pair} nearest-neighbour pairs, K x 0.2, intramonomer "
+                    f"classes at sigma 0.01, dimer classes at sigma 0.01 (R_nn / R)^3",
+        "solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "iso_sweeps": s["iso_sweeps"], "sweeps": s["sweeps"],
+        "e_total": s["e_total"], "attach_s": attach_s,
+        "pair_ladder_kernel": {"kernel": "lccd_ladder_lds_kernel (on pairs)", "bound": "hbm", "avg_launch_ms": ms,
+                               "algorithmic_bytes_per_launch": wb, "achieved_GBps": wb / (ms * 1e-3) / 1e9,
+                               "peak_GBps": HBM_PEAK_GBS, "frac": wb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                               "ladder_TFLOPs": fl / (ms * 1e-3) / 1e12, "launches": tm["dimer_launches"]},
+        "ring_kernel": {"kernel": "dimer_ring_kernel", "bound": "mfma", "avg_launch_ms": rms,
+                        "flops_per_launch": ring_flops, "achieved_TFLOPs": ring_flops / (rms * 1e-3) / 1e12,
+                        "peak_TFLOPs": PEAK["fp64"][0],
+                        "frac": ring_flops / (rms * 1e-3) / 1e12 / PEAK["fp64"][0], "padded_edge": npad},
+        # HIP events around the whole pair phase: the two launches above and the pair kernel
+        "pair_phase_avg_ms": tm["pair_ms"] / max(tm["pair_launches"], 1),
+    }
+    log(f"[dimer] {s['iso_sweeps']} + {s['sweeps']} sweeps, {dt * 1e3:.1f} ms per solve, pair ladder {ms:.3f} ms = "
+        f"{wb / (ms * 1e-3) / 1e9:.0f} GB/s, ring {rms:.3f} ms")
+    if with_cpu:
+        from oracle import mcpt_dimer
+        orc = mcpt_dimer.DimerOracle(p, ints, dints)
+        rng = np.random.default_rng(0)
+        k, t0 = 0, time.perf_counter()
+        while k < p.n_pair and time.perf_counter() - t0 < cpu_budget:
+            orc.internal(k, rng.standard_normal(orc.D_pair(k).shape) * 1e-3)
+            k += 1
+        per = (time.perf_counter() - t0) / max(k, 1)
+        sweeps = s["sweeps"] + 1
+        out["cpu_oracle_dimer_terms"] = {
+            "seconds_per_solve": per * p.n_pair * sweeps, "unit": "s", "kind": "oracle",
+            "sample": f"dimer-internal terms of {k} pairs ({per * 1e3:.1f} ms each), scaled to {p.n_pair} pairs x "
+                      f"{sweeps} Eq. 59 steps (the rest of the solve is not included)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -551,10 +644,14 @@ def main():
     ap.add_argument("--pmc-singles", action="store_true", help="--pmc-pass runs two singles sweeps instead")
     ap.add_argument("--pmc-lccd", action="store_true",
                     help="--pmc-pass runs two sweeps of step 5 and two of step 6 of the full monomer equation")
+    ap.add_argument("--pmc-dimer", action="store_true",
+                    help="--pmc-pass runs two sweeps of each step with the dimer-internal terms")
     ap.add_argument("--singles-steps", type=int, default=3, help="timed singles solves (0: skip)")
     ap.add_argument("--fd", type=int, default=1, help="1: time the finite-displacement workflow (0: skip)")
     ap.add_argument("--lccd-steps", type=int, default=2,
                     help="timed solves of the full monomer equation (0: skip)")
+    ap.add_argument("--dimer-steps", type=int, default=1,
+                    help="timed solves with the dimer-internal terms of Eq. 59 (0: skip)")
     ap.add_argument("--batched", type=int, default=0,
                     help="also time the batching form on this many uneven clusters (64 = full set)")
     args = ap.parse_args()
@@ -565,7 +662,8 @@ def main():
         sys.exit(2)
 
     if args.pmc_pass:
-        pmc_pass(args.workload, args.pmc_precision, singles=args.pmc_singles, lccd=args.pmc_lccd)
+        pmc_pass(args.workload, args.pmc_precision, singles=args.pmc_singles, lccd=args.pmc_lccd,
+                 dimer=args.pmc_dimer)
         return
     import paper_1409_2700_amd as mc
     from synth import make_workload, DEFAULT_COUPLING_SCALE
@@ -598,6 +696,9 @@ def main():
     lccd = None
     if args.lccd_steps > 0:
         lccd = lccd_mode(ctx, prob, args.lccd_steps, 1, args.tol, with_cpu=not args.no_cpu_baseline)
+    dimer = None
+    if args.dimer_steps > 0:
+        dimer = dimer_mode(ctx, args.dimer_steps, 1, args.tol, with_cpu=not args.no_cpu_baseline)
     ctx.close()
     served = None
     if args.serve_requests > 0:
@@ -652,6 +753,8 @@ def main():
         out["singles"] = singles
     if lccd is not None:
         out["full_monomer_equation"] = lccd
+    if dimer is not None:
+        out["dimer_internal_terms"] = dimer
     if fd is not None:
         out["finite_displacement"] = fd
     if served is not None:

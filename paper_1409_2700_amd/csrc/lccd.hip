@@ -510,13 +510,14 @@ __global__ __launch_bounds__(kLadLdsThreads) void lccd_ladder_lds_kernel(
 //   kind 1, side 0:  C_X Vs(Tau)                 at ((i,b),(j,a))  ->  - S[(i,a),(j,b)]
 //   kind 1, side 1:  C_Y Vs(Tau^T)               at ((j,a),(i,b))  ->  - S[(i,a),(j,b)]
 // with K-hat[(i,a),(i1,a1)] = K[i,i1,a,a1] and J-hat[(i,a),(i1,a1)] = J[i1,i,a,a1] of
-// the monomer, C-hat packed from the pair's class the way J-hat is, and Vs the
-// swap of the two virtual indices.  All blocks of a pair run on one XCD.
+// the monomer (2 K-hat - J-hat formed once per monomer at attach), C-hat packed
+// from the pair's class the way J-hat is, and Vs the swap of the two virtual
+// indices.  All blocks of a pair run on one XCD.
 __global__ __launch_bounds__(kLccdThreads, 2) void dimer_ring_kernel(
     const DimerDesc* __restrict__ dd, const MonoDesc* __restrict__ monos, const MonoDesc* __restrict__ pseudo,
-    int n_pair, int blocks_per_pair, const double* __restrict__ K, const double* __restrict__ J,
-    const double* __restrict__ CX, const double* __restrict__ CY, const double* __restrict__ Tau,
-    double* __restrict__ S, const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
+    int n_pair, int blocks_per_pair, const double* __restrict__ RM, const double* __restrict__ CX,
+    const double* __restrict__ CY, const double* __restrict__ Tau, double* __restrict__ S,
+    const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
     if (ctrl && ctrl->done) return;
     const int q = blockIdx.x / kXcds;
     const int part = q % blocks_per_pair;
@@ -545,9 +546,7 @@ __global__ __launch_bounds__(kLccdThreads, 2) void dimer_ring_kernel(
         const int kind = ks >> 1, side = ks & 1;
         const int sb = task - ks * nsb * nsb;
         const int tr0 = (sb / nsb) * kRingSB, tc0 = (sb % nsb) * kRingSB;
-        const MonoDesc m = monos[side ? e.y : e.x];
-        const double* A0 = kind == 0 ? K + m.mat_off : (side ? CY : CX) + d.mat_off;
-        const double* A1 = J + m.mat_off;
+        const double* A = kind == 0 ? RM + monos[side ? e.y : e.x].mat_off : (side ? CY : CX) + d.mat_off;
         int arow[kRingSB], bcol[kRingSB], ycol[kRingSB];
 #pragma unroll
         for (int u = 0; u < kRingSB; ++u) {
@@ -562,40 +561,45 @@ __global__ __launch_bounds__(kLccdThreads, 2) void dimer_ring_kernel(
         for (int u = 0; u < kRingSB; ++u)
 #pragma unroll
             for (int w = 0; w < kRingSB; ++w) acc[u][w] = d4(0.0);
-        for (int k0 = 0; k0 < np; k0 += 16) {
-            double a[kRingSB][4], b[kRingSB][4];
+        // the next k chunk's operands in flight while the current one is multiplied (the load
+        // past the last chunk repeats the last one instead of being branched around)
+        d4 an[kRingSB];
+        double bn[kRingSB][4];
+        auto load_chunk = [&](int k0) {
 #pragma unroll
-            for (int u = 0; u < kRingSB; ++u) {
-                const d4 x = load4(A0 + (int64_t)arow[u] * np + k0 + lk);
-                if (kind == 0) {
-                    const d4 y = load4(A1 + (int64_t)arow[u] * np + k0 + lk);
-                    a[u][0] = 2.0 * x.x - y.x;
-                    a[u][1] = 2.0 * x.y - y.y;
-                    a[u][2] = 2.0 * x.z - y.z;
-                    a[u][3] = 2.0 * x.w - y.w;
-                } else {
-                    a[u][0] = x.x;
-                    a[u][1] = x.y;
-                    a[u][2] = x.z;
-                    a[u][3] = x.w;
-                }
-            }
+            for (int u = 0; u < kRingSB; ++u) an[u] = load4(A + (int64_t)arow[u] * np + k0 + lk);
 #pragma unroll
             for (int w = 0; w < kRingSB; ++w) {
                 if (kind == 0 && side == 1) {
                     const d4 t = load4(Tp + (int64_t)bcol[w] * np + k0 + lk);
-                    b[w][0] = t.x;
-                    b[w][1] = t.y;
-                    b[w][2] = t.z;
-                    b[w][3] = t.w;
+                    bn[w][0] = t.x;
+                    bn[w][1] = t.y;
+                    bn[w][2] = t.z;
+                    bn[w][3] = t.w;
                 } else {
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
                         const int k = k0 + lk + s;
-                        b[w][s] = kind == 0 ? Tp[(int64_t)k * np + bcol[w]] : Tp[kofs[side][k] + ycol[w]];
+                        bn[w][s] = kind == 0 ? Tp[(int64_t)k * np + bcol[w]] : Tp[kofs[side][k] + ycol[w]];
                     }
                 }
             }
+        };
+        load_chunk(0);
+        for (int k0 = 0; k0 < np; k0 += 16) {
+            double a[kRingSB][4], b[kRingSB][4];
+#pragma unroll
+            for (int u = 0; u < kRingSB; ++u) {
+                a[u][0] = an[u].x;
+                a[u][1] = an[u].y;
+                a[u][2] = an[u].z;
+                a[u][3] = an[u].w;
+            }
+#pragma unroll
+            for (int w = 0; w < kRingSB; ++w)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) b[w][s] = bn[w][s];
+            load_chunk(k0 + 16 < np ? k0 + 16 : k0);
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -622,6 +626,13 @@ __global__ __launch_bounds__(kLccdThreads, 2) void dimer_ring_kernel(
                 }
             }
     }
+}
+
+// RM = 2 K - J over a buffer of monomer matrices (the ring matrix of the monomer rings of Eq. 59)
+__global__ void ring_matrix_kernel(const double* __restrict__ K, const double* __restrict__ J, double* __restrict__ RM,
+                                   int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        RM[e] = 2.0 * K[e] - J[e];
 }
 
 }  // namespace
@@ -725,12 +736,17 @@ int dimer_ring_blocks(int np) {
 }
 
 void launch_dimer_ring(const DimerDesc* dd, const MonoDesc* monos, const MonoDesc* pseudo, int n_pair, int blocks,
-                       const double* K, const double* J, const double* CX, const double* CY, const double* Tau,
-                       double* S, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
+                       const double* RM, const double* CX, const double* CY, const double* Tau, double* S,
+                       const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
     if (n_pair <= 0 || blocks <= 0) return;
     const int groups = (n_pair + kXcds - 1) / kXcds;
     hipLaunchKernelGGL(dimer_ring_kernel, dim3(groups * kXcds * blocks), dim3(kLccdThreads), 0, s, dd, monos, pseudo,
-                       n_pair, blocks, K, J, CX, CY, Tau, S, ctrl, cl);
+                       n_pair, blocks, RM, CX, CY, Tau, S, ctrl, cl);
+}
+
+void launch_ring_matrix(const double* K, const double* J, double* RM, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(ring_matrix_kernel, dim3(1024), dim3(256), 0, s, K, J, RM, n);
 }
 
 }  // namespace mcpt

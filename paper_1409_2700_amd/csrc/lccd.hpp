@@ -49,8 +49,10 @@ void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, i
 
 // The ring terms of the dimer equation, added into S with atomics (S must hold the ladders)
 int dimer_ring_blocks(int np);
+// RM = 2 K - J of the monomers (n elements of the monomer matrix buffers)
+void launch_ring_matrix(const double* K, const double* J, double* RM, int64_t n, hipStream_t s);
 void launch_dimer_ring(const DimerDesc* dd, const MonoDesc* monos, const MonoDesc* pseudo, int n_pair, int blocks,
-                       const double* K, const double* J, const double* CX, const double* CY, const double* Tau,
-                       double* S, const Ctrl* ctrl, const ClState* cl, hipStream_t s);
+                       const double* RM, const double* CX, const double* CY, const double* Tau, double* S,
+                       const Ctrl* ctrl, const ClState* cl, hipStream_t s);
 
 }  // namespace mcpt
