@@ -93,7 +93,7 @@ void free_dimer(mcpt_ctx* c, Resident* r) {
     r->d_dd = nullptr;
     r->d_pmono = nullptr;
     r->d_plccd = nullptr;
-    r->d_DW = r->d_DQ = r->d_DCX = r->d_DCY = r->d_Tau = r->d_S = r->d_DRM = nullptr;
+    r->d_DW = r->d_DQ = r->d_DCX = r->d_DCY = r->d_Tau = r->d_S = r->d_DRM = r->d_DY1 = r->d_DY2 = nullptr;
 }
 
 void free_lccd(mcpt_ctx* c, Resident* r) {
@@ -669,9 +669,12 @@ void pair_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int couple, const 
         record_end(x, a, 6, R->dimer_w_flops, R->dimer_w_bytes);
         record_begin(x, &a);
         launch_dimer_ring(R->d_dd, R->d_monos, R->d_pmono, (int)R->n_pair, R->dimer_ring_blocks, R->d_DRM,
-                          R->d_DCX, R->d_DCY, R->d_Tau, R->d_S, ctrl, cl, x.stream);
+                          R->d_DCX, R->d_DCY, R->d_Tau, R->d_S, R->d_DY1, R->d_DY2, ctrl, cl, x.stream);
         record_end(x, a, 7, 0.0, 0.0);
         p0.S = p1.S = R->d_S;
+        p0.Y1 = p1.Y1 = R->d_DY1;
+        p0.Y2 = p1.Y2 = R->d_DY2;
+        p0.v = p1.v = R->monos[0].v;
         p0.tau_out = p1.tau_out = R->d_Tau;
         p0.mat_stride = p1.mat_stride = R->dimer_mat;
     }
@@ -1290,7 +1293,8 @@ mcpt_status dimer_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_dimer_int
     auto rnd = [](int64_t bytes) { return (size_t)((std::max<int64_t>(bytes, 1) + 255) / 256 * 256); };
     const int64_t w_pack = P * rows * cols;
     const size_t keep = rnd(8 * w_pack) + rnd(8 * nq) + 4 * rnd(8 * P * mat) + rnd(sizeof(DimerDesc) * P) +
-                        rnd(sizeof(MonoDesc) * P) + rnd(sizeof(LccdDesc) * P) + rnd(8 * R->mat_elems);
+                        rnd(sizeof(MonoDesc) * P) + rnd(sizeof(LccdDesc) * P) + rnd(8 * R->mat_elems) +
+                        2 * rnd(8 * P * mat);
     const size_t staging = host ? rnd(8 * std::max(nw, nc)) : 0;
     {
         std::lock_guard<std::mutex> g(c->mu);
@@ -1311,11 +1315,11 @@ mcpt_status dimer_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_dimer_int
         *out = p;
         return MCPT_OK;
     };
-    void* pv[10] = {};
-    const size_t sizes[10] = {rnd(8 * w_pack), rnd(8 * nq), rnd(8 * P * mat), rnd(8 * P * mat), rnd(8 * P * mat),
+    void* pv[12] = {};
+    const size_t sizes[12] = {rnd(8 * w_pack), rnd(8 * nq), rnd(8 * P * mat), rnd(8 * P * mat), rnd(8 * P * mat),
                               rnd(8 * P * mat), rnd(sizeof(DimerDesc) * P), rnd(sizeof(MonoDesc) * P),
-                              rnd(sizeof(LccdDesc) * P), rnd(8 * R->mat_elems)};
-    for (int k = 0; k < 10; ++k)
+                              rnd(sizeof(LccdDesc) * P), rnd(8 * R->mat_elems), rnd(8 * P * mat), rnd(8 * P * mat)};
+    for (int k = 0; k < 12; ++k)
         if ((st = alloc(&pv[k], sizes[k])) != MCPT_OK) {
             free_dimer(c, R);
             return st;
@@ -1330,6 +1334,8 @@ mcpt_status dimer_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_dimer_int
     R->d_pmono = static_cast<MonoDesc*>(pv[7]);
     R->d_plccd = static_cast<LccdDesc*>(pv[8]);
     R->d_DRM = static_cast<double*>(pv[9]);
+    R->d_DY1 = static_cast<double*>(pv[10]);
+    R->d_DY2 = static_cast<double*>(pv[11]);
     auto fail_free = [&](mcpt_status e) {
         free_dimer(c, R);
         return e;
@@ -1342,6 +1348,8 @@ mcpt_status dimer_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_dimer_int
         return fail_free(fail(MCPT_ERR_DEVICE, "copy of dimer integrals failed"));
     launch_fill(R->d_Tau, P * mat, 0.0, s);
     launch_fill(R->d_S, P * mat, 0.0, s);
+    launch_fill(R->d_DY1, P * mat, 0.0, s);
+    launch_fill(R->d_DY2, P * mat, 0.0, s);
     launch_ring_matrix(R->d_K, R->d_J, R->d_DRM, R->mat_elems, s);
     const int pn = (int)P;
     if (host) {

@@ -502,22 +502,74 @@ __global__ __launch_bounds__(kLadLdsThreads) void lccd_ladder_lds_kernel(
 // ring terms of the dimer equation (Eq. 59)
 // ---------------------------------------------------------------------------
 // For a pair with amplitudes Tau (np x np, rows (i,a) of X, columns (j,b) of Y)
-// the monomer rings and the cross rings are four products, each output element
-// added into the pair's source S with an FP64 atomic (S already holds the two
-// ladders, stored before this launch):
-//   kind 0, side 0:  (2 K_X - J_X) Tau           at ((i,a),(j,b))  ->  + S[(i,a),(j,b)]
-//   kind 0, side 1:  (2 K_Y - J_Y) Tau^T         at ((j,b),(i,a))  ->  + S[(i,a),(j,b)]
-//   kind 1, side 0:  C_X Vs(Tau)                 at ((i,b),(j,a))  ->  - S[(i,a),(j,b)]
-//   kind 1, side 1:  C_Y Vs(Tau^T)               at ((j,a),(i,b))  ->  - S[(i,a),(j,b)]
-// with K-hat[(i,a),(i1,a1)] = K[i,i1,a,a1] and J-hat[(i,a),(i1,a1)] = J[i1,i,a,a1] of
-// the monomer (2 K-hat - J-hat formed once per monomer at attach), C-hat packed
-// from the pair's class the way J-hat is, and Vs the swap of the two virtual
-// indices.  All blocks of a pair run on one XCD.
+// the monomer rings are (2 K_X - J_X) Tau + Tau (2 K_Y - J_Y)^T, two products
+// into one accumulator added in place into the pair's source S (which holds the
+// two ladders, stored before this launch; every element of S has one owner
+// task); the cross rings are Y1 = C_X Vs(Tau) and Y2 = C_Y Vs(Tau^T), stored
+// as they come out, and the pair kernel subtracts Y1[(i,b),(j,a)] and
+// Y2[(j,a),(i,b)] when it forms Tau.  K-hat[(i,a),(i1,a1)] = K[i,i1,a,a1] and
+// J-hat[(i,a),(i1,a1)] = J[i1,i,a,a1] of the monomer (2 K-hat - J-hat formed once
+// per monomer at attach), C-hat packed from the pair's class the way J-hat is,
+// Vs the swap of the two virtual indices.  All blocks of a pair run on one XCD.
+// One product of a ring task into acc: A rows (k-contiguous, 32-byte loads) times B, where BM
+// selects B[k][c] = B[k np + c] (0), B[c np + k] (1, k-contiguous), or the Vs gather
+// B[kofs[k] + ycol[c]] (2).  The next k chunk's operands are in flight while the current one
+// is multiplied; the load past the last chunk repeats it instead of being branched around.
+template <int BM>
+__device__ inline void ring_product(d4 (&acc)[kRingSB][kRingSB], const double* A, const double* B, const int* kofs,
+                                    const int (&arow)[kRingSB], const int (&bcol)[kRingSB],
+                                    const int (&ycol)[kRingSB], int np, int lk) {
+    d4 an[kRingSB];
+    double bn[kRingSB][4];
+    auto load_chunk = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < kRingSB; ++u) an[u] = load4(A + (int64_t)arow[u] * np + k0 + lk);
+#pragma unroll
+        for (int w = 0; w < kRingSB; ++w) {
+            if (BM == 1) {
+                const d4 t = load4(B + (int64_t)bcol[w] * np + k0 + lk);
+                bn[w][0] = t.x;
+                bn[w][1] = t.y;
+                bn[w][2] = t.z;
+                bn[w][3] = t.w;
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int k = k0 + lk + s;
+                    bn[w][s] = BM == 0 ? B[(int64_t)k * np + bcol[w]] : B[kofs[k] + ycol[w]];
+                }
+            }
+        }
+    };
+    load_chunk(0);
+    for (int k0 = 0; k0 < np; k0 += 16) {
+        double a[kRingSB][4], b[kRingSB][4];
+#pragma unroll
+        for (int u = 0; u < kRingSB; ++u) {
+            a[u][0] = an[u].x;
+            a[u][1] = an[u].y;
+            a[u][2] = an[u].z;
+            a[u][3] = an[u].w;
+        }
+#pragma unroll
+        for (int w = 0; w < kRingSB; ++w)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) b[w][s] = bn[w][s];
+        load_chunk(k0 + 16 < np ? k0 + 16 : k0);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int u = 0; u < kRingSB; ++u)
+#pragma unroll
+                for (int w = 0; w < kRingSB; ++w) acc[u][w] = mfma(a[u][s], b[w][s], acc[u][w]);
+    }
+}
+
 __global__ __launch_bounds__(kLccdThreads, 2) void dimer_ring_kernel(
     const DimerDesc* __restrict__ dd, const MonoDesc* __restrict__ monos, const MonoDesc* __restrict__ pseudo,
     int n_pair, int blocks_per_pair, const double* __restrict__ RM, const double* __restrict__ CX,
-    const double* __restrict__ CY, const double* __restrict__ Tau, double* __restrict__ S,
-    const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
+    const double* __restrict__ CY, const double* __restrict__ Tau, double* __restrict__ S, double* __restrict__ Y1,
+    double* __restrict__ Y2, const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
     if (ctrl && ctrl->done) return;
     const int q = blockIdx.x / kXcds;
     const int part = q % blocks_per_pair;
@@ -535,18 +587,17 @@ __global__ __launch_bounds__(kLccdThreads, 2) void dimer_ring_kernel(
     }
     __syncthreads();
     const double* Tp = Tau + d.mat_off;
-    double* Sp = S + d.mat_off;
+    const double* RX = RM + monos[e.x].mat_off;
+    const double* RY = RM + monos[e.y].mat_off;
     const int nt = np / 16;
     const int nsb = (nt + kRingSB - 1) / kRingSB;
-    const int tasks = 4 * nsb * nsb;
+    const int tasks = 3 * nsb * nsb;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = (lane >> 4) * 4;
     for (int task = part * (kLccdThreads / 64) + wave; task < tasks; task += blocks_per_pair * (kLccdThreads / 64)) {
-        const int ks = task / (nsb * nsb);        // kind * 2 + side
-        const int kind = ks >> 1, side = ks & 1;
-        const int sb = task - ks * nsb * nsb;
+        const int kind = task / (nsb * nsb);      // 0: monomer rings, 1: C_X Vs(Tau), 2: C_Y Vs(Tau^T)
+        const int sb = task - kind * nsb * nsb;
         const int tr0 = (sb / nsb) * kRingSB, tc0 = (sb % nsb) * kRingSB;
-        const double* A = kind == 0 ? RM + monos[side ? e.y : e.x].mat_off : (side ? CY : CX) + d.mat_off;
         int arow[kRingSB], bcol[kRingSB], ycol[kRingSB];
 #pragma unroll
         for (int u = 0; u < kRingSB; ++u) {
@@ -554,60 +605,20 @@ __global__ __launch_bounds__(kLccdThreads, 2) void dimer_ring_kernel(
             arow[u] = r < np ? r : 0;
             bcol[u] = c < np ? c : 0;
             const int i1 = c / v, a = c - i1 * v;
-            ycol[u] = c < n ? (side ? i1 * v * np + a : a * np + i1 * v) : 0;
+            ycol[u] = c < n ? (kind == 2 ? i1 * v * np + a : a * np + i1 * v) : 0;
         }
         d4 acc[kRingSB][kRingSB];
 #pragma unroll
         for (int u = 0; u < kRingSB; ++u)
 #pragma unroll
             for (int w = 0; w < kRingSB; ++w) acc[u][w] = d4(0.0);
-        // the next k chunk's operands in flight while the current one is multiplied (the load
-        // past the last chunk repeats the last one instead of being branched around)
-        d4 an[kRingSB];
-        double bn[kRingSB][4];
-        auto load_chunk = [&](int k0) {
-#pragma unroll
-            for (int u = 0; u < kRingSB; ++u) an[u] = load4(A + (int64_t)arow[u] * np + k0 + lk);
-#pragma unroll
-            for (int w = 0; w < kRingSB; ++w) {
-                if (kind == 0 && side == 1) {
-                    const d4 t = load4(Tp + (int64_t)bcol[w] * np + k0 + lk);
-                    bn[w][0] = t.x;
-                    bn[w][1] = t.y;
-                    bn[w][2] = t.z;
-                    bn[w][3] = t.w;
-                } else {
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const int k = k0 + lk + s;
-                        bn[w][s] = kind == 0 ? Tp[(int64_t)k * np + bcol[w]] : Tp[kofs[side][k] + ycol[w]];
-                    }
-                }
-            }
-        };
-        load_chunk(0);
-        for (int k0 = 0; k0 < np; k0 += 16) {
-            double a[kRingSB][4], b[kRingSB][4];
-#pragma unroll
-            for (int u = 0; u < kRingSB; ++u) {
-                a[u][0] = an[u].x;
-                a[u][1] = an[u].y;
-                a[u][2] = an[u].z;
-                a[u][3] = an[u].w;
-            }
-#pragma unroll
-            for (int w = 0; w < kRingSB; ++w)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) b[w][s] = bn[w][s];
-            load_chunk(k0 + 16 < np ? k0 + 16 : k0);
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int u = 0; u < kRingSB; ++u)
-#pragma unroll
-                    for (int w = 0; w < kRingSB; ++w) acc[u][w] = mfma(a[u][s], b[w][s], acc[u][w]);
+        if (kind == 0) {   // (2K - J)_X Tau + Tau (2K - J)_Y^T on one accumulator
+            ring_product<0>(acc, RX, Tp, nullptr, arow, bcol, ycol, np, lk);
+            ring_product<1>(acc, Tp, RY, nullptr, arow, bcol, ycol, np, lk);
+        } else {
+            ring_product<2>(acc, (kind == 2 ? CY : CX) + d.mat_off, Tp, kofs[kind - 1], arow, bcol, ycol, np, lk);
         }
-        const double sgn = kind == 0 ? 1.0 : -1.0;
+        double* out = (kind == 0 ? S : kind == 1 ? Y1 : Y2) + d.mat_off;
 #pragma unroll
         for (int u = 0; u < kRingSB; ++u)
 #pragma unroll
@@ -617,12 +628,8 @@ __global__ __launch_bounds__(kLccdThreads, 2) void dimer_ring_kernel(
                 for (int t = 0; t < 4; ++t) {
                     const int r = (tr0 + u) * 16 + acc_row(lane, t);
                     if (r >= n || c >= n) continue;
-                    const int ri = r / v, ra = r - ri * v, ci = c / v, ca = c - ci * v;
-                    int64_t dst;
-                    if (kind == 0) dst = side ? (int64_t)c * np + r : (int64_t)r * np + c;
-                    else if (side == 0) dst = (int64_t)(ri * v + ca) * np + ci * v + ra;   // r = (i,b), c = (j,a)
-                    else dst = (int64_t)(ci * v + ra) * np + ri * v + ca;                  // r = (j,a), c = (i,b)
-                    unsafeAtomicAdd(Sp + dst, sgn * acc[u][w][t]);
+                    if (kind == 0) out[(int64_t)r * np + c] += acc[u][w][t];
+                    else out[(int64_t)r * np + c] = acc[u][w][t];
                 }
             }
     }
@@ -730,18 +737,18 @@ void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, i
 
 int dimer_ring_blocks(int np) {
     const int nt = np / 16, nsb = (nt + kRingSB - 1) / kRingSB;
-    const int tasks = 4 * nsb * nsb, per_block = kLccdThreads / 64;
+    const int tasks = 3 * nsb * nsb, per_block = kLccdThreads / 64;
     const int b = (tasks + per_block - 1) / per_block;
     return b < 8 ? b : 8;
 }
 
 void launch_dimer_ring(const DimerDesc* dd, const MonoDesc* monos, const MonoDesc* pseudo, int n_pair, int blocks,
                        const double* RM, const double* CX, const double* CY, const double* Tau, double* S,
-                       const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
+                       double* Y1, double* Y2, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
     if (n_pair <= 0 || blocks <= 0) return;
     const int groups = (n_pair + kXcds - 1) / kXcds;
     hipLaunchKernelGGL(dimer_ring_kernel, dim3(groups * kXcds * blocks), dim3(kLccdThreads), 0, s, dd, monos, pseudo,
-                       n_pair, blocks, RM, CX, CY, Tau, S, ctrl, cl);
+                       n_pair, blocks, RM, CX, CY, Tau, S, Y1, Y2, ctrl, cl);
 }
 
 void launch_ring_matrix(const double* K, const double* J, double* RM, int64_t n, hipStream_t s) {

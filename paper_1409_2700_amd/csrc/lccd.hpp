@@ -47,12 +47,13 @@ void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, i
                         const double* Y, double* L, const Ctrl* ctrl, const ClState* cl, hipStream_t s,
                         int rings = 1);
 
-// The ring terms of the dimer equation, added into S with atomics (S must hold the ladders)
+// The ring terms of the dimer equation: the monomer rings added into S (which must hold the
+// ladders), the cross rings stored in Y1 and Y2 for the pair kernel
 int dimer_ring_blocks(int np);
 // RM = 2 K - J of the monomers (n elements of the monomer matrix buffers)
 void launch_ring_matrix(const double* K, const double* J, double* RM, int64_t n, hipStream_t s);
 void launch_dimer_ring(const DimerDesc* dd, const MonoDesc* monos, const MonoDesc* pseudo, int n_pair, int blocks,
                        const double* RM, const double* CX, const double* CY, const double* Tau, double* S,
-                       const Ctrl* ctrl, const ClState* cl, hipStream_t s);
+                       double* Y1, double* Y2, const Ctrl* ctrl, const ClState* cl, hipStream_t s);
 
 }  // namespace mcpt

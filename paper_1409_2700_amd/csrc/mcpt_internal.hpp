@@ -39,11 +39,15 @@ __device__ inline double recip(double d) {
 struct PartOut {
     double* part;            // nullptr: FP64 atomics into G
     const int64_t* off;      // per pair of the launch
-    // dimer-internal terms (FP64 kernel only): S adds into the numerator of Tau and
-    // Tau is kept in tau_out, both np_X x np_Y at orig * mat_stride; nullptr: neither
+    // dimer-internal terms (FP64 kernel only, every monomer with v virtuals): S - Y1[(i,b),(j,a)]
+    // - Y2[(j,a),(i,b)] adds into the numerator of Tau[(i,a),(j,b)] and Tau is kept in tau_out,
+    // all np x np at orig * mat_stride; nullptr: none of it
     const double* S = nullptr;
+    const double* Y1 = nullptr;
+    const double* Y2 = nullptr;
     double* tau_out = nullptr;
     int64_t mat_stride = 0;
+    int v = 0;
 };
 
 struct MonoDesc {

@@ -429,8 +429,9 @@ __device__ inline PairView make_view(const PairDesc& pd, const MonoDesc* monos, 
 }
 
 // One body for both variants: IN_LDS stages V in LDS (the pair list given to
-// it holds only pairs that fit); otherwise V is read from L2.
-template <bool IN_LDS, int NT>
+// it holds only pairs that fit); otherwise V is read from L2.  DIMER adds the
+// dimer-internal source of po to the numerator of Tau and keeps Tau.
+template <bool IN_LDS, int NT, bool DIMER>
 __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_pair,
                                  const MonoDesc* __restrict__ monos, const double* __restrict__ dif,
                                  const double* __restrict__ V, const double* __restrict__ M,
@@ -474,8 +475,10 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
 
         // ---- Tau = D_XY * (V + M_X V + V M_Y^T), E_D2 = 4 <V, Tau> ----
         double epart = 0.0;
-        const double* Sp = po.S ? po.S + pd.orig * po.mat_stride : nullptr;
-        double* Tp = po.tau_out ? po.tau_out + pd.orig * po.mat_stride : nullptr;
+        const double* Sp = DIMER ? po.S + pd.orig * po.mat_stride : nullptr;
+        const double* Y1p = DIMER ? po.Y1 + pd.orig * po.mat_stride : nullptr;
+        const double* Y2p = DIMER ? po.Y2 + pd.orig * po.mat_stride : nullptr;
+        double* Tp = DIMER ? po.tau_out + pd.orig * po.mat_stride : nullptr;
         for_tasks(make_grid(RB, CB), make_grid(0, 0), wave, NW, [&](int, int r0, int c0, auto shape) {
             constexpr int NR = decltype(shape)::NR, NC = decltype(shape)::NC;
             d4 acc[NR][NC];
@@ -495,12 +498,17 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
                         if (r < p.nX && c < p.nY) {
                             const double dinv = recip(p.dX[r] + dc);
                             const double v = IN_LDS ? sV[r * p.ldv + c] : p.V[(int64_t)r * p.nY + c];
-                            const double src = Sp ? v + Sp[(int64_t)r * p.npY + c] : v;
+                            double src = v;
+                            if (DIMER) {   // r = (i,a), c = (j,b)
+                                const int i = r / po.v, a = r - i * po.v, jj = c / po.v, b = c - jj * po.v;
+                                src += Sp[(int64_t)r * p.npY + c] - Y1p[(int64_t)(i * po.v + b) * p.npY + jj * po.v + a] -
+                                       Y2p[(int64_t)(jj * po.v + a) * p.npY + i * po.v + b];
+                            }
                             tv = dinv * (src + acc[i][j][t]);
                             epart += v * tv;
                         }
                         if (couple) tau[(int64_t)r * p.npY + c] = tv;
-                        if (Tp) Tp[(int64_t)r * p.npY + c] = tv;
+                        if (DIMER) Tp[(int64_t)r * p.npY + c] = tv;
                     }
             }
         });
@@ -544,6 +552,7 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
     if (sink == 1.2345e300) ed2[0] = sink;   // keeps the prefetch loads; never true for finite inputs
 }
 
+template <bool DIMER>
 __global__ __launch_bounds__(kThreadsL) void pair_fp64_lds_kernel(
     const PairDesc* __restrict__ pairs, int64_t n_pair, const MonoDesc* __restrict__ monos,
     const double* __restrict__ dif, const double* __restrict__ V, const double* __restrict__ M,
@@ -553,10 +562,11 @@ __global__ __launch_bounds__(kThreadsL) void pair_fp64_lds_kernel(
     if (ctrl && ctrl->done) return;
     __shared__ __align__(16) double sV[kLdsV];
     __shared__ double red[kThreadsL / 64];
-    pair_body<true, kThreadsL>(pairs, n_pair, monos, dif, V, M, G, scratch, slot_elems, ed2, couple, cl, po, sV,
+    pair_body<true, kThreadsL, DIMER>(pairs, n_pair, monos, dif, V, M, G, scratch, slot_elems, ed2, couple, cl, po, sV,
                                red);
 }
 
+template <bool DIMER>
 __global__ __launch_bounds__(kThreadsG, 2) void pair_fp64_glb_kernel(
     const PairDesc* __restrict__ pairs, int64_t n_pair, const MonoDesc* __restrict__ monos,
     const double* __restrict__ dif, const double* __restrict__ V, const double* __restrict__ M,
@@ -565,7 +575,7 @@ __global__ __launch_bounds__(kThreadsG, 2) void pair_fp64_glb_kernel(
     const ClState* __restrict__ cl, PartOut po) {
     if (ctrl && ctrl->done) return;
     __shared__ double red[kThreadsG / 64];
-    pair_body<false, kThreadsG>(pairs, n_pair, monos, dif, V, M, G, scratch, slot_elems, ed2, couple, cl, po,
+    pair_body<false, kThreadsG, DIMER>(pairs, n_pair, monos, dif, V, M, G, scratch, slot_elems, ed2, couple, cl, po,
                                 nullptr, red);
 }
 
@@ -574,8 +584,8 @@ __global__ __launch_bounds__(kThreadsG, 2) void pair_fp64_glb_kernel(
 int pair_fp64_blocks_per_cu(int lds_variant) {
     int n = 0;
     hipError_t e = lds_variant
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_fp64_lds_kernel, kThreadsL, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_fp64_glb_kernel, kThreadsG, 0);
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_fp64_lds_kernel<false>, kThreadsL, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_fp64_glb_kernel<false>, kThreadsG, 0);
     if (e != hipSuccess || n < 1) n = 1;
     return n;
 }
@@ -587,12 +597,22 @@ void launch_pair_fp64(int lds_variant, PartOut po, const PairDesc* pairs, int64_
                       int64_t slot_elems, int grid, double* ed2, int couple, const Ctrl* ctrl, const ClState* cl,
                       hipStream_t s) {
     if (n_pair <= 0) return;
-    if (lds_variant)
-        hipLaunchKernelGGL(pair_fp64_lds_kernel, dim3(grid), dim3(kThreadsL), 0, s, pairs, n_pair, monos, dif, V,
-                           M, G, scratch, slot_elems, ed2, couple, ctrl, cl, po);
-    else
-        hipLaunchKernelGGL(pair_fp64_glb_kernel, dim3(grid), dim3(kThreadsG), 0, s, pairs, n_pair, monos, dif, V,
-                           M, G, scratch, slot_elems, ed2, couple, ctrl, cl, po);
+    const bool dimer = po.S != nullptr;
+    if (lds_variant) {
+        if (dimer)
+            hipLaunchKernelGGL(pair_fp64_lds_kernel<true>, dim3(grid), dim3(kThreadsL), 0, s, pairs, n_pair, monos,
+                               dif, V, M, G, scratch, slot_elems, ed2, couple, ctrl, cl, po);
+        else
+            hipLaunchKernelGGL(pair_fp64_lds_kernel<false>, dim3(grid), dim3(kThreadsL), 0, s, pairs, n_pair, monos,
+                               dif, V, M, G, scratch, slot_elems, ed2, couple, ctrl, cl, po);
+    } else {
+        if (dimer)
+            hipLaunchKernelGGL(pair_fp64_glb_kernel<true>, dim3(grid), dim3(kThreadsG), 0, s, pairs, n_pair, monos,
+                               dif, V, M, G, scratch, slot_elems, ed2, couple, ctrl, cl, po);
+        else
+            hipLaunchKernelGGL(pair_fp64_glb_kernel<false>, dim3(grid), dim3(kThreadsG), 0, s, pairs, n_pair, monos,
+                               dif, V, M, G, scratch, slot_elems, ed2, couple, ctrl, cl, po);
+    }
 }
 
 }  // namespace mcpt

@@ -96,6 +96,7 @@ struct Resident {
     LccdDesc* d_plccd = nullptr;
     double *d_DW = nullptr, *d_DQ = nullptr, *d_DCX = nullptr, *d_DCY = nullptr, *d_Tau = nullptr, *d_S = nullptr;
     double* d_DRM = nullptr;          // 2 K - J per monomer (the monomer rings of Eq. 59)
+    double *d_DY1 = nullptr, *d_DY2 = nullptr;   // the cross-ring products of each pair
     int64_t dimer_mat = 0;            // np^2: elements of one pair's matrix
     int dimer_ring_blocks = 0, dimer_ct = 1;
     int64_t dimer_lds_bytes = 0;
