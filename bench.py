@@ -546,10 +546,8 @@ def dimer_problem():
     """The 1000-monomer crystal with nearest-neighbour pairs only (2,700 pairs, the
     c3 crystal's blocks of those pairs), K at LCCD_K_SCALE, with the intramonomer
     and the dimer classes: the dimer class (vv|vv) alone is 4.25 MB per pair."""
-    from synth import LCCD_K_SCALE, cubic_sites, dimer_integrals, lccd_integrals, make_lattice_problem
-    p = make_lattice_problem(cubic_sites(10, 10, 10), 1.0, workload=3, k_scale=LCCD_K_SCALE)
-    p.meta["name"] = DIMER_WORKLOAD
-    return p, lccd_integrals(p), dimer_integrals(p)
+    from synth import make_dimer_workload
+    return make_dimer_workload(DIMER_WORKLOAD)
 
 
 def dimer_mode(ctx, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: bool = True):
@@ -578,6 +576,7 @@ def dimer_mode(ctx, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: bool 
     dt = (time.perf_counter() - t0) / max(steps, 1)
     tm = ctx.timing()
     ctx.set_timing(False)
+    e = ctx.energy(pid, want_t=False)
     ctx.release(pid)
     kl = max(tm["dimer_launches"], 1)
     ms = tm["dimer_ladder_ms"] / kl
@@ -603,6 +602,13 @@ def dimer_mode(ctx, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: bool 
         # HIP events around the whole pair phase: the two launches above and the pair kernel
         "pair_phase_avg_ms": tm["pair_ms"] / max(tm["pair_launches"], 1),
     }
+    gpath = os.path.join(ROOT, "tests", "golden", f"dimer-{DIMER_WORKLOAD}.json")
+    if os.path.exists(gpath):
+        g = json.load(open(gpath))
+        out["oracle_reference"] = {"e_total": g["e_total"], "sweeps": g["sweeps"], "file": os.path.relpath(gpath, ROOT)}
+        out["relative_error_e_total"] = abs(s["e_total"] - g["e_total"]) / abs(g["e_total"])
+        out["max_abs_error_e_m2_Eh"] = float(np.max(np.abs(e["e_m2"] - np.asarray(g["e_m2"]))))
+        out["max_abs_error_e_d2_Eh"] = float(np.max(np.abs(e["e_d2"][g["pair_index"]] - np.asarray(g["e_d2"]))))
     log(f"[dimer] {s['iso_sweeps']} + {s['sweeps']} sweeps, {dt * 1e3:.1f} ms per solve, pair ladder {ms:.3f} ms = "
         f"{wb / (ms * 1e-3) / 1e9:.0f} GB/s, ring {rms:.3f} ms")
     if with_cpu:

@@ -501,16 +501,6 @@ __global__ __launch_bounds__(kLadLdsThreads) void lccd_ladder_lds_kernel(
 // ---------------------------------------------------------------------------
 // ring terms of the dimer equation (Eq. 59)
 // ---------------------------------------------------------------------------
-// For a pair with amplitudes Tau (np x np, rows (i,a) of X, columns (j,b) of Y)
-// the monomer rings are (2 K_X - J_X) Tau + Tau (2 K_Y - J_Y)^T, two products
-// into one accumulator added in place into the pair's source S (which holds the
-// two ladders, stored before this launch; every element of S has one owner
-// task); the cross rings are Y1 = C_X Vs(Tau) and Y2 = C_Y Vs(Tau^T), stored
-// as they come out, and the pair kernel subtracts Y1[(i,b),(j,a)] and
-// Y2[(j,a),(i,b)] when it forms Tau.  K-hat[(i,a),(i1,a1)] = K[i,i1,a,a1] and
-// J-hat[(i,a),(i1,a1)] = J[i1,i,a,a1] of the monomer (2 K-hat - J-hat formed once
-// per monomer at attach), C-hat packed from the pair's class the way J-hat is,
-// Vs the swap of the two virtual indices.  All blocks of a pair run on one XCD.
 // One product of a ring task into acc: A rows (k-contiguous, 32-byte loads) times B, where BM
 // selects B[k][c] = B[k np + c] (0), B[c np + k] (1, k-contiguous), or the Vs gather
 // B[kofs[k] + ycol[c]] (2).  The next k chunk's operands are in flight while the current one
@@ -565,6 +555,16 @@ __device__ inline void ring_product(d4 (&acc)[kRingSB][kRingSB], const double* A
     }
 }
 
+// For a pair with amplitudes Tau (np x np, rows (i,a) of X, columns (j,b) of Y)
+// the monomer rings are (2 K_X - J_X) Tau + Tau (2 K_Y - J_Y)^T, two products
+// into one accumulator added in place into the pair's source S (which holds the
+// two ladders, stored before this launch; every element of S has one owner
+// task); the cross rings are Y1 = C_X Vs(Tau) and Y2 = C_Y Vs(Tau^T), stored
+// as they come out, and the pair kernel subtracts Y1[(i,b),(j,a)] and
+// Y2[(j,a),(i,b)] when it forms Tau.  K-hat[(i,a),(i1,a1)] = K[i,i1,a,a1] and
+// J-hat[(i,a),(i1,a1)] = J[i1,i,a,a1] of the monomer (2 K-hat - J-hat formed once
+// per monomer at attach), C-hat packed from the pair's class the way J-hat is,
+// Vs the swap of the two virtual indices.  All blocks of a pair run on one XCD.
 __global__ __launch_bounds__(kLccdThreads, 2) void dimer_ring_kernel(
     const DimerDesc* __restrict__ dd, const MonoDesc* __restrict__ monos, const MonoDesc* __restrict__ pseudo,
     int n_pair, int blocks_per_pair, const double* __restrict__ RM, const double* __restrict__ CX,

@@ -6,4 +6,5 @@ from .hf_lattice import (  # noqa: F401
     singles_source, LccdIntegrals, lccd_integrals, concat_lccd, make_lccd_workload, LCCD_K_SCALE,
     central_cell, displacement_scales, stretch_modes, scaled_problem, STRETCH_PATTERNS,
     SPACING_A, DEFAULT_COUPLING_SCALE, DimerIntegrals, dimer_integrals,
+    DIMER_WORKLOADS, make_dimer_workload,
 )

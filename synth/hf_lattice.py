@@ -594,6 +594,24 @@ def dimer_integrals(prob: Problem, *, workload: int | None = None, cluster: int 
     return DimerIntegrals(np.asarray(shapes, dtype=np.int64).reshape(-1, 4), cat(ws), cat(qs), cat(cxs), cat(cys))
 
 
+# named workloads with the dimer classes: the crystals with nearest-neighbour pairs only (the
+# (vv|vv) class alone is 4.25 MB per pair at o = 5, v = 27)
+DIMER_WORKLOADS = {
+    "hf-3x3x3-c1": dict(workload=7, dims=(3, 3, 3), cutoff=1.0),
+    "hf-10x10x10-c1": dict(workload=3, dims=(10, 10, 10), cutoff=1.0),
+}
+
+
+def make_dimer_workload(name: str, coupling_scale: float = DEFAULT_COUPLING_SCALE):
+    """A named crystal with K at LCCD_K_SCALE x its sigma, the intramonomer classes
+    and the dimer classes.  Returns (problem, intramonomer integrals, dimer integrals)."""
+    spec = DIMER_WORKLOADS[name]
+    p = make_lattice_problem(cubic_sites(*spec["dims"]), spec["cutoff"], workload=spec["workload"],
+                             coupling_scale=coupling_scale, k_scale=LCCD_K_SCALE)
+    p.meta["name"] = name
+    return p, lccd_integrals(p), dimer_integrals(p)
+
+
 # ---------------------------------------------------------------------------
 # finite-displacement modes (Sec. IV.A: symmetric stretches of the molecules of
 # a unit cell, five-point grid)

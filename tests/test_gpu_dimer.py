@@ -4,17 +4,23 @@ on uniform clusters of one to nine MFMA tiles per edge (n = 6, 51, 135, the
 last two with ragged tails), with physical-symmetry and with general
 integrals, the converged solve with equal sweep counts, graph replay, and the
 error paths.  Bar: 1e-10 relative (FP64), sweep counts equal."""
+import json
+import os
+import types
+
 import numpy as np
 import pytest
 
 from oracle import mcpt_dimer
-from synth import LCCD_K_SCALE, cubic_sites, dimer_integrals, lccd_integrals, make_lattice_problem
+from synth import (LCCD_K_SCALE, concat_lccd, cubic_sites, dimer_integrals, lccd_integrals, make_dimer_workload,
+                   make_lattice_problem)
 import paper_1409_2700_amd as mc
 from paper_1409_2700_amd import mcpt as binding
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-10
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -105,3 +111,37 @@ def test_errors_and_detach(ctx):
     with pytest.raises(mc.MCPTError):              # monomers of different sizes
         ctx.dimer_attach(pid, dimer_integrals(q))
     ctx.release(pid)
+
+
+def test_batch_equals_solo(ctx):
+    """Two clusters of one batch stop on their own residuals exactly as alone."""
+    a = cluster(2, 3, workload=950)
+    b = cluster(2, 3, dims=(3, 1, 1), workload=951)
+    solo = [run_gpu(ctx, *c, tol=TOL, max_sweeps=200)[0] for c in (a, b)]
+    pid = ctx.upload_batch([a[0], b[0]])
+    ctx.lccd_attach(pid, concat_lccd([a[1], b[1]]))
+    ctx.dimer_attach(pid, types.SimpleNamespace(**{k: np.concatenate([getattr(a[2], k), getattr(b[2], k)])
+                                                   for k in ("w", "q", "cx", "cy")}))
+    s = ctx.run(pid, tol=TOL, max_sweeps=200)
+    res = ctx.cluster_results(pid)
+    ctx.release(pid)
+    assert s["return"] == mc.MCPT_OK
+    for k in range(2):
+        assert res[k]["sweeps"] == solo[k]["sweeps"]
+        assert abs(res[k]["e_total"] - solo[k]["e_total"]) <= 1e-12 * abs(solo[k]["e_total"])
+
+
+@pytest.mark.parametrize("name", ["hf-3x3x3-c1", "hf-10x10x10-c1"])
+def test_converged_crystals_match_stored_oracle(ctx, name):
+    with open(os.path.join(GOLDEN, f"dimer-{name}.json")) as f:
+        g = json.load(f)
+    p, ints, dints = make_dimer_workload(name)
+    print(f"[gpu] dimer converged {name} N={p.n_mono} P={p.n_pair}", flush=True)
+    s, e = run_gpu(ctx, p, ints, dints, tol=g["tol"], max_sweeps=400, check_every=4)
+    assert s["return"] == mc.MCPT_OK and g["status"] == 0, s["error"]
+    assert s["sweeps"] == g["sweeps"]
+    assert abs(s["e_total"] - g["e_total"]) <= TOL * abs(g["e_total"])
+    assert abs(s["e_mono0"] - g["e_lccd_total"]) <= TOL * abs(g["e_lccd_total"])
+    assert rel(e["e_m2"], g["e_m2"]) <= TOL
+    assert rel(e["e_m2"] - e["de_m2"], g["e_lccd"]) <= TOL
+    assert rel(e["e_d2"][g["pair_index"]], g["e_d2"]) <= TOL
