@@ -37,3 +37,24 @@ def test_carved_subcluster_keeps_blocks_of_its_pairs():
     carved = set(idx)
     n_inside = sum(1 for (x, y) in base.pairs if x in carved and y in carved)
     assert n_inside == p.n_pair
+
+
+def test_dimer_integrals_seeded_and_symmetric():
+    """The dimer classes are keyed by the two sites (a pair drawn inside a larger
+    crystal equals the same pair drawn alone) and symmetric within each charge
+    distribution, (pq|rs) = (qp|rs) = (pq|sr)."""
+    import numpy as np
+    from synth import cubic_sites, dimer_integrals, make_lattice_problem
+    big = make_lattice_problem(cubic_sites(3, 1, 1), 1.0, o=2, v=3, workload=930)
+    small = make_lattice_problem(cubic_sites(2, 1, 1), 1.0, o=2, v=3, workload=930)
+    db, ds = dimer_integrals(big), dimer_integrals(small)
+    assert tuple(big.pairs[0]) == tuple(small.pairs[0]) == (0, 1)
+    for f in ("w_of", "q_of", "cx_of", "cy_of"):
+        assert np.array_equal(getattr(db, f)(0), getattr(ds, f)(0))
+    w = db.w_of(1)                                   # [a, b, a1, b1] = (a a1|b b1)
+    assert np.allclose(w, w.transpose(2, 1, 0, 3)) and np.allclose(w, w.transpose(0, 3, 2, 1))
+    q = db.q_of(1)                                   # [i1, j1, i, j] = (i1 i|j1 j)
+    assert np.allclose(q, q.transpose(2, 1, 0, 3)) and np.allclose(q, q.transpose(0, 3, 2, 1))
+    for c in (db.cx_of(1), db.cy_of(1)):             # (i1 i|b b1), (j1 j|a a1)
+        assert np.allclose(c, c.transpose(1, 0, 2, 3)) and np.allclose(c, c.transpose(0, 1, 3, 2))
+    assert not np.allclose(db.w_of(0), db.w_of(1))
