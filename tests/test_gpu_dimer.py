@@ -145,3 +145,47 @@ def test_converged_crystals_match_stored_oracle(ctx, name):
     assert rel(e["e_m2"], g["e_m2"]) <= TOL
     assert rel(e["e_m2"] - e["de_m2"], g["e_lccd"]) <= TOL
     assert rel(e["e_d2"][g["pair_index"]], g["e_d2"]) <= TOL
+
+
+def test_device_integrals(ctx):
+    """Dimer classes handed over in device memory give the host hand-over's results."""
+    import ctypes
+    hip = ctypes.CDLL(os.path.join("/opt/rocm/lib", "libamdhip64.so"))
+    p, ints, dints = cluster(3, 17, workload=952)
+    pid = ctx.upload(p)
+    ctx.lccd_attach(pid, ints)
+    ctx.dimer_attach(pid, dints)
+    a = ctx.run(pid, tol=TOL)
+    ea = ctx.energy(pid)
+    arrs = [np.ascontiguousarray(x) for x in (dints.w, dints.q, dints.cx, dints.cy)]
+    ptrs = []
+    try:
+        for arr in arrs:
+            d = ctypes.c_void_p()
+            assert hip.hipMalloc(ctypes.byref(d), ctypes.c_size_t(max(arr.nbytes, 8))) == 0
+            ptrs.append(d)
+            assert hip.hipMemcpy(d, arr.ctypes.data_as(ctypes.c_void_p), ctypes.c_size_t(arr.nbytes), 1) == 0
+        ctx.dimer_attach(pid, None, device_ptrs=tuple(d.value for d in ptrs))
+        b = ctx.run(pid, tol=TOL)
+        eb = ctx.energy(pid)
+    finally:
+        for d in ptrs:
+            hip.hipFree(d)
+    ctx.release(pid)
+    assert a["return"] == mc.MCPT_OK and a["sweeps"] == b["sweeps"]
+    assert rel(eb["e_m2"], ea["e_m2"]) <= 1e-13 and rel(eb["e_d2"], ea["e_d2"]) <= 1e-13
+
+
+def test_single_pair_and_no_pairs(ctx):
+    """One pair (two monomers) against the oracle; a problem without pairs is refused."""
+    p, ints, dints = cluster(5, 27, dims=(2, 1, 1), workload=953)
+    ref = mcpt_dimer.solve(p, ints, dints, tol=0.0, max_sweeps=3)
+    s, e = run_gpu(ctx, p, ints, dints, tol=0.0, max_sweeps=3)
+    assert s["return"] == mc.MCPT_OK, s["error"]
+    assert rel(e["t"], flat_t(ref)) <= TOL and rel(e["e_d2"], ref.e_d2) <= TOL
+    q = make_lattice_problem(cubic_sites(1, 1, 1), None, o=2, v=3, workload=954)
+    pid = ctx.upload(q)
+    ctx.lccd_attach(pid, lccd_integrals(q))
+    with pytest.raises(mc.MCPTError):
+        ctx.dimer_attach(pid, dimer_integrals(q))
+    ctx.release(pid)
