@@ -189,3 +189,21 @@ def test_single_pair_and_no_pairs(ctx):
     with pytest.raises(mc.MCPTError):
         ctx.dimer_attach(pid, dimer_integrals(q))
     ctx.release(pid)
+
+
+def test_largest_monomer_and_first_refused(ctx):
+    """o = 6, v = 23 (n = 138): three column tiles per ladder task and 155 KB of the
+    160 KiB of LDS, element by element after two sweeps; o = 6, v = 24 (n = 144, 168 KB
+    of amplitudes) is refused."""
+    p, ints, dints = cluster(6, 23, dims=(2, 1, 1), workload=955)
+    ref = mcpt_dimer.solve(p, ints, dints, tol=0.0, max_sweeps=2)
+    s, e = run_gpu(ctx, p, ints, dints, tol=0.0, max_sweeps=2)
+    assert s["return"] == mc.MCPT_OK, s["error"]
+    assert rel(e["t"], flat_t(ref)) <= TOL and rel(e["e_d2"], ref.e_d2) <= TOL
+    assert rel(e["e_m2"], ref.e_m2) <= TOL
+    q, qi, qd = cluster(6, 24, dims=(2, 1, 1), workload=956)
+    pid = ctx.upload(q)
+    ctx.lccd_attach(pid, qi)
+    with pytest.raises(mc.MCPTError):
+        ctx.dimer_attach(pid, qd)
+    ctx.release(pid)
