@@ -207,3 +207,24 @@ def test_largest_monomer_and_first_refused(ctx):
     with pytest.raises(mc.MCPTError):
         ctx.dimer_attach(pid, qd)
     ctx.release(pid)
+
+
+def test_lccd_reattach_detaches_dimer_terms(ctx):
+    """Attaching the intramonomer integrals again drops the dimer classes: the run
+    is the full monomer equation's, and the dimer terms can be attached again."""
+    from oracle import mcpt_lccd
+    p, ints, dints = cluster(3, 17, workload=957)
+    pid = ctx.upload(p)
+    ctx.lccd_attach(pid, ints)
+    ctx.dimer_attach(pid, dints)
+    ctx.lccd_attach(pid, ints)
+    s = ctx.run(pid, tol=0.0, max_sweeps=2)
+    e = ctx.energy(pid)
+    ref = mcpt_lccd.solve(p, ints, tol=0.0, max_sweeps=2)
+    assert s["return"] == mc.MCPT_OK and rel(e["e_d2"], ref.e_d2) <= TOL
+    ctx.dimer_attach(pid, dints)
+    s = ctx.run(pid, tol=0.0, max_sweeps=2)
+    e = ctx.energy(pid)
+    ctx.release(pid)
+    ref = mcpt_dimer.solve(p, ints, dints, tol=0.0, max_sweeps=2)
+    assert s["return"] == mc.MCPT_OK and rel(e["e_d2"], ref.e_d2) <= TOL and rel(e["t"], flat_t(ref)) <= TOL
