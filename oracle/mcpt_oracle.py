@@ -21,6 +21,16 @@ Readings taken where the paper is silent, garbled or ambiguous:
   terms with their printed signs), i.e. T = D * (v + ...), with
   eps^{ij}_{ab} = e_i + e_j - e_a - e_b and D = 1/eps (Eqs. 60-61).  At zero
   coupling this gives the (negative) closed-shell second-order energy.
+* Spin sum of the pair term.  The printed pair term of Eq. 58 carries no spin
+  factor, while every other Coulomb loop of the spin-adapted equations does
+  (the 2v - v rings, the 2T - T of Eq. 59, the 2v of the embedding field of
+  Eq. 26).  Sec. II.A states that the method is LCCD for canonical HF orbitals;
+  on integrals cut from one real two-electron tensor of a dimer without
+  exchange between the monomers, restricted spin-orbital LCCD reproduces the
+  spatial-orbital equations exactly when the summed k, c of Y run over both
+  spins, which doubles the printed term.  The oracle therefore carries the
+  factor 2 (the spin-summed reading); the printed half is a planted mistake
+  that the pins reject.
 * Every o.v.o.v dimer integral in Eqs. 55, 58 and 59 is the one Coulomb block
   V_XY[i, a, j, b] = (ai|bj) of real orbitals (Eq. 29 with i, a on X and j, b
   on Y); the block of the reversed pair is its transpose.
@@ -104,19 +114,24 @@ def dimer_amplitudes(V: np.ndarray, T_x: np.ndarray, T_y: np.ndarray, D_xy: np.n
     return D_xy * (src + from_x + from_y)
 
 
+SPIN_SUM = 2.0   # both spins of the summed k, c on Y (Sec. II.A: the method is LCCD)
+
+
 def pair_coupling(V: np.ndarray, Tau: np.ndarray) -> np.ndarray:
     """The pair term of Eq. (58) for one neighbour Y of X, as a tensor [i, i1, a, a1]:
 
-        v^{a1 k}_{i1 c} Tau^{a c}_{i k} + v^{a k}_{i c} Tau^{a1 c}_{i1 k}
+        2 (v^{a1 k}_{i1 c} Tau^{a c}_{i k} + v^{a k}_{i c} Tau^{a1 c}_{i1 k})
 
-    with c, k on Y, v^{a1 k}_{i1 c} = V[i1, a1, k, c], Tau^{ac}_{ik} = Tau[i, a, k, c]."""
+    with c, k on Y, v^{a1 k}_{i1 c} = V[i1, a1, k, c], Tau^{ac}_{ik} = Tau[i, a, k, c];
+    the factor 2 is the sum over the two spins of the spatial k, c on Y."""
     t1 = np.einsum("IAkc,iakc->iIaA", V, Tau, optimize=True)
     t2 = np.einsum("iakc,IAkc->iIaA", V, Tau, optimize=True)
-    return t1 + t2
+    return SPIN_SUM * (t1 + t2)
 
 
 def monomer_amplitudes(K: np.ndarray, D_x: np.ndarray, couplings) -> np.ndarray:
-    """T^{a a1}_{i i1} from Eq. (58): eps T = v^{a a1}_{i i1} + sum over Y of the pair term."""
+    """T^{a a1}_{i i1} from Eq. (58): eps T = v^{a a1}_{i i1} + sum over Y of the
+    (spin-summed) pair term."""
     rhs = K.copy()
     for c in couplings:
         rhs = rhs + c

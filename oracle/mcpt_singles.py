@@ -17,11 +17,15 @@ Readings taken where the paper is silent or ambiguous:
   an oo|vv one that is not an input, so it is dropped as a whole (the same
   rule as for the doubles).
 * Sign: eps^i_a t = w + (the printed coupling with its printed sign), with
-  eps^i_a = e_i - e_a, i.e. t = d * (w + sum_Y v t), d = 1 / (e_i - e_a); the
+  eps^i_a = e_i - e_a, i.e. t = d * (w + 2 sum_Y v t), d = 1 / (e_i - e_a); the
   same reading as the doubles.  At zero coupling the energy is then
   2 sum |w|^2 / (e_i - e_a) < 0, the textbook second-order singles energy.
 * v^{ak}_{ic} with i, a on X and k, c on Y is (ai|ck) = V_XY[i, a, k, c], the
   Coulomb block the doubles use; for the reversed pair it is V_XY transposed.
+* Spin sum: as for the pair term of Eq. 58, the summed k, c of Y run over both
+  spins (the intramonomer term's 2v has the same origin), so the pair sum
+  carries a factor 2: t = d * (w + 2 sum_Y v t).  Pinned against restricted
+  spin-orbital linear singles on a dimer cut from one real two-electron tensor.
 * One sweep updates every monomer from the previous amplitudes (Jacobi); the
   initial guess is the first-order amplitude t = d * w (step 4 starts from w);
   the residual is max |t_new - t| over all monomers; the divergence rule is the
@@ -33,7 +37,7 @@ import dataclasses
 
 import numpy as np
 
-from .mcpt_oracle import STATUS_DIVERGED, STATUS_NOT_CONVERGED, STATUS_OK, diverging
+from .mcpt_oracle import SPIN_SUM, STATUS_DIVERGED, STATUS_NOT_CONVERGED, STATUS_OK, diverging
 
 
 def singles_denominator(e_occ: np.ndarray, e_vir: np.ndarray) -> np.ndarray:
@@ -75,18 +79,19 @@ def _split(prob, w):
 
 
 def coupling(prob, t):
-    """u_X = sum over the neighbours Y of X of v^{ak}_{ic} t^c_k  (the pair sum of Eq. 57)."""
+    """u_X = 2 sum over the neighbours Y of X of v^{ak}_{ic} t^c_k  (the pair sum of
+    Eq. 57, summed over both spins of k, c)."""
     u = [np.zeros_like(tx) for tx in t]
     for p in range(prob.n_pair):
         x, y = (int(q) for q in prob.pairs[p])
         V = np.asarray(prob.v_of(p), dtype=np.float64)          # [i, a, k, c], i, a on X
         u[x] += np.einsum("iakc,kc->ia", V, t[y])
         u[y] += np.einsum("iakc,ia->kc", V, t[x])               # reversed pair: V_XY transposed
-    return u
+    return [SPIN_SUM * ux for ux in u]
 
 
 def solve(prob, w, tol: float = 1e-10, max_sweeps: int = 500) -> SinglesResult:
-    """Iterate t = d * (w + sum_Y v t) until max |t_new - t| < tol (tol == 0:
+    """Iterate t = d * (w + 2 sum_Y v t) until max |t_new - t| < tol (tol == 0:
     exactly max_sweeps sweeps, status OK unless the residual became non-finite)."""
     ws = _split(prob, w)
     d = [singles_denominator(*prob.eps_of(x)) for x in range(prob.n_mono)]

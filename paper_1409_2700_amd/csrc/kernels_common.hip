@@ -92,11 +92,11 @@ __device__ double block_max(double x, double* sh) {
 // S(r, c) are recomputed from inputs, never read from an output).
 // E_M2 = <2K - S(K), T> = <K, M> (Eq. 54).  Modes:
 //   init      T = D K, M, E_M2 -> em2 and em2_0
-//   update    T' = D (K + G + G^T), residual |T' - T|, M', E_M2(T')
+//   update    T' = D (K + 2 (G + G^T)), residual |T' - T|, M', E_M2(T')  (2: spin sum)
 //   from_t    M and E_M2 of the stored T
 //   e0        E_M2 of D K into em2_0 only
 //   update_r  as update, and R = T' - T kept, low-precision copy of 2R - S(R)
-//   corr      delta = R + D (G + G^T) (homogeneous equation), low-precision 2 delta - S(delta)
+//   corr      delta = R + 2 D (G + G^T) (homogeneous equation), low-precision 2 delta - S(delta)
 //   apply     T += delta - R (elementwise)
 // Mlo (optional) receives the low-precision copy of the combination written.
 // G is read, and Gz cleared, in GT: double, or float for the FP32 accumulation
@@ -143,11 +143,11 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
         if (mode == kMonoUpdate || mode == kMonoUpdateR) {
             if (Lt) {   // intramonomer terms of the full monomer equation
                 const double* Lx = Lt + d.mat_off;
-                tn = dinv * (((Kx[e_rc] + (double)Gx[e_rc]) + (double)Gx[e_t]) + Lx[e_rc]);
-                ts = dinv * (((Kx[e_s] + (double)Gx[e_s]) + (double)Gx[e_st]) + Lx[e_s]);
+                tn = dinv * (((Kx[e_rc] + kSpinSum * (double)Gx[e_rc]) + kSpinSum * (double)Gx[e_t]) + Lx[e_rc]);
+                ts = dinv * (((Kx[e_s] + kSpinSum * (double)Gx[e_s]) + kSpinSum * (double)Gx[e_st]) + Lx[e_s]);
             } else {
-                tn = dinv * ((Kx[e_rc] + (double)Gx[e_rc]) + (double)Gx[e_t]);
-                ts = dinv * ((Kx[e_s] + (double)Gx[e_s]) + (double)Gx[e_st]);
+                tn = dinv * ((Kx[e_rc] + kSpinSum * (double)Gx[e_rc]) + kSpinSum * (double)Gx[e_t]);
+                ts = dinv * ((Kx[e_s] + kSpinSum * (double)Gx[e_s]) + kSpinSum * (double)Gx[e_st]);
             }
             const double told = Tx[e_rc];
             rmax = max_nan(rmax, fabs(tn - told));
@@ -162,11 +162,11 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_kernel(
         } else if (mode == kMonoCorr) {
             if (Lt) {   // intramonomer terms of the correction (full monomer equation)
                 const double* Lx = Lt + d.mat_off;
-                tn = Rx[e_rc] + dinv * (((double)Gx[e_rc] + (double)Gx[e_t]) + Lx[e_rc]);
-                ts = Rx[e_s] + dinv * (((double)Gx[e_s] + (double)Gx[e_st]) + Lx[e_s]);
+                tn = Rx[e_rc] + dinv * ((kSpinSum * (double)Gx[e_rc] + kSpinSum * (double)Gx[e_t]) + Lx[e_rc]);
+                ts = Rx[e_s] + dinv * ((kSpinSum * (double)Gx[e_s] + kSpinSum * (double)Gx[e_st]) + Lx[e_s]);
             } else {
-                tn = Rx[e_rc] + dinv * ((double)Gx[e_rc] + (double)Gx[e_t]);
-                ts = Rx[e_s] + dinv * ((double)Gx[e_s] + (double)Gx[e_st]);
+                tn = Rx[e_rc] + dinv * (kSpinSum * (double)Gx[e_rc] + kSpinSum * (double)Gx[e_t]);
+                ts = Rx[e_s] + dinv * (kSpinSum * (double)Gx[e_s] + kSpinSum * (double)Gx[e_st]);
             }
             Dx[e_rc] = tn;
             lo = 2.0 * tn - ts;
@@ -259,8 +259,8 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_blocks_kernel(
                 __syncthreads();   // the previous block pair is done with sg
                 for (int idx = threadIdx.x; idx < v * v; idx += kMonoThreads) {
                     const int a = idx / v, b = idx - a * v;
-                    sg[0][a][b] = (double)Gx[(int64_t)(i * v + a) * np + j * v + b];
-                    sg[1][a][b] = (double)Gx[(int64_t)(j * v + a) * np + i * v + b];
+                    sg[0][a][b] = kSpinSum * (double)Gx[(int64_t)(i * v + a) * np + j * v + b];
+                    sg[1][a][b] = kSpinSum * (double)Gx[(int64_t)(j * v + a) * np + i * v + b];
                 }
                 __syncthreads();
             }

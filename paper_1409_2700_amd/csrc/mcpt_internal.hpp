@@ -19,6 +19,10 @@ namespace mcpt {
 
 constexpr int kTile = 16;              // MFMA tile edge; matrices are padded to a multiple
 constexpr int kMaxSweeps = 4096;       // length of the device residual history
+// The pair terms of Eqs. 57 and 58 sum k, c of the neighbour Y over both spins
+// (a closed-shell Coulomb loop; with it the equations are restricted LCCD,
+// Sec. II.A): the accumulated pair sums G and u enter the monomer updates twice.
+constexpr double kSpinSum = 2.0;
 
 // 1 / d for the denominators of Eqs. 60-61 (negative, |d| well above zero):
 // the hardware reciprocal estimate refined by two Newton-Raphson steps

@@ -4,7 +4,9 @@
 // With the terms the inputs can form, one Jacobi sweep is
 //
 //   u_X = sum over neighbours Y of v^{ak}_{ic} t^c_k = sum_Y V_XY t_Y
-//   t_X <- (w_X + u_X) / (e_i - e_a)                      (eps^i_a of Eq. 57)
+//   t_X <- (w_X + 2 u_X) / (e_i - e_a)                    (eps^i_a of Eq. 57)
+//
+// (the 2 sums k, c of Y over both spins)
 //   E_M1(X) = 2 w^i_a t^a_i                               (Eq. 53)
 //
 // where v^{ak}_{ic} = (ai|ck) = V_XY[(i,a),(k,c)] is the Coulomb block the
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(kSThreads) void singles_pair_kernel(
 }
 
 // init: t = w / d (first order), E_M1 into em1 and em1_0.
-// update: t' = (w + u) / d, residual max|t' - t|, E_M1(t'), u cleared for the next sweep.
+// update: t' = (w + 2 u) / d, residual max|t' - t|, E_M1(t'), u cleared for the next sweep.
 __global__ __launch_bounds__(kMonoThreadsS) void singles_mono_kernel(
     int init, const MonoDesc* __restrict__ monos, const double* __restrict__ dif, const double* __restrict__ w,
     double* __restrict__ u, double* __restrict__ t, double* __restrict__ em1, double* __restrict__ em1_0,
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(kMonoThreadsS) void singles_mono_kernel(
             tx[k] = tn;
             e += wx[k] * tn;
         } else {
-            const double tn = di * (wx[k] + ux[k]);
+            const double tn = di * (wx[k] + kSpinSum * ux[k]);
             rmax = max_nan(rmax, fabs(tn - tx[k]));
             tx[k] = tn;
             ux[k] = 0.0;

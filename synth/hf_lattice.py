@@ -35,8 +35,11 @@ SIGMA_V = 0.05
 EPS_OCC = (-1.5, -0.5)
 EPS_VIR = (0.2, 3.0)
 # default coupling scale: at scale 1 the sweep map of these random blocks has a
-# dominant eigenvalue > 1 and Jacobi diverges (stated deviation, see DESIGN)
-DEFAULT_COUPLING_SCALE = 0.25
+# dominant eigenvalue > 1 and Jacobi diverges.  The doubles sweep map depends on
+# the couplings through 2 x scale^2 (spin-summed pair term times V twice), and
+# 0.18 puts the 1000-monomer crystal at about the 15 micro-iterations the paper
+# reports; the singles map (linear in the scale) then contracts by about 0.6
+DEFAULT_COUPLING_SCALE = 0.18
 
 KIND_MONOMER = 0
 KIND_PAIR = 1

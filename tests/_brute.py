@@ -61,6 +61,33 @@ class Cluster:
         return self.chem(p, r, q, s)
 
 
+SPINS = (0, 1)   # alpha, beta
+
+
+def v_spin(cl: Cluster, p, sp, q, sq, r, sr, s, ss) -> float:
+    """<p sp, q sq | r sr, s ss> between spin orbitals: the spatial (pr|qs) when
+    electron 1 keeps its spin (sp == sr) and electron 2 keeps its spin (sq == ss)."""
+    return cl.v(p, q, r, s) if (sp == sr and sq == ss) else 0.0
+
+
+def pair_term(cl: Cluster, X: int, tau, i, i1, a, a1, sigma=0) -> float:
+    """The pair term of Eq. (58) at (i, i1, a, a1) for the alpha electron pair
+    (i, a) of X: the sum over every neighbour Y and every spin orbital k, c of Y
+    (both spins: the spatial-orbital equation runs over spin orbitals there, and
+    without exchange between monomers the dimer amplitude does not depend on
+    the spin of Y's electron) of v^{a1 k}_{i1 c} Tau^{ac}_{ik} + v^{ak}_{ic} Tau^{a1 c}_{i1 k}."""
+    s_ = 0.0
+    for Y in cl.neighbours[X]:
+        t = tau[(X, Y)]
+        for k in cl.occ[Y]:
+            for c in cl.vir[Y]:
+                for sk in SPINS:
+                    for sc in SPINS:
+                        s_ += v_spin(cl, a1, sigma, k, sk, i1, sigma, c, sc) * t[i.idx, a.idx, k.idx, c.idx]
+                        s_ += v_spin(cl, a, sigma, k, sk, i, sigma, c, sc) * t[i1.idx, a1.idx, k.idx, c.idx]
+    return s_
+
+
 def brute_tau(cl: Cluster, X: int, Y: int, T) -> np.ndarray:
     """Dimer amplitudes of the ordered pair (X, Y) from Eq. (59), reduced terms."""
     OX, VX, OY, VY = cl.occ[X], cl.vir[X], cl.occ[Y], cl.vir[Y]
@@ -93,12 +120,7 @@ def brute_T(cl: Cluster, X: int, tau) -> np.ndarray:
             for a in VX:
                 for a1 in VX:
                     rhs = cl.v(a, a1, i, i1)                    # v^{a a1}_{i i1}
-                    for Y in cl.neighbours[X]:
-                        t = tau[(X, Y)]
-                        for k in cl.occ[Y]:
-                            for c in cl.vir[Y]:
-                                rhs += cl.v(a1, k, i1, c) * t[i.idx, a.idx, k.idx, c.idx]
-                                rhs += cl.v(a, k, i, c) * t[i1.idx, a1.idx, k.idx, c.idx]
+                    rhs += pair_term(cl, X, tau, i, i1, a, a1)
                     eps = cl.e(i) + cl.e(i1) - cl.e(a) - cl.e(a1)
                     out[i.idx, i1.idx, a.idx, a1.idx] = rhs / eps
     return out
@@ -189,8 +211,12 @@ def dense_solve(prob):
                         for Y in cl.neighbours[X]:
                             for k in cl.occ[Y]:
                                 for c in cl.vir[Y]:
-                                    A[row, index[("U", X, Y, i.idx, a.idx, k.idx, c.idx)]] -= cl.v(a1, k, i1, c)
-                                    A[row, index[("U", X, Y, i1.idx, a1.idx, k.idx, c.idx)]] -= cl.v(a, k, i, c)
+                                    for sk in SPINS:           # spin orbitals k, c of Y
+                                        for sc in SPINS:
+                                            A[row, index[("U", X, Y, i.idx, a.idx, k.idx, c.idx)]] -= \
+                                                v_spin(cl, a1, 0, k, sk, i1, 0, c, sc)
+                                            A[row, index[("U", X, Y, i1.idx, a1.idx, k.idx, c.idx)]] -= \
+                                                v_spin(cl, a, 0, k, sk, i, 0, c, sc)
     for (X, Y) in ordered:
         for i in cl.occ[X]:
             for a in cl.vir[X]:
@@ -264,7 +290,8 @@ def brute_singles_first_order(cl: Cluster, w):
 
 def brute_singles_sweep(cl: Cluster, w, t):
     """One Jacobi sweep of Eq. (57), source and pair terms:
-    eps^i_a t^a_i = w^a_i + sum over neighbours Y, k, c in Y of v^{ak}_{ic} t^c_k."""
+    eps^i_a t^a_i = w^a_i + sum over neighbours Y and spin orbitals k, c of Y of
+    v^{ak}_{ic} t^c_k (closed shell: t^c_k is the same for both spins)."""
     out = []
     for X in range(cl.N):
         tx = np.zeros((len(cl.occ[X]), len(cl.vir[X])))
@@ -274,7 +301,9 @@ def brute_singles_sweep(cl: Cluster, w, t):
                 for Y in cl.neighbours[X]:
                     for k in cl.occ[Y]:
                         for c in cl.vir[Y]:
-                            rhs += cl.v(a, k, i, c) * t[Y][k.idx, c.idx]      # v^{ak}_{ic}
+                            for sk in SPINS:
+                                for sc in SPINS:                           # v^{ak}_{ic}, i, a alpha
+                                    rhs += v_spin(cl, a, 0, k, sk, i, 0, c, sc) * t[Y][k.idx, c.idx]
                 tx[i.idx, a.idx] = rhs / (cl.e(i) - cl.e(a))
         out.append(tx)
     return out

@@ -73,12 +73,7 @@ def brute_T_full(cl: LccdCluster, X: int, T, tau, couple=True) -> np.ndarray:
                 for a1 in V:
                     rhs = cl.v(a, a1, i, i1) + intramonomer(cl, X, T, i, i1, a, a1)
                     if couple:
-                        for Y in cl.neighbours[X]:
-                            ty = tau[(X, Y)]
-                            for k in cl.occ[Y]:
-                                for c in cl.vir[Y]:
-                                    rhs += cl.v(a1, k, i1, c) * ty[i.idx, a.idx, k.idx, c.idx]
-                                    rhs += cl.v(a, k, i, c) * ty[i1.idx, a1.idx, k.idx, c.idx]
+                        rhs += _brute.pair_term(cl, X, tau, i, i1, a, a1)
                     out[i.idx, i1.idx, a.idx, a1.idx] = rhs / (cl.e(i) + cl.e(i1) - cl.e(a) - cl.e(a1))
     return out
 
@@ -131,13 +126,7 @@ def dense_lccd(prob, ints):
                     for a in V:
                         for a1 in V:
                             eps = cl.e(i) + cl.e(i1) - cl.e(a) - cl.e(a1)
-                            c = intramonomer(cl, X, T, i, i1, a, a1)
-                            for Y in cl.neighbours[X]:
-                                ty = tau[(X, Y)]
-                                for k in cl.occ[Y]:
-                                    for cc in cl.vir[Y]:
-                                        c += cl.v(a1, k, i1, cc) * ty[i.idx, a.idx, k.idx, cc.idx]
-                                        c += cl.v(a, k, i, cc) * ty[i1.idx, a1.idx, k.idx, cc.idx]
+                            c = intramonomer(cl, X, T, i, i1, a, a1) + _brute.pair_term(cl, X, tau, i, i1, a, a1)
                             src = cl.v(a, a1, i, i1) if with_source else 0.0
                             r[i.idx, i1.idx, a.idx, a1.idx] = eps * T[X][i.idx, i1.idx, a.idx, a1.idx] - c - src
             out[offs[X]:offs[X + 1]] = r.ravel()

@@ -230,9 +230,60 @@ def pin_divergence_detected(orc):
     return r.status == -5, f"status {r.status} after {r.sweeps} sweeps"
 
 
+def coupling_only_dimer(sx, sy, seed, sigma=0.05):
+    """Two monomers whose only nonzero two-electron integrals are the Coulomb
+    integrals (ai|bj) between an occupied-virtual distribution of X and one of Y,
+    cut from one real tensor (pq|rs) of the dimer's orbitals (every permutation
+    of a real-orbital integral filled in).  The intramonomer block K is then zero
+    and the reduced equations are the complete equations of this Hamiltonian.
+    Returns (problem, g, orbital energies, orbital table)."""
+    rng = np.random.default_rng(seed)
+    (ox, vx), (oy, vy) = sx, sy
+    nx, ny = ox + vx, oy + vy
+    OX, VX = np.arange(ox), np.arange(ox, nx)
+    OY, VY = nx + np.arange(oy), nx + np.arange(oy, ny)
+    blk = rng.normal(0.0, sigma, size=(vx, ox, vy, oy))           # (a i|b j)
+    g = np.zeros((nx + ny,) * 4)
+    for (p_, q_), pq in (((VX, OX), blk), ((OX, VX), blk.transpose(1, 0, 2, 3))):
+        for (r_, s_), rs in (((VY, OY), pq), ((OY, VY), pq.transpose(0, 1, 3, 2))):
+            g[np.ix_(p_, q_, r_, s_)] = rs
+            g[np.ix_(r_, s_, p_, q_)] = rs.transpose(2, 3, 0, 1)
+    ex = np.concatenate([np.sort(rng.uniform(-1.5, -0.5, ox)), np.sort(rng.uniform(0.2, 3.0, vx))])
+    ey = np.concatenate([np.sort(rng.uniform(-1.5, -0.5, oy)), np.sort(rng.uniform(0.2, 3.0, vy))])
+    orbs = [(0, k < ox, k if k < ox else k - ox) for k in range(nx)] + \
+           [(1, k < oy, k if k < oy else k - oy) for k in range(ny)]
+    p = make_lattice_problem(cubic_sites(2, 1, 1), None, sizes=[sx, sy], workload=TEST_WORKLOAD)
+    assert p.n_pair == 1 and tuple(p.pairs[0]) == (0, 1)
+    p.eps[:] = np.concatenate([ex, ey])
+    p.k[:] = 0.0
+    p.v[:] = blk.transpose(1, 0, 3, 2).ravel()                      # V[i,a,j,b] = (ai|bj)
+    return p, g, np.concatenate([ex, ey]), orbs
+
+
+@_safe
+def pin_restricted_lccd_coupling(orc):
+    """On a dimer whose only integrals are the inter-monomer Coulomb class (K = 0),
+    the reduced equations are complete, and the method is LCCD (Sec. II.A): the
+    converged energy, T_X, T_Y (alpha-beta amplitudes) and Tau equal restricted
+    spin-orbital LCCD solved densely in the excitations that keep each electron
+    on its monomer.  Fixes the spin sum of the pair term of Eq. 58 (twice the
+    printed term) and the 2T - T of Eq. 59 against textbook LCCD."""
+    from .pins_dimer import compare_restricted_lccd
+    worst = 0.0
+    for sx, sy, seed in [((1, 2), (1, 2), 31), ((2, 2), (1, 3), 32), ((2, 3), (2, 2), 33)]:
+        p, g, e, orbs = coupling_only_dimer(sx, sy, seed, sigma=0.15)
+        r = orc.solve(p, tol=1e-15, max_sweeps=400)
+        if r.status != 0:
+            return False, f"status {r.status}"
+        if not np.any(r.T[0]):
+            return False, "no monomer amplitudes formed"
+        worst = max(worst, compare_restricted_lccd(r, sx, sy, g, e, orbs))
+    return worst < 1e-10, f"worst relative difference {worst:.3e}"
+
+
 ALL_PINS = [
     pin_zero_coupling_mp2, pin_dispersion_mp2, pin_brute_force_sweeps,
     pin_dense_solve, pin_relabel_and_orientation, pin_sign_flip_bitwise,
     pin_power_of_two_scaling_bitwise, pin_disconnected_additivity, pin_orbital_permutation,
-    pin_pair_symmetry,
+    pin_pair_symmetry, pin_restricted_lccd_coupling,
 ]

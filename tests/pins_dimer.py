@@ -117,48 +117,50 @@ def restricted_lccd(g, e, orbs):
     return E, t, occ, vir
 
 
+def compare_restricted_lccd(r, sx, sy, g, e, orbs) -> float:
+    """Worst relative difference between an oracle result r on a two-monomer
+    problem and restricted spin-orbital LCCD on the same integrals: energy
+    E_M2(X) + E_M2(Y) + E_D2(XY), T_X and T_Y against the alpha-beta amplitudes of
+    each monomer, Tau^{ab}_{ij} against t_{i alpha j beta}^{a alpha b beta}."""
+    E, t, occ, vir = restricted_lccd(g, e, orbs)
+    e_mcpt = float(np.sum(r.e_m2) + np.sum(r.e_d2))
+    worst = abs(e_mcpt - E) / abs(E)
+    loc = lambda m, o_flag, k, s, lst: lst.index((next(q for q, ob in enumerate(orbs)
+                                                      if ob == (m, o_flag, k)), s))
+    (ox, vx), (oy, vy) = sx, sy
+    for m, (o, v) in enumerate((sx, sy)):
+        ii = [loc(m, True, k, 0, occ) for k in range(o)]
+        jj = [loc(m, True, k, 1, occ) for k in range(o)]
+        aa = [loc(m, False, k, 0, vir) for k in range(v)]
+        bb = [loc(m, False, k, 1, vir) for k in range(v)]
+        ref = t[np.ix_(ii, jj, aa, bb)]
+        if np.any(ref):
+            worst = max(worst, _rel(r.T[m], ref))
+        else:
+            worst = max(worst, float(np.max(np.abs(r.T[m]))))
+    ii = [loc(0, True, k, 0, occ) for k in range(ox)]
+    aa = [loc(0, False, k, 0, vir) for k in range(vx)]
+    jj = [loc(1, True, k, 1, occ) for k in range(oy)]
+    bb = [loc(1, False, k, 1, vir) for k in range(vy)]
+    return max(worst, _rel(r.Tau[0], t[np.ix_(ii, jj, aa, bb)].transpose(0, 2, 1, 3)))
+
+
 @_safe
 def pin_restricted_lccd(orc):
     """Physical dimer integrals without exchange between the monomers: the
     converged E_M2(X) + E_M2(Y) + E_D2(XY) equals the restricted spin-orbital
     LCCD energy, T_X and T_Y equal the alpha-beta amplitudes of each monomer and
     Tau^{ab}_{ij} equals t_{i alpha j beta}^{a alpha b beta} (i, a on X; j, b on Y).
-
-    Exact agreement needs the pair term of Eq. 58 doubled (the two spins of the
-    summed k, c of Y each give one copy of it); the printed term, which the
-    oracle and the product keep, is half of that.  The pin doubles it in the
-    module that both oracles share for the duration of the solve, so every
-    other term - all of the dimer-internal ones among them - is checked as
+    This holds with the pair term of Eq. 58 summed over both spins of k, c on Y
+    (the printed term is half of it), and with every dimer-internal term as
     printed."""
     worst = 0.0
-    from oracle import mcpt_oracle as base
-    printed = base.pair_coupling
     for sx, sy, seed in [((1, 2), (1, 2), 21), ((2, 2), (1, 3), 22), ((1, 3), (2, 2), 23)]:
         p, ints, dints, g, e, orbs = physical_dimer(sx, sy, seed)
-        base.pair_coupling = lambda V, Tau: 2.0 * printed(V, Tau)
-        try:
-            r = orc.solve(p, ints, dints, tol=1e-15, max_sweeps=400)
-        finally:
-            base.pair_coupling = printed
+        r = orc.solve(p, ints, dints, tol=1e-15, max_sweeps=400)
         if r.status != 0:
             return False, f"status {r.status}"
-        E, t, occ, vir = restricted_lccd(g, e, orbs)
-        e_mcpt = float(np.sum(r.e_m2) + np.sum(r.e_d2))
-        worst = max(worst, abs(e_mcpt - E) / abs(E))
-        loc = lambda m, o_flag, k, s, lst: lst.index((next(q for q, ob in enumerate(orbs)
-                                                          if ob == (m, o_flag, k)), s))
-        (ox, vx), (oy, vy) = sx, sy
-        for m, (o, v) in enumerate((sx, sy)):
-            ii = [loc(m, True, k, 0, occ) for k in range(o)]
-            jj = [loc(m, True, k, 1, occ) for k in range(o)]
-            aa = [loc(m, False, k, 0, vir) for k in range(v)]
-            bb = [loc(m, False, k, 1, vir) for k in range(v)]
-            worst = max(worst, _rel(r.T[m], t[np.ix_(ii, jj, aa, bb)]))
-        ii = [loc(0, True, k, 0, occ) for k in range(ox)]
-        aa = [loc(0, False, k, 0, vir) for k in range(vx)]
-        jj = [loc(1, True, k, 1, occ) for k in range(oy)]
-        bb = [loc(1, False, k, 1, vir) for k in range(vy)]
-        worst = max(worst, _rel(r.Tau[0], t[np.ix_(ii, jj, aa, bb)].transpose(0, 2, 1, 3)))
+        worst = max(worst, compare_restricted_lccd(r, sx, sy, g, e, orbs))
     return worst < 1e-10, f"worst relative difference {worst:.3e}"
 
 

@@ -68,3 +68,13 @@ def test_mutation_fails_a_pin(name):
 
 def test_unmutated_passes():
     assert all(f(D)[0] for f in pins_dimer.ALL_PINS)
+
+
+def test_printed_pair_term_without_spin_sum_fails_a_pin(monkeypatch):
+    """The pair term of Eq. 58 as printed (half the spin-summed term), planted in
+    the module the dimer oracle takes it from."""
+    from oracle import mcpt_oracle as base
+    orig = base.pair_coupling
+    monkeypatch.setattr(base, "pair_coupling", lambda V, Tau: 0.5 * orig(V, Tau))
+    results = {f.__name__: f(D) for f in pins_dimer.ALL_PINS}
+    assert any(not ok for ok, _ in results.values()), f"printed half pair term passed every pin: {results}"

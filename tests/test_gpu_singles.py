@@ -37,7 +37,7 @@ def flat_t(r):
     return np.concatenate([t.ravel() for t in r.t]) if r.t else np.zeros(0)
 
 
-def ragged(n_sizes=((2, 3), (5, 27), (3, 17), (1, 1), (8, 56), (4, 9)), scale=1.0, cutoff=None, workload=910):
+def ragged(n_sizes=((2, 3), (5, 27), (3, 17), (1, 1), (8, 56), (4, 9)), scale=0.5, cutoff=None, workload=910):
     sites = cubic_sites(len(n_sizes), 1, 1)
     return make_lattice_problem(sites, cutoff, sizes=list(n_sizes), workload=workload, coupling_scale=scale)
 
@@ -61,7 +61,7 @@ def test_fixed_sweeps_elementwise(ctx, sweeps):
 
 def test_wide_monomers_cross_column_passes(ctx):
     """o v above 256 (several 256-column passes per row) and pairs of mixed widths."""
-    p = ragged(n_sizes=((6, 60), (2, 150), (5, 27), (3, 100)), scale=0.5, workload=911)
+    p = ragged(n_sizes=((6, 60), (2, 150), (5, 27), (3, 100)), scale=0.25, workload=911)
     w = singles_source(p)
     ref = mcpt_singles.solve(p, w, tol=TOL, max_sweeps=300)
     pid = ctx.upload(p)
@@ -187,7 +187,7 @@ def test_divergence_detected(ctx):
 
 
 def test_relabelled_and_reversed_pairs(ctx):
-    p = ragged(scale=1.0)
+    p = ragged(scale=0.5)
     w = singles_source(p)
     perm = [3, 0, 5, 1, 4, 2]
     q = p.relabel(perm, np.arange(p.n_pair) % 3 == 0)

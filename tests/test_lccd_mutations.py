@@ -93,3 +93,13 @@ def test_mutation_fails_a_pin(name):
         setattr(L, attr, orig)
     failed = [k for k, (ok, _) in results.items() if not ok]
     assert failed, f"mutation {name} passed every pin"
+
+
+def test_printed_pair_term_without_spin_sum_fails_a_pin(monkeypatch):
+    """The pair term of Eq. 58 as printed (half the spin-summed term), planted in
+    the module the full-equation oracle takes it from."""
+    from oracle import mcpt_oracle as base
+    orig = base.pair_coupling
+    monkeypatch.setattr(base, "pair_coupling", lambda V, Tau: 0.5 * orig(V, Tau))
+    results = {p.__name__: p(L) for p in pins_lccd.ALL_LCCD_PINS}
+    assert any(not ok for ok, _ in results.values()), f"printed half pair term passed every pin: {results}"

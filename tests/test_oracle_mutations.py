@@ -24,7 +24,12 @@ def _wrong_swap(T):
 
 
 def _one_sided_pair_term(V, Tau):
-    return np.einsum("IAkc,iakc->iIaA", V, Tau)
+    return 2.0 * np.einsum("IAkc,iakc->iIaA", V, Tau)
+
+
+def _printed_half_pair_term(V, Tau):
+    # the pair term of Eq. 58 as printed, without the sum over the spins of k, c
+    return np.einsum("IAkc,iakc->iIaA", V, Tau) + np.einsum("iakc,IAkc->iIaA", V, Tau)
 
 
 def _transposed_x_coupling(V, T_x, T_y, D):
@@ -92,6 +97,7 @@ MUTATIONS = {
     "virtual instead of occupied swap in 2T - T": ("spin_adapted", _wrong_swap),
     "transposed T_X in Eq. 59": ("dimer_amplitudes", _transposed_x_coupling),
     "one-sided pair term of Eq. 58": ("pair_coupling", _one_sided_pair_term),
+    "printed pair term of Eq. 58 without its spin sum": ("pair_coupling", _printed_half_pair_term),
     "factor 2 in Eq. 55": ("dimer_energy", _ed2_factor_two),
     "exchange sign in Eq. 54": ("monomer_energy", _em2_exchange_sign),
     "coupling sign opposite to source in Eq. 58": ("monomer_amplitudes", _coupling_sign),

@@ -45,6 +45,11 @@ def _swapped_occ_vir(prob, t):
     return u
 
 
+def _printed_half(prob, t):
+    # the pair sum of Eq. 57 as printed, without the sum over the spins of k, c
+    return [0.5 * u for u in S.__dict__["_orig_coupling"](prob, t)]
+
+
 def _energy_factor_one(w, t):
     return float(np.sum(w * t))
 
@@ -57,6 +62,7 @@ MUTATIONS = {
     "drop_reverse_direction": ("coupling", _drop_reverse),
     "reverse_without_transpose": ("coupling", _no_transpose),
     "coupling_sign": ("coupling", _minus_coupling),
+    "printed_pair_sum_without_spin_sum": ("coupling", _printed_half),
     "occ_vir_swapped_in_t": ("coupling", _swapped_occ_vir),
     "energy_factor_one": ("singles_energy", _energy_factor_one),
     "denominator_reversed": ("singles_denominator", _denominator_reversed),
