@@ -327,11 +327,14 @@ typedef struct {
  * the same o <= 6 and v <= 64 with its n x n amplitudes within 160 KiB (o = 5,
  * v = 27 is 146 KB) and the problem at most 65,535 pairs.  The arrays are read
  * before the call returns; the packed copies (W_XY as vX vY rows padded to 16,
- * columns to 32: ~8 v^4 bytes per pair), Q_XY, the packed C_X and C_Y and two
- * np x np matrices per pair (Tau and its source) stay with the problem and
- * count against the budget.  The problem's last results are dropped.  mcpt_run
- * of an attached problem accepts only the FP64 form (precision MCPT_FP64);
- * results are reproducible to rounding (the ring terms add with atomics).
+ * columns to 32: ~8 v^4 bytes per pair), Q_XY, the packed C_X and C_Y, four
+ * np x np matrices per pair (Tau, the ladder-plus-monomer-ring source S and the
+ * two cross-ring products Y1, Y2) and one np x np matrix per monomer (2K - J of
+ * the monomer rings) stay with the problem and count against the budget.  The
+ * problem's last results are dropped.  mcpt_run of an attached problem accepts
+ * only the FP64 form (precision MCPT_FP64) and has no deterministic mode: its
+ * results are reproducible to rounding only (the pair kernel adds the G_X and
+ * G_Y contributions with FP64 atomics; the dimer terms themselves use none).
  * Errors: MCPT_ERR_INVALID (NULL array, memory, no intramonomer integrals,
  * sizes), MCPT_ERR_NONFINITE, MCPT_ERR_ADMISSION, MCPT_ERR_NOMEM,
  * MCPT_ERR_UNKNOWN_ID, MCPT_ERR_DEVICE. */

@@ -13,7 +13,8 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmcpt.so")
 ARCH = os.environ.get("MCPT_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["capi.hip", "serve.hip", "kernels_common.hip", "pair_fp64.hip", "pair_lowp.hip", "singles.hip", "lccd.hip"]
+SOURCES = ["capi.hip", "serve.hip", "kernels_common.hip", "pair_fp64.hip", "pair_lowp.hip", "singles.hip", "lccd.hip",
+           "host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -15,19 +15,11 @@
 
 #include "../../include/mcpt.h"
 #include "mcpt_internal.hpp"
+#include "host.hpp"
 #include "runtime.hpp"
 #include "singles.hpp"
 
 namespace mcpt {
-
-thread_local std::string g_err;
-
-mcpt_status fail(mcpt_status s, const std::string& msg) {
-    g_err = msg;
-    return s;
-}
-
-const std::string& last_error_text() { return g_err; }
 
 #define HIP_TRY(expr)                                                                          \
     do {                                                                                       \
@@ -248,55 +240,6 @@ double pair_flops(const Resident& r, bool couple) {
     return f;
 }
 
-mcpt_status validate_problem(const mcpt_problem* pb) {
-    if (!pb) return fail(MCPT_ERR_INVALID, "problem is NULL");
-    if (pb->n_mono < 1) return fail(MCPT_ERR_INVALID, "n_mono must be >= 1");
-    if (!pb->n_occ || !pb->n_vir || !pb->eps || !pb->k_intra)
-        return fail(MCPT_ERR_INVALID, "n_occ, n_vir, eps and k_intra must be non-NULL");
-    if (pb->n_pair < 0) return fail(MCPT_ERR_INVALID, "n_pair must be >= 0");
-    if (pb->n_pair > 0 && (!pb->pair || !pb->v_dimer))
-        return fail(MCPT_ERR_INVALID, "pair and v_dimer must be non-NULL when n_pair > 0");
-    if (pb->memory != MCPT_HOST && pb->memory != MCPT_DEVICE)
-        return fail(MCPT_ERR_INVALID, "memory must be MCPT_HOST or MCPT_DEVICE");
-    for (int x = 0; x < pb->n_mono; ++x) {
-        const int o = pb->n_occ[x], v = pb->n_vir[x];
-        if (o < 1 || v < 1) return fail(MCPT_ERR_INVALID, "monomer " + std::to_string(x) + ": o, v must be >= 1");
-        if ((int64_t)o * v > 4096)
-            return fail(MCPT_ERR_INVALID, "monomer " + std::to_string(x) + ": o*v > 4096 not supported");
-    }
-    std::unordered_set<uint64_t> seen;
-    seen.reserve((size_t)pb->n_pair * 2);
-    for (int64_t p = 0; p < pb->n_pair; ++p) {
-        const int x = pb->pair[2 * p], y = pb->pair[2 * p + 1];
-        if (x < 0 || y < 0 || x >= pb->n_mono || y >= pb->n_mono)
-            return fail(MCPT_ERR_INVALID, "pair " + std::to_string(p) + " out of range");
-        if (x == y) return fail(MCPT_ERR_INVALID, "pair " + std::to_string(p) + " has X == Y");
-        const uint64_t key = ((uint64_t)std::min(x, y) << 32) | (uint32_t)std::max(x, y);
-        if (!seen.insert(key).second)
-            return fail(MCPT_ERR_INVALID, "pair " + std::to_string(p) + " duplicates an earlier pair");
-    }
-    return MCPT_OK;
-}
-
-mcpt_status check_energies(const std::vector<double>& eps, const mcpt_problem* pb) {
-    int64_t off = 0;
-    for (int x = 0; x < pb->n_mono; ++x) {
-        const int o = pb->n_occ[x], v = pb->n_vir[x];
-        double omax = -INFINITY, vmin = INFINITY;
-        for (int k = 0; k < o + v; ++k) {
-            const double e = eps[off + k];
-            if (!std::isfinite(e)) return fail(MCPT_ERR_NONFINITE, "non-finite orbital energy of monomer " + std::to_string(x));
-            if (k < o) omax = std::max(omax, e);
-            else vmin = std::min(vmin, e);
-        }
-        if (!(omax < vmin))
-            return fail(MCPT_ERR_INVALID, "monomer " + std::to_string(x) +
-                                              ": max occupied energy >= min virtual energy (denominator >= 0)");
-        off += o + v;
-    }
-    return MCPT_OK;
-}
-
 // Upload one or more independent clusters as one resident problem: monomers
 // and pairs are concatenated cluster after cluster (pair indices shifted by the
 // cluster's first monomer), each monomer and pair carries its cluster id, and
@@ -307,7 +250,7 @@ mcpt_status upload_batch(mcpt_ctx* c, Exec& x, const mcpt_problem* pbs, int n_cl
     mcpt_status st;
     for (int q = 0; q < n_cl; ++q) {
         if ((st = validate_problem(&pbs[q])) != MCPT_OK) {
-            if (n_cl > 1) g_err = "cluster " + std::to_string(q) + ": " + g_err;
+            if (n_cl > 1) prefix_error("cluster " + std::to_string(q) + ": ");
             return st;
         }
     }
@@ -381,7 +324,7 @@ mcpt_status upload_batch(mcpt_ctx* c, Exec& x, const mcpt_problem* pbs, int n_cl
     r->v_elems = vo;
     {
         const std::vector<MonoDesc>& m = r->monos;
-        auto lds = [&m](const PairDesc& d) { return pair_fits_lds(m[d.x].n, m[d.y].np); };
+        auto lds = [&m](const PairDesc& d) { return pair_fits_lds(m[d.x].n, m[d.x].np, m[d.y].np); };
         // within each range: blocks of kPairBlock x kPairBlock monomers (lower, upper index), so
         // that the pairs an XCD works on at a time share few monomers' M and G blocks
         const int B = kPairBlock;
@@ -404,8 +347,8 @@ mcpt_status upload_batch(mcpt_ctx* c, Exec& x, const mcpt_problem* pbs, int n_cl
         if (pbs[q].memory == MCPT_HOST) std::memcpy(eps.data() + eps_cl[q], pbs[q].eps, bytes);
         else HIP_TRY(hipMemcpy(eps.data() + eps_cl[q], pbs[q].eps, bytes, hipMemcpyDeviceToHost));
         std::vector<double> one(eps.begin() + eps_cl[q], eps.begin() + eps_cl[q + 1]);
-        if ((st = check_energies(one, &pbs[q])) != MCPT_OK) {
-            if (n_cl > 1) g_err = "cluster " + std::to_string(q) + ": " + g_err;
+        if ((st = check_energies(one.data(), &pbs[q])) != MCPT_OK) {
+            if (n_cl > 1) prefix_error("cluster " + std::to_string(q) + ": ");
             return st;
         }
     }
@@ -521,38 +464,9 @@ mcpt_status upload_batch(mcpt_ctx* c, Exec& x, const mcpt_problem* pbs, int n_cl
 // allocates for these clusters; sizes only, so admission can price a request
 // before anything is allocated.  Every buffer is rounded up to 256 bytes.
 size_t footprint(const mcpt_problem* pbs, int n, int precision) {
-    int64_t n_mono = 0, n_pair = 0, dif = 0, raw = 0, mat = 0, v = 0, vlo = 0, mlo = 0;
-    const int kc = precision == MCPT_FP64 ? 0 : lowp_chunk(precision);
-    auto ld = [kc](int64_t m) { return (m + kc - 1) / kc * kc; };
-    for (int q = 0; q < n; ++q) {
-        const mcpt_problem& p = pbs[q];
-        for (int x = 0; x < p.n_mono; ++x) {
-            const int64_t nx = (int64_t)p.n_occ[x] * p.n_vir[x], np = (nx + kTile - 1) / kTile * kTile;
-            dif += np;
-            raw += nx * nx;
-            mat += np * np;
-            if (kc) mlo += np * ld(nx);
-        }
-        for (int64_t k = 0; k < p.n_pair; ++k) {
-            const int x = p.pair[2 * k], y = p.pair[2 * k + 1];
-            const int64_t nx = (int64_t)p.n_occ[x] * p.n_vir[x], ny = (int64_t)p.n_occ[y] * p.n_vir[y];
-            v += nx * ny;
-            if (kc) vlo += (nx + kTile - 1) / kTile * kTile * ld(ny) + (ny + kTile - 1) / kTile * kTile * ld(nx);
-        }
-        n_mono += p.n_mono;
-        n_pair += p.n_pair;
-    }
-    auto r = [](int64_t bytes) { return (size_t)((std::max<int64_t>(bytes, 1) + 255) / 256 * 256); };
-    size_t b = r(n_mono * (int64_t)sizeof(MonoDesc)) + r(std::max<int64_t>(n_pair, 1) * (int64_t)sizeof(PairDesc)) +
-               r(8 * dif) + r(8 * raw) + 5 * r(8 * mat) + r(8 * std::max<int64_t>(v, 1)) + 3 * r(8 * n_mono) +
-               r(8 * std::max<int64_t>(n_pair, 1)) + r((int64_t)n * (int64_t)sizeof(ClState)) +
-               r(8 * (int64_t)n * kMaxSweeps) + 2 * r(8 * (int64_t)(n + 1)) + r(4 * (int64_t)n);
-    if (kc) {
-        const int64_t es = precision == MCPT_BF16 ? 2 : 4;
-        b += r(es * vlo) + r(es * mlo) + r(8 * std::max<int64_t>(n_pair, 1)) + r(8 * n_mono) + 2 * r(8 * mat);
-        if (precision == MCPT_BF16) b += r(8 * mat);   // two FP32 G buffers
-    }
-    return b;
+    const LayoutSizes ls{(int64_t)sizeof(MonoDesc), (int64_t)sizeof(PairDesc), (int64_t)sizeof(ClState), kTile,
+                         kMaxSweeps, lowp_chunk(MCPT_FP32), lowp_chunk(MCPT_BF16)};
+    return footprint(pbs, n, precision, ls);
 }
 
 mcpt_status exec_init(mcpt_ctx* c, Exec& x) {
@@ -1593,7 +1507,7 @@ mcpt_status fd_stencil(mcpt_ctx* c, Exec& x, Resident* B, int32_t n_modes, const
         r.d2e = (-r.e[4] + 16.0 * r.e[3] - 30.0 * r.e[2] + 16.0 * r.e[1] - r.e[0]) / (12.0 * step * step);
         r.status = MCPT_OK;
     }
-    g_err.clear();
+    clear_error();
     return MCPT_OK;
 }
 
@@ -1981,7 +1895,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
     if (out) *out = sm;
     if (sm.status != MCPT_OK)
         return fail((mcpt_status)sm.status, "not converged after " + std::to_string(sm.sweeps) + " sweeps");
-    g_err.clear();
+    clear_error();
     return MCPT_OK;
 }
 
@@ -2027,7 +1941,7 @@ mcpt_status mcpt_create(int device, size_t hbm_budget_bytes, mcpt_ctx** out) {
         exec_free(c.get(), c->main);
         return st;
     }
-    g_err.clear();
+    clear_error();
     *out = c.release();
     return MCPT_OK;
 }
@@ -2043,7 +1957,7 @@ void mcpt_destroy(mcpt_ctx* c) {
     delete c;
 }
 
-const char* mcpt_last_error(void) { return g_err.c_str(); }
+const char* mcpt_last_error(void) { return last_error_text().c_str(); }
 
 mcpt_status mcpt_set_stream(mcpt_ctx* c, void* hip_stream) {
     if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
@@ -2251,30 +2165,12 @@ mcpt_status mcpt_tune_export(mcpt_ctx* c, char* buf, size_t cap, size_t* len) {
 
 mcpt_status mcpt_tune_import(mcpt_ctx* c, const char* text) {
     if (!c || !text) return fail(MCPT_ERR_INVALID, "ctx or text is NULL");
+    std::vector<int> shapes(3 * lowp_variants());
+    for (int k = 0; k < lowp_variants(); ++k)
+        lowp_variant_shape(k, &shapes[3 * k], &shapes[3 * k + 1], &shapes[3 * k + 2]);
     std::map<std::string, int> add;
-    const std::string t(text);
-    size_t pos = 0;
-    while (pos < t.size()) {
-        size_t e = t.find('\n', pos);
-        if (e == std::string::npos) e = t.size();
-        const std::string line = t.substr(pos, e - pos);
-        pos = e + 1;
-        if (line.empty()) continue;
-        char key[512];
-        int sb = 0, nw = 0, pd = 0;
-        if (line.size() >= sizeof(key) || std::sscanf(line.c_str(), "%511s %d %d %d", key, &sb, &nw, &pd) != 4)
-            return fail(MCPT_ERR_INVALID, "bad tuning line: " + line);
-        int v = -1;
-        for (int k = 0; k < lowp_variants(); ++k) {
-            int a = 0, b = 0, d = 0;
-            lowp_variant_shape(k, &a, &b, &d);
-            if (a == sb && b == nw && d == pd) v = k;
-        }
-        if (v < 0)
-            return fail(MCPT_ERR_INVALID, "no tile variant " + std::to_string(sb) + " x " + std::to_string(nw) +
-                                              " depth " + std::to_string(pd));
-        add[key] = v;
-    }
+    const mcpt_status st = parse_tune_table(text, shapes.data(), lowp_variants(), &add);
+    if (st != MCPT_OK) return st;
     std::lock_guard<std::mutex> g(c->mu);
     for (const auto& kv : add) c->tune[kv.first] = kv.second;
     return MCPT_OK;

@@ -153,7 +153,7 @@ void launch_pair_fp64(int lds_variant, PartOut po, const PairDesc* pairs, int64_
                       double* scratch, int64_t slot_elems, int grid, double* ed2, int couple,
                       const Ctrl* ctrl, const ClState* cl, hipStream_t s);
 int pair_fp64_blocks_per_cu(int lds_variant);
-bool pair_fits_lds(int nX, int npY);
+bool pair_fits_lds(int nX, int npX, int npY);
 
 // ---- reduced-precision pair phase (pair_lowp.hip); precision 1 = FP32, 2 = BF16 ----
 int lowp_chunk(int precision);   // k chunk: rows of low-precision operands are padded to it

@@ -52,6 +52,7 @@ constexpr int kThreadsG = 256;   // V from L2: four wavefronts, two workgroups p
 constexpr int kSB = 3;           // super-block edge in tiles
 constexpr int kXcds = 8;
 constexpr int kLdsV = 19712;     // LDS doubles for V (157,696 B): nX * (npY + 2) must fit
+constexpr int kLdsD = 640;       // LDS doubles for the energy differences of X and Y: npX + npY must fit
 
 template <int R, int C>
 struct Shape {
@@ -437,7 +438,7 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
                                  const double* __restrict__ V, const double* __restrict__ M,
                                  double* __restrict__ G, double* __restrict__ scratch, int64_t slot_elems,
                                  double* __restrict__ ed2, int couple, const ClState* __restrict__ cl,
-                                 PartOut po, double* sV, double* red) {
+                                 PartOut po, double* sV, double* sD, double* red) {
     constexpr int NW = NT / 64;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double* tau = scratch + (int64_t)blockIdx.x * slot_elems;
@@ -470,6 +471,8 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
                             if (r < p.nX && c < p.ldv) sV[r * p.ldv + c] = tmp[k][m];
                         }
                 }
+            // the energy differences of X's rows and Y's columns (zero in the padding) for the epilogue
+            for (int k = threadIdx.x; k < p.npX + p.npY; k += NT) sD[k] = k < p.npX ? p.dX[k] : p.dY[k - p.npX];
             __syncthreads();
         }
 
@@ -485,28 +488,48 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
             zero(acc);
             if (IN_LDS) tau_sb_lds(p, sV, r0, c0, lane, acc);
             else tau_sb_glb(p, r0, c0, lane, acc);
+            // Epilogue, one tile column at a time: its inputs are gathered before its stores to
+            // the Tau slot (a global store orders later global loads behind it), indices are
+            // clamped into the valid block and the padding is masked by selects, so the loads
+            // issue back to back with one wait instead of a branch and a round trip per element.
+            // dX and dY are read at the padded indices directly (zero beyond n; masked).
+            const double* dXs = IN_LDS ? sD : p.dX;
+            const double* dYs = IN_LDS ? sD + p.npX : p.dY;
+            double dxr[NR][4];
+#pragma unroll
+            for (int i = 0; i < NR; ++i)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) dxr[i][t] = dXs[(r0 + i) * 16 + acc_row(lane, t)];
 #pragma unroll
             for (int j = 0; j < NC; ++j) {
                 const int c = (c0 + j) * 16 + acc_col(lane);
-                const double dc = p.dY[c];
+                const int cc = min(c, p.nY - 1);
+                const double dyc = dYs[c];
+                double vv[NR][4], dsrc[NR][4];
+#pragma unroll
+                for (int i = 0; i < NR; ++i)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int rr = min((r0 + i) * 16 + acc_row(lane, t), p.nX - 1);
+                        vv[i][t] = IN_LDS ? sV[rr * p.ldv + c] : p.V[(int64_t)rr * p.nY + cc];
+                        if (DIMER) {   // rr = (ii,a), cc = (jj,b): the clamped element's indices
+                            const int ii = rr / po.v, a = rr - ii * po.v, jj = cc / po.v, b = cc - jj * po.v;
+                            const int r = (r0 + i) * 16 + acc_row(lane, t);
+                            dsrc[i][t] = Sp[(int64_t)r * p.npY + c] -
+                                         Y1p[(int64_t)(ii * po.v + b) * p.npY + jj * po.v + a] -
+                                         Y2p[(int64_t)(jj * po.v + a) * p.npY + ii * po.v + b];
+                        }
+                    }
 #pragma unroll
                 for (int i = 0; i < NR; ++i)
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         const int r = (r0 + i) * 16 + acc_row(lane, t);
-                        double tv = 0.0;
-                        if (r < p.nX && c < p.nY) {
-                            const double dinv = recip(p.dX[r] + dc);
-                            const double v = IN_LDS ? sV[r * p.ldv + c] : p.V[(int64_t)r * p.nY + c];
-                            double src = v;
-                            if (DIMER) {   // r = (i,a), c = (j,b)
-                                const int i = r / po.v, a = r - i * po.v, jj = c / po.v, b = c - jj * po.v;
-                                src += Sp[(int64_t)r * p.npY + c] - Y1p[(int64_t)(i * po.v + b) * p.npY + jj * po.v + a] -
-                                       Y2p[(int64_t)(jj * po.v + a) * p.npY + i * po.v + b];
-                            }
-                            tv = dinv * (src + acc[i][j][t]);
-                            epart += v * tv;
-                        }
+                        const bool ok = r < p.nX && c < p.nY;
+                        const double dinv = recip(dxr[i][t] + dyc);
+                        const double src = DIMER ? vv[i][t] + dsrc[i][t] : vv[i][t];
+                        const double tv = ok ? dinv * (src + acc[i][j][t]) : 0.0;
+                        epart += ok ? vv[i][t] * tv : 0.0;
                         if (couple) tau[(int64_t)r * p.npY + c] = tv;
                         if (DIMER) Tp[(int64_t)r * p.npY + c] = tv;
                     }
@@ -561,9 +584,10 @@ __global__ __launch_bounds__(kThreadsL) void pair_fp64_lds_kernel(
     const ClState* __restrict__ cl, PartOut po) {
     if (ctrl && ctrl->done) return;
     __shared__ __align__(16) double sV[kLdsV];
+    __shared__ double sD[kLdsD];
     __shared__ double red[kThreadsL / 64];
     pair_body<true, kThreadsL, DIMER>(pairs, n_pair, monos, dif, V, M, G, scratch, slot_elems, ed2, couple, cl, po, sV,
-                               red);
+                                      sD, red);
 }
 
 template <bool DIMER>
@@ -576,7 +600,7 @@ __global__ __launch_bounds__(kThreadsG, 2) void pair_fp64_glb_kernel(
     if (ctrl && ctrl->done) return;
     __shared__ double red[kThreadsG / 64];
     pair_body<false, kThreadsG, DIMER>(pairs, n_pair, monos, dif, V, M, G, scratch, slot_elems, ed2, couple, cl, po,
-                                nullptr, red);
+                                       nullptr, nullptr, red);
 }
 
 }  // namespace
@@ -590,7 +614,7 @@ int pair_fp64_blocks_per_cu(int lds_variant) {
     return n;
 }
 
-bool pair_fits_lds(int nX, int npY) { return (int64_t)nX * (npY + 2) <= kLdsV; }
+bool pair_fits_lds(int nX, int npX, int npY) { return (int64_t)nX * (npY + 2) <= kLdsV && npX + npY <= kLdsD; }
 
 void launch_pair_fp64(int lds_variant, PartOut po, const PairDesc* pairs, int64_t n_pair, const MonoDesc* monos,
                       const double* dif, const double* V, const double* M, double* G, double* scratch,

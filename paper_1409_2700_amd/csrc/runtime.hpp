@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/mcpt.h"
+#include "host.hpp"
 #include "lccd.hpp"
 #include "mcpt_internal.hpp"
 
@@ -161,6 +162,7 @@ struct Request {
     mcpt_problem prob{};                // points into the vectors above
     mcpt_options opts{};
     size_t footprint = 0;               // device bytes of the request alone
+    int size_class = 0;                 // log2 of its pair-phase flops per sweep (batch fusing)
     double t_submit = 0.0;              // steady-clock seconds
     mcpt_summary sum{};
     uint64_t batch = 0;                 // internal resident id of the batch once run
@@ -205,12 +207,10 @@ struct mcpt_ctx {
 
 namespace mcpt {
 
-// shared between the solver runtime and the serving scheduler
-mcpt_status fail(mcpt_status s, const std::string& msg);
-const std::string& last_error_text();
+// shared between the solver runtime and the serving scheduler (the host-only
+// helpers - errors, validation, batch formation - are in host.hpp)
 mcpt_status exec_init(mcpt_ctx* c, Exec& x);
 void exec_free(mcpt_ctx* c, Exec& x);
-mcpt_status validate_problem(const mcpt_problem* pb);
 mcpt_status validate_options(const mcpt_options* o);
 size_t footprint(const mcpt_problem* pbs, int n, int precision);
 mcpt_status upload_batch(mcpt_ctx* c, Exec& x, const mcpt_problem* pbs, int n_cl, bool internal, uint64_t* id);

@@ -29,24 +29,6 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-bool same_options(const mcpt_options& a, const mcpt_options& b) {
-    return a.tol == b.tol && a.max_sweeps == b.max_sweeps && a.precision == b.precision && a.polish == b.polish &&
-           a.check_every == b.check_every && a.inner_sweeps == b.inner_sweeps && a.graph == b.graph &&
-           !a.warm_t && !b.warm_t;
-}
-
-// log2 of the pair-phase flops of one sweep: requests within one class of the
-// batch head are fused, so a batch is not held back by a much larger member
-int size_class(const mcpt_problem& p) {
-    double f = 0.0;
-    for (int64_t k = 0; k < p.n_pair; ++k) {
-        const double nx = (double)p.n_occ[p.pair[2 * k]] * p.n_vir[p.pair[2 * k]];
-        const double ny = (double)p.n_occ[p.pair[2 * k + 1]] * p.n_vir[p.pair[2 * k + 1]];
-        f += 4.0 * nx * ny * (nx + ny);
-    }
-    return f > 1.0 ? (int)std::floor(std::log2(f)) : 0;
-}
-
 bool head_fits(mcpt_ctx* c, Server& S) {
     if (S.queue.empty()) return false;
     const Request* h = S.reqs[S.queue.front()].get();
@@ -62,28 +44,24 @@ void worker_loop(mcpt_ctx* c, int w) {
         S.cv.wait(lk, [&] { return S.stop || head_fits(c, S); });
         if (S.stop) break;
         // ---- form a batch: the head, then compatible queued requests that fit ----
+        std::vector<QueuedRequest> view;
+        view.reserve(S.queue.size());
+        for (uint64_t t : S.queue) {
+            const Request* r = S.reqs[t].get();
+            view.push_back({r->footprint, r->prob.n_pair, r->size_class, &r->opts});
+        }
+        const std::vector<size_t> take =
+            form_batch(view, c->budget - c->in_use - c->reserved, S.params.max_batch, S.params.max_batch_pairs);
         std::vector<Request*> group;
         size_t reserve = 0;
-        int64_t pairs = 0;
-        Request* head = S.reqs[S.queue.front()].get();
-        const int cls0 = size_class(head->prob);
-        for (auto it = S.queue.begin(); it != S.queue.end();) {
-            Request* r = S.reqs[*it].get();
-            const bool first = group.empty();
-            if (!first && ((int)group.size() >= S.params.max_batch || !same_options(r->opts, head->opts) ||
-                           std::abs(size_class(r->prob) - cls0) > 1 ||
-                           pairs + r->prob.n_pair > S.params.max_batch_pairs)) {
-                ++it;
-                continue;
-            }
-            if (!first && c->in_use + c->reserved + reserve + r->footprint > c->budget) break;
+        for (size_t i : take) {
+            Request* r = S.reqs[S.queue[i]].get();
             group.push_back(r);
             reserve += r->footprint;
-            pairs += r->prob.n_pair;
             r->state = 1;
-            it = S.queue.erase(it);
-            if (head->opts.warm_t) break;   // a warm start runs alone
         }
+        for (size_t k = take.size(); k-- > 0;) S.queue.erase(S.queue.begin() + (std::ptrdiff_t)take[k]);
+        Request* head = group.front();
         x.reserved = reserve;
         c->reserved += reserve;
         ++S.busy;
@@ -346,6 +324,7 @@ mcpt_status mcpt_submit(mcpt_ctx* c, const mcpt_problem* prob, const mcpt_option
         r->opts = *opts;
         r->opts.warm_t = opts->warm_t ? r->warm_t.data() : nullptr;
         r->footprint = footprint(&r->prob, 1, opts->precision);
+        r->size_class = size_class(r->prob);
         r->t_submit = now_s();
         Server& S = server_of(c);
         std::lock_guard<std::mutex> g(c->mu);

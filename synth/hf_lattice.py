@@ -303,22 +303,44 @@ def make_workload(name: str, coupling_scale: float = DEFAULT_COUPLING_SCALE, **k
     return p
 
 
-def make_cluster_batch(n_clusters: int = 64, *, workload: int = 4, min_mono: int = 27,
-                       max_mono: int = 512, cutoff: float = 2.0,
-                       coupling_scale: float = DEFAULT_COUPLING_SCALE, mixed_sizes: bool = True,
-                       dtype_v=np.float64, first: int = 0):
-    """Uneven cubic-lattice clusters: n_mono log-uniform in [min, max], each
-    monomer o5v27 or o8v56 with probability 1/2."""
+def cluster_batch_sizes(n_clusters: int = 64, *, workload: int = 4, min_mono: int = 27,
+                        max_mono: int = 512, first: int = 0) -> list:
+    """Monomer counts of the clusters make_cluster_batch draws (log-uniform)."""
     out = []
     for c in range(first, first + n_clusters):
         rng = _rng(workload, c, KIND_CLUSTER)
-        n = int(round(math.exp(rng.uniform(math.log(min_mono), math.log(max_mono)))))
-        p = make_lattice_problem(cluster_sites(n), cutoff, workload=workload, cluster=c,
+        out.append(int(round(math.exp(rng.uniform(math.log(min_mono), math.log(max_mono))))))
+    return out
+
+
+def make_cluster_batch(n_clusters: int = 64, *, workload: int = 4, min_mono: int = 27,
+                       max_mono: int = 512, cutoff: float = 2.0,
+                       coupling_scale: float = DEFAULT_COUPLING_SCALE, mixed_sizes: bool = True,
+                       dtype_v=np.float64, first: int = 0, only=None, workers: int = 1):
+    """Uneven cubic-lattice clusters: n_mono log-uniform in [min, max], each
+    monomer o5v27 or o8v56 with probability 1/2.  only: optional list of cluster
+    indices to make (the others are skipped).  workers > 1 draws clusters on
+    that many threads (every draw is keyed by cluster and site, so the values
+    do not depend on it; NumPy's generators release the GIL)."""
+    sizes = cluster_batch_sizes(n_clusters, workload=workload, min_mono=min_mono, max_mono=max_mono,
+                                first=first)
+    which = [c for c in range(first, first + n_clusters) if only is None or c in only]
+
+    def one(c):
+        p = make_lattice_problem(cluster_sites(sizes[c - first]), cutoff, workload=workload, cluster=c,
                                  coupling_scale=coupling_scale, mixed_sizes=mixed_sizes,
                                  dtype_v=dtype_v)
         p.meta["name"] = f"cluster-{c}"
-        out.append(p)
-    return out
+        return p
+
+    if workers <= 1:
+        return [one(c) for c in which]
+    from concurrent.futures import ThreadPoolExecutor
+    # largest clusters first so the pool drains evenly; results in cluster order
+    order = sorted(which, key=lambda c: -sizes[c - first])
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        made = dict(zip(order, ex.map(one, order)))
+    return [made[c] for c in which]
 
 
 def make_served_request(r: int, *, workload: int = 5, min_mono: int = 8, max_mono: int = 1000,
