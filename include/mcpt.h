@@ -186,6 +186,22 @@ mcpt_status mcpt_upload(mcpt_ctx *ctx, const mcpt_problem *prob, uint64_t *id);
  * MCPT_ERR_UNKNOWN_ID, MCPT_ERR_DEVICE. */
 mcpt_status mcpt_run(mcpt_ctx *ctx, uint64_t id, const mcpt_options *opts, mcpt_summary *out);
 
+/* For callers that cannot allocate device memory (code running under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mcpt_run of
+ * a resident problem in FP64 (eager sweeps; precision MCPT_FP64, deterministic
+ * 0 and graph 0, else MCPT_ERR_INVALID) that allocates nothing.  The Tau
+ * scratch of the pair kernels - one slot of the largest pair's padded
+ * np_X x np_Y doubles per persistent workgroup - comes from a fixed
+ * library-owned device array of MCPT_STATIC_SCRATCH_BYTES instead of the
+ * context's allocated scratch; the grid is limited to the slots that fit.  A
+ * problem whose largest slot alone exceeds it is rejected (MCPT_ERR_INVALID).
+ * Each GPU keeps its own copy of the array until the process ends; every call
+ * on one GPU uses that copy, so calls that overlap on a GPU (several contexts
+ * or threads) race.  Results, outputs and errors otherwise as mcpt_run (FP64
+ * atomics in the pair kernels: equal to mcpt_run to rounding, not bitwise). */
+#define MCPT_STATIC_SCRATCH_BYTES (64ull << 20)
+mcpt_status mcpt_run_static(mcpt_ctx *ctx, uint64_t id, const mcpt_options *opts, mcpt_summary *out);
+
 /* Batching form: upload n independent clusters (probs[0..n-1], e.g. clusters
  * of different sizes and orbital counts) as one resident problem.  A run then
  * sweeps all of them together - every pair phase is one persistent launch over

@@ -212,6 +212,8 @@ void drain_timing(Timing& t) {
 }
 
 mcpt_status ensure_scratch(mcpt_ctx* c, Exec& x, int64_t slot_elems) {
+    if (x.fixed_scratch)   // the caller sized the static scratch; nothing may be allocated here
+        return slot_elems <= x.scratch_slot ? MCPT_OK : fail(MCPT_ERR_INVALID, "Tau slot exceeds the static scratch");
     const int grid = std::max(c->grid_lds, c->grid_glb);
     if (x.d_scratch && x.scratch_slot >= slot_elems && x.scratch_slots >= grid) return MCPT_OK;
     if (x.d_scratch) {
@@ -592,10 +594,12 @@ void pair_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int couple, const 
         p0.tau_out = p1.tau_out = R->d_Tau;
         p0.mat_stride = p1.mat_stride = R->dimer_mat;
     }
+    const int g_lds = x.grid_cap > 0 ? std::min(c->grid_lds, x.grid_cap) : c->grid_lds;
+    const int g_glb = x.grid_cap > 0 ? std::min(c->grid_glb, x.grid_cap) : c->grid_glb;
     launch_pair_fp64(1, p0, R->d_pairs, R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G, x.d_scratch,
-                     x.scratch_slot, c->grid_lds, R->d_ed2, couple, ctrl, cl, x.stream);
+                     x.scratch_slot, g_lds, R->d_ed2, couple, ctrl, cl, x.stream);
     launch_pair_fp64(0, p1, R->d_pairs + R->n_lds, R->n_pair - R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G,
-                     x.d_scratch, x.scratch_slot, c->grid_glb, R->d_ed2, couple, ctrl, cl, x.stream);
+                     x.d_scratch, x.scratch_slot, g_glb, R->d_ed2, couple, ctrl, cl, x.stream);
     if (det) launch_reduce_parts(R->d_monos, R->n_mono, R->d_csr_off, R->d_csr, R->d_part, G, R->d_cl, ctrl, x.stream);
 }
 
@@ -1903,7 +1907,36 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
 
 using namespace mcpt;
 
+// Tau scratch of mcpt_run_static, for callers that cannot allocate device memory:
+// one slot of the largest pair's padded npX x npY Tau per persistent workgroup of
+// the FP64 pair kernels.  Each GPU the library runs on holds its own copy for the
+// life of the process.  In host code `scratch` names a host-side stand-in, never
+// the device array: kernels receive the address hipGetSymbolAddress returns for
+// the current device (static_scratch_of).  Every mcpt_run_static on one GPU uses
+// that GPU's copy, so calls that overlap on a GPU race; the pair kernels write
+// each Tau slot in full before reading it, so no clearing is needed.
+static __device__ __align__(256) double scratch[MCPT_STATIC_SCRATCH_BYTES / sizeof(double)];
+
 namespace {
+
+std::mutex g_static_mu;
+std::map<int, double*> g_static_ptr;   // device -> address of its copy of scratch (g_static_mu)
+
+// The device address of this device's scratch array; the device must be current.
+mcpt_status static_scratch_of(int device, double** out) {
+    std::lock_guard<std::mutex> g(g_static_mu);
+    auto it = g_static_ptr.find(device);
+    if (it == g_static_ptr.end()) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MCPT_ERR_DEVICE, std::string("hipGetSymbolAddress of the static scratch: ") +
+                                             hipGetErrorString(e));
+        it = g_static_ptr.emplace(device, static_cast<double*>(ptr)).first;
+    }
+    *out = it->second;
+    return MCPT_OK;
+}
 
 // A caller-visible resident problem (served batches are reached through their tickets).
 Resident* find_resident(mcpt_ctx* c, uint64_t id) {
@@ -1938,6 +1971,10 @@ mcpt_status mcpt_create(int device, size_t hbm_budget_bytes, mcpt_ctx** out) {
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
     mcpt_status st = exec_init(c.get(), c->main);
     if (st != MCPT_OK) {
+        exec_free(c.get(), c->main);
+        return st;
+    }
+    if ((st = static_scratch_of(device, &c->static_scratch)) != MCPT_OK) {
         exec_free(c.get(), c->main);
         return st;
     }
@@ -2017,6 +2054,40 @@ mcpt_status mcpt_run(mcpt_ctx* c, uint64_t id, const mcpt_options* opts, mcpt_su
     if (!R) return unknown(id);
     try {
         return run(c, c->main, R, opts, out);
+    } catch (const std::exception& e) {
+        return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
+    }
+}
+
+mcpt_status mcpt_run_static(mcpt_ctx* c, uint64_t id, const mcpt_options* opts, mcpt_summary* out) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    mcpt_status st = validate_options(opts);
+    if (st != MCPT_OK) return st;
+    if (opts->precision != MCPT_FP64 || opts->deterministic || opts->graph)
+        return fail(MCPT_ERR_INVALID, "mcpt_run_static runs the FP64 eager solve only (precision FP64, "
+                                      "deterministic 0, graph 0)");
+    Resident* R = find_resident(c, id);
+    if (!R) return unknown(id);
+    const int64_t slot_bytes = R->max_slot * (int64_t)sizeof(double);
+    const int64_t slots = (int64_t)MCPT_STATIC_SCRATCH_BYTES / std::max<int64_t>(slot_bytes, 1);
+    if (slots < 1)
+        return fail(MCPT_ERR_INVALID, "the largest pair's Tau slot (" + std::to_string(slot_bytes) +
+                                          " bytes) exceeds the static scratch of " +
+                                          std::to_string((long long)MCPT_STATIC_SCRATCH_BYTES) + " bytes");
+    // the context's stream and control word, with the static array as the Tau scratch
+    Exec y;
+    y.stream = c->main.stream;
+    y.d_ctrl = c->main.d_ctrl;
+    y.h_ctrl = c->main.h_ctrl;
+    y.d_flag = c->main.d_flag;
+    y.h_flag = c->main.h_flag;
+    y.d_scratch = c->static_scratch;
+    y.scratch_slot = R->max_slot;
+    y.scratch_slots = (int)std::min<int64_t>(slots, std::max(c->grid_lds, c->grid_glb));
+    y.fixed_scratch = true;
+    y.grid_cap = y.scratch_slots;
+    try {
+        return run(c, y, R, opts, out);
     } catch (const std::exception& e) {
         return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
     }

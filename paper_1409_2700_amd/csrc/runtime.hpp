@@ -145,6 +145,8 @@ struct Exec {
     double* d_scratch = nullptr;        // FP64 Tau, one slot per workgroup
     int64_t scratch_slot = 0;
     int scratch_slots = 0;
+    bool fixed_scratch = false;         // d_scratch is the library's static array: never reallocated
+    int grid_cap = 0;                   // > 0: FP64 pair-kernel grids limited to the slots that fit
     void* d_scratch_lo = nullptr;       // reduced-precision Tau and Tau^T
     size_t scratch_lo_bytes = 0;
     int grid_lo = 0, grid_lo_lds = 0;   // persistent grids of the reduced-precision kernels
@@ -202,6 +204,7 @@ struct mcpt_ctx {
     int grid_lds = 0, grid_glb = 0;     // persistent grids of the two FP64 pair-kernel variants
     mcpt::Exec main;                    // the caller's stream (mcpt_run, mcpt_energy, ...)
     std::map<std::string, int> tune;    // autotuned lowp variant per "precision/shape key" (mu)
+    double* static_scratch = nullptr;   // this device's copy of the static Tau scratch (mcpt_run_static)
     std::unique_ptr<mcpt::Server> server;
 };
 

@@ -41,6 +41,7 @@ EXPORTS = [
     "mcpt_serve_config", "mcpt_submit", "mcpt_poll", "mcpt_wait", "mcpt_serve_stats",
     "mcpt_autotune", "mcpt_tune_export", "mcpt_tune_import", "mcpt_singles", "mcpt_singles_result",
     "mcpt_lccd_attach", "mcpt_upload_scaled", "mcpt_fd_stencil", "mcpt_dimer_attach",
+    "mcpt_run_static",
 ]
 
 
@@ -154,6 +155,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.mcpt_set_stream.argtypes = [P, P]
     lib.mcpt_upload.argtypes = [P, C.POINTER(mcpt_problem), C.POINTER(C.c_uint64)]
     lib.mcpt_run.argtypes = [P, C.c_uint64, C.POINTER(mcpt_options), C.POINTER(mcpt_summary)]
+    lib.mcpt_run_static.argtypes = [P, C.c_uint64, C.POINTER(mcpt_options), C.POINTER(mcpt_summary)]
     lib.mcpt_solve.argtypes = [P, C.POINTER(mcpt_problem), C.POINTER(mcpt_options),
                                C.POINTER(C.c_uint64), C.POINTER(mcpt_summary)]
     lib.mcpt_energy.argtypes = [P, C.c_uint64, P, P, P, P]
@@ -323,6 +325,17 @@ class Context:
         o = make_options(**opts)
         s = mcpt_summary()
         st = lib().mcpt_run(self.h, pid, C.byref(o), C.byref(s))
+        if raise_on_error:
+            _check(st)
+        d = s.as_dict()
+        d["return"] = st
+        return d
+
+    def run_static(self, pid: int, raise_on_error: bool = True, **opts) -> dict:
+        """mcpt_run_static: the FP64 eager solve with the library's fixed Tau scratch."""
+        o = make_options(**opts)
+        s = mcpt_summary()
+        st = lib().mcpt_run_static(self.h, pid, C.byref(o), C.byref(s))
         if raise_on_error:
             _check(st)
         d = s.as_dict()
