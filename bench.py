@@ -211,91 +211,131 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
 
 
-def serving(base, n_req, loads, workers, max_batch, tol):
-    """Served stream: requests carved from the resident crystal (sizes
-    log-uniform in [8, N], one monomer displaced), first solved alone one at a
-    time on the plain FP64 path (upload + solve), then all submitted at once (a
-    burst: its makespan measures the server's capacity), then with Poisson
-    arrivals at the given fractions of that measured capacity."""
+def _served_pass(ctx, stream, n_req, arrivals, max_inflight, tol, alone_e):
+    """Submit requests 0..n_req-1 (at the given arrival times, or as fast as the
+    in-flight limit lets them: closed loop), collect them on a polling thread, and
+    return latencies (the library's, from submission to result), completion and
+    submission times, statuses and the relative difference from the alone energy."""
     import threading
+    cv = threading.Condition()
+    outstanding = {}
+    lat, err, status = [None] * n_req, [None] * n_req, [None] * n_req
+    done_t, sub_t = [None] * n_req, [None] * n_req
+    state = {"done": 0}
+
+    def poller():
+        while True:
+            with cv:
+                if state["done"] == n_req:
+                    return
+                items = list(outstanding.items())
+            progressed = False
+            for t, r in items:
+                s = ctx.poll(t)
+                if s is None:
+                    continue
+                done_t[r] = time.perf_counter()
+                lat[r], status[r] = s["seconds"], s["status"]
+                err[r] = abs(s["e_total"] - alone_e[r]) / abs(alone_e[r])
+                ctx.release(t)
+                with cv:
+                    del outstanding[t]
+                    state["done"] += 1
+                    cv.notify_all()
+                progressed = True
+            if not progressed:
+                time.sleep(0.0005)
+
+    th = threading.Thread(target=poller)
+    th.start()
+    start = time.perf_counter()
+    for r in range(n_req):
+        if arrivals is not None:
+            delay = start + arrivals[r] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+        with cv:
+            cv.wait_for(lambda: len(outstanding) < max_inflight)
+        sub_t[r] = time.perf_counter() - start
+        with stream.lend(r) as p:
+            t = ctx.submit(p, tol=tol)
+        with cv:
+            outstanding[t] = r
+    th.join()
+    return start, lat, err, status, done_t, sub_t
+
+
+def serving(base, n_req, loads, workers, max_batch, tol, max_inflight=32):
+    """Served stream (synth.ServedStream: requests cut from the resident crystal,
+    sizes log-uniform in [8, N], one monomer displaced), first solved alone one at
+    a time on the plain FP64 path (upload + solve), then submitted in a closed
+    loop with at most max_inflight requests in flight (capacity: requests over
+    the makespan), then with Poisson arrivals at the given fractions of that
+    measured capacity.  Requests are lent as views of the relabelled crystal, so
+    host memory holds only the in-flight copies the library makes at submission."""
     import numpy as np
     import paper_1409_2700_amd as mc
-    from synth import carve_served_request, SEED_ROOT
+    from synth import ServedStream, SEED_ROOT
 
     t0 = time.time()
-    reqs = [carve_served_request(base, r) for r in range(n_req)]
-    sizes = [p.n_mono for p in reqs]
+    stream = ServedStream(base)
+    draws = [stream.draw(r) for r in range(n_req)]
+    sizes = [d[0] for d in draws]
+    pairs = [int(stream.pairs_below[n]) for n in sizes]
     log(f"[serve] {n_req} requests, monomers {min(sizes)}..{max(sizes)} (mean {np.mean(sizes):.0f}), "
-        f"pairs mean {np.mean([p.n_pair for p in reqs]):.0f}, made in {time.time() - t0:.1f}s")
+        f"pairs mean {np.mean(pairs):.0f}, stream prepared in {time.time() - t0:.1f}s")
     alone = []
     with mc.Context(0) as ctx:
-        pid, _ = ctx.solve(reqs[0], tol=tol)   # untimed warm-up
+        with stream.lend(0) as p:   # untimed warm-up
+            pid, _ = ctx.solve(p, tol=tol)
         ctx.release(pid)
-        for p in reqs:
-            t1 = time.perf_counter()
-            pid, s = ctx.solve(p, tol=tol)
-            alone.append((time.perf_counter() - t1, s["e_total"], s["sweeps"]))
+        for r in range(n_req):
+            with stream.lend(r) as p:
+                t1 = time.perf_counter()
+                pid, s = ctx.solve(p, tol=tol)
+                alone.append((time.perf_counter() - t1, s["e_total"], s["sweeps"]))
             ctx.release(pid)
     alone_lat = [a[0] for a in alone]
+    alone_e = [a[1] for a in alone]
     mean_alone = float(np.mean(alone_lat))
     out = {
         "requests": n_req, "monomers": {"min": int(min(sizes)), "mean": float(np.mean(sizes)),
                                          "max": int(max(sizes))},
-        "workload": f"carved from {base.n_mono}-monomer crystal, sizes log-uniform [8, {base.n_mono}], "
-                    f"one monomer displaced +-0.01 A",
+        "pairs": {"mean": float(np.mean(pairs)), "max": int(max(pairs))},
+        "workload": f"cut from the {base.n_mono}-monomer crystal: the n monomers nearest its centre, n "
+                    f"log-uniform in [8, {base.n_mono}], every pair among them, one monomer displaced +-0.01 A",
         "alone": {"p50_s": pct(alone_lat, 50), "p99_s": pct(alone_lat, 99), "mean_s": mean_alone,
-                  "solves_per_s": 1.0 / mean_alone, "path": "mcpt_solve, one at a time (upload + FP64 solve)"},
+                  "solves_per_s": 1.0 / mean_alone, "samples": n_req,
+                  "path": "mcpt_solve, one at a time (upload + FP64 solve)"},
         "workers": workers, "max_batch": max_batch, "loads": {},
     }
     log(f"[serve] alone: mean {mean_alone * 1e3:.1f} ms, p50 {pct(alone_lat, 50) * 1e3:.1f} ms")
     capacity = None
-    for load in ["burst"] + [x for x in loads if x != "burst"]:
-        rng = np.random.default_rng([SEED_ROOT, 5, 0 if load == "burst" else int(round(load * 1000))])
-        if load == "burst":
-            arrivals = np.zeros(n_req)
+    for load in ["capacity"] + [x for x in loads if x != "burst"]:
+        if load == "capacity":
+            arrivals, cap = None, max_inflight
         else:
-            arrivals = np.cumsum(rng.exponential(1.0 / (load * capacity), n_req))
-        lat, err, worst = [], [], []
+            rng = np.random.default_rng([SEED_ROOT, 5, int(round(load * 1000))])
+            arrivals, cap = np.cumsum(rng.exponential(1.0 / (load * capacity), n_req)), 2 * max_inflight
         with mc.Context(0) as ctx:
             ctx.serve_config(workers=workers, max_batch=max_batch)
-            tickets = [None] * n_req
-            ready = threading.Semaphore(0)
-            done_t = []
-
-            def waiter():
-                for k in range(n_req):
-                    ready.acquire()
-                    s = ctx.wait(tickets[k], 600000)
-                    done_t.append(time.perf_counter())
-                    lat.append(s["seconds"])
-                    worst.append(s["status"])
-                    err.append(abs(s["e_total"] - alone[k][1]) / abs(alone[k][1]))
-                    ctx.release(tickets[k])
-
-            th = threading.Thread(target=waiter)
-            th.start()
-            start = time.perf_counter()
-            for k in range(n_req):
-                delay = start + arrivals[k] - time.perf_counter()
-                if delay > 0:
-                    time.sleep(delay)
-                tickets[k] = ctx.submit(reqs[k], tol=tol)
-                ready.release()
-            th.join()
+            start, lat, err, status, done_t, sub_t = _served_pass(ctx, stream, n_req, arrivals, cap, tol, alone_e)
             st = ctx.serve_stats()
-        wall = max(done_t) - start
-        key = load if load == "burst" else f"{load:.2f}"
-        if load == "burst":
-            capacity = n_req / wall
+        makespan = max(done_t) - start
+        key = load if load == "capacity" else f"{load:.2f}"
+        entry = {"completed_solves_per_s": n_req / makespan, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99),
+                 "mean_s": float(np.mean(lat)), "batches": st["batches"], "samples": n_req,
+                 "all_ok": all(w == 0 for w in status), "max_rel_err_vs_alone": float(max(err))}
+        if load == "capacity":
+            capacity = n_req / makespan
             out["capacity_solves_per_s"] = capacity
             out["capacity_vs_alone"] = capacity * mean_alone
-        out["loads"][key] = {
-            "offered_solves_per_s": None if load == "burst" else load * capacity,
-            "completed_solves_per_s": n_req / wall, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99),
-            "mean_s": float(np.mean(lat)), "batches": st["batches"], "samples": len(lat),
-            "all_ok": all(w == 0 for w in worst), "max_rel_err_vs_alone": float(max(err)),
-        }
-        log(f"[serve] load {key}: {n_req / wall:.2f} solves/s, p50 {pct(lat, 50) * 1e3:.1f} ms, "
+            entry["max_in_flight"] = cap
+        else:
+            late = [max(0.0, sub_t[r] - arrivals[r]) for r in range(n_req)]
+            entry.update({"offered_solves_per_s": load * capacity, "submission_delay_p99_s": pct(late, 99)})
+        out["loads"][key] = entry
+        log(f"[serve] {key}: {n_req / makespan:.2f} solves/s, p50 {pct(lat, 50) * 1e3:.1f} ms, "
             f"p99 {pct(lat, 99) * 1e3:.1f} ms, {st['batches']} batches, max rel err {max(err):.1e}")
     return out
 
@@ -790,7 +830,7 @@ def main():
     ctx.close()
     served = None
     if args.serve_requests > 0:
-        served = serving(prob, args.serve_requests, [0.5, 0.8, "burst"], args.serve_workers, args.serve_batch,
+        served = serving(prob, args.serve_requests, [0.5, 0.8], args.serve_workers, args.serve_batch,
                          args.tol)
 
     h = results[args.headline]

@@ -23,8 +23,10 @@ builds the lattice and the cutoff pair list.
 """
 from __future__ import annotations
 
+import contextlib
 import dataclasses
 import math
+import threading
 
 import numpy as np
 
@@ -359,6 +361,106 @@ def make_served_request(r: int, *, workload: int = 5, min_mono: int = 8, max_mon
                              displacement=(mono, axis, sign * step_angstrom))
     p.meta["name"] = f"request-{r}"
     return p
+
+
+class ServedStream:
+    """The served stream cut from one resident crystal `base`: request r is the
+    n monomers nearest the crystal's centre (n log-uniform in [min_mono,
+    max_mono]; distance ties by index), every pair of `base` between them with
+    its block, and one of them displaced by +-step along a seeded axis (blocks of
+    its pairs rescaled by (R0 / R)^3, pair list unchanged) - the finite-
+    displacement geometries of the paper's frequency workflow.
+
+    The crystal is relabelled once by distance from its centre, with its pairs
+    ordered by their larger new index, so the monomers and pairs of every request
+    are prefixes of the relabelled arrays: making a request is one slice copy of
+    its blocks plus the rescaled blocks of the displaced monomer."""
+
+    def __init__(self, base: Problem, *, workload: int = 5, min_mono: int = 8, max_mono: int | None = None,
+                 step_angstrom: float = 0.01):
+        self.workload, self.min_mono, self.step = workload, min_mono, step_angstrom
+        N = base.n_mono
+        self.max_mono = N if max_mono is None else min(max_mono, N)
+        sites = np.asarray(base.sites, dtype=np.int64)
+        d2 = ((sites - sites.mean(axis=0)) ** 2).sum(axis=1)
+        order = np.lexsort((np.arange(N), d2))            # new index -> old index
+        inv = np.empty(N, dtype=np.int64)
+        inv[order] = np.arange(N)
+        self.n_occ, self.n_vir = base.n_occ[order].copy(), base.n_vir[order].copy()
+        self.sites = sites[order]
+        self.eps = np.concatenate([base.eps[base.eps_off[x]:base.eps_off[x + 1]] for x in order])
+        self.k = np.concatenate([base.k[base.k_off[x]:base.k_off[x + 1]] for x in order])
+        self.eoff = np.concatenate([[0], np.cumsum(self.n_occ.astype(np.int64) + self.n_vir)])
+        nxv = self.n_occ.astype(np.int64) * self.n_vir
+        self.koff = np.concatenate([[0], np.cumsum(nxv * nxv)])
+        px, py = inv[base.pairs[:, 0]], inv[base.pairs[:, 1]]
+        hi = np.maximum(px, py)
+        porder = np.lexsort((np.minimum(px, py), hi))
+        self.pairs = np.stack([px[porder], py[porder]], axis=1).astype(np.int32)
+        self.v = np.concatenate([base.v[base.v_off[p]:base.v_off[p + 1]] for p in porder])
+        psz = nxv[self.pairs[:, 0]] * nxv[self.pairs[:, 1]]
+        self.voff = np.concatenate([[0], np.cumsum(psz)])
+        self.pairs_below = np.searchsorted(hi[porder], np.arange(N + 1), side="left")   # pairs among the first n
+        self.meta = dict(base.meta)
+        self._lock = threading.Lock()
+
+    def draw(self, r: int):
+        """(n, displaced monomer, axis, signed shift) of request r."""
+        rng = _rng(self.workload, r, KIND_STREAM)
+        n = int(round(math.exp(rng.uniform(math.log(self.min_mono), math.log(self.max_mono)))))
+        n = max(1, min(n, self.max_mono))
+        mono = int(rng.integers(0, n))
+        axis = int(rng.integers(0, 3))
+        sign = 1.0 if rng.random() < 0.5 else -1.0
+        return n, mono, axis, sign * self.step
+
+    def _scales(self, n, mono, axis, shift):
+        """(pair index, factor) of the displaced monomer's pairs among the first n monomers."""
+        P = int(self.pairs_below[n])
+        pairs = self.pairs[:P]
+        pos = self.sites[:n].astype(np.float64) * SPACING_A
+        moved = pos[mono].copy()
+        moved[axis] += shift
+        out = []
+        for p in np.flatnonzero((pairs[:, 0] == mono) | (pairs[:, 1] == mono)):
+            x, y = int(pairs[p, 0]), int(pairs[p, 1])
+            other = pos[y] if x == mono else pos[x]
+            out.append((int(p), (float(np.linalg.norm(pos[mono] - other)) /
+                                 float(np.linalg.norm(moved - other))) ** 3))
+        return P, out
+
+    def _problem(self, r, n, P, v, shift_info):
+        meta = dict(self.meta)
+        meta.update(name=f"served-{r}", displacement=shift_info, carved_from=len(self.n_occ))
+        return Problem(self.n_occ[:n], self.n_vir[:n], self.eps[:self.eoff[n]], self.k[:self.koff[n]],
+                       self.pairs[:P], v, self.sites[:n], meta)
+
+    def request(self, r: int) -> Problem:
+        """Request r as a problem of its own (its blocks copied)."""
+        n, mono, axis, shift = self.draw(r)
+        P, scales = self._scales(n, mono, axis, shift)
+        v = self.v[:self.voff[P]].copy()
+        for p, f in scales:
+            v[self.voff[p]:self.voff[p + 1]] *= f
+        return self._problem(r, n, P, v, (mono, axis, shift))
+
+    @contextlib.contextmanager
+    def lend(self, r: int):
+        """Request r as views of the relabelled crystal, for a caller that copies
+        it (an upload or submission) before the block ends: the displaced
+        monomer's blocks are scaled in place and restored afterwards, one
+        request at a time."""
+        n, mono, axis, shift = self.draw(r)
+        P, scales = self._scales(n, mono, axis, shift)
+        with self._lock:
+            saved = [(p, self.v[self.voff[p]:self.voff[p + 1]].copy()) for p, _ in scales]
+            for p, f in scales:
+                self.v[self.voff[p]:self.voff[p + 1]] *= f
+            try:
+                yield self._problem(r, n, P, self.v[:self.voff[P]], (mono, axis, shift))
+            finally:
+                for p, blk in saved:
+                    self.v[self.voff[p]:self.voff[p + 1]] = blk
 
 
 def carve_served_request(base: Problem, r: int, *, workload: int = 5, min_mono: int = 8,

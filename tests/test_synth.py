@@ -58,3 +58,59 @@ def test_dimer_integrals_seeded_and_symmetric():
     for c in (db.cx_of(1), db.cy_of(1)):             # (i1 i|b b1), (j1 j|a a1)
         assert np.allclose(c, c.transpose(1, 0, 2, 3)) and np.allclose(c, c.transpose(0, 1, 3, 2))
     assert not np.allclose(db.w_of(0), db.w_of(1))
+
+
+def _by_sites(p):
+    """Monomer inputs and pair blocks keyed by lattice sites (orientation-free)."""
+    mono = {tuple(int(c) for c in p.sites[x]): (p.eps_of(x), p.k_of(x)) for x in range(p.n_mono)}
+    pairs = {}
+    for q, (x, y) in enumerate(p.pairs):
+        sx, sy = tuple(int(c) for c in p.sites[x]), tuple(int(c) for c in p.sites[y])
+        blk = p.v_of(q)
+        if sx > sy:
+            sx, sy, blk = sy, sx, blk.transpose(2, 3, 0, 1)
+        pairs[(sx, sy)] = blk
+    return mono, pairs
+
+
+def test_served_stream_request_equals_a_displaced_lattice_of_its_sites():
+    """A request of the prefix-relabelled stream is the crystal's own inputs on the
+    n monomers nearest the centre, with the displaced monomer's blocks rescaled
+    exactly as a from-scratch displaced lattice of those sites draws them."""
+    from synth import ServedStream
+    base = make_workload("hf-5x5x5-c2")
+    w = WORKLOADS["hf-5x5x5-c2"]
+    st = ServedStream(base)
+    sites = np.asarray(base.sites)
+    d2 = ((sites - sites.mean(axis=0)) ** 2).sum(axis=1)
+    for r in (0, 5, 17):
+        p = st.request(r)
+        n, mono, axis, shift = st.draw(r)
+        assert p.n_mono == n
+        nearest = {tuple(int(c) for c in sites[x]) for x in np.lexsort((np.arange(len(sites)), d2))[:n]}
+        assert {tuple(int(c) for c in s) for s in p.sites} == nearest
+        # the generator keys a pair's draw by its sites in lexicographic order, as the crystal lists them
+        lex = np.lexsort(np.asarray(p.sites)[:, ::-1].T)
+        pos_of = np.empty(n, dtype=np.int64)
+        pos_of[lex] = np.arange(n)
+        ref = make_lattice_problem(np.asarray(p.sites)[lex], w["cutoff"], workload=w["workload"],
+                                   displacement=(int(pos_of[mono]), axis, shift))
+        (ma, pa), (mb, pb) = _by_sites(p), _by_sites(ref)
+        assert ma.keys() == mb.keys() and pa.keys() == pb.keys()
+        for key in ma:
+            assert np.array_equal(ma[key][0][0], mb[key][0][0]) and np.array_equal(ma[key][1], mb[key][1])
+        for key in pa:
+            assert np.allclose(pa[key], pb[key], rtol=1e-14, atol=0.0), key
+
+
+def test_served_stream_lend_equals_request_and_restores():
+    from synth import ServedStream
+    base = make_workload("hf-5x5x5-c2")
+    st = ServedStream(base)
+    before = st.v.copy()
+    for r in (2, 9):
+        ref = st.request(r)
+        with st.lend(r) as p:
+            for f in ("n_occ", "n_vir", "eps", "k", "pairs", "v"):
+                assert np.array_equal(getattr(p, f), getattr(ref, f)), f
+        assert np.array_equal(st.v, before)
