@@ -660,17 +660,21 @@ def lccd_mode(ctx, prob, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: 
 
 
 DIMER_WORKLOAD = "hf-10x10x10-c1"
+DIMER_WORKLOADS = {
+    "hf-10x10x10-c1": "1000 monomers, their 2,700 nearest-neighbour pairs",
+    "hf-10x10x10-c1.5": "1000 monomers, their 7,560 nearest and face-diagonal pairs",
+}
 
 
-def dimer_problem():
-    """The 1000-monomer crystal with nearest-neighbour pairs only (2,700 pairs, the
-    c3 crystal's blocks of those pairs), K at LCCD_K_SCALE, with the intramonomer
-    and the dimer classes: the dimer class (vv|vv) alone is 4.25 MB per pair."""
+def dimer_problem(name=DIMER_WORKLOAD):
+    """A 1000-monomer crystal (the c3 crystal's blocks of its pairs), K at
+    LCCD_K_SCALE, with the intramonomer and the dimer classes: the dimer class
+    (vv|vv) alone is 4.25 MB per pair."""
     from synth import make_dimer_workload
-    return make_dimer_workload(DIMER_WORKLOAD)
+    return make_dimer_workload(name, workers=min(16, os.cpu_count() or 1))
 
 
-def dimer_mode(ctx, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: bool = True):
+def dimer_mode(ctx, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: bool = True, name=DIMER_WORKLOAD):
     """Full equations with the dimer-internal terms of Eq. 59 (Tau iterated):
     solves/s, the pair-ladder launch against the HBM roofline (algorithmic
     bytes = the packed <a b|a1 b1> stream, 8 round16(v^2) round32(v^2) per
@@ -678,8 +682,8 @@ def dimer_mode(ctx, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: bool 
     sample of pairs."""
     import numpy as np
     t0 = time.time()
-    p, ints, dints = dimer_problem()
-    log(f"[dimer] {DIMER_WORKLOAD}: N={p.n_mono} P={p.n_pair}, dimer classes {dints.nbytes() / 1e9:.2f} GB "
+    p, ints, dints = dimer_problem(name)
+    log(f"[dimer] {name}: N={p.n_mono} P={p.n_pair}, dimer classes {dints.nbytes() / 1e9:.2f} GB "
         f"made in {time.time() - t0:.1f}s")
     pid = ctx.upload(p)
     ctx.lccd_attach(pid, ints)
@@ -707,8 +711,9 @@ def dimer_mode(ctx, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: bool 
     ring_flops = 4 * 2.0 * (o * v) ** 3 * p.n_pair
     rms = tm["dimer_ring_ms"] / kl
     out = {
-        "workload": f"{DIMER_WORKLOAD}: 1000 monomers, {p.n_pair} nearest-neighbour pairs, K x 0.2, intramonomer "
-                    f"classes at sigma 0.01, dimer classes at sigma 0.01 (R_nn / R)^3",
+        "workload": f"{name}: {DIMER_WORKLOADS[name]}, K x 0.2, intramonomer classes at sigma 0.01, dimer "
+                    f"classes at sigma 0.01 (R_nn / R)^3",
+        "dimer_classes_GB": dints.nbytes() / 1e9,
         "solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "iso_sweeps": s["iso_sweeps"], "sweeps": s["sweeps"],
         "e_total": s["e_total"], "attach_s": attach_s,
         "pair_ladder_kernel": {"kernel": "lccd_ladder_lds_kernel (on pairs)", "bound": "hbm", "avg_launch_ms": ms,
@@ -722,7 +727,7 @@ def dimer_mode(ctx, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: bool 
         # HIP events around the whole pair phase: the two launches above and the pair kernel
         "pair_phase_avg_ms": tm["pair_ms"] / max(tm["pair_launches"], 1),
     }
-    gpath = os.path.join(ROOT, "tests", "golden", f"dimer-{DIMER_WORKLOAD}.json")
+    gpath = os.path.join(ROOT, "tests", "golden", f"dimer-{name}.json")
     if os.path.exists(gpath):
         g = json.load(open(gpath))
         out["oracle_reference"] = {"e_total": g["e_total"], "sweeps": g["sweeps"], "file": os.path.relpath(gpath, ROOT)}
@@ -827,6 +832,7 @@ def main():
     dimer = None
     if args.dimer_steps > 0:
         dimer = dimer_mode(ctx, args.dimer_steps, 1, args.tol, with_cpu=not args.no_cpu_baseline)
+        dimer["larger_crystal"] = dimer_mode(ctx, 1, 1, args.tol, with_cpu=False, name="hf-10x10x10-c1.5")
     ctx.close()
     served = None
     if args.serve_requests > 0:

@@ -241,9 +241,12 @@ mcpt_status mcpt_release(mcpt_ctx *ctx, uint64_t id);
 /* ---- Singles amplitudes (Eq. 57, program-flow step 4) ----
  * With the terms the inputs can form - the embedding source w and the pair sum
  * over neighbours Y of v^{ak}_{ic} t^c_k, where v^{ak}_{ic} = (ai|ck) =
- * V_XY[i][a][k][c] is the resident dimer block (the reversed pair uses V_XY^T);
- * the intramonomer term needs an integral class that is not an input and is
- * not formed - a sweep is t_X = (w_X + sum_Y V_XY t_Y) / (e_i - e_a) for every
+ * V_XY[i][a][k][c] is the resident dimer block (the reversed pair uses V_XY^T),
+ * summed over both spins of k, c (a factor 2); and, when the intramonomer
+ * classes are attached (mcpt_lccd_attach), the intramonomer term
+ * (2 v^{a i1}_{i a1} - v^{a i}_{a1 i1}) t^{a1}_{i1} with v^{a i1}_{i a1} =
+ * K[i][i1][a][a1] and v^{a i}_{a1 i1} = (a a1|i i1) = J[i][i1][a][a1] - a sweep
+ * is t_X = (w_X + 2 sum_Y V_XY t_Y [+ (2K - J) t_X]) / (e_i - e_a) for every
  * monomer from the previous t (Jacobi), from the first-order start
  * t = w / (e_i - e_a).  Each cluster of a batch stops on its own
  * max|t_new - t| < tol (tol == 0: exactly max_sweeps sweeps) under the divergence
@@ -355,6 +358,15 @@ typedef struct {
  * sizes), MCPT_ERR_NONFINITE, MCPT_ERR_ADMISSION, MCPT_ERR_NOMEM,
  * MCPT_ERR_UNKNOWN_ID, MCPT_ERR_DEVICE. */
 mcpt_status mcpt_dimer_attach(mcpt_ctx *ctx, uint64_t id, const mcpt_dimer_integrals *ints);
+
+/* Dimer amplitudes of the last run of a problem with the dimer terms attached:
+ * the Tau of the final Eq. 59 step, from which E_D2 is formed (Eq. 55).
+ * tau[sum over pairs of oX vX oY vY] (caller-allocated) receives
+ * Tau_XY[i][a][j][b] = Tau^{ab}_{ij} (i, a on the pair's first monomer),
+ * row-major, pairs concatenated in the caller's pair order.
+ * Errors: MCPT_ERR_INVALID (NULL, no dimer terms attached, never run),
+ * MCPT_ERR_UNKNOWN_ID, MCPT_ERR_DEVICE. */
+mcpt_status mcpt_dimer_tau(mcpt_ctx *ctx, uint64_t id, double *tau);
 
 /* ---- Finite-displacement geometries (Sec. IV.A: harmonic frequencies from
  * single points on a five-point grid, step 0.01 A in the paper) ----

@@ -12,10 +12,13 @@ E_M1(X) = 2 w^i_a t^a_i of Eq. 53 (em1).
 Readings taken where the paper is silent or ambiguous:
 
 * Terms kept: the one-electron embedding source w^a_i and the pair coupling
-  sum over neighbours Y of v^{ak}_{ic} t^c_k.  The intramonomer term
-  (2 v^{a i1}_{i a1} - v^{a i}_{a1 i1}) t^{a1}_{i1} pairs an ov|ov integral with
-  an oo|vv one that is not an input, so it is dropped as a whole (the same
-  rule as for the doubles).
+  sum over neighbours Y of v^{ak}_{ic} t^c_k; and, when the intramonomer
+  integral classes are given (the full monomer equation's inputs), the
+  intramonomer term (2 v^{a i1}_{i a1} - v^{a i}_{a1 i1}) t^{a1}_{i1} with
+  v^{a i1}_{i a1} = (ai|i1 a1) = K[i, i1, a, a1] (real orbitals) and
+  v^{a i}_{a1 i1} = (a a1|i i1) = J[i, i1, a, a1].  Without them the term is
+  dropped as a whole: it pairs an ov|ov integral with an oo|vv one, and keeping
+  half of it would be an arbitrary truncation (the rule of the doubles).
 * Sign: eps^i_a t = w + (the printed coupling with its printed sign), with
   eps^i_a = e_i - e_a, i.e. t = d * (w + 2 sum_Y v t), d = 1 / (e_i - e_a); the
   same reading as the doubles.  At zero coupling the energy is then
@@ -90,18 +93,30 @@ def coupling(prob, t):
     return [SPIN_SUM * ux for ux in u]
 
 
-def solve(prob, w, tol: float = 1e-10, max_sweeps: int = 500) -> SinglesResult:
-    """Iterate t = d * (w + 2 sum_Y v t) until max |t_new - t| < tol (tol == 0:
-    exactly max_sweeps sweeps, status OK unless the residual became non-finite)."""
+def intramonomer(K: np.ndarray, J: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """(2 v^{a i1}_{i a1} - v^{a i}_{a1 i1}) t^{a1}_{i1} of Eq. 57 as [i, a], with
+    v^{a i1}_{i a1} = K[i, i1, a, a1] and v^{a i}_{a1 i1} = J[i, i1, a, a1]."""
+    return np.einsum("IJAB,JB->IA", 2.0 * K - J, t)
+
+
+def solve(prob, w, tol: float = 1e-10, max_sweeps: int = 500, ints=None) -> SinglesResult:
+    """Iterate t = d * (w + 2 sum_Y v t [+ intramonomer term]) until
+    max |t_new - t| < tol (tol == 0: exactly max_sweeps sweeps, status OK unless
+    the residual became non-finite).  ints: the intramonomer integral classes
+    (an object with j_of(x) = J_X[i, j, a, b] = (ij|ab)), or None."""
     ws = _split(prob, w)
     d = [singles_denominator(*prob.eps_of(x)) for x in range(prob.n_mono)]
     t = [d[x] * ws[x] for x in range(prob.n_mono)]
     e0 = np.array([singles_energy(ws[x], t[x]) for x in range(prob.n_mono)])
+    KJ = None if ints is None else [(np.asarray(prob.k_of(x), dtype=np.float64),
+                                     np.asarray(ints.j_of(x), dtype=np.float64)) for x in range(prob.n_mono)]
     residuals = []
     status = STATUS_NOT_CONVERGED if tol > 0 else STATUS_OK
     sweeps = 0
     for _ in range(max_sweeps):
         u = coupling(prob, t)
+        if KJ is not None:
+            u = [u[x] + intramonomer(KJ[x][0], KJ[x][1], t[x]) for x in range(prob.n_mono)]
         t_new = [d[x] * (ws[x] + u[x]) for x in range(prob.n_mono)]
         r = max((float(np.max(np.abs(t_new[x] - t[x]))) for x in range(prob.n_mono) if t[x].size),
                 default=0.0)

@@ -945,8 +945,11 @@ mcpt_status singles(mcpt_ctx* c, Exec& x, Resident* R, const double* w, int32_t 
             }
         HIP_TRY(hipMemcpyAsync(R->d_cl1, zero.data(), R->n_cl * sizeof(ClState), hipMemcpyHostToDevice, s));
     }
-    launch_singles_mono(1, R->d_monos, R->n_mono, R->d_dif, R->d_w1, R->d_u1, R->d_t1, R->d_em1, R->d_em1_0,
-                        R->d_res1, nullptr, R->d_cl1, s);
+    // with the intramonomer classes attached, Eq. 57's intramonomer term joins the pair sum
+    const bool intra = R->lccd;
+    if (intra && !R->d_ui1 && (st = dev_alloc(c, R, &R->d_ui1, R->dif_elems)) != MCPT_OK) return st;
+    launch_singles_mono(1, R->d_monos, R->n_mono, R->d_dif, R->d_w1, R->d_u1, nullptr, R->d_t1, R->d_em1,
+                        R->d_em1_0, R->d_res1, nullptr, R->d_cl1, s);
     HIP_TRY(hipGetLastError());
     const int grid = singles_pair_grid(c->n_cu);
     const double vb = (double)R->v_elems * sizeof(double);
@@ -960,8 +963,10 @@ mcpt_status singles(mcpt_ctx* c, Exec& x, Resident* R, const double* w, int32_t 
             launch_singles_pair(R->d_pairs, R->n_pair, R->d_monos, R->d_V, R->d_t1, R->d_u1, grid, x.d_ctrl, R->d_cl1,
                                 s);
             record_end(x, a, 3, 0.0, vb);
-            launch_singles_mono(0, R->d_monos, R->n_mono, R->d_dif, R->d_w1, R->d_u1, R->d_t1, R->d_em1, R->d_em1_0,
-                                R->d_res1, x.d_ctrl, R->d_cl1, s);
+            if (intra)
+                launch_singles_intra(R->d_monos, R->n_mono, R->d_K, R->d_J, R->d_t1, R->d_ui1, x.d_ctrl, R->d_cl1, s);
+            launch_singles_mono(0, R->d_monos, R->n_mono, R->d_dif, R->d_w1, R->d_u1, intra ? R->d_ui1 : nullptr,
+                                R->d_t1, R->d_em1, R->d_em1_0, R->d_res1, x.d_ctrl, R->d_cl1, s);
             launch_reduce_sweep(R->n_cl, R->d_cl_mono, R->d_res1, R->d_cl1, R->d_hist1, x.d_ctrl, s);
             ++issued;
         }
@@ -2167,6 +2172,26 @@ mcpt_status mcpt_dimer_attach(mcpt_ctx* c, uint64_t id, const mcpt_dimer_integra
     } catch (const std::exception& e) {
         return fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
     }
+}
+
+mcpt_status mcpt_dimer_tau(mcpt_ctx* c, uint64_t id, double* tau) {
+    if (!c || !tau) return fail(MCPT_ERR_INVALID, "ctx or tau is NULL");
+    Resident* R = find_resident(c, id);
+    if (!R) return unknown(id);
+    if (!R->dimer) return fail(MCPT_ERR_INVALID, "problem has no dimer-internal terms attached");
+    if (!R->has_result) return fail(MCPT_ERR_INVALID, "problem has no result (not run, or diverged)");
+    HIP_TRY(hipSetDevice(c->device));
+    const int n = R->monos[0].n, np = R->monos[0].np;   // one monomer size with the dimer terms
+    const int64_t P = R->n_pair, mat = R->dimer_mat;
+    std::vector<double> h((size_t)(P * mat));
+    if (P > 0) HIP_TRY(hipMemcpyAsync(h.data(), R->d_Tau, P * mat * sizeof(double), hipMemcpyDeviceToHost,
+                                      c->main.stream));
+    HIP_TRY(hipStreamSynchronize(c->main.stream));
+    // pair p (caller order) is stored np x np at p * mat, row (i,a) = i v + a, column (j,b) = j v + b
+    for (int64_t p = 0; p < P; ++p)
+        for (int r = 0; r < n; ++r)
+            std::memcpy(tau + (p * n + r) * n, h.data() + p * mat + (int64_t)r * np, n * sizeof(double));
+    return MCPT_OK;
 }
 
 mcpt_status mcpt_singles(mcpt_ctx* c, uint64_t id, const double* w, int32_t memory, const mcpt_options* opts,

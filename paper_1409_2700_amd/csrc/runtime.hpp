@@ -71,6 +71,7 @@ struct Resident {
     // singles (made on the first mcpt_singles; freed with the problem): vectors in the padded
     // dif layout, per-monomer energies and residuals, per-cluster state and history
     double *d_w1 = nullptr, *d_t1 = nullptr, *d_u1 = nullptr;
+    double* d_ui1 = nullptr;          // intramonomer term of Eq. 57 (with the full monomer equation attached)
     double *d_em1 = nullptr, *d_em1_0 = nullptr, *d_res1 = nullptr, *d_hist1 = nullptr;
     ClState* d_cl1 = nullptr;
     int64_t* d_woff = nullptr;        // compact offsets of w per monomer (N + 1)

@@ -133,12 +133,50 @@ __global__ __launch_bounds__(kSThreads) void singles_pair_kernel(
     }
 }
 
+// Intramonomer term of Eq. 57, formed when the full monomer equation's integral
+// classes are attached: ui_X[(i,a)] = sum over (i1,a1) of
+// (2 v^{a i1}_{i a1} - v^{a i}_{a1 i1}) t^{a1}_{i1}, with v^{a i1}_{i a1} =
+// (ai|a1 i1) = K-hat[(i,a),(i1,a1)] and v^{a i}_{a1 i1} = (a a1|i i1) =
+// J[i][i1][a][a1], which the packed J-hat[(r,c)] = J[c_occ][r_occ][r_vir][c_vir]
+// holds at [(i1,a),(i,a1)].  One workgroup per monomer, t staged in LDS, a wave
+// per output row with the lanes over its columns (both matrices are read once per
+// sweep: 2 n^2 doubles per monomer, HBM-bound and small beside the pair phase).
+constexpr int kMaxN = 4096;
+__global__ __launch_bounds__(kMonoThreadsS) void singles_intra_kernel(
+    const MonoDesc* __restrict__ monos, const double* __restrict__ K, const double* __restrict__ Jh,
+    const double* __restrict__ t, double* __restrict__ ui, const Ctrl* __restrict__ ctrl,
+    const ClState* __restrict__ cl) {
+    if (ctrl && ctrl->done) return;
+    __shared__ double st[kMaxN];
+    const int x = blockIdx.x;
+    const MonoDesc d = monos[x];
+    if (cl && cl[d.cluster].done) return;
+    const int v = d.v, n = d.n, np = d.np;
+    const double* Kx = K + d.mat_off;
+    const double* Jx = Jh + d.mat_off;
+    for (int k = threadIdx.x; k < n; k += kMonoThreadsS) st[k] = t[d.dif_off + k];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int r = wave; r < n; r += kMonoThreadsS / 64) {
+        const int i = r / v, a = r - i * v;
+        double acc = 0.0;
+        for (int c = lane; c < n; c += 64) {
+            const int i1 = c / v, a1 = c - i1 * v;
+            acc += (2.0 * Kx[(int64_t)r * np + c] - Jx[(int64_t)(i1 * v + a) * np + i * v + a1]) * st[c];
+        }
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) ui[d.dif_off + r] = acc;
+    }
+}
+
 // init: t = w / d (first order), E_M1 into em1 and em1_0.
-// update: t' = (w + 2 u) / d, residual max|t' - t|, E_M1(t'), u cleared for the next sweep.
+// update: t' = (w + (2 u + ui)) / d (ui: the intramonomer term, or none), residual
+// max|t' - t|, E_M1(t'), u cleared for the next sweep.
 __global__ __launch_bounds__(kMonoThreadsS) void singles_mono_kernel(
     int init, const MonoDesc* __restrict__ monos, const double* __restrict__ dif, const double* __restrict__ w,
-    double* __restrict__ u, double* __restrict__ t, double* __restrict__ em1, double* __restrict__ em1_0,
-    double* __restrict__ res, const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
+    double* __restrict__ u, const double* __restrict__ ui, double* __restrict__ t, double* __restrict__ em1,
+    double* __restrict__ em1_0, double* __restrict__ res, const Ctrl* __restrict__ ctrl,
+    const ClState* __restrict__ cl) {
     if (ctrl && ctrl->done) return;
     __shared__ double sh[kMonoThreadsS];
     const int x = blockIdx.x;
@@ -156,7 +194,8 @@ __global__ __launch_bounds__(kMonoThreadsS) void singles_mono_kernel(
             tx[k] = tn;
             e += wx[k] * tn;
         } else {
-            const double tn = di * (wx[k] + kSpinSum * ux[k]);
+            const double cpl = ui ? kSpinSum * ux[k] + ui[d.dif_off + k] : kSpinSum * ux[k];
+            const double tn = di * (wx[k] + cpl);
             rmax = max_nan(rmax, fabs(tn - tx[k]));
             tx[k] = tn;
             ux[k] = 0.0;
@@ -220,11 +259,17 @@ void launch_singles_pair(const PairDesc* pairs, int64_t n_pair, const MonoDesc* 
 }
 
 void launch_singles_mono(int init, const MonoDesc* monos, int n_mono, const double* dif, const double* w, double* u,
-                         double* t, double* em1, double* em1_0, double* res, const Ctrl* ctrl, const ClState* cl,
-                         hipStream_t s) {
+                         const double* ui, double* t, double* em1, double* em1_0, double* res, const Ctrl* ctrl,
+                         const ClState* cl, hipStream_t s) {
     if (n_mono <= 0) return;
-    hipLaunchKernelGGL(singles_mono_kernel, dim3(n_mono), dim3(kMonoThreadsS), 0, s, init, monos, dif, w, u, t, em1,
-                       em1_0, res, ctrl, cl);
+    hipLaunchKernelGGL(singles_mono_kernel, dim3(n_mono), dim3(kMonoThreadsS), 0, s, init, monos, dif, w, u, ui, t,
+                       em1, em1_0, res, ctrl, cl);
+}
+
+void launch_singles_intra(const MonoDesc* monos, int n_mono, const double* K, const double* Jh, const double* t,
+                          double* ui, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
+    if (n_mono <= 0) return;
+    hipLaunchKernelGGL(singles_intra_kernel, dim3(n_mono), dim3(kMonoThreadsS), 0, s, monos, K, Jh, t, ui, ctrl, cl);
 }
 
 void launch_singles_clusters(int n_cl, const int64_t* cl_mono, const double* em1, const double* em1_0, ClState* cl,

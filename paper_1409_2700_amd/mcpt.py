@@ -41,7 +41,7 @@ EXPORTS = [
     "mcpt_serve_config", "mcpt_submit", "mcpt_poll", "mcpt_wait", "mcpt_serve_stats",
     "mcpt_autotune", "mcpt_tune_export", "mcpt_tune_import", "mcpt_singles", "mcpt_singles_result",
     "mcpt_lccd_attach", "mcpt_upload_scaled", "mcpt_fd_stencil", "mcpt_dimer_attach",
-    "mcpt_run_static",
+    "mcpt_run_static", "mcpt_dimer_tau",
 ]
 
 
@@ -156,6 +156,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.mcpt_upload.argtypes = [P, C.POINTER(mcpt_problem), C.POINTER(C.c_uint64)]
     lib.mcpt_run.argtypes = [P, C.c_uint64, C.POINTER(mcpt_options), C.POINTER(mcpt_summary)]
     lib.mcpt_run_static.argtypes = [P, C.c_uint64, C.POINTER(mcpt_options), C.POINTER(mcpt_summary)]
+    lib.mcpt_dimer_tau.argtypes = [P, C.c_uint64, P]
     lib.mcpt_solve.argtypes = [P, C.POINTER(mcpt_problem), C.POINTER(mcpt_options),
                                C.POINTER(C.c_uint64), C.POINTER(mcpt_summary)]
     lib.mcpt_energy.argtypes = [P, C.c_uint64, P, P, P, P]
@@ -420,6 +421,14 @@ class Context:
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (dints.w, dints.q, dints.cx, dints.cy)]
         di = mcpt_dimer_integrals(*[_ptr(a) for a in arrs], MCPT_HOST)
         _check(lib().mcpt_dimer_attach(self.h, pid, C.byref(di)))
+
+    def dimer_tau(self, pid: int) -> np.ndarray:
+        """Tau of every pair (mcpt_dimer_tau) as an array [pair, i, a, j, b] (one monomer size)."""
+        n_occ, n_vir, n_pair = self._sizes[pid]
+        o, v = int(n_occ[0]), int(n_vir[0])
+        tau = np.empty((n_pair, o, v, o, v))
+        _check(lib().mcpt_dimer_tau(self.h, pid, _ptr(tau)))
+        return tau
 
     # ---- finite-displacement geometries (mcpt_upload_scaled / mcpt_fd_stencil) ----
     def upload_scaled(self, base: int, pairs, scale) -> int:

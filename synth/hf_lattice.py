@@ -692,33 +692,47 @@ class DimerIntegrals:
 
 
 def dimer_integrals(prob: Problem, *, workload: int | None = None, cluster: int | None = None,
-                    sigma: float = SIGMA_DIMER) -> DimerIntegrals:
+                    sigma: float = SIGMA_DIMER, workers: int = 1) -> DimerIntegrals:
     """Seeded stand-ins for the dimer classes (vX vX|vY vY), (oX oX|oY oY),
     (oX oX|vY vY) and (oY oY|vX vX) of every stored pair, drawn N(0, s^2) with
     s = sigma (R_nn / R)^3 like the pair blocks and symmetrised as real orbitals
     require within each charge distribution ((pr|qs) = (rp|qs) = (pr|sq)).  Keyed
-    by the workload, the cluster and the two lattice sites."""
+    by the workload, the cluster and the two lattice sites, so workers > 1 (pairs
+    drawn on that many threads into preallocated arrays) gives the same values."""
     wl = int(prob.meta.get("workload", 0) if workload is None else workload)
     cl = int(prob.meta.get("cluster", 0) if cluster is None else cluster)
     sites = prob.sites if prob.sites is not None else np.stack([np.arange(prob.n_mono), np.zeros(prob.n_mono),
                                                                 np.zeros(prob.n_mono)], axis=1).astype(np.int64)
-    shapes, ws, qs, cxs, cys = [], [], [], [], []
-    for (x, y) in prob.pairs:
-        ox, vx, oy, vy = int(prob.n_occ[x]), int(prob.n_vir[x]), int(prob.n_occ[y]), int(prob.n_vir[y])
+    P = prob.n_pair
+    shapes = np.zeros((P, 4), dtype=np.int64)
+    for p, (x, y) in enumerate(prob.pairs):
+        shapes[p] = (int(prob.n_occ[x]), int(prob.n_vir[x]), int(prob.n_occ[y]), int(prob.n_vir[y]))
+    ox, vx, oy, vy = (shapes[:, k] for k in range(4))
+    offs = [np.concatenate([[0], np.cumsum(sz)]) for sz in (vx * vy * vx * vy, ox * oy * ox * oy,
+                                                          ox * ox * vy * vy, oy * oy * vx * vx)]
+    out = [np.empty(int(o[-1])) for o in offs]
+
+    def one(p):
+        x, y = (int(t) for t in prob.pairs[p])
+        a, b, c, d = (int(t) for t in shapes[p])
         r = float(np.linalg.norm((np.asarray(sites[x]) - np.asarray(sites[y])).astype(np.float64))) or 1.0
         s = sigma / r ** 3
         rng = _rng(wl, cl, KIND_DIMER, *sites[x], *sites[y])
-        g_vv = _symmetrised(rng, (vx, vx, vy, vy), _GROUP4, s)      # (a a1|b b1)
-        g_oo = _symmetrised(rng, (ox, ox, oy, oy), _GROUP4, s)      # (i1 i|j1 j)
-        g_ov = _symmetrised(rng, (ox, ox, vy, vy), _GROUP4, s)      # (i1 i|b b1)
-        g_vo = _symmetrised(rng, (oy, oy, vx, vx), _GROUP4, s)      # (j1 j|a a1)
-        shapes.append((ox, vx, oy, vy))
-        ws.append(np.ascontiguousarray(g_vv.transpose(0, 2, 1, 3)).ravel())   # <a b|a1 b1>
-        qs.append(np.ascontiguousarray(g_oo.transpose(0, 2, 1, 3)).ravel())   # <i1 j1|i j>
-        cxs.append(g_ov.ravel())
-        cys.append(g_vo.ravel())
-    cat = lambda parts: np.concatenate(parts) if parts else np.zeros(0)
-    return DimerIntegrals(np.asarray(shapes, dtype=np.int64).reshape(-1, 4), cat(ws), cat(qs), cat(cxs), cat(cys))
+        g_vv = _symmetrised(rng, (b, b, d, d), _GROUP4, s)      # (a a1|b b1)
+        g_oo = _symmetrised(rng, (a, a, c, c), _GROUP4, s)      # (i1 i|j1 j)
+        g_ov = _symmetrised(rng, (a, a, d, d), _GROUP4, s)      # (i1 i|b b1)
+        g_vo = _symmetrised(rng, (c, c, b, b), _GROUP4, s)      # (j1 j|a a1)
+        for k, blk in enumerate((g_vv.transpose(0, 2, 1, 3), g_oo.transpose(0, 2, 1, 3), g_ov, g_vo)):
+            out[k][offs[k][p]:offs[k][p + 1]] = blk.ravel()     # <a b|a1 b1>, <i1 j1|i j>, as drawn, as drawn
+
+    if workers > 1 and P > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(one, range(P)))
+    else:
+        for p in range(P):
+            one(p)
+    return DimerIntegrals(shapes.reshape(-1, 4), *out)
 
 
 # named workloads with the dimer classes: the crystals with nearest-neighbour pairs only (the
@@ -726,17 +740,19 @@ def dimer_integrals(prob: Problem, *, workload: int | None = None, cluster: int 
 DIMER_WORKLOADS = {
     "hf-3x3x3-c1": dict(workload=7, dims=(3, 3, 3), cutoff=1.0),
     "hf-10x10x10-c1": dict(workload=3, dims=(10, 10, 10), cutoff=1.0),
+    # nearest and face-diagonal neighbours (squared lattice distance <= 2): 7,560 pairs
+    "hf-10x10x10-c1.5": dict(workload=3, dims=(10, 10, 10), cutoff=1.5),
 }
 
 
-def make_dimer_workload(name: str, coupling_scale: float = DEFAULT_COUPLING_SCALE):
+def make_dimer_workload(name: str, coupling_scale: float = DEFAULT_COUPLING_SCALE, workers: int = 1):
     """A named crystal with K at LCCD_K_SCALE x its sigma, the intramonomer classes
     and the dimer classes.  Returns (problem, intramonomer integrals, dimer integrals)."""
     spec = DIMER_WORKLOADS[name]
     p = make_lattice_problem(cubic_sites(*spec["dims"]), spec["cutoff"], workload=spec["workload"],
                              coupling_scale=coupling_scale, k_scale=LCCD_K_SCALE)
     p.meta["name"] = name
-    return p, lccd_integrals(p), dimer_integrals(p)
+    return p, lccd_integrals(p), dimer_integrals(p, workers=workers)
 
 
 # ---------------------------------------------------------------------------

@@ -132,6 +132,49 @@ def pin_singles_disconnected_additivity(ms):
 
 
 @_safe
+def pin_singles_intramonomer_spin_orbital(ms):
+    """With the intramonomer classes: on a dimer whose integrals are all cut from
+    one real two-electron tensor g (no exchange between the monomers), the
+    converged amplitudes equal spin-orbital linear singles,
+        (e_i - e_a) t_i^a = w_i^a + sum over every occupied k and virtual c spin
+                            orbital of the dimer of <ak||ic> t_k^c,
+    with <ak|ic> = (ai|kc) = g[a, i, k, c] and <ak|ci> = g[a, c, k, i] read from g
+    itself, solved densely; alpha and beta amplitudes come out equal.  Fixes the
+    2v - v combination of Eq. 57's intramonomer term, its integral classes and
+    the spin sum of the pair term together."""
+    from .pins_dimer import physical_dimer
+    worst = 0.0
+    for sx, sy, seed in [((2, 3), (1, 3), 41), ((2, 2), (3, 2), 42)]:
+        p, ints, _, g, e, orbs = physical_dimer(sx, sy, seed)
+        rng = np.random.default_rng(seed)
+        w = rng.normal(0.0, 0.05, size=sum(p.n_ov(x) for x in range(p.n_mono)))
+        occ = [k for k, (_, o, _) in enumerate(orbs) if o]
+        vir = [k for k, (_, o, _) in enumerate(orbs) if not o]
+        so = [(m, i, a, s_) for m in (0, 1) for i in occ if orbs[i][0] == m
+              for a in vir if orbs[a][0] == m for s_ in (0, 1)]
+        n = len(so)
+        A = np.zeros((n, n))
+        rhs = np.zeros(n)
+        woff = {0: 0, 1: p.n_ov(0)}
+        for r_, (m, i, a, s_) in enumerate(so):
+            A[r_, r_] = e[i] - e[a]
+            rhs[r_] = w[woff[m] + orbs[i][2] * int(p.n_vir[m]) + orbs[a][2]]
+            for c_, (m2, k, c, sk) in enumerate(so):
+                direct = g[a, i, k, c]                         # <ak|ic>, spins of (a,i) and (k,c) each kept
+                exch = g[a, c, k, i] if sk == s_ else 0.0      # <ak|ci> needs a, c and k, i of one spin
+                A[r_, c_] -= direct - exch
+        t_so = np.linalg.solve(A, rhs)
+        t_a = np.array([t_so[r_] for r_, q in enumerate(so) if q[3] == 0])
+        t_b = np.array([t_so[r_] for r_, q in enumerate(so) if q[3] == 1])
+        r = ms.solve(p, w, tol=1e-14, max_sweeps=3000, ints=ints)
+        if r.status != 0:
+            return False, f"status {r.status}"
+        t = np.concatenate([tx.ravel() for tx in r.t])
+        worst = max(worst, _rel(t_b, t_a), _rel(t, t_a))
+    return worst < 1e-10, f"worst relative difference {worst:.3e}"
+
+
+@_safe
 def pin_singles_divergence_detected(ms):
     """A coupling far above the denominators makes the iteration diverge, and
     the rule says so."""
@@ -147,4 +190,5 @@ ALL_SINGLES_PINS = [
     pin_singles_relabel_and_orientation,
     pin_singles_disconnected_additivity,
     pin_singles_divergence_detected,
+    pin_singles_intramonomer_spin_orbital,
 ]

@@ -57,9 +57,16 @@ def run_gpu(ctx, p, ints, dints, **opts):
     ctx.dimer_attach(pid, dints)
     s = ctx.run(pid, raise_on_error=False, **opts)
     s["error"] = binding.last_error() if s["return"] != mc.MCPT_OK else ""
-    e = ctx.energy(pid) if s["return"] in (mc.MCPT_OK, mc.MCPT_ERR_NOT_CONVERGED) else None
+    e = None
+    if s["return"] in (mc.MCPT_OK, mc.MCPT_ERR_NOT_CONVERGED):
+        e = ctx.energy(pid)
+        e["tau"] = ctx.dimer_tau(pid)
     ctx.release(pid)
     return s, e
+
+
+def flat_tau(r):
+    return np.stack([np.asarray(t) for t in r.Tau])
 
 
 @pytest.mark.parametrize("o,v,general,sweeps", [(2, 3, False, 1), (2, 3, True, 3), (3, 17, False, 2),
@@ -72,6 +79,7 @@ def test_fixed_sweeps_elementwise(ctx, o, v, general, sweeps):
     assert s["return"] == mc.MCPT_OK, s["error"]
     assert s["sweeps"] == sweeps
     assert rel(e["t"], flat_t(ref)) <= TOL
+    assert rel(e["tau"], flat_tau(ref)) <= TOL      # every dimer amplitude, element by element
     assert rel(e["e_m2"], ref.e_m2) <= TOL
     assert rel(e["e_d2"], ref.e_d2) <= TOL
     assert abs(s["e_total"] - ref.e_total) <= TOL * abs(ref.e_total)
@@ -86,6 +94,7 @@ def test_converged_matches_oracle(ctx, graph):
     assert ref.status == 0 and s["return"] == mc.MCPT_OK, s["error"]
     assert s["sweeps"] == ref.sweeps
     assert rel(e["e_m2"], ref.e_m2) <= TOL and rel(e["e_d2"], ref.e_d2) <= TOL
+    assert rel(e["tau"], flat_tau(ref)) <= TOL and rel(e["t"], flat_t(ref)) <= TOL
     assert rel(e["e_m2"] - e["de_m2"], ref.e_m2_0) <= TOL
     assert abs(s["e_total"] - ref.e_total) <= TOL * abs(ref.e_total)
 
@@ -135,7 +144,7 @@ def test_batch_equals_solo(ctx):
 def test_converged_crystals_match_stored_oracle(ctx, name):
     with open(os.path.join(GOLDEN, f"dimer-{name}.json")) as f:
         g = json.load(f)
-    p, ints, dints = make_dimer_workload(name)
+    p, ints, dints = make_dimer_workload(name, workers=min(16, os.cpu_count() or 1))
     print(f"[gpu] dimer converged {name} N={p.n_mono} P={p.n_pair}", flush=True)
     s, e = run_gpu(ctx, p, ints, dints, tol=g["tol"], max_sweeps=400, check_every=4)
     assert s["return"] == mc.MCPT_OK and g["status"] == 0, s["error"]

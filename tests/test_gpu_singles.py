@@ -213,3 +213,50 @@ def test_no_pairs_closed_form(ctx):
     ctx.release(pid)
     assert s["sweeps"] == ref.sweeps == 1
     assert rel(out["e_m1"], ref.e_m1) <= TOL
+
+
+def _with_intramonomer(general, workload=912):
+    from synth import LCCD_K_SCALE, lccd_integrals
+    sizes = ((2, 3), (5, 27), (3, 17), (8, 56), (4, 9))
+    p = make_lattice_problem(cubic_sites(len(sizes), 1, 1), None, sizes=list(sizes), workload=workload,
+                             coupling_scale=0.5, k_scale=LCCD_K_SCALE)
+    ints = lccd_integrals(p)
+    if general:   # J without its real-orbital symmetry: J[i][i1] and J[i1][i] differ
+        ints.j[:] = np.random.default_rng(workload).normal(0.0, 0.01, size=ints.j.shape)
+    return p, ints
+
+
+@pytest.mark.parametrize("sweeps,general", [(1, False), (3, False), (3, True)])
+def test_intramonomer_term_fixed_sweeps(ctx, sweeps, general):
+    """With the intramonomer classes attached the singles include Eq. 57's
+    (2 v^{a i1}_{i a1} - v^{a i}_{a1 i1}) t^{a1}_{i1}: element by element against
+    the oracle given the same classes (and visibly different from without them)."""
+    p, ints = _with_intramonomer(general)
+    w = singles_source(p)
+    print(f"[gpu] singles with intramonomer term sweeps={sweeps} general={general}", flush=True)
+    ref = mcpt_singles.solve(p, w, tol=0.0, max_sweeps=sweeps, ints=ints)
+    plain = mcpt_singles.solve(p, w, tol=0.0, max_sweeps=sweeps)
+    assert rel(flat_t(plain), flat_t(ref)) > 1e-6
+    pid = ctx.upload(p)
+    ctx.lccd_attach(pid, ints)
+    s = ctx.singles(pid, w, tol=0.0, max_sweeps=sweeps)
+    out = ctx.singles_result(pid)
+    ctx.release(pid)
+    assert s["status"] == mc.MCPT_OK and s["sweeps"] == sweeps
+    assert rel(out["t1"], flat_t(ref)) <= TOL
+    assert rel(out["e_m1"], ref.e_m1) <= TOL
+
+
+def test_intramonomer_term_converged(ctx):
+    p, ints = _with_intramonomer(False, workload=913)
+    w = singles_source(p)
+    ref = mcpt_singles.solve(p, w, tol=TOL, max_sweeps=400, ints=ints)
+    pid = ctx.upload(p)
+    ctx.lccd_attach(pid, ints)
+    s = ctx.singles(pid, w, tol=TOL, max_sweeps=400)
+    out = ctx.singles_result(pid)
+    ctx.release(pid)
+    assert ref.status == 0 and s["status"] == mc.MCPT_OK
+    assert s["sweeps"] == ref.sweeps
+    assert abs(s["e_m1"] - ref.e_total) <= TOL * abs(ref.e_total)
+    assert rel(out["e_m1"], ref.e_m1) <= TOL

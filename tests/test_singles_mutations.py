@@ -50,6 +50,18 @@ def _printed_half(prob, t):
     return [0.5 * u for u in S.__dict__["_orig_coupling"](prob, t)]
 
 
+def _intra_factor_one(K, J, t):
+    return S.__dict__["_orig_intramonomer"](0.5 * K, J, t)
+
+
+def _intra_exchange_sign(K, J, t):
+    return S.__dict__["_orig_intramonomer"](K, -J, t)
+
+
+def _intra_classes_swapped(K, J, t):
+    return S.__dict__["_orig_intramonomer"](J, K, t)
+
+
 def _energy_factor_one(w, t):
     return float(np.sum(w * t))
 
@@ -63,6 +75,9 @@ MUTATIONS = {
     "reverse_without_transpose": ("coupling", _no_transpose),
     "coupling_sign": ("coupling", _minus_coupling),
     "printed_pair_sum_without_spin_sum": ("coupling", _printed_half),
+    "intramonomer_direct_factor_one": ("intramonomer", _intra_factor_one),
+    "intramonomer_exchange_sign": ("intramonomer", _intra_exchange_sign),
+    "intramonomer_k_and_j_swapped": ("intramonomer", _intra_classes_swapped),
     "occ_vir_swapped_in_t": ("coupling", _swapped_occ_vir),
     "energy_factor_one": ("singles_energy", _energy_factor_one),
     "denominator_reversed": ("singles_denominator", _denominator_reversed),
