@@ -87,7 +87,9 @@ __device__ inline typename Lowp<E>::Frag frag(const E* p) {
 // contiguous k from k0 + KL*(l/16)):
 //   Rows: a row-major matrix with k contiguous (global memory or LDS);
 //   Cols: the transpose of a row-major LDS matrix (element (row, k) at
-//         p[k * ld + row]), read as KL scalars per lane.
+//         p[k * ld + row]), read as KL scalars per lane; every row k of the
+//         chunk must be readable, and rows at or past the matrix's last are
+//         zero (padding rows), so the reads need no condition.
 template <class E>
 struct Rows {
     const E* p;
@@ -101,13 +103,12 @@ template <class E>
 struct Cols {
     const E* p;
     int ld;
-    int kmax;   // rows k >= kmax read as zero (the matrix stores only kmax rows)
     __device__ typename Lowp<E>::Frag operator()(int tile, int k0, int lane) const {
         typename Lowp<E>::Frag f;
         const int k = k0 + (lane >> 4) * Lowp<E>::KL;
         const E* q = p + (int64_t)k * ld + tile * 16 + (lane & 15);
 #pragma unroll
-        for (int e = 0; e < Lowp<E>::KL; ++e) f[e] = k + e < kmax ? q[(int64_t)e * ld] : E(0.0f);
+        for (int e = 0; e < Lowp<E>::KL; ++e) f[e] = q[(int64_t)e * ld];
         return f;
     }
 };
@@ -287,16 +288,17 @@ __global__ __launch_bounds__(kThreads) void convert_v_kernel(const PairDesc* __r
 }
 
 // Bytes of LDS the LDS-resident variant needs for a pair: V (npX rows) and,
-// for BF16, V^T (npY rows) and Tau (npX rows), each row padded by 16 bytes so
-// that the 16-byte fragment reads of 8 consecutive rows fall on distinct bank
-// groups.
+// for BF16, V^T (npY rows) and Tau (ldX rows: npX, then zero rows up to the k
+// range of the Tau^T fragments read as its columns), each row padded by 16
+// bytes so that the 16-byte fragment reads of 8 consecutive rows fall on
+// distinct bank groups.
 template <class E>
 __host__ __device__ inline int lds_row(int ld) { return ld + 16 / (int)sizeof(E); }
 
 template <class E>
 __host__ __device__ inline int64_t lds_bytes(int npX, int npY, int ldX, int ldY) {
     int64_t b = (int64_t)npX * lds_row<E>(ldY) * sizeof(E);
-    if (sizeof(E) == 2) b += (int64_t)npY * lds_row<E>(ldX) * sizeof(E) + (int64_t)npX * lds_row<E>(ldY) * sizeof(E);
+    if (sizeof(E) == 2) b += (int64_t)npY * lds_row<E>(ldX) * sizeof(E) + (int64_t)ldX * lds_row<E>(ldY) * sizeof(E);
     return b;
 }
 
@@ -358,6 +360,9 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
                     *reinterpret_cast<Chunk*>(sVt + r * sldX + c * VE) =
                         *reinterpret_cast<const Chunk*>(Vt + (int64_t)r * ldX + c * VE);
                 }
+                // Tau rows npX..ldX-1: zero, read as the k padding of the Tau^T fragments
+                for (int idx = threadIdx.x; idx < (ldX - npX) * sldY; idx += kThreadsK)
+                    sTau[(int64_t)npX * sldY + idx] = L::from(0.0);
             }
             __syncthreads();
         }
@@ -374,26 +379,36 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
             f4 acc[NR][NC];
             zero(acc);
             if (kVtLds) gemm<E, NR, NC, PD>(Rows<E>{MX, ldX}, Rows<E>{sVt, sldX}, ldX, r0, c0, lane, acc);   // M_X V
-            else if (IN_LDS) gemm<E, NR, NC, PD>(Rows<E>{MX, ldX}, Cols<E>{sV, sldY, npX}, ldX, r0, c0, lane, acc);
+            else if (IN_LDS) gemm<E, NR, NC, PD>(Rows<E>{MX, ldX}, Cols<E>{sV, sldY}, ldX, r0, c0, lane, acc);
             else gemm<E, NR, NC, PD>(Rows<E>{MX, ldX}, Rows<E>{Vt, ldX}, ldX, r0, c0, lane, acc);
             gemm<E, NR, NC, PD>(vrows(), Rows<E>{MY, ldY}, ldY, r0, c0, lane, acc);                        // V M_Y^T
+            // Epilogue, tile by tile: a tile's energy differences and V values are read
+            // before its stores, at the padded indices (V, its copies and the differences
+            // are zero-padded, so every read is in bounds), and the padding is masked by
+            // selects: the loads issue back to back instead of one branch and one L2 round
+            // trip per element.
 #pragma unroll
             for (int j = 0; j < NC; ++j) {
                 const int c = (c0 + j) * 16 + acc_col(lane);
-                const double dc = c < nY ? dY[c] : 0.0;
 #pragma unroll
                 for (int i = 0; i < NR; ++i) {
+                    const double dc = dY[c];
+                    double dr[4], vv[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int r = (r0 + i) * 16 + acc_row(lane, t);
+                        dr[t] = dX[r];
+                        vv[t] = v_at(r, c);
+                    }
                     E tv4[4];
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         const int r = (r0 + i) * 16 + acc_row(lane, t);
-                        double tv = 0.0;
-                        if (r < nX && c < nY) {
-                            const double dinv = recip(dX[r] + dc);
-                            const double v = v_at(r, c);
-                            tv = dinv * ((source ? v : 0.0) + (double)acc[i][j][t]);
-                            epart += v * tv;
-                        }
+                        const bool ok = r < nX && c < nY;
+                        const double dinv = recip(dr[t] + dc);
+                        const double v = vv[t];
+                        const double tv = ok ? dinv * ((source ? v : 0.0) + (double)acc[i][j][t]) : 0.0;
+                        epart += ok ? v * tv : 0.0;
                         tv4[t] = L::from(tv);
                         if (couple) {
                             if (kVtLds) sTau[r * sldY + c] = tv4[t];
@@ -405,6 +420,9 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
 #pragma unroll
                         for (int t = 0; t < 4; ++t) q[t] = tv4[t];
                     }
+                    // keep the next tile's loads after this tile's work (hoisting every tile's
+                    // loads would hold all their inputs in registers at once)
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
         });
@@ -456,9 +474,9 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
                     atomic_flush(GX, GfX, po.part ? po.part + po.off[pi] : nullptr, npX, nX, r0, c0, lane, acc);
                 } else {
                     if (kVtLds)   // Tau^T fragments as columns of the Tau kept in LDS
-                        gemm<E, NR, NC, PD>(Cols<E>{sTau, sldY, npX}, Rows<E>{sVt, sldX}, ldX, r0, c0, lane, acc);
+                        gemm<E, NR, NC, PD>(Cols<E>{sTau, sldY}, Rows<E>{sVt, sldX}, ldX, r0, c0, lane, acc);
                     else if (IN_LDS)
-                        gemm<E, NR, NC, PD>(Rows<E>{tauT, ldX}, Cols<E>{sV, sldY, npX}, ldX, r0, c0, lane, acc);
+                        gemm<E, NR, NC, PD>(Rows<E>{tauT, ldX}, Cols<E>{sV, sldY}, ldX, r0, c0, lane, acc);
                     else gemm<E, NR, NC, PD>(Rows<E>{tauT, ldX}, Rows<E>{Vt, ldX}, ldX, r0, c0, lane, acc);
                     atomic_flush(GY, GfY, po.part ? po.part + po.off[pi] + (int64_t)npX * npX : nullptr, npY, nY, r0,
                                  c0, lane, acc);
