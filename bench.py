@@ -811,6 +811,9 @@ def main():
     log(f"[bench] inputs {args.workload}: N={prob.n_mono} P={prob.n_pair} "
         f"({prob.nbytes() / 1e9:.2f} GB) in {time.time() - t0:.1f}s")
     ctx = mc.Context(0)
+    rates = mc.device_rates(0)
+    log(f"[bench] device FP64 pipes: MFMA {rates['mfma_f64_tflops']:.1f} TFLOP/s, "
+        f"VALU {rates['valu_f64_tflops']:.1f} TFLOP/s, clock {rates['clock_ghz']:.2f} GHz")
     t0 = time.time()
     pid = ctx.upload(prob)
     log(f"[bench] upload {time.time() - t0:.1f}s")
@@ -876,6 +879,9 @@ def main():
             "traffic_unit": "bytes per launch (L2-fabric, counters calibrated by a 1 GiB copy)",
             "kernel": kname, "avg_launch_ms": avg_ms,
             "flops_per_launch": flops_per_launch, "launches": kl,
+            # the sustained rate of the FP64 matrix pipe measured on this device at the kernel's occupancy
+            "device_rates": rates,
+            "frac_of_measured_mfma_f64": achieved / rates["mfma_f64_tflops"] if prec == 0 else None,
         },
         "monomer_phase": None if not mono_ms else {
             "bound": "hbm", "algorithmic_bytes_per_launch": mono_bytes, "avg_launch_ms": mono_ms,

@@ -417,6 +417,22 @@ mcpt_status mcpt_fd_stencil(mcpt_ctx *ctx, uint64_t base, int32_t n_modes, const
                             int32_t n_cell, const int32_t *cell, double step, const double *w,
                             const mcpt_options *opts, mcpt_fd_result *out);
 
+/* ---- Device characterization (roofline reporting; not part of the method) ----
+ * Sustained FP64 rates of the device, measured with register-only streams of
+ * independent operations at two waves per SIMD (the FP64 pair kernel's
+ * occupancy): v_mfma_f64_16x16x4 alone, and v_fma_f64 alone, in algorithmic
+ * TFLOP/s; the shader clock from the core clock counter against the 100 MHz
+ * real-time counter (of the last stream).  Allocates and frees its own small
+ * buffers on the device; takes ~0.1 s.
+ * Errors: MCPT_ERR_INVALID (no such device, NULL), MCPT_ERR_NOMEM, MCPT_ERR_DEVICE. */
+typedef struct {
+    double  mfma_f64_tflops;
+    double  valu_f64_tflops;
+    double  clock_ghz;
+    int32_t compute_units;
+} mcpt_rates;
+mcpt_status mcpt_device_rates(int device, mcpt_rates *out);
+
 /* ---- Tile autotuner of the reduced-precision pair kernel ----
  * The kernel exists in several tile shapes: each wave computes sb x sb output
  * tiles of 16 x 16 per task, nw waves per workgroup, pd k chunks loaded ahead.  mcpt_autotune times one

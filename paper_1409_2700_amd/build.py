@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libmcpt.so")
 ARCH = os.environ.get("MCPT_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["capi.hip", "serve.hip", "kernels_common.hip", "pair_fp64.hip", "pair_lowp.hip", "singles.hip", "lccd.hip",
-           "host.cpp"]
+           "host.cpp", "calib.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

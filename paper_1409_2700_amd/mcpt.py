@@ -41,7 +41,7 @@ EXPORTS = [
     "mcpt_serve_config", "mcpt_submit", "mcpt_poll", "mcpt_wait", "mcpt_serve_stats",
     "mcpt_autotune", "mcpt_tune_export", "mcpt_tune_import", "mcpt_singles", "mcpt_singles_result",
     "mcpt_lccd_attach", "mcpt_upload_scaled", "mcpt_fd_stencil", "mcpt_dimer_attach",
-    "mcpt_run_static", "mcpt_dimer_tau",
+    "mcpt_run_static", "mcpt_dimer_tau", "mcpt_device_rates",
 ]
 
 
@@ -87,6 +87,21 @@ class mcpt_timing(C.Structure):
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class mcpt_rates(C.Structure):
+    _fields_ = [("mfma_f64_tflops", C.c_double), ("valu_f64_tflops", C.c_double), ("clock_ghz", C.c_double),
+                ("compute_units", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+def device_rates(device: int = 0) -> dict:
+    """mcpt_device_rates: sustained FP64 MFMA and VALU rates and the shader clock."""
+    r = mcpt_rates()
+    _check(lib().mcpt_device_rates(device, C.byref(r)))
+    return r.as_dict()
 
 
 class mcpt_lccd_integrals(C.Structure):
@@ -157,6 +172,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.mcpt_run.argtypes = [P, C.c_uint64, C.POINTER(mcpt_options), C.POINTER(mcpt_summary)]
     lib.mcpt_run_static.argtypes = [P, C.c_uint64, C.POINTER(mcpt_options), C.POINTER(mcpt_summary)]
     lib.mcpt_dimer_tau.argtypes = [P, C.c_uint64, P]
+    lib.mcpt_device_rates.argtypes = [C.c_int, C.POINTER(mcpt_rates)]
     lib.mcpt_solve.argtypes = [P, C.POINTER(mcpt_problem), C.POINTER(mcpt_options),
                                C.POINTER(C.c_uint64), C.POINTER(mcpt_summary)]
     lib.mcpt_energy.argtypes = [P, C.c_uint64, P, P, P, P]
