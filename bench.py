@@ -95,14 +95,22 @@ def cpu_baseline(prob, sweeps: int, budget_s: float = 12.0) -> dict:
 
 def cpu_model() -> str:
     """The host CPU's model name (from /proc/cpuinfo), else the machine type."""
+    fields = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                key, _, val = line.partition(":")
+                key = key.strip()
+                if key in ("model name", "cpu family", "model", "stepping", "cpu MHz") and key not in fields:
+                    fields[key] = val.strip()
+                if not line.strip() and fields:
+                    break
     except OSError:
         pass
-    return platform.processor() or platform.machine()
+    if "model name" not in fields:
+        return platform.processor() or platform.machine()
+    extra = ", ".join(f"{k} {fields[k]}" for k in ("cpu family", "model", "stepping", "cpu MHz") if k in fields)
+    return f"{fields['model name']} ({extra})" if extra else fields["model name"]
 
 
 def oracle_threads() -> int:
