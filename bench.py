@@ -229,7 +229,7 @@ def _served_pass(ctx, stream, n_req, arrivals, max_inflight, tol, alone_e):
     outstanding = {}
     lat, err, status = [None] * n_req, [None] * n_req, [None] * n_req
     done_t, sub_t = [None] * n_req, [None] * n_req
-    state = {"done": 0}
+    state = {"done": 0, "submit_s": 0.0}
 
     def poller():
         while True:
@@ -267,20 +267,22 @@ def _served_pass(ctx, stream, n_req, arrivals, max_inflight, tol, alone_e):
         sub_t[r] = time.perf_counter() - start
         with stream.lend(r) as p:
             t = ctx.submit(p, tol=tol)
+        state["submit_s"] += time.perf_counter() - start - sub_t[r]
         with cv:
             outstanding[t] = r
     th.join()
-    return start, lat, err, status, done_t, sub_t
+    return start, lat, err, status, done_t, sub_t, state["submit_s"]
 
 
-def serving(base, n_req, loads, workers, max_batch, tol, max_inflight=32):
+def serving(base, n_req, loads, workers, max_batch, tol, max_inflight=32, staging_bytes=64 << 30):
     """Served stream (synth.ServedStream: requests cut from the resident crystal,
     sizes log-uniform in [8, N], one monomer displaced), first solved alone one at
     a time on the plain FP64 path (upload + solve), then submitted in a closed
     loop with at most max_inflight requests in flight (capacity: requests over
     the makespan), then with Poisson arrivals at the given fractions of that
     measured capacity.  Requests are lent as views of the relabelled crystal, so
-    host memory holds only the in-flight copies the library makes at submission."""
+    host memory holds only the in-flight copies the library makes at submission,
+    in pinned staging blocks up to staging_bytes (mcpt_serve_staging)."""
     import numpy as np
     import paper_1409_2700_amd as mc
     from synth import ServedStream, SEED_ROOT
@@ -319,21 +321,32 @@ def serving(base, n_req, loads, workers, max_batch, tol, max_inflight=32):
     }
     log(f"[serve] alone: mean {mean_alone * 1e3:.1f} ms, p50 {pct(alone_lat, 50) * 1e3:.1f} ms")
     capacity = None
+    # one scheduler for every pass, so the pinned staging blocks made for the first requests are reused;
+    # an untimed closed-loop pass over the first max_inflight requests makes them
+    ctx = mc.Context(0)
+    ctx.serve_config(workers=workers, max_batch=max_batch)
+    ctx.serve_staging(staging_bytes)
+    t0 = time.perf_counter()
+    _served_pass(ctx, stream, min(n_req, max_inflight), None, max_inflight, tol, alone_e)
+    st0 = ctx.serve_stats()
+    out["staging"] = {"cap_bytes": staging_bytes, "warmup_s": time.perf_counter() - t0,
+                      "pinned_bytes": st0["staging_pinned_bytes"]}
     for load in ["capacity"] + [x for x in loads if x != "burst"]:
         if load == "capacity":
             arrivals, cap = None, max_inflight
         else:
             rng = np.random.default_rng([SEED_ROOT, 5, int(round(load * 1000))])
             arrivals, cap = np.cumsum(rng.exponential(1.0 / (load * capacity), n_req)), 2 * max_inflight
-        with mc.Context(0) as ctx:
-            ctx.serve_config(workers=workers, max_batch=max_batch)
-            start, lat, err, status, done_t, sub_t = _served_pass(ctx, stream, n_req, arrivals, cap, tol, alone_e)
-            st = ctx.serve_stats()
+        b0 = ctx.serve_stats()["batches"]
+        start, lat, err, status, done_t, sub_t, sub_s = _served_pass(ctx, stream, n_req, arrivals, cap, tol, alone_e)
+        st = ctx.serve_stats()
         makespan = max(done_t) - start
         key = load if load == "capacity" else f"{load:.2f}"
         entry = {"completed_solves_per_s": n_req / makespan, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99),
-                 "mean_s": float(np.mean(lat)), "batches": st["batches"], "samples": n_req,
-                 "all_ok": all(w == 0 for w in status), "max_rel_err_vs_alone": float(max(err))}
+                 "mean_s": float(np.mean(lat)), "batches": st["batches"] - b0, "samples": n_req,
+                 "all_ok": all(w == 0 for w in status), "max_rel_err_vs_alone": float(max(err)),
+                 "submit_s": sub_s, "submit_share_of_makespan": sub_s / makespan,
+                 "staging_pinned_bytes": st["staging_pinned_bytes"], "staged_pageable": st["staged_pageable"]}
         if load == "capacity":
             capacity = n_req / makespan
             out["capacity_solves_per_s"] = capacity
@@ -344,7 +357,9 @@ def serving(base, n_req, loads, workers, max_batch, tol, max_inflight=32):
             entry.update({"offered_solves_per_s": load * capacity, "submission_delay_p99_s": pct(late, 99)})
         out["loads"][key] = entry
         log(f"[serve] {key}: {n_req / makespan:.2f} solves/s, p50 {pct(lat, 50) * 1e3:.1f} ms, "
-            f"p99 {pct(lat, 99) * 1e3:.1f} ms, {st['batches']} batches, max rel err {max(err):.1e}")
+            f"p99 {pct(lat, 99) * 1e3:.1f} ms, {entry['batches']} batches, max rel err {max(err):.1e}, "
+            f"submit {sub_s:.1f} s of {makespan:.1f} s")
+    ctx.close()
     return out
 
 

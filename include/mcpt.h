@@ -494,6 +494,8 @@ typedef struct {
     int32_t  running_batches;   /* batches on the device now */
     int32_t  workers;           /* worker threads (0 before the first submission) */
     int32_t  tickets;           /* live tickets (queued, running or holding results) */
+    uint64_t staging_pinned_bytes;  /* pinned host staging held for request copies */
+    uint64_t staged_pageable;   /* request arrays copied to pageable memory (staging full) */
 } mcpt_serve_counters;
 
 /* Scheduler parameters; only before the first mcpt_submit of the context.
@@ -501,6 +503,16 @@ typedef struct {
  * requests per batch, 1..4096 (default 32); max_batch_pairs: pairs per batch
  * (default 2^20).  Errors: MCPT_ERR_INVALID (range, scheduler running). */
 mcpt_status mcpt_serve_config(mcpt_ctx *ctx, int32_t workers, int32_t max_batch, int64_t max_batch_pairs);
+
+/* Host staging of submitted requests; only before the first mcpt_submit of the
+ * context.  mcpt_submit copies a request's integral arrays into pinned host
+ * blocks (power-of-two sizes from 1 MiB, made with hipHostMalloc on first need
+ * and reused by later requests), so the copy lands in pages that exist and the
+ * worker's upload is a DMA transfer; bytes caps the pinned memory held (default
+ * 16 GiB; 0: every request is copied to ordinary pageable memory, as it is when
+ * the cap is reached).  The blocks are freed with the context.
+ * Errors: MCPT_ERR_INVALID (scheduler running). */
+mcpt_status mcpt_serve_staging(mcpt_ctx *ctx, uint64_t bytes);
 
 /* Queue one solve.  The problem (host memory only) and options are checked and
  * copied before the call returns; *ticket names the request in mcpt_poll,

@@ -156,12 +156,65 @@ struct Exec {
 };
 
 // One served request: inputs copied at submission, then its place in a batch.
+// Pinned host staging of served requests: blocks of power-of-two sizes made with
+// hipHostMalloc on first need, up to a cap, and reused for later requests, so a
+// submission copies into memory whose pages already exist and the worker's
+// upload is a DMA transfer.  take() returns nullptr when the cap is reached.
+class PinnedPool {
+public:
+    ~PinnedPool();
+    void set_cap(size_t bytes);
+    double* take(size_t bytes);
+    void give(double* p);
+    size_t held() const;
+    uint64_t pageable() const;
+    void count_pageable();
+private:
+    mutable std::mutex mu_;
+    size_t cap_ = size_t(16) << 30;
+    size_t held_ = 0;
+    uint64_t pageable_ = 0;
+    std::map<int, std::vector<double*>> free_;   // log2 block size -> free blocks
+    std::map<double*, int> cls_;                  // every block -> log2 size
+};
+
+// A request's copy of a caller array: a pinned pool block, or ordinary memory
+// when the pool is full.
+class HostBuf {
+public:
+    HostBuf() = default;
+    HostBuf(double* p, PinnedPool* pool) : p_(p), pool_(pool) {}
+    HostBuf(const HostBuf&) = delete;
+    HostBuf& operator=(const HostBuf&) = delete;
+    HostBuf(HostBuf&& o) noexcept : p_(o.p_), pool_(o.pool_) { o.p_ = nullptr; }
+    HostBuf& operator=(HostBuf&& o) noexcept {
+        if (this != &o) {
+            reset();
+            p_ = o.p_;
+            pool_ = o.pool_;
+            o.p_ = nullptr;
+        }
+        return *this;
+    }
+    ~HostBuf() { reset(); }
+    double* get() const { return p_; }
+    void reset() {
+        if (!p_) return;
+        if (pool_) pool_->give(p_);
+        else delete[] p_;
+        p_ = nullptr;
+    }
+private:
+    double* p_ = nullptr;
+    PinnedPool* pool_ = nullptr;
+};
+
 struct Request {
     uint64_t ticket = 0;
     int state = 0;                      // 0 queued, 1 running, 2 done
     std::vector<int32_t> n_occ, n_vir, pair;
     std::vector<double> eps, warm_t;
-    std::unique_ptr<double[]> k_intra, v_dimer;
+    HostBuf k_intra, v_dimer;
     mcpt_problem prob{};                // points into the vectors above
     mcpt_options opts{};
     size_t footprint = 0;               // device bytes of the request alone
@@ -180,6 +233,7 @@ struct ServeParams {
 };
 
 struct Server {
+    PinnedPool pool;                    // first member: outlives the requests' buffers
     ServeParams params;
     std::deque<uint64_t> queue;         // queued tickets in arrival order (mu)
     std::map<uint64_t, std::unique_ptr<Request>> reqs;   // every live ticket (mu)

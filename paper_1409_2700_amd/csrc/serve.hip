@@ -23,6 +23,57 @@
 
 namespace mcpt {
 
+PinnedPool::~PinnedPool() {
+    for (auto& kv : cls_) (void)hipHostFree(kv.first);
+}
+
+void PinnedPool::set_cap(size_t bytes) {
+    std::lock_guard<std::mutex> g(mu_);
+    cap_ = bytes;
+}
+
+double* PinnedPool::take(size_t bytes) {
+    int k = 20;                                   // blocks of 1 MiB and up
+    while ((size_t(1) << k) < bytes) ++k;
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = free_.find(k);
+    if (it != free_.end() && !it->second.empty()) {
+        double* p = it->second.back();
+        it->second.pop_back();
+        return p;
+    }
+    const size_t sz = size_t(1) << k;
+    if (held_ + sz > cap_) return nullptr;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    held_ += sz;
+    cls_[static_cast<double*>(p)] = k;
+    return static_cast<double*>(p);
+}
+
+void PinnedPool::give(double* p) {
+    std::lock_guard<std::mutex> g(mu_);
+    free_[cls_.at(p)].push_back(p);
+}
+
+size_t PinnedPool::held() const {
+    std::lock_guard<std::mutex> g(mu_);
+    return held_;
+}
+
+uint64_t PinnedPool::pageable() const {
+    std::lock_guard<std::mutex> g(mu_);
+    return pageable_;
+}
+
+void PinnedPool::count_pageable() {
+    std::lock_guard<std::mutex> g(mu_);
+    ++pageable_;
+}
+
 namespace {
 
 double now_s() {
@@ -160,10 +211,14 @@ mcpt_status check_request(const mcpt_problem* pb) {
     return MCPT_OK;
 }
 
-// Copy of a large caller array, split over threads so that the first touch of
-// the new pages (most of the cost) proceeds in parallel.
-std::unique_ptr<double[]> copy_of(const double* src, int64_t n) {
-    std::unique_ptr<double[]> dst(new double[std::max<int64_t>(n, 1)]);
+// Copy of a large caller array into a pinned pool block (or, with the pool
+// full, new pageable memory), split over threads: memory bandwidth per thread
+// and, for new pages, their first touch set the cost.
+HostBuf copy_of(const double* src, int64_t n, PinnedPool& pool) {
+    const size_t bytes = (size_t)std::max<int64_t>(n, 1) * sizeof(double);
+    double* p = pool.take(bytes);
+    HostBuf dst = p ? HostBuf(p, &pool) : HostBuf(new double[std::max<int64_t>(n, 1)], nullptr);
+    if (!p) pool.count_pageable();
     const int64_t chunk = int64_t(8) << 20;   // 64 MiB
     const int nt = (int)std::min<int64_t>(8, (n + chunk - 1) / chunk);
     if (nt <= 1) {
@@ -171,9 +226,10 @@ std::unique_ptr<double[]> copy_of(const double* src, int64_t n) {
         return dst;
     }
     std::vector<std::thread> th;
+    double* d = dst.get();
     for (int t = 0; t < nt; ++t) {
         const int64_t b = n * t / nt, e = n * (t + 1) / nt;
-        th.emplace_back([&, b, e] { std::memcpy(dst.get() + b, src + b, (e - b) * sizeof(double)); });
+        th.emplace_back([d, src, b, e] { std::memcpy(d + b, src + b, (e - b) * sizeof(double)); });
     }
     for (auto& t : th) t.join();
     return dst;
@@ -292,6 +348,15 @@ mcpt_status mcpt_serve_config(mcpt_ctx* c, int32_t workers, int32_t max_batch, i
     return MCPT_OK;
 }
 
+mcpt_status mcpt_serve_staging(mcpt_ctx* c, uint64_t bytes) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    Server& S = server_of(c);
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!S.workers.empty()) return fail(MCPT_ERR_INVALID, "the scheduler is already running");
+    S.pool.set_cap((size_t)bytes);
+    return MCPT_OK;
+}
+
 mcpt_status mcpt_submit(mcpt_ctx* c, const mcpt_problem* prob, const mcpt_options* opts, uint64_t* ticket) {
     if (!c || !ticket) return fail(MCPT_ERR_INVALID, "ctx or ticket is NULL");
     mcpt_status st = validate_options(opts);
@@ -313,8 +378,9 @@ mcpt_status mcpt_submit(mcpt_ctx* c, const mcpt_problem* prob, const mcpt_option
         r->n_vir.assign(p.n_vir, p.n_vir + p.n_mono);
         r->pair.assign(p.pair ? p.pair : nullptr, p.pair ? p.pair + 2 * p.n_pair : nullptr);
         r->eps.assign(p.eps, p.eps + ne);
-        r->k_intra = copy_of(p.k_intra, nk);
-        r->v_dimer = copy_of(p.v_dimer, nv);
+        Server& S = server_of(c);
+        r->k_intra = copy_of(p.k_intra, nk, S.pool);
+        r->v_dimer = copy_of(p.v_dimer, nv, S.pool);
         int64_t nt = 0;
         for (int x = 0; x < p.n_mono; ++x) nt += (int64_t)p.n_occ[x] * p.n_vir[x] * p.n_occ[x] * p.n_vir[x];
         if (opts->warm_t) r->warm_t.assign(opts->warm_t, opts->warm_t + nt);
@@ -326,7 +392,6 @@ mcpt_status mcpt_submit(mcpt_ctx* c, const mcpt_problem* prob, const mcpt_option
         r->footprint = footprint(&r->prob, 1, opts->precision);
         r->size_class = size_class(r->prob);
         r->t_submit = now_s();
-        Server& S = server_of(c);
         std::lock_guard<std::mutex> g(c->mu);
         if (r->footprint > c->budget)
             return fail(MCPT_ERR_ADMISSION, "request needs " + std::to_string(r->footprint) +
@@ -390,6 +455,8 @@ mcpt_status mcpt_serve_stats(mcpt_ctx* c, mcpt_serve_counters* out) {
     out->running_batches = S.busy;
     out->workers = (int32_t)S.workers.size();
     for (const auto& kv : S.reqs) out->tickets += 1;
+    out->staging_pinned_bytes = S.pool.held();
+    out->staged_pageable = S.pool.pageable();
     return MCPT_OK;
 }
 

@@ -41,7 +41,7 @@ EXPORTS = [
     "mcpt_serve_config", "mcpt_submit", "mcpt_poll", "mcpt_wait", "mcpt_serve_stats",
     "mcpt_autotune", "mcpt_tune_export", "mcpt_tune_import", "mcpt_singles", "mcpt_singles_result",
     "mcpt_lccd_attach", "mcpt_upload_scaled", "mcpt_fd_stencil", "mcpt_dimer_attach",
-    "mcpt_run_static", "mcpt_dimer_tau", "mcpt_device_rates",
+    "mcpt_run_static", "mcpt_dimer_tau", "mcpt_device_rates", "mcpt_serve_staging",
 ]
 
 
@@ -140,6 +140,7 @@ class mcpt_serve_counters(C.Structure):
         ("completed", C.c_uint64), ("batches", C.c_uint64), ("budget", C.c_uint64),
         ("bytes_in_use", C.c_uint64), ("bytes_reserved", C.c_uint64), ("queued", C.c_int32),
         ("running_batches", C.c_int32), ("workers", C.c_int32), ("tickets", C.c_int32),
+        ("staging_pinned_bytes", C.c_uint64), ("staged_pageable", C.c_uint64),
     ]
 
     def as_dict(self) -> dict:
@@ -184,6 +185,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                      C.POINTER(C.c_uint64), C.POINTER(mcpt_summary)]
     lib.mcpt_cluster_results.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(mcpt_summary)]
     lib.mcpt_serve_config.argtypes = [P, C.c_int32, C.c_int32, C.c_int64]
+    lib.mcpt_serve_staging.argtypes = [P, C.c_uint64]
     lib.mcpt_submit.argtypes = [P, C.POINTER(mcpt_problem), C.POINTER(mcpt_options), C.POINTER(C.c_uint64)]
     lib.mcpt_poll.argtypes = [P, C.c_uint64, C.POINTER(mcpt_summary)]
     lib.mcpt_wait.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(mcpt_summary)]
@@ -507,6 +509,10 @@ class Context:
     # ---- serving (mcpt_submit / mcpt_poll) ----
     def serve_config(self, workers: int = 4, max_batch: int = 32, max_batch_pairs: int = 1 << 20):
         _check(lib().mcpt_serve_config(self.h, workers, max_batch, max_batch_pairs))
+
+    def serve_staging(self, nbytes: int):
+        """mcpt_serve_staging: cap of the pinned host staging of submitted requests."""
+        _check(lib().mcpt_serve_staging(self.h, nbytes))
 
     def submit(self, prob, **opts) -> int:
         """Queue one solve; returns its ticket (usable with energy / release once done)."""

@@ -200,3 +200,34 @@ def test_nonfinite_request_fails_alone(requests):
         with pytest.raises(mc.MCPTError):
             ctx.energy(ts[1])
         check_served(ctx, [probs[0], probs[2]], [ts[0], ts[2]], done, **opts)
+
+
+@pytest.mark.parametrize("cap", [0, 2 << 20, 1 << 34], ids=["pageable", "cap-2MiB", "pinned"])
+def test_staging_cap_keeps_results(requests, cap):
+    """Requests copied to pinned staging blocks, to pageable memory, or some of
+    each (a cap below the larger requests) all give the alone results; the
+    counters say which memory the copies went to, and pinned blocks are reused."""
+    opts = dict(tol=1e-10)
+    with mc.Context(0) as ctx:
+        ctx.serve_config(workers=2, max_batch=4)
+        ctx.serve_staging(cap)
+        print(f"[gpu] serve staging cap {cap}", flush=True)
+        tickets = [ctx.submit(p, **opts) for p in requests]
+        done = wait_all(ctx, tickets)
+        st = ctx.serve_stats()
+        check_served(ctx, requests, tickets, done, **opts)
+        # every request has two arrays (k_intra, v_dimer)
+        if cap == 0:
+            assert st["staging_pinned_bytes"] == 0 and st["staged_pageable"] == 2 * len(requests)
+        elif cap == 2 << 20:
+            assert 0 < st["staging_pinned_bytes"] <= cap and 0 < st["staged_pageable"] < 2 * len(requests)
+        else:
+            assert st["staged_pageable"] == 0 and st["staging_pinned_bytes"] > 0
+            for t in tickets:
+                ctx.release(t)
+            held = ctx.serve_stats()["staging_pinned_bytes"]
+            for p in requests[:3]:   # one at a time: each is served from blocks freed earlier
+                wait_all(ctx, [ctx.submit(p, **opts)])
+            assert ctx.serve_stats()["staging_pinned_bytes"] == held
+        with pytest.raises(mc.MCPTError):
+            ctx.serve_staging(cap)   # the scheduler is running
