@@ -723,7 +723,7 @@ mcpt_status ensure_lowp(mcpt_ctx* c, Exec& x, Resident* R, int prec) {
     R->lo_slot = (slot + 63) / 64 * 64;   // keeps every slot 16-byte aligned
     R->lo_v_bytes = (double)vo * es;
     R->lo_prec = prec;
-    // leading pairs whose V (and, for BF16, V^T) fit in LDS run in the LDS-resident kernel
+    // leading pairs whose V (and, for BF16, Tau) fit in LDS run in the LDS-resident kernel
     R->lo_n_lds = 0;
     R->lo_lds_bytes = 0;
     while (R->lo_n_lds < R->n_pair) {

@@ -29,6 +29,8 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s4 lds_s4;
 
 constexpr int kThreads = 256;   // conversion kernel
 constexpr int kXcds = 8;
@@ -110,6 +112,28 @@ struct Cols {
 #pragma unroll
         for (int e = 0; e < Lowp<E>::KL; ++e) f[e] = q[(int64_t)e * ld];
         return f;
+    }
+};
+
+// BF16 fragment of the transpose of a row-major LDS matrix (element (row, k) at
+// p[k * ld + row]) by two LDS transpose reads (ds_read_b64_tr_b16).  Within each
+// group of 16 lanes that instruction hands lane i, as its element j, element
+// i % 4 of the 4 consecutive 16-bit values at the address of lane 4 j + i / 4
+// of the group (measured).  So lane s of group g reads the 8 bytes at row
+// k0 + 8 g + 4 h + s / 4 (h = 0, 1 for the two halves of the fragment), columns
+// 16 tile + 4 (s % 4) .. + 3, and lane i receives column 16 tile + i of rows
+// k0 + 8 g + 4 h + j: the fragment the MFMA expects, k contiguous per lane.
+// Rows up to the last k of the chunk must be staged (zero past the matrix).
+struct ColsTr {
+    const __bf16* p;
+    int ld;
+    __device__ bf8 operator()(int tile, int k0, int lane) const {
+        const int g = lane >> 4, s = lane & 15;
+        __bf16* q = const_cast<__bf16*>(p) + (k0 + 8 * g + (s >> 2)) * ld + tile * 16 + 4 * (s & 3);
+        const s4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4*)q);
+        const s4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4*)(q + 4 * ld));
+        const bf4 a = __builtin_bit_cast(bf4, lo), b = __builtin_bit_cast(bf4, hi);
+        return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7);
     }
 };
 
@@ -287,9 +311,9 @@ __global__ __launch_bounds__(kThreads) void convert_v_kernel(const PairDesc* __r
     }
 }
 
-// Bytes of LDS the LDS-resident variant needs for a pair: V (npX rows) and,
-// for BF16, V^T (npY rows) and Tau (ldX rows: npX, then zero rows up to the k
-// range of the Tau^T fragments read as its columns), each row padded by 16
+// Bytes of LDS the LDS-resident variant needs for a pair: FP32 keeps V (npX
+// rows); BF16 keeps V and Tau, each with ldX rows (npX, then zero rows up to the
+// k range of the transposed fragments read from them), each row padded by 16
 // bytes so that the 16-byte fragment reads of 8 consecutive rows fall on
 // distinct bank groups.
 template <class E>
@@ -297,15 +321,16 @@ __host__ __device__ inline int lds_row(int ld) { return ld + 16 / (int)sizeof(E)
 
 template <class E>
 __host__ __device__ inline int64_t lds_bytes(int npX, int npY, int ldX, int ldY) {
-    int64_t b = (int64_t)npX * lds_row<E>(ldY) * sizeof(E);
-    if (sizeof(E) == 2) b += (int64_t)npY * lds_row<E>(ldX) * sizeof(E) + (int64_t)ldX * lds_row<E>(ldY) * sizeof(E);
-    return b;
+    (void)npY;
+    if (sizeof(E) == 2) return 2 * (int64_t)ldX * lds_row<E>(ldY) * sizeof(E);
+    return (int64_t)npX * lds_row<E>(ldY) * sizeof(E);
 }
 
 // One pair per workgroup iteration.  IN_LDS: V is staged in LDS once per pair
-// (BF16 also V^T, and Tau is kept in LDS; FP32 reads V^T fragments as columns
-// of the staged V) and every product takes one operand from LDS and the other
-// (M_X, M_Y, Tau^T, and Tau for FP32) from L2 (BF16 G_X: both from LDS);
+// (BF16 also keeps Tau in LDS and reads the transposed operands, V^T and Tau^T,
+// from them with LDS transpose reads; FP32 reads V^T fragments as columns of the
+// staged V) and every product takes one operand from LDS and the other (M_X,
+// M_Y, and Tau and Tau^T for FP32) from L2 (BF16 G_X and G_Y: both from LDS);
 // otherwise both operands come from L2.
 template <class E, int SB, int NW, int PD, bool IN_LDS>
 __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
@@ -316,7 +341,7 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
     const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl, PartOut po) {
     typedef Lowp<E> L;
     constexpr int kThreadsK = NW * 64;
-    constexpr bool kVtLds = IN_LDS && sizeof(E) == 2;
+    constexpr bool kTrLds = IN_LDS && sizeof(E) == 2;
     if (ctrl && ctrl->done) return;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ double red[NW];
@@ -340,11 +365,10 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
         const double* dY = dif + dy.dif_off;
         E* tauT = tau + (int64_t)npX * ldY;   // Tau: npX x ldY; Tau^T: npY x ldX
         const int RB = npX / 16, CB = npY / 16;
-        const int sldY = lds_row<E>(ldY), sldX = lds_row<E>(ldX);
-        E* sVt = sV + (int64_t)npX * sldY;
-        E* sTau = sVt + (int64_t)npY * sldX;   // BF16 only
+        const int sldY = lds_row<E>(ldY);
+        E* sTau = sV + (int64_t)ldX * sldY;   // BF16 only
 
-        if (IN_LDS) {   // stage V (and V^T) with 16-byte copies; padding rows and columns come zero
+        if (IN_LDS) {   // stage V with 16-byte copies; padding rows and columns come zero
             constexpr int VE = 16 / sizeof(E);
             typedef uint4 Chunk;
             const int cy = ldY / VE;
@@ -353,16 +377,12 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
                 *reinterpret_cast<Chunk*>(sV + r * sldY + c * VE) =
                     *reinterpret_cast<const Chunk*>(V + (int64_t)r * ldY + c * VE);
             }
-            if (kVtLds) {
-                const int cx = ldX / VE;
-                for (int idx = threadIdx.x; idx < npY * cx; idx += kThreadsK) {
-                    const int r = idx / cx, c = idx - r * cx;
-                    *reinterpret_cast<Chunk*>(sVt + r * sldX + c * VE) =
-                        *reinterpret_cast<const Chunk*>(Vt + (int64_t)r * ldX + c * VE);
-                }
-                // Tau rows npX..ldX-1: zero, read as the k padding of the Tau^T fragments
-                for (int idx = threadIdx.x; idx < (ldX - npX) * sldY; idx += kThreadsK)
+            if (kTrLds) {
+                // V and Tau rows npX..ldX-1: zero, read as the k padding of the transposed fragments
+                for (int idx = threadIdx.x; idx < (ldX - npX) * sldY; idx += kThreadsK) {
+                    sV[(int64_t)npX * sldY + idx] = L::from(0.0);
                     sTau[(int64_t)npX * sldY + idx] = L::from(0.0);
+                }
             }
             __syncthreads();
         }
@@ -378,7 +398,7 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
             constexpr int NR = decltype(shape)::NR, NC = decltype(shape)::NC;
             f4 acc[NR][NC];
             zero(acc);
-            if (kVtLds) gemm<E, NR, NC, PD>(Rows<E>{MX, ldX}, Rows<E>{sVt, sldX}, ldX, r0, c0, lane, acc);   // M_X V
+            if constexpr (kTrLds) gemm<E, NR, NC, PD>(Rows<E>{MX, ldX}, ColsTr{sV, sldY}, ldX, r0, c0, lane, acc);   // M_X V
             else if (IN_LDS) gemm<E, NR, NC, PD>(Rows<E>{MX, ldX}, Cols<E>{sV, sldY}, ldX, r0, c0, lane, acc);
             else gemm<E, NR, NC, PD>(Rows<E>{MX, ldX}, Rows<E>{Vt, ldX}, ldX, r0, c0, lane, acc);
             gemm<E, NR, NC, PD>(vrows(), Rows<E>{MY, ldY}, ldY, r0, c0, lane, acc);                        // V M_Y^T
@@ -411,11 +431,11 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
                         epart += ok ? v * tv : 0.0;
                         tv4[t] = L::from(tv);
                         if (couple) {
-                            if (kVtLds) sTau[r * sldY + c] = tv4[t];
+                            if (kTrLds) sTau[r * sldY + c] = tv4[t];
                             else tau[(int64_t)r * ldY + c] = tv4[t];
                         }
                     }
-                    if (couple && !kVtLds) {   // Tau^T row c, 4 consecutive columns (BF16 reads Tau from LDS)
+                    if (couple && !kTrLds) {   // Tau^T row c, 4 consecutive columns (BF16 reads Tau from LDS)
                         E* q = tauT + (int64_t)c * ldX + (r0 + i) * 16 + acc_row(lane, 0);
 #pragma unroll
                         for (int t = 0; t < 4; ++t) q[t] = tv4[t];
@@ -429,10 +449,10 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
         if (couple) {   // zero the k padding of Tau (columns npY..ldY) and Tau^T (columns npX..ldX)
             for (int idx = threadIdx.x; idx < npX * (ldY - npY); idx += kThreadsK) {
                 const int r = idx / (ldY - npY), c = npY + idx % (ldY - npY);
-                if (kVtLds) sTau[r * sldY + c] = L::from(0.0);
+                if (kTrLds) sTau[r * sldY + c] = L::from(0.0);
                 else tau[(int64_t)r * ldY + c] = L::from(0.0);
             }
-            for (int idx = threadIdx.x; !kVtLds && idx < npY * (ldX - npX); idx += kThreadsK) {
+            for (int idx = threadIdx.x; !kTrLds && idx < npY * (ldX - npX); idx += kThreadsK) {
                 const int r = idx / (ldX - npX), c = npX + idx % (ldX - npX);
                 tauT[(int64_t)r * ldX + c] = L::from(0.0);
             }
@@ -450,8 +470,7 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
             if (pn < n_pair) {
                 const PairDesc nd = pairs[pn];
                 const MonoDesc nx = monos[nd.x], ny = monos[nd.y];
-                const int64_t ne = (int64_t)nx.np * ((ny.n + L::KC - 1) / L::KC * L::KC) +
-                                   (int64_t)ny.np * ((nx.n + L::KC - 1) / L::KC * L::KC);
+                const int64_t ne = (int64_t)nx.np * ((ny.n + L::KC - 1) / L::KC * L::KC);   // V, not V^T
                 const E* vn = Vlo + lo_off[pn];
                 for (int64_t e = (int64_t)threadIdx.x * (64 / sizeof(E)); e < ne; e += (int64_t)kThreadsK * (64 / sizeof(E)))
                     sink += (float)vn[e];
@@ -469,12 +488,12 @@ __global__ __launch_bounds__(NW * 64) void pair_lowp_kernel(
                 f4 acc[NR][NC];
                 zero(acc);
                 if (which == 0) {
-                    if (kVtLds) gemm<E, NR, NC, PD>(Rows<E>{sTau, sldY}, vrows(), ldY, r0, c0, lane, acc);
+                    if (kTrLds) gemm<E, NR, NC, PD>(Rows<E>{sTau, sldY}, vrows(), ldY, r0, c0, lane, acc);
                     else gemm<E, NR, NC, PD>(Rows<E>{tau, ldY}, vrows(), ldY, r0, c0, lane, acc);
                     atomic_flush(GX, GfX, po.part ? po.part + po.off[pi] : nullptr, npX, nX, r0, c0, lane, acc);
                 } else {
-                    if (kVtLds)   // Tau^T fragments as columns of the Tau kept in LDS
-                        gemm<E, NR, NC, PD>(Cols<E>{sTau, sldY}, Rows<E>{sVt, sldX}, ldX, r0, c0, lane, acc);
+                    if constexpr (kTrLds)   // Tau^T and V, both transposed from the row-major LDS copies
+                        gemm<E, NR, NC, PD>(ColsTr{sTau, sldY}, ColsTr{sV, sldY}, ldX, r0, c0, lane, acc);
                     else if (IN_LDS)
                         gemm<E, NR, NC, PD>(Rows<E>{tauT, ldX}, Cols<E>{sV, sldY}, ldX, r0, c0, lane, acc);
                     else gemm<E, NR, NC, PD>(Rows<E>{tauT, ldX}, Rows<E>{Vt, ldX}, ldX, r0, c0, lane, acc);
