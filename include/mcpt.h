@@ -343,8 +343,10 @@ typedef struct {
 /* Attach (ints != NULL) or detach (NULL) the dimer classes of a resident
  * problem whose intramonomer integrals are attached (mcpt_lccd_attach; detaching
  * those, or attaching them again, detaches these too).  Every monomer must have
- * the same o <= 6 and v <= 64 with its n x n amplitudes within 160 KiB (o = 5,
- * v = 27 is 146 KB) and the problem at most 65,535 pairs.  The arrays are read
+ * the same o <= 8 and v <= 64, and the problem at most 65,535 pairs.  The pair
+ * ladder stages each pair's Tau in LDS when its n x n doubles fit 160 KiB (o = 5,
+ * v = 27 is 146 KB) and the hole pairs o^2 <= 48, and reads it from global
+ * memory otherwise (e.g. o = 8, v = 56).  The arrays are read
  * before the call returns; the packed copies (W_XY as vX vY rows padded to 16,
  * columns to 32: ~8 v^4 bytes per pair), Q_XY, the packed C_X and C_Y, four
  * np x np matrices per pair (Tau, the ladder-plus-monomer-ring source S and the

@@ -580,7 +580,8 @@ void pair_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int couple, const 
         // rings (added); the pair kernels add S into the numerator of Tau and keep the new Tau
         hipEvent_t a = nullptr;
         record_begin(x, &a);
-        launch_lccd_ladder(R->d_pmono, R->d_plccd, (int)R->n_pair, 1, R->dimer_ct, R->dimer_lds_bytes, R->d_DW,
+        launch_lccd_ladder(R->d_pmono, R->d_plccd, (int)R->n_pair, R->dimer_ladder_blocks, R->dimer_ct,
+                           R->dimer_lds_bytes, R->d_DW,
                            R->d_DQ, R->d_Tau, nullptr, nullptr, R->d_S, ctrl, cl, x.stream, 0);
         record_end(x, a, 6, R->dimer_w_flops, R->dimer_w_bytes);
         record_begin(x, &a);
@@ -1165,10 +1166,12 @@ mcpt_status dimer_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_dimer_int
     const int o = m0.o, v = m0.v, n = m0.n, np = m0.np, v2 = v * v;
     const int rows = round_up(v2, 16), cols = round_up(v2, 32);
     const int ct = lccd_ladder_ct(o);
-    const int64_t lds = lccd_ladder_lds_bytes(n, v, cols);
-    if (o > 6 || v > 64 || ct > 3 || lds > lccd_lds_limit())
-        return fail(MCPT_ERR_INVALID, "the dimer-internal terms support o <= 6, v <= 64 and n x n amplitudes "
-                                      "within 160 KiB");
+    // the pair ladder runs on the LDS-staged ladder kernel when a pair's n x n Tau fits one workgroup's
+    // LDS, else on the global-memory one (o^2 <= 64 hole pairs, v^2 <= 4096 in its offset tables)
+    int64_t lds = lccd_ladder_lds_bytes(n, v, cols);
+    if (lds > lccd_lds_limit() || ct > 3) lds = 0;
+    if (o > 8 || v > 64)
+        return fail(MCPT_ERR_INVALID, "the dimer-internal terms support o <= 8 and v <= 64");
     const int64_t P = R->n_pair, mat = (int64_t)np * np;
     const int64_t nw = P * v2 * v2, nq = P * o * o * o * o, nc = P * (int64_t)o * o * v2;
     if (!in->w_vvvv || !in->q_oooo || !in->c_x || !in->c_y) return fail(MCPT_ERR_INVALID, "an integral array is NULL");
@@ -1301,6 +1304,7 @@ mcpt_status dimer_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_dimer_int
     R->dimer_mat = mat;
     R->dimer_ct = ct;
     R->dimer_lds_bytes = lds;
+    R->dimer_ladder_blocks = lds > 0 ? 1 : lccd_ladder_blocks(rows, o);
     R->dimer_ring_blocks = dimer_ring_blocks(np);
     R->dimer_w_bytes = 8.0 * (double)w_pack;
     R->dimer_w_flops = 2.0 * (double)P * o * o * (double)v2 * v2;

@@ -398,7 +398,7 @@ template <int CT>
 __global__ __launch_bounds__(kLccdThreads, 2) void lccd_ladder_kernel(
     const MonoDesc* __restrict__ monos, const LccdDesc* __restrict__ ld, int n_mono, int blocks_per_mono,
     const double* __restrict__ W, const double* __restrict__ Q, const double* __restrict__ T,
-    const double* __restrict__ R12, const double* __restrict__ Y, double* __restrict__ L,
+    const double* __restrict__ R12, const double* __restrict__ Y, double* __restrict__ L, int rings,
     const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
     if (ctrl && ctrl->done) return;
     const int q = blockIdx.x / kXcds;
@@ -420,16 +420,18 @@ __global__ __launch_bounds__(kLccdThreads, 2) void lccd_ladder_kernel(
         hofs[k] = k < o2 ? kk * v * np + ll * v : 0;
     }
     __syncthreads();
-    LadderView g{W + l.w_off, Q + l.q_off, T + d.mat_off, R12 + d.mat_off, Y + d.mat_off, L + d.mat_off,
-                 kofs, hofs, l.ldw, l.w_rows, np, o, v, o2, v2, np};
+    LadderView g{W + l.w_off, Q + l.q_off, T + d.mat_off, rings ? R12 + d.mat_off : nullptr,
+                 rings ? Y + d.mat_off : nullptr, L + d.mat_off, kofs, hofs, l.ldw, l.w_rows, np, o, v, o2, v2, np};
     const int nrt = l.w_rows / 16;
     const int ntask_r = (nrt + kLadRT - 1) / kLadRT;
     const int nct = (o2 + 15) / 16;
     const int ngroups = (nct + CT - 1) / CT;
     const int tasks = ntask_r * ngroups;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int task = part * (kLccdThreads / 64) + wave; task < tasks; task += blocks_per_mono * (kLccdThreads / 64))
-        ladder_task<kLadRT, CT, 2, true>(g, (task / ngroups) * kLadRT, (task % ngroups) * CT, lane);
+    for (int task = part * (kLccdThreads / 64) + wave; task < tasks; task += blocks_per_mono * (kLccdThreads / 64)) {
+        if (rings) ladder_task<kLadRT, CT, 2, true>(g, (task / ngroups) * kLadRT, (task % ngroups) * CT, lane);
+        else ladder_task<kLadRT, CT, 2, false>(g, (task / ngroups) * kLadRT, (task % ngroups) * CT, lane);
+    }
 }
 
 // The same with the monomer's amplitudes staged in LDS (n x n doubles, row
@@ -718,19 +720,19 @@ void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, i
     switch (ct) {
         case 1:
             hipLaunchKernelGGL(lccd_ladder_kernel<1>, grid, block, 0, s, monos, ld, n_mono, ladder_blocks, W, Q, T,
-                               R12, Y, L, ctrl, cl);
+                               R12, Y, L, rings, ctrl, cl);
             break;
         case 2:
             hipLaunchKernelGGL(lccd_ladder_kernel<2>, grid, block, 0, s, monos, ld, n_mono, ladder_blocks, W, Q, T,
-                               R12, Y, L, ctrl, cl);
+                               R12, Y, L, rings, ctrl, cl);
             break;
         case 3:
             hipLaunchKernelGGL(lccd_ladder_kernel<3>, grid, block, 0, s, monos, ld, n_mono, ladder_blocks, W, Q, T,
-                               R12, Y, L, ctrl, cl);
+                               R12, Y, L, rings, ctrl, cl);
             break;
         default:
             hipLaunchKernelGGL(lccd_ladder_kernel<4>, grid, block, 0, s, monos, ld, n_mono, ladder_blocks, W, Q, T,
-                               R12, Y, L, ctrl, cl);
+                               R12, Y, L, rings, ctrl, cl);
             break;
     }
 }

@@ -2,8 +2,9 @@
 iterated) on the GPU against the oracle: fixed sweep counts element by element
 on uniform clusters of one to nine MFMA tiles per edge (n = 6, 51, 135, the
 last two with ragged tails), with physical-symmetry and with general
-integrals, the converged solve with equal sweep counts, graph replay, and the
-error paths.  Bar: 1e-10 relative (FP64), sweep counts equal."""
+integrals, monomers at and above the LDS limit of the staged pair ladder (up to
+o8v56, n = 448), the converged solve with equal sweep counts, graph replay, and
+the error paths.  Bar: 1e-10 relative (FP64), sweep counts equal."""
 import json
 import os
 import types
@@ -140,7 +141,7 @@ def test_batch_equals_solo(ctx):
         assert abs(res[k]["e_total"] - solo[k]["e_total"]) <= 1e-12 * abs(solo[k]["e_total"])
 
 
-@pytest.mark.parametrize("name", ["hf-3x3x3-c1", "hf-10x10x10-c1"])
+@pytest.mark.parametrize("name", ["hf-3x3x3-c1", "hf-10x10x10-c1", "hf-10x10x10-c1.5"])
 def test_converged_crystals_match_stored_oracle(ctx, name):
     with open(os.path.join(GOLDEN, f"dimer-{name}.json")) as f:
         g = json.load(f)
@@ -200,19 +201,39 @@ def test_single_pair_and_no_pairs(ctx):
     ctx.release(pid)
 
 
-def test_largest_monomer_and_first_refused(ctx):
-    """o = 6, v = 23 (n = 138): three column tiles per ladder task and 155 KB of the
-    160 KiB of LDS, element by element after two sweeps; o = 6, v = 24 (n = 144, 168 KB
-    of amplitudes) is refused."""
-    p, ints, dints = cluster(6, 23, dims=(2, 1, 1), workload=955)
+@pytest.mark.parametrize("o,v,workload", [(6, 23, 955), (6, 24, 956), (8, 56, 958)])
+def test_monomers_at_and_above_the_lds_limit(ctx, o, v, workload):
+    """o = 6, v = 23 (n = 138): the largest pair whose Tau fits the LDS-staged ladder
+    (three column tiles per task, 155 KB of the 160 KiB); o = 6, v = 24 (n = 144) and
+    o = 8, v = 56 (n = 448, four column tiles, 79 MB of W_XY per pair) run the pair
+    ladder from global memory.  Element by element after two sweeps."""
+    p, ints, dints = cluster(o, v, dims=(2, 1, 1), workload=workload)
+    print(f"[gpu] dimer o={o} v={v} n={o * v} fixed sweeps", flush=True)
     ref = mcpt_dimer.solve(p, ints, dints, tol=0.0, max_sweeps=2)
     s, e = run_gpu(ctx, p, ints, dints, tol=0.0, max_sweeps=2)
     assert s["return"] == mc.MCPT_OK, s["error"]
     assert rel(e["t"], flat_t(ref)) <= TOL and rel(e["e_d2"], ref.e_d2) <= TOL
+    assert rel(e["tau"], flat_tau(ref)) <= TOL
     assert rel(e["e_m2"], ref.e_m2) <= TOL
-    q, qi, qd = cluster(6, 24, dims=(2, 1, 1), workload=956)
+
+
+def test_o8v56_converged_and_too_large_refused(ctx):
+    """The o8v56 pair (at the crystal's coupling scale, where its monomer equations
+    converge) with the oracle's sweep count; o = 9 is refused (by the intramonomer
+    terms, which the dimer terms need)."""
+    p, ints, dints = cluster(8, 56, dims=(2, 1, 1), scale=0.18, workload=959)
+    print("[gpu] dimer o8v56 converged", flush=True)
+    ref = mcpt_dimer.solve(p, ints, dints, tol=TOL, max_sweeps=200)
+    s, e = run_gpu(ctx, p, ints, dints, tol=TOL, max_sweeps=200)
+    assert ref.status == 0 and s["return"] == mc.MCPT_OK, s["error"]
+    assert s["sweeps"] == ref.sweeps
+    assert rel(e["e_m2"], ref.e_m2) <= TOL and rel(e["e_d2"], ref.e_d2) <= TOL
+    assert rel(e["tau"], flat_tau(ref)) <= TOL
+    assert abs(s["e_total"] - ref.e_total) <= TOL * abs(ref.e_total)
+    q, qi, qd = cluster(9, 3, dims=(2, 1, 1), workload=960)
     pid = ctx.upload(q)
-    ctx.lccd_attach(pid, qi)
+    with pytest.raises(mc.MCPTError):
+        ctx.lccd_attach(pid, qi)
     with pytest.raises(mc.MCPTError):
         ctx.dimer_attach(pid, qd)
     ctx.release(pid)
