@@ -343,15 +343,19 @@ typedef struct {
 /* Attach (ints != NULL) or detach (NULL) the dimer classes of a resident
  * problem whose intramonomer integrals are attached (mcpt_lccd_attach; detaching
  * those, or attaching them again, detaches these too).  Every monomer must have
- * the same o <= 8 and v <= 64, and the problem at most 65,535 pairs.  The pair
- * ladder stages each pair's Tau in LDS when its n x n doubles fit 160 KiB (o = 5,
- * v = 27 is 146 KB) and the hole pairs o^2 <= 48, and reads it from global
- * memory otherwise (e.g. o = 8, v = 56).  The arrays are read
+ * o <= 8 and v <= 64 (the two monomers of a pair may differ in size), and the
+ * problem at most 65,535 pairs.  When every monomer has one size whose n x n
+ * Tau fits 160 KiB of LDS (o = 5, v = 27 is 146 KB) with o^2 <= 48, the pair
+ * ladder stages each pair's Tau in LDS; otherwise it reads Tau from global
+ * memory.  The classes of the pairs are concatenated in the caller's pair
+ * order, each with its own pair's sizes.  The arrays are read
  * before the call returns; the packed copies (W_XY as vX vY rows padded to 16,
- * columns to 32: ~8 v^4 bytes per pair), Q_XY, the packed C_X and C_Y, four
- * np x np matrices per pair (Tau, the ladder-plus-monomer-ring source S and the
- * two cross-ring products Y1, Y2) and one np x np matrix per monomer (2K - J of
- * the monomer rings) stay with the problem and count against the budget.  The
+ * columns to 32: ~8 (vX vY)^2 bytes per pair), Q_XY, the packed C_X and C_Y
+ * (oX vY and oY vX square, padded to 16), per pair Tau and the
+ * ladder-plus-monomer-ring source S (npX x npY each) and the two cross-ring
+ * products Y1, Y2 (oX vY x oY vX and its transpose shape, padded), and one
+ * np x np matrix per monomer (2K - J of the monomer rings) stay with the
+ * problem and count against the budget.  The
  * problem's last results are dropped.  mcpt_run of an attached problem accepts
  * only the FP64 form (precision MCPT_FP64) and has no deterministic mode: its
  * results are reproducible to rounding only (the pair kernel adds the G_X and

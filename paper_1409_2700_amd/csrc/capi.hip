@@ -81,6 +81,8 @@ void free_dimer(mcpt_ctx* c, Resident* r) {
         c->in_use -= std::min(c->in_use, r->dimer_bytes);
     }
     r->dimer_bytes = 0;
+    r->dimer_desc.clear();
+    r->dimer_tau_elems = 0;
     r->dimer = false;
     r->d_dd = nullptr;
     r->d_pmono = nullptr;
@@ -580,20 +582,22 @@ void pair_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int couple, const 
         // rings (added); the pair kernels add S into the numerator of Tau and keep the new Tau
         hipEvent_t a = nullptr;
         record_begin(x, &a);
-        launch_lccd_ladder(R->d_pmono, R->d_plccd, (int)R->n_pair, R->dimer_ladder_blocks, R->dimer_ct,
-                           R->dimer_lds_bytes, R->d_DW,
-                           R->d_DQ, R->d_Tau, nullptr, nullptr, R->d_S, ctrl, cl, x.stream, 0);
+        if (R->dimer_lds_bytes > 0)
+            launch_lccd_ladder(R->d_pmono, R->d_plccd, (int)R->n_pair, 1, R->dimer_ct, R->dimer_lds_bytes, R->d_DW,
+                               R->d_DQ, R->d_Tau, nullptr, nullptr, R->d_S, ctrl, cl, x.stream, 0);
+        else
+            launch_dimer_ladder(R->d_dd, (int)R->n_pair, R->dimer_ladder_blocks, R->dimer_ct, R->d_DW, R->d_DQ,
+                                R->d_Tau, R->d_S, ctrl, cl, x.stream);
         record_end(x, a, 6, R->dimer_w_flops, R->dimer_w_bytes);
         record_begin(x, &a);
-        launch_dimer_ring(R->d_dd, R->d_monos, R->d_pmono, (int)R->n_pair, R->dimer_ring_blocks, R->d_DRM,
-                          R->d_DCX, R->d_DCY, R->d_Tau, R->d_S, R->d_DY1, R->d_DY2, ctrl, cl, x.stream);
+        launch_dimer_ring(R->d_dd, R->d_monos, (int)R->n_pair, R->dimer_ring_blocks, R->d_DRM, R->d_DCX, R->d_DCY,
+                          R->d_Tau, R->d_S, R->d_DY1, R->d_DY2, ctrl, cl, x.stream);
         record_end(x, a, 7, 0.0, 0.0);
         p0.S = p1.S = R->d_S;
         p0.Y1 = p1.Y1 = R->d_DY1;
         p0.Y2 = p1.Y2 = R->d_DY2;
-        p0.v = p1.v = R->monos[0].v;
         p0.tau_out = p1.tau_out = R->d_Tau;
-        p0.mat_stride = p1.mat_stride = R->dimer_mat;
+        p0.dd = p1.dd = R->d_dd;
     }
     const int g_lds = x.grid_cap > 0 ? std::min(c->grid_lds, x.grid_cap) : c->grid_lds;
     const int g_glb = x.grid_cap > 0 ? std::min(c->grid_glb, x.grid_cap) : c->grid_glb;
@@ -1142,9 +1146,12 @@ mcpt_status lccd_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_lccd_integ
 }
 
 // Dimer classes of the dimer-internal terms of Eq. 59: validated, copied, packed
-// and kept with the problem; in == nullptr detaches.  Each pair is described to
-// the ladder kernel as a monomer would be: n = o v, its n x n matrices at
-// p np^2, its W_XY packed like a monomer's W.
+// and kept with the problem; in == nullptr detaches.  Each pair gets a DimerDesc
+// (sizes of its two monomers, offsets of its matrices).  When every monomer has
+// one size and a pair's n x n Tau fits one workgroup's LDS, the pair ladders run
+// on the LDS-staged monomer ladder kernel, each pair described to it as a
+// monomer would be (n = o v, its matrices at its Tau offset, its W_XY packed like
+// a monomer's W); otherwise on the global-memory pair ladder kernel.
 mcpt_status dimer_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_dimer_integrals* in) {
     mcpt_status st;
     if ((st = ensure_device(c)) != MCPT_OK) return st;
@@ -1159,21 +1166,70 @@ mcpt_status dimer_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_dimer_int
         return fail(MCPT_ERR_INVALID, "memory must be MCPT_HOST or MCPT_DEVICE");
     if (R->n_mono <= 0 || R->n_pair <= 0) return fail(MCPT_ERR_INVALID, "the problem has no pairs");
     if (R->n_pair > 65535) return fail(MCPT_ERR_INVALID, "the dimer-internal terms support at most 65,535 pairs");
+    for (const MonoDesc& m : R->monos)
+        if (m.o > 8 || m.v > 64) return fail(MCPT_ERR_INVALID, "the dimer-internal terms support o <= 8 and v <= 64");
     const MonoDesc m0 = R->monos[0];
-    for (int m = 1; m < R->n_mono; ++m)
-        if (R->monos[m].o != m0.o || R->monos[m].v != m0.v)
-            return fail(MCPT_ERR_INVALID, "the dimer-internal terms need every monomer of one size (o, v)");
-    const int o = m0.o, v = m0.v, n = m0.n, np = m0.np, v2 = v * v;
-    const int rows = round_up(v2, 16), cols = round_up(v2, 32);
-    const int ct = lccd_ladder_ct(o);
-    // the pair ladder runs on the LDS-staged ladder kernel when a pair's n x n Tau fits one workgroup's
-    // LDS, else on the global-memory one (o^2 <= 64 hole pairs, v^2 <= 4096 in its offset tables)
-    int64_t lds = lccd_ladder_lds_bytes(n, v, cols);
-    if (lds > lccd_lds_limit() || ct > 3) lds = 0;
-    if (o > 8 || v > 64)
-        return fail(MCPT_ERR_INVALID, "the dimer-internal terms support o <= 8 and v <= 64");
-    const int64_t P = R->n_pair, mat = (int64_t)np * np;
-    const int64_t nw = P * v2 * v2, nq = P * o * o * o * o, nc = P * (int64_t)o * o * v2;
+    bool one_size = true;
+    for (const MonoDesc& m : R->monos) one_size = one_size && m.o == m0.o && m.v == m0.v;
+    const int64_t P = R->n_pair;
+    // per pair (caller order): sizes, offsets in the packed buffers and in the caller's concatenation
+    std::vector<DimerDesc> dd(P);
+    for (const PairDesc& pd : R->pairs) {
+        DimerDesc d{};
+        d.x = pd.x;
+        d.y = pd.y;
+        d.cluster = pd.cluster;
+        dd[pd.orig] = d;
+    }
+    int64_t nw = 0, nq = 0, ncx = 0, ncy = 0, w_pack = 0, tau_el = 0, y_el = 0, cx_el = 0, cy_el = 0;
+    int max_rows = 16, max_o2 = 1, max_ring = 1;
+    double w_flops = 0.0;
+    for (int64_t p = 0; p < P; ++p) {
+        DimerDesc& d = dd[p];
+        const MonoDesc &mx = R->monos[d.x], &my = R->monos[d.y];
+        d.ox = mx.o;
+        d.vx = mx.v;
+        d.oy = my.o;
+        d.vy = my.v;
+        d.nx = mx.n;
+        d.ny = my.n;
+        d.npx = mx.np;
+        d.npy = my.np;
+        d.m1 = round_up(d.ox * d.vy, 16);
+        d.m2 = round_up(d.oy * d.vx, 16);
+        const int v2 = d.vx * d.vy, o2 = d.ox * d.oy;
+        d.w_rows = round_up(v2, 16);
+        d.ldw = round_up(v2, 32);
+        d.w_raw_off = nw;
+        d.q_off = nq;
+        d.cx_raw_off = ncx;
+        d.cy_raw_off = ncy;
+        d.w_off = w_pack;
+        d.tau_off = tau_el;
+        d.y1_off = d.y2_off = y_el;   // Y1 and Y2 sit in two buffers of the same layout size
+        d.cx_off = cx_el;
+        d.cy_off = cy_el;
+        nw += (int64_t)v2 * v2;
+        nq += (int64_t)o2 * o2;
+        ncx += (int64_t)d.ox * d.ox * d.vy * d.vy;
+        ncy += (int64_t)d.oy * d.oy * d.vx * d.vx;
+        w_pack += (int64_t)d.w_rows * d.ldw;
+        tau_el += (int64_t)d.npx * d.npy;
+        y_el += (int64_t)d.m1 * d.m2;
+        cx_el += (int64_t)d.m1 * d.m1;
+        cy_el += (int64_t)d.m2 * d.m2;
+        max_rows = std::max(max_rows, d.w_rows);
+        max_o2 = std::max(max_o2, o2);
+        max_ring = std::max(max_ring, dimer_ring_tasks(d));
+        w_flops += 2.0 * o2 * (double)v2 * v2;
+    }
+    // the LDS-staged ladder for one-size problems whose pairs fit it (the pair is its own "monomer")
+    const int np = m0.np, n = m0.n;
+    int64_t lds = 0;
+    if (one_size) {
+        lds = lccd_ladder_lds_bytes(n, m0.v, round_up(m0.v * m0.v, 32));
+        if (lds > lccd_lds_limit() || lccd_ladder_ct(m0.o) > 3) lds = 0;
+    }
     if (!in->w_vvvv || !in->q_oooo || !in->c_x || !in->c_y) return fail(MCPT_ERR_INVALID, "an integral array is NULL");
     const bool host = in->memory == MCPT_HOST;
     if (host) {
@@ -1182,46 +1238,41 @@ mcpt_status dimer_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_dimer_int
                 if (!std::isfinite(p[e])) return false;
             return true;
         };
-        if (!finite(in->w_vvvv, nw) || !finite(in->q_oooo, nq) || !finite(in->c_x, nc) || !finite(in->c_y, nc))
+        if (!finite(in->w_vvvv, nw) || !finite(in->q_oooo, nq) || !finite(in->c_x, ncx) || !finite(in->c_y, ncy))
             return fail(MCPT_ERR_NONFINITE, "dimer integrals have a non-finite value");
     } else {
         *x.h_flag = 0;
         HIP_TRY(hipMemcpyAsync(x.d_flag, x.h_flag, sizeof(int32_t), hipMemcpyHostToDevice, s));
         launch_nonfinite(in->w_vvvv, nw, x.d_flag, s);
         launch_nonfinite(in->q_oooo, nq, x.d_flag, s);
-        launch_nonfinite(in->c_x, nc, x.d_flag, s);
-        launch_nonfinite(in->c_y, nc, x.d_flag, s);
+        launch_nonfinite(in->c_x, ncx, x.d_flag, s);
+        launch_nonfinite(in->c_y, ncy, x.d_flag, s);
         HIP_TRY(hipMemcpyAsync(x.h_flag, x.d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (*x.h_flag) return fail(MCPT_ERR_NONFINITE, "dimer integrals have a non-finite value");
     }
-    // per pair (caller order): a monomer-like descriptor for the ladder and pack kernels
-    std::vector<int64_t> cl_of(P, 0);
-    std::vector<DimerDesc> dd(P);
-    for (const PairDesc& pd : R->pairs) {
-        dd[pd.orig] = DimerDesc{pd.x, pd.y};
-        cl_of[pd.orig] = pd.cluster;
-    }
-    std::vector<MonoDesc> pm(P);
-    std::vector<LccdDesc> pl(P);
-    for (int64_t p = 0; p < P; ++p) {
+    // the LDS-staged ladder takes monomer-like descriptors of the pairs
+    std::vector<MonoDesc> pm(lds > 0 ? P : 0);
+    std::vector<LccdDesc> pl(lds > 0 ? P : 0);
+    for (int64_t p = 0; lds > 0 && p < P; ++p) {
         MonoDesc d{};
-        d.o = o;
-        d.v = v;
+        d.o = m0.o;
+        d.v = m0.v;
         d.n = n;
         d.np = np;
-        d.mat_off = p * mat;
-        d.raw_off = p * (int64_t)o * o * v2;
-        d.cluster = (int32_t)cl_of[p];
+        d.mat_off = dd[p].tau_off;
+        d.cluster = dd[p].cluster;
         pm[p] = d;
-        pl[p] = LccdDesc{p * rows * cols, p * v2 * v2, p * o * o * o * o, rows, cols};
+        pl[p] = LccdDesc{dd[p].w_off, dd[p].w_raw_off, dd[p].q_off, dd[p].w_rows, dd[p].ldw};
     }
     auto rnd = [](int64_t bytes) { return (size_t)((std::max<int64_t>(bytes, 1) + 255) / 256 * 256); };
-    const int64_t w_pack = P * rows * cols;
-    const size_t keep = rnd(8 * w_pack) + rnd(8 * nq) + 4 * rnd(8 * P * mat) + rnd(sizeof(DimerDesc) * P) +
-                        rnd(sizeof(MonoDesc) * P) + rnd(sizeof(LccdDesc) * P) + rnd(8 * R->mat_elems) +
-                        2 * rnd(8 * P * mat);
-    const size_t staging = host ? rnd(8 * std::max(nw, nc)) : 0;
+    const size_t sizes[12] = {rnd(8 * w_pack), rnd(8 * nq), rnd(8 * cx_el), rnd(8 * cy_el), rnd(8 * tau_el),
+                              rnd(8 * tau_el), rnd(sizeof(DimerDesc) * P), rnd(sizeof(MonoDesc) * pm.size()),
+                              rnd(sizeof(LccdDesc) * pl.size()), rnd(8 * R->mat_elems), rnd(8 * y_el),
+                              rnd(8 * y_el)};
+    size_t keep = 0;
+    for (size_t b : sizes) keep += b;
+    const size_t staging = host ? rnd(8 * std::max(nw, std::max(ncx, ncy))) : 0;
     {
         std::lock_guard<std::mutex> g(c->mu);
         if (c->in_use + (c->reserved - x.reserved) + keep + staging > c->budget)
@@ -1242,9 +1293,6 @@ mcpt_status dimer_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_dimer_int
         return MCPT_OK;
     };
     void* pv[12] = {};
-    const size_t sizes[12] = {rnd(8 * w_pack), rnd(8 * nq), rnd(8 * P * mat), rnd(8 * P * mat), rnd(8 * P * mat),
-                              rnd(8 * P * mat), rnd(sizeof(DimerDesc) * P), rnd(sizeof(MonoDesc) * P),
-                              rnd(sizeof(LccdDesc) * P), rnd(8 * R->mat_elems), rnd(8 * P * mat), rnd(8 * P * mat)};
     for (int k = 0; k < 12; ++k)
         if ((st = alloc(&pv[k], sizes[k])) != MCPT_OK) {
             free_dimer(c, R);
@@ -1268,14 +1316,14 @@ mcpt_status dimer_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_dimer_int
     };
     const hipMemcpyKind kind = host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     if (hipMemcpyAsync(R->d_dd, dd.data(), P * sizeof(DimerDesc), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(R->d_pmono, pm.data(), P * sizeof(MonoDesc), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(R->d_plccd, pl.data(), P * sizeof(LccdDesc), hipMemcpyHostToDevice, s) != hipSuccess ||
+        (lds > 0 && hipMemcpyAsync(R->d_pmono, pm.data(), P * sizeof(MonoDesc), hipMemcpyHostToDevice, s) != hipSuccess) ||
+        (lds > 0 && hipMemcpyAsync(R->d_plccd, pl.data(), P * sizeof(LccdDesc), hipMemcpyHostToDevice, s) != hipSuccess) ||
         hipMemcpyAsync(R->d_DQ, in->q_oooo, nq * sizeof(double), kind, s) != hipSuccess)
         return fail_free(fail(MCPT_ERR_DEVICE, "copy of dimer integrals failed"));
-    launch_fill(R->d_Tau, P * mat, 0.0, s);
-    launch_fill(R->d_S, P * mat, 0.0, s);
-    launch_fill(R->d_DY1, P * mat, 0.0, s);
-    launch_fill(R->d_DY2, P * mat, 0.0, s);
+    launch_fill(R->d_Tau, tau_el, 0.0, s);
+    launch_fill(R->d_S, tau_el, 0.0, s);
+    launch_fill(R->d_DY1, y_el, 0.0, s);
+    launch_fill(R->d_DY2, y_el, 0.0, s);
     launch_ring_matrix(R->d_K, R->d_J, R->d_DRM, R->mat_elems, s);
     const int pn = (int)P;
     if (host) {
@@ -1287,27 +1335,27 @@ mcpt_status dimer_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_dimer_int
         }
         double* sd = static_cast<double*>(stage);
         hipError_t e = hipMemcpyAsync(stage, in->w_vvvv, nw * sizeof(double), hipMemcpyHostToDevice, s);
-        launch_lccd_pack(R->d_pmono, R->d_plccd, pn, sd, nullptr, R->d_DW, nullptr, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(stage, in->c_x, nc * sizeof(double), hipMemcpyHostToDevice, s);
-        launch_lccd_pack(R->d_pmono, R->d_plccd, pn, nullptr, sd, nullptr, R->d_DCX, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(stage, in->c_y, nc * sizeof(double), hipMemcpyHostToDevice, s);
-        launch_lccd_pack(R->d_pmono, R->d_plccd, pn, nullptr, sd, nullptr, R->d_DCY, s);
+        launch_dimer_pack(R->d_dd, pn, sd, nullptr, nullptr, R->d_DW, nullptr, nullptr, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(stage, in->c_x, ncx * sizeof(double), hipMemcpyHostToDevice, s);
+        launch_dimer_pack(R->d_dd, pn, nullptr, sd, nullptr, nullptr, R->d_DCX, nullptr, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(stage, in->c_y, ncy * sizeof(double), hipMemcpyHostToDevice, s);
+        launch_dimer_pack(R->d_dd, pn, nullptr, nullptr, sd, nullptr, nullptr, R->d_DCY, s);
         const hipError_t e2 = hipStreamSynchronize(s);
         (void)hipFree(stage);
         if (e != hipSuccess || e2 != hipSuccess) return fail_free(fail(MCPT_ERR_DEVICE, "upload of dimer integrals failed"));
     } else {
-        launch_lccd_pack(R->d_pmono, R->d_plccd, pn, in->w_vvvv, in->c_x, R->d_DW, R->d_DCX, s);
-        launch_lccd_pack(R->d_pmono, R->d_plccd, pn, nullptr, in->c_y, nullptr, R->d_DCY, s);
+        launch_dimer_pack(R->d_dd, pn, in->w_vvvv, in->c_x, in->c_y, R->d_DW, R->d_DCX, R->d_DCY, s);
     }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
         return fail_free(fail(MCPT_ERR_DEVICE, "packing of dimer integrals failed"));
-    R->dimer_mat = mat;
-    R->dimer_ct = ct;
+    R->dimer_desc = std::move(dd);
+    R->dimer_tau_elems = tau_el;
     R->dimer_lds_bytes = lds;
-    R->dimer_ladder_blocks = lds > 0 ? 1 : lccd_ladder_blocks(rows, o);
-    R->dimer_ring_blocks = dimer_ring_blocks(np);
+    R->dimer_ct = lds > 0 ? lccd_ladder_ct(m0.o) : dimer_ladder_ct(max_o2);
+    R->dimer_ladder_blocks = lds > 0 ? 1 : dimer_ladder_blocks(max_rows, max_o2);
+    R->dimer_ring_blocks = dimer_ring_blocks(max_ring);
     R->dimer_w_bytes = 8.0 * (double)w_pack;
-    R->dimer_w_flops = 2.0 * (double)P * o * o * (double)v2 * v2;
+    R->dimer_w_flops = w_flops;
     R->dimer = true;
     return MCPT_OK;
 }
@@ -1570,7 +1618,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
         return MCPT_OK;
     };
     if ((st = reset_state()) != MCPT_OK) return st;
-    if (R->dimer) launch_fill(R->d_Tau, R->n_pair * R->dimer_mat, 0.0, s);   // Tau before the first sweep
+    if (R->dimer) launch_fill(R->d_Tau, R->dimer_tau_elems, 0.0, s);   // Tau before the first sweep
     launch_fill(R->d_G[0], R->mat_elems, 0.0, s);
     launch_fill(R->d_G[1], R->mat_elems, 0.0, s);
     // intramonomer terms of the full monomer equation, L = P + H + R + R^T from the current T and M
@@ -2185,16 +2233,18 @@ mcpt_status mcpt_dimer_tau(mcpt_ctx* c, uint64_t id, double* tau) {
     if (!R->dimer) return fail(MCPT_ERR_INVALID, "problem has no dimer-internal terms attached");
     if (!R->has_result) return fail(MCPT_ERR_INVALID, "problem has no result (not run, or diverged)");
     HIP_TRY(hipSetDevice(c->device));
-    const int n = R->monos[0].n, np = R->monos[0].np;   // one monomer size with the dimer terms
-    const int64_t P = R->n_pair, mat = R->dimer_mat;
-    std::vector<double> h((size_t)(P * mat));
-    if (P > 0) HIP_TRY(hipMemcpyAsync(h.data(), R->d_Tau, P * mat * sizeof(double), hipMemcpyDeviceToHost,
-                                      c->main.stream));
+    std::vector<double> h((size_t)R->dimer_tau_elems);
+    if (R->dimer_tau_elems > 0)
+        HIP_TRY(hipMemcpyAsync(h.data(), R->d_Tau, R->dimer_tau_elems * sizeof(double), hipMemcpyDeviceToHost,
+                               c->main.stream));
     HIP_TRY(hipStreamSynchronize(c->main.stream));
-    // pair p (caller order) is stored np x np at p * mat, row (i,a) = i v + a, column (j,b) = j v + b
-    for (int64_t p = 0; p < P; ++p)
-        for (int r = 0; r < n; ++r)
-            std::memcpy(tau + (p * n + r) * n, h.data() + p * mat + (int64_t)r * np, n * sizeof(double));
+    // pair p (caller order) is stored npx x npy at its tau_off, row (i,a) = i vx + a, column (j,b) = j vy + b
+    int64_t out = 0;
+    for (const DimerDesc& d : R->dimer_desc) {
+        for (int r = 0; r < d.nx; ++r)
+            std::memcpy(tau + out + (int64_t)r * d.ny, h.data() + d.tau_off + (int64_t)r * d.npy, d.ny * sizeof(double));
+        out += (int64_t)d.nx * d.ny;
+    }
     return MCPT_OK;
 }
 

@@ -209,9 +209,12 @@ struct LadderView {
     const double* Y;
     double* L;
     const int* kofs;     // W column k = (c,d) -> T offset c ldt + d
-    const int* hofs;     // hole pair kk = (k,l) -> T offset k v ldt + l v
+    const int* hofs;     // hole pair kk = (k,l) -> T offset k vx ldt + l vy
     int ldw, w_rows, np, o, v, o2, v2;
     int ldt;             // row stride of T: np in global memory, n when staged in LDS
+    // the two sides of the amplitudes (rows (i,a): i < o, a < vx; columns (j,b): j < oy, b < vy):
+    // a monomer's, o = oy and v = vx = vy; a pair's, X and Y; ldl is the row stride of L
+    int oy, vx, vy, ldl;
 };
 
 // One wave task: kLadRT row tiles (rows m = (a,b) of W) x CT column tiles
@@ -226,14 +229,14 @@ __device__ void ladder_task(const LadderView& g, int tr0, int tc0, int lane) {
     for (int u = 0; u < RT; ++u) {
         const int m = (tr0 + u) * 16 + lr;
         arow[u] = m < g.w_rows ? m : 0;
-        const int a = m / g.v, b = m - a * g.v;
+        const int a = m / g.vy, b = m - a * g.vy;
         hrow[u] = m < g.v2 ? a * g.ldt + b : 0;
     }
 #pragma unroll
     for (int w = 0; w < CT; ++w) {
         const int n = (tc0 + w) * 16 + lr;
-        const int i = n / g.o, j = n - i * g.o;
-        bbase[w] = n < g.o2 ? i * g.v * g.ldt + j * g.v : 0;
+        const int i = n / g.oy, j = n - i * g.oy;
+        bbase[w] = n < g.o2 ? i * g.vx * g.ldt + j * g.vy : 0;
         ncol[w] = n;
     }
     d4 acc[RT][CT];
@@ -316,21 +319,21 @@ __device__ void ladder_task(const LadderView& g, int tr0, int tc0, int lane) {
     for (int w = 0; w < CT; ++w) {
         const int n = ncol[w];
         if (n >= g.o2) continue;
-        const int i = n / g.o, j = n - i * g.o;
+        const int i = n / g.oy, j = n - i * g.oy;
 #pragma unroll
         for (int u = 0; u < RT; ++u)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int m = (tr0 + u) * 16 + acc_row(lane, t);
                 if (m >= g.v2) continue;
-                const int a = m / g.v, b = m - a * g.v;
-                const int r = i * g.v + a, c = j * g.v + b;
+                const int a = m / g.vy, b = m - a * g.vy;
+                const int r = i * g.vx + a, c = j * g.vy + b;
                 if (WITH_R) {
                     const double rr = g.R12[(int64_t)r * g.np + c] - g.Y[(int64_t)(i * g.v + b) * g.np + j * g.v + a];
                     const double rt = g.R12[(int64_t)c * g.np + r] - g.Y[(int64_t)(j * g.v + a) * g.np + i * g.v + b];
                     g.L[(int64_t)r * g.np + c] = (acc[u][w][t] + rr) + rt;
                 } else {
-                    g.L[(int64_t)r * g.np + c] = acc[u][w][t];
+                    g.L[(int64_t)r * g.ldl + c] = acc[u][w][t];
                 }
             }
     }
@@ -421,7 +424,8 @@ __global__ __launch_bounds__(kLccdThreads, 2) void lccd_ladder_kernel(
     }
     __syncthreads();
     LadderView g{W + l.w_off, Q + l.q_off, T + d.mat_off, rings ? R12 + d.mat_off : nullptr,
-                 rings ? Y + d.mat_off : nullptr, L + d.mat_off, kofs, hofs, l.ldw, l.w_rows, np, o, v, o2, v2, np};
+                 rings ? Y + d.mat_off : nullptr, L + d.mat_off, kofs, hofs, l.ldw, l.w_rows, np, o, v, o2, v2, np,
+                 o, v, v, np};
     const int nrt = l.w_rows / 16;
     const int ntask_r = (nrt + kLadRT - 1) / kLadRT;
     const int nct = (o2 + 15) / 16;
@@ -483,8 +487,8 @@ __global__ __launch_bounds__(kLadLdsThreads) void lccd_ladder_lds_kernel(
         hofs[k] = k < o2 ? kk * v * n + ll * v : 0;
     }
     __syncthreads();
-    LadderView g{W + l.w_off, Q + l.q_off, sT, R12 + d.mat_off, Y + d.mat_off, L + d.mat_off,
-                 kofs, hofs, l.ldw, l.w_rows, np, o, v, o2, v2, n};
+    LadderView g{W + l.w_off, Q + l.q_off, sT, rings ? R12 + d.mat_off : nullptr, rings ? Y + d.mat_off : nullptr,
+                 L + d.mat_off, kofs, hofs, l.ldw, l.w_rows, np, o, v, o2, v2, n, o, v, v, np};
     constexpr int RT = 2;
     const int nrt = l.w_rows / 16;
     const int ntask_r = (nrt + RT - 1) / RT;
@@ -503,23 +507,24 @@ __global__ __launch_bounds__(kLadLdsThreads) void lccd_ladder_lds_kernel(
 // ---------------------------------------------------------------------------
 // ring terms of the dimer equation (Eq. 59)
 // ---------------------------------------------------------------------------
-// One product of a ring task into acc: A rows (k-contiguous, 32-byte loads) times B, where BM
-// selects B[k][c] = B[k np + c] (0), B[c np + k] (1, k-contiguous), or the Vs gather
-// B[kofs[k] + ycol[c]] (2).  The next k chunk's operands are in flight while the current one
-// is multiplied; the load past the last chunk repeats it instead of being branched around.
+// One product of a ring task into acc: A rows (k-contiguous, 32-byte loads, row stride lda) times B
+// over k < K (a multiple of 16), where BM selects B[k][c] = B[k ldb + c] (0), B[c ldb + k] (1,
+// k-contiguous), or the Vs gather B[kofs[k] + ycol[c]] (2).  The next k chunk's operands are in
+// flight while the current one is multiplied; the load past the last chunk repeats it instead of
+// being branched around.
 template <int BM>
 __device__ inline void ring_product(d4 (&acc)[kRingSB][kRingSB], const double* A, const double* B, const int* kofs,
                                     const int (&arow)[kRingSB], const int (&bcol)[kRingSB],
-                                    const int (&ycol)[kRingSB], int np, int lk) {
+                                    const int (&ycol)[kRingSB], int lda, int ldb, int K, int lk) {
     d4 an[kRingSB];
     double bn[kRingSB][4];
     auto load_chunk = [&](int k0) {
 #pragma unroll
-        for (int u = 0; u < kRingSB; ++u) an[u] = load4(A + (int64_t)arow[u] * np + k0 + lk);
+        for (int u = 0; u < kRingSB; ++u) an[u] = load4(A + (int64_t)arow[u] * lda + k0 + lk);
 #pragma unroll
         for (int w = 0; w < kRingSB; ++w) {
             if (BM == 1) {
-                const d4 t = load4(B + (int64_t)bcol[w] * np + k0 + lk);
+                const d4 t = load4(B + (int64_t)bcol[w] * ldb + k0 + lk);
                 bn[w][0] = t.x;
                 bn[w][1] = t.y;
                 bn[w][2] = t.z;
@@ -528,13 +533,13 @@ __device__ inline void ring_product(d4 (&acc)[kRingSB][kRingSB], const double* A
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const int k = k0 + lk + s;
-                    bn[w][s] = BM == 0 ? B[(int64_t)k * np + bcol[w]] : B[kofs[k] + ycol[w]];
+                    bn[w][s] = BM == 0 ? B[(int64_t)k * ldb + bcol[w]] : B[kofs[k] + ycol[w]];
                 }
             }
         }
     };
     load_chunk(0);
-    for (int k0 = 0; k0 < np; k0 += 16) {
+    for (int k0 = 0; k0 < K; k0 += 16) {
         double a[kRingSB][4], b[kRingSB][4];
 #pragma unroll
         for (int u = 0; u < kRingSB; ++u) {
@@ -547,7 +552,7 @@ __device__ inline void ring_product(d4 (&acc)[kRingSB][kRingSB], const double* A
         for (int w = 0; w < kRingSB; ++w)
 #pragma unroll
             for (int s = 0; s < 4; ++s) b[w][s] = bn[w][s];
-        load_chunk(k0 + 16 < np ? k0 + 16 : k0);
+        load_chunk(k0 + 16 < K ? k0 + 16 : k0);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -557,57 +562,74 @@ __device__ inline void ring_product(d4 (&acc)[kRingSB][kRingSB], const double* A
     }
 }
 
-// For a pair with amplitudes Tau (np x np, rows (i,a) of X, columns (j,b) of Y)
-// the monomer rings are (2 K_X - J_X) Tau + Tau (2 K_Y - J_Y)^T, two products
-// into one accumulator added in place into the pair's source S (which holds the
-// two ladders, stored before this launch; every element of S has one owner
-// task); the cross rings are Y1 = C_X Vs(Tau) and Y2 = C_Y Vs(Tau^T), stored
-// as they come out, and the pair kernel subtracts Y1[(i,b),(j,a)] and
+// For a pair with amplitudes Tau (npx x npy, rows (i,a) of X, columns (j,b) of Y) the
+// monomer rings are (2 K_X - J_X) Tau + Tau (2 K_Y - J_Y)^T, two products into one
+// accumulator added in place into the pair's source S (which holds the two ladders, stored
+// before this launch; every element of S has one owner task); the cross rings are
+// Y1 = C_X-hat Vs(Tau) (rows (i,b), columns (j,a)) and Y2 = C_Y-hat Vs(Tau^T) (rows (j,a),
+// columns (i,b)), stored as they come out, and the pair kernel subtracts Y1[(i,b),(j,a)] and
 // Y2[(j,a),(i,b)] when it forms Tau.  K-hat[(i,a),(i1,a1)] = K[i,i1,a,a1] and
-// J-hat[(i,a),(i1,a1)] = J[i1,i,a,a1] of the monomer (2 K-hat - J-hat formed once
-// per monomer at attach), C-hat packed from the pair's class the way J-hat is,
-// Vs the swap of the two virtual indices.  All blocks of a pair run on one XCD.
+// J-hat[(i,a),(i1,a1)] = J[i1,i,a,a1] of the monomer (2 K-hat - J-hat formed once per monomer
+// at attach), C_X-hat[(i,b),(i1,b1)] = C_X[i1][i][b][b1], C_Y-hat[(j,a),(j1,a1)] =
+// C_Y[j1][j][a][a1], Vs the swap of the two virtual indices.  Tasks are 3 x 3 super-blocks of
+// 16 x 16 tiles of the three outputs; all blocks of a pair run on one XCD.
+__host__ __device__ inline int ring_nsb(int rows) { return (rows / 16 + kRingSB - 1) / kRingSB; }
+
 __global__ __launch_bounds__(kLccdThreads, 2) void dimer_ring_kernel(
-    const DimerDesc* __restrict__ dd, const MonoDesc* __restrict__ monos, const MonoDesc* __restrict__ pseudo,
-    int n_pair, int blocks_per_pair, const double* __restrict__ RM, const double* __restrict__ CX,
-    const double* __restrict__ CY, const double* __restrict__ Tau, double* __restrict__ S, double* __restrict__ Y1,
-    double* __restrict__ Y2, const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
+    const DimerDesc* __restrict__ dd, const MonoDesc* __restrict__ monos, int n_pair, int blocks_per_pair,
+    const double* __restrict__ RM, const double* __restrict__ CX, const double* __restrict__ CY,
+    const double* __restrict__ Tau, double* __restrict__ S, double* __restrict__ Y1, double* __restrict__ Y2,
+    const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
     if (ctrl && ctrl->done) return;
     const int q = blockIdx.x / kXcds;
     const int part = q % blocks_per_pair;
     const int p = (q / blocks_per_pair) * kXcds + (int)(blockIdx.x % kXcds);
     if (p >= n_pair) return;
-    const MonoDesc d = pseudo[p];
-    if (cl && cl[d.cluster].done) return;
     const DimerDesc e = dd[p];
+    if (cl && cl[e.cluster].done) return;
     __shared__ int kofs[2][kLccdMaxNp];   // Vs gathers: row k of Vs(Tau) / Vs(Tau^T)
-    const int np = d.np, n = d.n, v = d.v;
-    for (int k = threadIdx.x; k < np; k += kLccdThreads) {
-        const int i2 = k / v, a2 = k - i2 * v;
-        kofs[0][k] = k < n ? i2 * v * np + a2 : 0;
-        kofs[1][k] = k < n ? a2 * np + i2 * v : 0;
+    const int npx = e.npx, npy = e.npy, vx = e.vx, vy = e.vy;
+    const int n1 = e.ox * vy, n2 = e.oy * vx;   // rows (i,b) of Y1, rows (j,a) of Y2
+    for (int k = threadIdx.x; k < e.m1; k += kLccdThreads) {   // Vs(Tau) row (i1,b1)
+        const int i1 = k / vy, b1 = k - i1 * vy;
+        kofs[0][k] = k < n1 ? i1 * vx * npy + b1 : 0;
+    }
+    for (int k = threadIdx.x; k < e.m2; k += kLccdThreads) {   // Vs(Tau^T) row (j1,a1)
+        const int j1 = k / vx, a1 = k - j1 * vx;
+        kofs[1][k] = k < n2 ? a1 * npy + j1 * vy : 0;
     }
     __syncthreads();
-    const double* Tp = Tau + d.mat_off;
+    const double* Tp = Tau + e.tau_off;
     const double* RX = RM + monos[e.x].mat_off;
     const double* RY = RM + monos[e.y].mat_off;
-    const int nt = np / 16;
-    const int nsb = (nt + kRingSB - 1) / kRingSB;
-    const int tasks = 3 * nsb * nsb;
+    const int s0c = ring_nsb(npy), s1c = ring_nsb(e.m2), s2c = ring_nsb(e.m1);
+    const int t0 = ring_nsb(npx) * s0c, t1 = ring_nsb(e.m1) * s1c, t2 = ring_nsb(e.m2) * s2c;
+    const int tasks = t0 + t1 + t2;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = (lane >> 4) * 4;
     for (int task = part * (kLccdThreads / 64) + wave; task < tasks; task += blocks_per_pair * (kLccdThreads / 64)) {
-        const int kind = task / (nsb * nsb);      // 0: monomer rings, 1: C_X Vs(Tau), 2: C_Y Vs(Tau^T)
-        const int sb = task - kind * nsb * nsb;
-        const int tr0 = (sb / nsb) * kRingSB, tc0 = (sb % nsb) * kRingSB;
+        // kind 0: monomer rings into S; 1: C_X-hat Vs(Tau) into Y1; 2: C_Y-hat Vs(Tau^T) into Y2
+        const int kind = task < t0 ? 0 : task < t0 + t1 ? 1 : 2;
+        const int sb = task - (kind == 0 ? 0 : kind == 1 ? t0 : t0 + t1);
+        const int nsc = kind == 0 ? s0c : kind == 1 ? s1c : s2c;
+        const int tr0 = (sb / nsc) * kRingSB, tc0 = (sb % nsc) * kRingSB;
+        const int rows = kind == 0 ? npx : kind == 1 ? e.m1 : e.m2;     // padded extents of the output
+        const int cols = kind == 0 ? npy : kind == 1 ? e.m2 : e.m1;
+        const int nr = kind == 0 ? e.nx : kind == 1 ? n1 : n2;           // valid extents
+        const int nc = kind == 0 ? e.ny : kind == 1 ? n2 : n1;
         int arow[kRingSB], bcol[kRingSB], ycol[kRingSB];
 #pragma unroll
         for (int u = 0; u < kRingSB; ++u) {
             const int r = (tr0 + u) * 16 + lr, c = (tc0 + u) * 16 + lr;
-            arow[u] = r < np ? r : 0;
-            bcol[u] = c < np ? c : 0;
-            const int i1 = c / v, a = c - i1 * v;
-            ycol[u] = c < n ? (kind == 2 ? i1 * v * np + a : a * np + i1 * v) : 0;
+            arow[u] = r < rows ? r : 0;
+            bcol[u] = c < cols ? c : 0;
+            if (kind == 1) {   // Vs(Tau) column (j,a)
+                const int j = c / vx, a = c - j * vx;
+                ycol[u] = c < n2 ? a * npy + j * vy : 0;
+            } else {           // Vs(Tau^T) column (i,b)
+                const int i = c / vy, b = c - i * vy;
+                ycol[u] = c < n1 ? i * vx * npy + b : 0;
+            }
         }
         d4 acc[kRingSB][kRingSB];
 #pragma unroll
@@ -615,12 +637,14 @@ __global__ __launch_bounds__(kLccdThreads, 2) void dimer_ring_kernel(
 #pragma unroll
             for (int w = 0; w < kRingSB; ++w) acc[u][w] = d4(0.0);
         if (kind == 0) {   // (2K - J)_X Tau + Tau (2K - J)_Y^T on one accumulator
-            ring_product<0>(acc, RX, Tp, nullptr, arow, bcol, ycol, np, lk);
-            ring_product<1>(acc, Tp, RY, nullptr, arow, bcol, ycol, np, lk);
+            ring_product<0>(acc, RX, Tp, nullptr, arow, bcol, ycol, npx, npy, npx, lk);
+            ring_product<1>(acc, Tp, RY, nullptr, arow, bcol, ycol, npy, npy, npy, lk);
+        } else if (kind == 1) {
+            ring_product<2>(acc, CX + e.cx_off, Tp, kofs[0], arow, bcol, ycol, e.m1, 0, e.m1, lk);
         } else {
-            ring_product<2>(acc, (kind == 2 ? CY : CX) + d.mat_off, Tp, kofs[kind - 1], arow, bcol, ycol, np, lk);
+            ring_product<2>(acc, CY + e.cy_off, Tp, kofs[1], arow, bcol, ycol, e.m2, 0, e.m2, lk);
         }
-        double* out = (kind == 0 ? S : kind == 1 ? Y1 : Y2) + d.mat_off;
+        double* out = kind == 0 ? S + e.tau_off : kind == 1 ? Y1 + e.y1_off : Y2 + e.y2_off;
 #pragma unroll
         for (int u = 0; u < kRingSB; ++u)
 #pragma unroll
@@ -629,11 +653,88 @@ __global__ __launch_bounds__(kLccdThreads, 2) void dimer_ring_kernel(
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int r = (tr0 + u) * 16 + acc_row(lane, t);
-                    if (r >= n || c >= n) continue;
-                    if (kind == 0) out[(int64_t)r * np + c] += acc[u][w][t];
-                    else out[(int64_t)r * np + c] = acc[u][w][t];
+                    if (r >= nr || c >= nc) continue;
+                    if (kind == 0) out[(int64_t)r * cols + c] += acc[u][w][t];
+                    else out[(int64_t)r * cols + c] = acc[u][w][t];
                 }
             }
+    }
+}
+
+// The pair ladders from global memory for pairs of any two monomer sizes: the monomer
+// ladder task on a pair's Tau (rows (i,a) of X, columns (j,b) of Y, row stride npy) with
+// its W_XY (rows (a,b), columns (a1,b1)) and Q_XY (rows (i1,j1), columns (i,j)); S = P + H.
+template <int CT>
+__global__ __launch_bounds__(kLccdThreads, 2) void dimer_ladder_kernel(
+    const DimerDesc* __restrict__ dd, int n_pair, int blocks_per_pair, const double* __restrict__ W,
+    const double* __restrict__ Q, const double* __restrict__ Tau, double* __restrict__ S,
+    const Ctrl* __restrict__ ctrl, const ClState* __restrict__ cl) {
+    if (ctrl && ctrl->done) return;
+    const int q = blockIdx.x / kXcds;
+    const int part = q % blocks_per_pair;
+    const int p = (q / blocks_per_pair) * kXcds + (int)(blockIdx.x % kXcds);
+    if (p >= n_pair) return;
+    const DimerDesc e = dd[p];
+    if (cl && cl[e.cluster].done) return;
+    __shared__ int kofs[kLccdMaxLdw];
+    __shared__ int hofs[64];
+    const int vx = e.vx, vy = e.vy, oy = e.oy, v2 = vx * vy, o2 = e.ox * oy, ldt = e.npy;
+    for (int k = threadIdx.x; k < e.ldw; k += kLccdThreads) {   // W column (a1,b1)
+        const int c = k / vy, d = k - c * vy;
+        kofs[k] = k < v2 ? c * ldt + d : 0;
+    }
+    for (int k = threadIdx.x; k < 64; k += kLccdThreads) {       // hole pair (k,l)
+        const int kk = k / oy, ll = k - kk * oy;
+        hofs[k] = k < o2 ? kk * vx * ldt + ll * vy : 0;
+    }
+    __syncthreads();
+    LadderView g{W + e.w_off, Q + e.q_off, Tau + e.tau_off, nullptr, nullptr, S + e.tau_off, kofs, hofs, e.ldw,
+                 e.w_rows, e.npx, e.ox, vx, o2, v2, ldt, oy, vx, vy, ldt};
+    const int nrt = e.w_rows / 16;
+    const int ntask_r = (nrt + kLadRT - 1) / kLadRT;
+    const int nct = (o2 + 15) / 16;
+    const int ngroups = (nct + CT - 1) / CT;
+    const int tasks = ntask_r * ngroups;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int task = part * (kLccdThreads / 64) + wave; task < tasks; task += blocks_per_pair * (kLccdThreads / 64))
+        ladder_task<kLadRT, CT, 2, false>(g, (task / ngroups) * kLadRT, (task % ngroups) * CT, lane);
+}
+
+// W_XY, C_X-hat and C_Y-hat of every pair from the caller's concatenated classes
+__global__ void dimer_pack_kernel(const DimerDesc* __restrict__ dd, const double* __restrict__ w_raw,
+                                  const double* __restrict__ cx_raw, const double* __restrict__ cy_raw,
+                                  double* __restrict__ W, double* __restrict__ CX, double* __restrict__ CY) {
+    const DimerDesc e = dd[blockIdx.y];
+    const int64_t step = (int64_t)gridDim.x * blockDim.x, first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v2 = e.vx * e.vy;
+    if (w_raw)
+        for (int64_t k = first; k < (int64_t)e.w_rows * e.ldw; k += step) {
+            const int r = (int)(k / e.ldw), c = (int)(k - (int64_t)r * e.ldw);
+            W[e.w_off + k] = (r < v2 && c < v2) ? w_raw[e.w_raw_off + (int64_t)r * v2 + c] : 0.0;
+        }
+    if (cx_raw) {   // C_X-hat[(i,b),(i1,b1)] = C_X[i1][i][b][b1], rows and columns over (ox, vy)
+        const int n1 = e.ox * e.vy;
+        for (int64_t k = first; k < (int64_t)e.m1 * e.m1; k += step) {
+            const int r = (int)(k / e.m1), c = (int)(k - (int64_t)r * e.m1);
+            double val = 0.0;
+            if (r < n1 && c < n1) {
+                const int i = r / e.vy, b = r - i * e.vy, i1 = c / e.vy, b1 = c - i1 * e.vy;
+                val = cx_raw[e.cx_raw_off + (((int64_t)i1 * e.ox + i) * e.vy + b) * e.vy + b1];
+            }
+            CX[e.cx_off + k] = val;
+        }
+    }
+    if (cy_raw) {   // C_Y-hat[(j,a),(j1,a1)] = C_Y[j1][j][a][a1], rows and columns over (oy, vx)
+        const int n2 = e.oy * e.vx;
+        for (int64_t k = first; k < (int64_t)e.m2 * e.m2; k += step) {
+            const int r = (int)(k / e.m2), c = (int)(k - (int64_t)r * e.m2);
+            double val = 0.0;
+            if (r < n2 && c < n2) {
+                const int j = r / e.vx, a = r - j * e.vx, j1 = c / e.vx, a1 = c - j1 * e.vx;
+                val = cy_raw[e.cy_raw_off + (((int64_t)j1 * e.oy + j) * e.vx + a) * e.vx + a1];
+            }
+            CY[e.cy_off + k] = val;
+        }
     }
 }
 
@@ -737,20 +838,67 @@ void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, i
     }
 }
 
-int dimer_ring_blocks(int np) {
-    const int nt = np / 16, nsb = (nt + kRingSB - 1) / kRingSB;
-    const int tasks = 3 * nsb * nsb, per_block = kLccdThreads / 64;
-    const int b = (tasks + per_block - 1) / per_block;
-    return b < 8 ? b : 8;
+int dimer_ring_tasks(const DimerDesc& d) {
+    return ring_nsb(d.npx) * ring_nsb(d.npy) + ring_nsb(d.m1) * ring_nsb(d.m2) + ring_nsb(d.m2) * ring_nsb(d.m1);
 }
 
-void launch_dimer_ring(const DimerDesc* dd, const MonoDesc* monos, const MonoDesc* pseudo, int n_pair, int blocks,
-                       const double* RM, const double* CX, const double* CY, const double* Tau, double* S,
-                       double* Y1, double* Y2, const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
+int dimer_ring_blocks(int max_tasks) {
+    const int per_block = kLccdThreads / 64;
+    const int b = (max_tasks + per_block - 1) / per_block;
+    return b < 64 ? (b > 0 ? b : 1) : 64;
+}
+
+void launch_dimer_ring(const DimerDesc* dd, const MonoDesc* monos, int n_pair, int blocks, const double* RM,
+                       const double* CX, const double* CY, const double* Tau, double* S, double* Y1, double* Y2,
+                       const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
     if (n_pair <= 0 || blocks <= 0) return;
-    const int groups = (n_pair + kXcds - 1) / kXcds;
-    hipLaunchKernelGGL(dimer_ring_kernel, dim3(groups * kXcds * blocks), dim3(kLccdThreads), 0, s, dd, monos, pseudo,
-                       n_pair, blocks, RM, CX, CY, Tau, S, Y1, Y2, ctrl, cl);
+    const dim3 grid(((n_pair + kXcds - 1) / kXcds) * kXcds * blocks), block(kLccdThreads);
+    hipLaunchKernelGGL(dimer_ring_kernel, grid, block, 0, s, dd, monos, n_pair, blocks, RM, CX, CY, Tau, S, Y1, Y2,
+                       ctrl, cl);
+}
+
+void launch_dimer_pack(const DimerDesc* dd, int n_pair, const double* w_raw, const double* cx_raw,
+                       const double* cy_raw, double* W, double* CX, double* CY, hipStream_t s) {
+    if (n_pair <= 0) return;
+    hipLaunchKernelGGL(dimer_pack_kernel, dim3(64, n_pair), dim3(256), 0, s, dd, w_raw, cx_raw, cy_raw, W, CX, CY);
+}
+
+int dimer_ladder_ct(int max_o2) {
+    const int nct = (max_o2 + 15) / 16;
+    return nct < kLadCT ? nct : kLadCT;
+}
+
+int dimer_ladder_blocks(int max_w_rows, int max_o2) {
+    const int nrt = max_w_rows / 16, ntr = (nrt + kLadRT - 1) / kLadRT;
+    const int nct = (max_o2 + 15) / 16, ct = dimer_ladder_ct(max_o2), ng = (nct + ct - 1) / ct;
+    const int tasks = ntr * ng, per_block = kLccdThreads / 64;
+    const int b = (tasks + per_block - 1) / per_block;
+    return b < 64 ? (b > 0 ? b : 1) : 64;
+}
+
+void launch_dimer_ladder(const DimerDesc* dd, int n_pair, int blocks_per_pair, int ct, const double* W,
+                         const double* Q, const double* Tau, double* S, const Ctrl* ctrl, const ClState* cl,
+                         hipStream_t s) {
+    if (n_pair <= 0 || blocks_per_pair <= 0) return;
+    const dim3 grid(((n_pair + kXcds - 1) / kXcds) * kXcds * blocks_per_pair), block(kLccdThreads);
+    switch (ct) {
+        case 1:
+            hipLaunchKernelGGL(dimer_ladder_kernel<1>, grid, block, 0, s, dd, n_pair, blocks_per_pair, W, Q, Tau, S,
+                               ctrl, cl);
+            break;
+        case 2:
+            hipLaunchKernelGGL(dimer_ladder_kernel<2>, grid, block, 0, s, dd, n_pair, blocks_per_pair, W, Q, Tau, S,
+                               ctrl, cl);
+            break;
+        case 3:
+            hipLaunchKernelGGL(dimer_ladder_kernel<3>, grid, block, 0, s, dd, n_pair, blocks_per_pair, W, Q, Tau, S,
+                               ctrl, cl);
+            break;
+        default:
+            hipLaunchKernelGGL(dimer_ladder_kernel<4>, grid, block, 0, s, dd, n_pair, blocks_per_pair, W, Q, Tau, S,
+                               ctrl, cl);
+            break;
+    }
 }
 
 void launch_ring_matrix(const double* K, const double* J, double* RM, int64_t n, hipStream_t s) {

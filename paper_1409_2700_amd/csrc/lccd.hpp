@@ -19,14 +19,6 @@ struct LccdDesc {
     int32_t ldw;         // v^2 rounded up to 32
 };
 
-// Per stored pair of the dimer-internal terms of Eq. 59: its two monomers.  The
-// pair's own n x n matrices (amplitudes, source, packed cross-ring classes) sit
-// at the mat_off of a per-pair MonoDesc, and its packed W_XY and Q_XY at the
-// offsets of a per-pair LccdDesc, so the monomer ladder kernel runs on pairs.
-struct DimerDesc {
-    int32_t x, y;
-};
-
 void launch_lccd_pack(const MonoDesc* monos, const LccdDesc* ld, int n_mono, const double* w_raw,
                       const double* j_raw, double* W, double* J, hipStream_t s);
 int lccd_ring_blocks(int max_np);
@@ -48,12 +40,27 @@ void launch_lccd_ladder(const MonoDesc* monos, const LccdDesc* ld, int n_mono, i
                         int rings = 1);
 
 // The ring terms of the dimer equation: the monomer rings added into S (which must hold the
-// ladders), the cross rings stored in Y1 and Y2 for the pair kernel
-int dimer_ring_blocks(int np);
+// ladders), the cross rings stored in Y1 and Y2 for the pair kernel.  dimer_ring_blocks: the
+// workgroups per pair for the pair of the most ring tasks.
+int dimer_ring_tasks(const DimerDesc& d);
+int dimer_ring_blocks(int max_tasks);
 // RM = 2 K - J of the monomers (n elements of the monomer matrix buffers)
 void launch_ring_matrix(const double* K, const double* J, double* RM, int64_t n, hipStream_t s);
-void launch_dimer_ring(const DimerDesc* dd, const MonoDesc* monos, const MonoDesc* pseudo, int n_pair, int blocks,
-                       const double* RM, const double* CX, const double* CY, const double* Tau, double* S,
-                       double* Y1, double* Y2, const Ctrl* ctrl, const ClState* cl, hipStream_t s);
+void launch_dimer_ring(const DimerDesc* dd, const MonoDesc* monos, int n_pair, int blocks, const double* RM,
+                       const double* CX, const double* CY, const double* Tau, double* S, double* Y1, double* Y2,
+                       const Ctrl* ctrl, const ClState* cl, hipStream_t s);
+// Pack the caller's dimer classes of every pair into the layouts of its DimerDesc: W_XY, C_X-hat
+// [(i,b),(i1,b1)] = C_X[i1][i][b][b1] and C_Y-hat[(j,a),(j1,a1)] = C_Y[j1][j][a][a1] (a null source
+// skips its part)
+void launch_dimer_pack(const DimerDesc* dd, int n_pair, const double* w_raw, const double* cx_raw,
+                       const double* cy_raw, double* W, double* CX, double* CY, hipStream_t s);
+// The pair ladders of every live pair from global memory: S = P + H (stored), for pairs of any
+// two monomer sizes; blocks_per_pair and ct as lccd_ladder_blocks / lccd_ladder_ct of the
+// largest w_rows and ox oy
+void launch_dimer_ladder(const DimerDesc* dd, int n_pair, int blocks_per_pair, int ct, const double* W,
+                         const double* Q, const double* Tau, double* S, const Ctrl* ctrl, const ClState* cl,
+                         hipStream_t s);
+int dimer_ladder_blocks(int max_w_rows, int max_o2);
+int dimer_ladder_ct(int max_o2);
 
 }  // namespace mcpt

@@ -40,18 +40,37 @@ __device__ inline double recip(double d) {
 // Deterministic accumulation: instead of adding its G_X and G_Y blocks to G
 // with atomics, pair p stores them at part + off[p] (np_X^2 values, then
 // np_Y^2), and a per-monomer kernel sums the stored blocks in pair order.
+// A stored pair of the dimer-internal terms of Eq. 59 (X = its first monomer): sizes and where
+// its matrices sit.  Tau and the source S are npx x npy (rows (i,a) = i vx + a, columns
+// (j,b) = j vy + b); the cross-ring classes C_X-hat (rows (i,b) = i vy + b) and C_Y-hat (rows
+// (j,a) = j vx + a) are m1 x m1 and m2 x m2, and their products Y1 = C_X-hat Vs(Tau) and
+// Y2 = C_Y-hat Vs(Tau^T) m1 x m2 and m2 x m1 (m1, m2 = ox vy and oy vx rounded up to 16);
+// W_XY is packed as w_rows x ldw (rows (a,b) = a vy + b padded to 16, columns to 32).
+struct DimerDesc {
+    int32_t x, y;
+    int32_t ox, vx, oy, vy;
+    int32_t nx, ny, npx, npy;
+    int32_t m1, m2;
+    int32_t w_rows, ldw;
+    int32_t cluster, pad;
+    int64_t tau_off;       // Tau and S
+    int64_t y1_off, y2_off;
+    int64_t cx_off, cy_off;
+    int64_t w_off, q_off;  // packed W_XY; Q_XY ((ox oy) x (ox oy), caller layout)
+    int64_t w_raw_off, cx_raw_off, cy_raw_off;   // the pair's classes in the caller's concatenation
+};
+
 struct PartOut {
     double* part;            // nullptr: FP64 atomics into G
     const int64_t* off;      // per pair of the launch
-    // dimer-internal terms (FP64 kernel only, every monomer with v virtuals): S - Y1[(i,b),(j,a)]
-    // - Y2[(j,a),(i,b)] adds into the numerator of Tau[(i,a),(j,b)] and Tau is kept in tau_out,
-    // all np x np at orig * mat_stride; nullptr: none of it
+    // dimer-internal terms (FP64 kernel only): S - Y1[(i,b),(j,a)] - Y2[(j,a),(i,b)] adds into
+    // the numerator of Tau[(i,a),(j,b)] and Tau is kept in tau_out, each at the offsets of the
+    // pair's DimerDesc (dd, indexed by the caller's pair index); nullptr: none of it
     const double* S = nullptr;
     const double* Y1 = nullptr;
     const double* Y2 = nullptr;
     double* tau_out = nullptr;
-    int64_t mat_stride = 0;
-    int v = 0;
+    const DimerDesc* dd = nullptr;
 };
 
 struct MonoDesc {

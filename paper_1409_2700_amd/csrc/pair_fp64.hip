@@ -478,10 +478,21 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
 
         // ---- Tau = D_XY * (V + M_X V + V M_Y^T), E_D2 = 4 <V, Tau> ----
         double epart = 0.0;
-        const double* Sp = DIMER ? po.S + pd.orig * po.mat_stride : nullptr;
-        const double* Y1p = DIMER ? po.Y1 + pd.orig * po.mat_stride : nullptr;
-        const double* Y2p = DIMER ? po.Y2 + pd.orig * po.mat_stride : nullptr;
-        double* Tp = DIMER ? po.tau_out + pd.orig * po.mat_stride : nullptr;
+        // the pair's dimer-internal source and Tau (sizes and offsets from its descriptor)
+        int dvx = 1, dvy = 1, dm1 = 0, dm2 = 0;
+        const double *Sp = nullptr, *Y1p = nullptr, *Y2p = nullptr;
+        double* Tp = nullptr;
+        if (DIMER) {
+            const DimerDesc& e = po.dd[pd.orig];
+            dvx = e.vx;
+            dvy = e.vy;
+            dm1 = e.m1;
+            dm2 = e.m2;
+            Sp = po.S + e.tau_off;
+            Y1p = po.Y1 + e.y1_off;
+            Y2p = po.Y2 + e.y2_off;
+            Tp = po.tau_out + e.tau_off;
+        }
         for_tasks(make_grid(RB, CB), make_grid(0, 0), wave, NW, [&](int, int r0, int c0, auto shape) {
             constexpr int NR = decltype(shape)::NR, NC = decltype(shape)::NC;
             d4 acc[NR][NC];
@@ -513,11 +524,11 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
                         const int rr = min((r0 + i) * 16 + acc_row(lane, t), p.nX - 1);
                         vv[i][t] = IN_LDS ? sV[rr * p.ldv + c] : p.V[(int64_t)rr * p.nY + cc];
                         if (DIMER) {   // rr = (ii,a), cc = (jj,b): the clamped element's indices
-                            const int ii = rr / po.v, a = rr - ii * po.v, jj = cc / po.v, b = cc - jj * po.v;
+                            const int ii = rr / dvx, a = rr - ii * dvx, jj = cc / dvy, b = cc - jj * dvy;
                             const int r = (r0 + i) * 16 + acc_row(lane, t);
                             dsrc[i][t] = Sp[(int64_t)r * p.npY + c] -
-                                         Y1p[(int64_t)(ii * po.v + b) * p.npY + jj * po.v + a] -
-                                         Y2p[(int64_t)(jj * po.v + a) * p.npY + ii * po.v + b];
+                                         Y1p[(int64_t)(ii * dvy + b) * dm2 + jj * dvx + a] -
+                                         Y2p[(int64_t)(jj * dvx + a) * dm1 + ii * dvy + b];
                         }
                     }
 #pragma unroll

@@ -99,7 +99,8 @@ struct Resident {
     double *d_DW = nullptr, *d_DQ = nullptr, *d_DCX = nullptr, *d_DCY = nullptr, *d_Tau = nullptr, *d_S = nullptr;
     double* d_DRM = nullptr;          // 2 K - J per monomer (the monomer rings of Eq. 59)
     double *d_DY1 = nullptr, *d_DY2 = nullptr;   // the cross-ring products of each pair
-    int64_t dimer_mat = 0;            // np^2: elements of one pair's matrix
+    std::vector<DimerDesc> dimer_desc;   // per pair (caller order): sizes and offsets
+    int64_t dimer_tau_elems = 0;         // elements of the Tau (and S) buffer
     int dimer_ring_blocks = 0, dimer_ct = 1, dimer_ladder_blocks = 1;
     int64_t dimer_lds_bytes = 0;
     double dimer_w_bytes = 0.0, dimer_w_flops = 0.0;

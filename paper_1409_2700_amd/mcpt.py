@@ -272,6 +272,7 @@ class Context:
         self.h = h
         self._sizes = {}
         self._clusters = {}
+        self._pairs = {}      # pair list (monomer indices) of each resident problem
 
     def close(self):
         if self.h:
@@ -298,6 +299,7 @@ class Context:
         pid = C.c_uint64()
         _check(lib().mcpt_upload(self.h, C.byref(hp.c), C.byref(pid)))
         self._sizes[pid.value] = (hp.n_occ.copy(), hp.n_vir.copy(), len(hp.pairs))
+        self._pairs[pid.value] = np.asarray(hp.pairs).reshape(-1, 2).copy()
         return pid.value
 
     def upload_batch(self, probs) -> int:
@@ -310,6 +312,9 @@ class Context:
         n_vir = np.concatenate([hp.n_vir for hp in hps])
         self._sizes[pid.value] = (n_occ, n_vir, int(sum(len(hp.pairs) for hp in hps)))
         self._clusters[pid.value] = [(len(hp.n_occ), len(hp.pairs)) for hp in hps]
+        offs = np.concatenate([[0], np.cumsum([len(hp.n_occ) for hp in hps])])
+        self._pairs[pid.value] = np.concatenate([np.asarray(hp.pairs).reshape(-1, 2) + offs[q]
+                                                 for q, hp in enumerate(hps)] or [np.zeros((0, 2), np.int32)])
         return pid.value
 
     def cluster_results(self, pid: int) -> list:
@@ -338,6 +343,7 @@ class Context:
         pid = C.c_uint64()
         _check(lib().mcpt_upload(self.h, C.byref(c), C.byref(pid)))
         self._sizes[pid.value] = (n_occ.copy(), n_vir.copy(), len(pairs))
+        self._pairs[pid.value] = pairs.copy()
         return pid.value
 
     def run(self, pid: int, raise_on_error: bool = True, **opts) -> dict:
@@ -441,10 +447,12 @@ class Context:
         _check(lib().mcpt_dimer_attach(self.h, pid, C.byref(di)))
 
     def dimer_tau(self, pid: int) -> np.ndarray:
-        """Tau of every pair (mcpt_dimer_tau) as an array [pair, i, a, j, b] (one monomer size)."""
-        n_occ, n_vir, n_pair = self._sizes[pid]
-        o, v = int(n_occ[0]), int(n_vir[0])
-        tau = np.empty((n_pair, o, v, o, v))
+        """Tau of every pair (mcpt_dimer_tau), flat in the caller's pair order: pair p
+        contributes Tau_XY[i][a][j][b], oX vX oY vY values."""
+        n_occ, n_vir, _ = self._sizes[pid]
+        pairs = self._pairs[pid]
+        nx = np.asarray(n_occ, dtype=np.int64) * np.asarray(n_vir, dtype=np.int64)
+        tau = np.empty(int(np.sum(nx[pairs[:, 0]] * nx[pairs[:, 1]])) if len(pairs) else 0)
         _check(lib().mcpt_dimer_tau(self.h, pid, _ptr(tau)))
         return tau
 
@@ -456,6 +464,8 @@ class Context:
         pid = C.c_uint64()
         _check(lib().mcpt_upload_scaled(self.h, base, len(pa), _ptr(pa), _ptr(sa), C.byref(pid)))
         self._sizes[pid.value] = self._sizes[base]
+        if base in self._pairs:
+            self._pairs[pid.value] = self._pairs[base]
         if base in self._clusters:
             self._clusters[pid.value] = self._clusters[base]
         return pid.value
@@ -481,6 +491,7 @@ class Context:
     def release(self, pid: int):
         _check(lib().mcpt_release(self.h, pid))
         self._sizes.pop(pid, None)
+        self._pairs.pop(pid, None)
 
     def set_timing(self, on: bool):
         _check(lib().mcpt_set_timing(self.h, 1 if on else 0))

@@ -3,8 +3,8 @@ iterated) on the GPU against the oracle: fixed sweep counts element by element
 on uniform clusters of one to nine MFMA tiles per edge (n = 6, 51, 135, the
 last two with ragged tails), with physical-symmetry and with general
 integrals, monomers at and above the LDS limit of the staged pair ladder (up to
-o8v56, n = 448), the converged solve with equal sweep counts, graph replay, and
-the error paths.  Bar: 1e-10 relative (FP64), sweep counts equal."""
+o8v56, n = 448), pairs of monomers of different sizes, the converged solve with
+equal sweep counts, graph replay, and the error paths.  Bar: 1e-10 relative (FP64), sweep counts equal."""
 import json
 import os
 import types
@@ -67,7 +67,7 @@ def run_gpu(ctx, p, ints, dints, **opts):
 
 
 def flat_tau(r):
-    return np.stack([np.asarray(t) for t in r.Tau])
+    return np.concatenate([np.asarray(t).ravel() for t in r.Tau])
 
 
 @pytest.mark.parametrize("o,v,general,sweeps", [(2, 3, False, 1), (2, 3, True, 3), (3, 17, False, 2),
@@ -115,12 +115,48 @@ def test_errors_and_detach(ctx):
     ref = mcpt_lccd.solve(p, ints, tol=0.0, max_sweeps=2)
     assert rel(ctx.energy(pid)["e_d2"], ref.e_d2) <= TOL
     ctx.release(pid)
-    q = make_lattice_problem(cubic_sites(2, 1, 1), None, sizes=[(2, 3), (2, 4)], workload=942)
-    pid = ctx.upload(q)
-    ctx.lccd_attach(pid, lccd_integrals(q))
-    with pytest.raises(mc.MCPTError):              # monomers of different sizes
-        ctx.dimer_attach(pid, dimer_integrals(q))
-    ctx.release(pid)
+
+
+def mixed_cluster(sizes, dims, scale=0.5, workload=961, general=False):
+    p = make_lattice_problem(cubic_sites(*dims), None, sizes=list(sizes), workload=workload, coupling_scale=scale,
+                             k_scale=LCCD_K_SCALE)
+    ints = lccd_integrals(p)
+    dints = dimer_integrals(p)
+    if general:
+        rng = np.random.default_rng(workload)
+        for arr in (dints.w, dints.q, dints.cx, dints.cy):
+            arr[:] = rng.normal(0.0, 0.01, size=arr.shape)
+    return p, ints, dints
+
+
+@pytest.mark.parametrize("general,sweeps", [(False, 1), (False, 3), (True, 2)])
+def test_mixed_sizes_fixed_sweeps(ctx, general, sweeps):
+    """Pairs of monomers of different sizes (X smaller or larger than Y, one side
+    o8v56 beyond the LDS-staged ladder): every T, every pair's Tau and the energies
+    element by element against the oracle."""
+    sizes = ((2, 3), (5, 27), (8, 56), (3, 17))
+    p, ints, dints = mixed_cluster(sizes, (2, 2, 1), general=general)
+    print(f"[gpu] dimer mixed sizes {sizes} P={p.n_pair} sweeps={sweeps} general={general}", flush=True)
+    ref = mcpt_dimer.solve(p, ints, dints, tol=0.0, max_sweeps=sweeps)
+    s, e = run_gpu(ctx, p, ints, dints, tol=0.0, max_sweeps=sweeps)
+    assert s["return"] == mc.MCPT_OK, s["error"]
+    assert rel(e["t"], flat_t(ref)) <= TOL
+    assert rel(e["tau"], flat_tau(ref)) <= TOL
+    assert rel(e["e_m2"], ref.e_m2) <= TOL and rel(e["e_d2"], ref.e_d2) <= TOL
+    assert abs(s["e_total"] - ref.e_total) <= TOL * abs(ref.e_total)
+
+
+def test_mixed_sizes_converged(ctx):
+    sizes = ((5, 27), (3, 17), (5, 27), (2, 9), (4, 11))
+    p, ints, dints = mixed_cluster(sizes, (5, 1, 1), scale=0.3, workload=962)
+    print(f"[gpu] dimer mixed sizes converged P={p.n_pair}", flush=True)
+    ref = mcpt_dimer.solve(p, ints, dints, tol=TOL, max_sweeps=200)
+    s, e = run_gpu(ctx, p, ints, dints, tol=TOL, max_sweeps=200)
+    assert ref.status == 0 and s["return"] == mc.MCPT_OK, s["error"]
+    assert s["sweeps"] == ref.sweeps
+    assert rel(e["e_m2"], ref.e_m2) <= TOL and rel(e["e_d2"], ref.e_d2) <= TOL
+    assert rel(e["tau"], flat_tau(ref)) <= TOL
+    assert abs(s["e_total"] - ref.e_total) <= TOL * abs(ref.e_total)
 
 
 def test_batch_equals_solo(ctx):
