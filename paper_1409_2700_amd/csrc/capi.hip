@@ -597,7 +597,12 @@ void pair_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int couple, const 
         p0.Y1 = p1.Y1 = R->d_DY1;
         p0.Y2 = p1.Y2 = R->d_DY2;
         p0.tau_out = p1.tau_out = R->d_Tau;
-        p0.dd = p1.dd = R->d_dd;
+        if (R->dimer_one_size) {   // np x np per pair at orig * np^2 (the one-size source form)
+            p0.mat_stride = p1.mat_stride = (int64_t)R->monos[0].np * R->monos[0].np;
+            p0.v = p1.v = R->monos[0].v;
+        } else {
+            p0.dd = p1.dd = R->d_dd;
+        }
     }
     const int g_lds = x.grid_cap > 0 ? std::min(c->grid_lds, x.grid_cap) : c->grid_lds;
     const int g_glb = x.grid_cap > 0 ? std::min(c->grid_glb, x.grid_cap) : c->grid_glb;
@@ -1349,6 +1354,7 @@ mcpt_status dimer_attach(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_dimer_int
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
         return fail_free(fail(MCPT_ERR_DEVICE, "packing of dimer integrals failed"));
     R->dimer_desc = std::move(dd);
+    R->dimer_one_size = one_size;
     R->dimer_tau_elems = tau_el;
     R->dimer_lds_bytes = lds;
     R->dimer_ct = lds > 0 ? lccd_ladder_ct(m0.o) : dimer_ladder_ct(max_o2);

@@ -64,13 +64,16 @@ struct PartOut {
     double* part;            // nullptr: FP64 atomics into G
     const int64_t* off;      // per pair of the launch
     // dimer-internal terms (FP64 kernel only): S - Y1[(i,b),(j,a)] - Y2[(j,a),(i,b)] adds into
-    // the numerator of Tau[(i,a),(j,b)] and Tau is kept in tau_out, each at the offsets of the
-    // pair's DimerDesc (dd, indexed by the caller's pair index); nullptr: none of it
+    // the numerator of Tau[(i,a),(j,b)] and Tau is kept in tau_out (S nullptr: none of it).  Every
+    // monomer of one size (dd nullptr): all np x np at orig * mat_stride, v virtuals; otherwise at
+    // the offsets of the pair's DimerDesc (dd, indexed by the caller's pair index)
     const double* S = nullptr;
     const double* Y1 = nullptr;
     const double* Y2 = nullptr;
     double* tau_out = nullptr;
     const DimerDesc* dd = nullptr;
+    int64_t mat_stride = 0;
+    int v = 0;
 };
 
 struct MonoDesc {

@@ -430,9 +430,10 @@ __device__ inline PairView make_view(const PairDesc& pd, const MonoDesc* monos, 
 }
 
 // One body for both variants: IN_LDS stages V in LDS (the pair list given to
-// it holds only pairs that fit); otherwise V is read from L2.  DIMER adds the
+// it holds only pairs that fit); otherwise V is read from L2.  DIMER (1: every
+// monomer of one size, 2: any sizes, from the pair's descriptor) adds the
 // dimer-internal source of po to the numerator of Tau and keeps Tau.
-template <bool IN_LDS, int NT, bool DIMER>
+template <bool IN_LDS, int NT, int DIMER>
 __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_pair,
                                  const MonoDesc* __restrict__ monos, const double* __restrict__ dif,
                                  const double* __restrict__ V, const double* __restrict__ M,
@@ -482,7 +483,14 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
         int dvx = 1, dvy = 1, dm1 = 0, dm2 = 0;
         const double *Sp = nullptr, *Y1p = nullptr, *Y2p = nullptr;
         double* Tp = nullptr;
-        if (DIMER) {
+        if (DIMER == 1) {   // one size: every pair's matrices np x np at orig * mat_stride
+            dvx = dvy = po.v;
+            dm1 = dm2 = p.npY;
+            Sp = po.S + pd.orig * po.mat_stride;
+            Y1p = po.Y1 + pd.orig * po.mat_stride;
+            Y2p = po.Y2 + pd.orig * po.mat_stride;
+            Tp = po.tau_out + pd.orig * po.mat_stride;
+        } else if (DIMER == 2) {
             const DimerDesc& e = po.dd[pd.orig];
             dvx = e.vx;
             dvy = e.vy;
@@ -523,7 +531,13 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
                     for (int t = 0; t < 4; ++t) {
                         const int rr = min((r0 + i) * 16 + acc_row(lane, t), p.nX - 1);
                         vv[i][t] = IN_LDS ? sV[rr * p.ldv + c] : p.V[(int64_t)rr * p.nY + cc];
-                        if (DIMER) {   // rr = (ii,a), cc = (jj,b): the clamped element's indices
+                        if (DIMER == 1) {   // rr = (ii,a), cc = (jj,b): the clamped element's indices
+                            const int ii = rr / dvx, a = rr - ii * dvx, jj = cc / dvx, b = cc - jj * dvx;
+                            const int r = (r0 + i) * 16 + acc_row(lane, t);
+                            dsrc[i][t] = Sp[(int64_t)r * p.npY + c] -
+                                         Y1p[(int64_t)(ii * dvx + b) * dm1 + jj * dvx + a] -
+                                         Y2p[(int64_t)(jj * dvx + a) * dm1 + ii * dvx + b];
+                        } else if (DIMER == 2) {
                             const int ii = rr / dvx, a = rr - ii * dvx, jj = cc / dvy, b = cc - jj * dvy;
                             const int r = (r0 + i) * 16 + acc_row(lane, t);
                             dsrc[i][t] = Sp[(int64_t)r * p.npY + c] -
@@ -586,7 +600,7 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
     if (sink == 1.2345e300) ed2[0] = sink;   // keeps the prefetch loads; never true for finite inputs
 }
 
-template <bool DIMER>
+template <int DIMER>
 __global__ __launch_bounds__(kThreadsL) void pair_fp64_lds_kernel(
     const PairDesc* __restrict__ pairs, int64_t n_pair, const MonoDesc* __restrict__ monos,
     const double* __restrict__ dif, const double* __restrict__ V, const double* __restrict__ M,
@@ -601,7 +615,7 @@ __global__ __launch_bounds__(kThreadsL) void pair_fp64_lds_kernel(
                                       sD, red);
 }
 
-template <bool DIMER>
+template <int DIMER>
 __global__ __launch_bounds__(kThreadsG, 2) void pair_fp64_glb_kernel(
     const PairDesc* __restrict__ pairs, int64_t n_pair, const MonoDesc* __restrict__ monos,
     const double* __restrict__ dif, const double* __restrict__ V, const double* __restrict__ M,
@@ -619,8 +633,8 @@ __global__ __launch_bounds__(kThreadsG, 2) void pair_fp64_glb_kernel(
 int pair_fp64_blocks_per_cu(int lds_variant) {
     int n = 0;
     hipError_t e = lds_variant
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_fp64_lds_kernel<false>, kThreadsL, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_fp64_glb_kernel<false>, kThreadsG, 0);
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_fp64_lds_kernel<0>, kThreadsL, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_fp64_glb_kernel<0>, kThreadsG, 0);
     if (e != hipSuccess || n < 1) n = 1;
     return n;
 }
@@ -632,20 +646,26 @@ void launch_pair_fp64(int lds_variant, PartOut po, const PairDesc* pairs, int64_
                       int64_t slot_elems, int grid, double* ed2, int couple, const Ctrl* ctrl, const ClState* cl,
                       hipStream_t s) {
     if (n_pair <= 0) return;
-    const bool dimer = po.S != nullptr;
+    const int dimer = po.S == nullptr ? 0 : po.dd ? 2 : 1;
     if (lds_variant) {
-        if (dimer)
-            hipLaunchKernelGGL(pair_fp64_lds_kernel<true>, dim3(grid), dim3(kThreadsL), 0, s, pairs, n_pair, monos,
+        if (dimer == 2)
+            hipLaunchKernelGGL(pair_fp64_lds_kernel<2>, dim3(grid), dim3(kThreadsL), 0, s, pairs, n_pair, monos,
+                               dif, V, M, G, scratch, slot_elems, ed2, couple, ctrl, cl, po);
+        else if (dimer == 1)
+            hipLaunchKernelGGL(pair_fp64_lds_kernel<1>, dim3(grid), dim3(kThreadsL), 0, s, pairs, n_pair, monos,
                                dif, V, M, G, scratch, slot_elems, ed2, couple, ctrl, cl, po);
         else
-            hipLaunchKernelGGL(pair_fp64_lds_kernel<false>, dim3(grid), dim3(kThreadsL), 0, s, pairs, n_pair, monos,
+            hipLaunchKernelGGL(pair_fp64_lds_kernel<0>, dim3(grid), dim3(kThreadsL), 0, s, pairs, n_pair, monos,
                                dif, V, M, G, scratch, slot_elems, ed2, couple, ctrl, cl, po);
     } else {
-        if (dimer)
-            hipLaunchKernelGGL(pair_fp64_glb_kernel<true>, dim3(grid), dim3(kThreadsG), 0, s, pairs, n_pair, monos,
+        if (dimer == 2)
+            hipLaunchKernelGGL(pair_fp64_glb_kernel<2>, dim3(grid), dim3(kThreadsG), 0, s, pairs, n_pair, monos,
+                               dif, V, M, G, scratch, slot_elems, ed2, couple, ctrl, cl, po);
+        else if (dimer == 1)
+            hipLaunchKernelGGL(pair_fp64_glb_kernel<1>, dim3(grid), dim3(kThreadsG), 0, s, pairs, n_pair, monos,
                                dif, V, M, G, scratch, slot_elems, ed2, couple, ctrl, cl, po);
         else
-            hipLaunchKernelGGL(pair_fp64_glb_kernel<false>, dim3(grid), dim3(kThreadsG), 0, s, pairs, n_pair, monos,
+            hipLaunchKernelGGL(pair_fp64_glb_kernel<0>, dim3(grid), dim3(kThreadsG), 0, s, pairs, n_pair, monos,
                                dif, V, M, G, scratch, slot_elems, ed2, couple, ctrl, cl, po);
     }
 }

@@ -101,6 +101,7 @@ struct Resident {
     double *d_DY1 = nullptr, *d_DY2 = nullptr;   // the cross-ring products of each pair
     std::vector<DimerDesc> dimer_desc;   // per pair (caller order): sizes and offsets
     int64_t dimer_tau_elems = 0;         // elements of the Tau (and S) buffer
+    bool dimer_one_size = false;         // every monomer of one size: Tau, S, Y1, Y2 np x np per pair
     int dimer_ring_blocks = 0, dimer_ct = 1, dimer_ladder_blocks = 1;
     int64_t dimer_lds_bytes = 0;
     double dimer_w_bytes = 0.0, dimer_w_flops = 0.0;
