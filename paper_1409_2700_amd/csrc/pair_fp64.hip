@@ -519,45 +519,74 @@ __device__ inline void pair_body(const PairDesc* __restrict__ pairs, int64_t n_p
             for (int i = 0; i < NR; ++i)
 #pragma unroll
                 for (int t = 0; t < 4; ++t) dxr[i][t] = dXs[(r0 + i) * 16 + acc_row(lane, t)];
+            if constexpr (DIMER == 0) {
 #pragma unroll
-            for (int j = 0; j < NC; ++j) {
-                const int c = (c0 + j) * 16 + acc_col(lane);
-                const int cc = min(c, p.nY - 1);
-                const double dyc = dYs[c];
-                double vv[NR][4], dsrc[NR][4];
+                for (int j = 0; j < NC; ++j) {
+                    const int c = (c0 + j) * 16 + acc_col(lane);
+                    const int cc = min(c, p.nY - 1);
+                    const double dyc = dYs[c];
+                    double vv[NR][4];
 #pragma unroll
-                for (int i = 0; i < NR; ++i)
+                    for (int i = 0; i < NR; ++i)
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int rr = min((r0 + i) * 16 + acc_row(lane, t), p.nX - 1);
-                        vv[i][t] = IN_LDS ? sV[rr * p.ldv + c] : p.V[(int64_t)rr * p.nY + cc];
-                        if (DIMER == 1) {   // rr = (ii,a), cc = (jj,b): the clamped element's indices
-                            const int ii = rr / dvx, a = rr - ii * dvx, jj = cc / dvx, b = cc - jj * dvx;
-                            const int r = (r0 + i) * 16 + acc_row(lane, t);
-                            dsrc[i][t] = Sp[(int64_t)r * p.npY + c] -
-                                         Y1p[(int64_t)(ii * dvx + b) * dm1 + jj * dvx + a] -
-                                         Y2p[(int64_t)(jj * dvx + a) * dm1 + ii * dvx + b];
-                        } else if (DIMER == 2) {
-                            const int ii = rr / dvx, a = rr - ii * dvx, jj = cc / dvy, b = cc - jj * dvy;
-                            const int r = (r0 + i) * 16 + acc_row(lane, t);
-                            dsrc[i][t] = Sp[(int64_t)r * p.npY + c] -
-                                         Y1p[(int64_t)(ii * dvy + b) * dm2 + jj * dvx + a] -
-                                         Y2p[(int64_t)(jj * dvx + a) * dm1 + ii * dvy + b];
+                        for (int t = 0; t < 4; ++t) {
+                            const int rr = min((r0 + i) * 16 + acc_row(lane, t), p.nX - 1);
+                            vv[i][t] = IN_LDS ? sV[rr * p.ldv + c] : p.V[(int64_t)rr * p.nY + cc];
                         }
-                    }
 #pragma unroll
-                for (int i = 0; i < NR; ++i)
+                    for (int i = 0; i < NR; ++i)
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int r = (r0 + i) * 16 + acc_row(lane, t);
-                        const bool ok = r < p.nX && c < p.nY;
-                        const double dinv = recip(dxr[i][t] + dyc);
-                        const double src = DIMER ? vv[i][t] + dsrc[i][t] : vv[i][t];
-                        const double tv = ok ? dinv * (src + acc[i][j][t]) : 0.0;
-                        epart += ok ? vv[i][t] * tv : 0.0;
-                        if (couple) tau[(int64_t)r * p.npY + c] = tv;
-                        if (DIMER) Tp[(int64_t)r * p.npY + c] = tv;
+                        for (int t = 0; t < 4; ++t) {
+                            const int r = (r0 + i) * 16 + acc_row(lane, t);
+                            const bool ok = r < p.nX && c < p.nY;
+                            const double dinv = recip(dxr[i][t] + dyc);
+                            const double tv = ok ? dinv * (vv[i][t] + acc[i][j][t]) : 0.0;
+                            epart += ok ? vv[i][t] * tv : 0.0;
+                            if (couple) tau[(int64_t)r * p.npY + c] = tv;
+                        }
+                }
+            } else {
+                // with the dimer source, four reads per element (V, S and the two cross-ring
+                // products at the clamped element rr = (ii,a), cc = (jj,b)): one tile at a time,
+                // or the gathered values of a whole tile column spill
+#pragma unroll
+                for (int j = 0; j < NC; ++j) {
+                    const int c = (c0 + j) * 16 + acc_col(lane);
+                    const int cc = min(c, p.nY - 1);
+                    const double dyc = dYs[c];
+#pragma unroll
+                    for (int i = 0; i < NR; ++i) {
+                        double vv[4], dsrc[4];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int rr = min((r0 + i) * 16 + acc_row(lane, t), p.nX - 1);
+                            const int r = (r0 + i) * 16 + acc_row(lane, t);
+                            vv[t] = IN_LDS ? sV[rr * p.ldv + c] : p.V[(int64_t)rr * p.nY + cc];
+                            if (DIMER == 1) {
+                                const int ii = rr / dvx, a = rr - ii * dvx, jj = cc / dvx, b = cc - jj * dvx;
+                                dsrc[t] = Sp[(int64_t)r * p.npY + c] -
+                                          Y1p[(int64_t)(ii * dvx + b) * dm1 + jj * dvx + a] -
+                                          Y2p[(int64_t)(jj * dvx + a) * dm1 + ii * dvx + b];
+                            } else {
+                                const int ii = rr / dvx, a = rr - ii * dvx, jj = cc / dvy, b = cc - jj * dvy;
+                                dsrc[t] = Sp[(int64_t)r * p.npY + c] -
+                                          Y1p[(int64_t)(ii * dvy + b) * dm2 + jj * dvx + a] -
+                                          Y2p[(int64_t)(jj * dvx + a) * dm1 + ii * dvy + b];
+                            }
+                        }
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int r = (r0 + i) * 16 + acc_row(lane, t);
+                            const bool ok = r < p.nX && c < p.nY;
+                            const double dinv = recip(dxr[i][t] + dyc);
+                            const double tv = ok ? dinv * (vv[t] + dsrc[t] + acc[i][j][t]) : 0.0;
+                            epart += ok ? vv[t] * tv : 0.0;
+                            if (couple) tau[(int64_t)r * p.npY + c] = tv;
+                            Tp[(int64_t)r * p.npY + c] = tv;
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
                     }
+                }
             }
         });
         epart = wave_sum(epart);
