@@ -274,7 +274,7 @@ def _served_pass(ctx, stream, n_req, arrivals, max_inflight, tol, alone_e):
     return start, lat, err, status, done_t, sub_t, state["submit_s"]
 
 
-def serving(base, n_req, loads, workers, max_batch, tol, max_inflight=32, staging_bytes=64 << 30):
+def serving(base, n_req, loads, workers, max_batch, tol, max_inflight=32, staging_bytes=64 << 30, mode=None):
     """Served stream (synth.ServedStream: requests cut from the resident crystal,
     sizes log-uniform in [8, N], one monomer displaced), first solved alone one at
     a time on the plain FP64 path (upload + solve), then submitted in a closed
@@ -321,33 +321,54 @@ def serving(base, n_req, loads, workers, max_batch, tol, max_inflight=32, stagin
     }
     log(f"[serve] alone: mean {mean_alone * 1e3:.1f} ms, p50 {pct(alone_lat, 50) * 1e3:.1f} ms")
     capacity = None
-    # one scheduler for every pass, so the pinned staging blocks made for the first requests are reused;
-    # an untimed closed-loop pass over the first max_inflight requests makes them
-    ctx = mc.Context(0)
-    ctx.serve_config(workers=workers, max_batch=max_batch)
-    ctx.serve_staging(staging_bytes)
-    t0 = time.perf_counter()
-    _served_pass(ctx, stream, min(n_req, max_inflight), None, max_inflight, tol, alone_e)
-    st0 = ctx.serve_stats()
-    out["staging"] = {"cap_bytes": staging_bytes, "warmup_s": time.perf_counter() - t0,
-                      "pinned_bytes": st0["staging_pinned_bytes"]}
-    for load in ["capacity"] + [x for x in loads if x != "burst"]:
-        if load == "capacity":
+
+    def scheduler(mode):
+        # one scheduler for several passes, so the pinned staging blocks made for the first requests are
+        # reused; an untimed closed-loop pass over the first max_inflight requests makes them
+        c = mc.Context(0)
+        c.serve_config(workers=workers, max_batch=max_batch)
+        c.serve_staging(staging_bytes)
+        c.serve_tick_mode(mode)
+        t0 = time.perf_counter()
+        _served_pass(c, stream, min(n_req, max_inflight), None, max_inflight, tol, alone_e)
+        return c, time.perf_counter() - t0
+
+    modes = {mc.MCPT_SERVE_BATCH_END: "batch_end", mc.MCPT_SERVE_RETIRE_AT_TICKS: "retire_at_ticks",
+             mc.MCPT_SERVE_JOIN_AT_TICKS: "join_at_ticks"}
+    if mode is None:
+        mode = mc.MCPT_SERVE_RETIRE_AT_TICKS   # the library's default
+    ctx, warm_s = scheduler(mode)
+    out["staging"] = {"cap_bytes": staging_bytes, "warmup_s": warm_s,
+                      "pinned_bytes": ctx.serve_stats()["staging_pinned_bytes"]}
+    out["tick_mode"] = modes[mode]
+    out["tick_modes"] = ("batch_end: a batch's requests are reported when its last one stops; retire_at_ticks: "
+                         "each request retires at the sweep tick where its solve stops; join_at_ticks: also "
+                         "admits queued requests into running batches at ticks (below saturation)")
+    extra = {f"capacity_{modes[m]}": m for m in modes if m != mode}
+    for load in ["capacity"] + [x for x in loads if x != "burst"] + list(extra):
+        if load in extra:
+            ctx.close()
+            ctx, _ = scheduler(extra[load])
+        if isinstance(load, str):
             arrivals, cap = None, max_inflight
         else:
             rng = np.random.default_rng([SEED_ROOT, 5, int(round(load * 1000))])
             arrivals, cap = np.cumsum(rng.exponential(1.0 / (load * capacity), n_req)), 2 * max_inflight
-        b0 = ctx.serve_stats()["batches"]
+        st0 = ctx.serve_stats()
         start, lat, err, status, done_t, sub_t, sub_s = _served_pass(ctx, stream, n_req, arrivals, cap, tol, alone_e)
         st = ctx.serve_stats()
         makespan = max(done_t) - start
-        key = load if load == "capacity" else f"{load:.2f}"
+        key = load if isinstance(load, str) else f"{load:.2f}"
         entry = {"completed_solves_per_s": n_req / makespan, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99),
-                 "mean_s": float(np.mean(lat)), "batches": st["batches"] - b0, "samples": n_req,
+                 "mean_s": float(np.mean(lat)), "batches": st["batches"] - st0["batches"],
+                 "joined_at_ticks": st["joined_at_ticks"] - st0["joined_at_ticks"], "samples": n_req,
                  "all_ok": all(w == 0 for w in status), "max_rel_err_vs_alone": float(max(err)),
                  "submit_s": sub_s, "submit_share_of_makespan": sub_s / makespan,
                  "staging_pinned_bytes": st["staging_pinned_bytes"], "staged_pageable": st["staged_pageable"]}
-        if load == "capacity":
+        if load in extra:
+            entry["max_in_flight"] = cap
+            entry["vs_default_capacity"] = (n_req / makespan) / capacity
+        elif load == "capacity":
             capacity = n_req / makespan
             out["capacity_solves_per_s"] = capacity
             out["capacity_vs_alone"] = capacity * mean_alone
@@ -357,8 +378,8 @@ def serving(base, n_req, loads, workers, max_batch, tol, max_inflight=32, stagin
             entry.update({"offered_solves_per_s": load * capacity, "submission_delay_p99_s": pct(late, 99)})
         out["loads"][key] = entry
         log(f"[serve] {key}: {n_req / makespan:.2f} solves/s, p50 {pct(lat, 50) * 1e3:.1f} ms, "
-            f"p99 {pct(lat, 99) * 1e3:.1f} ms, {entry['batches']} batches, max rel err {max(err):.1e}, "
-            f"submit {sub_s:.1f} s of {makespan:.1f} s")
+            f"p99 {pct(lat, 99) * 1e3:.1f} ms, {entry['batches']} batches, {entry['joined_at_ticks']} joined at "
+            f"ticks, max rel err {max(err):.1e}, submit {sub_s:.1f} s of {makespan:.1f} s")
     ctx.close()
     return out
 
@@ -792,6 +813,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=256, help="served-stream sample (0: skip)")
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=16)
+    ap.add_argument("--serve-mode", type=int, default=None,
+                    help="tick mode of the served passes (0 batch end, 1 retire at ticks, 2 join at ticks; "
+                         "default: the library's); the other modes get one capacity pass each")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="only launch a calibration copy and two fixed sweeps (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-precision", type=int, default=0, help="0 FP64, 1 FP32, 2 BF16 sweeps in --pmc-pass")
@@ -863,7 +887,7 @@ def main():
     served = None
     if args.serve_requests > 0:
         served = serving(prob, args.serve_requests, [0.5, 0.8], args.serve_workers, args.serve_batch,
-                         args.tol)
+                         args.tol, mode=args.serve_mode)
 
     h = results[args.headline]
     tm = h["timing"]

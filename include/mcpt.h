@@ -486,7 +486,9 @@ mcpt_status mcpt_timing_read(mcpt_ctx *ctx, mcpt_timing *out);
  * cost within a factor of four of it, while they fit.  The batch runs as an
  * mcpt_upload_batch problem, so each request's result is the one its own
  * solve gives.  Requests that arrive while batches run are taken by the next
- * free worker, and the workers' batches run concurrently on the device.
+ * free worker, and the workers' batches run concurrently on the device.  FP64
+ * batches retire each request at the sweep tick where its solve stops and can
+ * also admit queued requests there (mcpt_serve_tick_mode).
  * Results stay resident until mcpt_release(ticket); they count against the
  * budget, so admission waits while released memory is needed.
  */
@@ -502,6 +504,7 @@ typedef struct {
     int32_t  tickets;           /* live tickets (queued, running or holding results) */
     uint64_t staging_pinned_bytes;  /* pinned host staging held for request copies */
     uint64_t staged_pageable;   /* request arrays copied to pageable memory (staging full) */
+    uint64_t joined_at_ticks;   /* requests admitted into running batches at sweep ticks */
 } mcpt_serve_counters;
 
 /* Scheduler parameters; only before the first mcpt_submit of the context.
@@ -509,6 +512,31 @@ typedef struct {
  * requests per batch, 1..4096 (default 32); max_batch_pairs: pairs per batch
  * (default 2^20).  Errors: MCPT_ERR_INVALID (range, scheduler running). */
 mcpt_status mcpt_serve_config(mcpt_ctx *ctx, int32_t workers, int32_t max_batch, int64_t max_batch_pairs);
+
+/* What a served batch of FP64 plain sweeps (no graph, deterministic mode or warm
+ * start) does at its sweep ticks, the host checks after every check_every sweeps;
+ * only before the first mcpt_submit of the context.
+ *   MCPT_SERVE_BATCH_END: nothing; every request of the batch is reported when the
+ *     last one stops, as for other options.
+ *   MCPT_SERVE_RETIRE_AT_TICKS (default): a request whose solve has stopped retires
+ *     at that tick: its energies are computed (the energy pass over its pairs only)
+ *     and it is reported while the batch's other requests go on; its results stay
+ *     in the batch's memory until its ticket is released.
+ *   MCPT_SERVE_JOIN_AT_TICKS: as RETIRE, and while every worker is busy and at most
+ *     as many requests are queued as there are workers, requests at the head of the
+ *     queue with the same options and a pair-phase cost within a factor of four of
+ *     the batch's first request join it, in queue order, within max_batch,
+ *     max_batch_pairs and the budget (each priced at twice its footprint while it
+ *     comes in), if together they are at least as large as the batch's unfinished
+ *     requests: they are uploaded and copied with the unfinished clusters, whose
+ *     iteration state is kept, into one batch that the next sweeps run as one launch
+ *     per kernel.  The running batch pauses for the joiners' upload, which a batch
+ *     formed on a free worker overlaps with other batches' sweeps.
+ * In every mode a request's sweeps and result are those of its own solve (to the
+ * rounding of the G atomics).  Errors: MCPT_ERR_INVALID (unknown mode, scheduler
+ * running). */
+enum { MCPT_SERVE_BATCH_END = 0, MCPT_SERVE_RETIRE_AT_TICKS = 1, MCPT_SERVE_JOIN_AT_TICKS = 2 };
+mcpt_status mcpt_serve_tick_mode(mcpt_ctx *ctx, int32_t mode);
 
 /* Host staging of submitted requests; only before the first mcpt_submit of the
  * context.  mcpt_submit copies a request's integral arrays into pinned host

@@ -248,6 +248,26 @@ double pair_flops(const Resident& r, bool couple) {
 // and pairs are concatenated cluster after cluster (pair indices shifted by the
 // cluster's first monomer), each monomer and pair carries its cluster id, and
 // every cluster keeps its own stopping state during a run.
+// Processing order of the pairs: LDS-variant pairs first; within each range, blocks of
+// kPairBlock x kPairBlock monomers (lower, upper index), so that the pairs an XCD works on
+// at a time share few monomers' M and G blocks.
+void order_pairs(Resident* r) {
+    const std::vector<MonoDesc>& m = r->monos;
+    auto lds = [&m](const PairDesc& d) { return pair_fits_lds(m[d.x].n, m[d.x].np, m[d.y].np); };
+    const int B = kPairBlock;
+    std::stable_sort(r->pairs.begin(), r->pairs.end(), [&](const PairDesc& a, const PairDesc& b) {
+        const bool la = lds(a), lb = lds(b);
+        if (la != lb) return la;
+        const int a0 = std::min(a.x, a.y), b0 = std::min(b.x, b.y);
+        const int a1 = std::max(a.x, a.y), b1 = std::max(b.x, b.y);
+        if (a0 / B != b0 / B) return a0 / B < b0 / B;
+        if (a1 / B != b1 / B) return a1 / B < b1 / B;
+        if (a0 != b0) return a0 < b0;
+        return a1 < b1;
+    });
+    r->n_lds = std::count_if(r->pairs.begin(), r->pairs.end(), lds);
+}
+
 mcpt_status upload_batch(mcpt_ctx* c, Exec& x, const mcpt_problem* pbs, int n_cl, bool internal, uint64_t* id_out) {
     if (!pbs || n_cl < 1) return fail(MCPT_ERR_INVALID, "need at least one problem");
     if (!id_out) return fail(MCPT_ERR_INVALID, "id is NULL");
@@ -326,24 +346,8 @@ mcpt_status upload_batch(mcpt_ctx* c, Exec& x, const mcpt_problem* pbs, int n_cl
     }
     v_cl[n_cl] = vo;
     r->v_elems = vo;
-    {
-        const std::vector<MonoDesc>& m = r->monos;
-        auto lds = [&m](const PairDesc& d) { return pair_fits_lds(m[d.x].n, m[d.x].np, m[d.y].np); };
-        // within each range: blocks of kPairBlock x kPairBlock monomers (lower, upper index), so
-        // that the pairs an XCD works on at a time share few monomers' M and G blocks
-        const int B = kPairBlock;
-        std::stable_sort(r->pairs.begin(), r->pairs.end(), [&](const PairDesc& a, const PairDesc& b) {
-            const bool la = lds(a), lb = lds(b);
-            if (la != lb) return la;
-            const int a0 = std::min(a.x, a.y), b0 = std::min(b.x, b.y);
-            const int a1 = std::max(a.x, a.y), b1 = std::max(b.x, b.y);
-            if (a0 / B != b0 / B) return a0 / B < b0 / B;
-            if (a1 / B != b1 / B) return a1 / B < b1 / B;
-            if (a0 != b0) return a0 < b0;
-            return a1 < b1;
-        });
-        r->n_lds = std::count_if(r->pairs.begin(), r->pairs.end(), lds);
-    }
+    r->cl_v = v_cl;
+    order_pairs(r.get());
     // energies: validated on the host (small)
     std::vector<double> eps(eoff);
     for (int q = 0; q < n_cl; ++q) {
@@ -528,7 +532,8 @@ mcpt_status slice_results(mcpt_ctx* c, Exec& x, Resident* R, int q, double* e_m2
     if (e_d2 && p1 > p0)
         HIP_TRY(hipMemcpyAsync(e_d2, R->d_ed2 + p0, (p1 - p0) * sizeof(double), hipMemcpyDeviceToHost, s));
     if (t_amp && m1 > m0) {
-        launch_unpack(R->d_monos, R->n_mono, R->d_T, R->d_raw, R->max_n, s);
+        // only these monomers' T (a served batch may still be sweeping its other clusters)
+        launch_unpack(R->d_monos + m0, (int)(m1 - m0), R->d_T, R->d_raw, R->max_n, s);
         HIP_TRY(hipGetLastError());
         const int64_t r0 = R->monos[m0].raw_off;
         const int64_t r1 = m1 < R->n_mono ? R->monos[m1].raw_off : R->raw_elems;
@@ -572,8 +577,10 @@ void record_end(Exec& x, hipEvent_t a, int kind, double flops, double vbytes) {
 
 // Pair phase over all pairs: the LDS-resident-V kernel for the pairs that fit,
 // then the L2 variant for the rest (same stream, so G accumulates in order).
-void pair_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int couple, const Ctrl* ctrl) {
-    const ClState* cl = ctrl ? R->d_cl : nullptr;   // the final energy pass covers every cluster
+void pair_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int couple, const Ctrl* ctrl,
+                const ClState* cl_sel = nullptr) {
+    // the final energy pass covers every cluster, or those cl_sel does not mark done
+    const ClState* cl = cl_sel ? cl_sel : ctrl ? R->d_cl : nullptr;
     const bool det = R->det_on && couple;
     PartOut p0{det ? R->d_part : nullptr, R->d_part_off};
     PartOut p1{det ? R->d_part : nullptr, R->d_part_off ? R->d_part_off + R->n_lds : nullptr};
@@ -1963,6 +1970,282 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
     if (sm.status != MCPT_OK)
         return fail((mcpt_status)sm.status, "not converged after " + std::to_string(sm.sweeps) + " sweeps");
     clear_error();
+    return MCPT_OK;
+}
+
+// ---- served FP64 batches with admission at sweep ticks ----
+
+mcpt_status join_init(mcpt_ctx* c, Exec& x, Resident* R) {
+    mcpt_status st;
+    if ((st = ensure_device(c)) != MCPT_OK) return st;
+    if ((st = ensure_scratch(c, x, R->max_slot)) != MCPT_OK) return st;
+    hipStream_t s = x.stream;
+    std::vector<ClState> cs(R->n_cl, ClState{});
+    for (int q = 0; q < R->n_cl; ++q)
+        if (!R->cl_bad.empty() && R->cl_bad[q]) {   // never swept; reported as non-finite input
+            cs[q].done = 1;
+            cs[q].status = MCPT_ERR_NONFINITE;
+        }
+    HIP_TRY(hipMemcpyAsync(R->d_cl, cs.data(), R->n_cl * sizeof(ClState), hipMemcpyHostToDevice, s));
+    launch_monomer(kMonoInit, R->d_monos, R->n_mono, R->max_v, R->d_dif, R->d_K, nullptr, nullptr, R->d_T, R->d_M,
+                   R->d_em2, R->d_em2_0, R->d_res, nullptr, nullptr, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    R->g_cur = 0;   // upload left both G buffers zero
+    R->has_result = false;
+    return MCPT_OK;
+}
+
+mcpt_status join_sweeps(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, std::vector<ClState>* cs) {
+    mcpt_status st;
+    if ((st = ensure_scratch(c, x, R->max_slot)) != MCPT_OK) return st;
+    hipStream_t s = x.stream;
+    Ctrl& h = *x.h_ctrl;   // the stream is idle: the last tick synchronised it
+    std::memset(&h, 0, sizeof(Ctrl));
+    h.fixed = o->tol == 0.0;
+    h.max_sweeps = o->max_sweeps;
+    h.tol = o->tol;
+    HIP_TRY(hipMemcpyAsync(x.d_ctrl, &h, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+    const int every = o->check_every > 0 ? o->check_every : 1;
+    for (int k = 0; k < every; ++k) {
+        int& cur = R->g_cur;
+        pair_phase(c, x, R, R->d_G[cur], 1, x.d_ctrl);
+        launch_monomer(kMonoUpdate, R->d_monos, R->n_mono, R->max_v, R->d_dif, R->d_K, R->d_G[cur], R->d_G[cur ^ 1],
+                       R->d_T, R->d_M, R->d_em2, R->d_em2_0, R->d_res, x.d_ctrl, R->d_cl, s);
+        cur ^= 1;
+        launch_reduce_sweep(R->n_cl, R->d_cl_mono, R->d_res, R->d_cl, R->d_hist, x.d_ctrl, s);
+    }
+    if ((st = sync_ctrl(x)) != MCPT_OK) return st;
+    cs->assign(R->n_cl, ClState{});
+    HIP_TRY(hipMemcpyAsync(cs->data(), R->d_cl, R->n_cl * sizeof(ClState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MCPT_OK;
+}
+
+mcpt_status join_finish(mcpt_ctx* c, Exec& x, Resident* R, const std::vector<int>& qs, const mcpt_options* o,
+                        std::vector<char>* has, std::vector<mcpt_summary>* sums) {
+    mcpt_status st;
+    hipStream_t s = x.stream;
+    has->assign(qs.size(), 0);
+    sums->assign(qs.size(), mcpt_summary{});
+    std::vector<ClState> cs(R->n_cl);
+    HIP_TRY(hipMemcpyAsync(cs.data(), R->d_cl, R->n_cl * sizeof(ClState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    // results exist for converged clusters and for those out of sweeps, as in a solve
+    std::vector<char> keep(R->n_cl, 0);
+    bool any = false;
+    for (int q : qs)
+        if (cs[q].status != MCPT_ERR_DIVERGED && cs[q].status != MCPT_ERR_NONFINITE) keep[q] = any = true;
+    if (any) {
+        // energies of the finished clusters' final amplitudes: the energy pass over their pairs only
+        // (a selection that marks every other cluster done), then the per-cluster sums
+        if (!R->d_cl_sel && (st = dev_alloc(c, R, &R->d_cl_sel, R->n_cl)) != MCPT_OK) return st;
+        std::vector<ClState> sel(R->n_cl, ClState{});
+        for (int q = 0; q < R->n_cl; ++q) sel[q].done = keep[q] ? 0 : 1;
+        HIP_TRY(hipMemcpyAsync(R->d_cl_sel, sel.data(), R->n_cl * sizeof(ClState), hipMemcpyHostToDevice, s));
+        pair_phase(c, x, R, R->d_G[R->g_cur], 0, nullptr, R->d_cl_sel);
+        launch_reduce_final(R->n_cl, R->d_cl_mono, R->d_cl_pair, R->d_em2, R->d_em2_0, R->d_ed2, R->d_cl, x.d_ctrl, s);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(cs.data(), R->d_cl, R->n_cl * sizeof(ClState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        R->has_result = true;   // the finished clusters' results can be read (slice_results)
+    }
+    for (size_t i = 0; i < qs.size(); ++i) {
+        const int q = qs[i];
+        mcpt_summary& sm = (*sums)[i];
+        sm.residual = cs[q].residual;
+        sm.sweeps = cs[q].sweeps;
+        if (cs[q].status == MCPT_ERR_NONFINITE) sm.status = MCPT_ERR_NONFINITE;
+        else if (cs[q].status == MCPT_ERR_DIVERGED) sm.status = MCPT_ERR_DIVERGED;
+        else if (o->tol == 0.0 || (cs[q].sweeps > 0 && cs[q].residual < o->tol)) sm.status = MCPT_OK;
+        else sm.status = MCPT_ERR_NOT_CONVERGED;
+        if (!keep[q]) continue;
+        (*has)[i] = 1;
+        sm.e_mono = cs[q].e_mono;
+        sm.e_dimer = cs[q].e_dimer;
+        sm.e_total = cs[q].e_mono + cs[q].e_dimer;
+        sm.e_mono0 = cs[q].e_mono0;
+    }
+    return MCPT_OK;
+}
+
+mcpt_status join_concat(mcpt_ctx* c, Exec& x, const std::vector<std::pair<Resident*, int>>& parts, uint64_t* id_out) {
+    if (parts.empty()) return fail(MCPT_ERR_INVALID, "nothing to join");
+    mcpt_status st;
+    auto m = std::make_unique<Resident>();
+    Resident* M = m.get();
+    const int n_cl = (int)parts.size();
+    M->n_cl = n_cl;
+    M->cl_mono.assign(n_cl + 1, 0);
+    M->cl_pair.assign(n_cl + 1, 0);
+    M->cl_v.assign(n_cl + 1, 0);
+    M->cl_bad.assign(n_cl, 0);
+    // the element ranges of cluster q of R in each array (clusters are contiguous, in order)
+    struct Span {
+        int64_t m0, m1, p0, p1, v0, v1, mat0, mat1, dif0, dif1, raw0, raw1, eps0, eps1;
+    };
+    auto span_of = [](const Resident* R, int q) {
+        Span r{};
+        r.m0 = R->cl_mono[q];
+        r.m1 = R->cl_mono[q + 1];
+        r.p0 = R->cl_pair[q];
+        r.p1 = R->cl_pair[q + 1];
+        r.v0 = R->cl_v[q];
+        r.v1 = R->cl_v[q + 1];
+        const bool last = r.m1 >= R->n_mono;
+        const MonoDesc& a = R->monos[r.m0];
+        r.mat0 = a.mat_off;
+        r.dif0 = a.dif_off;
+        r.raw0 = a.raw_off;
+        r.eps0 = a.eps_off;
+        r.mat1 = last ? R->mat_elems : R->monos[r.m1].mat_off;
+        r.dif1 = last ? R->dif_elems : R->monos[r.m1].dif_off;
+        r.raw1 = last ? R->raw_elems : R->monos[r.m1].raw_off;
+        r.eps1 = last ? R->eps_elems : R->monos[r.m1].eps_off;
+        return r;
+    };
+    std::vector<Span> sp(n_cl);
+    std::vector<Span> dst(n_cl);
+    int64_t mat = 0, dif = 0, raw = 0, eps = 0;
+    for (int k = 0; k < n_cl; ++k) {
+        const Resident* R = parts[k].first;
+        const int q = parts[k].second;
+        const Span a = sp[k] = span_of(R, q);
+        Span& b = dst[k];
+        b.m0 = M->cl_mono[k];
+        b.p0 = M->cl_pair[k];
+        b.v0 = M->cl_v[k];
+        b.mat0 = mat;
+        b.dif0 = dif;
+        b.raw0 = raw;
+        b.eps0 = eps;
+        for (int64_t i = a.m0; i < a.m1; ++i) {
+            MonoDesc d = R->monos[i];
+            d.mat_off += b.mat0 - a.mat0;
+            d.dif_off += b.dif0 - a.dif0;
+            d.raw_off += b.raw0 - a.raw0;
+            d.eps_off += b.eps0 - a.eps0;
+            d.cluster = k;
+            M->monos.push_back(d);
+            M->max_n = std::max(M->max_n, d.n);
+            M->max_v = std::max(M->max_v, d.v);
+            M->max_np = std::max(M->max_np, d.np);
+        }
+        for (const PairDesc& pd : R->pairs) {
+            if (pd.cluster != q) continue;
+            PairDesc e = pd;
+            e.x = (int)(e.x + b.m0 - a.m0);
+            e.y = (int)(e.y + b.m0 - a.m0);
+            e.v_off += b.v0 - a.v0;
+            e.orig += b.p0 - a.p0;
+            e.cluster = k;
+            M->pairs.push_back(e);
+        }
+        M->cl_mono[k + 1] = b.m0 + (a.m1 - a.m0);
+        M->cl_pair[k + 1] = b.p0 + (a.p1 - a.p0);
+        M->cl_v[k + 1] = b.v0 + (a.v1 - a.v0);
+        mat += a.mat1 - a.mat0;
+        dif += a.dif1 - a.dif0;
+        raw += a.raw1 - a.raw0;
+        eps += a.eps1 - a.eps0;
+        if (!R->cl_bad.empty()) M->cl_bad[k] = R->cl_bad[q];
+    }
+    if (M->cl_mono[n_cl] > INT32_MAX) return fail(MCPT_ERR_INVALID, "too many monomers");
+    M->n_mono = (int)M->cl_mono[n_cl];
+    M->n_pair = M->cl_pair[n_cl];
+    M->v_elems = M->cl_v[n_cl];
+    M->mat_elems = mat;
+    M->dif_elems = dif;
+    M->raw_elems = raw;
+    M->eps_elems = eps;
+    for (const PairDesc& d : M->pairs)
+        M->max_slot = std::max<int64_t>(M->max_slot, (int64_t)M->monos[d.x].np * M->monos[d.y].np);
+    order_pairs(M);
+#define ALLOC(ptr, n)                                          \
+    do {                                                       \
+        if ((st = dev_alloc(c, M, &(ptr), (n))) != MCPT_OK) { \
+            free_resident(c, M);                               \
+            return st;                                         \
+        }                                                      \
+    } while (0)
+    ALLOC(M->d_monos, M->n_mono);
+    ALLOC(M->d_pairs, std::max<int64_t>(M->n_pair, 1));
+    ALLOC(M->d_dif, M->dif_elems);
+    ALLOC(M->d_raw, M->raw_elems);
+    ALLOC(M->d_K, M->mat_elems);
+    ALLOC(M->d_T, M->mat_elems);
+    ALLOC(M->d_M, M->mat_elems);
+    ALLOC(M->d_G[0], M->mat_elems);
+    ALLOC(M->d_G[1], M->mat_elems);
+    ALLOC(M->d_V, std::max<int64_t>(M->v_elems, 1));
+    ALLOC(M->d_em2, M->n_mono);
+    ALLOC(M->d_em2_0, M->n_mono);
+    ALLOC(M->d_res, M->n_mono);
+    ALLOC(M->d_ed2, std::max<int64_t>(M->n_pair, 1));
+    ALLOC(M->d_cl, n_cl);
+    ALLOC(M->d_hist, (int64_t)n_cl * kMaxSweeps);
+    ALLOC(M->d_cl_mono, n_cl + 1);
+    ALLOC(M->d_cl_pair, n_cl + 1);
+#undef ALLOC
+    hipStream_t s = x.stream;
+    struct Copy {
+        void* dst;
+        const void* src;
+        size_t bytes;
+    };
+    std::vector<Copy> copies;   // device to device
+    auto dd = [&](void* d, const void* src, int64_t bytes) {
+        if (bytes > 0) copies.push_back({d, src, (size_t)bytes});
+    };
+    for (int k = 0; k < n_cl; ++k) {
+        const Resident* R = parts[k].first;
+        const int q = parts[k].second;
+        const Span& a = sp[k];
+        const Span& b = dst[k];
+        const int64_t D = sizeof(double);
+        dd(M->d_dif + b.dif0, R->d_dif + a.dif0, (a.dif1 - a.dif0) * D);
+        dd(M->d_K + b.mat0, R->d_K + a.mat0, (a.mat1 - a.mat0) * D);
+        dd(M->d_T + b.mat0, R->d_T + a.mat0, (a.mat1 - a.mat0) * D);
+        dd(M->d_M + b.mat0, R->d_M + a.mat0, (a.mat1 - a.mat0) * D);
+        dd(M->d_V + b.v0, R->d_V + a.v0, (a.v1 - a.v0) * D);
+        dd(M->d_em2 + b.m0, R->d_em2 + a.m0, (a.m1 - a.m0) * D);
+        dd(M->d_em2_0 + b.m0, R->d_em2_0 + a.m0, (a.m1 - a.m0) * D);
+        dd(M->d_res + b.m0, R->d_res + a.m0, (a.m1 - a.m0) * D);
+        dd(M->d_ed2 + b.p0, R->d_ed2 + a.p0, (a.p1 - a.p0) * D);
+        dd(M->d_cl + k, R->d_cl + q, (int64_t)sizeof(ClState));
+        dd(M->d_hist + (int64_t)k * kMaxSweeps, R->d_hist + (int64_t)q * kMaxSweeps, kMaxSweeps * D);
+    }
+    hipError_t e = hipSuccess;
+    for (const Copy& cp : copies) {
+        e = hipMemcpyAsync(cp.dst, cp.src, cp.bytes, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) break;
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(M->d_monos, M->monos.data(), M->monos.size() * sizeof(MonoDesc), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && M->n_pair)
+        e = hipMemcpyAsync(M->d_pairs, M->pairs.data(), M->pairs.size() * sizeof(PairDesc), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(M->d_cl_mono, M->cl_mono.data(), (n_cl + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(M->d_cl_pair, M->cl_pair.data(), (n_cl + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        // both G buffers zero: the next sweep accumulates into one and its update clears the other
+        launch_fill(M->d_G[0], M->mat_elems, 0.0, s);
+        launch_fill(M->d_G[1], M->mat_elems, 0.0, s);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        free_resident(c, M);
+        return fail(MCPT_ERR_DEVICE, std::string("joining batches: ") + hipGetErrorString(e));
+    }
+    M->g_cur = 0;
+    M->internal = true;
+    M->cl_last.assign(n_cl, mcpt_summary{});
+    std::lock_guard<std::mutex> g(c->mu);
+    M->id = c->next_id++;
+    *id_out = M->id;
+    c->res[M->id] = std::move(m);
     return MCPT_OK;
 }
 

@@ -142,7 +142,7 @@ mcpt_status parse_tune_table(const char* text, const int* shapes, int n_shapes,
 bool same_options(const mcpt_options& a, const mcpt_options& b) {
     return a.tol == b.tol && a.max_sweeps == b.max_sweeps && a.precision == b.precision && a.polish == b.polish &&
            a.check_every == b.check_every && a.inner_sweeps == b.inner_sweeps && a.graph == b.graph &&
-           !a.warm_t && !b.warm_t;
+           a.deterministic == b.deterministic && !a.warm_t && !b.warm_t;
 }
 
 int size_class(const mcpt_problem& p) {
@@ -175,6 +175,32 @@ std::vector<size_t> form_batch(const std::vector<QueuedRequest>& queue, size_t f
         if (head.opts->warm_t) break;   // a warm start runs alone
     }
     return group;
+}
+
+bool joinable(const mcpt_options& o) {
+    return o.precision == MCPT_FP64 && !o.graph && !o.deterministic && !o.warm_t && o.max_sweeps > 0;
+}
+
+std::vector<size_t> join_batch(const std::vector<QueuedRequest>& queue, size_t free_bytes, const mcpt_options& batch,
+                               int batch_class, int live, int64_t live_pairs, size_t live_bytes, int max_batch,
+                               int64_t max_batch_pairs) {
+    std::vector<size_t> take;
+    if (!joinable(batch)) return take;
+    size_t used = 0;
+    int64_t pairs = live_pairs;
+    int n = live;
+    for (size_t i = 0; i < queue.size() && n < max_batch; ++i) {
+        const QueuedRequest& r = queue[i];
+        if (!same_options(*r.opts, batch) || std::abs(r.size_class - batch_class) > 1 ||
+            pairs + r.n_pair > max_batch_pairs || r.footprint > (free_bytes - used) / 2)
+            break;
+        take.push_back(i);
+        used += 2 * r.footprint;
+        pairs += r.n_pair;
+        ++n;
+    }
+    if (used / 2 < live_bytes) take.clear();   // copying the unfinished clusters would cost more than the joiners
+    return take;
 }
 
 }  // namespace mcpt

@@ -66,4 +66,21 @@ struct QueuedRequest {
 std::vector<size_t> form_batch(const std::vector<QueuedRequest>& queue, size_t free_bytes, int max_batch,
                                int64_t max_batch_pairs);
 
+// Serving at sweep ticks: the queued requests that join a running FP64 batch whose clusters
+// run with options `batch` and whose first request had size class batch_class, now holding
+// `live` unfinished requests with live_pairs pairs.  Joiners are taken from the head of the
+// queue, in order, while each has the batch's options (FP64 plain sweeps, at least one: no
+// reduced precision, graphs, deterministic accumulation or warm start), a size class within one
+// of batch_class, and room in max_batch, max_batch_pairs and free_bytes, where each costs twice
+// its footprint (its upload, then its copy in the merged batch).  The first request that does
+// not qualify ends the run, so a request a running batch cannot take is never overtaken by joins:
+// the batches drain and a free worker takes it.  A join copies the unfinished clusters
+// (live_bytes of footprint) into the merged batch: it happens only when the joiners' footprint
+// is at least that, i.e. near the end of a batch, where merging fills launches that its last
+// clusters alone would leave mostly idle.
+bool joinable(const mcpt_options& o);
+std::vector<size_t> join_batch(const std::vector<QueuedRequest>& queue, size_t free_bytes, const mcpt_options& batch,
+                               int batch_class, int live, int64_t live_pairs, size_t live_bytes, int max_batch,
+                               int64_t max_batch_pairs);
+
 }  // namespace mcpt

@@ -46,6 +46,7 @@ struct Resident {
     int n_cl = 1;
     std::vector<int64_t> cl_mono, cl_pair;
     int64_t *d_cl_mono = nullptr, *d_cl_pair = nullptr;
+    std::vector<int64_t> cl_v;        // first V element of each cluster (n_cl + 1)
     ClState* d_cl = nullptr;
     double* d_hist = nullptr;
     std::vector<mcpt_summary> cl_last;
@@ -119,7 +120,11 @@ struct Resident {
     size_t det_bytes = 0;
     // served batches: owned by the scheduler, never visible to the caller under this id
     bool internal = false;
-    int refs = 0;                 // tickets still holding this batch's results
+    int refs = 0;                 // tickets still holding this batch's results, + 1 while a worker runs it
+    // served batches with admission at sweep ticks: the G buffer the next sweep accumulates
+    // into, and the cluster selection of the energy pass of clusters that finished
+    int g_cur = 0;
+    ClState* d_cl_sel = nullptr;
 };
 
 struct Timing {
@@ -232,6 +237,7 @@ struct ServeParams {
     int workers = 4;                    // concurrent streams, each running one batch at a time
     int max_batch = 32;                 // requests fused into one batch
     int64_t max_batch_pairs = 1 << 20;  // pair budget of one batch
+    int tick_mode = MCPT_SERVE_RETIRE_AT_TICKS;   // mcpt_serve_tick_mode: what FP64 batches do at sweep ticks
 };
 
 struct Server {
@@ -246,6 +252,7 @@ struct Server {
     bool stop = false;
     int busy = 0;                       // workers running a batch (mu)
     uint64_t batches = 0, served = 0;   // counters (mu)
+    uint64_t joined = 0;                // requests admitted into running batches at sweep ticks (mu)
 };
 
 }  // namespace mcpt
@@ -278,6 +285,20 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
 void release_resident(mcpt_ctx* c, uint64_t id);   // takes mu itself
 mcpt_status slice_results(mcpt_ctx* c, Exec& x, Resident* R, int q, double* e_m2, double* de_m2, double* e_d2,
                           double* t_amp);
+// Served FP64 batches with admission at sweep ticks (the plain Jacobi form only):
+// join_init starts the iteration of a freshly uploaded batch (T = D K, every cluster
+// at sweep 0, clusters with non-finite inputs stopped); join_sweeps runs `every`
+// sweeps and returns every cluster's state; join_finish computes the energies of
+// finished clusters, whose results then stay readable in the batch (slice_results)
+// while its other clusters go on (*has: a result exists - converged or out of
+// sweeps; *sums the summaries); join_concat builds one batch from clusters of
+// several batches, keeping each cluster's iteration state, so its sweeps continue
+// exactly where they stopped.
+mcpt_status join_init(mcpt_ctx* c, Exec& x, Resident* R);
+mcpt_status join_sweeps(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, std::vector<ClState>* cs);
+mcpt_status join_finish(mcpt_ctx* c, Exec& x, Resident* R, const std::vector<int>& qs, const mcpt_options* o,
+                        std::vector<char>* has, std::vector<mcpt_summary>* sums);
+mcpt_status join_concat(mcpt_ctx* c, Exec& x, const std::vector<std::pair<Resident*, int>>& parts, uint64_t* id);
 void serve_stop(mcpt_ctx* c);
 bool serve_owns(mcpt_ctx* c, uint64_t ticket);
 mcpt_status serve_energy(mcpt_ctx* c, uint64_t ticket, double* e_m2, double* de_m2, double* e_d2, double* t_amp);

@@ -10,8 +10,11 @@
 // request's result is the one its own solve gives.  Requests that arrive while
 // batches run are taken by the next free worker: the workers' streams run
 // concurrently, so batches overlap on the device, and a request never waits
-// for the whole queue to drain.  Results stay resident on the device until the
-// ticket is released; the memory they hold counts against the admission budget.
+// for the whole queue to drain.  FP64 batches of plain sweeps work at sweep
+// ticks (run_joined): at each host check their finished requests retire, and,
+// in the join mode, compatible queued requests join the running clusters in one
+// batch.  Results stay resident on the device until the ticket is released; the
+// memory they hold counts against the admission budget.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -86,6 +89,213 @@ bool head_fits(mcpt_ctx* c, Server& S) {
     return c->in_use + c->reserved + h->footprint <= c->budget;
 }
 
+// A served FP64 batch with admission at sweep ticks; request mem[q] is cluster q of the
+// running batch.  At every host check the clusters that finished are reported; their results
+// stay readable in the batch (its other clusters' sweeps skip them) until their tickets are
+// released.  While every worker is busy, compatible requests at the head of the queue are
+// uploaded and joined with the unfinished clusters into a new batch that continues each
+// cluster's iteration where it stopped, so a request's sweeps and result are those of its own
+// solve.  A batch is freed once neither a worker runs it nor a ticket holds results in it
+// (Resident::refs).  Called and returns without mu; the caller's reservation x.reserved is kept
+// equal to the unfinished requests' footprint (plus twice the joiners' while they come in).
+void run_joined(mcpt_ctx* c, Server& S, Exec& x, std::vector<Request*> mem) {
+    const mcpt_options o = mem.front()->opts;
+    const int cls = mem.front()->size_class;
+    auto report = [&](Request* r, const mcpt_summary& sm, uint64_t res, int q, const std::string& err, double t) {
+        r->sum = sm;
+        r->batch = res;
+        r->cluster = q;
+        if (sm.status != MCPT_OK) r->error = err.empty() ? "request did not converge" : err;
+        r->sum.seconds = t - r->t_submit;   // latency: submission to result
+        r->state = 2;
+        ++S.served;
+    };
+    auto fail_group = [&](const std::vector<Request*>& g, mcpt_status st) {
+        const std::string err = last_error_text();
+        const double t = now_s();
+        std::lock_guard<std::mutex> lg(c->mu);
+        for (Request* r : g) {
+            mcpt_summary sm{};
+            sm.status = st == MCPT_OK ? MCPT_ERR_DEVICE : st;
+            report(r, sm, 0, 0, err, t);
+        }
+        S.done_cv.notify_all();
+        S.cv.notify_all();
+    };
+    auto reserve = [&](size_t bytes) {   // under mu
+        c->reserved -= std::min(c->reserved, x.reserved);
+        x.reserved = bytes;
+        c->reserved += bytes;
+    };
+    auto leave = [&](uint64_t id) {   // the worker's hold on a batch ends; freed if no ticket holds results
+        bool drop = false;
+        {
+            std::lock_guard<std::mutex> lg(c->mu);
+            drop = --c->res[id]->refs == 0;
+        }
+        if (drop) release_resident(c, id);
+    };
+    auto start = [&](std::vector<Request*>& g, uint64_t* id) -> mcpt_status {
+        std::vector<mcpt_problem> probs;
+        probs.reserve(g.size());
+        for (Request* r : g) probs.push_back(r->prob);
+        mcpt_status st;
+        try {
+            st = upload_batch(c, x, probs.data(), (int)probs.size(), true, id);
+        } catch (const std::exception& e) {
+            st = fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
+        }
+        for (Request* r : g) {   // the device holds the inputs now (or the upload failed)
+            r->k_intra.reset();
+            r->v_dimer.reset();
+            r->prob.k_intra = r->prob.v_dimer = nullptr;
+        }
+        if (st != MCPT_OK) return st;
+        Resident* B = nullptr;
+        {
+            std::lock_guard<std::mutex> lg(c->mu);
+            B = c->res[*id].get();
+            B->refs = 1;
+        }
+        if ((st = join_init(c, x, B)) != MCPT_OK) release_resident(c, *id);
+        return st;
+    };
+    uint64_t rid = 0;
+    mcpt_status st = start(mem, &rid);
+    if (st != MCPT_OK) {
+        fail_group(mem, st);
+        return;
+    }
+    Resident* R = nullptr;
+    {
+        std::lock_guard<std::mutex> lg(c->mu);
+        R = c->res[rid].get();
+    }
+    std::vector<char> done(mem.size(), 0);
+    for (;;) {
+        std::vector<ClState> cs;
+        st = join_sweeps(c, x, R, &o, &cs);
+        std::vector<int> fin, live;
+        std::vector<char> has;
+        std::vector<mcpt_summary> sums;
+        if (st == MCPT_OK) {
+            for (size_t q = 0; q < mem.size(); ++q) {
+                if (cs[q].done && !done[q]) fin.push_back((int)q);
+                if (!cs[q].done) live.push_back((int)q);
+            }
+            if (!fin.empty()) st = join_finish(c, x, R, fin, &o, &has, &sums);
+        }
+        if (st != MCPT_OK) {
+            std::vector<Request*> rest;
+            for (size_t q = 0; q < mem.size(); ++q)
+                if (!done[q]) rest.push_back(mem[q]);
+            fail_group(rest, st);
+            leave(rid);
+            return;
+        }
+        std::vector<Request*> joiners;
+        {
+            std::lock_guard<std::mutex> lg(c->mu);
+            const double t = now_s();
+            for (size_t i = 0; i < fin.size(); ++i) {
+                report(mem[fin[i]], sums[i], has[i] ? rid : 0, fin[i], std::string(), t);
+                if (has[i]) ++R->refs;
+                done[fin[i]] = 1;
+            }
+            size_t fp_live = 0;
+            int64_t live_pairs = 0;
+            for (int q : live) {
+                fp_live += mem[q]->footprint;
+                live_pairs += mem[q]->prob.n_pair;
+            }
+            reserve(fp_live);
+            const size_t used = c->in_use + (c->reserved - x.reserved) + fp_live;
+            // joins below saturation only: a join pauses this batch for the joiners' upload, which a
+            // new batch on a free worker overlaps with the other batches' sweeps; with more requests
+            // queued than workers, batches formed at their start keep the device as busy
+            if (S.params.tick_mode == MCPT_SERVE_JOIN_AT_TICKS && !S.stop && !S.queue.empty() &&
+                S.busy >= (int)S.workers.size() &&
+                S.queue.size() <= S.workers.size() && used < c->budget) {
+                std::vector<QueuedRequest> view;
+                view.reserve(S.queue.size());
+                for (uint64_t tk : S.queue) {
+                    const Request* r = S.reqs[tk].get();
+                    view.push_back({r->footprint, r->prob.n_pair, r->size_class, &r->opts});
+                }
+                const std::vector<size_t> take =
+                    join_batch(view, c->budget - used, o, cls, (int)live.size(), live_pairs, fp_live,
+                               S.params.max_batch, S.params.max_batch_pairs);
+                size_t add = 0;
+                for (size_t i : take) {
+                    Request* r = S.reqs[S.queue[i]].get();
+                    r->state = 1;
+                    joiners.push_back(r);
+                    add += 2 * r->footprint;
+                }
+                for (size_t k = take.size(); k-- > 0;) S.queue.erase(S.queue.begin() + (std::ptrdiff_t)take[k]);
+                reserve(fp_live + add);
+                S.joined += joiners.size();
+            }
+            if (!fin.empty()) {
+                S.done_cv.notify_all();
+                S.cv.notify_all();
+            }
+        }
+        if (!joiners.empty()) {
+            uint64_t bid = 0;
+            bool replaced = false;   // the running batch is now another one, with clusters mem
+            st = start(joiners, &bid);
+            if (st != MCPT_OK) {
+                fail_group(joiners, st);   // the running clusters go on without them
+            } else if (live.empty()) {     // nothing to carry over: the joiners' batch runs as it is
+                leave(rid);
+                rid = bid;
+                mem = joiners;
+                replaced = true;
+            } else {
+                Resident* B = nullptr;
+                {
+                    std::lock_guard<std::mutex> lg(c->mu);
+                    B = c->res[bid].get();
+                }
+                std::vector<std::pair<Resident*, int>> parts;
+                for (int q : live) parts.push_back({R, q});
+                for (int k = 0; k < (int)joiners.size(); ++k) parts.push_back({B, k});
+                uint64_t mid = 0;
+                st = join_concat(c, x, parts, &mid);
+                if (st != MCPT_OK) {
+                    fail_group(joiners, st);
+                } else {
+                    {
+                        std::lock_guard<std::mutex> lg(c->mu);
+                        c->res[mid]->refs = 1;
+                    }
+                    leave(rid);
+                    rid = mid;
+                    std::vector<Request*> next;
+                    for (int q : live) next.push_back(mem[q]);
+                    next.insert(next.end(), joiners.begin(), joiners.end());
+                    mem = next;
+                    replaced = true;
+                }
+                leave(bid);
+            }
+            if (replaced) done.assign(mem.size(), 0);
+            std::lock_guard<std::mutex> lg(c->mu);
+            R = c->res[rid].get();
+            size_t fp = 0;
+            for (size_t q = 0; q < mem.size(); ++q)
+                if (!done[q]) fp += mem[q]->footprint;
+            reserve(fp);
+            continue;
+        }
+        if (live.empty()) {
+            leave(rid);
+            return;
+        }
+    }
+}
+
 void worker_loop(mcpt_ctx* c, int w) {
     Server& S = *c->server;
     Exec& x = *S.execs[w];
@@ -117,6 +327,17 @@ void worker_loop(mcpt_ctx* c, int w) {
         c->reserved += reserve;
         ++S.busy;
         lk.unlock();
+        if (S.params.tick_mode != MCPT_SERVE_BATCH_END && joinable(head->opts)) {
+            run_joined(c, S, x, group);
+            lk.lock();
+            c->reserved -= std::min(c->reserved, x.reserved);
+            x.reserved = 0;
+            --S.busy;
+            ++S.batches;
+            S.done_cv.notify_all();
+            S.cv.notify_all();
+            continue;
+        }
 
         // ---- upload and solve the batch on this worker's stream ----
         std::vector<mcpt_problem> probs;
@@ -348,6 +569,17 @@ mcpt_status mcpt_serve_config(mcpt_ctx* c, int32_t workers, int32_t max_batch, i
     return MCPT_OK;
 }
 
+mcpt_status mcpt_serve_tick_mode(mcpt_ctx* c, int32_t mode) {
+    if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
+    if (mode < MCPT_SERVE_BATCH_END || mode > MCPT_SERVE_JOIN_AT_TICKS)
+        return fail(MCPT_ERR_INVALID, "mode must be MCPT_SERVE_BATCH_END, _RETIRE_AT_TICKS or _JOIN_AT_TICKS");
+    Server& S = server_of(c);
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!S.workers.empty()) return fail(MCPT_ERR_INVALID, "the scheduler is already running");
+    S.params.tick_mode = mode;
+    return MCPT_OK;
+}
+
 mcpt_status mcpt_serve_staging(mcpt_ctx* c, uint64_t bytes) {
     if (!c) return fail(MCPT_ERR_INVALID, "ctx is NULL");
     Server& S = server_of(c);
@@ -457,6 +689,7 @@ mcpt_status mcpt_serve_stats(mcpt_ctx* c, mcpt_serve_counters* out) {
     for (const auto& kv : S.reqs) out->tickets += 1;
     out->staging_pinned_bytes = S.pool.held();
     out->staged_pageable = S.pool.pageable();
+    out->joined_at_ticks = S.joined;
     return MCPT_OK;
 }
 

@@ -26,6 +26,7 @@ MCPT_ERR_UNKNOWN_ID = -8
 
 MCPT_FP64, MCPT_FP32, MCPT_BF16 = 0, 1, 2
 MCPT_HOST, MCPT_DEVICE = 0, 1
+MCPT_SERVE_BATCH_END, MCPT_SERVE_RETIRE_AT_TICKS, MCPT_SERVE_JOIN_AT_TICKS = 0, 1, 2
 
 STATUS_NAMES = {
     0: "MCPT_OK", 1: "MCPT_PENDING", -1: "MCPT_ERR_INVALID", -2: "MCPT_ERR_NOMEM",
@@ -42,6 +43,7 @@ EXPORTS = [
     "mcpt_autotune", "mcpt_tune_export", "mcpt_tune_import", "mcpt_singles", "mcpt_singles_result",
     "mcpt_lccd_attach", "mcpt_upload_scaled", "mcpt_fd_stencil", "mcpt_dimer_attach",
     "mcpt_run_static", "mcpt_dimer_tau", "mcpt_device_rates", "mcpt_serve_staging",
+    "mcpt_serve_tick_mode",
 ]
 
 
@@ -141,6 +143,7 @@ class mcpt_serve_counters(C.Structure):
         ("bytes_in_use", C.c_uint64), ("bytes_reserved", C.c_uint64), ("queued", C.c_int32),
         ("running_batches", C.c_int32), ("workers", C.c_int32), ("tickets", C.c_int32),
         ("staging_pinned_bytes", C.c_uint64), ("staged_pageable", C.c_uint64),
+        ("joined_at_ticks", C.c_uint64),
     ]
 
     def as_dict(self) -> dict:
@@ -186,6 +189,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.mcpt_cluster_results.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(mcpt_summary)]
     lib.mcpt_serve_config.argtypes = [P, C.c_int32, C.c_int32, C.c_int64]
     lib.mcpt_serve_staging.argtypes = [P, C.c_uint64]
+    lib.mcpt_serve_tick_mode.argtypes = [P, C.c_int32]
     lib.mcpt_submit.argtypes = [P, C.POINTER(mcpt_problem), C.POINTER(mcpt_options), C.POINTER(C.c_uint64)]
     lib.mcpt_poll.argtypes = [P, C.c_uint64, C.POINTER(mcpt_summary)]
     lib.mcpt_wait.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(mcpt_summary)]
@@ -524,6 +528,11 @@ class Context:
     def serve_staging(self, nbytes: int):
         """mcpt_serve_staging: cap of the pinned host staging of submitted requests."""
         _check(lib().mcpt_serve_staging(self.h, nbytes))
+
+    def serve_tick_mode(self, mode: int):
+        """mcpt_serve_tick_mode: MCPT_SERVE_BATCH_END, MCPT_SERVE_RETIRE_AT_TICKS (default) or
+        MCPT_SERVE_JOIN_AT_TICKS."""
+        _check(lib().mcpt_serve_tick_mode(self.h, mode))
 
     def submit(self, prob, **opts) -> int:
         """Queue one solve; returns its ticket (usable with energy / release once done)."""

@@ -219,6 +219,83 @@ static void test_batches() {
         if (q[0].opts->warm_t) CHECK(g.size() == 1);
     }
     CHECK(form_batch({}, 100, 4, 100).empty());
+    mcpt_options det = base;
+    det.deterministic = 1;
+    CHECK(!same_options(base, det));
+}
+
+// Admission at sweep ticks into a running FP64 batch: the head of the queue, in order, while
+// each request is compatible, priced at twice its footprint, and within the batch's request and
+// pair limits; the first that does not qualify ends the run.
+static void test_joins() {
+    std::mt19937_64 rng(27001409);
+    mcpt_options base{};
+    base.tol = 1e-10;
+    base.max_sweeps = 200;
+    mcpt_options lowp = base, det = base, graph = base;
+    lowp.precision = MCPT_BF16;
+    det.deterministic = 1;
+    graph.graph = 1;
+    const double warm = 0.0;
+    mcpt_options warm_opts = base;
+    warm_opts.warm_t = &warm;
+    CHECK(joinable(base));
+    mcpt_options none = base;
+    none.max_sweeps = 0;
+    CHECK(!joinable(lowp) && !joinable(det) && !joinable(graph) && !joinable(warm_opts) && !joinable(none));
+    const mcpt_options* kinds[5] = {&base, &lowp, &det, &graph, &warm_opts};
+    for (int trial = 0; trial < 2000; ++trial) {
+        const int n = (int)(rng() % 40);
+        std::vector<QueuedRequest> q;
+        for (int i = 0; i < n; ++i) {
+            const int kind = (int)(rng() % 8);
+            q.push_back({(size_t)(1 + rng() % 1000), (int64_t)(rng() % 5000), (int)(20 + rng() % 6),
+                         kind < 4 ? kinds[kind] : (kind == 4 ? kinds[4] : &base)});
+        }
+        const mcpt_options& batch = trial % 5 == 0 ? *kinds[rng() % 5] : base;
+        const size_t free_b = (size_t)(rng() % 8000);
+        const int cls = (int)(20 + rng() % 6);
+        const int live = (int)(rng() % 8);
+        const int max_batch = 1 + (int)(rng() % 16);
+        const int64_t live_pairs = (int64_t)(rng() % 10000);
+        const int64_t max_pairs = (int64_t)(rng() % 40000);
+        const size_t live_bytes = trial % 3 == 0 ? (size_t)(rng() % 3000) : 0;
+        const std::vector<size_t> g =
+            join_batch(q, free_b, batch, cls, live, live_pairs, live_bytes, max_batch, max_pairs);
+        if (!joinable(batch)) {
+            CHECK(g.empty());
+            continue;
+        }
+        if (live_bytes) {   // the same scan without the copy rule: taken whole, or not at all
+            const std::vector<size_t> h = join_batch(q, free_b, batch, cls, live, live_pairs, 0, max_batch, max_pairs);
+            size_t fp = 0;
+            for (size_t k : h) fp += q[k].footprint;
+            CHECK(fp >= live_bytes ? g == h : g.empty());
+            if (g.empty()) continue;
+        }
+        size_t used = 0;
+        int64_t pairs = live_pairs;
+        for (size_t k = 0; k < g.size(); ++k) {
+            CHECK(g[k] < q.size());
+            if (k) CHECK(g[k] > g[k - 1]);
+            const QueuedRequest& r = q[g[k]];
+            CHECK(same_options(*r.opts, batch) && joinable(*r.opts));
+            CHECK(std::abs(r.size_class - cls) <= 1);
+            used += 2 * r.footprint;
+            pairs += r.n_pair;
+        }
+        CHECK(used <= free_b);
+        CHECK(pairs <= std::max(max_pairs, live_pairs));
+        CHECK(live + (int)g.size() <= std::max(max_batch, live));
+        // the joiners are the head of the queue, in order, up to the first that does not qualify
+        for (size_t k = 0; k < g.size(); ++k) CHECK(g[k] == k);
+        if (g.size() < q.size() && live + (int)g.size() < max_batch) {
+            const QueuedRequest& r = q[g.size()];
+            CHECK(!same_options(*r.opts, batch) || std::abs(r.size_class - cls) > 1 || pairs + r.n_pair > max_pairs ||
+                  2 * r.footprint > free_b - used);
+        }
+    }
+    CHECK(join_batch({}, 100, base, 20, 0, 0, 0, 4, 100).empty());
 }
 
 static void test_size_class() {
@@ -237,6 +314,7 @@ int main() {
     test_footprint();
     test_tune_parser();
     test_batches();
+    test_joins();
     test_size_class();
     if (failures) {
         std::fprintf(stderr, "%d checks failed\n", failures);

@@ -106,7 +106,7 @@ def test_late_small_requests_overtake_a_large_one():
     small = [make_served_request(1001 + k, min_mono=8, max_mono=8) for k in range(3)]
     with mc.Context(0) as ctx:
         ctx.serve_config(workers=2, max_batch=8)
-        tb = ctx.submit(big, tol=1e-12)
+        tb = ctx.submit(big, tol=0.0, max_sweeps=200)   # fixed sweeps: on the device for a while
         t0 = time.time()
         while ctx.serve_stats()["running_batches"] == 0 and ctx.poll(tb) is None and time.time() - t0 < 10:
             time.sleep(0.0005)
@@ -121,12 +121,25 @@ def test_late_small_requests_overtake_a_large_one():
             assert abs(done_small[t]["e_total"] - s1["e_total"]) <= SAME_RTOL * abs(s1["e_total"])
 
 
+def settled(ctx, timeout_s=30.0):
+    """Serving counters once no batch is on the device (a batch frees its memory
+    just after reporting its last request)."""
+    t0 = time.time()
+    st = ctx.serve_stats()
+    while st["running_batches"] and time.time() - t0 < timeout_s:
+        time.sleep(0.002)
+        st = ctx.serve_stats()
+    return st
+
+
 def test_admission_waits_for_memory():
+    """Admission prices a request at its footprint beside the results finished
+    requests hold (their batch stays on the device until their tickets are released)."""
     probs = [make_served_request(2000, min_mono=30, max_mono=30)] * 3
     with mc.Context(0) as probe:
         t = probe.submit(probs[0], tol=1e-10)
         probe.wait(t, 60000)
-        one = probe.serve_stats()["bytes_in_use"]
+        one = settled(probe)["bytes_in_use"]
     assert one > 0
     with mc.Context(0, hbm_budget=int(2.5 * one)) as ctx:
         ctx.serve_config(workers=3, max_batch=1)
@@ -136,13 +149,74 @@ def test_admission_waits_for_memory():
         assert a["status"] == b["status"] == mc.MCPT_OK
         # both results are held: the third request cannot be admitted
         assert ctx.wait(ts[2], 300) is None
-        st = ctx.serve_stats()
+        st = settled(ctx)
         assert st["queued"] == 1 and st["bytes_in_use"] <= st["budget"]
         ctx.release(ts[0])
         c = ctx.wait(ts[2], 60000)
         assert c is not None and c["status"] == mc.MCPT_OK
         assert abs(c["e_total"] - a["e_total"]) <= SAME_RTOL * abs(a["e_total"])
-        assert ctx.serve_stats()["bytes_in_use"] <= ctx.serve_stats()["budget"]
+        assert settled(ctx)["bytes_in_use"] <= ctx.serve_stats()["budget"]
+
+
+@pytest.mark.parametrize("mode", [mc.MCPT_SERVE_JOIN_AT_TICKS, mc.MCPT_SERVE_RETIRE_AT_TICKS,
+                                  mc.MCPT_SERVE_BATCH_END], ids=["join", "retire", "batch-end"])
+def test_requests_join_a_running_batch(mode):
+    """With the only worker busy and a short queue, a request submitted while a
+    batch runs joins it at a sweep tick: it is uploaded and merged with the
+    batch's unfinished clusters, whose iteration continues where it stopped, and
+    each request retires at the tick where its own solve stops.  Every sweep
+    count and result equals the alone solve's; with admission at ticks off, the
+    request waits for the batch to end."""
+    ticks = mode == mc.MCPT_SERVE_JOIN_AT_TICKS
+    # fixed sweeps keep the first request on the device while the others are copied in; the
+    # joiner is larger than it (a join copies the unfinished clusters, so it needs that)
+    first = make_served_request(3000, min_mono=40, max_mono=40, cutoff=2.0)
+    late = [make_served_request(3001 + k, min_mono=50, max_mono=60, cutoff=2.0) for k in range(4)]
+    opts = dict(tol=0.0, max_sweeps=400, check_every=1)
+    with mc.Context(0) as ctx:
+        ctx.serve_config(workers=1, max_batch=8)
+        ctx.serve_tick_mode(mode)
+        print(f"[gpu] join mode={mode} sizes {first.n_mono} {[p.n_mono for p in late]}", flush=True)
+        t0 = ctx.submit(first, **opts)
+        t_start = time.time()
+        while ctx.serve_stats()["running_batches"] == 0 and time.time() - t_start < 10:
+            time.sleep(0.0002)
+        ts = [ctx.submit(late[0], **opts)]
+        first_running = ctx.poll(t0) is None
+        t_start = time.time()
+        while ticks and ctx.serve_stats()["queued"] and time.time() - t_start < 0.5:
+            time.sleep(0.0002)   # taken by a join at the next tick
+        ts += [ctx.submit(p, **opts) for p in late[1:]]
+        done = wait_all(ctx, [t0] + ts)
+        st = settled(ctx)
+        assert st["completed"] == 5
+        assert first_running, "the first request ended before the second was submitted"
+        if ticks:
+            assert st["joined_at_ticks"] >= 1
+        else:
+            assert st["joined_at_ticks"] == 0
+            assert st["batches"] >= 2
+        check_served(ctx, [first] + late, [t0] + ts, done, **opts)
+        for t in [t0] + ts:
+            ctx.release(t)
+        assert settled(ctx)["bytes_in_use"] == 0
+
+
+def test_joined_requests_retire_one_by_one():
+    """Requests of one batch that stop at different sweeps retire at their own
+    ticks (a converged one does not wait for the others), with results readable
+    while the batch goes on and after it has ended."""
+    probs = [make_served_request(3100 + k, min_mono=60, max_mono=90) for k in range(6)]
+    opts = dict(tol=1e-11, check_every=1)
+    with mc.Context(0) as ctx:
+        ctx.serve_config(workers=1, max_batch=3)
+        ts = [ctx.submit(p, **opts) for p in probs]
+        done = wait_all(ctx, ts)
+        st = settled(ctx)
+        assert st["completed"] == len(probs) and st["tickets"] == len(probs)
+        check_served(ctx, probs, ts, done, **opts)
+        with pytest.raises(mc.MCPTError):
+            ctx.serve_tick_mode(mc.MCPT_SERVE_BATCH_END)   # the scheduler is running
 
 
 def test_submit_errors_and_cancel(requests):
