@@ -274,7 +274,8 @@ def _served_pass(ctx, stream, n_req, arrivals, max_inflight, tol, alone_e):
     return start, lat, err, status, done_t, sub_t, state["submit_s"]
 
 
-def serving(base, n_req, loads, workers, max_batch, tol, max_inflight=32, staging_bytes=64 << 30, mode=None):
+def serving(base, n_req, loads, workers, max_batch, tol, max_inflight=32, staging_bytes=64 << 30, mode=None,
+            compare=(0,)):
     """Served stream (synth.ServedStream: requests cut from the resident crystal,
     sizes log-uniform in [8, N], one monomer displaced), first solved alone one at
     a time on the plain FP64 path (upload + solve), then submitted in a closed
@@ -344,7 +345,7 @@ def serving(base, n_req, loads, workers, max_batch, tol, max_inflight=32, stagin
     out["tick_modes"] = ("batch_end: a batch's requests are reported when its last one stops; retire_at_ticks: "
                          "each request retires at the sweep tick where its solve stops; join_at_ticks: also "
                          "admits queued requests into running batches at ticks (below saturation)")
-    extra = {f"capacity_{modes[m]}": m for m in modes if m != mode}
+    extra = {f"capacity_{modes[m]}": m for m in modes if m != mode and m in compare}
     for load in ["capacity"] + [x for x in loads if x != "burst"] + list(extra):
         if load in extra:
             ctx.close()
@@ -815,7 +816,9 @@ def main():
     ap.add_argument("--serve-batch", type=int, default=16)
     ap.add_argument("--serve-mode", type=int, default=None,
                     help="tick mode of the served passes (0 batch end, 1 retire at ticks, 2 join at ticks; "
-                         "default: the library's); the other modes get one capacity pass each")
+                         "default: the library's)")
+    ap.add_argument("--serve-compare", default="0",
+                    help="comma-separated other tick modes that get one capacity pass each ('' for none)")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="only launch a calibration copy and two fixed sweeps (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-precision", type=int, default=0, help="0 FP64, 1 FP32, 2 BF16 sweeps in --pmc-pass")
@@ -887,7 +890,8 @@ def main():
     served = None
     if args.serve_requests > 0:
         served = serving(prob, args.serve_requests, [0.5, 0.8], args.serve_workers, args.serve_batch,
-                         args.tol, mode=args.serve_mode)
+                         args.tol, mode=args.serve_mode,
+                         compare=tuple(int(m) for m in args.serve_compare.split(",") if m.strip()))
 
     h = results[args.headline]
     tm = h["timing"]

@@ -1978,8 +1978,7 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
 mcpt_status join_init(mcpt_ctx* c, Exec& x, Resident* R) {
     mcpt_status st;
     if ((st = ensure_device(c)) != MCPT_OK) return st;
-    if ((st = ensure_scratch(c, x, R->max_slot)) != MCPT_OK) return st;
-    hipStream_t s = x.stream;
+    hipStream_t s = x.stream;   // no Tau scratch needed here: join_sweeps sizes the sweeping stream's
     std::vector<ClState> cs(R->n_cl, ClState{});
     for (int q = 0; q < R->n_cl; ++q)
         if (!R->cl_bad.empty() && R->cl_bad[q]) {   // never swept; reported as non-finite input

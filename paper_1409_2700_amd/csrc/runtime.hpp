@@ -247,6 +247,7 @@ struct Server {
     std::map<uint64_t, std::unique_ptr<Request>> reqs;   // every live ticket (mu)
     std::vector<std::thread> workers;
     std::vector<std::unique_ptr<Exec>> execs;
+    std::vector<std::unique_ptr<Exec>> uploads;   // per worker: the stream joiners are uploaded on
     std::condition_variable cv;         // queue, memory or stop changed
     std::condition_variable done_cv;    // a request finished
     bool stop = false;

@@ -16,6 +16,7 @@
 // batch.  Results stay resident on the device until the ticket is released; the
 // memory they hold counts against the admission budget.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -92,13 +93,15 @@ bool head_fits(mcpt_ctx* c, Server& S) {
 // A served FP64 batch with admission at sweep ticks; request mem[q] is cluster q of the
 // running batch.  At every host check the clusters that finished are reported; their results
 // stay readable in the batch (its other clusters' sweeps skip them) until their tickets are
-// released.  While every worker is busy, compatible requests at the head of the queue are
-// uploaded and joined with the unfinished clusters into a new batch that continues each
-// cluster's iteration where it stopped, so a request's sweeps and result are those of its own
-// solve.  A batch is freed once neither a worker runs it nor a ticket holds results in it
-// (Resident::refs).  Called and returns without mu; the caller's reservation x.reserved is kept
-// equal to the unfinished requests' footprint (plus twice the joiners' while they come in).
-void run_joined(mcpt_ctx* c, Server& S, Exec& x, std::vector<Request*> mem) {
+// released.  In the join mode, compatible requests at the head of the queue are uploaded on the
+// worker's second stream (xu, from a helper thread) while the batch keeps sweeping, and at the
+// first tick after the upload they are joined with the unfinished clusters into a new batch that
+// continues each cluster's iteration where it stopped, so a request's sweeps and result are
+// those of its own solve.  A batch is freed once neither a worker runs it nor a ticket holds
+// results in it (Resident::refs).  Called and returns without mu; the caller's reservation
+// x.reserved is kept equal to the unfinished requests' footprint (plus twice the joiners' until
+// they are merged).
+void run_joined(mcpt_ctx* c, Server& S, Exec& x, Exec& xu, std::vector<Request*> mem) {
     const mcpt_options o = mem.front()->opts;
     const int cls = mem.front()->size_class;
     auto report = [&](Request* r, const mcpt_summary& sm, uint64_t res, int q, const std::string& err, double t) {
@@ -110,8 +113,7 @@ void run_joined(mcpt_ctx* c, Server& S, Exec& x, std::vector<Request*> mem) {
         r->state = 2;
         ++S.served;
     };
-    auto fail_group = [&](const std::vector<Request*>& g, mcpt_status st) {
-        const std::string err = last_error_text();
+    auto fail_group = [&](const std::vector<Request*>& g, mcpt_status st, const std::string& err) {
         const double t = now_s();
         std::lock_guard<std::mutex> lg(c->mu);
         for (Request* r : g) {
@@ -122,9 +124,9 @@ void run_joined(mcpt_ctx* c, Server& S, Exec& x, std::vector<Request*> mem) {
         S.done_cv.notify_all();
         S.cv.notify_all();
     };
-    auto reserve = [&](size_t bytes) {   // under mu
+    auto reserve = [&](size_t bytes) {   // under mu; an upload on xu leaves this worker's reservation out too
         c->reserved -= std::min(c->reserved, x.reserved);
-        x.reserved = bytes;
+        x.reserved = xu.reserved = bytes;
         c->reserved += bytes;
     };
     auto leave = [&](uint64_t id) {   // the worker's hold on a batch ends; freed if no ticket holds results
@@ -135,13 +137,14 @@ void run_joined(mcpt_ctx* c, Server& S, Exec& x, std::vector<Request*> mem) {
         }
         if (drop) release_resident(c, id);
     };
-    auto start = [&](std::vector<Request*>& g, uint64_t* id) -> mcpt_status {
+    // upload a group as a new batch on stream ex and start its iteration (T = D K)
+    auto start = [&](Exec& ex, std::vector<Request*>& g, uint64_t* id, std::string* err) -> mcpt_status {
         std::vector<mcpt_problem> probs;
         probs.reserve(g.size());
         for (Request* r : g) probs.push_back(r->prob);
         mcpt_status st;
         try {
-            st = upload_batch(c, x, probs.data(), (int)probs.size(), true, id);
+            st = upload_batch(c, ex, probs.data(), (int)probs.size(), true, id);
         } catch (const std::exception& e) {
             st = fail(MCPT_ERR_NOMEM, std::string("host exception: ") + e.what());
         }
@@ -150,20 +153,42 @@ void run_joined(mcpt_ctx* c, Server& S, Exec& x, std::vector<Request*> mem) {
             r->v_dimer.reset();
             r->prob.k_intra = r->prob.v_dimer = nullptr;
         }
-        if (st != MCPT_OK) return st;
-        Resident* B = nullptr;
-        {
-            std::lock_guard<std::mutex> lg(c->mu);
-            B = c->res[*id].get();
-            B->refs = 1;
+        if (st == MCPT_OK) {
+            Resident* B = nullptr;
+            {
+                std::lock_guard<std::mutex> lg(c->mu);
+                B = c->res[*id].get();
+                B->refs = 1;
+            }
+            if ((st = join_init(c, ex, B)) != MCPT_OK) release_resident(c, *id);
         }
-        if ((st = join_init(c, x, B)) != MCPT_OK) release_resident(c, *id);
+        if (st != MCPT_OK) *err = last_error_text();   // the error text is per thread
         return st;
     };
+    // joiners on their way to the device
+    struct Pending {
+        std::vector<Request*> g;
+        size_t bytes = 0;          // their reservation: twice their footprint
+        uint64_t bid = 0;
+        mcpt_status st = MCPT_OK;
+        std::string err;
+        std::atomic<bool> finished{false};
+        std::thread th;
+    };
+    std::unique_ptr<Pending> pend;
+    auto finish_upload = [&]() {   // wait for the helper thread; on failure the joiners fail
+        pend->th.join();
+        if (pend->st != MCPT_OK) {
+            fail_group(pend->g, pend->st, pend->err);
+            pend.reset();
+        }
+    };
+
     uint64_t rid = 0;
-    mcpt_status st = start(mem, &rid);
+    std::string err0;
+    mcpt_status st = start(x, mem, &rid, &err0);
     if (st != MCPT_OK) {
-        fail_group(mem, st);
+        fail_group(mem, st, err0);
         return;
     }
     Resident* R = nullptr;
@@ -186,10 +211,18 @@ void run_joined(mcpt_ctx* c, Server& S, Exec& x, std::vector<Request*> mem) {
             if (!fin.empty()) st = join_finish(c, x, R, fin, &o, &has, &sums);
         }
         if (st != MCPT_OK) {
+            const std::string err = last_error_text();
             std::vector<Request*> rest;
             for (size_t q = 0; q < mem.size(); ++q)
                 if (!done[q]) rest.push_back(mem[q]);
-            fail_group(rest, st);
+            if (pend) {   // the joiners fail with the batch they were to join
+                finish_upload();
+                if (pend) {
+                    leave(pend->bid);
+                    rest.insert(rest.end(), pend->g.begin(), pend->g.end());
+                }
+            }
+            fail_group(rest, st, err);
             leave(rid);
             return;
         }
@@ -208,14 +241,14 @@ void run_joined(mcpt_ctx* c, Server& S, Exec& x, std::vector<Request*> mem) {
                 fp_live += mem[q]->footprint;
                 live_pairs += mem[q]->prob.n_pair;
             }
-            reserve(fp_live);
-            const size_t used = c->in_use + (c->reserved - x.reserved) + fp_live;
-            // joins below saturation only: a join pauses this batch for the joiners' upload, which a
-            // new batch on a free worker overlaps with the other batches' sweeps; with more requests
-            // queued than workers, batches formed at their start keep the device as busy
-            if (S.params.tick_mode == MCPT_SERVE_JOIN_AT_TICKS && !S.stop && !S.queue.empty() &&
-                S.busy >= (int)S.workers.size() &&
-                S.queue.size() <= S.workers.size() && used < c->budget) {
+            const size_t pending = pend ? pend->bytes : 0;
+            reserve(fp_live + pending);
+            const size_t used = c->in_use + (c->reserved - x.reserved) + fp_live + pending;
+            // joins below saturation only: with more requests queued than workers, batches formed at
+            // their start keep the device as busy; one group of joiners at a time
+            if (S.params.tick_mode == MCPT_SERVE_JOIN_AT_TICKS && !pend && !live.empty() && !S.stop &&
+                !S.queue.empty() && S.busy >= (int)S.workers.size() && S.queue.size() <= S.workers.size() &&
+                used < c->budget) {
                 std::vector<QueuedRequest> view;
                 view.reserve(S.queue.size());
                 for (uint64_t tk : S.queue) {
@@ -233,24 +266,41 @@ void run_joined(mcpt_ctx* c, Server& S, Exec& x, std::vector<Request*> mem) {
                     add += 2 * r->footprint;
                 }
                 for (size_t k = take.size(); k-- > 0;) S.queue.erase(S.queue.begin() + (std::ptrdiff_t)take[k]);
-                reserve(fp_live + add);
-                S.joined += joiners.size();
+                if (!joiners.empty()) {
+                    reserve(fp_live + add);
+                    S.joined += joiners.size();
+                }
             }
             if (!fin.empty()) {
                 S.done_cv.notify_all();
                 S.cv.notify_all();
             }
         }
-        if (!joiners.empty()) {
-            uint64_t bid = 0;
-            bool replaced = false;   // the running batch is now another one, with clusters mem
-            st = start(joiners, &bid);
-            if (st != MCPT_OK) {
-                fail_group(joiners, st);   // the running clusters go on without them
-            } else if (live.empty()) {     // nothing to carry over: the joiners' batch runs as it is
+        if (!joiners.empty()) {   // upload them while the batch goes on sweeping
+            pend = std::make_unique<Pending>();
+            pend->g = joiners;
+            for (Request* r : joiners) pend->bytes += 2 * r->footprint;
+            Pending* pp = pend.get();
+            pp->th = std::thread([&start, &xu, pp] {
+                pp->st = start(xu, pp->g, &pp->bid, &pp->err);
+                pp->finished.store(true, std::memory_order_release);
+            });
+        }
+        // merge a finished upload (or wait for it when nothing else is left to sweep)
+        bool ready = false;
+        if (pend && (live.empty() || pend->finished.load(std::memory_order_acquire))) {
+            finish_upload();
+            ready = pend != nullptr;
+        }
+        if (ready) {
+            const uint64_t bid = pend->bid;
+            std::vector<Request*> jg = pend->g;
+            pend.reset();
+            bool replaced = false;
+            if (live.empty()) {   // nothing to carry over: the joiners' batch runs as it is
                 leave(rid);
                 rid = bid;
-                mem = joiners;
+                mem = jg;
                 replaced = true;
             } else {
                 Resident* B = nullptr;
@@ -260,11 +310,11 @@ void run_joined(mcpt_ctx* c, Server& S, Exec& x, std::vector<Request*> mem) {
                 }
                 std::vector<std::pair<Resident*, int>> parts;
                 for (int q : live) parts.push_back({R, q});
-                for (int k = 0; k < (int)joiners.size(); ++k) parts.push_back({B, k});
+                for (int k = 0; k < (int)jg.size(); ++k) parts.push_back({B, k});
                 uint64_t mid = 0;
                 st = join_concat(c, x, parts, &mid);
                 if (st != MCPT_OK) {
-                    fail_group(joiners, st);
+                    fail_group(jg, st, last_error_text());
                 } else {
                     {
                         std::lock_guard<std::mutex> lg(c->mu);
@@ -274,7 +324,7 @@ void run_joined(mcpt_ctx* c, Server& S, Exec& x, std::vector<Request*> mem) {
                     rid = mid;
                     std::vector<Request*> next;
                     for (int q : live) next.push_back(mem[q]);
-                    next.insert(next.end(), joiners.begin(), joiners.end());
+                    next.insert(next.end(), jg.begin(), jg.end());
                     mem = next;
                     replaced = true;
                 }
@@ -289,7 +339,7 @@ void run_joined(mcpt_ctx* c, Server& S, Exec& x, std::vector<Request*> mem) {
             reserve(fp);
             continue;
         }
-        if (live.empty()) {
+        if (live.empty() && !pend) {
             leave(rid);
             return;
         }
@@ -328,10 +378,10 @@ void worker_loop(mcpt_ctx* c, int w) {
         ++S.busy;
         lk.unlock();
         if (S.params.tick_mode != MCPT_SERVE_BATCH_END && joinable(head->opts)) {
-            run_joined(c, S, x, group);
+            run_joined(c, S, x, *S.uploads[w], group);
             lk.lock();
             c->reserved -= std::min(c->reserved, x.reserved);
-            x.reserved = 0;
+            x.reserved = S.uploads[w]->reserved = 0;
             --S.busy;
             ++S.batches;
             S.done_cv.notify_all();
@@ -459,14 +509,18 @@ HostBuf copy_of(const double* src, int64_t n, PinnedPool& pool) {
 mcpt_status start_server(mcpt_ctx* c) {
     Server& S = *c->server;
     if (!S.workers.empty()) return MCPT_OK;
-    for (int w = 0; w < S.params.workers; ++w) {
+    for (int w = 0; w < 2 * S.params.workers; ++w) {
         auto x = std::make_unique<Exec>();
         mcpt_status st = exec_init(c, *x);
         if (st != MCPT_OK) {
             exec_free(c, *x);
+            for (auto& e : S.execs) exec_free(c, *e);
+            for (auto& e : S.uploads) exec_free(c, *e);
+            S.execs.clear();
+            S.uploads.clear();
             return st;
         }
-        S.execs.push_back(std::move(x));
+        (w < S.params.workers ? S.execs : S.uploads).push_back(std::move(x));
     }
     for (int w = 0; w < S.params.workers; ++w) S.workers.emplace_back(worker_loop, c, w);
     return MCPT_OK;
@@ -499,7 +553,9 @@ void serve_stop(mcpt_ctx* c) {
     for (auto& t : S.workers) t.join();
     S.workers.clear();
     for (auto& x : S.execs) exec_free(c, *x);
+    for (auto& x : S.uploads) exec_free(c, *x);
     S.execs.clear();
+    S.uploads.clear();
 }
 
 bool serve_owns(mcpt_ctx* c, uint64_t ticket) {
