@@ -305,3 +305,56 @@ def test_staging_cap_keeps_results(requests, cap):
             assert ctx.serve_stats()["staging_pinned_bytes"] == held
         with pytest.raises(mc.MCPTError):
             ctx.serve_staging(cap)   # the scheduler is running
+
+
+def test_retired_result_read_while_its_batch_runs():
+    """A request that retires while a slower request of its batch is still
+    sweeping can be read at once (its results stay in the batch, which goes on
+    skipping its clusters), and it equals its alone solve; so does the slower one."""
+    fast = make_served_request(3200, min_mono=100, max_mono=100, cutoff=2.0, coupling_scale=0.05)
+    slow = make_served_request(3201, min_mono=100, max_mono=100, cutoff=2.0, coupling_scale=0.35)
+    opts = dict(tol=1e-13, max_sweeps=400, check_every=1)
+    with mc.Context(0) as ctx:
+        ctx.serve_config(workers=1, max_batch=4)
+        tf, ts = ctx.submit(fast, **opts), ctx.submit(slow, **opts)
+        sf = ctx.wait(tf, 60000)
+        slow_running = ctx.poll(ts) is None
+        ef = ctx.energy(tf)   # while the slow request sweeps, most likely
+        print(f"[gpu] retired read: fast {sf['sweeps']} sweeps, slow still running: {slow_running}", flush=True)
+        ss = ctx.wait(ts, 60000)
+        assert ss["sweeps"] > sf["sweeps"]
+        s1, e1 = alone(fast, **opts)
+        assert sf["sweeps"] == s1["sweeps"] and abs(sf["e_total"] - s1["e_total"]) <= SAME_RTOL * abs(s1["e_total"])
+        assert rel(ef["e_m2"], e1["e_m2"]) <= SAME_RTOL and rel(ef["t"], e1["t"]) <= 1e-10
+        assert rel(ef["e_d2"], e1["e_d2"]) <= 1e-11
+        check_served(ctx, [fast, slow], [tf, ts], {tf: sf, ts: ss}, **opts)
+
+
+def test_nonfinite_joiner_fails_alone():
+    """A request with a NaN in its dimer blocks that joins a running batch at a
+    sweep tick fails by itself with MCPT_ERR_NONFINITE; the batch it joined and
+    a later good joiner are unaffected."""
+    first = make_served_request(3300, min_mono=40, max_mono=40, cutoff=2.0)
+    bad = make_served_request(3301, min_mono=55, max_mono=55, cutoff=2.0)
+    bad.v = bad.v.copy()
+    bad.v[7] = np.nan
+    good = make_served_request(3302, min_mono=55, max_mono=55, cutoff=2.0)
+    opts = dict(tol=0.0, max_sweeps=400, check_every=1)
+    with mc.Context(0) as ctx:
+        ctx.serve_config(workers=1, max_batch=8)
+        ctx.serve_tick_mode(mc.MCPT_SERVE_JOIN_AT_TICKS)
+        t0 = ctx.submit(first, **opts)
+        t_start = time.time()
+        while ctx.serve_stats()["running_batches"] == 0 and time.time() - t_start < 10:
+            time.sleep(0.0002)
+        tb = ctx.submit(bad, **opts)
+        t_start = time.time()
+        while ctx.serve_stats()["queued"] and time.time() - t_start < 0.5:
+            time.sleep(0.0002)
+        tg = ctx.submit(good, **opts)
+        done = wait_all(ctx, [t0, tb, tg])
+        assert ctx.serve_stats()["joined_at_ticks"] >= 1
+        assert done[tb]["status"] == mc.MCPT_ERR_NONFINITE
+        with pytest.raises(mc.MCPTError):
+            ctx.energy(tb)
+        check_served(ctx, [first, good], [t0, tg], done, **opts)
