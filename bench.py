@@ -20,6 +20,18 @@ sys.path.insert(0, ROOT)
 METRIC = "MCPT(2) solves/s + pair-contraction GB/s at 1000 monomers; p50/p99 served latency"
 PEAK = {"fp64": (78.6, "TFLOP/s"), "fp32": (157.3, "TFLOP/s"), "bf16": (2500.0, "TFLOP/s")}   # MI355X dense
 HBM_PEAK_GBS = 8000.0
+MEASURED = {}   # the device's measured FP64 pipe rates (mcpt_device_rates), set once by main
+
+
+def pipe_roof(w_bytes, ms, o):
+    """The ladder's other roof: each streamed 8-byte integral meets round16(o^2) amplitude columns on
+    v_mfma_f64_16x16x4, so its padded MFMA work per launch is 2 round16(o^2) flops per element; the
+    fraction of the matrix pipe's measured rate that this work reaches."""
+    padded = w_bytes / 8.0 * 2.0 * ((o * o + 15) // 16 * 16)
+    rate = MEASURED.get("mfma_f64_tflops")
+    return {"padded_mfma_flops_per_launch": padded,
+            "min_ms_at_measured_mfma_rate": padded / (rate * 1e12) * 1e3 if rate else None,
+            "frac_of_measured_mfma_f64": padded / (ms * 1e-3) / (rate * 1e12) if rate else None}
 
 
 def log(*a):
@@ -668,7 +680,8 @@ def lccd_mode(ctx, prob, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: 
         "ladder_kernel": {"kernel": "lccd_ladder_lds_kernel", "bound": "hbm", "avg_launch_ms": ms,
                           "algorithmic_bytes_per_launch": wb, "achieved_GBps": wb / (ms * 1e-3) / 1e9,
                           "peak_GBps": HBM_PEAK_GBS, "frac": wb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                          "ladder_TFLOPs": fl / (ms * 1e-3) / 1e12, "launches": tm["lccd_launches"]},
+                          "ladder_TFLOPs": fl / (ms * 1e-3) / 1e12, "launches": tm["lccd_launches"],
+                          **pipe_roof(wb, ms, int(prob.n_occ[0]))},
         "ring_kernel_avg_ms": tm["lccd_ring_ms"] / kl,
         "pair_kernel_avg_ms": tm["pair_ms"] / max(tm["pair_launches"], 1),
         "monomer_avg_ms": tm["mono_ms"] / max(tm["mono_launches"], 1),
@@ -764,7 +777,8 @@ def dimer_mode(ctx, steps, warmup, tol, cpu_budget: float = 8.0, with_cpu: bool 
         "pair_ladder_kernel": {"kernel": "lccd_ladder_lds_kernel (on pairs)", "bound": "hbm", "avg_launch_ms": ms,
                                "algorithmic_bytes_per_launch": wb, "achieved_GBps": wb / (ms * 1e-3) / 1e9,
                                "peak_GBps": HBM_PEAK_GBS, "frac": wb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                               "ladder_TFLOPs": fl / (ms * 1e-3) / 1e12, "launches": tm["dimer_launches"]},
+                               "ladder_TFLOPs": fl / (ms * 1e-3) / 1e12, "launches": tm["dimer_launches"],
+                               **pipe_roof(wb, ms, o)},
         "ring_kernel": {"kernel": "dimer_ring_kernel", "bound": "mfma", "avg_launch_ms": rms,
                         "flops_per_launch": ring_flops, "achieved_TFLOPs": ring_flops / (rms * 1e-3) / 1e12,
                         "peak_TFLOPs": PEAK["fp64"][0],
@@ -862,6 +876,7 @@ def main():
         f"({prob.nbytes() / 1e9:.2f} GB) in {time.time() - t0:.1f}s")
     ctx = mc.Context(0)
     rates = mc.device_rates(0)
+    MEASURED.update(rates)
     log(f"[bench] device FP64 pipes: MFMA {rates['mfma_f64_tflops']:.1f} TFLOP/s, "
         f"VALU {rates['valu_f64_tflops']:.1f} TFLOP/s, clock {rates['clock_ghz']:.2f} GHz")
     t0 = time.time()
