@@ -528,10 +528,11 @@ mcpt_status mcpt_serve_config(mcpt_ctx *ctx, int32_t workers, int32_t max_batch,
  *     the batch's first request join it, in queue order, within max_batch,
  *     max_batch_pairs and the budget (each priced at twice its footprint while it
  *     comes in), if together they are at least as large as the batch's unfinished
- *     requests: they are uploaded and copied with the unfinished clusters, whose
- *     iteration state is kept, into one batch that the next sweeps run as one launch
- *     per kernel.  The running batch pauses for the joiners' upload, which a batch
- *     formed on a free worker overlaps with other batches' sweeps.
+ *     requests: they are uploaded on a second stream of the worker while the batch
+ *     keeps sweeping, then copied with the unfinished clusters, whose iteration state
+ *     is kept, into one batch that the next sweeps run as one launch per kernel.
+ *     Measured on a served stream of mixed sizes, this shortens the median latency
+ *     at moderate load and costs capacity and tail latency.
  * In every mode a request's sweeps and result are those of its own solve (to the
  * rounding of the G atomics).  Errors: MCPT_ERR_INVALID (unknown mode, scheduler
  * running). */
