@@ -577,6 +577,79 @@ void record_end(Exec& x, hipEvent_t a, int kind, double flops, double vbytes) {
 
 // Pair phase over all pairs: the LDS-resident-V kernel for the pairs that fit,
 // then the L2 variant for the rest (same stream, so G accumulates in order).
+#ifndef MCPT_GLB_SPLIT
+#define MCPT_GLB_SPLIT 1
+#endif
+
+// Task layout of the split form for the pairs read from L2 (processing indices n_lds..n_pair):
+// chunks of at most grid_glb pairs, so that each chunk's Tau fits the Tau scratch (one slot of the
+// largest pair per persistent workgroup); pair k of a chunk goes to XCD k % 8.
+mcpt_status ensure_glb_plan(mcpt_ctx* c, Resident* R) {
+    if (R->glb_plan) return MCPT_OK;
+    const int64_t first = R->n_lds, n = R->n_pair - R->n_lds;
+    const int chunk = std::max(c->grid_glb, 1);
+    std::vector<int32_t> xpair, pre_tau, pre_g;
+    std::vector<int64_t> off;
+    struct Bases {
+        size_t x, p;
+        int m;
+        std::array<int, 9> xbeg;
+    };
+    std::vector<Bases> bases;
+    for (int64_t k0 = 0; k0 < n; k0 += chunk) {
+        const int m = (int)std::min<int64_t>(chunk, n - k0);
+        Bases b{xpair.size(), pre_tau.size(), m, {}};
+        int64_t o = 0;
+        int32_t tt = 0, tg = 0;
+        for (int xc = 0; xc < 8; ++xc) {
+            b.xbeg[xc] = (int)(xpair.size() - b.x);
+            for (int k = xc; k < m; k += 8) {
+                const PairDesc& d = R->pairs[first + k0 + k];
+                const int npX = R->monos[d.x].np, npY = R->monos[d.y].np;
+                xpair.push_back((int32_t)(first + k0 + k));
+                off.push_back(o);
+                pre_tau.push_back(tt);
+                pre_g.push_back(tg);
+                o += (int64_t)npX * npY;
+                tt += glb_tau_tasks(npX, npY);
+                tg += glb_g_tasks(npX, npY);
+            }
+        }
+        b.xbeg[8] = m;
+        pre_tau.push_back(tt);
+        pre_g.push_back(tg);
+        bases.push_back(b);
+    }
+    R->glb_tau.clear();
+    R->glb_g.clear();
+    R->glb_n.clear();
+    if (n > 0) {
+        int32_t *d_xpair = nullptr, *d_pt = nullptr, *d_pg = nullptr;
+        int64_t* d_off = nullptr;
+        mcpt_status st;
+        if ((st = dev_alloc(c, R, &d_xpair, (int64_t)xpair.size())) != MCPT_OK ||
+            (st = dev_alloc(c, R, &d_off, (int64_t)off.size())) != MCPT_OK ||
+            (st = dev_alloc(c, R, &d_pt, (int64_t)pre_tau.size())) != MCPT_OK ||
+            (st = dev_alloc(c, R, &d_pg, (int64_t)pre_g.size())) != MCPT_OK)
+            return st;
+        HIP_TRY(hipMemcpy(d_xpair, xpair.data(), xpair.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(d_off, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(d_pt, pre_tau.data(), pre_tau.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(d_pg, pre_g.data(), pre_g.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        for (const Bases& b : bases) {
+            GlbTasks t{d_xpair + b.x, d_off + b.x, d_pt + b.p, {}};
+            for (int i = 0; i < 9; ++i) t.xbeg[i] = b.xbeg[i];
+            GlbTasks g = t;
+            g.pre = d_pg + b.p;
+            R->glb_tau.push_back(t);
+            R->glb_g.push_back(g);
+            R->glb_n.push_back(b.m);
+        }
+    }
+    R->glb_plan = true;
+    return MCPT_OK;
+}
+
 void pair_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int couple, const Ctrl* ctrl,
                 const ClState* cl_sel = nullptr) {
     // the final energy pass covers every cluster, or those cl_sel does not mark done
@@ -615,8 +688,19 @@ void pair_phase(mcpt_ctx* c, Exec& x, Resident* R, double* G, int couple, const 
     const int g_glb = x.grid_cap > 0 ? std::min(c->grid_glb, x.grid_cap) : c->grid_glb;
     launch_pair_fp64(1, p0, R->d_pairs, R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G, x.d_scratch,
                      x.scratch_slot, g_lds, R->d_ed2, couple, ctrl, cl, x.stream);
-    launch_pair_fp64(0, p1, R->d_pairs + R->n_lds, R->n_pair - R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M, G,
-                     x.d_scratch, x.scratch_slot, g_glb, R->d_ed2, couple, ctrl, cl, x.stream);
+    // pairs from L2: split into Tau and G launches per chunk (XCD-local tasks) in the plain form
+    // (not in deterministic mode, energy pass included: the split form adds E_D2 with atomics)
+    const bool split = MCPT_GLB_SPLIT && R->n_pair > R->n_lds && !R->dimer && !R->det_on && !x.fixed_scratch &&
+                       x.grid_cap == 0 && x.scratch_slots >= c->grid_glb && x.scratch_slot >= R->max_slot &&
+                       ensure_glb_plan(c, R) == MCPT_OK;
+    if (split) {
+        for (size_t k = 0; k < R->glb_n.size(); ++k)
+            launch_pair_fp64_split(R->glb_tau[k], R->glb_g[k], R->glb_n[k], R->d_pairs, R->d_monos, R->d_dif,
+                                   R->d_V, R->d_M, G, x.d_scratch, g_glb, R->d_ed2, couple, ctrl, cl, x.stream);
+    } else {
+        launch_pair_fp64(0, p1, R->d_pairs + R->n_lds, R->n_pair - R->n_lds, R->d_monos, R->d_dif, R->d_V, R->d_M,
+                         G, x.d_scratch, x.scratch_slot, g_glb, R->d_ed2, couple, ctrl, cl, x.stream);
+    }
     if (det) launch_reduce_parts(R->d_monos, R->n_mono, R->d_csr_off, R->d_csr, R->d_part, G, R->d_cl, ctrl, x.stream);
 }
 
@@ -1590,6 +1674,9 @@ mcpt_status run(mcpt_ctx* c, Exec& x, Resident* R, const mcpt_options* o, mcpt_s
     if (st != MCPT_OK) return st;
     if ((st = ensure_device(c)) != MCPT_OK) return st;
     if ((st = ensure_scratch(c, x, R->max_slot)) != MCPT_OK) return st;
+    // the split form's task layout, built here because its copies may not run under graph capture
+    // (the solve that allocates nothing keeps the one-launch kernel)
+    if (!x.fixed_scratch && (st = ensure_glb_plan(c, R)) != MCPT_OK) return st;
     if (R->dimer && o->precision != MCPT_FP64)
         return fail(MCPT_ERR_INVALID, "a problem with dimer-internal terms runs in FP64 only");
     if (R->lccd && o->deterministic)

@@ -176,6 +176,24 @@ void launch_pair_fp64(int lds_variant, PartOut po, const PairDesc* pairs, int64_
                       const Ctrl* ctrl, const ClState* cl, hipStream_t s);
 int pair_fp64_blocks_per_cu(int lds_variant);
 bool pair_fits_lds(int nX, int npX, int npY);
+// Pairs read from L2 in two launches per chunk of at most one pair per persistent workgroup:
+// Tau of every pair (into the chunk's slots of the Tau scratch), then, if couple != 0, G.  Pair k
+// of a chunk belongs to XCD k % 8, whose workgroups take its pairs' tasks (3 x 3 tile blocks) in
+// pair order, so the V and M blocks they read stay in that XCD's L2.  Plain FP64 form only (no
+// dimer source, no stored partials).
+struct GlbTasks {
+    const int32_t* xpair;   // processing index of each pair of the chunk, grouped by XCD
+    const int64_t* tau_off; // element offset of its Tau in the scratch (row stride npY)
+    const int32_t* pre;     // exclusive prefix of the pairs' task counts (n + 1 entries)
+    int xbeg[9];            // XCD x's pairs: xpair[xbeg[x] .. xbeg[x + 1])
+};
+// tasks of a pair: Tau blocks SR x SC, G blocks SR^2 + SC^2 (SR = ceil(npX / 48), SC = ceil(npY / 48))
+int glb_tau_tasks(int npX, int npY);
+int glb_g_tasks(int npX, int npY);
+void launch_pair_fp64_split(const GlbTasks& tau_tasks, const GlbTasks& g_tasks, int n_chunk_pairs,
+                            const PairDesc* pairs, const MonoDesc* monos, const double* dif, const double* V,
+                            const double* M, double* G, double* scratch, int grid, double* ed2, int couple,
+                            const Ctrl* ctrl, const ClState* cl, hipStream_t s);
 
 // ---- reduced-precision pair phase (pair_lowp.hip); precision 1 = FP32, 2 = BF16 ----
 int lowp_chunk(int precision);   // k chunk: rows of low-precision operands are padded to it

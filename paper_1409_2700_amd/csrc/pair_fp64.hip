@@ -657,7 +657,182 @@ __global__ __launch_bounds__(kThreadsG, 2) void pair_fp64_glb_kernel(
                                        nullptr, nullptr, red);
 }
 
+// ---------------------------------------------------------------------------
+// pairs from L2, split: Tau tasks, then G tasks, each a 3 x 3 block of tiles
+// of one pair (edge blocks tile by tile), taken by the waves of the XCD the
+// pair belongs to in pair order
+// ---------------------------------------------------------------------------
+__device__ inline int sb_count(int tiles) { return (tiles + kSB - 1) / kSB; }
+
+// the pair j of XCD group [b, e) that task t falls in (pre: exclusive prefix of task counts)
+__device__ inline int task_pair(const int32_t* __restrict__ pre, int b, int e, int t) {
+    int lo = b, hi = e - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// wave-level task loop shared by the two kernels: f(j, local task) for every task of this wave
+template <class F>
+__device__ inline void for_glb_tasks(const GlbTasks& T, int wave, F&& f) {
+    constexpr int NW = kThreadsG / 64;
+    const int x = blockIdx.x % kXcds, local = blockIdx.x / kXcds, per = gridDim.x / kXcds;
+    const int b = T.xbeg[x], e = T.xbeg[x + 1];
+    if (b >= e) return;
+    const int t1 = T.pre[e], gw = local * NW + wave, nw = per * NW;
+    for (int t = T.pre[b] + gw; t < t1; t += nw) {
+        const int j = task_pair(T.pre, b, e, t);
+        f(j, t - T.pre[j]);
+    }
+}
+
+// Tau = D_XY * (V + M_X V + V M_Y^T) on tiles (r0.., c0..) into the pair's Tau slot; returns the
+// lane's part of <V, Tau>
+template <int NR, int NC>
+__device__ inline double tau_block_glb(const PairView& p, double* tau, int r0, int c0, int lane, int couple) {
+    d4 acc[NR][NC];
+    zero(acc);
+    tau_sb_glb(p, r0, c0, lane, acc);
+    double dxr[NR][4];
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) dxr[i][t] = p.dX[(r0 + i) * 16 + acc_row(lane, t)];
+    double epart = 0.0;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        const int c = (c0 + j) * 16 + acc_col(lane);
+        const int cc = min(c, p.nY - 1);
+        const double dyc = p.dY[c];
+        double vv[NR][4];
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int rr = min((r0 + i) * 16 + acc_row(lane, t), p.nX - 1);
+                vv[i][t] = p.V[(int64_t)rr * p.nY + cc];
+            }
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int r = (r0 + i) * 16 + acc_row(lane, t);
+                const bool ok = r < p.nX && c < p.nY;
+                const double tv = ok ? recip(dxr[i][t] + dyc) * (vv[i][t] + acc[i][j][t]) : 0.0;
+                epart += ok ? vv[i][t] * tv : 0.0;
+                if (couple) tau[(int64_t)r * p.npY + c] = tv;
+            }
+    }
+    return epart;
+}
+
+// E_D2 of the chunk's pairs of live clusters set to zero before their Tau tasks add to it
+__global__ __launch_bounds__(256) void glb_zero_ed2_kernel(const PairDesc* __restrict__ pairs,
+                                                            const int32_t* __restrict__ xpair, int n,
+                                                            double* __restrict__ ed2, const Ctrl* __restrict__ ctrl,
+                                                            const ClState* __restrict__ cl) {
+    if (ctrl && ctrl->done) return;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const PairDesc pd = pairs[xpair[k]];
+    if (cl && cl[pd.cluster].done) return;
+    ed2[pd.orig] = 0.0;
+}
+
+__global__ __launch_bounds__(kThreadsG, 2) void pair_glb_tau_kernel(
+    GlbTasks T, const PairDesc* __restrict__ pairs, const MonoDesc* __restrict__ monos,
+    const double* __restrict__ dif, const double* __restrict__ V, const double* __restrict__ M,
+    double* __restrict__ scratch, double* __restrict__ ed2, int couple, const Ctrl* __restrict__ ctrl,
+    const ClState* __restrict__ cl) {
+    if (ctrl && ctrl->done) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for_glb_tasks(T, wave, [&](int j, int lt) {
+        const PairDesc pd = pairs[T.xpair[j]];
+        if (cl && cl[pd.cluster].done) return;   // uniform over the wave
+        const PairView p = make_view(pd, monos, dif, V, M, nullptr);
+        double* tau = scratch + T.tau_off[j];
+        const int RB = p.npX / 16, CB = p.npY / 16, SC = sb_count(CB);
+        const int r0 = (lt / SC) * kSB, c0 = (lt % SC) * kSB;
+        const int nr = min(kSB, RB - r0), nc = min(kSB, CB - c0);
+        double epart = 0.0;
+        if (nr == kSB && nc == kSB) {
+            epart = tau_block_glb<kSB, kSB>(p, tau, r0, c0, lane, couple);
+        } else {
+            for (int i = 0; i < nr; ++i)
+                for (int k = 0; k < nc; ++k) epart += tau_block_glb<1, 1>(p, tau, r0 + i, c0 + k, lane, couple);
+        }
+        epart = wave_sum(epart);
+        if (lane == 0) unsafeAtomicAdd(ed2 + pd.orig, 4.0 * epart);
+    });
+}
+
+template <int NR, int NC>
+__device__ inline void g_block_glb(const PairView& p, const double* tau, int which, int r0, int c0, int lane) {
+    d4 acc[NR][NC];
+    zero(acc);
+    if (which == 0) {
+        gx_sb_glb(p, tau, r0, c0, lane, acc);
+        atomic_flush(p.GX, nullptr, p.npX, p.nX, r0, c0, lane, acc);
+    } else {
+        gy_sb_glb(p, tau, r0, c0, lane, acc);
+        atomic_flush(p.GY, nullptr, p.npY, p.nY, r0, c0, lane, acc);
+    }
+}
+
+__global__ __launch_bounds__(kThreadsG, 2) void pair_glb_g_kernel(
+    GlbTasks T, const PairDesc* __restrict__ pairs, const MonoDesc* __restrict__ monos,
+    const double* __restrict__ dif, const double* __restrict__ V, const double* __restrict__ M,
+    double* __restrict__ G, const double* __restrict__ scratch, const Ctrl* __restrict__ ctrl,
+    const ClState* __restrict__ cl) {
+    if (ctrl && ctrl->done) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for_glb_tasks(T, wave, [&](int j, int lt) {
+        const PairDesc pd = pairs[T.xpair[j]];
+        if (cl && cl[pd.cluster].done) return;
+        const PairView p = make_view(pd, monos, dif, V, M, G);
+        const double* tau = scratch + T.tau_off[j];
+        const int RB = p.npX / 16, CB = p.npY / 16, SR = sb_count(RB), SC = sb_count(CB);
+        const int which = lt < SR * SR ? 0 : 1;
+        const int S = which ? SC : SR, n = which ? CB : RB, u = which ? lt - SR * SR : lt;
+        const int r0 = (u / S) * kSB, c0 = (u % S) * kSB;
+        const int nr = min(kSB, n - r0), nc = min(kSB, n - c0);
+        if (nr == kSB && nc == kSB) {
+            g_block_glb<kSB, kSB>(p, tau, which, r0, c0, lane);
+        } else {
+            for (int i = 0; i < nr; ++i)
+                for (int k = 0; k < nc; ++k) g_block_glb<1, 1>(p, tau, which, r0 + i, c0 + k, lane);
+        }
+    });
+}
+
 }  // namespace
+
+int glb_tau_tasks(int npX, int npY) {
+    const int sr = (npX / 16 + kSB - 1) / kSB, sc = (npY / 16 + kSB - 1) / kSB;
+    return sr * sc;
+}
+
+int glb_g_tasks(int npX, int npY) {
+    const int sr = (npX / 16 + kSB - 1) / kSB, sc = (npY / 16 + kSB - 1) / kSB;
+    return sr * sr + sc * sc;
+}
+
+void launch_pair_fp64_split(const GlbTasks& tau_tasks, const GlbTasks& g_tasks, int n_chunk_pairs,
+                            const PairDesc* pairs, const MonoDesc* monos, const double* dif, const double* V,
+                            const double* M, double* G, double* scratch, int grid, double* ed2, int couple,
+                            const Ctrl* ctrl, const ClState* cl, hipStream_t s) {
+    if (n_chunk_pairs <= 0) return;
+    hipLaunchKernelGGL(glb_zero_ed2_kernel, dim3((n_chunk_pairs + 255) / 256), dim3(256), 0, s, pairs,
+                       tau_tasks.xpair, n_chunk_pairs, ed2, ctrl, cl);
+    hipLaunchKernelGGL(pair_glb_tau_kernel, dim3(grid), dim3(kThreadsG), 0, s, tau_tasks, pairs, monos, dif, V, M,
+                       scratch, ed2, couple, ctrl, cl);
+    if (couple)
+        hipLaunchKernelGGL(pair_glb_g_kernel, dim3(grid), dim3(kThreadsG), 0, s, g_tasks, pairs, monos, dif, V, M,
+                           G, scratch, ctrl, cl);
+}
 
 int pair_fp64_blocks_per_cu(int lds_variant) {
     int n = 0;

@@ -121,6 +121,11 @@ struct Resident {
     // served batches: owned by the scheduler, never visible to the caller under this id
     bool internal = false;
     int refs = 0;                 // tickets still holding this batch's results, + 1 while a worker runs it
+    // pairs read from L2 in the split form (launch_pair_fp64_split): per chunk of at most one pair
+    // per persistent workgroup, the XCD-grouped pair lists, Tau offsets and task prefixes
+    bool glb_plan = false;
+    std::vector<GlbTasks> glb_tau, glb_g;
+    std::vector<int> glb_n;
     // served batches with admission at sweep ticks: the G buffer the next sweep accumulates
     // into, and the cluster selection of the energy pass of clusters that finished
     int g_cur = 0;
