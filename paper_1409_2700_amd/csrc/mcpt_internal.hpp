@@ -179,8 +179,8 @@ bool pair_fits_lds(int nX, int npX, int npY);
 // Pairs read from L2 in two launches per chunk of at most one pair per persistent workgroup:
 // Tau of every pair (into the chunk's slots of the Tau scratch), then, if couple != 0, G.  Pair k
 // of a chunk belongs to XCD k % 8, whose workgroups take its pairs' tasks (3 x 3 tile blocks) in
-// pair order, so the V and M blocks they read stay in that XCD's L2.  Plain FP64 form only (no
-// dimer source, no stored partials).
+// pair order: a few pairs per XCD at a time, dealt out in even rounds of blocks rather than whole
+// pairs per workgroup.  Plain FP64 form only (no dimer source, no stored partials).
 struct GlbTasks {
     const int32_t* xpair;   // processing index of each pair of the chunk, grouped by XCD
     const int64_t* tau_off; // element offset of its Tau in the scratch (row stride npY)
